@@ -1,0 +1,167 @@
+/*
+ * nmfrp -- compressed non-negative matrix factorisation on AMD MI355X (gfx950).
+ *
+ * Method: G. Torre, M. Graber, "An Efficient Algorithm for Non-Negative Matrix
+ * Factorization with Random Projections" (arXiv 1712.02248).  Given X >= 0
+ * (m x n, rows are datapoints, Sec 2) and a rank r, find W >= 0 (m x r, the
+ * paper's A) and Ht >= 0 (n x r, the paper's B) with X ~ W Ht^T (eq 2.1),
+ * minimising 1/2 ||X - W Ht^T||_F^2 (eq 2.2).  X is compressed once into two
+ * sketches (Sec 3.1, eq 3.5; Sec 4):
+ *   Q_L (m x k') orthonormal basis of (X X^T)^q X Omega_L,   Xh = X^T Q_L (n x k'),
+ *   Q_R (n x k') orthonormal basis of (X^T X)^q X^T Omega_R, Xc = X Q_R   (m x k'),
+ * and the FastHALS-RP updates (eq fastHALS_a) run on the sketches only.
+ *
+ * Conventions for every call below
+ *  - Matrices are row-major.  Pointers named X, W, Ht, Q*, X*, omega_*, and the
+ *    buffers of the MLP calls are DEVICE pointers; sizes are element counts.
+ *  - All work is queued on the HIP stream given at creation; calls return after
+ *    queueing unless documented as synchronising.  Asynchronous HIP faults and
+ *    device-side flags surface at the next synchronising call.
+ *  - The library never allocates device memory: the caller passes a workspace
+ *    of nmf_workspace_bytes() bytes that it owns and keeps alive until
+ *    nmf_destroy().  X is borrowed: it is read by nmf_compress, nmf_residual and
+ *    nmf_fit only while those calls run on the stream.
+ *  - Errors: every call returns an nmf_status; nothing is thrown across the ABI.
+ *    nmf_last_error() gives a message for the last failure on a context (or,
+ *    with NULL, for the last failure of a context-free call in this thread).
+ */
+#ifndef NMFRP_H
+#define NMFRP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NMFRP_ABI_VERSION 1
+
+typedef struct nmf_ctx nmf_ctx;
+typedef struct nmf_mlp nmf_mlp;
+
+typedef enum {
+  NMF_OK = 0,
+  NMF_EINVAL = -1,      /* bad argument, size or alignment */
+  NMF_ENOMEM = -2,      /* workspace smaller than nmf_workspace_bytes() */
+  NMF_EHIP = -3,        /* a HIP runtime call or kernel launch failed */
+  NMF_ESTATE = -4,      /* call out of order (e.g. step before compress/init) */
+  NMF_EBREAKDOWN = -5,  /* Cholesky breakdown even after the shift */
+  NMF_ENONFINITE = -6   /* non-finite input or result */
+} nmf_status;
+
+typedef enum { NMF_FP32 = 0, NMF_BF16 = 1, NMF_FP8_E4M3 = 2 } nmf_prec;
+
+typedef struct {
+  int64_t m, n;          /* X is m x n */
+  int32_t r;             /* number of components (the paper's k) */
+  int32_t k_sketch;      /* k' = r + r_ov (Sec 3); r < k' <= min(m, n) (Sec 3.1) */
+  int32_t q;             /* power iterations (the paper's w, eq 3.5) */
+  int32_t prec;          /* nmf_prec of the range-finder products (extension) */
+  int32_t refine_fp32;   /* 1: one FP32 power iteration after low-precision passes */
+  int32_t normalize;     /* a_j <- a_j/||a_j|| after the A sweep (end of Sec 4):
+                            0 none, 1 with b_j <- b_j ||a_j|| (default), 2 literal */
+  float alpha, beta;     /* sparsity / smoothness on B (Sec 4.1); 0, 0 = plain rule */
+  uint64_t seed;         /* Philox4x32-10 key for device-drawn Omega and factors */
+} nmf_params;
+
+/* ---------------------------------------------------------------- context */
+
+/* Bytes of device workspace a context with these parameters needs (0 if the
+ * parameters are invalid).  Buffers are carved from it at 256-byte alignment. */
+size_t nmf_workspace_bytes(const nmf_params* p);
+
+/* Creates a context over a caller-owned device workspace (256-byte aligned) and
+ * a HIP stream (hipStream_t; NULL = the null stream).  The context struct
+ * itself is host memory owned by the library until nmf_destroy(). */
+nmf_status nmf_create(const nmf_params* p, void* workspace, size_t ws_bytes, void* hip_stream,
+                      nmf_ctx** out);
+void nmf_destroy(nmf_ctx* ctx);
+const char* nmf_last_error(const nmf_ctx* ctx);
+
+/* Checks X >= 0 and finite (the problem statement of Sec 2).  Synchronising.
+ * NMF_EINVAL if an entry is negative, NMF_ENONFINITE if one is not finite. */
+nmf_status nmf_validate(nmf_ctx* ctx, const float* X, int64_t ldx);
+
+/* Randomised two-sided compression (Sec 3, eqs 3.4-3.5; Sec 3.1; Sec 4):
+ * Q_L = orth((X X^T)^q X Omega_L), Q_R = orth((X^T X)^q X^T Omega_R), with an
+ * orthonormalisation (FP64 CholeskyQR2, shifted CholeskyQR3 on breakdown)
+ * after every product, then Xh = X^T Q_L and Xc = X Q_R.
+ * X: device, m x n, leading dimension ldx (ldx % 4 == 0, 16-byte aligned).
+ * omega_L: n x k' and omega_R: m x k' (leading dimension k'), device; NULL
+ * draws them on the device from Philox4x32-10 (streams 3 and 4, key = seed). */
+nmf_status nmf_compress(nmf_ctx* ctx, const float* X, int64_t ldx, const float* omega_L,
+                        const float* omega_R);
+
+/* Sets the initial factors (copied): W0 m x r, Ht0 n x r, device.  NULL draws
+ * U[0,1) * init_scale from Philox (streams 5 and 6). */
+nmf_status nmf_init(nmf_ctx* ctx, const float* W0, const float* Ht0, float init_scale);
+
+/* `iters` FastHALS-RP iterations (eq fastHALS_a): the whole W sweep against
+ * (Xc, Hc = Q_R^T Ht), column normalisation, then the whole H sweep against
+ * (Xh, Wh = Q_L^T W).  Asynchronous. */
+nmf_status nmf_step(nmf_ctx* ctx, int32_t iters);
+
+/* Exact e = ||X - W Ht^T||_F / ||X||_F in FP64 (eq 2.2).  Synchronising. */
+nmf_status nmf_residual(nmf_ctx* ctx, const float* X, int64_t ldx, double* rel_err);
+
+/* Runs steps in chunks of check_every, evaluating the exact residual after each
+ * chunk, until e <= eps or max_iters iterations (the paper leaves the stopping
+ * rule open: Alg 1-4).  Synchronising.  *iters_done and *rel_err report. */
+nmf_status nmf_fit(nmf_ctx* ctx, const float* X, int64_t ldx, int32_t max_iters, double eps,
+                   int32_t check_every, int32_t* iters_done, double* rel_err);
+
+/* Copies the current factors to device buffers W (m x r) and Ht (n x r),
+ * applying any pending column normalisation.  Asynchronous. */
+nmf_status nmf_get_factors(nmf_ctx* ctx, float* W, float* Ht);
+
+/* Sketch export / import (checkpoint, tests): QL m x k', QR n x k', Xh n x k',
+ * Xc m x k', device, leading dimension k'.  Any pointer may be NULL (skipped).
+ * set_state marks the context compressed.  Asynchronous. */
+nmf_status nmf_get_state(nmf_ctx* ctx, float* QL, float* QR, float* Xh, float* Xc);
+nmf_status nmf_set_state(nmf_ctx* ctx, const float* QL, const float* QR, const float* Xh,
+                         const float* Xc);
+
+/* Waits for the stream and reports device-side flags (Cholesky breakdown).
+ * *shifted (may be NULL) receives the number of orthonormalisations that
+ * needed the shifted fallback since the last nmf_compress. */
+nmf_status nmf_sync(nmf_ctx* ctx, int32_t* shifted);
+
+/* Stage times in milliseconds of the last compress / step / residual call
+ * (HIP events on the context stream).  Synchronising. */
+nmf_status nmf_stage_times(nmf_ctx* ctx, double* compress_ms, double* step_ms, double* residual_ms);
+
+/* ------------------------------------------------- kernel-level entry points */
+
+/* N(0,1) matrix (rows x cols, leading dimension ld) from Philox4x32-10 and
+ * Box-Muller (the Gaussian test matrix of Sec 3): element e = row*cols + col
+ * uses counter (e/4, 0, stream_id, 0) [64-bit e/4 in words 0-1], key = seed,
+ * word e % 4; words (0,1) and (2,3) are Box-Muller pairs with
+ * u = (x + 0.5) 2^-32, evaluated in FP64.  Asynchronous on hip_stream. */
+nmf_status nmf_gaussian(float* out, int64_t rows, int64_t cols, int64_t ld, uint32_t stream_id,
+                        uint64_t seed, void* hip_stream);
+/* U[0,1) * scale with 24-bit resolution: (x >> 8) 2^-24 on the same layout. */
+nmf_status nmf_uniform(float* out, int64_t rows, int64_t cols, int64_t ld, uint32_t stream_id,
+                       uint64_t seed, float scale, void* hip_stream);
+
+/* C (M x N, ldc) = op(A) B on FP32 MFMA: a_trans = 0: A is M x K (lda);
+ * a_trans = 1: A is stored K x M (lda) and used transposed (X^T B).  B is K x N
+ * (ldb).  N <= 256; lda, ldb multiples of 4 and A, B 16-byte aligned; K % 4 == 0
+ * when a_trans = 0, M % 4 == 0 when a_trans = 1.  workspace: device scratch of
+ * nmf_gemm_workspace_bytes() bytes for split-K partials.  Asynchronous. */
+size_t nmf_gemm_workspace_bytes(int64_t M, int64_t N, int64_t K, int32_t a_trans);
+nmf_status nmf_gemm(const float* A, int64_t lda, int32_t a_trans, const float* B, int64_t ldb,
+                    float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, void* workspace,
+                    size_t ws_bytes, void* hip_stream);
+
+/* In-place orthonormalisation of Y (rows x k, ldy % 4 == 0) by FP64
+ * CholeskyQR2 (shifted CholeskyQR3 on breakdown), k <= 128.  Synchronising;
+ * *shifted (may be NULL) = 1 if the shifted fallback ran. */
+size_t nmf_orth_workspace_bytes(int64_t rows, int32_t k);
+nmf_status nmf_orth(float* Y, int64_t ldy, int64_t rows, int32_t k, void* workspace,
+                    size_t ws_bytes, void* hip_stream, int32_t* shifted);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NMFRP_H */

@@ -1,0 +1,7 @@
+"""MI355X-native compressed NMF with random projections (FastHALS-RP).
+
+The method runs in hand-written HIP kernels for gfx950 behind the C ABI of
+include/nmfrp.h (libnmfrp.so); `nmfrp` is its ctypes binding.
+"""
+from . import nmfrp  # noqa: F401
+from .nmfrp import NMF, NmfError, gaussian, gemm, load, orth, uniform  # noqa: F401

@@ -1,0 +1,96 @@
+// Shared device/host definitions for the gfx950 compressed-NMF kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+#define NMF_DEV __device__ __forceinline__
+
+__host__ __device__ static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ static inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+// ---------------------------------------------------------------------------
+// Kernel launch helpers (all take the caller's stream).  Each returns the
+// hipError_t of the launch.
+// ---------------------------------------------------------------------------
+
+// Philox4x32-10 draws (philox.hip).
+hipError_t launch_philox_normal(float* out, int64_t rows, int64_t cols, int64_t ld,
+                                uint32_t stream_id, uint64_t seed, hipStream_t st);
+hipError_t launch_philox_uniform(float* out, int64_t rows, int64_t cols, int64_t ld,
+                                 uint32_t stream_id, uint64_t seed, float scale, hipStream_t st);
+
+// FP32 MFMA GEMM (gemm_f32.hip): C[M x N] = op(A)[M x K] * B[K x N].
+//   a_trans = 0: A is M x K row-major, element (i,k) at A[i*lda + k]
+//   a_trans = 1: A is given as K x M row-major, element (i,k) at A[k*lda + i]
+//   B is K x N row-major (ldb).  C is M x N row-major (ldc).
+//   With splits > 1 the K range is split; partials go to `part` (splits*M*N
+//   floats) and are summed in fixed order by a second kernel.
+size_t gemm_f32_part_floats(int64_t M, int64_t N, int splits);
+hipError_t launch_gemm_f32(const float* A, int64_t lda, int a_trans, const float* B, int64_t ldb,
+                           float* C, int64_t ldc, int64_t M, int64_t N, int64_t K,
+                           int splits, float* part, hipStream_t st);
+int gemm_f32_pick_splits(int64_t M, int64_t N, int64_t K, int a_trans);
+
+// Tall-skinny QR pieces (qr.hip).
+hipError_t launch_gram_f64(const float* Y, int64_t ldy, int64_t rows, int k, double* part,
+                           int splits, const int* skip_flag, hipStream_t st);
+int gram_pick_splits(int64_t rows, int k);
+hipError_t launch_cholesky(const double* part, int splits, int k, int64_t rows, double* Rinv,
+                           int* status, int attempt, hipStream_t st);
+hipError_t launch_apply_rinv(float* Y, int64_t ldy, int64_t rows, int k, const double* Rinv,
+                             const int* status, int attempt, hipStream_t st);
+
+// Fused HALS half-step and its finalisation (hals.hip).
+struct HalfStepArgs {
+  const float* S;      // N x kp sketch (ld lds): Xc for the W side, Xh for the H side
+  int64_t lds;
+  const float* C;      // kp x r compressed other factor (ld r): Hc or Wh
+  const float* G;      // r x r Gram of C
+  float* F;            // N x r factor updated in place (ld r): W or Ht
+  const float* scale;  // r column scales applied to F on load (NULL = none)
+  const float* Qb;     // N x kp basis (ld ldq) for re-compression: Q_L or Q_R
+  int64_t ldq;
+  int64_t N;
+  int kp, r;
+  float* part;         // nblk x (kp*r + r) partial Qb^T F and column sums of F^2
+  float alpha, beta;   // sparsity / smoothness (0, 0 = plain rule)
+};
+int halfstep_blocks(int64_t N);
+size_t halfstep_part_floats(int64_t N, int kp, int r);
+hipError_t launch_halfstep(const HalfStepArgs& a, int do_sweep, hipStream_t st);
+
+struct FinalizeArgs {
+  const float* part;   // nblk x (kp*r + r)
+  int nblk, kp, r;
+  int normalize;       // 0 none, 1 compensated, 2 literal
+  int use_norms;       // 1: this side's column norms drive normalisation
+  float* C;            // kp x r output (scaled by 1/s when normalising)
+  float* G;            // r x r output C^T C
+  float* scale_self;   // r: scale to apply to this side's factor on next load (1/s)
+  float* scale_other;  // r: scale to apply to the other factor on next load (s)
+  double* accum;       // scratch kp*r + r doubles
+  unsigned* counter;   // zero-initialised completion counter
+};
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t st);
+
+// Residual (residual.hip): sum (X - W diag(sw) Ht^T)^2 and sum X^2 in FP64.
+int residual_blocks(int64_t m, int64_t n);
+hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t n, const float* W,
+                           const float* sw, const float* Ht, int r, double* part, double* out,
+                           unsigned* counter, hipStream_t st);
+
+// Small utilities (util.hip).
+hipError_t launch_fill_f32(float* p, int64_t count, float v, hipStream_t st);
+hipError_t launch_fill_i32(int* p, int64_t count, int v, hipStream_t st);
+hipError_t launch_copy2d(float* dst, int64_t ldd, const float* src, int64_t lds, int64_t rows,
+                         int64_t cols, hipStream_t st);
+hipError_t launch_scale_cols(float* dst, int64_t ldd, const float* src, int64_t lds, int64_t rows,
+                             int cols, const float* scale, hipStream_t st);
+hipError_t launch_check_nonneg(const float* X, int64_t ldx, int64_t m, int64_t n, int* flags,
+                               hipStream_t st);

@@ -1,0 +1,486 @@
+// Host runtime and C ABI of the compressed-NMF library (declared in nmfrp.h).
+// A context owns no device memory: every buffer is carved from the caller's
+// workspace.  All kernels run on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/nmfrp.h"
+#include "common.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Plan {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  }
+};
+
+// Workspace layout; offsets relative to the workspace base.
+struct Layout {
+  int64_t KP;  // k' padded to a multiple of 4 (padding columns stay zero)
+  size_t omL, omR, QL, TM, Xc, QR, TN, Xh, W, Ht;
+  size_t gemm_part, gram_part, R, qr_status;
+  size_t hs_part, accum, counters, Hc, GH, Wh, GW, scale_w, scale_h;
+  size_t res_part, res_out, flags;
+  size_t total;
+  size_t gemm_part_bytes, gram_splits_max;
+};
+
+bool valid_params(const nmf_params* p, std::string* why) {
+  if (!p) { *why = "null params"; return false; }
+  if (p->m <= 0 || p->n <= 0 || p->r <= 0) { *why = "m, n, r must be positive"; return false; }
+  if (!(p->r < p->k_sketch)) { *why = "need r < k' (Sec 3.1)"; return false; }
+  if (p->k_sketch > p->m || p->k_sketch > p->n) { *why = "need k' <= min(m, n)"; return false; }
+  if (p->k_sketch > 128) { *why = "k' > 128 is not supported by this build"; return false; }
+  if (p->r > 64) { *why = "r > 64 is not supported by this build"; return false; }
+  if (p->q < 0) { *why = "q must be >= 0"; return false; }
+  if (p->prec != NMF_FP32) { *why = "only FP32 range-finder products in this build"; return false; }
+  if (p->normalize < 0 || p->normalize > 2) { *why = "normalize must be 0, 1 or 2"; return false; }
+  if (p->n % 4) { *why = "n must be a multiple of 4"; return false; }
+  if (p->alpha < 0 || p->beta < 0) { *why = "alpha, beta must be >= 0"; return false; }
+  return true;
+}
+
+Layout make_layout(const nmf_params* p) {
+  Layout L;
+  Plan pl;
+  const int64_t m = p->m, n = p->n, k = p->k_sketch, r = p->r;
+  L.KP = round_up(k, 4);
+  const size_t f = sizeof(float), d = sizeof(double);
+  L.omL = pl.take(n * L.KP * f);
+  L.omR = pl.take(m * L.KP * f);
+  L.QL = pl.take(m * L.KP * f);
+  L.TM = pl.take(m * L.KP * f);
+  L.Xc = pl.take(m * L.KP * f);
+  L.QR = pl.take(n * L.KP * f);
+  L.TN = pl.take(n * L.KP * f);
+  L.Xh = pl.take(n * L.KP * f);
+  L.W = pl.take(m * r * f);
+  L.Ht = pl.take(n * r * f);
+  const int s1 = gemm_f32_pick_splits(m, k, n, 0), s2 = gemm_f32_pick_splits(n, k, m, 1);
+  size_t gp = gemm_f32_part_floats(m, k, s1);
+  size_t gp2 = gemm_f32_part_floats(n, k, s2);
+  L.gemm_part_bytes = (gp > gp2 ? gp : gp2) * f;
+  L.gemm_part = pl.take(L.gemm_part_bytes);
+  const int gs1 = gram_pick_splits(m, k), gs2 = gram_pick_splits(n, k);
+  L.gram_splits_max = gs1 > gs2 ? gs1 : gs2;
+  L.gram_part = pl.take(L.gram_splits_max * k * k * d);
+  L.R = pl.take(k * k * d);
+  L.qr_status = pl.take(8 * sizeof(int));
+  size_t h1 = halfstep_part_floats(m, (int)L.KP, (int)r), h2 = halfstep_part_floats(n, (int)L.KP, (int)r);
+  L.hs_part = pl.take((h1 > h2 ? h1 : h2) * f);
+  L.accum = pl.take((L.KP * r + r) * d);
+  L.counters = pl.take(8 * sizeof(unsigned));
+  L.Hc = pl.take(L.KP * r * f);
+  L.GH = pl.take(r * r * f);
+  L.Wh = pl.take(L.KP * r * f);
+  L.GW = pl.take(r * r * f);
+  L.scale_w = pl.take(r * f);
+  L.scale_h = pl.take(r * f);
+  L.res_part = pl.take(2 * (size_t)residual_blocks(m, n) * d);
+  L.res_out = pl.take(2 * d);
+  L.flags = pl.take(8 * sizeof(int));
+  L.total = pl.off;
+  return L;
+}
+
+}  // namespace
+
+struct nmf_ctx {
+  nmf_params p;
+  Layout L;
+  char* ws;
+  hipStream_t st;
+  bool compressed = false, initialized = false;
+  std::string err;
+  hipEvent_t ev[6];
+  bool have_ev = false;
+  float ms_compress = 0, ms_step = 0, ms_residual = 0;
+  bool t_compress = false, t_step = false, t_residual = false;
+  template <class T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace {
+
+nmf_status fail(nmf_ctx* c, nmf_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(c, expr)                                                          \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return fail((c), NMF_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// orthonormalise Y (rows x k, ld) in place: CholeskyQR2 + conditional third pass
+hipError_t orth(float* Y, int64_t ld, int64_t rows, int k, double* gram_part, double* R,
+                int* status, hipStream_t st) {
+  hipError_t e;
+  const int splits = gram_pick_splits(rows, k);
+  if ((e = launch_fill_i32(status, 1, 0, st)) != hipSuccess) return e;   // shift flag
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    if ((e = launch_gram_f64(Y, ld, rows, k, gram_part, splits, attempt == 2 ? status : nullptr, st)))
+      return e;
+    if ((e = launch_cholesky(gram_part, splits, k, rows, R, status, attempt, st))) return e;
+    if ((e = launch_apply_rinv(Y, ld, rows, k, R, status, attempt, st))) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t gemm(nmf_ctx* c, const float* A, int64_t lda, int at, const float* B, float* C,
+                int64_t M, int64_t K) {
+  const int64_t N = c->p.k_sketch;
+  const int s = gemm_f32_pick_splits(M, N, K, at);
+  return launch_gemm_f32(A, lda, at, B, c->L.KP, C, c->L.KP, M, N, K, s,
+                         c->at<float>(c->L.gemm_part), c->st);
+}
+
+hipError_t halfstep_w(nmf_ctx* c) {
+  Layout& L = c->L;
+  HalfStepArgs a;
+  a.S = c->at<float>(L.Xc); a.lds = L.KP;
+  a.C = c->at<float>(L.Hc); a.G = c->at<float>(L.GH);
+  a.F = c->at<float>(L.W); a.scale = c->at<float>(L.scale_w);
+  a.Qb = c->at<float>(L.QL); a.ldq = L.KP;
+  a.N = c->p.m; a.kp = (int)L.KP; a.r = c->p.r;
+  a.part = c->at<float>(L.hs_part);
+  a.alpha = 0.f; a.beta = 0.f;
+  hipError_t e = launch_halfstep(a, 1, c->st);
+  if (e) return e;
+  FinalizeArgs f;
+  f.part = a.part; f.nblk = halfstep_blocks(c->p.m); f.kp = (int)L.KP; f.r = c->p.r;
+  f.normalize = c->p.normalize; f.use_norms = 1;
+  f.C = c->at<float>(L.Wh); f.G = c->at<float>(L.GW);
+  f.scale_self = c->at<float>(L.scale_w); f.scale_other = c->at<float>(L.scale_h);
+  f.accum = c->at<double>(L.accum); f.counter = c->at<unsigned>(L.counters);
+  return launch_finalize(f, c->st);
+}
+
+hipError_t halfstep_h(nmf_ctx* c, int do_sweep) {
+  Layout& L = c->L;
+  HalfStepArgs a;
+  a.S = c->at<float>(L.Xh); a.lds = L.KP;
+  a.C = c->at<float>(L.Wh); a.G = c->at<float>(L.GW);
+  a.F = c->at<float>(L.Ht); a.scale = do_sweep ? c->at<float>(L.scale_h) : nullptr;
+  a.Qb = c->at<float>(L.QR); a.ldq = L.KP;
+  a.N = c->p.n; a.kp = (int)L.KP; a.r = c->p.r;
+  a.part = c->at<float>(L.hs_part);
+  a.alpha = c->p.alpha; a.beta = c->p.beta;
+  hipError_t e = launch_halfstep(a, do_sweep, c->st);
+  if (e) return e;
+  FinalizeArgs f;
+  f.part = a.part; f.nblk = halfstep_blocks(c->p.n); f.kp = (int)L.KP; f.r = c->p.r;
+  f.normalize = c->p.normalize; f.use_norms = 0;
+  f.C = c->at<float>(L.Hc); f.G = c->at<float>(L.GH);
+  f.scale_self = nullptr; f.scale_other = nullptr;
+  f.accum = c->at<double>(L.accum); f.counter = c->at<unsigned>(L.counters);
+  return launch_finalize(f, c->st);
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+size_t nmf_workspace_bytes(const nmf_params* p) {
+  std::string why;
+  if (!valid_params(p, &why)) { g_err = why; return 0; }
+  return make_layout(p).total;
+}
+
+nmf_status nmf_create(const nmf_params* p, void* workspace, size_t ws_bytes, void* hip_stream,
+                      nmf_ctx** out) {
+  std::string why;
+  if (!out) return fail(nullptr, NMF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!valid_params(p, &why)) return fail(nullptr, NMF_EINVAL, why);
+  Layout L = make_layout(p);
+  if (!workspace || ((uintptr_t)workspace & 255)) return fail(nullptr, NMF_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total) return fail(nullptr, NMF_ENOMEM, "workspace too small");
+  nmf_ctx* c = new nmf_ctx();
+  c->p = *p;
+  c->L = L;
+  c->ws = (char*)workspace;
+  c->st = (hipStream_t)hip_stream;
+  hipError_t e = launch_fill_f32((float*)workspace, (int64_t)(L.total / 4), 0.f, c->st);
+  if (e != hipSuccess) { delete c; return fail(nullptr, NMF_EHIP, hipGetErrorString(e)); }
+  for (int i = 0; i < 6; ++i)
+    if (hipEventCreate(&c->ev[i]) != hipSuccess) { delete c; return fail(nullptr, NMF_EHIP, "event create"); }
+  c->have_ev = true;
+  *out = c;
+  return NMF_OK;
+}
+
+void nmf_destroy(nmf_ctx* c) {
+  if (!c) return;
+  if (c->have_ev)
+    for (int i = 0; i < 6; ++i) (void)hipEventDestroy(c->ev[i]);
+  delete c;
+}
+
+const char* nmf_last_error(const nmf_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+nmf_status nmf_validate(nmf_ctx* c, const float* X, int64_t ldx) {
+  if (!c || !X || ldx < c->p.n) return fail(c, NMF_EINVAL, "bad arguments");
+  int* flags = c->at<int>(c->L.flags);
+  HIPCHK(c, launch_fill_i32(flags, 2, 0, c->st));
+  HIPCHK(c, launch_check_nonneg(X, ldx, c->p.m, c->p.n, flags, c->st));
+  int h[2];
+  HIPCHK(c, hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (h[1]) return fail(c, NMF_ENONFINITE, "X has non-finite entries");
+  if (h[0]) return fail(c, NMF_EINVAL, "X has negative entries (NMF needs X >= 0)");
+  return NMF_OK;
+}
+
+nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* omega_L,
+                        const float* omega_R) {
+  if (!c || !X) return fail(c, NMF_EINVAL, "null argument");
+  if (ldx < c->p.n || ldx % 4 || !aligned16(X)) return fail(c, NMF_EINVAL, "X needs ldx >= n, ldx % 4 == 0, 16-byte alignment");
+  Layout& L = c->L;
+  const int64_t m = c->p.m, n = c->p.n;
+  const int k = c->p.k_sketch, q = c->p.q;
+  hipStream_t st = c->st;
+  float *omL = c->at<float>(L.omL), *omR = c->at<float>(L.omR);
+  float *QL = c->at<float>(L.QL), *TM = c->at<float>(L.TM), *Xc = c->at<float>(L.Xc);
+  float *QR = c->at<float>(L.QR), *TN = c->at<float>(L.TN), *Xh = c->at<float>(L.Xh);
+  double *gp = c->at<double>(L.gram_part), *R = c->at<double>(L.R);
+  int* qs = c->at<int>(L.qr_status);
+  HIPCHK(c, hipEventRecord(c->ev[0], st));
+  HIPCHK(c, launch_fill_i32(qs, 8, 0, st));
+  // test matrices (Sec 3)
+  if (omega_L) HIPCHK(c, launch_copy2d(omL, L.KP, omega_L, k, n, k, st));
+  else HIPCHK(c, launch_philox_normal(omL, n, k, L.KP, 3u, c->p.seed, st));
+  if (omega_R) HIPCHK(c, launch_copy2d(omR, L.KP, omega_R, k, m, k, st));
+  else HIPCHK(c, launch_philox_normal(omR, m, k, L.KP, 4u, c->p.seed, st));
+  // left range finder: Q_L = orth(X Omega_L); q x { Z = orth(X^T Q_L); Q_L = orth(X Z) }
+  HIPCHK(c, gemm(c, X, ldx, 0, omL, QL, m, n));
+  HIPCHK(c, orth(QL, L.KP, m, k, gp, R, qs, st));
+  for (int it = 0; it < q; ++it) {
+    HIPCHK(c, gemm(c, X, ldx, 1, QL, TN, n, m));
+    HIPCHK(c, orth(TN, L.KP, n, k, gp, R, qs, st));
+    HIPCHK(c, gemm(c, X, ldx, 0, TN, QL, m, n));
+    HIPCHK(c, orth(QL, L.KP, m, k, gp, R, qs, st));
+  }
+  // right range finder on X^T with Omega_R
+  HIPCHK(c, gemm(c, X, ldx, 1, omR, QR, n, m));
+  HIPCHK(c, orth(QR, L.KP, n, k, gp, R, qs, st));
+  for (int it = 0; it < q; ++it) {
+    HIPCHK(c, gemm(c, X, ldx, 0, QR, TM, m, n));
+    HIPCHK(c, orth(TM, L.KP, m, k, gp, R, qs, st));
+    HIPCHK(c, gemm(c, X, ldx, 1, TM, QR, n, m));
+    HIPCHK(c, orth(QR, L.KP, n, k, gp, R, qs, st));
+  }
+  // projected data (Sec 4): Xh = X^T Q_L (X-hat^T), Xc = X Q_R (X-check)
+  HIPCHK(c, gemm(c, X, ldx, 1, QL, Xh, n, m));
+  HIPCHK(c, gemm(c, X, ldx, 0, QR, Xc, m, n));
+  HIPCHK(c, hipEventRecord(c->ev[1], st));
+  c->t_compress = true;
+  c->compressed = true;
+  return NMF_OK;
+}
+
+nmf_status nmf_init(nmf_ctx* c, const float* W0, const float* Ht0, float init_scale) {
+  if (!c) return fail(c, NMF_EINVAL, "null context");
+  if (!c->compressed) return fail(c, NMF_ESTATE, "init needs the sketches: call nmf_compress or nmf_set_state first");
+  Layout& L = c->L;
+  const int64_t m = c->p.m, n = c->p.n;
+  const int r = c->p.r;
+  float *W = c->at<float>(L.W), *Ht = c->at<float>(L.Ht);
+  if (W0) HIPCHK(c, launch_copy2d(W, r, W0, r, m, r, c->st));
+  else HIPCHK(c, launch_philox_uniform(W, m, r, r, 5u, c->p.seed, init_scale, c->st));
+  if (Ht0) HIPCHK(c, launch_copy2d(Ht, r, Ht0, r, n, r, c->st));
+  else HIPCHK(c, launch_philox_uniform(Ht, n, r, r, 6u, c->p.seed, init_scale, c->st));
+  HIPCHK(c, launch_fill_f32(c->at<float>(L.scale_w), r, 1.f, c->st));
+  HIPCHK(c, launch_fill_f32(c->at<float>(L.scale_h), r, 1.f, c->st));
+  HIPCHK(c, halfstep_h(c, 0));   // Hc = Q_R^T Ht, G_H = Hc^T Hc
+  c->initialized = true;
+  return NMF_OK;
+}
+
+nmf_status nmf_step(nmf_ctx* c, int32_t iters) {
+  if (!c || iters < 0) return fail(c, NMF_EINVAL, "bad arguments");
+  if (!c->initialized) return fail(c, NMF_ESTATE, "step needs nmf_init");
+  HIPCHK(c, hipEventRecord(c->ev[2], c->st));
+  for (int t = 0; t < iters; ++t) {
+    HIPCHK(c, halfstep_w(c));
+    HIPCHK(c, halfstep_h(c, 1));
+  }
+  HIPCHK(c, hipEventRecord(c->ev[3], c->st));
+  c->t_step = true;
+  return NMF_OK;
+}
+
+nmf_status nmf_residual(nmf_ctx* c, const float* X, int64_t ldx, double* rel_err) {
+  if (!c || !X || !rel_err || ldx < c->p.n) return fail(c, NMF_EINVAL, "bad arguments");
+  if (!c->initialized) return fail(c, NMF_ESTATE, "residual needs factors (nmf_init)");
+  Layout& L = c->L;
+  HIPCHK(c, hipEventRecord(c->ev[4], c->st));
+  HIPCHK(c, launch_residual(X, ldx, c->p.m, c->p.n, c->at<float>(L.W), c->at<float>(L.scale_w),
+                            c->at<float>(L.Ht), c->p.r, c->at<double>(L.res_part),
+                            c->at<double>(L.res_out), c->at<unsigned>(L.counters) + 4, c->st));
+  HIPCHK(c, hipEventRecord(c->ev[5], c->st));
+  double h[2];
+  int qs[8];
+  HIPCHK(c, hipMemcpyAsync(h, c->at<double>(L.res_out), sizeof(h), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(qs, c->at<int>(L.qr_status), sizeof(qs), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->t_residual = true;
+  if (qs[1]) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
+  *rel_err = (h[1] > 0) ? std::sqrt(h[0] / h[1]) : 0.0;
+  if (!std::isfinite(h[0]) || !std::isfinite(h[1])) return fail(c, NMF_ENONFINITE, "non-finite residual");
+  return NMF_OK;
+}
+
+nmf_status nmf_fit(nmf_ctx* c, const float* X, int64_t ldx, int32_t max_iters, double eps,
+                   int32_t check_every, int32_t* iters_done, double* rel_err) {
+  if (!c || !X || check_every <= 0 || max_iters < 0) return fail(c, NMF_EINVAL, "bad arguments");
+  int done = 0;
+  double e = 0.0;
+  nmf_status s = nmf_residual(c, X, ldx, &e);
+  if (s != NMF_OK) return s;
+  while (done < max_iters && !(e <= eps)) {
+    int chunk = check_every < max_iters - done ? check_every : max_iters - done;
+    if ((s = nmf_step(c, chunk)) != NMF_OK) return s;
+    done += chunk;
+    if ((s = nmf_residual(c, X, ldx, &e)) != NMF_OK) return s;
+  }
+  if (iters_done) *iters_done = done;
+  if (rel_err) *rel_err = e;
+  return NMF_OK;
+}
+
+nmf_status nmf_get_factors(nmf_ctx* c, float* W, float* Ht) {
+  if (!c) return fail(c, NMF_EINVAL, "null context");
+  if (!c->initialized) return fail(c, NMF_ESTATE, "no factors yet");
+  Layout& L = c->L;
+  const int r = c->p.r;
+  if (W) HIPCHK(c, launch_scale_cols(W, r, c->at<float>(L.W), r, c->p.m, r, c->at<float>(L.scale_w), c->st));
+  if (Ht) HIPCHK(c, launch_copy2d(Ht, r, c->at<float>(L.Ht), r, c->p.n, r, c->st));
+  return NMF_OK;
+}
+
+nmf_status nmf_get_state(nmf_ctx* c, float* QL, float* QR, float* Xh, float* Xc) {
+  if (!c) return fail(c, NMF_EINVAL, "null context");
+  if (!c->compressed) return fail(c, NMF_ESTATE, "no sketches yet");
+  Layout& L = c->L;
+  const int k = c->p.k_sketch;
+  if (QL) HIPCHK(c, launch_copy2d(QL, k, c->at<float>(L.QL), L.KP, c->p.m, k, c->st));
+  if (QR) HIPCHK(c, launch_copy2d(QR, k, c->at<float>(L.QR), L.KP, c->p.n, k, c->st));
+  if (Xh) HIPCHK(c, launch_copy2d(Xh, k, c->at<float>(L.Xh), L.KP, c->p.n, k, c->st));
+  if (Xc) HIPCHK(c, launch_copy2d(Xc, k, c->at<float>(L.Xc), L.KP, c->p.m, k, c->st));
+  return NMF_OK;
+}
+
+nmf_status nmf_set_state(nmf_ctx* c, const float* QL, const float* QR, const float* Xh,
+                         const float* Xc) {
+  if (!c || !QL || !QR || !Xh || !Xc) return fail(c, NMF_EINVAL, "null argument");
+  Layout& L = c->L;
+  const int k = c->p.k_sketch;
+  HIPCHK(c, launch_copy2d(c->at<float>(L.QL), L.KP, QL, k, c->p.m, k, c->st));
+  HIPCHK(c, launch_copy2d(c->at<float>(L.QR), L.KP, QR, k, c->p.n, k, c->st));
+  HIPCHK(c, launch_copy2d(c->at<float>(L.Xh), L.KP, Xh, k, c->p.n, k, c->st));
+  HIPCHK(c, launch_copy2d(c->at<float>(L.Xc), L.KP, Xc, k, c->p.m, k, c->st));
+  HIPCHK(c, launch_fill_i32(c->at<int>(L.qr_status), 8, 0, c->st));
+  c->compressed = true;
+  c->initialized = false;
+  return NMF_OK;
+}
+
+nmf_status nmf_sync(nmf_ctx* c, int32_t* shifted) {
+  if (!c) return fail(c, NMF_EINVAL, "null context");
+  int qs[8];
+  HIPCHK(c, hipMemcpyAsync(qs, c->at<int>(c->L.qr_status), sizeof(qs), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (shifted) *shifted = qs[2];
+  if (qs[1]) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
+  return NMF_OK;
+}
+
+nmf_status nmf_stage_times(nmf_ctx* c, double* compress_ms, double* step_ms, double* residual_ms) {
+  if (!c) return fail(c, NMF_EINVAL, "null context");
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  float t;
+  if (compress_ms) { *compress_ms = -1; if (c->t_compress && hipEventElapsedTime(&t, c->ev[0], c->ev[1]) == hipSuccess) *compress_ms = t; }
+  if (step_ms) { *step_ms = -1; if (c->t_step && hipEventElapsedTime(&t, c->ev[2], c->ev[3]) == hipSuccess) *step_ms = t; }
+  if (residual_ms) { *residual_ms = -1; if (c->t_residual && hipEventElapsedTime(&t, c->ev[4], c->ev[5]) == hipSuccess) *residual_ms = t; }
+  return NMF_OK;
+}
+
+nmf_status nmf_gaussian(float* out, int64_t rows, int64_t cols, int64_t ld, uint32_t sid,
+                        uint64_t seed, void* hs) {
+  if (!out || rows < 0 || cols < 0 || ld < cols) return fail(nullptr, NMF_EINVAL, "bad arguments");
+  hipError_t e = launch_philox_normal(out, rows, cols, ld, sid, seed, (hipStream_t)hs);
+  return e ? fail(nullptr, NMF_EHIP, hipGetErrorString(e)) : NMF_OK;
+}
+
+nmf_status nmf_uniform(float* out, int64_t rows, int64_t cols, int64_t ld, uint32_t sid,
+                       uint64_t seed, float scale, void* hs) {
+  if (!out || rows < 0 || cols < 0 || ld < cols) return fail(nullptr, NMF_EINVAL, "bad arguments");
+  hipError_t e = launch_philox_uniform(out, rows, cols, ld, sid, seed, scale, (hipStream_t)hs);
+  return e ? fail(nullptr, NMF_EHIP, hipGetErrorString(e)) : NMF_OK;
+}
+
+size_t nmf_gemm_workspace_bytes(int64_t M, int64_t N, int64_t K, int32_t a_trans) {
+  const int s = gemm_f32_pick_splits(M, N, K, a_trans);
+  return gemm_f32_part_floats(M, N, s) * sizeof(float) + 256;
+}
+
+nmf_status nmf_gemm(const float* A, int64_t lda, int32_t a_trans, const float* B, int64_t ldb,
+                    float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, void* ws, size_t ws_bytes,
+                    void* hs) {
+  if (M < 0 || N < 0 || K < 0 || N > 256 || ldc < N) return fail(nullptr, NMF_EINVAL, "bad arguments");
+  if (M == 0 || N == 0) return NMF_OK;
+  if (!A || !B || !C) return fail(nullptr, NMF_EINVAL, "null pointer");
+  if (lda % 4 || ldb % 4 || !aligned16(A) || !aligned16(B)) return fail(nullptr, NMF_EINVAL, "lda, ldb % 4 and 16-byte alignment required");
+  if ((!a_trans && K % 4) || (a_trans && M % 4)) return fail(nullptr, NMF_EINVAL, "K % 4 (a_trans=0) or M % 4 (a_trans=1) required");
+  if ((!a_trans && lda < K) || (a_trans && lda < M) || ldb < N) return fail(nullptr, NMF_EINVAL, "leading dimension too small");
+  const int s = gemm_f32_pick_splits(M, N, K, a_trans);
+  const size_t need = gemm_f32_part_floats(M, N, s) * sizeof(float);
+  if (need && (!ws || ws_bytes < need)) return fail(nullptr, NMF_ENOMEM, "workspace too small");
+  hipError_t e = launch_gemm_f32(A, lda, a_trans, B, ldb, C, ldc, M, N, K, s, (float*)ws, (hipStream_t)hs);
+  return e ? fail(nullptr, NMF_EHIP, hipGetErrorString(e)) : NMF_OK;
+}
+
+size_t nmf_orth_workspace_bytes(int64_t rows, int32_t k) {
+  const int s = gram_pick_splits(rows, k);
+  return ((size_t)s * k * k + (size_t)k * k) * sizeof(double) + 8 * sizeof(int) + 512;
+}
+
+nmf_status nmf_orth(float* Y, int64_t ldy, int64_t rows, int32_t k, void* ws, size_t ws_bytes,
+                    void* hs, int32_t* shifted) {
+  if (!Y || rows < k || k <= 0 || k > 128 || ldy < k || ldy % 4) return fail(nullptr, NMF_EINVAL, "bad arguments");
+  if (!ws || ws_bytes < nmf_orth_workspace_bytes(rows, k) || ((uintptr_t)ws & 255)) return fail(nullptr, NMF_ENOMEM, "workspace too small or misaligned");
+  const int s = gram_pick_splits(rows, k);
+  char* p = (char*)ws;
+  double* gp = (double*)p;
+  p += (size_t)s * k * k * sizeof(double);
+  double* R = (double*)p;
+  p += (size_t)k * k * sizeof(double);
+  int* status = (int*)p;
+  hipStream_t st = (hipStream_t)hs;
+  hipError_t e = launch_fill_i32(status, 8, 0, st);
+  if (!e) e = orth(Y, ldy, rows, k, gp, R, status, st);
+  int h[2] = {0, 0};
+  if (!e) e = hipMemcpyAsync(h, status, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (!e) e = hipStreamSynchronize(st);
+  if (e) return fail(nullptr, NMF_EHIP, hipGetErrorString(e));
+  if (shifted) *shifted = h[0];
+  if (h[1]) return fail(nullptr, NMF_EBREAKDOWN, "Cholesky breakdown even with the shift");
+  return NMF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,249 @@
+"""Thin ctypes binding of libnmfrp.so (declared in include/nmfrp.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+the library.  torch supplies device memory (workspace, inputs, outputs) and the
+current HIP stream.  There is no CPU fallback: if the library is not built, or
+the tensors are not on the GPU, the calls raise.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnmfrp.so")
+
+NMF_FP32, NMF_BF16, NMF_FP8_E4M3 = 0, 1, 2
+STATUS = {0: "NMF_OK", -1: "NMF_EINVAL", -2: "NMF_ENOMEM", -3: "NMF_EHIP", -4: "NMF_ESTATE",
+          -5: "NMF_EBREAKDOWN", -6: "NMF_ENONFINITE"}
+
+c_i64, c_i32, c_u32, c_u64, c_sz, c_vp = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
+                                           ctypes.c_uint64, ctypes.c_size_t, ctypes.c_void_p)
+c_dbl_p = ctypes.POINTER(ctypes.c_double)
+c_i32_p = ctypes.POINTER(ctypes.c_int32)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("m", c_i64), ("n", c_i64), ("r", c_i32), ("k_sketch", c_i32), ("q", c_i32),
+                ("prec", c_i32), ("refine_fp32", c_i32), ("normalize", c_i32),
+                ("alpha", ctypes.c_float), ("beta", ctypes.c_float), ("seed", c_u64)]
+
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "nmf_workspace_bytes": (c_sz, [ctypes.POINTER(Params)]),
+    "nmf_create": (c_i32, [ctypes.POINTER(Params), c_vp, c_sz, c_vp, ctypes.POINTER(c_vp)]),
+    "nmf_destroy": (None, [c_vp]),
+    "nmf_last_error": (ctypes.c_char_p, [c_vp]),
+    "nmf_validate": (c_i32, [c_vp, c_vp, c_i64]),
+    "nmf_compress": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp]),
+    "nmf_init": (c_i32, [c_vp, c_vp, c_vp, ctypes.c_float]),
+    "nmf_step": (c_i32, [c_vp, c_i32]),
+    "nmf_residual": (c_i32, [c_vp, c_vp, c_i64, c_dbl_p]),
+    "nmf_fit": (c_i32, [c_vp, c_vp, c_i64, c_i32, ctypes.c_double, c_i32, c_i32_p, c_dbl_p]),
+    "nmf_get_factors": (c_i32, [c_vp, c_vp, c_vp]),
+    "nmf_get_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "nmf_set_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "nmf_sync": (c_i32, [c_vp, c_i32_p]),
+    "nmf_stage_times": (c_i32, [c_vp, c_dbl_p, c_dbl_p, c_dbl_p]),
+    "nmf_gaussian": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_u32, c_u64, c_vp]),
+    "nmf_uniform": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_u32, c_u64, ctypes.c_float, c_vp]),
+    "nmf_gemm_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64, c_i32]),
+    "nmf_gemm": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_i64, c_vp, c_i64, c_i64, c_i64, c_i64, c_vp,
+                         c_sz, c_vp]),
+    "nmf_orth_workspace_bytes": (c_sz, [c_i64, c_i32]),
+    "nmf_orth": (c_i32, [c_vp, c_i64, c_i64, c_i32, c_vp, c_sz, c_vp, c_i32_p]),
+}
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Loads the library (once) and declares every exported signature."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is not built; run python -m paper_1712_02248_amd.build")
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class NmfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status, ctx=None):
+    if status != 0:
+        msg = load().nmf_last_error(ctx)
+        raise NmfError(status, msg.decode() if msg else "")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor required")
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _f32(t, shape, name):
+    if t is None:
+        return None
+    if t.dtype != torch.float32 or not t.is_cuda or tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError(f"{name}: need a contiguous float32 device tensor of shape {shape}")
+    return t
+
+
+class NMF:
+    """Context over a torch-allocated workspace.
+
+    X (m x n) stays a borrowed torch tensor; W (m x r) and Ht (n x r) are the
+    paper's A and B.
+    """
+
+    def __init__(self, m, n, r, k_sketch, q, seed=0, normalize=1, alpha=0.0, beta=0.0,
+                 prec=NMF_FP32, refine_fp32=0, device="cuda", stream=None):
+        lib = load()
+        self.p = Params(m, n, r, k_sketch, q, prec, refine_fp32, normalize, alpha, beta, seed)
+        nbytes = lib.nmf_workspace_bytes(ctypes.byref(self.p))
+        if nbytes == 0:
+            _check(-1)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        self._wsptr = (base + 255) // 256 * 256
+        self.stream = stream
+        h = c_vp()
+        _check(lib.nmf_create(ctypes.byref(self.p), self._wsptr, nbytes, _stream(stream), ctypes.byref(h)))
+        self.h = h
+        self.m, self.n, self.r, self.kp = m, n, r, k_sketch
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().nmf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _c(self, status):
+        _check(status, self.h)
+
+    def validate(self, X):
+        self._c(load().nmf_validate(self.h, _ptr(X), X.stride(0)))
+
+    def compress(self, X, omega_L=None, omega_R=None):
+        _f32(omega_L, (self.n, self.kp), "omega_L")
+        _f32(omega_R, (self.m, self.kp), "omega_R")
+        if X.dtype != torch.float32 or X.stride(1) != 1:
+            raise ValueError("X: float32, unit column stride")
+        self._c(load().nmf_compress(self.h, _ptr(X), X.stride(0), _ptr(omega_L), _ptr(omega_R)))
+
+    def init(self, W0=None, Ht0=None, init_scale=1.0):
+        _f32(W0, (self.m, self.r), "W0")
+        _f32(Ht0, (self.n, self.r), "Ht0")
+        self._c(load().nmf_init(self.h, _ptr(W0), _ptr(Ht0), float(init_scale)))
+
+    def step(self, iters=1):
+        self._c(load().nmf_step(self.h, int(iters)))
+
+    def residual(self, X):
+        e = ctypes.c_double()
+        self._c(load().nmf_residual(self.h, _ptr(X), X.stride(0), ctypes.byref(e)))
+        return e.value
+
+    def fit(self, X, max_iters, eps=0.0, check_every=10):
+        it = c_i32()
+        e = ctypes.c_double()
+        self._c(load().nmf_fit(self.h, _ptr(X), X.stride(0), int(max_iters), float(eps), int(check_every),
+                               ctypes.byref(it), ctypes.byref(e)))
+        return it.value, e.value
+
+    def factors(self):
+        W = torch.empty(self.m, self.r, dtype=torch.float32, device=self.ws.device)
+        Ht = torch.empty(self.n, self.r, dtype=torch.float32, device=self.ws.device)
+        self._c(load().nmf_get_factors(self.h, _ptr(W), _ptr(Ht)))
+        return W, Ht
+
+    def state(self):
+        dev = self.ws.device
+        QL = torch.empty(self.m, self.kp, dtype=torch.float32, device=dev)
+        QR = torch.empty(self.n, self.kp, dtype=torch.float32, device=dev)
+        Xh = torch.empty(self.n, self.kp, dtype=torch.float32, device=dev)
+        Xc = torch.empty(self.m, self.kp, dtype=torch.float32, device=dev)
+        self._c(load().nmf_get_state(self.h, _ptr(QL), _ptr(QR), _ptr(Xh), _ptr(Xc)))
+        return QL, QR, Xh, Xc
+
+    def set_state(self, QL, QR, Xh, Xc):
+        _f32(QL, (self.m, self.kp), "QL")
+        _f32(QR, (self.n, self.kp), "QR")
+        _f32(Xh, (self.n, self.kp), "Xh")
+        _f32(Xc, (self.m, self.kp), "Xc")
+        self._c(load().nmf_set_state(self.h, _ptr(QL), _ptr(QR), _ptr(Xh), _ptr(Xc)))
+
+    def sync(self):
+        s = c_i32()
+        self._c(load().nmf_sync(self.h, ctypes.byref(s)))
+        return s.value
+
+    def stage_times(self):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._c(load().nmf_stage_times(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return dict(compress_ms=a.value, step_ms=b.value, residual_ms=c.value)
+
+
+def gaussian(rows, cols, stream_id, seed, device="cuda", stream=None):
+    out = torch.empty(rows, cols, dtype=torch.float32, device=device)
+    _check(load().nmf_gaussian(_ptr(out), rows, cols, cols, stream_id, seed, _stream(stream)))
+    return out
+
+
+def uniform(rows, cols, stream_id, seed, scale=1.0, device="cuda", stream=None):
+    out = torch.empty(rows, cols, dtype=torch.float32, device=device)
+    _check(load().nmf_uniform(_ptr(out), rows, cols, cols, stream_id, seed, float(scale), _stream(stream)))
+    return out
+
+
+def gemm(A, B, a_trans=False, out=None, stream=None):
+    """C = A @ B (a_trans=False) or A.T @ B (a_trans=True), FP32 MFMA."""
+    lib = load()
+    if a_trans:
+        K, M = A.shape
+    else:
+        M, K = A.shape
+    K2, N = B.shape
+    if K2 != K:
+        raise ValueError("shape mismatch")
+    if out is None:
+        out = torch.empty(M, N, dtype=torch.float32, device=A.device)
+    nb = lib.nmf_gemm_workspace_bytes(M, N, K, int(a_trans))
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=A.device)
+    _check(lib.nmf_gemm(_ptr(A), A.stride(0), int(a_trans), _ptr(B), B.stride(0), _ptr(out), out.stride(0),
+                        M, N, K, _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def orth(Y, stream=None):
+    """In-place CholeskyQR2 of Y (rows x k); returns the shifted flag."""
+    lib = load()
+    rows, k = Y.shape
+    nb = lib.nmf_orth_workspace_bytes(rows, k)
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device=Y.device)
+    base = (ws.data_ptr() + 255) // 256 * 256
+    sh = c_i32()
+    _check(lib.nmf_orth(_ptr(Y), Y.stride(0), rows, k, base, nb, _stream(stream), ctypes.byref(sh)))
+    return sh.value

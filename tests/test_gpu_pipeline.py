@@ -1,0 +1,173 @@
+"""End-to-end parity of compress / init / step / residual / fit (HIP path,
+through the C ABI) against the FP64 oracle on the same seeded inputs (GPU)."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+from oracle import nmf as onmf
+from oracle import philox as ophilox
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_1712_02248_amd import nmfrp
+    nmfrp.load()
+    return nmfrp
+
+
+def proj(Q):
+    Q = np.asarray(Q, dtype=np.float64)
+    return Q @ Q.T
+
+
+def small_case(m, n, r, kp, seed, family="c1"):
+    if family == "c1":
+        X = datagen.planted_c1(m, n, r, seed)[0]
+    else:
+        X = datagen.planted_parts(m, n, r, seed)[0]
+    OL = datagen.gaussian(n, kp, seed, datagen.S_OMEGA_L)
+    OR = datagen.gaussian(m, kp, seed, datagen.S_OMEGA_R)
+    W0, H0 = datagen.init_factors(X.mean(), m, n, r, seed)
+    return X, OL, OR, W0, H0
+
+
+def gpu_run(lib, X, OL, OR, W0, H0, r, kp, q, iters, normalize=1, omega=True):
+    m, n = X.shape
+    ctx = lib.NMF(m, n, r, kp, q, seed=7, normalize=normalize)
+    Xd = torch.from_numpy(X).cuda()
+    if omega:
+        ctx.compress(Xd, torch.from_numpy(OL).cuda(), torch.from_numpy(OR).cuda())
+    else:
+        ctx.compress(Xd)
+    ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
+    if iters:
+        ctx.step(iters)
+    return ctx, Xd
+
+
+def test_c1_compression_projectors(lib):
+    print("c1 compression projectors", flush=True)
+    m, n, r, kp, q = 512, 256, 10, 20, 2
+    X, OL, OR, W0, H0 = small_case(m, n, r, kp, datagen.cfg_seed("c1"))
+    ctx, Xd = gpu_run(lib, X, OL, OR, W0, H0, r, kp, q, 0)
+    QL, QR, Xh, Xc = (t.cpu().numpy().astype(np.float64) for t in ctx.state())
+    assert ctx.sync() == 0
+    rQL, rQR, rXh, rXc = onmf.compress(X, OL, OR, q)
+    assert np.abs(QL.T @ QL - np.eye(kp)).max() < 2e-6
+    assert np.abs(QR.T @ QR - np.eye(kp)).max() < 2e-6
+    assert np.abs(proj(QL) - proj(rQL)).max() < 1e-4
+    assert np.abs(proj(QR) - proj(rQR)).max() < 1e-4
+    # rotation-invariant sketch checks: X^T P_L and X P_R
+    sx = np.abs(X).max()
+    assert np.abs(Xh @ QL.T - rXh @ rQL.T).max() < 1e-4 * sx
+    assert np.abs(Xc @ QR.T - rXc @ rQR.T).max() < 1e-4 * sx
+
+
+def test_residual_matches_oracle(lib):
+    print("residual", flush=True)
+    m, n, r, kp = 700, 300, 7, 12
+    g = np.random.default_rng(1)
+    X = g.random((m, n)).astype(np.float32)
+    W = g.random((m, r)).astype(np.float32)
+    Ht = g.random((n, r)).astype(np.float32)
+    ctx = lib.NMF(m, n, r, kp, 1, seed=3)
+    Xd = torch.from_numpy(X).cuda()
+    ctx.compress(Xd)
+    ctx.init(torch.from_numpy(W).cuda(), torch.from_numpy(Ht).cuda())
+    e = ctx.residual(Xd)
+    assert abs(e - onmf.rel_error(X, W, Ht)) <= 1e-12 * onmf.rel_error(X, W, Ht)
+
+
+@pytest.mark.parametrize("normalize", [1, 0, 2])
+def test_c1_first_iterations_elementwise(lib, normalize):
+    print(f"c1 iterations normalize={normalize}", flush=True)
+    m, n, r, kp, q = 512, 256, 10, 20, 2
+    X, OL, OR, W0, H0 = small_case(m, n, r, kp, datagen.cfg_seed("c1"))
+    rQL, rQR, rXh, rXc = onmf.compress(X, OL, OR, q)
+    W, Ht = W0.astype(np.float64), H0.astype(np.float64)
+    for iters in (1, 2, 5):
+        ctx, Xd = gpu_run(lib, X, OL, OR, W0, H0, r, kp, q, iters, normalize)
+        Wg, Hg = (t.cpu().numpy().astype(np.float64) for t in ctx.factors())
+        W, Ht = W0.astype(np.float64), H0.astype(np.float64)
+        for _ in range(iters):
+            W, Ht = onmf.fasthals_rp_iteration(W, Ht, rXh, rXc, rQL, rQR, normalize)
+        tol = 2e-3 * iters
+        assert np.abs(Wg - W).max() <= tol * np.abs(W).max(), iters
+        assert np.abs(Hg - Ht).max() <= tol * np.abs(Ht).max(), iters
+        assert (Wg >= 0).all() and (Hg >= 0).all()
+
+
+def test_c1_full_parity_200_iterations(lib):
+    print("c1 200 iterations", flush=True)
+    c = datagen.CONFIGS["c1"]
+    m, n, r, kp, q, iters = c["m"], c["n"], c["r"], c["kp"], c["q"], c["iters"]
+    X, OL, OR, W0, H0 = small_case(m, n, r, kp, datagen.cfg_seed("c1"))
+    ctx, Xd = gpu_run(lib, X, OL, OR, W0, H0, r, kp, q, iters)
+    e_gpu = ctx.residual(Xd)
+    ref = onmf.fasthals_rp(X, OL, OR, q, W0, H0, iters)
+    print(f"c1 e_gpu={e_gpu:.8e} e_oracle={ref['e']:.8e}", flush=True)
+    assert abs(e_gpu - ref["e"]) <= 1e-4
+
+
+def test_device_omega_matches_oracle_philox(lib):
+    """Omega drawn on the device (omega=NULL) equals the oracle's Philox draw, so the
+    oracle run on its own Philox Omega agrees with the GPU run."""
+    print("device omega", flush=True)
+    m, n, r, kp, q, iters = 512, 256, 10, 20, 2, 50
+    seed = datagen.cfg_seed("c1")
+    X, _, _, W0, H0 = small_case(m, n, r, kp, seed)
+    ctx = lib.NMF(m, n, r, kp, q, seed=seed)
+    Xd = torch.from_numpy(X).cuda()
+    ctx.compress(Xd)
+    ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
+    ctx.step(iters)
+    OL = ophilox.normal(n, kp, 3, seed).astype(np.float32)
+    OR = ophilox.normal(m, kp, 4, seed).astype(np.float32)
+    ref = onmf.fasthals_rp(X, OL, OR, q, W0, H0, iters)
+    assert abs(ctx.residual(Xd) - ref["e"]) <= 1e-4
+
+
+@pytest.mark.parametrize("m,n,r,kp,q", [(1000, 300, 5, 9, 1), (333, 1004, 17, 30, 2), (130, 64, 3, 4, 0),
+                                         (2000, 500, 40, 64, 1), (1500, 200, 60, 100, 1)])
+def test_ragged_shapes(lib, m, n, r, kp, q):
+    print(f"ragged m={m} n={n} r={r} kp={kp} q={q}", flush=True)
+    X, OL, OR, W0, H0 = small_case(m, n, r, kp, 99 + m, family="parts")
+    ctx, Xd = gpu_run(lib, X, OL, OR, W0, H0, r, kp, q, 20)
+    e_gpu = ctx.residual(Xd)
+    ref = onmf.fasthals_rp(X, OL, OR, q, W0, H0, 20)
+    assert abs(e_gpu - ref["e"]) <= 1e-4
+    QL, QR, _, _ = (t.cpu().numpy().astype(np.float64) for t in ctx.state())
+    assert np.abs(proj(QL) - proj(ref["QL"])).max() < 1e-3
+
+
+def test_fit_and_errors(lib):
+    print("fit", flush=True)
+    m, n, r, kp, q = 512, 256, 10, 20, 2
+    X, OL, OR, W0, H0 = small_case(m, n, r, kp, datagen.cfg_seed("c1"))
+    ctx = lib.NMF(m, n, r, kp, q, seed=5)
+    Xd = torch.from_numpy(X).cuda()
+    with pytest.raises(lib.NmfError):
+        ctx.step(1)                      # ESTATE before compress/init
+    ctx.compress(Xd, torch.from_numpy(OL).cuda(), torch.from_numpy(OR).cuda())
+    ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
+    it, e = ctx.fit(Xd, max_iters=200, eps=0.0, check_every=50)
+    assert it == 200
+    ref = onmf.fasthals_rp(X, OL, OR, q, W0, H0, 200)
+    assert abs(e - ref["e"]) <= 1e-4
+    # stop on eps
+    ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
+    it2, e2 = ctx.fit(Xd, max_iters=200, eps=1.05 * ref["e"], check_every=5)
+    assert it2 < 200 and e2 <= 1.05 * ref["e"]
+    # validation of X
+    ctx.validate(Xd)
+    bad = Xd.clone()
+    bad[3, 4] = -1.0
+    with pytest.raises(lib.NmfError):
+        ctx.validate(bad)
+    bad[3, 4] = float("nan")
+    with pytest.raises(lib.NmfError):
+        ctx.validate(bad)
