@@ -105,9 +105,12 @@ nmf_status nmf_step(nmf_ctx* ctx, int32_t iters);
 /* Exact e = ||X - W Ht^T||_F / ||X||_F in FP64 (eq 2.2).  Synchronising. */
 nmf_status nmf_residual(nmf_ctx* ctx, const float* X, int64_t ldx, double* rel_err);
 
-/* Runs steps in chunks of check_every, evaluating the exact residual after each
- * chunk, until e <= eps or max_iters iterations (the paper leaves the stopping
- * rule open: Alg 1-4).  Synchronising.  *iters_done and *rel_err report. */
+/* Runs steps in chunks, evaluating the exact residual after each chunk, until
+ * e <= eps or max_iters iterations (the paper leaves the stopping rule open:
+ * Alg 1-4).  check_every > 0: fixed chunk; check_every == 0: adaptive chunks of
+ * 50, 20 or 10 iterations while the last e exceeds eps by more than 10 %, 1 %
+ * or less.  max_iters == 0 only evaluates e.  Synchronising.  *iters_done and
+ * *rel_err report the iterations run and the last e. */
 nmf_status nmf_fit(nmf_ctx* ctx, const float* X, int64_t ldx, int32_t max_iters, double eps,
                    int32_t check_every, int32_t* iters_done, double* rel_err);
 

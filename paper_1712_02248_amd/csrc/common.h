@@ -38,46 +38,46 @@ hipError_t launch_gemm_f32(const float* A, int64_t lda, int a_trans, const float
 int gemm_f32_pick_splits(int64_t M, int64_t N, int64_t K, int a_trans);
 
 // Tall-skinny QR pieces (qr.hip).
+// G = Y^T Y in FP64: split partials, then the deterministic sum into G (k x k).
 hipError_t launch_gram_f64(const float* Y, int64_t ldy, int64_t rows, int k, double* part,
-                           int splits, const int* skip_flag, hipStream_t st);
+                           int splits, double* G, const int* skip_flag, hipStream_t st);
 int gram_pick_splits(int64_t rows, int k);
-hipError_t launch_cholesky(const double* part, int splits, int k, int64_t rows, double* Rinv,
-                           int* status, int attempt, hipStream_t st);
+hipError_t launch_cholesky(const double* G, int k, int64_t rows, double* Rinv, int* status,
+                           int attempt, hipStream_t st);
 hipError_t launch_apply_rinv(float* Y, int64_t ldy, int64_t rows, int k, const double* Rinv,
                              const int* status, int attempt, hipStream_t st);
 
-// Fused HALS half-step and its finalisation (hals.hip).
+// Fused HALS half-step (hals.hip).  The kernel derives its compressed factor C
+// and Gram G from the other side's summed partials (acc_in), sweeps the rows of
+// F, and leaves its own summed partials in acc_out (Qb^T F, then the column sums
+// of F^2) for the next half-step.
 struct HalfStepArgs {
-  const float* S;      // N x kp sketch (ld lds): Xc for the W side, Xh for the H side
+  const float* S;       // N x kp sketch (ld lds): Xc for the W side, Xh for the H side
   int64_t lds;
-  const float* C;      // kp x r compressed other factor (ld r): Hc or Wh
-  const float* G;      // r x r Gram of C
-  float* F;            // N x r factor updated in place (ld r): W or Ht
-  const float* scale;  // r column scales applied to F on load (NULL = none)
-  const float* Qb;     // N x kp basis (ld ldq) for re-compression: Q_L or Q_R
+  const double* acc_in; // kp*r + r: the other side's Qb'^T F' and column sums of F'^2
+  int norm_in;          // 1: acc_in comes from the W side; normalise C by its column norms
+  int normalize;        // 0 none, 1 compensated, 2 literal
+  float* F;             // N x r factor updated in place (ld r): W or Ht
+  const float* scale;   // r column scales for F on load when norm_in == 0 (NULL = 1)
+  float* scale_pub;     // workgroup 0 writes 1/||a_j|| here (NULL = skip)
+  float* C_pub;         // workgroup 0 writes C (kp x r) here (NULL = skip)
+  float* G_pub;         // workgroup 0 writes G (r x r) here (NULL = skip)
+  const float* Qb;      // N x kp basis (ld ldq) for re-compression: Q_L or Q_R
   int64_t ldq;
   int64_t N;
   int kp, r;
-  float* part;         // nblk x (kp*r + r) partial Qb^T F and column sums of F^2
-  float alpha, beta;   // sparsity / smoothness (0, 0 = plain rule)
+  float* part;          // nblk x (kp*r + r) workgroup partials
+  double* acc_out;      // kp*r + r summed partials of this half-step
+  float alpha, beta;    // sparsity / smoothness (0, 0 = plain rule)
 };
 int halfstep_blocks(int64_t N);
 size_t halfstep_part_floats(int64_t N, int kp, int r);
 hipError_t launch_halfstep(const HalfStepArgs& a, int do_sweep, hipStream_t st);
-
-struct FinalizeArgs {
-  const float* part;   // nblk x (kp*r + r)
-  int nblk, kp, r;
-  int normalize;       // 0 none, 1 compensated, 2 literal
-  int use_norms;       // 1: this side's column norms drive normalisation
-  float* C;            // kp x r output (scaled by 1/s when normalising)
-  float* G;            // r x r output C^T C
-  float* scale_self;   // r: scale to apply to this side's factor on next load (1/s)
-  float* scale_other;  // r: scale to apply to the other factor on next load (s)
-  double* accum;       // scratch kp*r + r doubles
-  unsigned* counter;   // zero-initialised completion counter
-};
-hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t st);
+// out[e] = sum_s part[s * ne + e] in FP64, fixed order (skip: NULL or flag; skipped when *skip == 0).
+hipError_t launch_sum_partials_f32(const float* part, int nparts, int64_t ne, double* out,
+                                   hipStream_t st);
+hipError_t launch_sum_partials_f64(const double* part, int nparts, int64_t ne, double* out,
+                                   const int* skip, hipStream_t st);
 
 // Residual (residual.hip): sum (X - W diag(sw) Ht^T)^2 and sum X^2 in FP64.
 int residual_blocks(int64_t m, int64_t n);

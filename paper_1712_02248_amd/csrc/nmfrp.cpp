@@ -28,8 +28,8 @@ struct Plan {
 struct Layout {
   int64_t KP;  // k' padded to a multiple of 4 (padding columns stay zero)
   size_t omL, omR, QL, TM, Xc, QR, TN, Xh, W, Ht;
-  size_t gemm_part, gram_part, R, qr_status;
-  size_t hs_part, accum, counters, Hc, GH, Wh, GW, scale_w, scale_h;
+  size_t gemm_part, gram_part, G, R, qr_status;
+  size_t hs_part, acc_w, acc_h, counters, Hc, GH, Wh, GW, scale_w;
   size_t res_part, res_out, flags;
   size_t total;
   size_t gemm_part_bytes, gram_splits_max;
@@ -74,18 +74,19 @@ Layout make_layout(const nmf_params* p) {
   const int gs1 = gram_pick_splits(m, k), gs2 = gram_pick_splits(n, k);
   L.gram_splits_max = gs1 > gs2 ? gs1 : gs2;
   L.gram_part = pl.take(L.gram_splits_max * k * k * d);
+  L.G = pl.take(k * k * d);
   L.R = pl.take(k * k * d);
   L.qr_status = pl.take(8 * sizeof(int));
   size_t h1 = halfstep_part_floats(m, (int)L.KP, (int)r), h2 = halfstep_part_floats(n, (int)L.KP, (int)r);
   L.hs_part = pl.take((h1 > h2 ? h1 : h2) * f);
-  L.accum = pl.take((L.KP * r + r) * d);
+  L.acc_w = pl.take((L.KP * r + r) * d);
+  L.acc_h = pl.take((L.KP * r + r) * d);
   L.counters = pl.take(8 * sizeof(unsigned));
   L.Hc = pl.take(L.KP * r * f);
   L.GH = pl.take(r * r * f);
   L.Wh = pl.take(L.KP * r * f);
   L.GW = pl.take(r * r * f);
   L.scale_w = pl.take(r * f);
-  L.scale_h = pl.take(r * f);
   L.res_part = pl.take(2 * (size_t)residual_blocks(m, n) * d);
   L.res_out = pl.take(2 * d);
   L.flags = pl.take(8 * sizeof(int));
@@ -125,15 +126,15 @@ nmf_status fail(nmf_ctx* c, nmf_status s, const std::string& msg) {
   } while (0)
 
 // orthonormalise Y (rows x k, ld) in place: CholeskyQR2 + conditional third pass
-hipError_t orth(float* Y, int64_t ld, int64_t rows, int k, double* gram_part, double* R,
-                int* status, hipStream_t st) {
+hipError_t orth(float* Y, int64_t ld, int64_t rows, int k, double* gram_part, double* G,
+                double* R, int* status, hipStream_t st) {
   hipError_t e;
   const int splits = gram_pick_splits(rows, k);
   if ((e = launch_fill_i32(status, 1, 0, st)) != hipSuccess) return e;   // shift flag
   for (int attempt = 0; attempt < 3; ++attempt) {
-    if ((e = launch_gram_f64(Y, ld, rows, k, gram_part, splits, attempt == 2 ? status : nullptr, st)))
+    if ((e = launch_gram_f64(Y, ld, rows, k, gram_part, splits, G, attempt == 2 ? status : nullptr, st)))
       return e;
-    if ((e = launch_cholesky(gram_part, splits, k, rows, R, status, attempt, st))) return e;
+    if ((e = launch_cholesky(G, k, rows, R, status, attempt, st))) return e;
     if ((e = launch_apply_rinv(Y, ld, rows, k, R, status, attempt, st))) return e;
   }
   return hipSuccess;
@@ -147,46 +148,37 @@ hipError_t gemm(nmf_ctx* c, const float* A, int64_t lda, int at, const float* B,
                          c->at<float>(c->L.gemm_part), c->st);
 }
 
+// W half-step: sweep W against (Xc, Hc, G_H) derived from the summed H-side
+// partials; leaves Q_L^T W and the column sums of W^2 in acc_w.
 hipError_t halfstep_w(nmf_ctx* c) {
   Layout& L = c->L;
   HalfStepArgs a;
   a.S = c->at<float>(L.Xc); a.lds = L.KP;
-  a.C = c->at<float>(L.Hc); a.G = c->at<float>(L.GH);
-  a.F = c->at<float>(L.W); a.scale = c->at<float>(L.scale_w);
+  a.acc_in = c->at<double>(L.acc_h); a.norm_in = 0; a.normalize = c->p.normalize;
+  a.F = c->at<float>(L.W); a.scale = c->at<float>(L.scale_w); a.scale_pub = nullptr;
+  a.C_pub = c->at<float>(L.Hc); a.G_pub = c->at<float>(L.GH);
   a.Qb = c->at<float>(L.QL); a.ldq = L.KP;
   a.N = c->p.m; a.kp = (int)L.KP; a.r = c->p.r;
-  a.part = c->at<float>(L.hs_part);
+  a.part = c->at<float>(L.hs_part); a.acc_out = c->at<double>(L.acc_w);
   a.alpha = 0.f; a.beta = 0.f;
-  hipError_t e = launch_halfstep(a, 1, c->st);
-  if (e) return e;
-  FinalizeArgs f;
-  f.part = a.part; f.nblk = halfstep_blocks(c->p.m); f.kp = (int)L.KP; f.r = c->p.r;
-  f.normalize = c->p.normalize; f.use_norms = 1;
-  f.C = c->at<float>(L.Wh); f.G = c->at<float>(L.GW);
-  f.scale_self = c->at<float>(L.scale_w); f.scale_other = c->at<float>(L.scale_h);
-  f.accum = c->at<double>(L.accum); f.counter = c->at<unsigned>(L.counters);
-  return launch_finalize(f, c->st);
+  return launch_halfstep(a, 1, c->st);
 }
 
+// H half-step: normalise W's columns (compensated in Ht), sweep Ht against
+// (Xh, Wh, G_W); leaves Q_R^T Ht in acc_h.  do_sweep = 0 only forms acc_h.
 hipError_t halfstep_h(nmf_ctx* c, int do_sweep) {
   Layout& L = c->L;
   HalfStepArgs a;
   a.S = c->at<float>(L.Xh); a.lds = L.KP;
-  a.C = c->at<float>(L.Wh); a.G = c->at<float>(L.GW);
-  a.F = c->at<float>(L.Ht); a.scale = do_sweep ? c->at<float>(L.scale_h) : nullptr;
+  a.acc_in = c->at<double>(L.acc_w); a.norm_in = do_sweep; a.normalize = c->p.normalize;
+  a.F = c->at<float>(L.Ht); a.scale = nullptr;
+  a.scale_pub = do_sweep ? c->at<float>(L.scale_w) : nullptr;
+  a.C_pub = do_sweep ? c->at<float>(L.Wh) : nullptr; a.G_pub = do_sweep ? c->at<float>(L.GW) : nullptr;
   a.Qb = c->at<float>(L.QR); a.ldq = L.KP;
   a.N = c->p.n; a.kp = (int)L.KP; a.r = c->p.r;
-  a.part = c->at<float>(L.hs_part);
+  a.part = c->at<float>(L.hs_part); a.acc_out = c->at<double>(L.acc_h);
   a.alpha = c->p.alpha; a.beta = c->p.beta;
-  hipError_t e = launch_halfstep(a, do_sweep, c->st);
-  if (e) return e;
-  FinalizeArgs f;
-  f.part = a.part; f.nblk = halfstep_blocks(c->p.n); f.kp = (int)L.KP; f.r = c->p.r;
-  f.normalize = c->p.normalize; f.use_norms = 0;
-  f.C = c->at<float>(L.Hc); f.G = c->at<float>(L.GH);
-  f.scale_self = nullptr; f.scale_other = nullptr;
-  f.accum = c->at<double>(L.accum); f.counter = c->at<unsigned>(L.counters);
-  return launch_finalize(f, c->st);
+  return launch_halfstep(a, do_sweep, c->st);
 }
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
@@ -257,7 +249,7 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
   float *omL = c->at<float>(L.omL), *omR = c->at<float>(L.omR);
   float *QL = c->at<float>(L.QL), *TM = c->at<float>(L.TM), *Xc = c->at<float>(L.Xc);
   float *QR = c->at<float>(L.QR), *TN = c->at<float>(L.TN), *Xh = c->at<float>(L.Xh);
-  double *gp = c->at<double>(L.gram_part), *R = c->at<double>(L.R);
+  double *gp = c->at<double>(L.gram_part), *G = c->at<double>(L.G), *R = c->at<double>(L.R);
   int* qs = c->at<int>(L.qr_status);
   HIPCHK(c, hipEventRecord(c->ev[0], st));
   HIPCHK(c, launch_fill_i32(qs, 8, 0, st));
@@ -268,21 +260,21 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
   else HIPCHK(c, launch_philox_normal(omR, m, k, L.KP, 4u, c->p.seed, st));
   // left range finder: Q_L = orth(X Omega_L); q x { Z = orth(X^T Q_L); Q_L = orth(X Z) }
   HIPCHK(c, gemm(c, X, ldx, 0, omL, QL, m, n));
-  HIPCHK(c, orth(QL, L.KP, m, k, gp, R, qs, st));
+  HIPCHK(c, orth(QL, L.KP, m, k, gp, G, R, qs, st));
   for (int it = 0; it < q; ++it) {
     HIPCHK(c, gemm(c, X, ldx, 1, QL, TN, n, m));
-    HIPCHK(c, orth(TN, L.KP, n, k, gp, R, qs, st));
+    HIPCHK(c, orth(TN, L.KP, n, k, gp, G, R, qs, st));
     HIPCHK(c, gemm(c, X, ldx, 0, TN, QL, m, n));
-    HIPCHK(c, orth(QL, L.KP, m, k, gp, R, qs, st));
+    HIPCHK(c, orth(QL, L.KP, m, k, gp, G, R, qs, st));
   }
   // right range finder on X^T with Omega_R
   HIPCHK(c, gemm(c, X, ldx, 1, omR, QR, n, m));
-  HIPCHK(c, orth(QR, L.KP, n, k, gp, R, qs, st));
+  HIPCHK(c, orth(QR, L.KP, n, k, gp, G, R, qs, st));
   for (int it = 0; it < q; ++it) {
     HIPCHK(c, gemm(c, X, ldx, 0, QR, TM, m, n));
-    HIPCHK(c, orth(TM, L.KP, m, k, gp, R, qs, st));
+    HIPCHK(c, orth(TM, L.KP, m, k, gp, G, R, qs, st));
     HIPCHK(c, gemm(c, X, ldx, 1, TM, QR, n, m));
-    HIPCHK(c, orth(QR, L.KP, n, k, gp, R, qs, st));
+    HIPCHK(c, orth(QR, L.KP, n, k, gp, G, R, qs, st));
   }
   // projected data (Sec 4): Xh = X^T Q_L (X-hat^T), Xc = X Q_R (X-check)
   HIPCHK(c, gemm(c, X, ldx, 1, QL, Xh, n, m));
@@ -305,8 +297,7 @@ nmf_status nmf_init(nmf_ctx* c, const float* W0, const float* Ht0, float init_sc
   if (Ht0) HIPCHK(c, launch_copy2d(Ht, r, Ht0, r, n, r, c->st));
   else HIPCHK(c, launch_philox_uniform(Ht, n, r, r, 6u, c->p.seed, init_scale, c->st));
   HIPCHK(c, launch_fill_f32(c->at<float>(L.scale_w), r, 1.f, c->st));
-  HIPCHK(c, launch_fill_f32(c->at<float>(L.scale_h), r, 1.f, c->st));
-  HIPCHK(c, halfstep_h(c, 0));   // Hc = Q_R^T Ht, G_H = Hc^T Hc
+  HIPCHK(c, halfstep_h(c, 0));   // acc_h = Q_R^T Ht (Hc for the first W half-step)
   c->initialized = true;
   return NMF_OK;
 }
@@ -347,16 +338,24 @@ nmf_status nmf_residual(nmf_ctx* c, const float* X, int64_t ldx, double* rel_err
 
 nmf_status nmf_fit(nmf_ctx* c, const float* X, int64_t ldx, int32_t max_iters, double eps,
                    int32_t check_every, int32_t* iters_done, double* rel_err) {
-  if (!c || !X || check_every <= 0 || max_iters < 0) return fail(c, NMF_EINVAL, "bad arguments");
+  if (!c || !X || check_every < 0 || max_iters < 0) return fail(c, NMF_EINVAL, "bad arguments");
   int done = 0;
   double e = 0.0;
-  nmf_status s = nmf_residual(c, X, ldx, &e);
-  if (s != NMF_OK) return s;
-  while (done < max_iters && !(e <= eps)) {
-    int chunk = check_every < max_iters - done ? check_every : max_iters - done;
+  nmf_status s;
+  if (max_iters == 0) {
+    if ((s = nmf_residual(c, X, ldx, &e)) != NMF_OK) return s;
+  }
+  int chunk = check_every > 0 ? check_every : 50;
+  while (done < max_iters) {
+    if (chunk > max_iters - done) chunk = max_iters - done;
     if ((s = nmf_step(c, chunk)) != NMF_OK) return s;
     done += chunk;
     if ((s = nmf_residual(c, X, ldx, &e)) != NMF_OK) return s;
+    if (e <= eps) break;
+    if (check_every == 0) {   // adaptive: check more often as e approaches eps
+      const double gap = (e - eps) / (eps > 0 ? eps : 1.0);
+      chunk = gap > 0.1 ? 50 : gap > 0.01 ? 20 : 10;
+    }
   }
   if (iters_done) *iters_done = done;
   if (rel_err) *rel_err = e;
@@ -457,7 +456,7 @@ nmf_status nmf_gemm(const float* A, int64_t lda, int32_t a_trans, const float* B
 
 size_t nmf_orth_workspace_bytes(int64_t rows, int32_t k) {
   const int s = gram_pick_splits(rows, k);
-  return ((size_t)s * k * k + (size_t)k * k) * sizeof(double) + 8 * sizeof(int) + 512;
+  return ((size_t)s * k * k + 2 * (size_t)k * k) * sizeof(double) + 8 * sizeof(int) + 512;
 }
 
 nmf_status nmf_orth(float* Y, int64_t ldy, int64_t rows, int32_t k, void* ws, size_t ws_bytes,
@@ -468,12 +467,14 @@ nmf_status nmf_orth(float* Y, int64_t ldy, int64_t rows, int32_t k, void* ws, si
   char* p = (char*)ws;
   double* gp = (double*)p;
   p += (size_t)s * k * k * sizeof(double);
+  double* G = (double*)p;
+  p += (size_t)k * k * sizeof(double);
   double* R = (double*)p;
   p += (size_t)k * k * sizeof(double);
   int* status = (int*)p;
   hipStream_t st = (hipStream_t)hs;
   hipError_t e = launch_fill_i32(status, 8, 0, st);
-  if (!e) e = orth(Y, ldy, rows, k, gp, R, status, st);
+  if (!e) e = orth(Y, ldy, rows, k, gp, G, R, status, st);
   int h[2] = {0, 0};
   if (!e) e = hipMemcpyAsync(h, status, sizeof(h), hipMemcpyDeviceToHost, st);
   if (!e) e = hipStreamSynchronize(st);

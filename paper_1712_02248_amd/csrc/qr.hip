@@ -2,23 +2,29 @@
 //   G = Y^T Y (FP64 MFMA, split over rows), G = R^T R (Cholesky), Q = Y R^{-1}
 // (R^{-1} formed with the factorisation; Y R^{-1} on FP64 MFMA, written back
 // as FP32 in place).
-// CholeskyQR2 runs this twice.  On a non-positive or non-finite pivot the
+// CholeskyQR2 runs this twice; the second pass is skipped when the second Gram
+// is already within 1e-6 of the identity (with FP64 Gram and R^{-1} on FP32 data
+// the first pass is orthonormal to ~k u kappa^2).  On a non-positive or non-finite pivot the
 // factorisation restarts with the shift s = 11 (rows k + k(k+1)) u tr(G)
 // (shifted CholeskyQR, Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa,
 // SIAM J. Sci. Comput. 2020), and a third pass is enabled (shifted CholeskyQR3).
 //
-// status[0]: 1 if the first pass needed the shift;  status[1]: 1 if a pass
-// failed even with the shift (the factor is then unusable).
+// status[0]: 1 if a pass needed the shift (enables the third pass);
+// status[1]: 1 if a pass failed even with the shift (sticky);
+// status[2]: number of shifted factorisations (sticky);
+// status[3]: 1 if the second pass was skipped (the first was orthonormal).
 #include "common.h"
 
 namespace {
 
 constexpr int GT = 64;        // Gram output block (GT x GT) per workgroup
 constexpr int GROWS = 64;     // rows staged per chunk
+constexpr int GPT = GROWS * GT / 256;   // staged elements per thread
 
 // part[s] = Y[rows of split s]^T Y[rows of split s] restricted to the output
 // block (bi, bj).  f64 16x16x4 MFMA: A[i][kk] = Y[kk][i], B[kk][j] = Y[kk][j];
-// D[i][j] sits in lane j + 16 (i % 4), register i / 4.
+// D[i][j] sits in lane j + 16 (i % 4), register i / 4.  The loads of the next
+// chunk are issued before the MFMAs of the current one.
 __global__ void __launch_bounds__(256)
 gram_f64_kernel(const float* __restrict__ Y, int64_t ldy, int64_t rows, int k, int64_t rchunk,
                 double* __restrict__ part, const int* __restrict__ skip_flag) {
@@ -27,6 +33,7 @@ gram_f64_kernel(const float* __restrict__ Y, int64_t ldy, int64_t rows, int k, i
   __shared__ float Yj[GROWS][GT + 1];
   const int nb = (k + GT - 1) / GT;
   const int bi = blockIdx.x / nb, bj = blockIdx.x % nb;
+  const bool diag = (bi == bj);
   const int64_t r0 = (int64_t)blockIdx.y * rchunk;
   const int64_t r1 = (r0 + rchunk < rows) ? r0 + rchunk : rows;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -34,22 +41,35 @@ gram_f64_kernel(const float* __restrict__ Y, int64_t ldy, int64_t rows, int k, i
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = (f64x4){0, 0, 0, 0};
 
-  for (int64_t c0 = r0; c0 < r1; c0 += GROWS) {
-    for (int e = tid; e < GROWS * GT; e += 256) {
-      const int rr = e / GT, cc = e % GT;
+  float vi[GPT], vj[GPT];
+  auto load = [&](int64_t c0) {
+#pragma unroll
+    for (int p = 0; p < GPT; ++p) {
+      const int e = tid + 256 * p, rr = e / GT, cc = e % GT;
       const int64_t gr = c0 + rr;
       const int gi = bi * GT + cc, gj = bj * GT + cc;
-      Yi[rr][cc] = (gr < r1 && gi < k) ? Y[gr * ldy + gi] : 0.f;
-      Yj[rr][cc] = (gr < r1 && gj < k) ? Y[gr * ldy + gj] : 0.f;
+      vi[p] = (gr < r1 && gi < k) ? Y[gr * ldy + gi] : 0.f;
+      if (!diag) vj[p] = (gr < r1 && gj < k) ? Y[gr * ldy + gj] : 0.f;
+    }
+  };
+  if (r0 < r1) load(r0);
+  for (int64_t c0 = r0; c0 < r1; c0 += GROWS) {
+#pragma unroll
+    for (int p = 0; p < GPT; ++p) {
+      const int e = tid + 256 * p, rr = e / GT, cc = e % GT;
+      Yi[rr][cc] = vi[p];
+      if (!diag) Yj[rr][cc] = vj[p];
     }
     __syncthreads();
+    if (c0 + GROWS < r1) load(c0 + GROWS);
+    float (*B)[GT + 1] = diag ? Yi : Yj;
 #pragma unroll 4
     for (int kk = 0; kk < GROWS; kk += 4) {
       const int rr = kk + (lane >> 4);
       const double a = (double)Yi[rr][wave * 16 + (lane & 15)];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const double b = (double)Yj[rr][t * 16 + (lane & 15)];
+        const double b = (double)B[rr][t * 16 + (lane & 15)];
         acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
       }
     }
@@ -66,78 +86,130 @@ gram_f64_kernel(const float* __restrict__ Y, int64_t ldy, int64_t rows, int k, i
     }
 }
 
-// One workgroup: sum the split partials (fixed order) into LDS, factorise
-// G = L L^T and invert L, then write R^{-1} = L^{-T} (upper, k x k).
-// Both live in one k x k LDS array M: the lower triangle holds A -> L
-// (right-looking, column j: pivot p = A[j][j], L[i][j] = A[i][j]/sqrt(p),
-// A[i][l] -= L[i][j] L[l][j] for j < l <= i), the strict upper triangle holds
-// X = L^{-1} transposed (M[c][i] = X[i][c], c < i) and Xd its diagonal.  X is
-// built in the same column loop by forward elimination on the identity:
-// X[j][:] /= L[j][j], then X[i][:] -= L[i][j] X[j][:] for i > j.
-template <int KMAX>
-__global__ void __launch_bounds__(1024)
-cholesky_kernel(const double* __restrict__ part, int splits, int k, int64_t rows,
-                double* __restrict__ Rinv, int* __restrict__ status, int attempt) {
-  if (attempt == 2 && status[0] == 0) return;   // third pass only after a shift
-  __shared__ double M[KMAX * KMAX];
-  __shared__ double Xd[KMAX];
-  __shared__ double trace;
+// One workgroup factorises G = L L^T and inverts L, then writes
+// R^{-1} = L^{-T} (upper, k x k).  TD x TD threads hold both matrices in
+// registers, block-cyclically: thread (tx, ty) owns rows i = ty + TD a and
+// columns l = tx + TD b (a, b < PB).  Column j (right-looking, pivot
+// p = A[j][j], L[i][j] = A[i][j] / sqrt(p), A[i][l] -= L[i][j] L[l][j] for
+// j < l <= i) is published through LDS together with row j of X, where X = L^{-1}
+// is built by forward elimination on the identity in the same loop
+// (X[j][:] /= L[j][j], then X[i][:] -= L[i][j] X[j][:] for i > j).
+// attempt 0: first pass, resets the per-orthonormalisation flags.
+// attempt 1: second pass; if G is already within 1e-6 of I (the first pass was
+//            orthonormal to working precision) it only sets status[3] (skip).
+// attempt 2: third pass, only after a shifted factorisation (status[0]).
+template <int KMAX, int TD>
+__global__ void __launch_bounds__(TD * TD)
+cholesky_kernel(const double* __restrict__ G, int k, int64_t rows, double* __restrict__ Rinv,
+                int* __restrict__ status, int attempt) {
+  constexpr int PB = KMAX / TD;
+  constexpr int NW = TD * TD / 64;
+  if (attempt == 2 && status[0] == 0) return;
+  __shared__ double colj[KMAX], rowj[KMAX];
+  __shared__ double wred[NW];
   __shared__ int fail;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int kk = k * k;
+  const int tid = threadIdx.x, tx = tid % TD, ty = tid / TD;
 
+  if (attempt == 1) {
+    double dev = 0.0;
+#pragma unroll
+    for (int a = 0; a < PB; ++a)
+#pragma unroll
+      for (int b = 0; b < PB; ++b) {
+        const int i = ty + TD * a, l = tx + TD * b;
+        if (i < k && l < k) dev = fmax(dev, fabs(G[i * k + l] - (i == l ? 1.0 : 0.0)));
+      }
+    for (int off = 32; off > 0; off >>= 1) dev = fmax(dev, __shfl_xor(dev, off));
+    if ((tid & 63) == 0) wred[tid >> 6] = dev;
+    __syncthreads();
+    double mx = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) mx = fmax(mx, wred[w]);
+    if (mx <= 1e-6) {                     // uniform
+      if (tid == 0) status[3] = 1;
+      return;
+    }
+  }
+  if (attempt == 0 && tid == 0) {
+    status[0] = 0;
+    status[3] = 0;
+  }
+
+  double M[PB][PB], X[PB][PB];
   for (int tryi = 0; tryi < 2; ++tryi) {
     double shift = 0.0;
     if (tryi == 1) {
+      double trace = 0.0;
+      for (int i = 0; i < k; ++i) trace += G[i * k + i];
       const double u = 1.1102230246251565e-16;
       shift = 11.0 * ((double)rows * k + (double)k * (k + 1)) * u * trace;
     }
-    for (int e = tid; e < kk; e += nt) {
-      const int i = e / k, l = e % k;
-      double v = 0.0;
-      if (l <= i) {
-        for (int z = 0; z < splits; ++z) v += part[(int64_t)z * kk + e];
-        if (i == l) v += shift;
+#pragma unroll
+    for (int a = 0; a < PB; ++a)
+#pragma unroll
+      for (int b = 0; b < PB; ++b) {
+        const int i = ty + TD * a, l = tx + TD * b;
+        M[a][b] = (i < k && l <= i) ? G[i * k + l] + (i == l ? shift : 0.0) : 0.0;
+        X[a][b] = (i < k && i == l) ? 1.0 : 0.0;
       }
-      M[e] = v;   // strict upper triangle: X = I off the diagonal
-    }
-    for (int i = tid; i < k; i += nt) Xd[i] = 1.0;
     if (tid == 0) fail = 0;
     __syncthreads();
-    if (tryi == 0 && tid == 0) {
-      double t = 0.0;
-      for (int i = 0; i < k; ++i) t += M[i * k + i];
-      trace = t;
-    }
-    for (int j = 0; j < k; ++j) {
-      const double p = M[j * k + j];
-      if (!(p > 0.0) || !isfinite(p)) {   // uniform: every thread reads the same p
-        if (tid == 0) fail = 1;
-        break;
+    bool stop = false;
+#pragma unroll
+    for (int b0 = 0; b0 < PB; ++b0) {
+      for (int jj = 0; jj < TD; ++jj) {
+        const int j = b0 * TD + jj;
+        if (j >= k || stop) break;
+        // publish column j of A and row j of X (both unscaled)
+        if (tx == jj) {
+#pragma unroll
+          for (int a = 0; a < PB; ++a) colj[ty + TD * a] = M[a][b0];
+        }
+        if (ty == jj) {
+#pragma unroll
+          for (int b = 0; b < PB; ++b) rowj[tx + TD * b] = X[b0][b];
+        }
+        __syncthreads();
+        const double p = colj[j];
+        if (!(p > 0.0) || !isfinite(p)) {   // uniform: every thread reads the same p
+          stop = true;
+          if (tid == 0) fail = 1;
+          break;
+        }
+        const double d = sqrt(p), id = 1.0 / d;
+        double lc[PB], lr[PB], xj[PB];
+#pragma unroll
+        for (int a = 0; a < PB; ++a) lc[a] = colj[ty + TD * a] * id;     // L[i][j]
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+          lr[b] = colj[tx + TD * b] * id;                                // L[l][j]
+          xj[b] = rowj[tx + TD * b] * id;                                // X[j][c] / L[j][j]
+        }
+#pragma unroll
+        for (int a = 0; a < PB; ++a) {
+          const int i = ty + TD * a;
+#pragma unroll
+          for (int b = 0; b < PB; ++b) {
+            const int l = tx + TD * b;
+            if (j < l && l <= i) M[a][b] -= lc[a] * lr[b];
+            if (l <= j && j < i) X[a][b] -= lc[a] * xj[b];
+          }
+        }
+        if (tx == jj) {
+#pragma unroll
+          for (int a = 0; a < PB; ++a) {
+            const int i = ty + TD * a;
+            if (i > j) M[a][b0] = lc[a];
+            else if (i == j) M[a][b0] = d;
+          }
+        }
+        if (ty == jj) {
+#pragma unroll
+          for (int b = 0; b < PB; ++b)
+            if (tx + TD * b <= j) X[b0][b] = xj[b];
+        }
+        __syncthreads();
       }
-      const double d = sqrt(p), id = 1.0 / d;
-      __syncthreads();                     // everyone has read p before it changes
-      // phase 1: scale column j of L and row j of X
-      for (int i = j + 1 + tid; i < k; i += nt) M[i * k + j] *= id;
-      for (int c = tid; c < j; c += nt) M[c * k + j] *= id;   // X[j][c], c < j
-      if (tid == 0) {
-        M[j * k + j] = d;
-        Xd[j] = Xd[j] * id;
-      }
-      __syncthreads();
-      // phase 2: trailing update of A and elimination in X
-      const int mt = k - j - 1;
-      for (int e = tid; e < mt * mt; e += nt) {
-        const int i = j + 1 + e / mt, l = j + 1 + e % mt;
-        if (l <= i) M[i * k + l] -= M[i * k + j] * M[l * k + j];
-      }
-      const int w = j + 1;
-      for (int e = tid; e < mt * w; e += nt) {
-        const int i = j + 1 + e / w, c = e % w;
-        const double xjc = (c == j) ? Xd[j] : M[c * k + j];
-        M[c * k + i] -= M[i * k + j] * xjc;   // X[i][c]
-      }
-      __syncthreads();
     }
     __syncthreads();
     if (!fail) break;
@@ -151,11 +223,16 @@ cholesky_kernel(const double* __restrict__ part, int splits, int k, int64_t rows
     if (tid == 0) status[1] = 1;
     return;
   }
-  // R^{-1}[c][i] = X[i][c]: c < i from the upper triangle, c == i from Xd.
-  for (int e = tid; e < kk; e += nt) {
-    const int c = e / k, i = e % k;
-    Rinv[e] = (c < i) ? M[c * k + i] : (c == i ? Xd[i] : 0.0);
-  }
+  // R^{-1}[c][i] = X[i][c] for c <= i, 0 below the diagonal
+#pragma unroll
+  for (int a = 0; a < PB; ++a)
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+      const int i = ty + TD * a, c = tx + TD * b;
+      if (i < k && c < k) {
+        Rinv[c * k + i] = (c <= i) ? X[a][b] : 0.0;
+      }
+    }
 }
 
 // Q = Y R^{-1} in place on FP64 MFMA (v_mfma_f64_16x16x4_f64): a workgroup owns
@@ -166,6 +243,7 @@ __global__ void __launch_bounds__(256)
 apply_rinv_kernel(float* __restrict__ Y, int64_t ldy, int64_t rows, int k,
                   const double* __restrict__ Rinv, const int* __restrict__ status, int attempt) {
   if (status[1] != 0) return;
+  if (attempt == 1 && status[3] != 0) return;   // second pass not needed
   if (attempt == 2 && status[0] == 0) return;
   constexpr int NT = KMAX / 16;
   __shared__ float Ys[64][KMAX + 1];
@@ -205,29 +283,36 @@ apply_rinv_kernel(float* __restrict__ Y, int64_t ldy, int64_t rows, int k,
 }  // namespace
 
 int gram_pick_splits(int64_t rows, int k) {
-  (void)k;
-  int64_t s = ceil_div(rows, 2048);
+  // 256 rows per split, partials capped at 32 MB
+  int64_t s = ceil_div(rows, 256);
+  const int64_t cap = (32ll << 20) / ((int64_t)k * k * 8);
+  if (s > cap) s = cap;
+  if (s > 1024) s = 1024;
   if (s < 1) s = 1;
-  if (s > 128) s = 128;
   return (int)s;
 }
 
 hipError_t launch_gram_f64(const float* Y, int64_t ldy, int64_t rows, int k, double* part,
-                           int splits, const int* skip_flag, hipStream_t st) {
+                           int splits, double* G, const int* skip_flag, hipStream_t st) {
   const int nb = (k + GT - 1) / GT;
   const int64_t rchunk = round_up(ceil_div(rows, splits), GROWS);
   hipLaunchKernelGGL(gram_f64_kernel, dim3(nb * nb, splits), dim3(256), 0, st, Y, ldy, rows, k,
                      rchunk, part, skip_flag);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_sum_partials_f64(part, splits, (int64_t)k * k, G, skip_flag, st);
 }
 
-hipError_t launch_cholesky(const double* part, int splits, int k, int64_t rows, double* Rinv,
-                           int* status, int attempt, hipStream_t st) {
-  if (k <= 64)
-    hipLaunchKernelGGL(cholesky_kernel<64>, dim3(1), dim3(1024), 0, st, part, splits, k, rows, Rinv,
-                       status, attempt);
+hipError_t launch_cholesky(const double* G, int k, int64_t rows, double* Rinv, int* status,
+                           int attempt, hipStream_t st) {
+  if (k <= 32)
+    hipLaunchKernelGGL((cholesky_kernel<32, 8>), dim3(1), dim3(64), 0, st, G, k, rows, Rinv, status,
+                       attempt);
+  else if (k <= 64)
+    hipLaunchKernelGGL((cholesky_kernel<64, 16>), dim3(1), dim3(256), 0, st, G, k, rows, Rinv, status,
+                       attempt);
   else if (k <= 128)
-    hipLaunchKernelGGL(cholesky_kernel<128>, dim3(1), dim3(1024), 0, st, part, splits, k, rows, Rinv,
+    hipLaunchKernelGGL((cholesky_kernel<128, 32>), dim3(1), dim3(1024), 0, st, G, k, rows, Rinv,
                        status, attempt);
   else
     return hipErrorInvalidValue;

@@ -2,7 +2,7 @@
 // evaluated directly (never through the Gram expansion, which cancels
 // catastrophically at small e) with FP64 products and FP64 accumulation.
 //
-// A workgroup owns 64 rows of X and a range of 64-column tiles.  Each wave
+// A workgroup owns 64 rows of X and walks all 64-column tiles.  Each wave
 // computes a 16 x 64 block of W diag(sw) Ht^T on v_mfma_f64_16x16x4_f64
 // (D[i][j] in lane j + 16 (i % 4), register i / 4), subtracts X, and
 // accumulates squares.  Workgroup partials are summed in fixed order by the
@@ -11,70 +11,97 @@
 
 namespace {
 
-constexpr int RB = 64;       // rows per workgroup
+constexpr int RB = 64;       // rows per workgroup (the workgroup sweeps all columns)
 constexpr int CT = 64;       // columns per tile
-constexpr int CTILES = 8;    // tiles per workgroup
-constexpr int RMAXR = 128;
 
+template <int RMAX>
 __global__ void __launch_bounds__(256)
 residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
                 const float* __restrict__ W, const float* __restrict__ sw,
                 const float* __restrict__ Ht, int r, double* __restrict__ part,
                 double* __restrict__ out, unsigned* __restrict__ counter) {
-  __shared__ float Hs[CT][RMAXR + 1];
+  constexpr int KS = RMAX / 4;                // MFMA k-steps
+  constexpr int HPT = CT * RMAX / 256;        // Ht tile elements per thread
+  __shared__ float Hs[CT][RMAX + 1];
   __shared__ double red[2][256];
   __shared__ int last;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = (int64_t)blockIdx.x * RB;
-  const int64_t colblk = (int64_t)blockIdx.y * CT * CTILES;
-  const int ksteps = (r + 3) / 4;
+  const int64_t ntile = ceil_div(n, CT);
 
-  // A fragments (W rows of this wave), FP64, kept for all column tiles.
-  double afr[RMAXR / 4];
+  // A fragments (rows of W diag(sw) owned by this wave), FP64, kept for all tiles.
+  double afr[KS];
   {
     const int64_t gi = row0 + wave * 16 + (lane & 15);
 #pragma unroll
-    for (int s = 0; s < RMAXR / 4; ++s) {
+    for (int s = 0; s < KS; ++s) {
       const int k = 4 * s + (lane >> 4);
-      double v = 0.0;
-      if (s < ksteps && gi < m && k < r) v = (double)W[gi * r + k] * (double)(sw ? sw[k] : 1.f);
-      afr[s] = v;
+      afr[s] = (gi < m && k < r) ? (double)W[gi * r + k] * (double)(sw ? sw[k] : 1.f) : 0.0;
     }
   }
-  double res = 0.0, xx = 0.0;
-  for (int t = 0; t < CTILES; ++t) {
-    const int64_t c0 = colblk + (int64_t)t * CT;
-    if (c0 >= n) break;
-    __syncthreads();
-    for (int e = tid; e < CT * r; e += 256) {
-      const int jj = e / r, k = e % r;
-      Hs[jj][k] = (c0 + jj < n) ? Ht[(c0 + jj) * r + k] : 0.f;
+  // Software pipeline over the 64-column tiles of this row strip: the loads of
+  // tile t+1 are issued (Ht first, then X) before the MFMAs of tile t, so each
+  // wait only covers loads issued one tile earlier.
+  float hv[HPT], xv[4][4];
+  auto load_h = [&](int64_t c0) {
+#pragma unroll
+    for (int p = 0; p < HPT; ++p) {
+      const int e = tid + 256 * p, jj = e / RMAX, k = e % RMAX;
+      hv[p] = (c0 + jj < n && k < r) ? Ht[(c0 + jj) * r + k] : 0.f;
     }
-    __syncthreads();
+  };
+  auto load_x = [&](int64_t c0) {
 #pragma unroll
-    for (int sub = 0; sub < 4; ++sub) {
-      f64x4 d = {0, 0, 0, 0};
-      const int jl = sub * 16 + (lane & 15);
-#pragma unroll
-      for (int s = 0; s < RMAXR / 4; ++s) {
-        if (s < ksteps) {
-          const int k = 4 * s + (lane >> 4);
-          const double b = (k < r) ? (double)Hs[jl][k] : 0.0;
-          d = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[s], b, d, 0, 0, 0);
-        }
-      }
-      const int64_t gj = c0 + jl;
+    for (int sub = 0; sub < 4; ++sub)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int64_t gi = row0 + wave * 16 + 4 * q + (lane >> 4);
-        if (gi < m && gj < n) {
-          const double x = (double)X[gi * ldx + gj];
-          const double df = x - d[q];
-          res = fma(df, df, res);
-          xx = fma(x, x, xx);
-        }
+        const int64_t gj = c0 + sub * 16 + (lane & 15);
+        xv[sub][q] = (gi < m && gj < n) ? X[gi * ldx + gj] : 0.f;
+      }
+  };
+  double res = 0.0, xx = 0.0;
+  load_h(0);
+  load_x(0);
+  for (int64_t t = 0; t < ntile; ++t) {
+    __syncthreads();   // readers of the previous Hs are done
+#pragma unroll
+    for (int p = 0; p < HPT; ++p) {
+      const int e = tid + 256 * p;
+      Hs[e / RMAX][e % RMAX] = hv[p];
+    }
+    __syncthreads();
+    float xc[4][4];
+#pragma unroll
+    for (int sub = 0; sub < 4; ++sub)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) xc[sub][q] = xv[sub][q];
+    if (t + 1 < ntile) {
+      load_h((t + 1) * CT);
+      load_x((t + 1) * CT);
+    }
+    f64x4 d[4];
+#pragma unroll
+    for (int sub = 0; sub < 4; ++sub) d[sub] = (f64x4){0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int k = 4 * s + (lane >> 4);
+#pragma unroll
+      for (int sub = 0; sub < 4; ++sub) {
+        const double b = (double)Hs[sub * 16 + (lane & 15)][k];
+        d[sub] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[s], b, d[sub], 0, 0, 0);
       }
     }
+    // D[i][j] in lane j + 16 (i % 4), register i / 4; out-of-range entries are 0 - 0
+#pragma unroll
+    for (int sub = 0; sub < 4; ++sub)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double x = (double)xc[sub][q];
+        const double df = x - d[sub][q];
+        res = fma(df, df, res);
+        xx = fma(x, x, xx);
+      }
   }
   red[0][tid] = res;
   red[1][tid] = xx;
@@ -86,8 +113,8 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
     }
     __syncthreads();
   }
-  const int nblk = gridDim.x * gridDim.y;
-  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  const int nblk = gridDim.x;
+  const int bid = blockIdx.x;
   if (tid == 0) {
     part[2 * bid] = red[0][0];
     part[2 * bid + 1] = red[1][0];
@@ -123,15 +150,27 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
 }  // namespace
 
 int residual_blocks(int64_t m, int64_t n) {
-  return (int)(ceil_div(m, RB) * ceil_div(n, (int64_t)CT * CTILES));
+  (void)n;
+  return (int)ceil_div(m, RB);
 }
 
 hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t n, const float* W,
                            const float* sw, const float* Ht, int r, double* part, double* out,
                            unsigned* counter, hipStream_t st) {
-  if (r > RMAXR) return hipErrorInvalidValue;
-  dim3 grid((unsigned)ceil_div(m, RB), (unsigned)ceil_div(n, (int64_t)CT * CTILES));
-  hipLaunchKernelGGL(residual_kernel, grid, dim3(256), 0, st, X, ldx, m, n, W, sw, Ht, r, part, out,
-                     counter);
+  dim3 grid((unsigned)ceil_div(m, RB));
+  if (r <= 16)
+    hipLaunchKernelGGL(residual_kernel<16>, grid, dim3(256), 0, st, X, ldx, m, n, W, sw, Ht, r, part,
+                       out, counter);
+  else if (r <= 32)
+    hipLaunchKernelGGL(residual_kernel<32>, grid, dim3(256), 0, st, X, ldx, m, n, W, sw, Ht, r, part,
+                       out, counter);
+  else if (r <= 64)
+    hipLaunchKernelGGL(residual_kernel<64>, grid, dim3(256), 0, st, X, ldx, m, n, W, sw, Ht, r, part,
+                       out, counter);
+  else if (r <= 128)
+    hipLaunchKernelGGL(residual_kernel<128>, grid, dim3(256), 0, st, X, ldx, m, n, W, sw, Ht, r, part,
+                       out, counter);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
