@@ -57,8 +57,10 @@ typedef struct {
   int32_t r;             /* number of components (the paper's k) */
   int32_t k_sketch;      /* k' = r + r_ov (Sec 3); r < k' <= min(m, n) (Sec 3.1) */
   int32_t q;             /* power iterations (the paper's w, eq 3.5) */
-  int32_t prec;          /* nmf_prec of the range-finder products (extension) */
-  int32_t refine_fp32;   /* 1: one FP32 power iteration after low-precision passes */
+  int32_t prec;          /* nmf_prec of the range-finder products (extension); the
+                            final sketches Xh, Xc are always FP32 products on X */
+  int32_t refine_fp32;   /* 1: one FP32 power iteration per side after the
+                            low-precision range finder */
   int32_t normalize;     /* a_j <- a_j/||a_j|| after the A sweep (end of Sec 4):
                             0 none, 1 with b_j <- b_j ||a_j|| (default), 2 literal */
   float alpha, beta;     /* sparsity / smoothness on B (Sec 4.1); 0, 0 = plain rule */
@@ -156,6 +158,29 @@ size_t nmf_gemm_workspace_bytes(int64_t M, int64_t N, int64_t K, int32_t a_trans
 nmf_status nmf_gemm(const float* A, int64_t lda, int32_t a_trans, const float* B, int64_t ldb,
                     float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, void* workspace,
                     size_t ws_bytes, void* hip_stream);
+
+/* Low-precision copies of X for the range-finder products (extension): writes
+ * Xq (m x ldq) and its transpose XqT (n x ldqt), zero padded; ldq >= n and
+ * ldqt >= m, both multiples of 128.  prec = NMF_BF16: uint16 BF16 bit patterns,
+ * round to nearest even.  prec = NMF_FP8_E4M3: OCP e4m3 codes of x 2^-e, where e
+ * is the exponent of the 128 x 128 tile holding x (smallest e with
+ * amax(tile) <= 448 2^e, 0 for an all-zero tile), round to nearest even with
+ * saturation; tile_exp receives ceil(m/128) x ceil(n/128) exponents (row-major,
+ * device).  Asynchronous. */
+nmf_status nmf_quantize_x(const float* X, int64_t ldx, int64_t m, int64_t n, int32_t prec, void* Xq,
+                          int64_t ldq, void* XqT, int64_t ldqt, int32_t* tile_exp, void* hip_stream);
+
+/* C (M x N, ldc) = A (M x Kpad, low precision, K-contiguous) times B (K x N FP32,
+ * ldb), FP32 accumulation.  B is rounded to the same format (and transposed) in
+ * the workspace first; for FP8 with one power-of-two scale per 128-row block of B.
+ * FP8 A carries tile exponents: tile (ti, tk) of A at EA[ti * ea_i + tk * ea_k].
+ * Kpad >= K is a multiple of 128 and A's columns K..Kpad-1 are zero.  N <= 256.
+ * workspace: nmf_gemm_lowp_workspace_bytes() bytes, 256-byte aligned.  Asynchronous. */
+size_t nmf_gemm_lowp_workspace_bytes(int64_t M, int64_t N, int64_t Kpad);
+nmf_status nmf_gemm_lowp(int32_t prec, const void* A, int64_t lda, const int32_t* EA, int64_t ea_i,
+                         int64_t ea_k, const float* B, int64_t ldb, int64_t K, int64_t N, float* C,
+                         int64_t ldc, int64_t M, int64_t Kpad, void* workspace, size_t ws_bytes,
+                         void* hip_stream);
 
 /* In-place orthonormalisation of Y (rows x k, ldy % 4 == 0) by FP64
  * CholeskyQR2 (shifted CholeskyQR3 on breakdown), k <= 128.  Synchronising;

@@ -101,6 +101,61 @@ def compress(X, Omega_L, Omega_R, q, orth=householder_q):
     return QL, QR, X.T @ QL, X @ QR
 
 
+def quantize_thin(B, fmt):
+    """Thin operand of a low-precision product as the GPU rounds it: BF16 of the
+    FP32 values, or e4m3 with one power-of-two scale per 128-row block."""
+    from . import quant
+    B32 = np.asarray(B, dtype=np.float32)
+    if fmt == "bf16":
+        return quant.bf16_round(B32)
+    out = np.empty(B32.shape)
+    for k0 in range(0, B32.shape[0], 128):
+        blk = B32[k0:k0 + 128].astype(np.float64)
+        amax = float(np.max(np.abs(blk))) if blk.size else 0.0
+        e = 0
+        if amax > 0:
+            e = int(np.ceil(np.log2(amax / 448.0)))
+            while amax > 448.0 * 2.0 ** e:
+                e += 1
+            while amax <= 448.0 * 2.0 ** (e - 1):
+                e -= 1
+        out[k0:k0 + 128] = quant.e4m3_round(blk * 2.0 ** -e) * 2.0 ** e
+    return out
+
+
+def quantize_data(X, fmt):
+    """Data matrix as stored for the low-precision products (BF16, or e4m3 with
+    128 x 128 power-of-two block scales), as FP64 values."""
+    from . import quant
+    if fmt == "bf16":
+        return quant.bf16_round(np.asarray(X, dtype=np.float32))
+    return quant.e4m3_block_quantise(np.asarray(X, dtype=np.float32).astype(np.float64))[0]
+
+
+def compress_lowp(X, Omega_L, Omega_R, q, fmt, refine=False, orth=householder_q):
+    """Model of the low-precision compression: every range-finder product uses
+    the quantised X and a quantised thin operand; optionally one FP32-exact
+    power iteration per side; the projected data always use the exact X."""
+    X = np.asarray(X, dtype=np.float64)
+    Xq = quantize_data(X, fmt)
+
+    def prod(A, B):
+        return A @ quantize_thin(B, fmt)
+
+    QL = orth(prod(Xq, Omega_L))
+    for _ in range(q):
+        Z = orth(prod(Xq.T, QL))
+        QL = orth(prod(Xq, Z))
+    QR = orth(prod(Xq.T, Omega_R))
+    for _ in range(q):
+        Z = orth(prod(Xq, QR))
+        QR = orth(prod(Xq.T, Z))
+    if refine:
+        QL = orth(X @ orth(X.T @ QL))
+        QR = orth(X.T @ orth(X @ QR))
+    return QL, QR, X.T @ QL, X @ QR
+
+
 # ----------------------------------------------------------------------------
 # Update rules
 # ----------------------------------------------------------------------------
@@ -290,14 +345,18 @@ def gini(B):
 # ----------------------------------------------------------------------------
 
 def fasthals_rp(X, Omega_L, Omega_R, q, W0, H0t, iters, normalize=1, orth=householder_q,
-                record=False):
-    """Compress, then `iters` FastHALS-RP iterations.  Returns a dict."""
-    QL, QR, Xh, Xc = compress(X, Omega_L, Omega_R, q, orth)
+                record=False, fmt=None, refine=False, alpha=0.0, beta=0.0):
+    """Compress (exactly, or with the low-precision model when fmt is 'bf16' or
+    'fp8'), then `iters` FastHALS-RP iterations.  Returns a dict."""
+    if fmt is None:
+        QL, QR, Xh, Xc = compress(X, Omega_L, Omega_R, q, orth)
+    else:
+        QL, QR, Xh, Xc = compress_lowp(X, Omega_L, Omega_R, q, fmt, refine, orth)
     W = np.array(W0, dtype=np.float64)
     Ht = np.array(H0t, dtype=np.float64)
     hist = []
     for _ in range(iters):
-        W, Ht = fasthals_rp_iteration(W, Ht, Xh, Xc, QL, QR, normalize)
+        W, Ht = fasthals_rp_iteration(W, Ht, Xh, Xc, QL, QR, normalize, alpha, beta)
         if record:
             hist.append(rel_error(X, W, Ht))
     return dict(QL=QL, QR=QR, Xh=Xh, Xc=Xc, W=W, Ht=Ht, e=rel_error(X, W, Ht), hist=hist)

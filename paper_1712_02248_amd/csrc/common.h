@@ -8,6 +8,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 #define NMF_DEV __device__ __forceinline__
 
@@ -36,6 +37,30 @@ hipError_t launch_gemm_f32(const float* A, int64_t lda, int a_trans, const float
                            float* C, int64_t ldc, int64_t M, int64_t N, int64_t K,
                            int splits, float* part, hipStream_t st);
 int gemm_f32_pick_splits(int64_t M, int64_t N, int64_t K, int a_trans);
+
+// Low-precision copies of X and of the thin operand (quant.hip).  Xq is m x ldq,
+// XqT is n x ldqt; ldq, ldqt are multiples of 128 and the padding is zero.
+hipError_t launch_quant_bf16(const float* X, int64_t ldx, int64_t m, int64_t n, uint16_t* Xq,
+                             int64_t ldq, uint16_t* XqT, int64_t ldqt, hipStream_t st);
+// E: ceil(m/128) x ceil(n/128) tile exponents (row-major).
+hipError_t launch_quant_fp8(const float* X, int64_t ldx, int64_t m, int64_t n, int* E, uint8_t* Xq,
+                            int64_t ldq, uint8_t* XqT, int64_t ldqt, hipStream_t st);
+hipError_t launch_prep_b_bf16(const float* B, int64_t ldb, int64_t K, int64_t N, uint16_t* Bt,
+                              int64_t ldbt, hipStream_t st);
+// Ebt: ceil(K/128) exponents, one per 128-row block of B.
+hipError_t launch_prep_b_fp8(const float* B, int64_t ldb, int64_t K, int64_t N, int* Ebt, uint8_t* Bt,
+                             int64_t ldbt, hipStream_t st);
+
+// Low-precision NT products (gemm_lp.hip): C[M x N] = A[M x Kpad] Bt[N x Kpad]^T.
+int gemm_lp_pick_splits(int64_t M, int64_t N, int64_t Kpad, int bm);
+hipError_t launch_gemm_bf16_nt(const uint16_t* A, int64_t lda, const uint16_t* Bt, int64_t ldbt,
+                               float* C, int64_t ldc, int64_t M, int64_t N, int64_t Kpad, int splits,
+                               float* part, hipStream_t st);
+// EA: exponent of A's 128 x 128 tile (ti, tk) at EA[ti * ea_i + tk * ea_k]; EB per 128-row block.
+hipError_t launch_gemm_fp8_nt(const uint8_t* A, int64_t lda, const int* EA, int64_t ea_i, int64_t ea_k,
+                              const uint8_t* Bt, int64_t ldbt, const int* EB, float* C, int64_t ldc,
+                              int64_t M, int64_t N, int64_t Kpad, int splits, float* part,
+                              hipStream_t st);
 
 // Tall-skinny QR pieces (qr.hip).
 // G = Y^T Y in FP64: split partials, then the deterministic sum into G (k x k).

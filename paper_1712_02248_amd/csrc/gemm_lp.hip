@@ -1,0 +1,301 @@
+// Low-precision compression products (extension): C[M x N] = A[M x K] Bt[N x K]^T
+// with both operands K-contiguous ("NT"), FP32 accumulation, FP32 output.
+// A is the low-precision copy of X (for X B) or of X^T (for X^T B); Bt is the
+// transposed low-precision copy of the thin operand (Omega or Q).  K is padded
+// to the tile depth with zeros in both operands.
+//
+// BF16: v_mfma_f32_32x32x16_bf16, lane l holds A[l % 32][16s + 8(l / 32) .. +7];
+//       D[i][j] in lane j + 32 ((i / 4) % 2), register (i / 8) 4 + i % 4.
+// FP8 (e4m3): v_mfma_scale_f32_16x16x128_f8f6f4, lane l holds
+//       A[l % 16][32(l / 16) .. +31]; D[i][j] in lane j + 16 (i / 4), register i % 4.
+//       Each 128-deep step multiplies by 2^(eA + eB) through the E8M0 scale
+//       operands: eA is the exponent of X's 128 x 128 tile, eB that of the thin
+//       operand's 128-row block.
+#include "common.h"
+
+namespace {
+
+// ------------------------------------------------------------------------- BF16
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(256)
+gemm_bf16_nt_kernel(const uint16_t* __restrict__ A, int64_t lda, const uint16_t* __restrict__ Bt,
+                    int64_t ldbt, float* __restrict__ C, int64_t ldc, int64_t M, int64_t N,
+                    int64_t Kpad, int64_t kchunk) {
+  constexpr int BK = 64, ROW = BK + 8;                    // u16 per LDS row
+  constexpr int TM = BM / WM / 32, TN = BN / WN / 32;
+  constexpr int AV = BM * BK / 8 / 256, BV = BN * BK / 8 / 256;   // 16-byte loads per thread
+  static_assert(AV >= 1 && BV >= 1 && WM * WN == 4, "tiling");
+  __shared__ __attribute__((aligned(16))) uint16_t As[BM * ROW];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * ROW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t i0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kend = kbeg + kchunk < Kpad ? kbeg + kchunk : Kpad;
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int x = 0; x < 16; ++x) acc[a][b][x] = 0.f;
+  i32x4 ra[AV], rb[BV];
+  const i32x4 z4 = {0, 0, 0, 0};
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int p = 0; p < AV; ++p) {
+      const int f = tid + 256 * p, row = f / (BK / 8), c8 = f % (BK / 8);
+      const int64_t gi = i0 + row;
+      ra[p] = gi < M ? *(const i32x4*)(A + gi * lda + k0 + 8 * c8) : z4;
+    }
+#pragma unroll
+    for (int p = 0; p < BV; ++p) {
+      const int f = tid + 256 * p, row = f / (BK / 8), c8 = f % (BK / 8);
+      const int64_t gj = n0 + row;
+      rb[p] = gj < N ? *(const i32x4*)(Bt + gj * ldbt + k0 + 8 * c8) : z4;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int p = 0; p < AV; ++p) {
+      const int f = tid + 256 * p, row = f / (BK / 8), c8 = f % (BK / 8);
+      *(i32x4*)(As + row * ROW + 8 * c8) = ra[p];
+    }
+#pragma unroll
+    for (int p = 0; p < BV; ++p) {
+      const int f = tid + 256 * p, row = f / (BK / 8), c8 = f % (BK / 8);
+      *(i32x4*)(Bs + row * ROW + 8 * c8) = rb[p];
+    }
+  };
+  const int half = lane >> 5, l32 = lane & 31;
+  if (kbeg < kend) {
+    load(kbeg);
+    store();
+    __syncthreads();
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+      const bool more = k0 + BK < kend;
+      if (more) load(k0 + BK);
+#pragma unroll
+      for (int ks = 0; ks < BK / 16; ++ks) {
+        bf16x8 af[TM], bf[TN];
+#pragma unroll
+        for (int a = 0; a < TM; ++a) {
+          const int il = wm * (BM / WM) + a * 32 + l32;
+          af[a] = *(const bf16x8*)(As + il * ROW + ks * 16 + 8 * half);
+        }
+#pragma unroll
+        for (int b = 0; b < TN; ++b) {
+          const int jl = wn * (BN / WN) + b * 32 + l32;
+          bf[b] = *(const bf16x8*)(Bs + jl * ROW + ks * 16 + 8 * half);
+        }
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+          for (int b = 0; b < TN; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
+      }
+      __syncthreads();
+      if (more) {
+        store();
+        __syncthreads();
+      }
+    }
+  }
+  float* Cz = C + (int64_t)blockIdx.z * (M * ldc);
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int64_t gj = n0 + wn * (BN / WN) + b * 32 + l32;
+#pragma unroll
+      for (int x = 0; x < 16; ++x) {
+        const int il = (x >> 2) * 8 + half * 4 + (x & 3);
+        const int64_t gi = i0 + wm * (BM / WM) + a * 32 + il;
+        if (gi < M && gj < N) Cz[gi * ldc + gj] = acc[a][b][x];
+      }
+    }
+}
+
+// -------------------------------------------------------------------------- FP8
+// BM = 128 rows of A (one X tile row-block), BN columns, BK = 128 (one scale block).
+template <int BN, int WN>
+__global__ void __launch_bounds__(256)
+gemm_fp8_nt_kernel(const uint8_t* __restrict__ A, int64_t lda, const int* __restrict__ EA,
+                   int64_t ea_i, int64_t ea_k, const uint8_t* __restrict__ Bt, int64_t ldbt,
+                   const int* __restrict__ EB, float* __restrict__ C, int64_t ldc, int64_t M,
+                   int64_t N, int64_t Kpad, int64_t kchunk) {
+  constexpr int BM = 128, BK = 128, ROW = BK + 16;         // bytes per LDS row
+  constexpr int WM = 4 / WN;
+  constexpr int TM = BM / WM / 16, TN = BN / WN / 16;      // 16x16 tiles per wave
+  constexpr int AV = BM * BK / 16 / 256, BV = BN * BK / 16 / 256;
+  static_assert(AV >= 1 && BV >= 1, "tiling");
+  __shared__ __attribute__((aligned(16))) uint8_t As[BM * ROW];
+  __shared__ __attribute__((aligned(16))) uint8_t Bs[BN * ROW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t i0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kend = kbeg + kchunk < Kpad ? kbeg + kchunk : Kpad;
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  i32x4 ra[AV], rb[BV];
+  const i32x4 z4 = {0, 0, 0, 0};
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int p = 0; p < AV; ++p) {
+      const int f = tid + 256 * p, row = f / (BK / 16), c16 = f % (BK / 16);
+      const int64_t gi = i0 + row;
+      ra[p] = gi < M ? *(const i32x4*)(A + gi * lda + k0 + 16 * c16) : z4;
+    }
+#pragma unroll
+    for (int p = 0; p < BV; ++p) {
+      const int f = tid + 256 * p, row = f / (BK / 16), c16 = f % (BK / 16);
+      const int64_t gj = n0 + row;
+      rb[p] = gj < N ? *(const i32x4*)(Bt + gj * ldbt + k0 + 16 * c16) : z4;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int p = 0; p < AV; ++p) {
+      const int f = tid + 256 * p, row = f / (BK / 16), c16 = f % (BK / 16);
+      *(i32x4*)(As + row * ROW + 16 * c16) = ra[p];
+    }
+#pragma unroll
+    for (int p = 0; p < BV; ++p) {
+      const int f = tid + 256 * p, row = f / (BK / 16), c16 = f % (BK / 16);
+      *(i32x4*)(Bs + row * ROW + 16 * c16) = rb[p];
+    }
+  };
+  const int g4 = lane >> 4, l16 = lane & 15;
+  const int64_t ti = i0 / 128;
+  if (kbeg < kend) {
+    load(kbeg);
+    store();
+    __syncthreads();
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+      const bool more = k0 + BK < kend;
+      if (more) load(k0 + BK);
+      const int64_t kb = k0 / 128;
+      const int sa = 127 + EA[ti * ea_i + kb * ea_k];
+      const int sb = 127 + EB[kb];
+      i32x8 af[TM], bf[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) {
+        const int il = wm * (BM / WM) + a * 16 + l16;
+        const i32x4 lo = *(const i32x4*)(As + il * ROW + 32 * g4);
+        const i32x4 hi = *(const i32x4*)(As + il * ROW + 32 * g4 + 16);
+        af[a] = (i32x8){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      }
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        const int jl = wn * (BN / WN) + b * 16 + l16;
+        const i32x4 lo = *(const i32x4*)(Bs + jl * ROW + 32 * g4);
+        const i32x4 hi = *(const i32x4*)(Bs + jl * ROW + 32 * g4 + 16);
+        bf[b] = (i32x8){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      }
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[a], bf[b], acc[a][b], 0, 0, 0,
+                                                                        sa, 0, sb);
+      __syncthreads();
+      if (more) {
+        store();
+        __syncthreads();
+      }
+    }
+  }
+  float* Cz = C + (int64_t)blockIdx.z * (M * ldc);
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int64_t gj = n0 + wn * (BN / WN) + b * 16 + l16;
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int64_t gi = i0 + wm * (BM / WM) + a * 16 + 4 * g4 + x;
+        if (gi < M && gj < N) Cz[gi * ldc + gj] = acc[a][b][x];
+      }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+splitk_reduce_lp(const float* __restrict__ part, int splits, float* __restrict__ C, int64_t ldc,
+                 int64_t M, int64_t N) {
+  const int64_t total = M * N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / N, j = e - i * N;
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * total + e];
+    C[i * ldc + j] = s;
+  }
+}
+
+int bn_lp(int64_t N) { return N <= 32 ? 32 : N <= 64 ? 64 : N <= 128 ? 128 : 256; }
+
+hipError_t finish(float* part, int splits, float* C, int64_t ldc, int64_t M, int64_t N, hipStream_t st) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || splits == 1) return e;
+  int64_t g = ceil_div(M * N, 256);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(splitk_reduce_lp, dim3((unsigned)g), dim3(256), 0, st, part, splits, C, ldc, M, N);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int gemm_lp_pick_splits(int64_t M, int64_t N, int64_t Kpad, int bm) {
+  const int64_t tiles = ceil_div(M, bm) * ceil_div(N, bn_lp(N));
+  if (tiles <= 0) return 1;
+  int64_t s = ceil_div(1024, tiles);
+  const int64_t kmax = Kpad / 512;  // at least 512 deep per split
+  if (s > kmax) s = kmax;
+  if (s > 64) s = 64;
+  if (s < 1) s = 1;
+  return (int)s;
+}
+
+hipError_t launch_gemm_bf16_nt(const uint16_t* A, int64_t lda, const uint16_t* Bt, int64_t ldbt,
+                               float* C, int64_t ldc, int64_t M, int64_t N, int64_t Kpad, int splits,
+                               float* part, hipStream_t st) {
+  if (M == 0 || N == 0) return hipSuccess;
+  if (N > 256 || Kpad % 64 || lda % 8 || ldbt % 8) return hipErrorInvalidValue;
+  float* out = splits > 1 ? part : C;
+  const int64_t ldo = splits > 1 ? N : ldc;
+  const int64_t kchunk = round_up(ceil_div(Kpad, splits), 64);
+  const int bn = bn_lp(N);
+  const int bm = bn <= 128 ? 128 : 64;
+  dim3 grid((unsigned)ceil_div(M, bm), (unsigned)ceil_div(N, bn), (unsigned)splits);
+  switch (bn) {
+    case 32: hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 32, 4, 1>), grid, dim3(256), 0, st, A, lda, Bt, ldbt, out, ldo, M, N, Kpad, kchunk); break;
+    case 64: hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 64, 2, 2>), grid, dim3(256), 0, st, A, lda, Bt, ldbt, out, ldo, M, N, Kpad, kchunk); break;
+    case 128: hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 128, 2, 2>), grid, dim3(256), 0, st, A, lda, Bt, ldbt, out, ldo, M, N, Kpad, kchunk); break;
+    default: hipLaunchKernelGGL((gemm_bf16_nt_kernel<64, 256, 1, 4>), grid, dim3(256), 0, st, A, lda, Bt, ldbt, out, ldo, M, N, Kpad, kchunk); break;
+  }
+  return finish(part, splits, C, ldc, M, N, st);
+}
+
+hipError_t launch_gemm_fp8_nt(const uint8_t* A, int64_t lda, const int* EA, int64_t ea_i, int64_t ea_k,
+                              const uint8_t* Bt, int64_t ldbt, const int* EB, float* C, int64_t ldc,
+                              int64_t M, int64_t N, int64_t Kpad, int splits, float* part,
+                              hipStream_t st) {
+  if (M == 0 || N == 0) return hipSuccess;
+  if (N > 256 || Kpad % 128 || lda % 16 || ldbt % 16) return hipErrorInvalidValue;
+  float* out = splits > 1 ? part : C;
+  const int64_t ldo = splits > 1 ? N : ldc;
+  const int64_t kchunk = round_up(ceil_div(Kpad, splits), 128);
+  const int bn = bn_lp(N);
+  dim3 grid((unsigned)ceil_div(M, 128), (unsigned)ceil_div(N, bn), (unsigned)splits);
+  switch (bn) {
+    case 32: hipLaunchKernelGGL((gemm_fp8_nt_kernel<32, 1>), grid, dim3(256), 0, st, A, lda, EA, ea_i, ea_k, Bt, ldbt, EB, out, ldo, M, N, Kpad, kchunk); break;
+    case 64: hipLaunchKernelGGL((gemm_fp8_nt_kernel<64, 2>), grid, dim3(256), 0, st, A, lda, EA, ea_i, ea_k, Bt, ldbt, EB, out, ldo, M, N, Kpad, kchunk); break;
+    case 128: hipLaunchKernelGGL((gemm_fp8_nt_kernel<128, 2>), grid, dim3(256), 0, st, A, lda, EA, ea_i, ea_k, Bt, ldbt, EB, out, ldo, M, N, Kpad, kchunk); break;
+    default: hipLaunchKernelGGL((gemm_fp8_nt_kernel<256, 4>), grid, dim3(256), 0, st, A, lda, EA, ea_i, ea_k, Bt, ldbt, EB, out, ldo, M, N, Kpad, kchunk); break;
+  }
+  return finish(part, splits, C, ldc, M, N, st);
+}

@@ -31,6 +31,8 @@ struct Layout {
   size_t gemm_part, gram_part, G, R, qr_status;
   size_t hs_part, acc_w, acc_h, counters, Hc, GH, Wh, GW, scale_w;
   size_t res_part, res_out, flags;
+  int64_t ldq, ldqt;                 // low-precision copies of X: m x ldq and n x ldqt
+  size_t Xq, XqT, Ex, Bt, Eb;
   size_t total;
   size_t gemm_part_bytes, gram_splits_max;
 };
@@ -43,7 +45,8 @@ bool valid_params(const nmf_params* p, std::string* why) {
   if (p->k_sketch > 128) { *why = "k' > 128 is not supported by this build"; return false; }
   if (p->r > 64) { *why = "r > 64 is not supported by this build"; return false; }
   if (p->q < 0) { *why = "q must be >= 0"; return false; }
-  if (p->prec != NMF_FP32) { *why = "only FP32 range-finder products in this build"; return false; }
+  if (p->prec < NMF_FP32 || p->prec > NMF_FP8_E4M3) { *why = "prec must be FP32, BF16 or FP8_E4M3"; return false; }
+  if (p->refine_fp32 < 0 || p->refine_fp32 > 1) { *why = "refine_fp32 must be 0 or 1"; return false; }
   if (p->normalize < 0 || p->normalize > 2) { *why = "normalize must be 0, 1 or 2"; return false; }
   if (p->n % 4) { *why = "n must be a multiple of 4"; return false; }
   if (p->alpha < 0 || p->beta < 0) { *why = "alpha, beta must be >= 0"; return false; }
@@ -69,6 +72,15 @@ Layout make_layout(const nmf_params* p) {
   const int s1 = gemm_f32_pick_splits(m, k, n, 0), s2 = gemm_f32_pick_splits(n, k, m, 1);
   size_t gp = gemm_f32_part_floats(m, k, s1);
   size_t gp2 = gemm_f32_part_floats(n, k, s2);
+  L.ldq = round_up(n, 128);
+  L.ldqt = round_up(m, 128);
+  if (p->prec != NMF_FP32) {
+    const int bm = 128;
+    const int l1 = gemm_lp_pick_splits(m, k, L.ldq, bm), l2 = gemm_lp_pick_splits(n, k, L.ldqt, bm);
+    const size_t q1 = l1 > 1 ? (size_t)l1 * m * k : 0, q2 = l2 > 1 ? (size_t)l2 * n * k : 0;
+    if (q1 > gp) gp = q1;
+    if (q2 > gp2) gp2 = q2;
+  }
   L.gemm_part_bytes = (gp > gp2 ? gp : gp2) * f;
   L.gemm_part = pl.take(L.gemm_part_bytes);
   const int gs1 = gram_pick_splits(m, k), gs2 = gram_pick_splits(n, k);
@@ -90,6 +102,15 @@ Layout make_layout(const nmf_params* p) {
   L.res_part = pl.take(2 * (size_t)residual_blocks(m, n) * d);
   L.res_out = pl.take(2 * d);
   L.flags = pl.take(8 * sizeof(int));
+  L.Xq = L.XqT = L.Ex = L.Bt = L.Eb = 0;
+  if (p->prec != NMF_FP32) {
+    const size_t es = p->prec == NMF_BF16 ? 2 : 1;
+    L.Xq = pl.take((size_t)m * L.ldq * es);
+    L.XqT = pl.take((size_t)n * L.ldqt * es);
+    L.Ex = pl.take((size_t)ceil_div(m, 128) * ceil_div(n, 128) * sizeof(int));
+    L.Bt = pl.take((size_t)k * (L.ldq > L.ldqt ? L.ldq : L.ldqt) * es);
+    L.Eb = pl.take((size_t)ceil_div(L.ldq > L.ldqt ? L.ldq : L.ldqt, 128) * sizeof(int));
+  }
   L.total = pl.off;
   return L;
 }
@@ -146,6 +167,31 @@ hipError_t gemm(nmf_ctx* c, const float* A, int64_t lda, int at, const float* B,
   const int s = gemm_f32_pick_splits(M, N, K, at);
   return launch_gemm_f32(A, lda, at, B, c->L.KP, C, c->L.KP, M, N, K, s,
                          c->at<float>(c->L.gemm_part), c->st);
+}
+
+// Low-precision range-finder product: side 0 -> X B (B is n x k'), side 1 ->
+// X^T B (B is m x k'); the thin operand is rounded (and transposed) first.
+hipError_t gemm_lowp(nmf_ctx* c, int side, const float* B, float* C) {
+  Layout& L = c->L;
+  const int64_t m = c->p.m, n = c->p.n, k = c->p.k_sketch;
+  const int64_t M = side ? n : m, K = side ? m : n, Kpad = side ? L.ldqt : L.ldq;
+  const int s = gemm_lp_pick_splits(M, k, Kpad, 128);
+  float* part = c->at<float>(L.gemm_part);
+  hipError_t e;
+  if (c->p.prec == NMF_BF16) {
+    uint16_t* Bt = c->at<uint16_t>(L.Bt);
+    if ((e = launch_prep_b_bf16(B, L.KP, K, k, Bt, Kpad, c->st))) return e;
+    const uint16_t* A = side ? c->at<uint16_t>(L.XqT) : c->at<uint16_t>(L.Xq);
+    return launch_gemm_bf16_nt(A, Kpad, Bt, Kpad, C, L.KP, M, k, Kpad, s, part, c->st);
+  }
+  uint8_t* Bt = c->at<uint8_t>(L.Bt);
+  int* Eb = c->at<int>(L.Eb);
+  if ((e = launch_prep_b_fp8(B, L.KP, K, k, Eb, Bt, Kpad, c->st))) return e;
+  const uint8_t* A = side ? c->at<uint8_t>(L.XqT) : c->at<uint8_t>(L.Xq);
+  const int64_t tn = ceil_div(n, 128);
+  // X tile (a, b) exponent at Ex[a * tn + b]; A = X: (ti, tk) = (a, b); A = X^T: (ti, tk) = (b, a)
+  return launch_gemm_fp8_nt(A, Kpad, c->at<int>(L.Ex), side ? 1 : tn, side ? tn : 1, Bt, Kpad, Eb, C,
+                            L.KP, M, k, Kpad, s, part, c->st);
 }
 
 // W half-step: sweep W against (Xc, Hc, G_H) derived from the summed H-side
@@ -258,25 +304,52 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
   else HIPCHK(c, launch_philox_normal(omL, n, k, L.KP, 3u, c->p.seed, st));
   if (omega_R) HIPCHK(c, launch_copy2d(omR, L.KP, omega_R, k, m, k, st));
   else HIPCHK(c, launch_philox_normal(omR, m, k, L.KP, 4u, c->p.seed, st));
+  // range-finder products: FP32 on X, or on its low-precision copy (extension)
+  const bool lp = c->p.prec != NMF_FP32;
+  if (lp) {
+    if (c->p.prec == NMF_BF16)
+      HIPCHK(c, launch_quant_bf16(X, ldx, m, n, c->at<uint16_t>(L.Xq), L.ldq, c->at<uint16_t>(L.XqT),
+                                  L.ldqt, st));
+    else
+      HIPCHK(c, launch_quant_fp8(X, ldx, m, n, c->at<int>(L.Ex), c->at<uint8_t>(L.Xq), L.ldq,
+                                 c->at<uint8_t>(L.XqT), L.ldqt, st));
+  }
+  auto XB = [&](const float* B, float* C) -> hipError_t {            // X B  (m x k')
+    return lp ? gemm_lowp(c, 0, B, C) : gemm(c, X, ldx, 0, B, C, m, n);
+  };
+  auto XtB = [&](const float* B, float* C) -> hipError_t {           // X^T B (n x k')
+    return lp ? gemm_lowp(c, 1, B, C) : gemm(c, X, ldx, 1, B, C, n, m);
+  };
   // left range finder: Q_L = orth(X Omega_L); q x { Z = orth(X^T Q_L); Q_L = orth(X Z) }
-  HIPCHK(c, gemm(c, X, ldx, 0, omL, QL, m, n));
+  HIPCHK(c, XB(omL, QL));
   HIPCHK(c, orth(QL, L.KP, m, k, gp, G, R, qs, st));
   for (int it = 0; it < q; ++it) {
+    HIPCHK(c, XtB(QL, TN));
+    HIPCHK(c, orth(TN, L.KP, n, k, gp, G, R, qs, st));
+    HIPCHK(c, XB(TN, QL));
+    HIPCHK(c, orth(QL, L.KP, m, k, gp, G, R, qs, st));
+  }
+  // right range finder on X^T with Omega_R
+  HIPCHK(c, XtB(omR, QR));
+  HIPCHK(c, orth(QR, L.KP, n, k, gp, G, R, qs, st));
+  for (int it = 0; it < q; ++it) {
+    HIPCHK(c, XB(QR, TM));
+    HIPCHK(c, orth(TM, L.KP, m, k, gp, G, R, qs, st));
+    HIPCHK(c, XtB(TM, QR));
+    HIPCHK(c, orth(QR, L.KP, n, k, gp, G, R, qs, st));
+  }
+  // optional FP32 refinement: one power iteration per side on the exact X
+  if (lp && c->p.refine_fp32) {
     HIPCHK(c, gemm(c, X, ldx, 1, QL, TN, n, m));
     HIPCHK(c, orth(TN, L.KP, n, k, gp, G, R, qs, st));
     HIPCHK(c, gemm(c, X, ldx, 0, TN, QL, m, n));
     HIPCHK(c, orth(QL, L.KP, m, k, gp, G, R, qs, st));
-  }
-  // right range finder on X^T with Omega_R
-  HIPCHK(c, gemm(c, X, ldx, 1, omR, QR, n, m));
-  HIPCHK(c, orth(QR, L.KP, n, k, gp, G, R, qs, st));
-  for (int it = 0; it < q; ++it) {
     HIPCHK(c, gemm(c, X, ldx, 0, QR, TM, m, n));
     HIPCHK(c, orth(TM, L.KP, m, k, gp, G, R, qs, st));
     HIPCHK(c, gemm(c, X, ldx, 1, TM, QR, n, m));
     HIPCHK(c, orth(QR, L.KP, n, k, gp, G, R, qs, st));
   }
-  // projected data (Sec 4): Xh = X^T Q_L (X-hat^T), Xc = X Q_R (X-check)
+  // projected data (Sec 4), always FP32 on X: Xh = X^T Q_L (X-hat^T), Xc = X Q_R (X-check)
   HIPCHK(c, gemm(c, X, ldx, 1, QL, Xh, n, m));
   HIPCHK(c, gemm(c, X, ldx, 0, QR, Xc, m, n));
   HIPCHK(c, hipEventRecord(c->ev[1], st));
@@ -451,6 +524,57 @@ nmf_status nmf_gemm(const float* A, int64_t lda, int32_t a_trans, const float* B
   const size_t need = gemm_f32_part_floats(M, N, s) * sizeof(float);
   if (need && (!ws || ws_bytes < need)) return fail(nullptr, NMF_ENOMEM, "workspace too small");
   hipError_t e = launch_gemm_f32(A, lda, a_trans, B, ldb, C, ldc, M, N, K, s, (float*)ws, (hipStream_t)hs);
+  return e ? fail(nullptr, NMF_EHIP, hipGetErrorString(e)) : NMF_OK;
+}
+
+nmf_status nmf_quantize_x(const float* X, int64_t ldx, int64_t m, int64_t n, int32_t prec, void* Xq,
+                          int64_t ldq, void* XqT, int64_t ldqt, int32_t* tile_exp, void* hs) {
+  if (!X || !Xq || !XqT || m <= 0 || n <= 0 || ldx < n) return fail(nullptr, NMF_EINVAL, "bad arguments");
+  if (ldq < n || ldqt < m || ldq % 128 || ldqt % 128) return fail(nullptr, NMF_EINVAL, "ldq, ldqt: >= n, m and multiples of 128");
+  hipError_t e;
+  if (prec == NMF_BF16) {
+    e = launch_quant_bf16(X, ldx, m, n, (uint16_t*)Xq, ldq, (uint16_t*)XqT, ldqt, (hipStream_t)hs);
+  } else if (prec == NMF_FP8_E4M3) {
+    if (!tile_exp) return fail(nullptr, NMF_EINVAL, "tile_exp required for FP8");
+    e = launch_quant_fp8(X, ldx, m, n, tile_exp, (uint8_t*)Xq, ldq, (uint8_t*)XqT, ldqt, (hipStream_t)hs);
+  } else {
+    return fail(nullptr, NMF_EINVAL, "prec must be BF16 or FP8_E4M3");
+  }
+  return e ? fail(nullptr, NMF_EHIP, hipGetErrorString(e)) : NMF_OK;
+}
+
+size_t nmf_gemm_lowp_workspace_bytes(int64_t M, int64_t N, int64_t Kpad) {
+  const int s = gemm_lp_pick_splits(M, N, Kpad, 128);
+  return (size_t)N * Kpad * 2 + (size_t)ceil_div(Kpad, 128) * 4 + (s > 1 ? (size_t)s * M * N * 4 : 0) + 1024;
+}
+
+nmf_status nmf_gemm_lowp(int32_t prec, const void* A, int64_t lda, const int32_t* EA, int64_t ea_i,
+                         int64_t ea_k, const float* B, int64_t ldb, int64_t K, int64_t N, float* C,
+                         int64_t ldc, int64_t M, int64_t Kpad, void* ws, size_t ws_bytes, void* hs) {
+  if (M < 0 || N <= 0 || N > 256 || K <= 0 || Kpad < K || Kpad % 128 || ldb < N || ldc < N || lda < Kpad)
+    return fail(nullptr, NMF_EINVAL, "bad arguments");
+  if (M == 0) return NMF_OK;
+  if (!A || !B || !C || !ws || ws_bytes < nmf_gemm_lowp_workspace_bytes(M, N, Kpad) || ((uintptr_t)ws & 255))
+    return fail(nullptr, NMF_EINVAL, "null pointer or workspace too small / misaligned");
+  hipStream_t st = (hipStream_t)hs;
+  char* p = (char*)ws;
+  void* Bt = p;
+  p += round_up((int64_t)N * Kpad * 2, 256);
+  int* Eb = (int*)p;
+  p += round_up(ceil_div(Kpad, 128) * 4, 256);
+  float* part = (float*)p;
+  const int s = gemm_lp_pick_splits(M, N, Kpad, 128);
+  hipError_t e;
+  if (prec == NMF_BF16) {
+    e = launch_prep_b_bf16(B, ldb, K, N, (uint16_t*)Bt, Kpad, st);
+    if (!e) e = launch_gemm_bf16_nt((const uint16_t*)A, lda, (const uint16_t*)Bt, Kpad, C, ldc, M, N, Kpad, s, part, st);
+  } else if (prec == NMF_FP8_E4M3) {
+    if (!EA) return fail(nullptr, NMF_EINVAL, "EA required for FP8");
+    e = launch_prep_b_fp8(B, ldb, K, N, Eb, (uint8_t*)Bt, Kpad, st);
+    if (!e) e = launch_gemm_fp8_nt((const uint8_t*)A, lda, EA, ea_i, ea_k, (const uint8_t*)Bt, Kpad, Eb, C, ldc, M, N, Kpad, s, part, st);
+  } else {
+    return fail(nullptr, NMF_EINVAL, "prec must be BF16 or FP8_E4M3");
+  }
   return e ? fail(nullptr, NMF_EHIP, hipGetErrorString(e)) : NMF_OK;
 }
 

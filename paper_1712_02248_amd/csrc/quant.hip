@@ -1,0 +1,246 @@
+// Low-precision copies of X for the compression products (extension: BF16 and
+// OCP FP8 e4m3 range-finder passes).  X (m x n FP32) is read once and written
+// both as Xq (m x ldq) and as its transpose XqT (n x ldqt), so that X B and X^T B
+// are both products with K-contiguous operands; padding columns are zero.
+//
+// BF16: round to nearest, ties to even, on the FP32 bit pattern.
+// FP8 e4m3 (OCP "FN"): one power-of-two scale 2^e per 128 x 128 tile of X, e the
+// smallest integer with amax(tile) <= 448 2^e (0 for an all-zero tile); codes are
+// x 2^-e rounded to nearest even with saturation to +-448.  The scale is shared
+// by the tile and its transpose.
+#include "common.h"
+
+namespace {
+
+NMF_DEV uint16_t bf16_rne(float x) {
+  uint32_t u = __builtin_bit_cast(uint32_t, x);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40);  // quiet NaN
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// e4m3 code of y (|y| <= 448 after scaling), round to nearest even, saturating.
+NMF_DEV uint8_t e4m3_rne(float y) {
+  uint32_t u = __builtin_bit_cast(uint32_t, y);
+  const uint8_t sign = (uint8_t)((u >> 24) & 0x80u);
+  float a = fabsf(y);
+  if (!(a == a)) return (uint8_t)(sign | 0x7F);          // NaN
+  if (a >= 464.0f) return (uint8_t)(sign | 0x7E);        // beyond the rounding midpoint: saturate to 448
+  // subnormal grid spacing 2^-9 below 2^-6; normal spacing 2^(e-3)
+  int e;
+  frexpf(a, &e);                                         // a = f 2^e, f in [0.5, 1)
+  int ex = e - 1;                                        // a in [2^ex, 2^(ex+1))
+  if (ex < -6) ex = -6;
+  const float spacing = ldexpf(1.0f, ex - 3);
+  float qv = rintf(a / spacing) * spacing;               // exact: power-of-two spacing
+  if (qv > 448.0f) qv = 448.0f;
+  if (qv == 0.0f) return sign;
+  int qe;
+  const float qf = frexpf(qv, &qe);                      // qv = qf 2^qe
+  int E = qe - 1 + 7;                                    // biased exponent
+  uint32_t mant;
+  if (E <= 0) {                                          // subnormal: qv = m 2^-9
+    E = 0;
+    mant = (uint32_t)(qv * 512.0f);
+  } else {
+    mant = (uint32_t)((qf * 2.0f - 1.0f) * 8.0f);
+  }
+  return (uint8_t)(sign | (E << 3) | mant);
+}
+
+constexpr int QT = 64;   // transpose tile
+
+// BF16 copy and transposed copy, 64 x 64 tiles through LDS.
+__global__ void __launch_bounds__(256)
+quant_bf16_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
+                  uint16_t* __restrict__ Xq, int64_t ldq, uint16_t* __restrict__ XqT, int64_t ldqt) {
+  __shared__ uint16_t T[QT][QT + 2];
+  const int64_t i0 = (int64_t)blockIdx.y * QT, j0 = (int64_t)blockIdx.x * QT;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  uint16_t v[16];
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int ii = ty + 4 * p;
+    const int64_t gi = i0 + ii, gj = j0 + tx;
+    v[p] = (gi < m && gj < n) ? bf16_rne(X[gi * ldx + gj]) : (uint16_t)0;
+  }
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int ii = ty + 4 * p;
+    const int64_t gi = i0 + ii, gj = j0 + tx;
+    if (gi < m && gj < ldq) Xq[gi * ldq + gj] = v[p];
+    T[ii][tx] = v[p];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int jj = ty + 4 * p;
+    const int64_t gj = j0 + jj, gi = i0 + tx;
+    if (gj < n && gi < ldqt) XqT[gj * ldqt + gi] = T[tx][jj];
+  }
+}
+
+// Per-tile power-of-two exponents of X (128 x 128 tiles): one workgroup per tile.
+__global__ void __launch_bounds__(256)
+tile_exp_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n, int* __restrict__ E,
+                int tiles_n) {
+  __shared__ float red[256];
+  const int64_t i0 = (int64_t)blockIdx.y * 128, j0 = (int64_t)blockIdx.x * 128;
+  float amax = 0.f;
+  for (int e = threadIdx.x; e < 128 * 128; e += 256) {
+    const int ii = e / 128, jj = e % 128;
+    const int64_t gi = i0 + ii, gj = j0 + jj;
+    if (gi < m && gj < n) amax = fmaxf(amax, fabsf(X[gi * ldx + gj]));
+  }
+  red[threadIdx.x] = amax;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float a = red[0];
+    int e = 0;
+    if (a > 0.f) {
+      // smallest e with a <= 448 2^e (exact comparisons with power-of-two factors)
+      int fe;
+      frexpf(a / 448.0f, &fe);
+      e = fe - 1;
+      while (a > ldexpf(448.0f, e)) ++e;
+      while (a <= ldexpf(448.0f, e - 1)) --e;
+    }
+    E[blockIdx.y * tiles_n + blockIdx.x] = e;
+  }
+}
+
+// FP8 codes of X and of its transpose, with the tile exponents.
+__global__ void __launch_bounds__(256)
+quant_fp8_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
+                 const int* __restrict__ E, int tiles_n, uint8_t* __restrict__ Xq, int64_t ldq,
+                 uint8_t* __restrict__ XqT, int64_t ldqt) {
+  __shared__ uint8_t T[QT][QT + 4];
+  const int64_t i0 = (int64_t)blockIdx.y * QT, j0 = (int64_t)blockIdx.x * QT;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int e = E[(i0 / 128) * tiles_n + (j0 / 128)];    // 64-tiles nest inside 128-tiles
+  const float s = ldexpf(1.0f, -e);
+  uint8_t v[16];
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int ii = ty + 4 * p;
+    const int64_t gi = i0 + ii, gj = j0 + tx;
+    v[p] = (gi < m && gj < n) ? e4m3_rne(X[gi * ldx + gj] * s) : (uint8_t)0;
+  }
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int ii = ty + 4 * p;
+    const int64_t gi = i0 + ii, gj = j0 + tx;
+    if (gi < m && gj < ldq) Xq[gi * ldq + gj] = v[p];
+    T[ii][tx] = v[p];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int jj = ty + 4 * p;
+    const int64_t gj = j0 + jj, gi = i0 + tx;
+    if (gj < n && gi < ldqt) XqT[gj * ldqt + gi] = T[tx][jj];
+  }
+}
+
+// B (K x N FP32, ldb) -> Bt (N x ldbt BF16), transposed and rounded; zero padding.
+__global__ void __launch_bounds__(256)
+prep_b_bf16_kernel(const float* __restrict__ B, int64_t ldb, int64_t K, int64_t N,
+                   uint16_t* __restrict__ Bt, int64_t ldbt) {
+  const int64_t total = N * ldbt;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / ldbt, k = e - j * ldbt;
+    Bt[e] = (k < K) ? bf16_rne(B[k * ldb + j]) : (uint16_t)0;
+  }
+}
+
+// B -> Bt in e4m3 with one power-of-two scale per 128-row block of B (shared by
+// all columns): Ebt[kb] = smallest e with amax(B[128 kb .. 128 kb + 127, :]) <= 448 2^e.
+__global__ void __launch_bounds__(256)
+prep_b_fp8_exp_kernel(const float* __restrict__ B, int64_t ldb, int64_t K, int64_t N, int* __restrict__ Ebt) {
+  __shared__ float red[256];
+  const int64_t k0 = (int64_t)blockIdx.x * 128;
+  float amax = 0.f;
+  for (int64_t e = threadIdx.x; e < 128 * N; e += 256) {
+    const int64_t k = k0 + e / N, j = e % N;
+    if (k < K) amax = fmaxf(amax, fabsf(B[k * ldb + j]));
+  }
+  red[threadIdx.x] = amax;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float a = red[0];
+    int e = 0;
+    if (a > 0.f) {
+      int fe;
+      frexpf(a / 448.0f, &fe);
+      e = fe - 1;
+      while (a > ldexpf(448.0f, e)) ++e;
+      while (a <= ldexpf(448.0f, e - 1)) --e;
+    }
+    Ebt[blockIdx.x] = e;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+prep_b_fp8_kernel(const float* __restrict__ B, int64_t ldb, int64_t K, int64_t N,
+                  const int* __restrict__ Ebt, uint8_t* __restrict__ Bt, int64_t ldbt) {
+  const int64_t total = N * ldbt;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / ldbt, k = e - j * ldbt;
+    uint8_t v = 0;
+    if (k < K) v = e4m3_rne(B[k * ldb + j] * ldexpf(1.0f, -Ebt[k / 128]));
+    Bt[e] = v;
+  }
+}
+
+unsigned grid1(int64_t total) {
+  int64_t g = ceil_div(total, 256);
+  if (g < 1) g = 1;
+  if (g > 16384) g = 16384;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_quant_bf16(const float* X, int64_t ldx, int64_t m, int64_t n, uint16_t* Xq,
+                             int64_t ldq, uint16_t* XqT, int64_t ldqt, hipStream_t st) {
+  dim3 grid((unsigned)ceil_div(ldq, QT), (unsigned)ceil_div(ldqt, QT));
+  hipLaunchKernelGGL(quant_bf16_kernel, grid, dim3(256), 0, st, X, ldx, m, n, Xq, ldq, XqT, ldqt);
+  return hipGetLastError();
+}
+
+hipError_t launch_quant_fp8(const float* X, int64_t ldx, int64_t m, int64_t n, int* E, uint8_t* Xq,
+                            int64_t ldq, uint8_t* XqT, int64_t ldqt, hipStream_t st) {
+  const int tn = (int)ceil_div(n, 128), tm = (int)ceil_div(m, 128);
+  hipLaunchKernelGGL(tile_exp_kernel, dim3(tn, tm), dim3(256), 0, st, X, ldx, m, n, E, tn);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dim3 grid((unsigned)ceil_div(ldq, QT), (unsigned)ceil_div(ldqt, QT));
+  hipLaunchKernelGGL(quant_fp8_kernel, grid, dim3(256), 0, st, X, ldx, m, n, E, tn, Xq, ldq, XqT, ldqt);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_b_bf16(const float* B, int64_t ldb, int64_t K, int64_t N, uint16_t* Bt,
+                              int64_t ldbt, hipStream_t st) {
+  hipLaunchKernelGGL(prep_b_bf16_kernel, dim3(grid1(N * ldbt)), dim3(256), 0, st, B, ldb, K, N, Bt, ldbt);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep_b_fp8(const float* B, int64_t ldb, int64_t K, int64_t N, int* Ebt, uint8_t* Bt,
+                             int64_t ldbt, hipStream_t st) {
+  hipLaunchKernelGGL(prep_b_fp8_exp_kernel, dim3((unsigned)ceil_div(K, 128)), dim3(256), 0, st, B, ldb, K,
+                     N, Ebt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(prep_b_fp8_kernel, dim3(grid1(N * ldbt)), dim3(256), 0, st, B, ldb, K, N, Ebt, Bt, ldbt);
+  return hipGetLastError();
+}

@@ -51,6 +51,10 @@ _SIGS = {
     "nmf_gemm_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64, c_i32]),
     "nmf_gemm": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_i64, c_vp, c_i64, c_i64, c_i64, c_i64, c_vp,
                          c_sz, c_vp]),
+    "nmf_quantize_x": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp]),
+    "nmf_gemm_lowp_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64]),
+    "nmf_gemm_lowp": (c_i32, [c_i32, c_vp, c_i64, c_vp, c_i64, c_i64, c_vp, c_i64, c_i64, c_i64, c_vp, c_i64,
+                              c_i64, c_i64, c_vp, c_sz, c_vp]),
     "nmf_orth_workspace_bytes": (c_sz, [c_i64, c_i32]),
     "nmf_orth": (c_i32, [c_vp, c_i64, c_i64, c_i32, c_vp, c_sz, c_vp, c_i32_p]),
 }
@@ -247,3 +251,32 @@ def orth(Y, stream=None):
     sh = c_i32()
     _check(lib.nmf_orth(_ptr(Y), Y.stride(0), rows, k, base, nb, _stream(stream), ctypes.byref(sh)))
     return sh.value
+
+
+def quantize_x(X, prec, stream=None):
+    """Low-precision copies of X: returns (Xq, XqT, tile_exp or None) as raw device
+    tensors (uint16 BF16 patterns or uint8 e4m3 codes), ld padded to 128."""
+    lib = load()
+    m, n = X.shape
+    ldq, ldqt = -(-n // 128) * 128, -(-m // 128) * 128
+    dt = torch.int16 if prec == NMF_BF16 else torch.uint8
+    Xq = torch.empty(m, ldq, dtype=dt, device=X.device)
+    XqT = torch.empty(n, ldqt, dtype=dt, device=X.device)
+    E = torch.empty(-(-m // 128), -(-n // 128), dtype=torch.int32, device=X.device) if prec == NMF_FP8_E4M3 else None
+    _check(lib.nmf_quantize_x(_ptr(X), X.stride(0), m, n, prec, _ptr(Xq), ldq, _ptr(XqT), ldqt, _ptr(E),
+                              _stream(stream)))
+    return Xq, XqT, E
+
+
+def gemm_lowp(prec, A, K, B, E=None, ea=(0, 0), stream=None):
+    """C = A[:, :K] @ B with A a low-precision copy (K-contiguous rows, ld % 128 == 0)."""
+    lib = load()
+    M, Kpad = A.shape
+    N = B.shape[1]
+    C = torch.empty(M, N, dtype=torch.float32, device=A.device)
+    nb = lib.nmf_gemm_lowp_workspace_bytes(M, N, Kpad)
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device=A.device)
+    base = (ws.data_ptr() + 255) // 256 * 256
+    _check(lib.nmf_gemm_lowp(prec, _ptr(A), A.stride(0), _ptr(E), ea[0], ea[1], _ptr(B), B.stride(0), K, N,
+                             _ptr(C), C.stride(0), M, Kpad, base, nb, _stream(stream)))
+    return C

@@ -1,0 +1,107 @@
+"""Low-precision compression extension on the GPU: quantisers bit-exact against
+library casts and the oracle's block-scale model, low-precision products
+against FP64 on the same rounded operands, and whole runs against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+from oracle import nmf as onmf
+from oracle import quant
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_1712_02248_amd import nmfrp
+    nmfrp.load()
+    return nmfrp
+
+
+def _x(m, n, seed, spread=True):
+    g = np.random.default_rng(seed)
+    X = g.random((m, n)) * (10.0 ** g.integers(-3, 3, (m, n)) if spread else 1.0)
+    X[: m // 7, : n // 5] = 0.0                       # an all-zero region (zero tiles)
+    return X.astype(np.float32)
+
+
+@pytest.mark.parametrize("m,n", [(300, 200), (128, 128), (1000, 36), (64, 1100)])
+def test_quantize_bf16_bit_exact(lib, m, n):
+    print(f"quant bf16 {m}x{n}", flush=True)
+    X = _x(m, n, m + n)
+    Xq, XqT, _ = lib.quantize_x(torch.from_numpy(X).cuda(), lib.NMF_BF16)
+    Xq, XqT = Xq.cpu(), XqT.cpu()
+    want = torch.from_numpy(X).to(torch.bfloat16).view(torch.int16)
+    assert torch.equal(Xq[:, :n], want)
+    assert torch.equal(XqT[:, :m], want.T.contiguous())
+    assert int(Xq[:, n:].abs().sum()) == 0 and int(XqT[:, m:].abs().sum()) == 0
+
+
+@pytest.mark.parametrize("m,n", [(300, 200), (256, 384), (1000, 36)])
+def test_quantize_fp8_matches_block_model(lib, m, n):
+    print(f"quant fp8 {m}x{n}", flush=True)
+    X = _x(m, n, 7 * m + n)
+    Xq, XqT, E = lib.quantize_x(torch.from_numpy(X).cuda(), lib.NMF_FP8_E4M3)
+    Xq, XqT, E = Xq.cpu(), XqT.cpu(), E.cpu().numpy()
+    deq_ref, E_ref, codes_ref = quant.e4m3_block_quantise(X.astype(np.float64))
+    assert np.array_equal(E, E_ref)
+    codes = Xq[:, :n].contiguous().view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(codes, codes_ref)
+    codesT = XqT[:, :m].contiguous().view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(codesT, codes_ref.T)
+    assert int(Xq[:, n:].to(torch.int32).sum()) == 0
+
+
+@pytest.mark.parametrize("fmt,m,n,k,side", [("bf16", 1000, 300, 20, 0), ("bf16", 1000, 300, 64, 1),
+                                            ("bf16", 4096, 2048, 128, 1), ("fp8", 1000, 300, 20, 0),
+                                            ("fp8", 1000, 300, 64, 1), ("fp8", 2048, 4096, 128, 0),
+                                            ("bf16", 300, 5000, 256, 0), ("fp8", 513, 700, 256, 1)])
+def test_lowp_products(lib, fmt, m, n, k, side):
+    print(f"lowp gemm {fmt} {m}x{n} k={k} side={side}", flush=True)
+    X = _x(m, n, m + 3 * n + k, spread=False)
+    prec = lib.NMF_BF16 if fmt == "bf16" else lib.NMF_FP8_E4M3
+    Xd = torch.from_numpy(X).cuda()
+    Xq, XqT, E = lib.quantize_x(Xd, prec)
+    K = m if side else n
+    B = np.random.default_rng(k).standard_normal((K, k)).astype(np.float32)
+    tn = -(-n // 128)
+    A = XqT if side else Xq
+    ea = (1, tn) if side else (tn, 1)
+    C = lib.gemm_lowp(prec, A, K, torch.from_numpy(B).cuda(), E, ea).cpu().numpy().astype(np.float64)
+    Xdeq = onmf.quantize_data(X, fmt)
+    Aref = Xdeq.T if side else Xdeq
+    Bq = onmf.quantize_thin(B, fmt)
+    ref = Aref @ Bq
+    bound = 2.0 * K * 2.0 ** -24 * (np.abs(Aref) @ np.abs(Bq)) + 1e-30
+    assert np.all(np.abs(C - ref) <= bound)
+
+
+@pytest.mark.parametrize("fmt,refine", [("bf16", 0), ("bf16", 1), ("fp8", 0), ("fp8", 1)])
+def test_lowp_compression_runs(lib, fmt, refine):
+    """Whole run with low-precision range-finder products: the error after the
+    iterations is compared with the oracle's model of the same rounding (R_q)
+    and with the exact FP64 run (R_true); both gaps are printed.  Compared near
+    convergence (400 iterations): early iterates depend sensitively on the
+    basis of the sketch, which the two sides round differently."""
+    print(f"lowp run {fmt} refine={refine}", flush=True)
+    m, n, r, kp, q, iters = 2000, 512, 10, 20, 2, 400
+    seed = 4242
+    X = datagen.planted_parts(m, n, r, seed)[0]
+    OL = datagen.gaussian(n, kp, seed, datagen.S_OMEGA_L)
+    OR = datagen.gaussian(m, kp, seed, datagen.S_OMEGA_R)
+    W0, H0 = datagen.init_factors(X.mean(), m, n, r, seed)
+    prec = lib.NMF_BF16 if fmt == "bf16" else lib.NMF_FP8_E4M3
+    ctx = lib.NMF(m, n, r, kp, q, seed=seed, prec=prec, refine_fp32=refine)
+    Xd = torch.from_numpy(X).cuda()
+    ctx.compress(Xd, torch.from_numpy(OL).cuda(), torch.from_numpy(OR).cuda())
+    ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
+    ctx.step(iters)
+    e = ctx.residual(Xd)
+    Rq = onmf.fasthals_rp(X, OL, OR, q, W0, H0, iters, fmt=fmt, refine=bool(refine))["e"]
+    Rt = onmf.fasthals_rp(X, OL, OR, q, W0, H0, iters)["e"]
+    print(f"  e_gpu={e:.6e} R_q={Rq:.6e} R_true={Rt:.6e} |gpu-Rq|={abs(e - Rq):.2e} |gpu-Rtrue|={abs(e - Rt):.2e}",
+          flush=True)
+    assert abs(e - Rq) <= 1e-4
+    assert abs(e - Rt) <= 1e-4
