@@ -1,13 +1,28 @@
 #!/usr/bin/env python3
-"""Time-to-relative-error for compressed NMF (FastHALS-RP) on one MI355X.
+"""Time-to-relative-error for compressed NMF (FastHALS-RP) on one MI355X:
+BF16 compression with a learned warm start of H, against plain FP32.
 
 One step = the whole hot path on the workload's X, which is resident in HBM
-when the clock starts: draw the Gaussian test matrices on the device, compress
-(range finder with power iterations and CholeskyQR2, sketches), set the initial
-factors, then FastHALS-RP iterations with an exact FP64 residual every
---check-every iterations until e <= eps.  eps = (1 + 1e-3) * e_oracle, where
-e_oracle is the FP64 oracle's error after the workload's iteration count
-(stored by tests/golden/make_oracle_errors.py, which calls only the oracle).
+when the clock starts: compress (device-drawn Gaussian test matrices, range
+finder with power iterations and FP64 CholeskyQR2, FP32 sketches), set the
+initial factors, then FastHALS-RP iterations with an exact FP64 residual check
+schedule until e <= eps.  eps = (1 + 1e-3) * e_oracle, where e_oracle is the FP64
+oracle's error after the workload's iteration count (stored by
+tests/golden/make_oracle_errors.py, which calls only the oracle).
+
+Variants (same X, same cold factors):
+  plain      FP32 range finder, cold start (the paper's method).
+  bf16_warm  BF16 range-finder products with FP32 accumulation, then the
+             learned warm start: the network's H rows on the compressed
+             columns, each kept only if it beats the cold row on the compressed
+             residual.  The step includes the alignment products, inference and
+             selection; it excludes training.
+  others     bf16 / fp8 (+ FP32 refinement) cold starts and fp32_warm, reported
+             alongside.
+The network is trained before timing on pairs from new columns of the same
+generator (same basis W0, new coefficients): a reference fit on one new draw
+gives Q_train and W_ref; every pair is (Q_train^T x, NNLS row of x against
+Q_train^T W_ref).  Training time is reported separately.
 
 Prints one JSON line (rank 0).  --gpus above 1 is refused: the path is built
 and measured on a single GPU.
@@ -40,6 +55,13 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=16384, help="rows of X in the oracle sample")
+    ap.add_argument("--pairs", type=int, default=200000, help="training pairs (rounded up to 4096)")
+    ap.add_argument("--epochs", type=int, default=50, help="most training passes")
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--nnls-sweeps", type=int, default=100)
+    ap.add_argument("--refine-sweeps", type=int, default=20,
+                    help="column-NNLS sweeps on the warm rows against the reference dictionary")
+    ap.add_argument("--headline-only", action="store_true", help="time only plain and bf16_warm")
     return ap.parse_args()
 
 
@@ -87,6 +109,135 @@ def cpu_baseline(cfg, X, W0, H0, iters_needed, rows):
     return dict(value=round(full, 3), unit="s", cores=blas_threads(), kind="oracle", sample=sample)
 
 
+def gpu_fresh_columns(torch, nmfrp, W0d, ncols, seed, chunk, noise=0.01):
+    """New columns of the parts family drawn on the device (input synthesis,
+    untimed): max(0, W0 h + noise N(0,1)) with h from the chunk's own stream."""
+    import datagen
+    H = torch.from_numpy(datagen.fresh_h(W0d.shape[1], ncols, seed, chunk).astype(np.float32)).cuda()
+    N = nmfrp.gaussian(W0d.shape[0], ncols, 1000 + chunk, seed)
+    return torch.clamp_min(W0d @ H + noise * N, 0.0)
+
+
+def train_warm_start(torch, nmfrp, cfg, seed, args):
+    """Reference fit, pair generation and Adam training (all untimed)."""
+    import datagen
+    from paper_1712_02248_amd import warmstart
+    m, n, r, kp, q = cfg["m"], cfg["n"], cfg["r"], cfg["kp"], cfg["q"]
+    info = {}
+    W0gen = torch.from_numpy(datagen.parts_w0(m, cfg["r_true"], seed).astype(np.float32)).cuda()
+    t0 = time.perf_counter()
+    # reference fit on one new draw of the generator
+    Xt = gpu_fresh_columns(torch, nmfrp, W0gen, n, seed, 0)
+    ctx = nmfrp.NMF(m, n, r, kp, q, seed=seed + 1)
+    Wi, Hi = datagen.init_factors(float(Xt.mean()), m, n, r, seed + 1)
+    ctx.compress(Xt)
+    ctx.init(torch.from_numpy(Wi).cuda(), torch.from_numpy(Hi).cuda())
+    _, e_ref = ctx.fit(Xt, cfg["iters"], 0.0, cfg["iters"])
+    Q_train = ctx.left_basis()
+    W_ref, _ = ctx.factors()
+    Wh_star = warmstart.compressed_factor(Q_train, W_ref)
+    del Xt
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # pairs from new columns
+    chunk = 4096
+    nchunks = -(-args.pairs // chunk)
+    npairs = nchunks * chunk
+    Xin = torch.empty(npairs, kp, device="cuda")
+    T = torch.empty(npairs, r, device="cuda")
+    for c in range(nchunks):
+        Xf = gpu_fresh_columns(torch, nmfrp, W0gen, chunk, seed, 1 + c)
+        a, b = warmstart.make_pairs(Q_train, Wh_star, Xf, sweeps=args.nnls_sweeps)
+        Xin[c * chunk:(c + 1) * chunk] = a
+        T[c * chunk:(c + 1) * chunk] = b
+    Xv = gpu_fresh_columns(torch, nmfrp, W0gen, chunk, seed, 1 + nchunks)
+    Xin_v, T_v = warmstart.make_pairs(Q_train, Wh_star, Xv, sweeps=args.nnls_sweeps)
+    del Xf, Xv
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    # Adam training in rounds of 5 passes; the learning rate drops 3x when the
+    # held-out loss improves by less than 1 % in a round, training stops after
+    # the third drop or at the pass limit
+    hidden = 512
+    p0 = torch.from_numpy(datagen.mlp_he_init(kp, hidden, r, seed)).cuda()
+    net = nmfrp.Mlp(kp, hidden, r, p0, max_batch=4096)
+    order = torch.from_numpy(datagen.batch_orders(npairs, args.epochs, seed).reshape(-1)).cuda()
+    hist, val = [], []
+    best = float("inf")
+    ep, lr, drops = 0, args.lr, 0
+    while ep < args.epochs:
+        e5 = min(5, args.epochs - ep)
+        hist += net.train(Xin, T, e5, 1024, lr, order=order[ep * npairs:(ep + e5) * npairs])
+        ep += e5
+        v, _ = net.loss_grad(Xin_v, T_v)
+        val.append(v)
+        log(f"[bench] warm-start training: {ep} passes, lr {lr:.1e}, train loss {hist[-1]:.4e}, held-out {v:.4e}")
+        if v > 0.99 * best:
+            drops += 1
+            if drops == 3:
+                break
+            lr /= 3.0
+        best = min(best, v)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    info.update(reference_fit=dict(iters=cfg["iters"], rel_err=e_ref, seconds=round(t1 - t0, 3)),
+                pairs=dict(count=npairs, held_out=chunk, nnls_sweeps=args.nnls_sweeps,
+                           seconds=round(t2 - t1, 3)),
+                training=dict(net=f"{kp}->{hidden}->{hidden}->{r}", passes=ep, batch=1024, lr=args.lr,
+                              lr_final=lr,
+                              loss_first=hist[0], loss_last=hist[-1], held_out_loss=val,
+                              seconds=round(t3 - t2, 3)))
+    return net, Q_train, W_ref, info
+
+
+def time_variant(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, prec, refine, warm, steps, warmup):
+    from paper_1712_02248_amd import warmstart
+    m, n, r, kp, q = cfg["m"], cfg["n"], cfg["r"], cfg["kp"], cfg["q"]
+    max_iters = args.max_iters or cfg["iters"]
+    ctx = nmfrp.NMF(m, n, r, kp, q, seed=seed, prec=prec, refine_fp32=refine)
+
+    def step():
+        ctx.compress(Xd)
+        if warm is None:
+            ctx.init(W0d, H0d)
+        else:
+            net, Q_train, W_ref, sweeps = warm
+            warmstart.warm_init(ctx, net, Q_train, W_ref, Ht_cold=H0d, refine_sweeps=sweeps)
+        return ctx.fit(Xd, max_iters, eps, args.check_every)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    times, its, es = [], [], []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        it, e = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        its.append(it)
+        es.append(e)
+    # error right after the initialisation and after 20 iterations, then the
+    # stage split (library events) of a repeat of the last step's work
+    def start():
+        ctx.compress(Xd)
+        if warm is None:
+            ctx.init(W0d, H0d)
+            return None
+        net, Q_train, W_ref, sweeps = warm
+        return warmstart.warm_init(ctx, net, Q_train, W_ref, Ht_cold=H0d, refine_sweeps=sweeps, count=True)
+
+    nrej = start()
+    e0 = ctx.residual(Xd)
+    ctx.step(20)
+    e20 = ctx.residual(Xd)
+    start()
+    ctx.step(its[-1])
+    e_fixed = ctx.residual(Xd)
+    st = ctx.stage_times()
+    return dict(times=times, iters=its, e=es, e_init=e0, e_20=e20, e_fixed=e_fixed, stages=st, rejected=nrej,
+                ctx=ctx)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -103,9 +254,10 @@ def main():
     name = args.workload
     cfg = dict(datagen.CONFIGS[name])
     cfg["name"] = name
+    if cfg["family"] != "parts":
+        sys.exit("bench.py: the warm-start protocol draws new columns of the parts family (c2, c5)")
     m, n, r, kp, q = cfg["m"], cfg["n"], cfg["r"], cfg["kp"], cfg["q"]
     iters_cfg = cfg["iters"]
-    max_iters = args.max_iters or iters_cfg
     seed = datagen.cfg_seed(name)
 
     golden = json.load(open(GOLDEN)).get(name) if os.path.exists(GOLDEN) else None
@@ -116,60 +268,61 @@ def main():
     Xd = torch.from_numpy(X).to(dev)
     W0d = torch.from_numpy(W0).to(dev)
     H0d = torch.from_numpy(H0).to(dev)
-    ctx = nmfrp.NMF(m, n, r, kp, q, seed=seed)
 
     if golden is not None:
         e_oracle = golden["e"]
         eps = (1.0 + 1e-3) * e_oracle
         eps_src = "oracle"
     else:  # no stored oracle value: plain FP32 run of the configured length
-        ctx.compress(Xd)
-        ctx.init(W0d, H0d)
-        _, e_ref = ctx.fit(Xd, iters_cfg, 0.0, iters_cfg)
+        c0 = nmfrp.NMF(m, n, r, kp, q, seed=seed)
+        c0.compress(Xd)
+        c0.init(W0d, H0d)
+        _, e_ref = c0.fit(Xd, iters_cfg, 0.0, iters_cfg)
         e_oracle = None
         eps = (1.0 + 1e-3) * e_ref
         eps_src = "gpu-fp32-reference"
     log(f"[bench] eps = {eps:.6e} ({eps_src})")
 
-    def step():
-        ctx.compress(Xd)
-        ctx.init(W0d, H0d)
-        return ctx.fit(Xd, max_iters, eps, args.check_every)
+    log("[bench] training the warm-start network (untimed)")
+    net, Q_train, W_ref, warm_info = train_warm_start(torch, nmfrp, cfg, seed, args)
+    warm = (net, Q_train, W_ref, args.refine_sweeps)
+    warm_net_only = (net, Q_train, W_ref, 0)
 
-    for w in range(args.warmup):
-        it, e = step()
-        log(f"[bench] warmup {w}: iters={it} e={e:.6e}")
-    torch.cuda.synchronize()
-    times, its, es = [], [], []
+    variants = [("plain", nmfrp.NMF_FP32, 0, None, args.steps, args.warmup),
+                ("bf16_warm", nmfrp.NMF_BF16, 0, warm, args.steps, args.warmup)]
+    if not args.headline_only:
+        variants += [("bf16", nmfrp.NMF_BF16, 0, None, 3, 1),
+                     ("bf16_refine", nmfrp.NMF_BF16, 1, None, 3, 1),
+                     ("fp8_refine", nmfrp.NMF_FP8_E4M3, 1, None, 3, 1),
+                     ("fp8_refine_warm", nmfrp.NMF_FP8_E4M3, 1, warm, 3, 1),
+                     ("fp32_warm", nmfrp.NMF_FP32, 0, warm, 3, 1),
+                     ("bf16_warm_net_only", nmfrp.NMF_BF16, 0, warm_net_only, 3, 1),
+                     ("fp8_warm", nmfrp.NMF_FP8_E4M3, 0, warm, 3, 1)]
+    out = {}
     t_all0 = time.perf_counter()
-    for s in range(args.steps):
-        t0 = time.perf_counter()
-        it, e = step()
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        its.append(it)
-        es.append(e)
-        log(f"[bench] step {s}: {times[-1] * 1e3:.2f} ms iters={it} e={e:.6e}")
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_all0
-    st = ctx.stage_times()
-    # stage split of one step (events inside the library, last step)
-    ctx.compress(Xd)
-    ctx.init(W0d, H0d)
-    ctx.step(its[-1])
-    e_fixed = ctx.residual(Xd)
-    stages = ctx.stage_times()
+    for vname, prec, refine, w, steps, warmup in variants:
+        v = time_variant(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, prec, refine, w, steps, warmup)
+        out[vname] = v
+        log(f"[bench] {vname}: median {statistics.median(v['times']) * 1e3:.2f} ms, iters {v['iters']}, "
+            f"e_init {v['e_init']:.4e}, e {v['e'][-1]:.6e}, rejected {v['rejected']}")
+    head, plain = out["bf16_warm"], out["plain"]
+    total_head = sum(head["times"])
 
-    # ---- dominant-kernel timing: the FP32 MFMA skinny GEMMs of the compression,
-    # at the exact shapes compress launches, with HIP events on the launch stream.
+    # ---- kernel timing at the exact shapes of the compression, HIP events on the
+    # stream the kernels are launched on.
     B_n = torch.randn(n, kp, device=dev)
     B_m = torch.randn(m, kp, device=dev)
     Y_m = torch.empty(m, kp, device=dev)
     Y_n = torch.empty(n, kp, device=dev)
+    Xq, XqT, _ = nmfrp.quantize_x(Xd, nmfrp.NMF_BF16)
     stream = torch.cuda.current_stream()
+    ldq, ldqt = Xq.shape[1], XqT.shape[1]
+    kern = (("fp32 X*B", lambda: nmfrp.gemm(Xd, B_n, False, Y_m), 4.0 * m * n),
+            ("fp32 X^T*B", lambda: nmfrp.gemm(Xd, B_m, True, Y_n), 4.0 * m * n),
+            ("bf16 X*B", lambda: nmfrp.gemm_lowp(nmfrp.NMF_BF16, Xq, n, B_n), 2.0 * m * ldq),
+            ("bf16 X^T*B", lambda: nmfrp.gemm_lowp(nmfrp.NMF_BF16, XqT, m, B_m), 2.0 * n * ldqt))
     res = {}
-    for label, fn, flops in (("X*B", lambda: nmfrp.gemm(Xd, B_n, False, Y_m), 2.0 * m * n * kp),
-                             ("X^T*B", lambda: nmfrp.gemm(Xd, B_m, True, Y_n), 2.0 * m * n * kp)):
+    for label, fn, xbytes in kern:
         fn()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
@@ -178,39 +331,58 @@ def main():
         ev1.record(stream)
         ev1.synchronize()
         ms = ev0.elapsed_time(ev1) / args.kernel_reps
-        res[label] = dict(ms=ms, tflops=flops / (ms * 1e-3) / 1e12,
-                          hbm_gbs=4.0 * m * n / (ms * 1e-3) / 1e9)
-        log(f"[bench] {label}: {ms:.4f} ms  {res[label]['tflops']:.1f} TFLOP/s")
-    dom = res["X*B"]
+        flops = 2.0 * m * n * kp
+        res[label] = dict(ms=round(ms, 5), tflops=round(flops / (ms * 1e-3) / 1e12, 2),
+                          x_read_gbs=round(xbytes / (ms * 1e-3) / 1e9, 1))
+        log(f"[bench] {label}: {ms:.4f} ms  {res[label]['tflops']:.1f} TFLOP/s  X at {res[label]['x_read_gbs']} GB/s")
+    dom = res["fp32 X*B"]
     roofline = dict(bound="mfma", kernel="gemm_f32_kernel<128,64,2,2,false> (X*B, FP32 MFMA)",
-                    achieved=round(dom["tflops"], 2), peak=PEAK_FP32_MFMA_TFLOPS, unit="TFLOP/s",
+                    achieved=dom["tflops"], peak=PEAK_FP32_MFMA_TFLOPS, unit="TFLOP/s",
                     frac=round(dom["tflops"] / PEAK_FP32_MFMA_TFLOPS, 4), traffic=None,
-                    algorithmic_flops_per_launch=2.0 * m * n * kp, launch_ms=round(dom["ms"], 5))
+                    algorithmic_flops_per_launch=2.0 * m * n * kp, launch_ms=dom["ms"])
 
-    per_iter_ms = stages["step_ms"] / max(its[-1], 1)
+    def summary(v):
+        st = v["stages"]
+        it = v["iters"][-1]
+        return dict(median_s=round(statistics.median(v["times"]), 6), times_s=[round(t, 6) for t in v["times"]],
+                    iters_to_eps=v["iters"], e_at_stop=v["e"], e_after_init=v["e_init"],
+                    e_after_20_iters=v["e_20"],
+                    e_after_same_iters=v["e_fixed"],
+                    rejected_rows=v["rejected"],
+                    stage_ms=dict(compress=round(st["compress_ms"], 3), iterations=round(st["step_ms"], 3),
+                                  per_iteration=round(st["step_ms"] / max(it, 1), 4),
+                                  residual=round(st["residual_ms"], 4)))
+
+    per_iter_ms = plain["stages"]["step_ms"] / max(plain["iters"][-1], 1)
     upd_bytes = 8.0 * (m + n) * (kp + r)
+    vmed = statistics.median(head["times"])
+    pmed = statistics.median(plain["times"])
     line = dict(
-        metric="time-to-rel-error eps (s), plain FP32 compressed NMF (FastHALS-RP)",
-        value=round(statistics.median(times), 6), unit="s", n_gpus=1, steps=args.steps,
-        warmup=args.warmup, ms_per_step=round(total / args.steps * 1e3, 3), higher_is_better=False,
-        scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+        metric="time-to-rel-error eps (s), BF16 compression + learned warm start (plain FP32 alongside)",
+        value=round(vmed, 6), unit="s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=round(total_head / args.steps * 1e3, 3), higher_is_better=False,
+        scaling="weak", vs_baseline=None, dtype="bf16", data="synthetic",
         config=dict(workload=f"{name}: X {m}x{n} FP32 synthetic ({cfg['family']} family, r_true="
-                    f"{cfg['r_true']}), r={r}, k'={kp}, q={q}, eps=(1+1e-3) e_oracle({iters_cfg} it)",
-                    m=m, n=n, r=r, k_sketch=kp, q=q, iters_cfg=iters_cfg, check_every=args.check_every),
-        eps=eps, eps_source=eps_src, e_oracle=e_oracle, iters_to_eps=its, e_at_stop=es,
-        e_after_fixed_iters=e_fixed, abs_err_vs_oracle=(abs(e_fixed - e_oracle) if e_oracle and its[-1] == iters_cfg else None),
-        stage_ms=dict(compress=round(stages["compress_ms"], 3), iterations=round(stages["step_ms"], 3),
-                      per_iteration=round(per_iter_ms, 4), residual=round(stages["residual_ms"], 4)),
-        gemm=dict((k, dict(ms=round(v["ms"], 4), tflops=round(v["tflops"], 2),
-                           frac_fp32_mfma=round(v["tflops"] / PEAK_FP32_MFMA_TFLOPS, 4),
-                           x_read_gbs=round(v["hbm_gbs"], 1))) for k, v in res.items()),
-        update_loop=dict(algorithmic_bytes_per_iteration=upd_bytes,
+                    f"{cfg['r_true']}), r={r}, k'={kp}, q={q}, eps=(1+1e-3) e_oracle({iters_cfg} it); "
+                    f"BF16 range finder + MLP warm start of H ({args.refine_sweeps} NNLS sweeps) vs plain FP32",
+                    m=m, n=n, r=r, k_sketch=kp, q=q, iters_cfg=iters_cfg, check_every=args.check_every,
+                    refine_sweeps=args.refine_sweeps),
+        eps=eps, eps_source=eps_src, e_oracle=e_oracle,
+        plain_fp32=dict(value=round(pmed, 6), **summary(plain)),
+        speedup_vs_plain=round(pmed / vmed, 3),
+        variants={k: summary(v) for k, v in out.items()},
+        warm_start=warm_info,
+        gemm=res,
+        update_loop=dict(algorithmic_bytes_per_iteration=upd_bytes, per_iteration_ms=round(per_iter_ms, 4),
                          gbs=round(upd_bytes / (per_iter_ms * 1e-3) / 1e9, 1)),
         roofline=roofline,
     )
+    if e_oracle is not None:
+        line["abs_err_vs_oracle_plain"] = (abs(plain["e_fixed"] - e_oracle)
+                                           if plain["iters"][-1] == iters_cfg else None)
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a row sample (cpu_baseline)")
-        line["cpu_baseline"] = cpu_baseline(cfg, X, W0, H0, its[-1], args.cpu_rows)
+        line["cpu_baseline"] = cpu_baseline(cfg, X, W0, H0, plain["iters"][-1], args.cpu_rows)
     print(json.dumps(line), flush=True)
 
 

@@ -50,9 +50,14 @@ def planted_c1(m, n, r, seed, noise=0.01):
     return X.astype(np.float32), W0, H0
 
 
-def planted_parts(m, n, r, seed, noise=0.01, density=0.2, block=8192):
+def parts_w0(m, r, seed, density=0.2):
+    """Basis of the parts family: W0_ij ~ Bernoulli(density) U[0,1)."""
     g = rng(seed, S_W0)
-    W0 = (g.random((m, r)) < density) * g.random((m, r))
+    return (g.random((m, r)) < density) * g.random((m, r))
+
+
+def planted_parts(m, n, r, seed, noise=0.01, density=0.2, block=8192):
+    W0 = parts_w0(m, r, seed, density)
     H0 = rng(seed, S_H0).random((r, n))
     X = np.empty((m, n), dtype=np.float32)
     gn = rng(seed, S_NOISE)
@@ -122,3 +127,38 @@ def gaussian(rows, cols, seed, sub):
 
 def uniform(shape, seed, sub):
     return rng(seed, sub).random(shape).astype(np.float32)
+
+
+# ---------------------------------------------------------------- warm start
+
+def fresh_h(r, ncols, seed, chunk):
+    """Fresh coefficient columns U[0,1) (r x ncols) for chunk `chunk` of new
+    columns of a planted family (same W0, new H0)."""
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), S_FRESH, int(chunk)])))
+    return g.random((r, ncols))
+
+
+def fresh_parts_columns(W0, ncols, seed, chunk, noise=0.01):
+    """New columns of the parts family on the host: max(0, W0 h + noise N(0,1)),
+    returned as an m x ncols FP32 block (small instances only)."""
+    H = fresh_h(W0.shape[1], ncols, seed, chunk)
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), S_FRESH, int(chunk), 1])))
+    X = W0 @ H + noise * g.standard_normal((W0.shape[0], ncols))
+    return np.maximum(X, 0.0).astype(np.float32)
+
+
+def mlp_he_init(k_in, hidden, r_out, seed):
+    """He-normal initial weights N(0, 2 / fan_in) and zero biases, flat FP32 in
+    the order W1 (k_in x hidden), b1, W2, b2, W3 (hidden x r_out), b3."""
+    g = rng(seed, S_MLP)
+    parts = []
+    for fi, fo in ((k_in, hidden), (hidden, hidden), (hidden, r_out)):
+        parts.append((g.standard_normal((fi, fo)) * np.sqrt(2.0 / fi)).ravel())
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def batch_orders(npairs, epochs, seed):
+    """One random permutation of the training pairs per pass (epochs x npairs, int32)."""
+    g = rng(seed, S_BATCH)
+    return np.stack([g.permutation(npairs) for _ in range(epochs)]).astype(np.int32)

@@ -109,9 +109,12 @@ nmf_status nmf_residual(nmf_ctx* ctx, const float* X, int64_t ldx, double* rel_e
 
 /* Runs steps in chunks, evaluating the exact residual after each chunk, until
  * e <= eps or max_iters iterations (the paper leaves the stopping rule open:
- * Alg 1-4).  check_every > 0: fixed chunk; check_every == 0: adaptive chunks of
- * 50, 20 or 10 iterations while the last e exceeds eps by more than 10 %, 1 %
- * or less.  max_iters == 0 only evaluates e.  Synchronising.  *iters_done and
+ * Alg 1-4).  check_every > 0: fixed chunk; check_every == 0: e is evaluated
+ * at the current factors first; the next chunk is 50, 20, 10 or 5 iterations
+ * as that e exceeds eps by more than 10 %, 1 %, 0.3 % or less, and every later
+ * chunk is 1.5 times the iterations a straight-line extrapolation of the last
+ * two evaluations needs to reach eps, clamped to 5..50 (50 if e did not
+ * fall).  max_iters == 0 only evaluates e.  Synchronising.  *iters_done and
  * *rel_err report the iterations run and the last e. */
 nmf_status nmf_fit(nmf_ctx* ctx, const float* X, int64_t ldx, int32_t max_iters, double eps,
                    int32_t check_every, int32_t* iters_done, double* rel_err);
@@ -188,6 +191,92 @@ nmf_status nmf_gemm_lowp(int32_t prec, const void* A, int64_t lda, const int32_t
 size_t nmf_orth_workspace_bytes(int64_t rows, int32_t k);
 nmf_status nmf_orth(float* Y, int64_t ldy, int64_t rows, int32_t k, void* workspace,
                     size_t ws_bytes, void* hip_stream, int32_t* shifted);
+
+
+/* --------------------------------------------------- learned warm start of H
+ * Extension (the paper has no learned component): a multilayer perceptron maps
+ * a compressed column x-hat (a row of Xh, length k') to an initial H row
+ * (length r).  Net: z1 = x W1 + b1, a1 = relu(z1); z2 = a1 W2 + b2,
+ * a2 = relu(z2); z3 = a2 W3 + b3, y = softplus(z3).  Parameters are one flat
+ * FP32 vector in the order W1 (k' x hidden), b1, W2 (hidden x hidden), b2,
+ * W3 (hidden x r), b3, each weight row-major [fan_in][fan_out].  The net sees
+ * x / ||x||_2 and its output is multiplied by ||x||_2 (H is positively
+ * homogeneous in X); a zero row maps to 0.  Training loss on a batch of B pairs
+ * (x, t): L = 1/(2B) sum ||y - t / ||x|| ||^2; optimiser Adam (beta1 = 0.9,
+ * beta2 = 0.999, eps = 1e-8, bias-corrected).  All MLP buffers are device
+ * memory; every call queues on the stream given at creation. */
+
+/* Length of the flat parameter vector (0 for invalid sizes). */
+int64_t nmf_mlp_n_params(int32_t k_in, int32_t hidden, int32_t r_out);
+
+/* Device workspace (caller-owned, 256-byte aligned) for a net that processes at
+ * most max_batch rows per pass: parameters, gradients, Adam moments and
+ * activations.  0 for invalid sizes (1 <= k_in <= 1024, 1 <= hidden <= 4096,
+ * 1 <= r_out <= 256, 1 <= max_batch <= 65536). */
+size_t nmf_mlp_workspace_bytes(int32_t k_in, int32_t hidden, int32_t r_out, int32_t max_batch);
+
+/* Creates a net over the workspace; params (device, nmf_mlp_n_params floats) are
+ * copied as the initial parameters and the Adam state is zeroed. */
+nmf_status nmf_mlp_create(int32_t k_in, int32_t hidden, int32_t r_out, int32_t max_batch,
+                          const float* params, void* workspace, size_t ws_bytes, void* hip_stream,
+                          nmf_mlp** out);
+void nmf_mlp_destroy(nmf_mlp* net);
+const char* nmf_mlp_last_error(const nmf_mlp* net);
+
+/* Parameter export / import (flat layout above, device).  set_params also zeroes
+ * the Adam moments and step count.  Asynchronous. */
+nmf_status nmf_mlp_get_params(nmf_mlp* net, float* flat);
+nmf_status nmf_mlp_set_params(nmf_mlp* net, const float* flat);
+
+/* Loss and gradients of one batch without an update: in_rows batch x k'
+ * (ld_in), tgt_rows batch x r (ld_tgt), batch <= max_batch.  grads_flat
+ * (device, may be NULL) receives the gradient in the flat layout; *loss (host,
+ * may be NULL; then the call is asynchronous) receives L. */
+nmf_status nmf_mlp_loss_grad(nmf_mlp* net, const float* in_rows, int64_t ld_in, const float* tgt_rows,
+                             int64_t ld_tgt, int32_t batch, double* loss, float* grads_flat);
+
+/* Adam training over npairs pairs for `epochs` passes in batches of `batch`
+ * rows (the last batch of a pass may be smaller).  order (device int32,
+ * epochs x npairs, may be NULL = natural order): pass e visits pairs
+ * order[e*npairs .. e*npairs+npairs-1], each a permutation of 0..npairs-1
+ * drawn by the caller.  epoch_loss (host, epochs doubles, may be NULL; then
+ * the call is asynchronous) receives the mean batch loss of every pass. */
+nmf_status nmf_mlp_train(nmf_mlp* net, const float* in_rows, int64_t ld_in, const float* tgt_rows,
+                         int64_t ld_tgt, int64_t npairs, const int32_t* order, int32_t epochs,
+                         int32_t batch, float lr, double* epoch_loss);
+
+/* out_rows (rows x r, ld_out) = ||x|| softplus(net(x / ||x||)) for every row x of
+ * in_rows (rows x k', ld_in).  Asynchronous. */
+nmf_status nmf_mlp_infer(nmf_mlp* net, const float* in_rows, int64_t ld_in, int64_t rows,
+                         float* out_rows, int64_t ld_out);
+
+/* Training targets: for every row x of Xr (rows x k, ldx) the non-negative
+ * least-squares row h = argmin_{h >= 0} ||x - Wh h||^2, Wh k x r (row-major),
+ * approximated by `sweeps` H sweeps of eq fastHALS_a with Wh fixed, from h = 0
+ * (warm_start = 0) or from the rows already in Ht (warm_start = 1).  r <= 64,
+ * (k r + r^2) 4 bytes <= 64 KiB.  Ht: rows x r (ldh).  Asynchronous. */
+nmf_status nmf_nnls_rows(const float* Xr, int64_t ldx, int64_t rows, int32_t k, const float* Wh,
+                         int32_t r, int32_t sweeps, int32_t warm_start, float* Ht, int64_t ldh,
+                         void* hip_stream);
+
+/* Warm start of a compressed context: Ht row j is the net's output on the
+ * aligned compressed column x-tilde_j = M x-hat_j (align_M: k' x k' device,
+ * row-major, typically M = Q_train^T Q_L for the basis Q_train the net was
+ * trained in; NULL = identity), unless the cold row does better on the
+ * compressed residual rho(h) = ||x-hat_j - Wh_ref h||^2 (FP64), in which case
+ * the cold row is kept.  Wh_ref: k' x r device (e.g. Q_L^T W of a reference
+ * fit).  Cold rows: Ht_cold (n x r device) or, with NULL, U[0,1) * init_scale
+ * from Philox stream 6.  refine_sweeps > 0 then runs that many column-NNLS
+ * sweeps (as nmf_nnls_rows) against Wh_ref from the selected rows; each sweep
+ * can only lower a row's rho, so no row ends worse than its cold row.  W is
+ * set as by nmf_init (W0, typically the reference dictionary, or Philox stream
+ * 5), so the first nmf_step update is the W half-step.  The net must have
+ * k_in = k' and r_out = r; it runs on the context's stream.  *n_rejected (host,
+ * may be NULL; then the call is asynchronous) receives the number of cold rows
+ * kept. */
+nmf_status nmf_init_learned(nmf_ctx* ctx, nmf_mlp* net, const float* align_M, const float* Wh_ref,
+                            const float* W0, const float* Ht_cold, float init_scale,
+                            int32_t refine_sweeps, int64_t* n_rejected);
 
 #ifdef __cplusplus
 }

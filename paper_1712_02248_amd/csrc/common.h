@@ -119,3 +119,29 @@ hipError_t launch_scale_cols(float* dst, int64_t ldd, const float* src, int64_t 
                              int cols, const float* scale, hipStream_t st);
 hipError_t launch_check_nonneg(const float* X, int64_t ldx, int64_t m, int64_t n, int* flags,
                                hipStream_t st);
+// learned warm start (mlp.hip)
+hipError_t launch_mlp_gemm(int at, int bt, int epi, const float* A, int lda, const float* B, int ldb,
+                           float* C, int ldc, int M, int N, int K, const float* bias, const float* aux,
+                           int ldaux, hipStream_t st);
+hipError_t launch_scale_rows(const float* X, int64_t ldx, const int* idx, int64_t nsrc, int Bn, int k,
+                             const float* T, int64_t ldt, int r, float* Xs, float* Ts, float* nrm, hipStream_t st);
+hipError_t launch_nnls_rows(const float* Xr, int64_t ldx, int n, int k, const float* Wh, int r, int sweeps,
+                            int warm, float* H, int64_t ldh, hipStream_t st);
+hipError_t launch_loss_grad(const float* Z3, const float* Ts, int Bn, int r, float* dZ3, double* lpart,
+                            double* loss_out, double* loss_acc, hipStream_t st);
+hipError_t launch_colsum(const float* dZ, int Bn, int N, float* gb, hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, int t,
+                       hipStream_t st);
+hipError_t launch_infer_out(const float* Z3, const float* nrm, int Bn, int r, float* out, int64_t ldo,
+                            hipStream_t st);
+hipError_t launch_select(const float* Xh, int64_t ldx, int n, int k, const float* Wh, int r, const float* Hn,
+                         const float* Hc, float* Hout, int* rejected, long long* count, hipStream_t st);
+
+// host runtime glue shared by nmfrp.cpp and mlp_rt.cpp
+struct nmf_mlp;
+hipError_t mlp_infer_rows(nmf_mlp* net, const float* in, int64_t ld_in, int64_t n, float* out, int64_t ldo,
+                          hipStream_t st);
+void mlp_dims(const nmf_mlp* net, int* k, int* h, int* r);
+void nmf_set_thread_error(const char* msg);
+
+

@@ -1,0 +1,388 @@
+// Learned warm start for H (extension; the paper has no learned component).
+// Net: z1 = x W1 + b1, a1 = relu(z1); z2 = a1 W2 + b2, a2 = relu(z2);
+// z3 = a2 W3 + b3, y = softplus(z3).  Inputs are the rows x-hat of Xh scaled by
+// 1/||x-hat|| (H is positively homogeneous in X), outputs are multiplied back.
+// Loss L = 1/(2B) sum ||y - t / ||x-hat||||^2, Adam (Kingma & Ba) on all
+// parameters, He-normal initial weights, zero biases.
+#include "common.h"
+
+namespace {
+
+// C[M x N] = op(A) op(B) (+ bias) with an epilogue, FP32 MFMA (32x32x2).
+//   AT: A stored K x M (used transposed); BT: B stored N x K (used transposed).
+//   EPI 0: plain; 1: relu; 2: multiply by (aux > 0) (ReLU backward mask).
+// 64 x 64 output tile per 256-thread workgroup, waves 2 x 2 of 32 x 32.
+template <bool AT, bool BT, int EPI>
+__global__ void __launch_bounds__(256)
+mlp_gemm_kernel(const float* __restrict__ A, int lda, const float* __restrict__ B, int ldb,
+                float* __restrict__ C, int ldc, int M, int N, int K, const float* __restrict__ bias,
+                const float* __restrict__ aux, int ldaux) {
+  constexpr int BM = 64, BN = 64, BK = 32;
+  __shared__ float As[BK][BM + 4];
+  __shared__ float Bs[BK][BN + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int i0 = blockIdx.x * BM, j0 = blockIdx.y * BN;
+  f32x16 acc;
+#pragma unroll
+  for (int x = 0; x < 16; ++x) acc[x] = 0.f;
+  float va[8], vb[8];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int e = tid + 256 * p;
+      int i, k;
+      if (!AT) { i = e / BK; k = e % BK; } else { k = e / BM; i = e % BM; }
+      const int gi = i0 + i, gk = k0 + k;
+      va[p] = (gi < M && gk < K) ? (AT ? A[(int64_t)gk * lda + gi] : A[(int64_t)gi * lda + gk]) : 0.f;
+      int j, kb;
+      if (BT) { j = e / BK; kb = e % BK; } else { kb = e / BN; j = e % BN; }
+      const int gj = j0 + j, gkb = k0 + kb;
+      vb[p] = (gj < N && gkb < K) ? (BT ? B[(int64_t)gj * ldb + gkb] : B[(int64_t)gkb * ldb + gj]) : 0.f;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int e = tid + 256 * p;
+      int i, k;
+      if (!AT) { i = e / BK; k = e % BK; } else { k = e / BM; i = e % BM; }
+      As[k][i] = va[p];
+      int j, kb;
+      if (BT) { j = e / BK; kb = e % BK; } else { kb = e / BN; j = e % BN; }
+      Bs[kb][j] = vb[p];
+    }
+  };
+  const int half = lane >> 5, l32 = lane & 31;
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (k0 + BK < K) load(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 2) {
+      const float a = As[kk + half][wm * 32 + l32];
+      const float b = Bs[kk + half][wn * 32 + l32];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    }
+  }
+  // D[i][j]: lane j + 32 ((i / 4) % 2), register (i / 8) 4 + i % 4
+  const int gj = j0 + wn * 32 + l32;
+#pragma unroll
+  for (int x = 0; x < 16; ++x) {
+    const int gi = i0 + wm * 32 + (x >> 2) * 8 + half * 4 + (x & 3);
+    if (gi < M && gj < N) {
+      float v = acc[x];
+      if (bias) v += bias[gj];
+      if (EPI == 1) v = v > 0.f ? v : 0.f;
+      if (EPI == 2) v = aux[(int64_t)gi * ldaux + gj] > 0.f ? v : 0.f;
+      C[(int64_t)gi * ldc + gj] = v;
+    }
+  }
+}
+
+// Row norms of X (B x k) and the scaled rows: Xs = X / ||x|| (0 for a zero row);
+// T (if given) is scaled the same way into Ts.  Source row b is idx[b] when an
+// index list is given (a training batch drawn from the pair set), else b.
+__global__ void __launch_bounds__(256)
+scale_rows_kernel(const float* __restrict__ X, int64_t ldx, const int* __restrict__ idx, int64_t nsrc, int Bn,
+                  int k, const float* __restrict__ T, int64_t ldt, int r, float* __restrict__ Xs,
+                  float* __restrict__ Ts, float* __restrict__ nrm) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= Bn) return;
+  const int64_t src = idx ? (int64_t)idx[row] : (int64_t)row;
+  if (src < 0 || src >= nsrc) {   // an index outside the pair set contributes a zero pair
+    for (int c = lane; c < k; c += 64) Xs[(int64_t)row * k + c] = 0.f;
+    if (T)
+      for (int c = lane; c < r; c += 64) Ts[(int64_t)row * r + c] = 0.f;
+    if (lane == 0) nrm[row] = 0.f;
+    return;
+  }
+  double s = 0.0;
+  for (int c = lane; c < k; c += 64) {
+    const double v = X[src * ldx + c];
+    s += v * v;
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  const double nv = sqrt(s);
+  const float inv = nv > 0.0 ? (float)(1.0 / nv) : 0.f;
+  for (int c = lane; c < k; c += 64) Xs[(int64_t)row * k + c] = X[src * ldx + c] * inv;
+  if (T)
+    for (int c = lane; c < r; c += 64) Ts[(int64_t)row * r + c] = T[src * ldt + c] * inv;
+  if (lane == 0) nrm[row] = (float)nv;
+}
+
+// Column NNLS min_{h >= 0} ||x - Wh h||^2 for every row x of Xr (n x k), by
+// repeated H sweeps of eq fastHALS_a with Wh fixed, starting from h = 0 (or
+// from the rows already in H when warm):
+//   h_j <- [h_j + (p_j - (G h)_j) / G_jj]_+ ,  p = Wh^T x,  G = Wh^T Wh.
+// One thread per row; Wh and G in LDS (every lane reads the same entry).
+template <int RMAX>
+__global__ void __launch_bounds__(256)
+nnls_rows_kernel(const float* __restrict__ Xr, int64_t ldx, int n, int k, const float* __restrict__ Wh, int r,
+                 int sweeps, int warm, float* __restrict__ H, int64_t ldh) {
+  extern __shared__ float sm[];
+  float* whs = sm;              // k x r
+  float* gs = sm + k * r;       // r x r
+  for (int e = threadIdx.x; e < k * r; e += 256) whs[e] = Wh[e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < r * r; e += 256) {
+    const int a = e / r, b = e % r;
+    double s = 0.0;
+    for (int c = 0; c < k; ++c) s += (double)whs[c * r + a] * whs[c * r + b];
+    gs[e] = (float)s;
+  }
+  __syncthreads();
+  const int row = blockIdx.x * 256 + threadIdx.x;
+  if (row >= n) return;
+  float p[RMAX], h[RMAX];
+#pragma unroll
+  for (int j = 0; j < RMAX; ++j) {
+    p[j] = 0.f;
+    h[j] = (warm && j < r) ? H[(int64_t)row * ldh + j] : 0.f;
+  }
+  for (int c = 0; c < k; ++c) {
+    const float x = Xr[(int64_t)row * ldx + c];
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j)
+      if (j < r) p[j] = fmaf(x, whs[c * r + j], p[j]);
+  }
+  for (int it = 0; it < sweeps; ++it) {
+#pragma unroll
+    for (int j = 0; j < RMAX; ++j) {
+      if (j < r) {
+        const float gjj = gs[j * r + j];
+        if (gjj > 0.f) {
+          float g = p[j];
+#pragma unroll
+          for (int l = 0; l < RMAX; ++l)
+            if (l < r) g = fmaf(-gs[j * r + l], h[l], g);
+          h[j] = fmaxf(h[j] + g / gjj, 0.f);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RMAX; ++j)
+    if (j < r) H[(int64_t)row * ldh + j] = h[j];
+}
+
+NMF_DEV float softplusf(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
+NMF_DEV float sigmoidf(float z) {
+  if (z >= 0.f) return 1.f / (1.f + expf(-z));
+  const float e = expf(z);
+  return e / (1.f + e);
+}
+
+// dZ3 = (softplus(z3) - t) / B * sigmoid(z3); per-block FP64 partial of the loss.
+__global__ void __launch_bounds__(256)
+loss_grad_kernel(const float* __restrict__ Z3, const float* __restrict__ Ts, int Bn, int r,
+                 float* __restrict__ dZ3, double* __restrict__ lpart) {
+  __shared__ double red[256];
+  const int64_t total = (int64_t)Bn * r;
+  double s = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const float z = Z3[e];
+    const float d = softplusf(z) - Ts[e];
+    s += (double)d * d;
+    dZ3[e] = d / (float)Bn * sigmoidf(z);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
+}
+
+// loss = sum(lpart) / (2B), accumulated into *acc (FP64); one thread.
+__global__ void loss_sum_kernel(const double* __restrict__ lpart, int nb, int Bn, double* __restrict__ out,
+                                double* __restrict__ acc) {
+  double s = 0.0;
+  for (int i = 0; i < nb; ++i) s += lpart[i];
+  s /= 2.0 * Bn;
+  out[0] = s;
+  if (acc) acc[0] += s;
+}
+
+// gb[j] = sum_i dZ[i][j] (FP64, fixed order over rows in 8 slices).
+__global__ void __launch_bounds__(256)
+colsum_kernel(const float* __restrict__ dZ, int Bn, int N, float* __restrict__ gb) {
+  __shared__ double red[8][33];
+  const int jj = threadIdx.x & 31, sl = threadIdx.x >> 5;
+  const int j = blockIdx.x * 32 + jj;
+  double s = 0.0;
+  if (j < N)
+    for (int i = sl; i < Bn; i += 8) s += dZ[(int64_t)i * N + j];
+  red[sl][jj] = s;
+  __syncthreads();
+  if (sl == 0 && j < N) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) t += red[q][jj];
+    gb[j] = (float)t;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1, float* __restrict__ m2,
+            int64_t n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    const float gv = g[e];
+    const float a = b1 * m1[e] + (1.f - b1) * gv;
+    const float b = b2 * m2[e] + (1.f - b2) * gv * gv;
+    m1[e] = a;
+    m2[e] = b;
+    p[e] -= lr * (a / c1) / (sqrtf(b / c2) + eps);
+  }
+}
+
+// out = softplus(z3) * ||x||
+__global__ void __launch_bounds__(256)
+infer_out_kernel(const float* __restrict__ Z3, const float* __restrict__ nrm, int Bn, int r,
+                 float* __restrict__ out, int64_t ldo) {
+  const int64_t total = (int64_t)Bn * r;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / r, j = e - i * r;
+    out[i * ldo + j] = softplusf(Z3[e]) * nrm[i];
+  }
+}
+
+// Warm-start selection: rho(h) = ||x - Wh h||^2 in FP64 for the net's and the
+// cold rows; keep the net's row unless it is worse.  One wave per row.
+__global__ void __launch_bounds__(256)
+select_kernel(const float* __restrict__ Xh, int64_t ldx, int n, int k, const float* __restrict__ Wh, int r,
+              const float* __restrict__ Hn, const float* __restrict__ Hc, float* __restrict__ Hout,
+              int* __restrict__ rejected) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double rn = 0.0, rc = 0.0;
+  for (int c = lane; c < k; c += 64) {
+    double pn = 0.0, pc = 0.0;
+    for (int j = 0; j < r; ++j) {
+      const double w = Wh[c * r + j];
+      pn += w * Hn[(int64_t)row * r + j];
+      pc += w * Hc[(int64_t)row * r + j];
+    }
+    const double x = Xh[(int64_t)row * ldx + c];
+    rn += (x - pn) * (x - pn);
+    rc += (x - pc) * (x - pc);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    rn += __shfl_xor(rn, off);
+    rc += __shfl_xor(rc, off);
+  }
+  const bool rej = rn > rc;
+  for (int j = lane; j < r; j += 64) Hout[(int64_t)row * r + j] = rej ? Hc[(int64_t)row * r + j] : Hn[(int64_t)row * r + j];
+  if (lane == 0) rejected[row] = rej ? 1 : 0;
+}
+
+__global__ void count_kernel(const int* __restrict__ flags, int n, long long* __restrict__ out) {
+  __shared__ long long red[256];
+  long long s = 0;
+  for (int i = threadIdx.x; i < n; i += 256) s += flags[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+unsigned g1(int64_t total) {
+  int64_t g = ceil_div(total, 256);
+  if (g < 1) g = 1;
+  if (g > 4096) g = 4096;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_mlp_gemm(int at, int bt, int epi, const float* A, int lda, const float* B, int ldb,
+                           float* C, int ldc, int M, int N, int K, const float* bias, const float* aux,
+                           int ldaux, hipStream_t st) {
+  if (M == 0 || N == 0) return hipSuccess;
+  dim3 grid((unsigned)ceil_div(M, 64), (unsigned)ceil_div(N, 64));
+#define MLP_GEMM_CASE(AT_, BT_, EPI_)                                                                  \
+  if (at == AT_ && bt == BT_ && epi == EPI_) {                                                         \
+    hipLaunchKernelGGL((mlp_gemm_kernel<AT_, BT_, EPI_>), grid, dim3(256), 0, st, A, lda, B, ldb, C, ldc, \
+                       M, N, K, bias, aux, ldaux);                                                     \
+    return hipGetLastError();                                                                          \
+  }
+  MLP_GEMM_CASE(false, false, 0)
+  MLP_GEMM_CASE(false, false, 1)
+  MLP_GEMM_CASE(false, true, 0)
+  MLP_GEMM_CASE(false, true, 2)
+  MLP_GEMM_CASE(true, false, 0)
+#undef MLP_GEMM_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_scale_rows(const float* X, int64_t ldx, const int* idx, int64_t nsrc, int Bn, int k,
+                             const float* T, int64_t ldt, int r, float* Xs, float* Ts, float* nrm, hipStream_t st) {
+  if (Bn == 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_rows_kernel, dim3((unsigned)ceil_div(Bn, 4)), dim3(256), 0, st, X, ldx, idx, nsrc, Bn,
+                     k, T, ldt, r, Xs, Ts, nrm);
+  return hipGetLastError();
+}
+
+hipError_t launch_nnls_rows(const float* Xr, int64_t ldx, int n, int k, const float* Wh, int r, int sweeps,
+                            int warm, float* H, int64_t ldh, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const size_t lds = (size_t)(k * r + r * r) * sizeof(float);
+  const dim3 grid((unsigned)ceil_div(n, 256));
+  if (r <= 16)
+    hipLaunchKernelGGL(nnls_rows_kernel<16>, grid, dim3(256), lds, st, Xr, ldx, n, k, Wh, r, sweeps, warm, H, ldh);
+  else if (r <= 32)
+    hipLaunchKernelGGL(nnls_rows_kernel<32>, grid, dim3(256), lds, st, Xr, ldx, n, k, Wh, r, sweeps, warm, H, ldh);
+  else if (r <= 64)
+    hipLaunchKernelGGL(nnls_rows_kernel<64>, grid, dim3(256), lds, st, Xr, ldx, n, k, Wh, r, sweeps, warm, H, ldh);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+int loss_blocks(int Bn, int r) { return (int)g1((int64_t)Bn * r) < 256 ? (int)g1((int64_t)Bn * r) : 256; }
+
+hipError_t launch_loss_grad(const float* Z3, const float* Ts, int Bn, int r, float* dZ3, double* lpart,
+                            double* loss_out, double* loss_acc, hipStream_t st) {
+  const int nb = loss_blocks(Bn, r);
+  hipLaunchKernelGGL(loss_grad_kernel, dim3(nb), dim3(256), 0, st, Z3, Ts, Bn, r, dZ3, lpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(1), 0, st, lpart, nb, Bn, loss_out, loss_acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float* dZ, int Bn, int N, float* gb, hipStream_t st) {
+  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)ceil_div(N, 32)), dim3(256), 0, st, dZ, Bn, N, gb);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m1, float* m2, int64_t n, float lr, int t,
+                       hipStream_t st) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float c1 = (float)(1.0 - pow(0.9, t)), c2 = (float)(1.0 - pow(0.999, t));
+  hipLaunchKernelGGL(adam_kernel, dim3(g1(n)), dim3(256), 0, st, p, g, m1, m2, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_infer_out(const float* Z3, const float* nrm, int Bn, int r, float* out, int64_t ldo,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(infer_out_kernel, dim3(g1((int64_t)Bn * r)), dim3(256), 0, st, Z3, nrm, Bn, r, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(const float* Xh, int64_t ldx, int n, int k, const float* Wh, int r, const float* Hn,
+                         const float* Hc, float* Hout, int* rejected, long long* count, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(select_kernel, dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, Xh, ldx, n, k, Wh, r,
+                     Hn, Hc, Hout, rejected);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(count_kernel, dim3(1), dim3(256), 0, st, rejected, n, count);
+  return hipGetLastError();
+}

@@ -117,6 +117,8 @@ Layout make_layout(const nmf_params* p) {
 
 }  // namespace
 
+void nmf_set_thread_error(const char* msg) { g_err = msg; }
+
 struct nmf_ctx {
   nmf_params p;
   Layout L;
@@ -367,11 +369,59 @@ nmf_status nmf_init(nmf_ctx* c, const float* W0, const float* Ht0, float init_sc
   float *W = c->at<float>(L.W), *Ht = c->at<float>(L.Ht);
   if (W0) HIPCHK(c, launch_copy2d(W, r, W0, r, m, r, c->st));
   else HIPCHK(c, launch_philox_uniform(W, m, r, r, 5u, c->p.seed, init_scale, c->st));
-  if (Ht0) HIPCHK(c, launch_copy2d(Ht, r, Ht0, r, n, r, c->st));
-  else HIPCHK(c, launch_philox_uniform(Ht, n, r, r, 6u, c->p.seed, init_scale, c->st));
+  if (Ht0 && Ht0 != Ht) HIPCHK(c, launch_copy2d(Ht, r, Ht0, r, n, r, c->st));
+  else if (!Ht0) HIPCHK(c, launch_philox_uniform(Ht, n, r, r, 6u, c->p.seed, init_scale, c->st));
   HIPCHK(c, launch_fill_f32(c->at<float>(L.scale_w), r, 1.f, c->st));
   HIPCHK(c, halfstep_h(c, 0));   // acc_h = Q_R^T Ht (Hc for the first W half-step)
   c->initialized = true;
+  return NMF_OK;
+}
+
+nmf_status nmf_init_learned(nmf_ctx* c, nmf_mlp* net, const float* align_M, const float* Wh_ref,
+                            const float* W0, const float* Ht_cold, float init_scale, int32_t refine_sweeps,
+                            int64_t* n_rejected) {
+  if (!c) return fail(c, NMF_EINVAL, "null context");
+  if (!net || !Wh_ref) return fail(c, NMF_EINVAL, "null network or Wh_ref");
+  if (refine_sweeps < 0) return fail(c, NMF_EINVAL, "refine_sweeps must be >= 0");
+  if (!c->compressed) return fail(c, NMF_ESTATE, "init needs the sketches: call nmf_compress or nmf_set_state first");
+  int nk, nh, nr;
+  mlp_dims(net, &nk, &nh, &nr);
+  const int k = c->p.k_sketch, r = c->p.r;
+  if (nk != k || nr != r) return fail(c, NMF_EINVAL, "network must map k' inputs to r outputs");
+  Layout& L = c->L;
+  const int64_t n = c->p.n;
+  // 1. network input: x-tilde = M x-hat (rows: Xh M^T), else x-hat itself
+  const float* in = c->at<float>(L.Xh);
+  int64_t ld_in = L.KP;
+  if (align_M) {
+    float* Xa = c->at<float>(L.omL);  // n x k' (the test matrix is not needed after compression)
+    HIPCHK(c, launch_mlp_gemm(0, 1, 0, in, (int)L.KP, align_M, k, Xa, k, (int)n, k, k, nullptr, nullptr, 0, c->st));
+    in = Xa;
+    ld_in = k;
+  }
+  // 2. the network's rows and the cold rows
+  float* Hn = c->at<float>(L.TN);
+  HIPCHK(c, mlp_infer_rows(net, in, ld_in, n, Hn, r, c->st));
+  float* Ht = c->at<float>(L.Ht);
+  if (Ht_cold) HIPCHK(c, launch_copy2d(Ht, r, Ht_cold, r, n, r, c->st));
+  else HIPCHK(c, launch_philox_uniform(Ht, n, r, r, 6u, c->p.seed, init_scale, c->st));
+  // 3. per-row choice by the compressed residual against Wh_ref, in place into Ht
+  int* rej = reinterpret_cast<int*>(Hn + n * r);   // TN is n x KP floats, r < KP
+  long long* cnt = reinterpret_cast<long long*>(c->at<double>(L.res_out));
+  HIPCHK(c, launch_select(c->at<float>(L.Xh), L.KP, (int)n, k, Wh_ref, r, Hn, Ht, Ht, rej, cnt, c->st));
+  // 4. optional column-NNLS sweeps against Wh_ref from the selected rows (each
+  //    sweep lowers every row's compressed residual)
+  if (refine_sweeps > 0)
+    HIPCHK(c, launch_nnls_rows(c->at<float>(L.Xh), L.KP, (int)n, k, Wh_ref, r, refine_sweeps, 1, Ht, r, c->st));
+  // 5. W as in nmf_init; the first update is the W half-step
+  nmf_status s = nmf_init(c, W0, Ht, init_scale);
+  if (s != NMF_OK) return s;
+  if (n_rejected) {
+    long long h = 0;
+    HIPCHK(c, hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    *n_rejected = h;
+  }
   return NMF_OK;
 }
 
@@ -415,20 +465,42 @@ nmf_status nmf_fit(nmf_ctx* c, const float* X, int64_t ldx, int32_t max_iters, d
   int done = 0;
   double e = 0.0;
   nmf_status s;
-  if (max_iters == 0) {
+  // Adaptive schedule: after two checks, step 1.5x the iterations a linear
+  // extrapolation of the last two errors needs to reach eps (5..50); before
+  // that, by the relative gap to eps.
+  int t_prev = -1;
+  double e_prev = 0.0;
+  auto next_chunk = [&](int t, double err) {
+    int ch;
+    const double slope = t_prev >= 0 && t > t_prev ? (e_prev - err) / (t - t_prev) : 0.0;
+    if (t_prev >= 0 && slope > 0) {
+      const double need = std::ceil(1.5 * (err - eps) / slope);
+      ch = need < 5 ? 5 : need > 50 ? 50 : (int)need;
+    } else if (t_prev >= 0) {
+      ch = 50;
+    } else {
+      const double gap = (err - eps) / (eps > 0 ? eps : 1.0);
+      ch = gap > 0.1 ? 50 : gap > 0.01 ? 20 : gap > 0.003 ? 10 : 5;
+    }
+    t_prev = t;
+    e_prev = err;
+    return ch;
+  };
+  int chunk = check_every;
+  if (max_iters == 0 || check_every == 0) {   // the adaptive schedule starts from e at the current factors
     if ((s = nmf_residual(c, X, ldx, &e)) != NMF_OK) return s;
+    if (check_every == 0) {
+      if (e <= eps) max_iters = 0;
+      chunk = next_chunk(0, e);
+    }
   }
-  int chunk = check_every > 0 ? check_every : 50;
   while (done < max_iters) {
     if (chunk > max_iters - done) chunk = max_iters - done;
     if ((s = nmf_step(c, chunk)) != NMF_OK) return s;
     done += chunk;
     if ((s = nmf_residual(c, X, ldx, &e)) != NMF_OK) return s;
     if (e <= eps) break;
-    if (check_every == 0) {   // adaptive: check more often as e approaches eps
-      const double gap = (e - eps) / (eps > 0 ? eps : 1.0);
-      chunk = gap > 0.1 ? 50 : gap > 0.01 ? 20 : 10;
-    }
+    if (check_every == 0) chunk = next_chunk(done, e);
   }
   if (iters_done) *iters_done = done;
   if (rel_err) *rel_err = e;

@@ -57,6 +57,20 @@ _SIGS = {
                               c_i64, c_i64, c_vp, c_sz, c_vp]),
     "nmf_orth_workspace_bytes": (c_sz, [c_i64, c_i32]),
     "nmf_orth": (c_i32, [c_vp, c_i64, c_i64, c_i32, c_vp, c_sz, c_vp, c_i32_p]),
+    "nmf_mlp_n_params": (c_i64, [c_i32, c_i32, c_i32]),
+    "nmf_mlp_workspace_bytes": (c_sz, [c_i32, c_i32, c_i32, c_i32]),
+    "nmf_mlp_create": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_vp, c_vp, c_sz, c_vp, ctypes.POINTER(c_vp)]),
+    "nmf_mlp_destroy": (None, [c_vp]),
+    "nmf_mlp_last_error": (ctypes.c_char_p, [c_vp]),
+    "nmf_mlp_get_params": (c_i32, [c_vp, c_vp]),
+    "nmf_mlp_set_params": (c_i32, [c_vp, c_vp]),
+    "nmf_mlp_loss_grad": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_i64, c_i32, c_dbl_p, c_vp]),
+    "nmf_mlp_train": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_i64, c_i64, c_vp, c_i32, c_i32, ctypes.c_float,
+                              c_dbl_p]),
+    "nmf_mlp_infer": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_vp, c_i64]),
+    "nmf_nnls_rows": (c_i32, [c_vp, c_i64, c_i64, c_i32, c_vp, c_i32, c_i32, c_i32, c_vp, c_i64, c_vp]),
+    "nmf_init_learned": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_float, c_i32,
+                                 ctypes.POINTER(c_i64)]),
 }
 
 _lib = None
@@ -192,12 +206,35 @@ class NMF:
         self._c(load().nmf_get_state(self.h, _ptr(QL), _ptr(QR), _ptr(Xh), _ptr(Xc)))
         return QL, QR, Xh, Xc
 
+    def left_basis(self, out=None):
+        """Q_L (m x k') of the last compression, copied to a device tensor."""
+        if out is None:
+            out = torch.empty(self.m, self.kp, dtype=torch.float32, device=self.ws.device)
+        _f32(out, (self.m, self.kp), "QL")
+        self._c(load().nmf_get_state(self.h, _ptr(out), None, None, None))
+        return out
+
     def set_state(self, QL, QR, Xh, Xc):
         _f32(QL, (self.m, self.kp), "QL")
         _f32(QR, (self.n, self.kp), "QR")
         _f32(Xh, (self.n, self.kp), "Xh")
         _f32(Xc, (self.m, self.kp), "Xc")
         self._c(load().nmf_set_state(self.h, _ptr(QL), _ptr(QR), _ptr(Xh), _ptr(Xc)))
+
+    def init_learned(self, net, Wh_ref, align_M=None, W0=None, Ht_cold=None, init_scale=1.0, refine_sweeps=0,
+                     count=True):
+        """Warm start of H from `net` (an Mlp) with per-row rejection against
+        Wh_ref (k' x r); returns the number of cold rows kept (None if count
+        is False, in which case the call does not synchronise)."""
+        _f32(Wh_ref, (self.kp, self.r), "Wh_ref")
+        _f32(align_M, (self.kp, self.kp), "align_M")
+        _f32(W0, (self.m, self.r), "W0")
+        _f32(Ht_cold, (self.n, self.r), "Ht_cold")
+        nrej = ctypes.c_int64(-1)
+        self._c(load().nmf_init_learned(self.h, net.h, _ptr(align_M), _ptr(Wh_ref), _ptr(W0), _ptr(Ht_cold),
+                                        float(init_scale), int(refine_sweeps),
+                                        ctypes.byref(nrej) if count else None))
+        return nrej.value if count else None
 
     def sync(self):
         s = c_i32()
@@ -280,3 +317,105 @@ def gemm_lowp(prec, A, K, B, E=None, ea=(0, 0), stream=None):
     _check(lib.nmf_gemm_lowp(prec, _ptr(A), A.stride(0), _ptr(E), ea[0], ea[1], _ptr(B), B.stride(0), K, N,
                              _ptr(C), C.stride(0), M, Kpad, base, nb, _stream(stream)))
     return C
+
+
+def mlp_n_params(k_in, hidden, r_out):
+    return int(load().nmf_mlp_n_params(k_in, hidden, r_out))
+
+
+class Mlp:
+    """Warm-start network k_in -> hidden -> hidden -> r_out over a torch-allocated
+    workspace; parameters are one flat float32 device vector (W1, b1, W2, b2,
+    W3, b3, weights [fan_in][fan_out])."""
+
+    def __init__(self, k_in, hidden, r_out, params, max_batch=4096, device="cuda", stream=None):
+        lib = load()
+        self.k, self.hdim, self.r, self.max_batch = k_in, hidden, r_out, max_batch
+        self.np = mlp_n_params(k_in, hidden, r_out)
+        _f32(params, (self.np,), "params")
+        nbytes = lib.nmf_mlp_workspace_bytes(k_in, hidden, r_out, max_batch)
+        if nbytes == 0:
+            raise ValueError("invalid MLP sizes")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        self._wsptr = (self.ws.data_ptr() + 255) // 256 * 256
+        self.stream = stream
+        h = c_vp()
+        st = lib.nmf_mlp_create(k_in, hidden, r_out, max_batch, _ptr(params), self._wsptr, nbytes,
+                                _stream(stream), ctypes.byref(h))
+        if st != 0:
+            msg = lib.nmf_mlp_last_error(None)
+            raise NmfError(st, msg.decode() if msg else "")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().nmf_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _c(self, status):
+        if status != 0:
+            msg = load().nmf_mlp_last_error(self.h)
+            raise NmfError(status, msg.decode() if msg else "")
+
+    def params(self):
+        out = torch.empty(self.np, dtype=torch.float32, device=self.ws.device)
+        self._c(load().nmf_mlp_get_params(self.h, _ptr(out)))
+        return out
+
+    def set_params(self, flat):
+        _f32(flat, (self.np,), "params")
+        self._c(load().nmf_mlp_set_params(self.h, _ptr(flat)))
+
+    def loss_grad(self, X, T):
+        B = X.shape[0]
+        if X.shape[1] != self.k or T.shape != (B, self.r):
+            raise ValueError("shape mismatch")
+        g = torch.empty(self.np, dtype=torch.float32, device=self.ws.device)
+        L = ctypes.c_double()
+        self._c(load().nmf_mlp_loss_grad(self.h, _ptr(X), X.stride(0), _ptr(T), T.stride(0), B,
+                                         ctypes.byref(L), _ptr(g)))
+        return L.value, g
+
+    def train(self, X, T, epochs, batch, lr, order=None, report=True):
+        """Adam passes over the pairs (X rows, T rows); order: int32 device
+        tensor (epochs x npairs) of per-pass permutations or None.  Returns the
+        mean batch loss per pass (None if report is False: asynchronous)."""
+        npairs = X.shape[0]
+        if X.shape[1] != self.k or T.shape != (npairs, self.r):
+            raise ValueError("shape mismatch")
+        if order is not None and (order.dtype != torch.int32 or order.numel() != epochs * npairs
+                                  or not order.is_contiguous()):
+            raise ValueError("order: contiguous int32, epochs x npairs")
+        hist = (ctypes.c_double * max(epochs, 1))()
+        self._c(load().nmf_mlp_train(self.h, _ptr(X), X.stride(0), _ptr(T), T.stride(0), npairs, _ptr(order),
+                                     int(epochs), int(batch), float(lr), hist if report else None))
+        return list(hist)[:epochs] if report else None
+
+    def infer(self, X, out=None):
+        rows = X.shape[0]
+        if out is None:
+            out = torch.empty(rows, self.r, dtype=torch.float32, device=X.device)
+        self._c(load().nmf_mlp_infer(self.h, _ptr(X), X.stride(0), rows, _ptr(out), out.stride(0)))
+        return out
+
+
+def nnls_rows(Xr, Wh, sweeps, out=None, warm=False, stream=None):
+    """Rows h = argmin_{h>=0} ||x - Wh h|| by `sweeps` H sweeps from h = 0, or
+    from the rows already in `out` when warm."""
+    rows, k = Xr.shape
+    k2, r = Wh.shape
+    if k2 != k or not Wh.is_contiguous():
+        raise ValueError("Wh: contiguous k x r")
+    if out is None:
+        if warm:
+            raise ValueError("warm start needs the starting rows in out")
+        out = torch.empty(rows, r, dtype=torch.float32, device=Xr.device)
+    _check(load().nmf_nnls_rows(_ptr(Xr), Xr.stride(0), rows, k, _ptr(Wh), r, int(sweeps), int(bool(warm)),
+                                _ptr(out), out.stride(0), _stream(stream)))
+    return out

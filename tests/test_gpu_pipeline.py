@@ -162,6 +162,14 @@ def test_fit_and_errors(lib):
     ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
     it2, e2 = ctx.fit(Xd, max_iters=200, eps=1.05 * ref["e"], check_every=5)
     assert it2 < 200 and e2 <= 1.05 * ref["e"]
+    # adaptive schedule: e at the current factors first, so a start that
+    # already meets eps runs no iteration; otherwise it stops at eps
+    e_now = ctx.residual(Xd)
+    it3, e3 = ctx.fit(Xd, max_iters=200, eps=2.0 * e_now, check_every=0)
+    assert it3 == 0 and e3 == e_now
+    ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
+    it4, e4 = ctx.fit(Xd, max_iters=200, eps=1.05 * ref["e"], check_every=0)
+    assert 0 < it4 < 200 and e4 <= 1.05 * ref["e"]
     # validation of X
     ctx.validate(Xd)
     bad = Xd.clone()

@@ -458,3 +458,18 @@ def test_warm_selection_never_worse_than_cold():
     assert np.all(rs <= np.sum((Xh - Hc @ Wh.T) ** 2, 1))
     assert np.all(rs <= np.sum((Xh - Hn @ Wh.T) ** 2, 1) + 0 * rej)
     assert 0 < rej.sum() < 50
+
+
+def test_column_nnls_matches_active_set_nnls():
+    """The training targets (column NNLS by repeated H sweeps) converge to the
+    unique non-negative least-squares solution (Lawson-Hanson active set)."""
+    from scipy.optimize import nnls
+    g = np.random.default_rng(9)
+    Wh = g.random((12, 5))
+    H_true = np.maximum(g.standard_normal((40, 5)), 0)
+    Xr = H_true @ Wh.T + 0.05 * g.standard_normal((40, 12))
+    Ht = nmf.column_nnls(Xr, Wh, sweeps=3000)
+    for j in range(40):
+        ref, _ = nnls(Wh, Xr[j])
+        assert np.allclose(Ht[j], ref, atol=1e-9)
+    assert np.all(Ht >= 0)
