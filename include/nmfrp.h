@@ -253,8 +253,9 @@ nmf_status nmf_mlp_infer(nmf_mlp* net, const float* in_rows, int64_t ld_in, int6
 /* Training targets: for every row x of Xr (rows x k, ldx) the non-negative
  * least-squares row h = argmin_{h >= 0} ||x - Wh h||^2, Wh k x r (row-major),
  * approximated by `sweeps` H sweeps of eq fastHALS_a with Wh fixed, from h = 0
- * (warm_start = 0) or from the rows already in Ht (warm_start = 1).  r <= 64,
- * (k r + r^2) 4 bytes <= 64 KiB.  Ht: rows x r (ldh).  Asynchronous. */
+ * (warm_start = 0) or from the rows already in Ht (warm_start = 1).  r <= 64
+ * and (k + R + 1) R 4 bytes <= 64 KiB with R = 16, 32 or 64, the smallest
+ * that holds r.  Ht: rows x r (ldh).  Asynchronous. */
 nmf_status nmf_nnls_rows(const float* Xr, int64_t ldx, int64_t rows, int32_t k, const float* Wh,
                          int32_t r, int32_t sweeps, int32_t warm_start, float* Ht, int64_t ldh,
                          void* hip_stream);

@@ -125,6 +125,7 @@ hipError_t launch_mlp_gemm(int at, int bt, int epi, const float* A, int lda, con
                            int ldaux, hipStream_t st);
 hipError_t launch_scale_rows(const float* X, int64_t ldx, const int* idx, int64_t nsrc, int Bn, int k,
                              const float* T, int64_t ldt, int r, float* Xs, float* Ts, float* nrm, hipStream_t st);
+size_t nnls_rows_lds_bytes(int k, int r);
 hipError_t launch_nnls_rows(const float* Xr, int64_t ldx, int n, int k, const float* Wh, int r, int sweeps,
                             int warm, float* H, int64_t ldh, hipStream_t st);
 hipError_t launch_loss_grad(const float* Z3, const float* Ts, int Bn, int r, float* dZ3, double* lpart,

@@ -46,10 +46,11 @@ gemm_f32_kernel(const float* __restrict__ A, int64_t lda, const float* __restric
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
-  f32x4 ra[A_V4], rb[B_V4];
+  // two K steps in flight in registers (R0, R1) while the LDS tile is consumed
+  f32x4 ra0[A_V4], rb0[B_V4], ra1[A_V4], rb1[B_V4];
   const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
 
-  auto load_tile = [&](int64_t k0) {
+  auto load_tile = [&](f32x4* ra, f32x4* rb, int64_t k0) {
 #pragma unroll
     for (int p = 0; p < A_V4; ++p) {
       const int f = tid + 256 * p;
@@ -81,7 +82,7 @@ gemm_f32_kernel(const float* __restrict__ A, int64_t lda, const float* __restric
       rb[p] = v;
     }
   };
-  auto store_tile = [&]() {
+  auto store_tile = [&](const f32x4* ra, const f32x4* rb) {
 #pragma unroll
     for (int p = 0; p < A_V4; ++p) {
       const int f = tid + 256 * p;
@@ -102,45 +103,59 @@ gemm_f32_kernel(const float* __restrict__ A, int64_t lda, const float* __restric
   };
 
   const int half = lane >> 5, l32 = lane & 31;
-  if (kbeg < kend) {
-    load_tile(kbeg);
-    store_tile();
-    __syncthreads();
-    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-      const bool more = k0 + BK < kend;
-      if (more) load_tile(k0 + BK);
+  auto compute = [&]() {
 #pragma unroll
-      for (int g = 0; g < BK / 8; ++g) {
-        const int kb = 8 * g + 4 * half;
-        f32x4 af[TM], bf[TN];
+    for (int g = 0; g < BK / 8; ++g) {
+      const int kb = 8 * g + 4 * half;
+      f32x4 af[TM], bf[TN];
 #pragma unroll
-        for (int a = 0; a < TM; ++a) {
-          const int il = wm * (BM / WM) + a * 32 + l32;
-          if (!AT) {
-            af[a] = *(const f32x4*)(As + il * AROW + kb);
-          } else {
+      for (int a = 0; a < TM; ++a) {
+        const int il = wm * (BM / WM) + a * 32 + l32;
+        if (!AT) {
+          af[a] = *(const f32x4*)(As + il * AROW + kb);
+        } else {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) af[a][s] = As[(kb + s) * AROW + il];
-          }
+          for (int s = 0; s < 4; ++s) af[a][s] = As[(kb + s) * AROW + il];
         }
-#pragma unroll
-        for (int b = 0; b < TN; ++b) {
-          const int jl = wn * (BN / WN) + b * 32 + l32;
-#pragma unroll
-          for (int s = 0; s < 4; ++s) bf[b][s] = Bs[(kb + s) * BROW + jl];
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-          for (int a = 0; a < TM; ++a)
-#pragma unroll
-            for (int b = 0; b < TN; ++b)
-              acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a][s], bf[b][s], acc[a][b], 0, 0, 0);
       }
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        const int jl = wn * (BN / WN) + b * 32 + l32;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) bf[b][s] = Bs[(kb + s) * BROW + jl];
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+          for (int b = 0; b < TN; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a][s], bf[b][s], acc[a][b], 0, 0, 0);
+    }
+  };
+  // steps t = 0 .. T-1 at k = kbeg + t BK; the LDS tile holds step t while
+  // steps t + 1 and t + 2 load into the register sets
+  const int64_t T = kend > kbeg ? ceil_div(kend - kbeg, (int64_t)BK) : 0;
+  if (T > 0) {
+    load_tile(ra0, rb0, kbeg);
+    if (T > 1) load_tile(ra1, rb1, kbeg + BK);
+    store_tile(ra0, rb0);
+    __syncthreads();
+    if (T > 2) load_tile(ra0, rb0, kbeg + 2 * BK);
+    for (int64_t t = 0; t < T; t += 2) {
+      compute();   // LDS: step t; R1: step t + 1; R0: step t + 2
       __syncthreads();
-      if (more) {
-        store_tile();
+      if (t + 1 < T) {
+        store_tile(ra1, rb1);
         __syncthreads();
+        if (t + 3 < T) load_tile(ra1, rb1, kbeg + (t + 3) * BK);
+        compute();   // LDS: step t + 1; R0: step t + 2; R1: step t + 3
+        __syncthreads();
+        if (t + 2 < T) {
+          store_tile(ra0, rb0);
+          __syncthreads();
+          if (t + 4 < T) load_tile(ra0, rb0, kbeg + (t + 4) * BK);
+        }
       }
     }
   }

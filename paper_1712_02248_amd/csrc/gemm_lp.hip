@@ -39,9 +39,10 @@ gemm_bf16_nt_kernel(const uint16_t* __restrict__ A, int64_t lda, const uint16_t*
     for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int x = 0; x < 16; ++x) acc[a][b][x] = 0.f;
-  i32x4 ra[AV], rb[BV];
+  // two K steps in flight in registers (R0, R1) while the LDS tile is consumed
+  i32x4 ra0[AV], rb0[BV], ra1[AV], rb1[BV];
   const i32x4 z4 = {0, 0, 0, 0};
-  auto load = [&](int64_t k0) {
+  auto load = [&](i32x4* ra, i32x4* rb, int64_t k0) {
 #pragma unroll
     for (int p = 0; p < AV; ++p) {
       const int f = tid + 256 * p, row = f / (BK / 8), c8 = f % (BK / 8);
@@ -55,7 +56,7 @@ gemm_bf16_nt_kernel(const uint16_t* __restrict__ A, int64_t lda, const uint16_t*
       rb[p] = gj < N ? *(const i32x4*)(Bt + gj * ldbt + k0 + 8 * c8) : z4;
     }
   };
-  auto store = [&]() {
+  auto store = [&](const i32x4* ra, const i32x4* rb) {
 #pragma unroll
     for (int p = 0; p < AV; ++p) {
       const int f = tid + 256 * p, row = f / (BK / 8), c8 = f % (BK / 8);
@@ -68,36 +69,52 @@ gemm_bf16_nt_kernel(const uint16_t* __restrict__ A, int64_t lda, const uint16_t*
     }
   };
   const int half = lane >> 5, l32 = lane & 31;
-  if (kbeg < kend) {
-    load(kbeg);
-    store();
-    __syncthreads();
-    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-      const bool more = k0 + BK < kend;
-      if (more) load(k0 + BK);
+  auto compute = [&]() {
 #pragma unroll
-      for (int ks = 0; ks < BK / 16; ++ks) {
-        bf16x8 af[TM], bf[TN];
+    for (int ks = 0; ks < BK / 16; ++ks) {
+      bf16x8 af[TM], bf[TN];
 #pragma unroll
-        for (int a = 0; a < TM; ++a) {
-          const int il = wm * (BM / WM) + a * 32 + l32;
-          af[a] = *(const bf16x8*)(As + il * ROW + ks * 16 + 8 * half);
-        }
-#pragma unroll
-        for (int b = 0; b < TN; ++b) {
-          const int jl = wn * (BN / WN) + b * 32 + l32;
-          bf[b] = *(const bf16x8*)(Bs + jl * ROW + ks * 16 + 8 * half);
-        }
-#pragma unroll
-        for (int a = 0; a < TM; ++a)
-#pragma unroll
-          for (int b = 0; b < TN; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
+      for (int a = 0; a < TM; ++a) {
+        const int il = wm * (BM / WM) + a * 32 + l32;
+        af[a] = *(const bf16x8*)(As + il * ROW + ks * 16 + 8 * half);
       }
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        const int jl = wn * (BN / WN) + b * 32 + l32;
+        bf[b] = *(const bf16x8*)(Bs + jl * ROW + ks * 16 + 8 * half);
+      }
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+  };
+  // steps t = 0 .. T-1 at k = kbeg + t BK; the LDS tile holds step t while
+  // steps t + 1 and t + 2 load into the register sets
+  const int64_t T = kend > kbeg ? (kend - kbeg) / BK : 0;
+  if (T > 0) {
+    load(ra0, rb0, kbeg);
+    if (T > 1) load(ra1, rb1, kbeg + BK);
+    store(ra0, rb0);
+    __syncthreads();
+    if (T > 2) load(ra0, rb0, kbeg + 2 * BK);
+    for (int64_t t = 0; t < T; t += 2) {
+      // LDS: step t; R1: step t + 1; R0: step t + 2
+      compute();
       __syncthreads();
-      if (more) {
-        store();
+      if (t + 1 < T) {
+        store(ra1, rb1);
         __syncthreads();
+        if (t + 3 < T) load(ra1, rb1, kbeg + (t + 3) * BK);
+        // LDS: step t + 1; R0: step t + 2; R1: step t + 3
+        compute();
+        __syncthreads();
+        if (t + 2 < T) {
+          store(ra0, rb0);
+          __syncthreads();
+          if (t + 4 < T) load(ra0, rb0, kbeg + (t + 4) * BK);
+        }
       }
     }
   }

@@ -113,59 +113,98 @@ scale_rows_kernel(const float* __restrict__ X, int64_t ldx, const int* __restric
   if (lane == 0) nrm[row] = (float)nv;
 }
 
+NMF_DEV float quad_bcast_f(float v, int src) {
+  const int x = __builtin_bit_cast(int, v);
+  int y;
+  switch (src) {   // folds to one DPP move once src is a constant
+    case 0: y = __builtin_amdgcn_mov_dpp(x, 0x00, 0xF, 0xF, false); break;
+    case 1: y = __builtin_amdgcn_mov_dpp(x, 0x55, 0xF, 0xF, false); break;
+    case 2: y = __builtin_amdgcn_mov_dpp(x, 0xAA, 0xF, 0xF, false); break;
+    default: y = __builtin_amdgcn_mov_dpp(x, 0xFF, 0xF, 0xF, false); break;
+  }
+  return __builtin_bit_cast(float, y);
+}
+
 // Column NNLS min_{h >= 0} ||x - Wh h||^2 for every row x of Xr (n x k), by
 // repeated H sweeps of eq fastHALS_a with Wh fixed, starting from h = 0 (or
 // from the rows already in H when warm):
-//   h_j <- [h_j + (p_j - (G h)_j) / G_jj]_+ ,  p = Wh^T x,  G = Wh^T Wh.
-// One thread per row; Wh and G in LDS (every lane reads the same entry).
+//   h_j <- [h_j + (p_j - (G h)_j) / G_jj]_+ ,  p = Wh^T x,  G = Wh^T Wh,
+// j ascending (Gauss-Seidel); components with G_jj = 0 stay unchanged.
+// A quad of lanes per row; lane q owns components q RQ .. q RQ + RQ - 1 of h
+// and p.  (G h)_j is evaluated afresh for every j: each lane sums its own
+// components, and the four partial sums are added in the same order in every
+// lane.  Wh, G and 1/G_jj are staged in LDS, zero padded to RMAX columns.
+// 64 rows per 256-thread block.
 template <int RMAX>
 __global__ void __launch_bounds__(256)
 nnls_rows_kernel(const float* __restrict__ Xr, int64_t ldx, int n, int k, const float* __restrict__ Wh, int r,
                  int sweeps, int warm, float* __restrict__ H, int64_t ldh) {
+  constexpr int RQ = RMAX / 4;
   extern __shared__ float sm[];
-  float* whs = sm;              // k x r
-  float* gs = sm + k * r;       // r x r
-  for (int e = threadIdx.x; e < k * r; e += 256) whs[e] = Wh[e];
-  __syncthreads();
-  for (int e = threadIdx.x; e < r * r; e += 256) {
-    const int a = e / r, b = e % r;
-    double s = 0.0;
-    for (int c = 0; c < k; ++c) s += (double)whs[c * r + a] * whs[c * r + b];
-    gs[e] = (float)s;
+  float* whs = sm;                      // k x RMAX
+  float* gs = sm + k * RMAX;            // RMAX x RMAX
+  float* rd = gs + RMAX * RMAX;         // RMAX
+  for (int e = threadIdx.x; e < k * RMAX; e += 256) {
+    const int c = e / RMAX, j = e % RMAX;
+    whs[e] = j < r ? Wh[(int64_t)c * r + j] : 0.f;
   }
   __syncthreads();
-  const int row = blockIdx.x * 256 + threadIdx.x;
-  if (row >= n) return;
-  float p[RMAX], h[RMAX];
+  for (int e = threadIdx.x; e < RMAX * RMAX; e += 256) {
+    const int a = e / RMAX, b = e % RMAX;
+    double s = 0.0;
+    for (int c = 0; c < k; ++c) s += (double)whs[c * RMAX + a] * whs[c * RMAX + b];
+    gs[e] = (float)s;
+    if (a == b) rd[a] = s > 0.0 ? (float)(1.0 / s) : 0.f;
+  }
+  __syncthreads();
+  const int q = threadIdx.x & 3;
+  const int row = blockIdx.x * 64 + (threadIdx.x >> 2);
+  const bool valid = row < n;
+  const int c0 = q * RQ;
+  float f[RQ], p[RQ];
 #pragma unroll
-  for (int j = 0; j < RMAX; ++j) {
-    p[j] = 0.f;
-    h[j] = (warm && j < r) ? H[(int64_t)row * ldh + j] : 0.f;
+  for (int t = 0; t < RQ; ++t) {
+    f[t] = (warm && valid && c0 + t < r) ? H[(int64_t)row * ldh + c0 + t] : 0.f;
+    p[t] = 0.f;
   }
   for (int c = 0; c < k; ++c) {
-    const float x = Xr[(int64_t)row * ldx + c];
+    const float x = valid ? Xr[(int64_t)row * ldx + c] : 0.f;
 #pragma unroll
-    for (int j = 0; j < RMAX; ++j)
-      if (j < r) p[j] = fmaf(x, whs[c * r + j], p[j]);
+    for (int t = 0; t < RQ; t += 4) {
+      const f32x4 w = *(const f32x4*)(whs + c * RMAX + c0 + t);
+      p[t] = fmaf(x, w[0], p[t]);
+      p[t + 1] = fmaf(x, w[1], p[t + 1]);
+      p[t + 2] = fmaf(x, w[2], p[t + 2]);
+      p[t + 3] = fmaf(x, w[3], p[t + 3]);
+    }
   }
   for (int it = 0; it < sweeps; ++it) {
 #pragma unroll
     for (int j = 0; j < RMAX; ++j) {
-      if (j < r) {
-        const float gjj = gs[j * r + j];
-        if (gjj > 0.f) {
-          float g = p[j];
+      const float rdj = rd[j];
+      if (rdj > 0.f) {                  // uniform over the block
+        float s = 0.f;
 #pragma unroll
-          for (int l = 0; l < RMAX; ++l)
-            if (l < r) g = fmaf(-gs[j * r + l], h[l], g);
-          h[j] = fmaxf(h[j] + g / gjj, 0.f);
+        for (int t = 0; t < RQ; t += 4) {
+          const f32x4 gv = *(const f32x4*)(gs + j * RMAX + c0 + t);
+          s = fmaf(gv[0], f[t], s);
+          s = fmaf(gv[1], f[t + 1], s);
+          s = fmaf(gv[2], f[t + 2], s);
+          s = fmaf(gv[3], f[t + 3], s);
+        }
+        const float gh = (quad_bcast_f(s, 0) + quad_bcast_f(s, 1)) + (quad_bcast_f(s, 2) + quad_bcast_f(s, 3));
+        if (q == j / RQ) {
+          const int t = j % RQ;
+          f[t] = fmaxf(fmaf(p[t] - gh, rdj, f[t]), 0.f);
         }
       }
     }
   }
+  if (valid) {
 #pragma unroll
-  for (int j = 0; j < RMAX; ++j)
-    if (j < r) H[(int64_t)row * ldh + j] = h[j];
+    for (int t = 0; t < RQ; ++t)
+      if (c0 + t < r) H[(int64_t)row * ldh + c0 + t] = f[t];
+  }
 }
 
 NMF_DEV float softplusf(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
@@ -329,11 +368,16 @@ hipError_t launch_scale_rows(const float* X, int64_t ldx, const int* idx, int64_
   return hipGetLastError();
 }
 
+size_t nnls_rows_lds_bytes(int k, int r) {
+  const int rmax = r <= 16 ? 16 : r <= 32 ? 32 : 64;
+  return (size_t)(k * rmax + rmax * rmax + rmax) * sizeof(float);
+}
+
 hipError_t launch_nnls_rows(const float* Xr, int64_t ldx, int n, int k, const float* Wh, int r, int sweeps,
                             int warm, float* H, int64_t ldh, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  const size_t lds = (size_t)(k * r + r * r) * sizeof(float);
-  const dim3 grid((unsigned)ceil_div(n, 256));
+  const size_t lds = nnls_rows_lds_bytes(k, r);
+  const dim3 grid((unsigned)ceil_div(n, 64));
   if (r <= 16)
     hipLaunchKernelGGL(nnls_rows_kernel<16>, grid, dim3(256), lds, st, Xr, ldx, n, k, Wh, r, sweeps, warm, H, ldh);
   else if (r <= 32)

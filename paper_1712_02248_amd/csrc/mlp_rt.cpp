@@ -293,7 +293,7 @@ nmf_status nmf_nnls_rows(const float* Xr, int64_t ldx, int64_t rows, int32_t k, 
   if (rows < 0 || k < 1 || r < 1 || sweeps < 0) return mfail(nullptr, NMF_EINVAL, "bad sizes");
   if (warm_start != 0 && warm_start != 1) return mfail(nullptr, NMF_EINVAL, "warm_start must be 0 or 1");
   if (r > 64) return mfail(nullptr, NMF_EINVAL, "r > 64 is not supported by this build");
-  if ((size_t)(k * r + r * r) * sizeof(float) > 64 * 1024) return mfail(nullptr, NMF_EINVAL, "k r + r^2 too large");
+  if (k > 1024 || nnls_rows_lds_bytes(k, r) > 64 * 1024) return mfail(nullptr, NMF_EINVAL, "k too large for r");
   if (rows > INT32_MAX) return mfail(nullptr, NMF_EINVAL, "too many rows");
   if (rows == 0) return NMF_OK;
   if (!Xr || !Wh || !Ht) return mfail(nullptr, NMF_EINVAL, "null pointer");

@@ -80,6 +80,65 @@ quant_bf16_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n
   }
 }
 
+// BF16 copy and transposed copy over 128 x 128 tiles (n % 4 == 0, ldx % 4 == 0,
+// X 16-byte aligned).  Each thread converts two rows x four columns per pass
+// (float4 loads, 8-byte stores of Xq); the pairs are packed into 32-bit LDS
+// words of the transposed tile, which is written out as 8-byte runs of XqT.
+constexpr int QV = 128;
+__global__ void __launch_bounds__(256)
+quant_bf16_v4_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
+                     uint16_t* __restrict__ Xq, int64_t ldq, uint16_t* __restrict__ XqT, int64_t ldqt) {
+  __shared__ uint32_t T[QV][QV / 2 + 1];          // T[j][i/2] = (bf16 x[i][j], bf16 x[i+1][j])
+  const int64_t i0 = (int64_t)blockIdx.y * QV, j0 = (int64_t)blockIdx.x * QV;
+  const int l = threadIdx.x & 31, rp = threadIdx.x >> 5;
+  const int64_t gj = j0 + 4 * l;
+  const bool colok = gj < n;                       // n % 4 == 0: all four columns or none
+  f32x4 v[16];
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t gi = i0 + 2 * (rp + 8 * p) + h;
+      f32x4 z = {0.f, 0.f, 0.f, 0.f};
+      v[2 * p + h] = (colok && gi < m) ? *(const f32x4*)(X + gi * ldx + gj) : z;
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 8; ++p) {
+    const int ip = rp + 8 * p;                      // row pair within the tile
+    uint16_t b[2][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int d = 0; d < 4; ++d) b[h][d] = bf16_rne(v[2 * p + h][d]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t gi = i0 + 2 * ip + h;
+      if (gi < m && gj < ldq) {
+        uint2 w;
+        w.x = (uint32_t)b[h][0] | ((uint32_t)b[h][1] << 16);
+        w.y = (uint32_t)b[h][2] | ((uint32_t)b[h][3] << 16);
+        *(uint2*)(Xq + gi * ldq + gj) = w;
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < 4; ++d) T[4 * l + d][ip] = (uint32_t)b[0][d] | ((uint32_t)b[1][d] << 16);
+  }
+  __syncthreads();
+  // XqT row j0 + jj, columns i0 + 4 l .. i0 + 4 l + 3
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int jj = rp + 8 * p;
+    const int64_t gjt = j0 + jj, gi = i0 + 4 * l;
+    if (gjt < n && gi < ldqt) {
+      uint2 w;
+      w.x = T[jj][2 * l];
+      w.y = T[jj][2 * l + 1];
+      *(uint2*)(XqT + gjt * ldqt + gi) = w;
+    }
+  }
+}
+
 // Per-tile power-of-two exponents of X (128 x 128 tiles): one workgroup per tile.
 __global__ void __launch_bounds__(256)
 tile_exp_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n, int* __restrict__ E,
@@ -213,8 +272,15 @@ unsigned grid1(int64_t total) {
 
 hipError_t launch_quant_bf16(const float* X, int64_t ldx, int64_t m, int64_t n, uint16_t* Xq,
                              int64_t ldq, uint16_t* XqT, int64_t ldqt, hipStream_t st) {
-  dim3 grid((unsigned)ceil_div(ldq, QT), (unsigned)ceil_div(ldqt, QT));
-  hipLaunchKernelGGL(quant_bf16_kernel, grid, dim3(256), 0, st, X, ldx, m, n, Xq, ldq, XqT, ldqt);
+  const bool vec = n % 4 == 0 && ldx % 4 == 0 && ((uintptr_t)X & 15) == 0 && ((uintptr_t)Xq & 7) == 0 &&
+                   ((uintptr_t)XqT & 7) == 0 && ldq % QV == 0 && ldqt % QV == 0;
+  if (vec) {
+    dim3 grid((unsigned)(ldq / QV), (unsigned)(ldqt / QV));
+    hipLaunchKernelGGL(quant_bf16_v4_kernel, grid, dim3(256), 0, st, X, ldx, m, n, Xq, ldq, XqT, ldqt);
+  } else {
+    dim3 grid((unsigned)ceil_div(ldq, QT), (unsigned)ceil_div(ldqt, QT));
+    hipLaunchKernelGGL(quant_bf16_kernel, grid, dim3(256), 0, st, X, ldx, m, n, Xq, ldq, XqT, ldqt);
+  }
   return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ def _x(m, n, seed, spread=True):
     return X.astype(np.float32)
 
 
-@pytest.mark.parametrize("m,n", [(300, 200), (128, 128), (1000, 36), (64, 1100)])
+@pytest.mark.parametrize("m,n", [(300, 200), (128, 128), (1000, 36), (64, 1100), (77, 130), (2, 4)])
 def test_quantize_bf16_bit_exact(lib, m, n):
     print(f"quant bf16 {m}x{n}", flush=True)
     X = _x(m, n, m + n)
