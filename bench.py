@@ -63,6 +63,8 @@ def parse():
                     help="column-NNLS sweeps on the warm rows against the reference dictionary")
     ap.add_argument("--headline-only", action="store_true", help="time only plain and bf16_warm")
     ap.add_argument("--variants", default="", help="comma list of variants to time (default: all)")
+    ap.add_argument("--probe-kernels", action="store_true",
+                    help="only a copy of known size and the dominant kernel (for counter runs)")
     return ap.parse_args()
 
 
@@ -257,6 +259,108 @@ def time_variant(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, prec, refine,
                 ctx=ctx)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_bf16_c2_traffic.md")
+DOMINANT_SRC = os.path.join(ROOT, "paper_1712_02248_amd", "csrc", "gemm_lp.hip")
+
+
+def source_digest(path):
+    import hashlib
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when it is missing or was taken on a different source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source sha256/16") != source_digest(DOMINANT_SRC):
+        return None
+    try:
+        return float(vals["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def kernel_timing(torch, nmfrp, Xd, m, n, kp, reps):
+    """Per-launch times of the compression products at the workload's shapes.
+    The dominant kernel of the BF16 path, the BF16 product, is timed alone on
+    prepared operands (X B and X^T B alternating, as the range finder issues
+    them); the FP32 products are timed per library call (product plus split-K
+    sum)."""
+    dev = Xd.device
+    B_n = torch.randn(n, kp, device=dev)
+    B_m = torch.randn(m, kp, device=dev)
+    Y_m = torch.empty(m, kp, device=dev)
+    Y_n = torch.empty(n, kp, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, count):
+        fn()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            fn()
+        ev1.record(stream)
+        ev1.synchronize()
+        return ev0.elapsed_time(ev1) / (reps * count)
+
+    flops = 2.0 * m * n * kp
+    res = {}
+    for label, fn in (("fp32 X*B (call)", lambda: nmfrp.gemm(Xd, B_n, False, Y_m)),
+                      ("fp32 X^T*B (call)", lambda: nmfrp.gemm(Xd, B_m, True, Y_n))):
+        ms = timed(fn, 1)
+        res[label] = dict(ms=round(ms, 5), tflops=round(flops / (ms * 1e-3) / 1e12, 2),
+                          frac_fp32_mfma=round(flops / (ms * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4),
+                          x_gbs=round(4.0 * m * n / (ms * 1e-3) / 1e9, 1))
+    Xq, XqT, _ = nmfrp.quantize_x(Xd, nmfrp.NMF_BF16)
+    P1 = nmfrp.LowpProduct(nmfrp.NMF_BF16, Xq, n, B_n)
+    P2 = nmfrp.LowpProduct(nmfrp.NMF_BF16, XqT, m, B_m)
+    alg = 2.0 * m * n                     # bytes of X per launch (BF16)
+    for label, fn, cnt in (("bf16 X*B (kernel)", P1.run, 1), ("bf16 X^T*B (kernel)", P2.run, 1),
+                           ("bf16 both (kernel)", lambda: (P1.run(), P2.run()), 2)):
+        ms = timed(fn, cnt)
+        res[label] = dict(ms=round(ms, 5), tflops=round(flops / (ms * 1e-3) / 1e12, 2),
+                          x_gbs=round(alg / (ms * 1e-3) / 1e9, 1))
+        log(f"[bench] {label}: {ms:.4f} ms  {res[label]['tflops']:.1f} TFLOP/s  X at {res[label]['x_gbs']} GB/s")
+    dom = res["bf16 both (kernel)"]
+    achieved = alg / (dom["ms"] * 1e-3) / 1e9
+    traffic = measured_traffic()
+    res["roofline"] = dict(
+        bound="hbm", kernel="gemm_bf16_nt_kernel<128,64,2,2> (BF16 range-finder product; X B and X^T B "
+                            "alternating, split-K partials)",
+        achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s", frac=round(achieved / PEAK_HBM_GBS, 4),
+        traffic=traffic, algorithmic_bytes_per_launch=alg, units_per_launch=f"{m}x{n} X elements, 2 B each",
+        launch_us=round(dom["ms"] * 1e3, 2), splits=[P1.splits, P2.splits],
+        mfma_tflops=dom["tflops"], mfma_frac_bf16=round(dom["tflops"] / 2500.0, 4))
+    return res
+
+
+def probe_kernels(torch, nmfrp, Xd, m, n, kp, reps):
+    """For hardware-counter runs: a plain copy of known size, then the dominant
+    kernel at the workload's shapes (reps launches of each shape)."""
+    src = torch.empty(m * n, dtype=torch.float32, device=Xd.device).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    B_n = torch.randn(n, kp, device=Xd.device)
+    B_m = torch.randn(m, kp, device=Xd.device)
+    Xq, XqT, _ = nmfrp.quantize_x(Xd, nmfrp.NMF_BF16)
+    P1 = nmfrp.LowpProduct(nmfrp.NMF_BF16, Xq, n, B_n)
+    P2 = nmfrp.LowpProduct(nmfrp.NMF_BF16, XqT, m, B_m)
+    for _ in range(reps):
+        P1.run()
+        P2.run()
+    torch.cuda.synchronize()
+    print(json.dumps(dict(probe="kernels", copy_bytes=4 * m * n, bf16_x_bytes=2 * m * n,
+                          splits=[P1.splits, P2.splits], M=[m, n], N=kp, reps=reps,
+                          source_sha256_16=source_digest(DOMINANT_SRC))), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -280,6 +384,11 @@ def main():
     seed = datagen.cfg_seed(name)
 
     golden = json.load(open(GOLDEN)).get(name) if os.path.exists(GOLDEN) else None
+    if args.probe_kernels:   # counters do not depend on the values of X
+        g = torch.Generator(device="cuda:0")
+        g.manual_seed(seed)
+        probe_kernels(torch, nmfrp, torch.rand(m, n, device="cuda:0", generator=g), m, n, kp, 5)
+        return
     log(f"[bench] generating {name} X {m}x{n} on the host")
     X = datagen.make_x(name)
     W0, H0 = datagen.init_factors(X.mean(), m, n, r, seed)
@@ -332,37 +441,9 @@ def main():
     total_head = sum(head["times"])
 
     # ---- kernel timing at the exact shapes of the compression, HIP events on the
-    # stream the kernels are launched on.
-    B_n = torch.randn(n, kp, device=dev)
-    B_m = torch.randn(m, kp, device=dev)
-    Y_m = torch.empty(m, kp, device=dev)
-    Y_n = torch.empty(n, kp, device=dev)
-    Xq, XqT, _ = nmfrp.quantize_x(Xd, nmfrp.NMF_BF16)
-    stream = torch.cuda.current_stream()
-    ldq, ldqt = Xq.shape[1], XqT.shape[1]
-    kern = (("fp32 X*B", lambda: nmfrp.gemm(Xd, B_n, False, Y_m), 4.0 * m * n),
-            ("fp32 X^T*B", lambda: nmfrp.gemm(Xd, B_m, True, Y_n), 4.0 * m * n),
-            ("bf16 X*B", lambda: nmfrp.gemm_lowp(nmfrp.NMF_BF16, Xq, n, B_n), 2.0 * m * ldq),
-            ("bf16 X^T*B", lambda: nmfrp.gemm_lowp(nmfrp.NMF_BF16, XqT, m, B_m), 2.0 * n * ldqt))
-    res = {}
-    for label, fn, xbytes in kern:
-        fn()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
-        for _ in range(args.kernel_reps):
-            fn()
-        ev1.record(stream)
-        ev1.synchronize()
-        ms = ev0.elapsed_time(ev1) / args.kernel_reps
-        flops = 2.0 * m * n * kp
-        res[label] = dict(ms=round(ms, 5), tflops=round(flops / (ms * 1e-3) / 1e12, 2),
-                          x_read_gbs=round(xbytes / (ms * 1e-3) / 1e9, 1))
-        log(f"[bench] {label}: {ms:.4f} ms  {res[label]['tflops']:.1f} TFLOP/s  X at {res[label]['x_read_gbs']} GB/s")
-    dom = res["fp32 X*B"]
-    roofline = dict(bound="mfma", kernel="gemm_f32_kernel<128,64,2,2,false> (X*B, FP32 MFMA)",
-                    achieved=dom["tflops"], peak=PEAK_FP32_MFMA_TFLOPS, unit="TFLOP/s",
-                    frac=round(dom["tflops"] / PEAK_FP32_MFMA_TFLOPS, 4), traffic=None,
-                    algorithmic_flops_per_launch=2.0 * m * n * kp, launch_ms=dom["ms"])
+    # stream the kernels are launched on (the current torch stream).
+    kt = kernel_timing(torch, nmfrp, Xd, m, n, kp, args.kernel_reps)
+    roofline = kt.pop("roofline")
 
     def summary(v):
         st = v["stages"]
@@ -396,7 +477,7 @@ def main():
         speedup_vs_plain=round(pmed / vmed, 3) if plain else None,
         variants={k: summary(v) for k, v in out.items()},
         warm_start=warm_info,
-        gemm=res,
+        gemm=kt,
         update_loop=dict(algorithmic_bytes_per_iteration=upd_bytes, per_iteration_ms=round(per_iter_ms, 4),
                          gbs=round(upd_bytes / (per_iter_ms * 1e-3) / 1e9, 1)),
         roofline=roofline,

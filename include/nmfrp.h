@@ -185,6 +185,21 @@ nmf_status nmf_gemm_lowp(int32_t prec, const void* A, int64_t lda, const int32_t
                          int64_t ldc, int64_t M, int64_t Kpad, void* workspace, size_t ws_bytes,
                          void* hip_stream);
 
+/* The same product in parts, for callers that keep the thin operand prepared
+ * (and for timing the product kernel alone).  nmf_lowp_prepare_thin rounds B
+ * (K x N FP32, ldb) to the format and transposes it into Bt (N x Kpad, zero
+ * padded; FP8 also writes the Kpad/128 block exponents EB).
+ * nmf_gemm_lowp_splits gives the split-K count nmf_gemm_lowp uses.
+ * nmf_gemm_lowp_prepared launches only the product kernel: with splits == 1 it
+ * writes C (M x N, ldc); with splits > 1 it writes partial z (M x N, leading
+ * dimension N) at C + z M N, which the caller sums.  Asynchronous. */
+nmf_status nmf_lowp_prepare_thin(int32_t prec, const float* B, int64_t ldb, int64_t K, int64_t N, void* Bt,
+                                 int64_t Kpad, int32_t* EB, void* hip_stream);
+int32_t nmf_gemm_lowp_splits(int64_t M, int64_t N, int64_t Kpad);
+nmf_status nmf_gemm_lowp_prepared(int32_t prec, const void* A, int64_t lda, const int32_t* EA, int64_t ea_i,
+                                  int64_t ea_k, const void* Bt, const int32_t* EB, int64_t N, float* C,
+                                  int64_t ldc, int64_t M, int64_t Kpad, int32_t splits, void* hip_stream);
+
 /* In-place orthonormalisation of Y (rows x k, ldy % 4 == 0) by FP64
  * CholeskyQR2 (shifted CholeskyQR3 on breakdown), k <= 128.  Synchronising;
  * *shifted (may be NULL) = 1 if the shifted fallback ran. */

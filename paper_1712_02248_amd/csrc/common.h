@@ -55,12 +55,12 @@ hipError_t launch_prep_b_fp8(const float* B, int64_t ldb, int64_t K, int64_t N, 
 int gemm_lp_pick_splits(int64_t M, int64_t N, int64_t Kpad, int bm);
 hipError_t launch_gemm_bf16_nt(const uint16_t* A, int64_t lda, const uint16_t* Bt, int64_t ldbt,
                                float* C, int64_t ldc, int64_t M, int64_t N, int64_t Kpad, int splits,
-                               float* part, hipStream_t st);
+                               float* part, hipStream_t st, bool reduce = true);
 // EA: exponent of A's 128 x 128 tile (ti, tk) at EA[ti * ea_i + tk * ea_k]; EB per 128-row block.
 hipError_t launch_gemm_fp8_nt(const uint8_t* A, int64_t lda, const int* EA, int64_t ea_i, int64_t ea_k,
                               const uint8_t* Bt, int64_t ldbt, const int* EB, float* C, int64_t ldc,
                               int64_t M, int64_t N, int64_t Kpad, int splits, float* part,
-                              hipStream_t st);
+                              hipStream_t st, bool reduce = true);
 
 // Tall-skinny QR pieces (qr.hip).
 // G = Y^T Y in FP64: split partials, then the deterministic sum into G (k x k).

@@ -20,7 +20,7 @@ template <int BM, int BN, int WM, int WN>
 __global__ void __launch_bounds__(256)
 gemm_bf16_nt_kernel(const uint16_t* __restrict__ A, int64_t lda, const uint16_t* __restrict__ Bt,
                     int64_t ldbt, float* __restrict__ C, int64_t ldc, int64_t M, int64_t N,
-                    int64_t Kpad, int64_t kchunk) {
+                    int64_t Kpad, int64_t kchunk, int rot_xcd) {
   constexpr int BK = 64, ROW = BK + 8;                    // u16 per LDS row
   constexpr int TM = BM / WM / 32, TN = BN / WN / 32;
   constexpr int AV = BM * BK / 8 / 256, BV = BN * BK / 8 / 256;   // 16-byte loads per thread
@@ -93,12 +93,21 @@ gemm_bf16_nt_kernel(const uint16_t* __restrict__ A, int64_t lda, const uint16_t*
   // steps t = 0 .. T-1 at k = kbeg + t BK; the LDS tile holds step t while
   // steps t + 1 and t + 2 load into the register sets
   const int64_t T = kend > kbeg ? (kend - kbeg) / BK : 0;
+  // Rotated K order, which spreads concurrent loads of A over the HBM channels.
+  // rot_xcd = 0: every workgroup starts at its own step.  rot_xcd = 1 (thin
+  // operand too large to stay in L2 under arbitrary order): the workgroups of
+  // one XCD (dispatch ids are dealt round-robin over the 8 XCDs) share a start
+  // step and so read the thin operand in step from their L2, and the 8 XCDs
+  // start 1/8 of the range apart.
+  const int64_t wg = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+  const int64_t rot = T == 0 ? 0 : rot_xcd ? ((wg % 8) * T) / 8 : (int64_t)blockIdx.x % T;
+  auto kstep = [&](int64_t s) { return kbeg + ((s + rot) % T) * BK; };
   if (T > 0) {
-    load(ra0, rb0, kbeg);
-    if (T > 1) load(ra1, rb1, kbeg + BK);
+    load(ra0, rb0, kstep(0));
+    if (T > 1) load(ra1, rb1, kstep(1));
     store(ra0, rb0);
     __syncthreads();
-    if (T > 2) load(ra0, rb0, kbeg + 2 * BK);
+    if (T > 2) load(ra0, rb0, kstep(2));
     for (int64_t t = 0; t < T; t += 2) {
       // LDS: step t; R1: step t + 1; R0: step t + 2
       compute();
@@ -106,14 +115,14 @@ gemm_bf16_nt_kernel(const uint16_t* __restrict__ A, int64_t lda, const uint16_t*
       if (t + 1 < T) {
         store(ra1, rb1);
         __syncthreads();
-        if (t + 3 < T) load(ra1, rb1, kbeg + (t + 3) * BK);
+        if (t + 3 < T) load(ra1, rb1, kstep(t + 3));
         // LDS: step t + 1; R0: step t + 2; R1: step t + 3
         compute();
         __syncthreads();
         if (t + 2 < T) {
           store(ra0, rb0);
           __syncthreads();
-          if (t + 4 < T) load(ra0, rb0, kbeg + (t + 4) * BK);
+          if (t + 4 < T) load(ra0, rb0, kstep(t + 4));
         }
       }
     }
@@ -140,7 +149,7 @@ __global__ void __launch_bounds__(256)
 gemm_fp8_nt_kernel(const uint8_t* __restrict__ A, int64_t lda, const int* __restrict__ EA,
                    int64_t ea_i, int64_t ea_k, const uint8_t* __restrict__ Bt, int64_t ldbt,
                    const int* __restrict__ EB, float* __restrict__ C, int64_t ldc, int64_t M,
-                   int64_t N, int64_t Kpad, int64_t kchunk) {
+                   int64_t N, int64_t Kpad, int64_t kchunk, int rot_xcd) {
   constexpr int BM = 128, BK = 128, ROW = BK + 16;         // bytes per LDS row
   constexpr int WM = 4 / WN;
   constexpr int TM = BM / WM / 16, TN = BN / WN / 16;      // 16x16 tiles per wave
@@ -188,13 +197,19 @@ gemm_fp8_nt_kernel(const uint8_t* __restrict__ A, int64_t lda, const int* __rest
   };
   const int g4 = lane >> 4, l16 = lane & 15;
   const int64_t ti = i0 / 128;
-  if (kbeg < kend) {
-    load(kbeg);
+  // rotated K-step order, as in the BF16 kernel
+  const int64_t T = kend > kbeg ? (kend - kbeg) / BK : 0;
+  const int64_t wg = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+  const int64_t rot = T == 0 ? 0 : rot_xcd ? ((wg % 8) * T) / 8 : (int64_t)blockIdx.x % T;
+  auto kstep = [&](int64_t s) { return kbeg + ((s + rot) % T) * BK; };
+  if (T > 0) {
+    load(kstep(0));
     store();
     __syncthreads();
-    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-      const bool more = k0 + BK < kend;
-      if (more) load(k0 + BK);
+    for (int64_t t = 0; t < T; ++t) {
+      const int64_t k0 = kstep(t);
+      const bool more = t + 1 < T;
+      if (more) load(kstep(t + 1));
       const int64_t kb = k0 / 128;
       const int sa = 127 + EA[ti * ea_i + kb * ea_k];
       const int sb = 127 + EB[kb];
@@ -255,6 +270,12 @@ splitk_reduce_lp(const float* __restrict__ part, int splits, float* __restrict__
 
 int bn_lp(int64_t N) { return N <= 32 ? 32 : N <= 64 ? 64 : N <= 128 ? 128 : 256; }
 
+// Per-XCD rotation when the thin-operand slices the grid streams (splits
+// slices of N x kchunk elements) exceed a quarter of one XCD's 4 MiB L2.
+int rot_per_xcd(int64_t N, int64_t kchunk, int splits, int elem_bytes) {
+  return (double)N * kchunk * elem_bytes * splits > 1024.0 * 1024.0 ? 1 : 0;
+}
+
 hipError_t finish(float* part, int splits, float* C, int64_t ldc, int64_t M, int64_t N, hipStream_t st) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || splits == 1) return e;
@@ -279,7 +300,7 @@ int gemm_lp_pick_splits(int64_t M, int64_t N, int64_t Kpad, int bm) {
 
 hipError_t launch_gemm_bf16_nt(const uint16_t* A, int64_t lda, const uint16_t* Bt, int64_t ldbt,
                                float* C, int64_t ldc, int64_t M, int64_t N, int64_t Kpad, int splits,
-                               float* part, hipStream_t st) {
+                               float* part, hipStream_t st, bool reduce) {
   if (M == 0 || N == 0) return hipSuccess;
   if (N > 256 || Kpad % 64 || lda % 8 || ldbt % 8) return hipErrorInvalidValue;
   float* out = splits > 1 ? part : C;
@@ -288,19 +309,21 @@ hipError_t launch_gemm_bf16_nt(const uint16_t* A, int64_t lda, const uint16_t* B
   const int bn = bn_lp(N);
   const int bm = bn <= 128 ? 128 : 64;
   dim3 grid((unsigned)ceil_div(M, bm), (unsigned)ceil_div(N, bn), (unsigned)splits);
+  const int rx = rot_per_xcd(N, kchunk, splits, 2);
   switch (bn) {
-    case 32: hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 32, 4, 1>), grid, dim3(256), 0, st, A, lda, Bt, ldbt, out, ldo, M, N, Kpad, kchunk); break;
-    case 64: hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 64, 2, 2>), grid, dim3(256), 0, st, A, lda, Bt, ldbt, out, ldo, M, N, Kpad, kchunk); break;
-    case 128: hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 128, 2, 2>), grid, dim3(256), 0, st, A, lda, Bt, ldbt, out, ldo, M, N, Kpad, kchunk); break;
-    default: hipLaunchKernelGGL((gemm_bf16_nt_kernel<64, 256, 1, 4>), grid, dim3(256), 0, st, A, lda, Bt, ldbt, out, ldo, M, N, Kpad, kchunk); break;
+    case 32: hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 32, 4, 1>), grid, dim3(256), 0, st, A, lda, Bt, ldbt, out, ldo, M, N, Kpad, kchunk, rx); break;
+    case 64: hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 64, 2, 2>), grid, dim3(256), 0, st, A, lda, Bt, ldbt, out, ldo, M, N, Kpad, kchunk, rx); break;
+    case 128: hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 128, 2, 2>), grid, dim3(256), 0, st, A, lda, Bt, ldbt, out, ldo, M, N, Kpad, kchunk, rx); break;
+    default: hipLaunchKernelGGL((gemm_bf16_nt_kernel<64, 256, 1, 4>), grid, dim3(256), 0, st, A, lda, Bt, ldbt, out, ldo, M, N, Kpad, kchunk, rx); break;
   }
+  if (!reduce) return hipGetLastError();
   return finish(part, splits, C, ldc, M, N, st);
 }
 
 hipError_t launch_gemm_fp8_nt(const uint8_t* A, int64_t lda, const int* EA, int64_t ea_i, int64_t ea_k,
                               const uint8_t* Bt, int64_t ldbt, const int* EB, float* C, int64_t ldc,
                               int64_t M, int64_t N, int64_t Kpad, int splits, float* part,
-                              hipStream_t st) {
+                              hipStream_t st, bool reduce) {
   if (M == 0 || N == 0) return hipSuccess;
   if (N > 256 || Kpad % 128 || lda % 16 || ldbt % 16) return hipErrorInvalidValue;
   float* out = splits > 1 ? part : C;
@@ -308,11 +331,13 @@ hipError_t launch_gemm_fp8_nt(const uint8_t* A, int64_t lda, const int* EA, int6
   const int64_t kchunk = round_up(ceil_div(Kpad, splits), 128);
   const int bn = bn_lp(N);
   dim3 grid((unsigned)ceil_div(M, 128), (unsigned)ceil_div(N, bn), (unsigned)splits);
+  const int rx = rot_per_xcd(N, kchunk, splits, 1);
   switch (bn) {
-    case 32: hipLaunchKernelGGL((gemm_fp8_nt_kernel<32, 1>), grid, dim3(256), 0, st, A, lda, EA, ea_i, ea_k, Bt, ldbt, EB, out, ldo, M, N, Kpad, kchunk); break;
-    case 64: hipLaunchKernelGGL((gemm_fp8_nt_kernel<64, 2>), grid, dim3(256), 0, st, A, lda, EA, ea_i, ea_k, Bt, ldbt, EB, out, ldo, M, N, Kpad, kchunk); break;
-    case 128: hipLaunchKernelGGL((gemm_fp8_nt_kernel<128, 2>), grid, dim3(256), 0, st, A, lda, EA, ea_i, ea_k, Bt, ldbt, EB, out, ldo, M, N, Kpad, kchunk); break;
-    default: hipLaunchKernelGGL((gemm_fp8_nt_kernel<256, 4>), grid, dim3(256), 0, st, A, lda, EA, ea_i, ea_k, Bt, ldbt, EB, out, ldo, M, N, Kpad, kchunk); break;
+    case 32: hipLaunchKernelGGL((gemm_fp8_nt_kernel<32, 1>), grid, dim3(256), 0, st, A, lda, EA, ea_i, ea_k, Bt, ldbt, EB, out, ldo, M, N, Kpad, kchunk, rx); break;
+    case 64: hipLaunchKernelGGL((gemm_fp8_nt_kernel<64, 2>), grid, dim3(256), 0, st, A, lda, EA, ea_i, ea_k, Bt, ldbt, EB, out, ldo, M, N, Kpad, kchunk, rx); break;
+    case 128: hipLaunchKernelGGL((gemm_fp8_nt_kernel<128, 2>), grid, dim3(256), 0, st, A, lda, EA, ea_i, ea_k, Bt, ldbt, EB, out, ldo, M, N, Kpad, kchunk, rx); break;
+    default: hipLaunchKernelGGL((gemm_fp8_nt_kernel<256, 4>), grid, dim3(256), 0, st, A, lda, EA, ea_i, ea_k, Bt, ldbt, EB, out, ldo, M, N, Kpad, kchunk, rx); break;
   }
+  if (!reduce) return hipGetLastError();
   return finish(part, splits, C, ldc, M, N, st);
 }

@@ -650,6 +650,44 @@ nmf_status nmf_gemm_lowp(int32_t prec, const void* A, int64_t lda, const int32_t
   return e ? fail(nullptr, NMF_EHIP, hipGetErrorString(e)) : NMF_OK;
 }
 
+nmf_status nmf_lowp_prepare_thin(int32_t prec, const float* B, int64_t ldb, int64_t K, int64_t N, void* Bt,
+                                 int64_t Kpad, int32_t* EB, void* hs) {
+  if (N <= 0 || N > 256 || K <= 0 || Kpad < K || Kpad % 128 || ldb < N) return fail(nullptr, NMF_EINVAL, "bad arguments");
+  if (!B || !Bt || (prec == NMF_FP8_E4M3 && !EB)) return fail(nullptr, NMF_EINVAL, "null pointer");
+  hipError_t e;
+  if (prec == NMF_BF16) e = launch_prep_b_bf16(B, ldb, K, N, (uint16_t*)Bt, Kpad, (hipStream_t)hs);
+  else if (prec == NMF_FP8_E4M3) e = launch_prep_b_fp8(B, ldb, K, N, EB, (uint8_t*)Bt, Kpad, (hipStream_t)hs);
+  else return fail(nullptr, NMF_EINVAL, "prec must be BF16 or FP8_E4M3");
+  return e ? fail(nullptr, NMF_EHIP, hipGetErrorString(e)) : NMF_OK;
+}
+
+int32_t nmf_gemm_lowp_splits(int64_t M, int64_t N, int64_t Kpad) {
+  if (M <= 0 || N <= 0 || Kpad <= 0) return 1;
+  return gemm_lp_pick_splits(M, N, Kpad, 128);
+}
+
+nmf_status nmf_gemm_lowp_prepared(int32_t prec, const void* A, int64_t lda, const int32_t* EA, int64_t ea_i,
+                                  int64_t ea_k, const void* Bt, const int32_t* EB, int64_t N, float* C,
+                                  int64_t ldc, int64_t M, int64_t Kpad, int32_t splits, void* hs) {
+  if (M < 0 || N <= 0 || N > 256 || Kpad <= 0 || Kpad % 128 || lda < Kpad || splits < 1 || splits > 64 ||
+      (splits == 1 && ldc < N))
+    return fail(nullptr, NMF_EINVAL, "bad arguments");
+  if (M == 0) return NMF_OK;
+  if (!A || !Bt || !C || (prec == NMF_FP8_E4M3 && (!EA || !EB))) return fail(nullptr, NMF_EINVAL, "null pointer");
+  hipStream_t st = (hipStream_t)hs;
+  hipError_t e;
+  // splits > 1: the kernel writes partial z at C + z M N (leading dimension N)
+  if (prec == NMF_BF16)
+    e = launch_gemm_bf16_nt((const uint16_t*)A, lda, (const uint16_t*)Bt, Kpad, C, ldc, M, N, Kpad, splits, C, st,
+                            false);
+  else if (prec == NMF_FP8_E4M3)
+    e = launch_gemm_fp8_nt((const uint8_t*)A, lda, EA, ea_i, ea_k, (const uint8_t*)Bt, Kpad, EB, C, ldc, M, N, Kpad,
+                           splits, C, st, false);
+  else
+    return fail(nullptr, NMF_EINVAL, "prec must be BF16 or FP8_E4M3");
+  return e ? fail(nullptr, NMF_EHIP, hipGetErrorString(e)) : NMF_OK;
+}
+
 size_t nmf_orth_workspace_bytes(int64_t rows, int32_t k) {
   const int s = gram_pick_splits(rows, k);
   return ((size_t)s * k * k + 2 * (size_t)k * k) * sizeof(double) + 8 * sizeof(int) + 512;

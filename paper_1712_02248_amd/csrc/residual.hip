@@ -2,7 +2,8 @@
 // evaluated directly (never through the Gram expansion, which cancels
 // catastrophically at small e) with FP64 products and FP64 accumulation.
 //
-// A workgroup owns 64 rows of X and walks all 64-column tiles.  Each wave
+// A workgroup owns 64 rows of X and walks all 64-column tiles, starting at
+// tile (workgroup index mod tile count).  Each wave
 // computes a 16 x 64 block of W diag(sw) Ht^T on v_mfma_f64_16x16x4_f64
 // (D[i][j] in lane j + 16 (i % 4), register i / 4), subtracts X, and
 // accumulates squares.  Workgroup partials are summed in fixed order by the
@@ -60,9 +61,13 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
         xv[sub][q] = (gi < m && gj < n) ? X[gi * ldx + gj] : 0.f;
       }
   };
+  // workgroups start at different column tiles (rotated order) so that
+  // concurrent loads of X spread over the HBM channels
+  const int64_t rot = (int64_t)blockIdx.x % ntile;
+  auto col0 = [&](int64_t t) { return ((t + rot) % ntile) * CT; };
   double res = 0.0, xx = 0.0;
-  load_h(0);
-  load_x(0);
+  load_h(col0(0));
+  load_x(col0(0));
   for (int64_t t = 0; t < ntile; ++t) {
     __syncthreads();   // readers of the previous Hs are done
 #pragma unroll
@@ -77,8 +82,8 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
 #pragma unroll
       for (int q = 0; q < 4; ++q) xc[sub][q] = xv[sub][q];
     if (t + 1 < ntile) {
-      load_h((t + 1) * CT);
-      load_x((t + 1) * CT);
+      load_h(col0(t + 1));
+      load_x(col0(t + 1));
     }
     f64x4 d[4];
 #pragma unroll

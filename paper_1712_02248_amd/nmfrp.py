@@ -55,6 +55,10 @@ _SIGS = {
     "nmf_gemm_lowp_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64]),
     "nmf_gemm_lowp": (c_i32, [c_i32, c_vp, c_i64, c_vp, c_i64, c_i64, c_vp, c_i64, c_i64, c_i64, c_vp, c_i64,
                               c_i64, c_i64, c_vp, c_sz, c_vp]),
+    "nmf_lowp_prepare_thin": (c_i32, [c_i32, c_vp, c_i64, c_i64, c_i64, c_vp, c_i64, c_vp, c_vp]),
+    "nmf_gemm_lowp_splits": (c_i32, [c_i64, c_i64, c_i64]),
+    "nmf_gemm_lowp_prepared": (c_i32, [c_i32, c_vp, c_i64, c_vp, c_i64, c_i64, c_vp, c_vp, c_i64, c_vp, c_i64,
+                                       c_i64, c_i64, c_i32, c_vp]),
     "nmf_orth_workspace_bytes": (c_sz, [c_i64, c_i32]),
     "nmf_orth": (c_i32, [c_vp, c_i64, c_i64, c_i32, c_vp, c_sz, c_vp, c_i32_p]),
     "nmf_mlp_n_params": (c_i64, [c_i32, c_i32, c_i32]),
@@ -419,3 +423,30 @@ def nnls_rows(Xr, Wh, sweeps, out=None, warm=False, stream=None):
     _check(load().nmf_nnls_rows(_ptr(Xr), Xr.stride(0), rows, k, _ptr(Wh), r, int(sweeps), int(bool(warm)),
                                 _ptr(out), out.stride(0), _stream(stream)))
     return out
+
+
+class LowpProduct:
+    """C = A[:, :K] @ B with the thin operand B (K x N) prepared once; A is a
+    low-precision copy from quantize_x.  run() launches only the product kernel
+    (split-K partials, if any, land in self.part and are summed by result())."""
+
+    def __init__(self, prec, A, K, B, E=None, ea=(0, 0), stream=None):
+        lib = load()
+        self.prec, self.A, self.E, self.ea, self.stream = prec, A, E, ea, stream
+        self.M, self.Kpad = A.shape
+        self.N = B.shape[1]
+        dt = torch.int16 if prec == NMF_BF16 else torch.uint8
+        self.Bt = torch.zeros(self.N, self.Kpad, dtype=dt, device=A.device)
+        self.EB = torch.zeros(max(self.Kpad // 128, 1), dtype=torch.int32, device=A.device)
+        _check(lib.nmf_lowp_prepare_thin(prec, _ptr(B), B.stride(0), K, self.N, _ptr(self.Bt), self.Kpad,
+                                         _ptr(self.EB), _stream(stream)))
+        self.splits = int(lib.nmf_gemm_lowp_splits(self.M, self.N, self.Kpad))
+        self.part = torch.empty(self.splits, self.M, self.N, dtype=torch.float32, device=A.device)
+
+    def run(self):
+        _check(load().nmf_gemm_lowp_prepared(self.prec, _ptr(self.A), self.A.stride(0), _ptr(self.E), self.ea[0],
+                                             self.ea[1], _ptr(self.Bt), _ptr(self.EB), self.N, _ptr(self.part),
+                                             self.N, self.M, self.Kpad, self.splits, _stream(self.stream)))
+
+    def result(self):
+        return self.part.sum(dim=0) if self.splits > 1 else self.part[0]

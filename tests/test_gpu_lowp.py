@@ -78,6 +78,31 @@ def test_lowp_products(lib, fmt, m, n, k, side):
     assert np.all(np.abs(C - ref) <= bound)
 
 
+@pytest.mark.parametrize("fmt,m,n,k,side", [("bf16", 1000, 300, 64, 0), ("bf16", 4096, 512, 64, 1),
+                                            ("fp8", 1000, 300, 64, 0), ("fp8", 4096, 512, 32, 1)])
+def test_prepared_product_matches_full_product(lib, fmt, m, n, k, side):
+    """The product kernel on a prepared thin operand, with its split-K partials
+    summed in the library's order (z ascending, FP32), is bit-identical to the
+    one-call product."""
+    print(f"prepared lowp {fmt} {m}x{n} k={k} side={side}", flush=True)
+    X = _x(m, n, 7 * m + n, spread=False)
+    prec = lib.NMF_BF16 if fmt == "bf16" else lib.NMF_FP8_E4M3
+    Xq, XqT, E = lib.quantize_x(torch.from_numpy(X).cuda(), prec)
+    K = m if side else n
+    B = torch.from_numpy(np.random.default_rng(k + side).standard_normal((K, k)).astype(np.float32)).cuda()
+    tn = -(-n // 128)
+    A = XqT if side else Xq
+    ea = (1, tn) if side else (tn, 1)
+    full = lib.gemm_lowp(prec, A, K, B, E, ea).cpu().numpy()
+    pp = lib.LowpProduct(prec, A, K, B, E, ea)
+    pp.run()
+    parts = pp.part.cpu().numpy()
+    acc = np.zeros_like(parts[0])
+    for z in range(parts.shape[0]):
+        acc = (acc + parts[z]).astype(np.float32)
+    assert np.array_equal(acc, full)
+
+
 @pytest.mark.parametrize("fmt,refine", [("bf16", 0), ("bf16", 1), ("fp8", 0), ("fp8", 1)])
 def test_lowp_compression_runs(lib, fmt, refine):
     """Whole run with low-precision range-finder products: the error after the
