@@ -107,6 +107,14 @@ nmf_status nmf_step(nmf_ctx* ctx, int32_t iters);
 /* Exact e = ||X - W Ht^T||_F / ||X||_F in FP64 (eq 2.2).  Synchronising. */
 nmf_status nmf_residual(nmf_ctx* ctx, const float* X, int64_t ldx, double* rel_err);
 
+/* Sketch-only estimate of e from the left sketch (Sec 3: X ~ Q_L Q_L^T X):
+ *   e_p^2 = (||X||^2 - ||Xh||^2 + sum_j ||xh_j - Wh h_j||^2) / ||X||^2,
+ * with Wh = Q_L^T W of the last H sweep; equal to e when the columns of W lie
+ * in range(Q_L), otherwise an approximation (no pass over X).  Needs at least
+ * one nmf_step since the last init and ||X||^2 from an exact nmf_residual or
+ * nmf_fit since the last compression (NMF_ESTATE otherwise).  Synchronising. */
+nmf_status nmf_proxy_residual(nmf_ctx* ctx, double* rel_err);
+
 /* Runs steps in chunks, evaluating the exact residual after each chunk, until
  * e <= eps or max_iters iterations (the paper leaves the stopping rule open:
  * Alg 1-4).  check_every > 0: fixed chunk; check_every == 0: e is evaluated

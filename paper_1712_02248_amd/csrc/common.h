@@ -106,6 +106,9 @@ hipError_t launch_sum_partials_f64(const double* part, int nparts, int64_t ne, d
 
 // Residual (residual.hip): sum (X - W diag(sw) Ht^T)^2 and sum X^2 in FP64.
 int residual_blocks(int64_t m, int64_t n);
+int proxy_blocks(int64_t n);
+hipError_t launch_proxy(const float* Xh, int64_t ldx, const float* Ht, int r, const float* Wh, int kp, int64_t n,
+                        double* part, hipStream_t st);
 hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t n, const float* W,
                            const float* sw, const float* Ht, int r, double* part, double* out,
                            unsigned* counter, hipStream_t st);

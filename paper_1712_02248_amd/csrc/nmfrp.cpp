@@ -30,7 +30,7 @@ struct Layout {
   size_t omL, omR, QL, TM, Xc, QR, TN, Xh, W, Ht;
   size_t gemm_part, gram_part, G, R, qr_status;
   size_t hs_part, acc_w, acc_h, counters, Hc, GH, Wh, GW, scale_w;
-  size_t res_part, res_out, flags;
+  size_t res_part, res_out, flags, proxy_part, proxy_out;
   int64_t ldq, ldqt;                 // low-precision copies of X: m x ldq and n x ldqt
   size_t Xq, XqT, Ex, Bt, Eb;
   size_t total;
@@ -102,6 +102,8 @@ Layout make_layout(const nmf_params* p) {
   L.res_part = pl.take(2 * (size_t)residual_blocks(m, n) * d);
   L.res_out = pl.take(2 * d);
   L.flags = pl.take(8 * sizeof(int));
+  L.proxy_part = pl.take(2 * 256 * d);
+  L.proxy_out = pl.take(2 * d);
   L.Xq = L.XqT = L.Ex = L.Bt = L.Eb = 0;
   if (p->prec != NMF_FP32) {
     const size_t es = p->prec == NMF_BF16 ? 2 : 1;
@@ -124,7 +126,8 @@ struct nmf_ctx {
   Layout L;
   char* ws;
   hipStream_t st;
-  bool compressed = false, initialized = false;
+  bool compressed = false, initialized = false, stepped = false;
+  double normX2 = -1.0;   // ||X||^2 from the last exact residual on this compression
   std::string err;
   hipEvent_t ev[6];
   bool have_ev = false;
@@ -357,6 +360,8 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
   HIPCHK(c, hipEventRecord(c->ev[1], st));
   c->t_compress = true;
   c->compressed = true;
+  c->stepped = false;
+  c->normX2 = -1.0;
   return NMF_OK;
 }
 
@@ -374,6 +379,7 @@ nmf_status nmf_init(nmf_ctx* c, const float* W0, const float* Ht0, float init_sc
   HIPCHK(c, launch_fill_f32(c->at<float>(L.scale_w), r, 1.f, c->st));
   HIPCHK(c, halfstep_h(c, 0));   // acc_h = Q_R^T Ht (Hc for the first W half-step)
   c->initialized = true;
+  c->stepped = false;
   return NMF_OK;
 }
 
@@ -435,6 +441,7 @@ nmf_status nmf_step(nmf_ctx* c, int32_t iters) {
   }
   HIPCHK(c, hipEventRecord(c->ev[3], c->st));
   c->t_step = true;
+  if (iters > 0) c->stepped = true;
   return NMF_OK;
 }
 
@@ -456,6 +463,25 @@ nmf_status nmf_residual(nmf_ctx* c, const float* X, int64_t ldx, double* rel_err
   if (qs[1]) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
   *rel_err = (h[1] > 0) ? std::sqrt(h[0] / h[1]) : 0.0;
   if (!std::isfinite(h[0]) || !std::isfinite(h[1])) return fail(c, NMF_ENONFINITE, "non-finite residual");
+  c->normX2 = h[1];
+  return NMF_OK;
+}
+
+nmf_status nmf_proxy_residual(nmf_ctx* c, double* rel_err) {
+  if (!c || !rel_err) return fail(c, NMF_EINVAL, "bad arguments");
+  if (!c->stepped) return fail(c, NMF_ESTATE, "the proxy needs at least one nmf_step after init");
+  if (!(c->normX2 > 0)) return fail(c, NMF_ESTATE, "the proxy needs ||X||^2 from an exact residual on this compression");
+  Layout& L = c->L;
+  const int nb = proxy_blocks(c->p.n);
+  HIPCHK(c, launch_proxy(c->at<float>(L.Xh), L.KP, c->at<float>(L.Ht), c->p.r, c->at<float>(L.Wh), c->p.k_sketch,
+                         c->p.n, c->at<double>(L.proxy_part), c->st));
+  HIPCHK(c, launch_sum_partials_f64(c->at<double>(L.proxy_part), nb, 2, c->at<double>(L.proxy_out), nullptr, c->st));
+  double h[2];
+  HIPCHK(c, hipMemcpyAsync(h, c->at<double>(L.proxy_out), sizeof(h), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  const double e2 = (c->normX2 - h[1] + h[0]) / c->normX2;
+  if (!std::isfinite(e2)) return fail(c, NMF_ENONFINITE, "non-finite proxy");
+  *rel_err = std::sqrt(e2 > 0 ? e2 : 0.0);
   return NMF_OK;
 }
 
@@ -540,6 +566,8 @@ nmf_status nmf_set_state(nmf_ctx* c, const float* QL, const float* QR, const flo
   HIPCHK(c, launch_copy2d(c->at<float>(L.Xc), L.KP, Xc, k, c->p.m, k, c->st));
   HIPCHK(c, launch_fill_i32(c->at<int>(L.qr_status), 8, 0, c->st));
   c->compressed = true;
+  c->stepped = false;
+  c->normX2 = -1.0;
   c->initialized = false;
   return NMF_OK;
 }

@@ -152,6 +152,47 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
   }
 }
 
+
+// Sketch-only proxy of the residual (Sec 3: Q_L Q_L^T X approximates X):
+//   e_p^2 = (||X||^2 - ||Xh||^2 + sum_j ||xh_j - Wh h_j||^2) / ||X||^2,
+// exact when the columns of W lie in range(Q_L).  Per row j of Xh (n x k') and
+// Ht (n x r), one wave: lane c forms d_c = xh_jc - sum_l Wh[c][l] h_jl.
+// Block partials (two FP64 sums) go to part[2 blockIdx.x + {0, 1}].
+__global__ void __launch_bounds__(256)
+proxy_kernel(const float* __restrict__ Xh, int64_t ldx, const float* __restrict__ Ht, int r,
+             const float* __restrict__ Wh, int kp, int64_t n, double* __restrict__ part) {
+  extern __shared__ float whs[];                 // kp x r
+  __shared__ double red[2][256];
+  for (int e = threadIdx.x; e < kp * r; e += 256) whs[e] = Wh[e];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double sd = 0.0, sx = 0.0;
+  for (int64_t row = (int64_t)blockIdx.x * 4 + wave; row < n; row += (int64_t)gridDim.x * 4) {
+    for (int c = lane; c < kp; c += 64) {
+      double acc = 0.0;
+      for (int l = 0; l < r; ++l) acc += (double)whs[c * r + l] * (double)Ht[row * r + l];
+      const double x = Xh[row * ldx + c];
+      const double d = x - acc;
+      sd += d * d;
+      sx += x * x;
+    }
+  }
+  red[0][threadIdx.x] = sd;
+  red[1][threadIdx.x] = sx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = red[0][0];
+    part[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
 }  // namespace
 
 int residual_blocks(int64_t m, int64_t n) {
@@ -177,5 +218,17 @@ hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t n, co
                        out, counter);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+int proxy_blocks(int64_t n) {
+  int64_t b = ceil_div(n, 4);
+  return (int)(b < 256 ? (b < 1 ? 1 : b) : 256);
+}
+
+hipError_t launch_proxy(const float* Xh, int64_t ldx, const float* Ht, int r, const float* Wh, int kp, int64_t n,
+                        double* part, hipStream_t st) {
+  const size_t lds = (size_t)kp * r * sizeof(float);
+  hipLaunchKernelGGL(proxy_kernel, dim3(proxy_blocks(n)), dim3(256), lds, st, Xh, ldx, Ht, r, Wh, kp, n, part);
   return hipGetLastError();
 }

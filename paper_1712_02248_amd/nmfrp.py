@@ -40,6 +40,7 @@ _SIGS = {
     "nmf_init": (c_i32, [c_vp, c_vp, c_vp, ctypes.c_float]),
     "nmf_step": (c_i32, [c_vp, c_i32]),
     "nmf_residual": (c_i32, [c_vp, c_vp, c_i64, c_dbl_p]),
+    "nmf_proxy_residual": (c_i32, [c_vp, c_dbl_p]),
     "nmf_fit": (c_i32, [c_vp, c_vp, c_i64, c_i32, ctypes.c_double, c_i32, c_i32_p, c_dbl_p]),
     "nmf_get_factors": (c_i32, [c_vp, c_vp, c_vp]),
     "nmf_get_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
@@ -186,6 +187,12 @@ class NMF:
     def residual(self, X):
         e = ctypes.c_double()
         self._c(load().nmf_residual(self.h, _ptr(X), X.stride(0), ctypes.byref(e)))
+        return e.value
+
+    def proxy_residual(self):
+        """Sketch-only estimate of the relative error (see nmf_proxy_residual)."""
+        e = ctypes.c_double()
+        self._c(load().nmf_proxy_residual(self.h, ctypes.byref(e)))
         return e.value
 
     def fit(self, X, max_iters, eps=0.0, check_every=10):

@@ -161,59 +161,63 @@ def test_nnls_rows_match_oracle(lib, k, r, rows, sweeps):
 
 
 def test_init_learned_selection_matches_oracle(lib):
-    """nmf_init_learned: network rows on the aligned inputs, per-row rejection by
-    the compressed residual, W as given, then the first step is the W half-step
-    (checked against the oracle iteration from the selected factors)."""
+    """nmf_init_learned against the oracle run on its own compression of the same
+    seeded inputs: the network's rows on the aligned inputs x-tilde = M x-hat
+    (M = G^T Q_L), per-row rejection by rho(h) = ||x-hat - Q_L^T W_ref h||^2, the
+    optional column-NNLS refinement, and the first iteration from the selected
+    factors.  Each side forms M and Q_L^T W_ref from its own Q_L; all of these
+    are independent of the basis chosen for range(Q_L)."""
     print("init_learned selection", flush=True)
     m, n, r, kp, q = 512, 256, 10, 20, 2
     seed = datagen.cfg_seed("c1")
     X = datagen.planted_c1(m, n, r, seed)[0]
     OL = datagen.gaussian(n, kp, seed, datagen.S_OMEGA_L)
     OR = datagen.gaussian(m, kp, seed, datagen.S_OMEGA_R)
-    W0, Hrand = datagen.init_factors(X.mean(), m, n, r, seed)
+    W0, _ = datagen.init_factors(X.mean(), m, n, r, seed)
+    G = datagen.gaussian(m, kp, seed + 1, datagen.S_FRESH)
+    Wref = datagen.uniform((m, r), seed + 2, datagen.S_FRESH)
+    # cold rows: zero on even rows (an untrained net loses to them), far off on
+    # odd rows (the net wins there)
+    Hcold = (1e3 * datagen.uniform((n, r), seed + 3, datagen.S_FRESH)).astype(np.float32)
+    Hcold[0::2] = 0.0
+    hdim = 64
+    p0 = datagen.mlp_he_init(kp, hdim, r, seed=52)
+    # ---- oracle
+    QL, QR, Xh, Xc = onmf.compress(X, OL, OR, q)
+    M = G.T.astype(np.float64) @ QL
+    Wh = QL.T @ Wref.astype(np.float64)
+    P = omlp.unflatten(p0.astype(np.float64), kp, hdim, r)
+    Hn = omlp.infer(P, Xh @ M.T)
+    Hsel, rej = omlp.select_warm(Xh, Wh, Hn, Hcold)
+    rho_n = np.sum((Xh - Hn @ Wh.T) ** 2, 1)
+    rho_c = np.sum((Xh - Hcold.astype(np.float64) @ Wh.T) ** 2, 1)
+    clear = np.abs(rho_n - rho_c) > 1e-3 * rho_c
+    assert 0 < rej.sum() < n and clear.sum() > 0.9 * n        # both branches exercised
+    Href = onmf.column_nnls(Xh, Wh, 7, Ht0=Hsel)
+    W1, H1 = onmf.fasthals_rp_iteration(W0, Hsel, Xh, Xc, QL, QR, normalize=1)
+    # ---- HIP path
+    from paper_1712_02248_amd import warmstart
     ctx = lib.NMF(m, n, r, kp, q, seed=7)
     ctx.compress(dev(X), dev(OL), dev(OR))
-    QL, QR, Xh, Xc = (t.cpu().numpy().astype(np.float64) for t in ctx.state())
-    g = np.random.default_rng(51)
-    M = np.linalg.qr(g.standard_normal((kp, kp)))[0].astype(np.float32)
-    Wref = g.random((m, r))
-    Wh_ref = (QL.T @ Wref).astype(np.float32)
-    # cold rows: the NNLS optimum on even rows (the untrained net loses there),
-    # far-off values on odd rows (the net wins there)
-    Hopt = onmf.column_nnls(Xh, Wh_ref.astype(np.float64), 300)
-    Hcold = np.where((np.arange(n) % 2 == 0)[:, None], Hopt, 1e3 * Hrand).astype(np.float32)
-    p0 = datagen.mlp_he_init(kp, 64, r, seed=52)
-    net = lib.Mlp(kp, 64, r, dev(p0), max_batch=100)      # three inference chunks
-    nrej = ctx.init_learned(net, dev(Wh_ref), align_M=dev(M), W0=dev(W0), Ht_cold=dev(Hcold))
-    Wg, Hg = (t.cpu().numpy() for t in ctx.factors())
-    assert np.array_equal(Wg, W0)
-    P = omlp.unflatten(p0.astype(np.float64), kp, 64, r)
-    Hn = omlp.infer(P, Xh @ M.T.astype(np.float64))
-    Hsel, rej = omlp.select_warm(Xh, Wh_ref.astype(np.float64), Hn, Hcold)
-    rho_n = np.sum((Xh - Hn @ Wh_ref.T.astype(np.float64)) ** 2, 1)
-    rho_c = np.sum((Xh - Hcold @ Wh_ref.T.astype(np.float64)) ** 2, 1)
-    clear = np.abs(rho_n - rho_c) > 1e-4 * rho_c
-    assert 0 < rej.sum() < n                                # both branches exercised
+    net = lib.Mlp(kp, hdim, r, dev(p0), max_batch=100)      # three inference chunks
+    nrej = warmstart.warm_init(ctx, net, dev(G), dev(Wref), Ht_cold=dev(Hcold), W0=dev(W0), count=True)
+    Wg, Hg = (t.cpu().numpy().astype(np.float64) for t in ctx.factors())
+    assert np.array_equal(Wg, W0.astype(np.float64))
     gpu_rej = np.all(Hg == Hcold, axis=1)
     assert np.array_equal(gpu_rej[clear], rej[clear])
     assert abs(nrej - rej.sum()) <= np.sum(~clear)
     scale = np.abs(Hsel).max(axis=1, keepdims=True) + 1e-30
     assert np.max((np.abs(Hg - Hsel) / scale)[clear]) <= 1e-4
-    # never worse than cold on the compressed residual (exact property)
-    rho_g = np.sum((Xh - Hg.astype(np.float64) @ Wh_ref.T.astype(np.float64)) ** 2, 1)
-    assert np.all(rho_g <= rho_c * (1 + 1e-5))
-    # first iteration from the selected factors
     ctx.step(1)
-    W1, H1 = (t.cpu().numpy().astype(np.float64) for t in ctx.factors())
-    rW, rH = onmf.fasthals_rp_iteration(W0, Hg, Xh, Xc, QL, QR, normalize=1)
-    assert rel_norm(W1, rW) <= 1e-4 and rel_norm(H1, rH) <= 1e-4
-    # column-NNLS refinement of the selected rows against Wh_ref
-    ctx.init_learned(net, dev(Wh_ref), align_M=dev(M), W0=dev(W0), Ht_cold=dev(Hcold), refine_sweeps=7)
-    _, Hr = (t.cpu().numpy() for t in ctx.factors())
-    ref_r = onmf.column_nnls(Xh, Wh_ref.astype(np.float64), 7, Ht0=Hg.astype(np.float64))
-    assert np.max(np.abs(Hr - ref_r) / (np.abs(ref_r).max(axis=1, keepdims=True) + 1e-30)) <= 1e-4
-    rho_r = np.sum((Xh - Hr.astype(np.float64) @ Wh_ref.T.astype(np.float64)) ** 2, 1)
-    assert np.all(rho_r <= rho_g * (1 + 1e-5))
+    Wg1, Hg1 = (t.cpu().numpy().astype(np.float64) for t in ctx.factors())
+    assert rel_norm(Wg1, W1) <= 1e-4 and rel_norm(Hg1, H1) <= 1e-4
+    # with the refinement sweeps
+    ctx.compress(dev(X), dev(OL), dev(OR))
+    warmstart.warm_init(ctx, net, dev(G), dev(Wref), Ht_cold=dev(Hcold), W0=dev(W0), refine_sweeps=7)
+    _, Hr = (t.cpu().numpy().astype(np.float64) for t in ctx.factors())
+    assert np.max((np.abs(Hr - Href) / (np.abs(Href).max(axis=1, keepdims=True) + 1e-30))[clear]) <= 1e-4
+    rho_r = np.sum((Xh - Hr @ Wh.T) ** 2, 1)
+    assert np.all(rho_r <= np.minimum(rho_n, rho_c) * (1 + 1e-4))    # never worse than cold
 
 
 def test_init_learned_rejects_bad_arguments(lib):

@@ -113,6 +113,27 @@ def test_c1_full_parity_200_iterations(lib):
     assert abs(e_gpu - ref["e"]) <= 1e-4
 
 
+def test_proxy_residual_matches_oracle(lib):
+    """Sketch-only proxy (needs a step and an exact residual first) against the
+    oracle's proxy on its own run from the same seeded inputs."""
+    print("proxy residual", flush=True)
+    m, n, r, kp, q, iters = 512, 256, 10, 20, 2, 30
+    X, OL, OR, W0, H0 = small_case(m, n, r, kp, datagen.cfg_seed("c1"))
+    ctx, Xd = gpu_run(lib, X, OL, OR, W0, H0, r, kp, q, 0)
+    with pytest.raises(lib.NmfError):
+        ctx.proxy_residual()             # no step since init
+    ctx.step(iters)
+    with pytest.raises(lib.NmfError):
+        ctx.proxy_residual()             # no exact residual on this compression yet
+    e = ctx.residual(Xd)
+    ep = ctx.proxy_residual()
+    ref = onmf.fasthals_rp(X, OL, OR, q, W0, H0, iters)
+    nx2 = float(np.sum(X.astype(np.float64) ** 2))
+    ep_ref = onmf.proxy_rel_error(nx2, ref["Xh"], ref["QL"].T @ ref["W"], ref["Ht"])
+    print(f"proxy gpu={ep:.8e} oracle={ep_ref:.8e} exact={e:.8e}", flush=True)
+    assert abs(ep - ep_ref) <= 1e-4      # an estimate of e, not a bound: no check against e
+
+
 def test_device_omega_matches_oracle_philox(lib):
     """Omega drawn on the device (omega=NULL) equals the oracle's Philox draw, so the
     oracle run on its own Philox Omega agrees with the GPU run."""
@@ -179,3 +200,28 @@ def test_fit_and_errors(lib):
     bad[3, 4] = float("nan")
     with pytest.raises(lib.NmfError):
         ctx.validate(bad)
+
+
+@pytest.mark.parametrize("alpha,beta", [(0.5, 0.0), (0.0, 2.0), (0.3, 1.0)])
+def test_sparsity_smoothness_rule_matches_oracle(lib, alpha, beta):
+    """FastHALS-RP with the alpha (L1) and beta (L2) terms on B (Sec 4.1), no
+    normalisation (the rule is stated for the unnormalised B), 20 iterations:
+    factors elementwise and the error against the oracle's own run."""
+    print(f"constrained alpha={alpha} beta={beta}", flush=True)
+    m, n, r, kp, q, iters = 512, 256, 10, 20, 2, 20
+    X, OL, OR, W0, H0 = small_case(m, n, r, kp, datagen.cfg_seed("c1"))
+    ctx = lib.NMF(m, n, r, kp, q, seed=5, normalize=0, alpha=alpha, beta=beta)
+    Xd = torch.from_numpy(X).cuda()
+    ctx.compress(Xd, torch.from_numpy(OL).cuda(), torch.from_numpy(OR).cuda())
+    ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
+    ctx.step(iters)
+    e = ctx.residual(Xd)
+    Wg, Hg = (t.cpu().numpy().astype(np.float64) for t in ctx.factors())
+    ref = onmf.fasthals_rp(X, OL, OR, q, W0, H0, iters, normalize=0, alpha=alpha, beta=beta)
+    assert abs(e - ref["e"]) <= 1e-4
+    assert np.abs(Hg - ref["Ht"]).max() <= 2e-3 * np.abs(ref["Ht"]).max()
+    assert np.abs(Wg - ref["W"]).max() <= 2e-3 * np.abs(ref["W"]).max()
+    # the L1 term produces exact zeros in B where the oracle has them
+    zo = ref["Ht"] == 0
+    if alpha > 0:
+        assert zo.any() and np.mean(Hg[zo] == 0) > 0.99
