@@ -110,20 +110,27 @@ nmf_status nmf_residual(nmf_ctx* ctx, const float* X, int64_t ldx, double* rel_e
 /* Sketch-only estimate of e from the left sketch (Sec 3: X ~ Q_L Q_L^T X):
  *   e_p^2 = (||X||^2 - ||Xh||^2 + sum_j ||xh_j - Wh h_j||^2) / ||X||^2,
  * with Wh = Q_L^T W of the last H sweep; equal to e when the columns of W lie
- * in range(Q_L), otherwise an approximation (no pass over X).  Needs at least
- * one nmf_step since the last init and ||X||^2 from an exact nmf_residual or
- * nmf_fit since the last compression (NMF_ESTATE otherwise).  Synchronising. */
+ * in range(Q_L), otherwise an approximation (no pass over X).  ||X||^2 is
+ * accumulated in FP64 by nmf_compress (during the X Q_R product).  Needs at
+ * least one nmf_step since the last init and a compression by nmf_compress
+ * (not nmf_set_state); NMF_ESTATE otherwise.  Synchronising. */
 nmf_status nmf_proxy_residual(nmf_ctx* ctx, double* rel_err);
 
 /* Runs steps in chunks, evaluating the exact residual after each chunk, until
  * e <= eps or max_iters iterations (the paper leaves the stopping rule open:
- * Alg 1-4).  check_every > 0: fixed chunk; check_every == 0: e is evaluated
- * at the current factors first; the next chunk is 50, 20, 10 or 5 iterations
- * as that e exceeds eps by more than 10 %, 1 %, 0.3 % or less, and every later
- * chunk is 1.5 times the iterations a straight-line extrapolation of the last
- * two evaluations needs to reach eps, clamped to 5..50 (50 if e did not
- * fall).  max_iters == 0 only evaluates e.  Synchronising.  *iters_done and
- * *rel_err report the iterations run and the last e. */
+ * Alg 1-4).  check_every > 0: fixed chunk.  check_every == 0 after
+ * nmf_compress: until the first exact residual, chunks (5 first, then 1.2
+ * times the straight-line extrapolation of the last two proxy values, 5..50)
+ * are followed by the sketch-only proxy (nmf_proxy_residual, no pass over X);
+ * the first exact residual runs once the proxy is within 1 % of eps, after 100
+ * iterations, or at max_iters.  From then on every chunk ends with an exact
+ * residual and is 1.5 times the iterations a straight-line extrapolation of
+ * the last two exact values needs to reach eps (5..50; by the gap to eps:
+ * 50, 20, 10, 5 for more than 10 %, 1 %, 0.3 % or less when there is no
+ * slope).  check_every == 0 after nmf_set_state (no ||X||^2): the same exact
+ * schedule, starting with e at the current factors.  Only an exact e <= eps
+ * stops.  max_iters == 0 only evaluates e.  Synchronising.  *iters_done and
+ * *rel_err report the iterations run and the last exact e. */
 nmf_status nmf_fit(nmf_ctx* ctx, const float* X, int64_t ldx, int32_t max_iters, double eps,
                    int32_t check_every, int32_t* iters_done, double* rel_err);
 

@@ -18,7 +18,8 @@ constexpr int BK = 32;
 template <int BM, int BN, int WM, int WN, bool AT>
 __global__ void __launch_bounds__(256)
 gemm_f32_kernel(const float* __restrict__ A, int64_t lda, const float* __restrict__ B, int64_t ldb,
-                float* __restrict__ C, int64_t ldc, int64_t M, int64_t N, int64_t K, int64_t kchunk) {
+                float* __restrict__ C, int64_t ldc, int64_t M, int64_t N, int64_t K, int64_t kchunk,
+                double* __restrict__ sq) {
   constexpr int TM = BM / WM / 32, TN = BN / WN / 32;
   static_assert(TM >= 1 && TN >= 1 && WM * WN == 4, "bad tiling");
   constexpr int AROW = AT ? (BM + 4) : (BK + 4);
@@ -82,7 +83,17 @@ gemm_f32_kernel(const float* __restrict__ A, int64_t lda, const float* __restric
       rb[p] = v;
     }
   };
+  // optional FP64 sum of squares of A (first column tile of the grid only, so
+  // every element of A is counted once): ||X||^2 for free with X Q
+  const bool want_sq = !AT && sq != nullptr && blockIdx.y == 0;
+  double asq = 0.0;
   auto store_tile = [&](const f32x4* ra, const f32x4* rb) {
+    if (want_sq) {
+#pragma unroll
+      for (int p = 0; p < A_V4; ++p)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) asq = fma((double)ra[p][e], (double)ra[p][e], asq);
+    }
 #pragma unroll
     for (int p = 0; p < A_V4; ++p) {
       const int f = tid + 256 * p;
@@ -163,6 +174,16 @@ gemm_f32_kernel(const float* __restrict__ A, int64_t lda, const float* __restric
     }
   }
 
+  if (want_sq) {   // block sum in fixed order -> sq[blockIdx.x + gridDim.x blockIdx.z]
+    __shared__ double red[256];
+    red[tid] = asq;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    if (tid == 0) sq[blockIdx.x + (int64_t)gridDim.x * blockIdx.z] = red[0];
+  }
   // D[i][j] of a 32x32 tile: lane j + 32*((i/4)%2), register (i/8)*4 + i%4.
   float* Cz = C + (int64_t)blockIdx.z * (M * ldc);  // partial slice when split
 #pragma unroll
@@ -194,15 +215,15 @@ splitk_reduce(const float* __restrict__ part, int splits, float* __restrict__ C,
 
 template <int BM, int BN, int WM, int WN>
 hipError_t run(const float* A, int64_t lda, int a_trans, const float* B, int64_t ldb, float* C,
-               int64_t ldc, int64_t M, int64_t N, int64_t K, int splits, hipStream_t st) {
+               int64_t ldc, int64_t M, int64_t N, int64_t K, int splits, double* sq, hipStream_t st) {
   const int64_t kchunk = round_up(ceil_div(K, splits), BK);
   dim3 grid((unsigned)ceil_div(M, BM), (unsigned)ceil_div(N, BN), (unsigned)splits);
   if (a_trans)
     hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, true>), grid, dim3(256), 0, st, A, lda, B,
-                       ldb, C, ldc, M, N, K, kchunk);
+                       ldb, C, ldc, M, N, K, kchunk, nullptr);
   else
     hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, WM, WN, false>), grid, dim3(256), 0, st, A, lda, B,
-                       ldb, C, ldc, M, N, K, kchunk);
+                       ldb, C, ldc, M, N, K, kchunk, sq);
   return hipGetLastError();
 }
 
@@ -210,6 +231,9 @@ int bn_for(int64_t N) { return N <= 32 ? 32 : N <= 64 ? 64 : N <= 128 ? 128 : 25
 int bm_for(int bn) { return bn <= 128 ? 128 : 64; }
 
 }  // namespace
+
+// Number of sum-of-squares partials launch_gemm_f32 writes for these sizes.
+int gemm_f32_sq_parts(int64_t M, int64_t N, int splits) { return (int)(ceil_div(M, bm_for(bn_for(N))) * splits); }
 
 int gemm_f32_pick_splits(int64_t M, int64_t N, int64_t K, int a_trans) {
   (void)a_trans;
@@ -230,7 +254,7 @@ size_t gemm_f32_part_floats(int64_t M, int64_t N, int splits) {
 
 hipError_t launch_gemm_f32(const float* A, int64_t lda, int a_trans, const float* B, int64_t ldb,
                            float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, int splits,
-                           float* part, hipStream_t st) {
+                           float* part, hipStream_t st, double* sq) {
   if (M == 0 || N == 0) return hipSuccess;
   if (N > 256 || splits < 1) return hipErrorInvalidValue;
   if (lda % 4 || ldb % 4 || ((uintptr_t)A & 15) || ((uintptr_t)B & 15)) return hipErrorInvalidValue;
@@ -240,10 +264,10 @@ hipError_t launch_gemm_f32(const float* A, int64_t lda, int a_trans, const float
   const int64_t ldo = splits > 1 ? N : ldc;
   hipError_t e;
   switch (bn_for(N)) {
-    case 32: e = run<128, 32, 4, 1>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, st); break;
-    case 64: e = run<128, 64, 2, 2>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, st); break;
-    case 128: e = run<128, 128, 2, 2>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, st); break;
-    default: e = run<64, 256, 1, 4>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, st); break;
+    case 32: e = run<128, 32, 4, 1>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;
+    case 64: e = run<128, 64, 2, 2>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;
+    case 128: e = run<128, 128, 2, 2>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;
+    default: e = run<64, 256, 1, 4>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;
   }
   if (e != hipSuccess || splits == 1) return e;
   int64_t g = ceil_div(M * N, 256);

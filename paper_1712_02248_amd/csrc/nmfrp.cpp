@@ -30,7 +30,7 @@ struct Layout {
   size_t omL, omR, QL, TM, Xc, QR, TN, Xh, W, Ht;
   size_t gemm_part, gram_part, G, R, qr_status;
   size_t hs_part, acc_w, acc_h, counters, Hc, GH, Wh, GW, scale_w;
-  size_t res_part, res_out, flags, proxy_part, proxy_out;
+  size_t res_part, res_out, flags, proxy_part, proxy_out, xsq_part;
   int64_t ldq, ldqt;                 // low-precision copies of X: m x ldq and n x ldqt
   size_t Xq, XqT, Ex, Bt, Eb;
   size_t total;
@@ -103,7 +103,8 @@ Layout make_layout(const nmf_params* p) {
   L.res_out = pl.take(2 * d);
   L.flags = pl.take(8 * sizeof(int));
   L.proxy_part = pl.take(2 * 256 * d);
-  L.proxy_out = pl.take(2 * d);
+  L.proxy_out = pl.take(3 * d);            // proxy sums, then ||X||^2 from compression
+  L.xsq_part = pl.take((size_t)gemm_f32_sq_parts(m, k, 64) * d);
   L.Xq = L.XqT = L.Ex = L.Bt = L.Eb = 0;
   if (p->prec != NMF_FP32) {
     const size_t es = p->prec == NMF_BF16 ? 2 : 1;
@@ -127,7 +128,7 @@ struct nmf_ctx {
   char* ws;
   hipStream_t st;
   bool compressed = false, initialized = false, stepped = false;
-  double normX2 = -1.0;   // ||X||^2 from the last exact residual on this compression
+  bool xsq_valid = false;  // ||X||^2 of the compressed X is in proxy_out[2]
   std::string err;
   hipEvent_t ev[6];
   bool have_ev = false;
@@ -151,13 +152,17 @@ nmf_status fail(nmf_ctx* c, nmf_status s, const std::string& msg) {
       return fail((c), NMF_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// orthonormalise Y (rows x k, ld) in place: CholeskyQR2 + conditional third pass
+// Orthonormalise Y (rows x k, ld) in place.  final: CholeskyQR2 with the
+// shifted third pass on breakdown (the bases the sketches are built on).  Not
+// final (an intermediate basis of the subspace iteration, which only has to
+// span the same space and be well conditioned): one CholeskyQR pass, shifted
+// on breakdown; its orthogonality error is about kappa(Y)^2 u_fp64.
 hipError_t orth(float* Y, int64_t ld, int64_t rows, int k, double* gram_part, double* G,
-                double* R, int* status, hipStream_t st) {
+                double* R, int* status, hipStream_t st, bool final = true) {
   hipError_t e;
   const int splits = gram_pick_splits(rows, k);
-  if ((e = launch_fill_i32(status, 1, 0, st)) != hipSuccess) return e;   // shift flag
-  for (int attempt = 0; attempt < 3; ++attempt) {
+  const int passes = final ? 3 : 1;       // the first pass resets the shift flags
+  for (int attempt = 0; attempt < passes; ++attempt) {
     if ((e = launch_gram_f64(Y, ld, rows, k, gram_part, splits, G, attempt == 2 ? status : nullptr, st)))
       return e;
     if ((e = launch_cholesky(G, k, rows, R, status, attempt, st))) return e;
@@ -325,43 +330,51 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
   auto XtB = [&](const float* B, float* C) -> hipError_t {           // X^T B (n x k')
     return lp ? gemm_lowp(c, 1, B, C) : gemm(c, X, ldx, 1, B, C, n, m);
   };
-  // left range finder: Q_L = orth(X Omega_L); q x { Z = orth(X^T Q_L); Q_L = orth(X Z) }
+  // left range finder: Q_L = orth(X Omega_L); q x { Z = orth(X^T Q_L); Q_L = orth(X Z) };
+  // only the last orthonormalisation of each side is a full CholeskyQR2
+  const bool refine = lp && c->p.refine_fp32;
   HIPCHK(c, XB(omL, QL));
-  HIPCHK(c, orth(QL, L.KP, m, k, gp, G, R, qs, st));
+  HIPCHK(c, orth(QL, L.KP, m, k, gp, G, R, qs, st, q == 0 && !refine));
   for (int it = 0; it < q; ++it) {
     HIPCHK(c, XtB(QL, TN));
-    HIPCHK(c, orth(TN, L.KP, n, k, gp, G, R, qs, st));
+    HIPCHK(c, orth(TN, L.KP, n, k, gp, G, R, qs, st, false));
     HIPCHK(c, XB(TN, QL));
-    HIPCHK(c, orth(QL, L.KP, m, k, gp, G, R, qs, st));
+    HIPCHK(c, orth(QL, L.KP, m, k, gp, G, R, qs, st, it == q - 1 && !refine));
   }
   // right range finder on X^T with Omega_R
   HIPCHK(c, XtB(omR, QR));
-  HIPCHK(c, orth(QR, L.KP, n, k, gp, G, R, qs, st));
+  HIPCHK(c, orth(QR, L.KP, n, k, gp, G, R, qs, st, q == 0 && !refine));
   for (int it = 0; it < q; ++it) {
     HIPCHK(c, XB(QR, TM));
-    HIPCHK(c, orth(TM, L.KP, m, k, gp, G, R, qs, st));
+    HIPCHK(c, orth(TM, L.KP, m, k, gp, G, R, qs, st, false));
     HIPCHK(c, XtB(TM, QR));
-    HIPCHK(c, orth(QR, L.KP, n, k, gp, G, R, qs, st));
+    HIPCHK(c, orth(QR, L.KP, n, k, gp, G, R, qs, st, it == q - 1 && !refine));
   }
   // optional FP32 refinement: one power iteration per side on the exact X
-  if (lp && c->p.refine_fp32) {
+  if (refine) {
     HIPCHK(c, gemm(c, X, ldx, 1, QL, TN, n, m));
-    HIPCHK(c, orth(TN, L.KP, n, k, gp, G, R, qs, st));
+    HIPCHK(c, orth(TN, L.KP, n, k, gp, G, R, qs, st, false));
     HIPCHK(c, gemm(c, X, ldx, 0, TN, QL, m, n));
-    HIPCHK(c, orth(QL, L.KP, m, k, gp, G, R, qs, st));
+    HIPCHK(c, orth(QL, L.KP, m, k, gp, G, R, qs, st, true));
     HIPCHK(c, gemm(c, X, ldx, 0, QR, TM, m, n));
-    HIPCHK(c, orth(TM, L.KP, m, k, gp, G, R, qs, st));
+    HIPCHK(c, orth(TM, L.KP, m, k, gp, G, R, qs, st, false));
     HIPCHK(c, gemm(c, X, ldx, 1, TM, QR, n, m));
-    HIPCHK(c, orth(QR, L.KP, n, k, gp, G, R, qs, st));
+    HIPCHK(c, orth(QR, L.KP, n, k, gp, G, R, qs, st, true));
   }
   // projected data (Sec 4), always FP32 on X: Xh = X^T Q_L (X-hat^T), Xc = X Q_R (X-check)
   HIPCHK(c, gemm(c, X, ldx, 1, QL, Xh, n, m));
-  HIPCHK(c, gemm(c, X, ldx, 0, QR, Xc, m, n));
+  {   // Xc = X Q_R, with ||X||^2 in FP64 from the same pass (for the proxy residual)
+    const int s = gemm_f32_pick_splits(m, k, n, 0);
+    double* sqp = c->at<double>(L.xsq_part);
+    HIPCHK(c, launch_gemm_f32(X, ldx, 0, QR, L.KP, Xc, L.KP, m, k, n, s, c->at<float>(L.gemm_part), st, sqp));
+    HIPCHK(c, launch_sum_partials_f64(sqp, gemm_f32_sq_parts(m, k, s), 1, c->at<double>(L.proxy_out) + 2,
+                                      nullptr, st));
+  }
   HIPCHK(c, hipEventRecord(c->ev[1], st));
   c->t_compress = true;
   c->compressed = true;
   c->stepped = false;
-  c->normX2 = -1.0;
+  c->xsq_valid = true;
   return NMF_OK;
 }
 
@@ -463,31 +476,95 @@ nmf_status nmf_residual(nmf_ctx* c, const float* X, int64_t ldx, double* rel_err
   if (qs[1]) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
   *rel_err = (h[1] > 0) ? std::sqrt(h[0] / h[1]) : 0.0;
   if (!std::isfinite(h[0]) || !std::isfinite(h[1])) return fail(c, NMF_ENONFINITE, "non-finite residual");
-  c->normX2 = h[1];
   return NMF_OK;
 }
 
 nmf_status nmf_proxy_residual(nmf_ctx* c, double* rel_err) {
   if (!c || !rel_err) return fail(c, NMF_EINVAL, "bad arguments");
   if (!c->stepped) return fail(c, NMF_ESTATE, "the proxy needs at least one nmf_step after init");
-  if (!(c->normX2 > 0)) return fail(c, NMF_ESTATE, "the proxy needs ||X||^2 from an exact residual on this compression");
+  if (!c->xsq_valid) return fail(c, NMF_ESTATE, "the proxy needs ||X||^2 from nmf_compress (not nmf_set_state)");
   Layout& L = c->L;
   const int nb = proxy_blocks(c->p.n);
   HIPCHK(c, launch_proxy(c->at<float>(L.Xh), L.KP, c->at<float>(L.Ht), c->p.r, c->at<float>(L.Wh), c->p.k_sketch,
                          c->p.n, c->at<double>(L.proxy_part), c->st));
   HIPCHK(c, launch_sum_partials_f64(c->at<double>(L.proxy_part), nb, 2, c->at<double>(L.proxy_out), nullptr, c->st));
-  double h[2];
+  double h[3];
   HIPCHK(c, hipMemcpyAsync(h, c->at<double>(L.proxy_out), sizeof(h), hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
-  const double e2 = (c->normX2 - h[1] + h[0]) / c->normX2;
+  if (!(h[2] > 0)) return fail(c, NMF_ENONFINITE, "||X||^2 is zero or not finite");
+  const double e2 = (h[2] - h[1] + h[0]) / h[2];
   if (!std::isfinite(e2)) return fail(c, NMF_ENONFINITE, "non-finite proxy");
   *rel_err = std::sqrt(e2 > 0 ? e2 : 0.0);
   return NMF_OK;
 }
 
+namespace {
+
+// Adaptive schedule.  Phase 1 (no exact value yet): chunks of 5 or more with
+// the sketch-only proxy after each (no pass over X); the first exact FP64
+// residual runs once the proxy is within 1 % of eps, or after 100 iterations.
+// Phase 2: the next chunk is 1.5x the iterations a straight-line extrapolation
+// of the last two exact values needs to reach eps (5..50).  Only an exact
+// e <= eps stops the fit.
+nmf_status fit_proxy_schedule(nmf_ctx* c, const float* X, int64_t ldx, int32_t max_iters, double eps,
+                              int* iters_done, double* rel_err) {
+  nmf_status s;
+  int done = 0, chunk = 5;
+  double e = NAN;
+  int t_prev = -1;        // last evaluation (proxy in phase 1, exact in phase 2)
+  double v_prev = 0.0;
+  bool exact_seen = false;
+  auto extrapolate = [&](double v, int t, double lo, double hi, double fac) {
+    const double slope = t_prev >= 0 && t > t_prev ? (v_prev - v) / (t - t_prev) : 0.0;
+    int ch;
+    if (slope > 0) {
+      const double need = std::ceil(fac * (v - eps) / slope);
+      ch = need < lo ? (int)lo : need > hi ? (int)hi : (int)need;
+    } else {
+      const double gap = (v - eps) / (eps > 0 ? eps : 1.0);
+      ch = gap > 0.1 ? 50 : gap > 0.01 ? 20 : gap > 0.003 ? 10 : 5;
+    }
+    t_prev = t;
+    v_prev = v;
+    return ch;
+  };
+  while (done < max_iters) {
+    if (chunk > max_iters - done) chunk = max_iters - done;
+    if ((s = nmf_step(c, chunk)) != NMF_OK) return s;
+    done += chunk;
+    if (!exact_seen) {
+      double p;
+      if ((s = nmf_proxy_residual(c, &p)) != NMF_OK) return s;
+      if (p > eps * 1.01 && done < 100 && done < max_iters) {
+        chunk = extrapolate(p, done, 5, 50, 1.2);
+        continue;
+      }
+      exact_seen = true;
+      t_prev = -1;        // phase 2 extrapolates exact values only
+    }
+    if ((s = nmf_residual(c, X, ldx, &e)) != NMF_OK) return s;
+    if (e <= eps) break;
+    chunk = extrapolate(e, done, 5, 50, 1.5);
+  }
+  if (std::isnan(e) && (s = nmf_residual(c, X, ldx, &e)) != NMF_OK) return s;
+  *iters_done = done;
+  *rel_err = e;
+  return NMF_OK;
+}
+
+}  // namespace
+
 nmf_status nmf_fit(nmf_ctx* c, const float* X, int64_t ldx, int32_t max_iters, double eps,
                    int32_t check_every, int32_t* iters_done, double* rel_err) {
   if (!c || !X || check_every < 0 || max_iters < 0) return fail(c, NMF_EINVAL, "bad arguments");
+  if (check_every == 0 && max_iters > 0 && c->xsq_valid && c->initialized) {
+    int it = 0;
+    double ee = 0.0;
+    const nmf_status st = fit_proxy_schedule(c, X, ldx, max_iters, eps, &it, &ee);
+    if (iters_done) *iters_done = it;
+    if (rel_err) *rel_err = ee;
+    return st;
+  }
   int done = 0;
   double e = 0.0;
   nmf_status s;
@@ -567,7 +644,7 @@ nmf_status nmf_set_state(nmf_ctx* c, const float* QL, const float* QR, const flo
   HIPCHK(c, launch_fill_i32(c->at<int>(L.qr_status), 8, 0, c->st));
   c->compressed = true;
   c->stepped = false;
-  c->normX2 = -1.0;
+  c->xsq_valid = false;
   c->initialized = false;
   return NMF_OK;
 }

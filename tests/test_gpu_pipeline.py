@@ -123,10 +123,15 @@ def test_proxy_residual_matches_oracle(lib):
     with pytest.raises(lib.NmfError):
         ctx.proxy_residual()             # no step since init
     ctx.step(iters)
-    with pytest.raises(lib.NmfError):
-        ctx.proxy_residual()             # no exact residual on this compression yet
+    ep = ctx.proxy_residual()            # ||X||^2 comes from the compression pass
     e = ctx.residual(Xd)
-    ep = ctx.proxy_residual()
+    # a context filled from exported sketches has no ||X||^2
+    other = lib.NMF(m, n, r, kp, q, seed=5)
+    other.set_state(*ctx.state())
+    other.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
+    other.step(1)
+    with pytest.raises(lib.NmfError):
+        other.proxy_residual()
     ref = onmf.fasthals_rp(X, OL, OR, q, W0, H0, iters)
     nx2 = float(np.sum(X.astype(np.float64) ** 2))
     ep_ref = onmf.proxy_rel_error(nx2, ref["Xh"], ref["QL"].T @ ref["W"], ref["Ht"])
@@ -183,14 +188,24 @@ def test_fit_and_errors(lib):
     ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
     it2, e2 = ctx.fit(Xd, max_iters=200, eps=1.05 * ref["e"], check_every=5)
     assert it2 < 200 and e2 <= 1.05 * ref["e"]
-    # adaptive schedule: e at the current factors first, so a start that
-    # already meets eps runs no iteration; otherwise it stops at eps
+    # adaptive schedule (proxy-guided after nmf_compress): a start that already
+    # meets eps stops after the first chunk of 5; otherwise it stops at eps
     e_now = ctx.residual(Xd)
     it3, e3 = ctx.fit(Xd, max_iters=200, eps=2.0 * e_now, check_every=0)
-    assert it3 == 0 and e3 == e_now
+    assert it3 == 5 and e3 <= 2.0 * e_now
     ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
     it4, e4 = ctx.fit(Xd, max_iters=200, eps=1.05 * ref["e"], check_every=0)
     assert 0 < it4 < 200 and e4 <= 1.05 * ref["e"]
+    assert abs(ctx.residual(Xd) - e4) <= 1e-12 * e4          # the reported e is exact
+    # without ||X||^2 (sketches imported): e at the current factors comes first
+    imp = lib.NMF(m, n, r, kp, q, seed=5)
+    imp.set_state(*ctx.state())
+    imp.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
+    e_imp = imp.residual(Xd)
+    it5, e5 = imp.fit(Xd, max_iters=200, eps=2.0 * e_imp, check_every=0)
+    assert it5 == 0 and e5 == e_imp
+    it6, e6 = imp.fit(Xd, max_iters=200, eps=1.05 * ref["e"], check_every=0)
+    assert 0 < it6 < 200 and e6 <= 1.05 * ref["e"]
     # validation of X
     ctx.validate(Xd)
     bad = Xd.clone()
