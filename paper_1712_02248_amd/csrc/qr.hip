@@ -105,7 +105,7 @@ cholesky_kernel(const double* __restrict__ G, int k, int64_t rows, double* __res
   constexpr int PB = KMAX / TD;
   constexpr int NW = TD * TD / 64;
   if (attempt == 2 && status[0] == 0) return;
-  __shared__ double colj[KMAX], rowj[KMAX];
+  __shared__ double colj[2][KMAX], rowj[2][KMAX];   // double-buffered: one barrier per column
   __shared__ double wred[NW];
   __shared__ int fail;
   const int tid = threadIdx.x, tx = tid % TD, ty = tid / TD;
@@ -160,30 +160,36 @@ cholesky_kernel(const double* __restrict__ G, int k, int64_t rows, double* __res
       for (int jj = 0; jj < TD; ++jj) {
         const int j = b0 * TD + jj;
         if (j >= k || stop) break;
-        // publish column j of A and row j of X (both unscaled)
+        // publish column j of A and row j of X (both unscaled) into buffer j % 2;
+        // a thread writes buffer j % 2 again only after the barrier of step
+        // j + 1, which every reader of step j has passed
+        const int bf = j & 1;
         if (tx == jj) {
 #pragma unroll
-          for (int a = 0; a < PB; ++a) colj[ty + TD * a] = M[a][b0];
+          for (int a = 0; a < PB; ++a) colj[bf][ty + TD * a] = M[a][b0];
         }
         if (ty == jj) {
 #pragma unroll
-          for (int b = 0; b < PB; ++b) rowj[tx + TD * b] = X[b0][b];
+          for (int b = 0; b < PB; ++b) rowj[bf][tx + TD * b] = X[b0][b];
         }
         __syncthreads();
-        const double p = colj[j];
+        const double p = colj[bf][j];
         if (!(p > 0.0) || !isfinite(p)) {   // uniform: every thread reads the same p
           stop = true;
           if (tid == 0) fail = 1;
           break;
         }
-        const double d = sqrt(p), id = 1.0 / d;
+        // 1/sqrt(p): hardware estimate and one Newton step; d = p / sqrt(p)
+        double id = __builtin_amdgcn_rsq(p);
+        id = id * fma(-0.5 * p * id, id, 1.5);
+        const double d = p * id;
         double lc[PB], lr[PB], xj[PB];
 #pragma unroll
-        for (int a = 0; a < PB; ++a) lc[a] = colj[ty + TD * a] * id;     // L[i][j]
+        for (int a = 0; a < PB; ++a) lc[a] = colj[bf][ty + TD * a] * id;     // L[i][j]
 #pragma unroll
         for (int b = 0; b < PB; ++b) {
-          lr[b] = colj[tx + TD * b] * id;                                // L[l][j]
-          xj[b] = rowj[tx + TD * b] * id;                                // X[j][c] / L[j][j]
+          lr[b] = colj[bf][tx + TD * b] * id;                                // L[l][j]
+          xj[b] = rowj[bf][tx + TD * b] * id;                                // X[j][c] / L[j][j]
         }
 #pragma unroll
         for (int a = 0; a < PB; ++a) {
@@ -208,7 +214,6 @@ cholesky_kernel(const double* __restrict__ G, int k, int64_t rows, double* __res
           for (int b = 0; b < PB; ++b)
             if (tx + TD * b <= j) X[b0][b] = xj[b];
         }
-        __syncthreads();
       }
     }
     __syncthreads();
@@ -237,7 +242,9 @@ cholesky_kernel(const double* __restrict__ G, int k, int64_t rows, double* __res
 
 // Q = Y R^{-1} in place on FP64 MFMA (v_mfma_f64_16x16x4_f64): a workgroup owns
 // 64 rows (16 per wave) and all k columns; the tile is read into LDS before any
-// write, so rows of other workgroups are never touched.
+// write, so rows of other workgroups are never touched.  The tile is staged with
+// batched float4 loads (ldy % 4 == 0); for k <= 64 R^{-1} is staged in LDS too
+// (row stride KMAX + 2 doubles), larger k reads it from L2.
 template <int KMAX>
 __global__ void __launch_bounds__(256)
 apply_rinv_kernel(float* __restrict__ Y, int64_t ldy, int64_t rows, int k,
@@ -246,12 +253,33 @@ apply_rinv_kernel(float* __restrict__ Y, int64_t ldy, int64_t rows, int k,
   if (attempt == 1 && status[3] != 0) return;   // second pass not needed
   if (attempt == 2 && status[0] == 0) return;
   constexpr int NT = KMAX / 16;
-  __shared__ float Ys[64][KMAX + 1];
+  constexpr bool RS = KMAX <= 64;
+  constexpr int V4 = 64 * KMAX / 4 / 256;       // float4 per thread
+  constexpr int RST = KMAX + 2;
+  __shared__ float Ys[64][KMAX + 4];
+  __shared__ double Rs[RS ? KMAX : 1][RS ? RST : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = (int64_t)blockIdx.x * 64;
-  for (int e = tid; e < 64 * KMAX; e += 256) {
-    const int i = e / KMAX, c = e % KMAX;
-    Ys[i][c] = (row0 + i < rows && c < k) ? Y[(row0 + i) * ldy + c] : 0.f;
+  f32x4 v[V4];
+#pragma unroll
+  for (int p = 0; p < V4; ++p) {
+    const int e = tid + 256 * p, i = e / (KMAX / 4), c = 4 * (e % (KMAX / 4));
+    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    v[p] = (row0 + i < rows && c < k) ? *(const f32x4*)(Y + (row0 + i) * ldy + c) : z;
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+      if (c + d >= k) v[p][d] = 0.f;          // a partial last group (k % 4 != 0)
+  }
+  if (RS) {
+    for (int e = tid; e < KMAX * KMAX; e += 256) {
+      const int a = e / KMAX, b = e % KMAX;
+      Rs[a][b] = (a < k && b < k) ? Rinv[a * k + b] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < V4; ++p) {
+    const int e = tid + 256 * p, i = e / (KMAX / 4), c = 4 * (e % (KMAX / 4));
+    *(f32x4*)(&Ys[i][c]) = v[p];
   }
   __syncthreads();
   f64x4 acc[NT];
@@ -265,7 +293,9 @@ apply_rinv_kernel(float* __restrict__ Y, int64_t ldy, int64_t rows, int k,
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int j = t * 16 + (lane & 15);
-      const double b = (kr < k && j < k) ? Rinv[kr * k + j] : 0.0;
+      double b;
+      if (RS) b = Rs[kr][j];
+      else b = (kr < k && j < k) ? Rinv[kr * k + j] : 0.0;
       acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
     }
   }

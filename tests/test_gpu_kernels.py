@@ -89,3 +89,23 @@ def test_orth_shifted_fallback(lib):
     assert np.abs(Q.T @ Q - np.eye(k)).max() < 1e-4
     Y64 = Y.astype(np.float64)
     assert np.linalg.norm(Y64 - Q @ (Q.T @ Y64)) / np.linalg.norm(Y64) < 1e-5
+
+
+def test_orth_partial_column_group_ignores_padding(lib):
+    """k = 37 inside rows of 40 floats: the padding columns hold NaN and must be
+    neither read into the result nor written."""
+    print("orth k=37 ld=40", flush=True)
+    rows, k, ld = 3000, 37, 40
+    g = np.random.default_rng(5)
+    Y = g.standard_normal((rows, k)) @ np.diag(np.logspace(0, 2, k))
+    full = np.full((rows, ld), np.nan, dtype=np.float32)
+    full[:, :k] = Y
+    Fd = torch.from_numpy(full).cuda()
+    Yd = Fd[:, :k]
+    assert lib.orth(Yd) == 0
+    F = Fd.cpu().numpy()
+    assert np.isnan(F[:, k:]).all()
+    Q = F[:, :k].astype(np.float64)
+    assert np.abs(Q.T @ Q - np.eye(k)).max() < 2e-6
+    Qr = onmf.householder_q(Y)
+    assert np.abs(Q @ Q.T - Qr @ Qr.T).max() < 1e-4
