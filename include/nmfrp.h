@@ -75,7 +75,8 @@ size_t nmf_workspace_bytes(const nmf_params* p);
 
 /* Creates a context over a caller-owned device workspace (256-byte aligned) and
  * a HIP stream (hipStream_t; NULL = the null stream).  The context struct
- * itself is host memory owned by the library until nmf_destroy(). */
+ * itself is host memory owned by the library until nmf_destroy(), as are one
+ * internal HIP stream and two events used by nmf_compress. */
 nmf_status nmf_create(const nmf_params* p, void* workspace, size_t ws_bytes, void* hip_stream,
                       nmf_ctx** out);
 void nmf_destroy(nmf_ctx* ctx);
@@ -91,7 +92,10 @@ nmf_status nmf_validate(nmf_ctx* ctx, const float* X, int64_t ldx);
  * after every product, then Xh = X^T Q_L and Xc = X Q_R.
  * X: device, m x n, leading dimension ldx (ldx % 4 == 0, 16-byte aligned).
  * omega_L: n x k' and omega_R: m x k' (leading dimension k'), device; NULL
- * draws them on the device from Philox4x32-10 (streams 3 and 4, key = seed). */
+ * draws them on the device from Philox4x32-10 (streams 3 and 4, key = seed).
+ * The right range finder runs on a second stream owned by the context (default
+ * priority), forked from and joined back to the context stream within the call,
+ * so the work is ordered on the context stream as usual. */
 nmf_status nmf_compress(nmf_ctx* ctx, const float* X, int64_t ldx, const float* omega_L,
                         const float* omega_R);
 

@@ -28,11 +28,12 @@ struct Plan {
 struct Layout {
   int64_t KP;  // k' padded to a multiple of 4 (padding columns stay zero)
   size_t omL, omR, QL, TM, Xc, QR, TN, Xh, W, Ht;
-  size_t gemm_part, gram_part, G, R, qr_status;
+  size_t gemm_part, gram_part, G, R, qr_status;     // chain 0 (left range finder)
+  size_t gemm_part2, gram_part2, G2, R2;             // chain 1 (right range finder); status at qr_status + 8
   size_t hs_part, acc_w, acc_h, counters, Hc, GH, Wh, GW, scale_w;
   size_t res_part, res_out, flags, proxy_part, proxy_out, xsq_part;
   int64_t ldq, ldqt;                 // low-precision copies of X: m x ldq and n x ldqt
-  size_t Xq, XqT, Ex, Bt, Eb;
+  size_t Xq, XqT, Ex, Bt, Eb, Bt2, Eb2;
   size_t total;
   size_t gemm_part_bytes, gram_splits_max;
 };
@@ -83,12 +84,16 @@ Layout make_layout(const nmf_params* p) {
   }
   L.gemm_part_bytes = (gp > gp2 ? gp : gp2) * f;
   L.gemm_part = pl.take(L.gemm_part_bytes);
+  L.gemm_part2 = pl.take(L.gemm_part_bytes);
   const int gs1 = gram_pick_splits(m, k), gs2 = gram_pick_splits(n, k);
   L.gram_splits_max = gs1 > gs2 ? gs1 : gs2;
   L.gram_part = pl.take(L.gram_splits_max * k * k * d);
+  L.gram_part2 = pl.take(L.gram_splits_max * k * k * d);
   L.G = pl.take(k * k * d);
   L.R = pl.take(k * k * d);
-  L.qr_status = pl.take(8 * sizeof(int));
+  L.qr_status = pl.take(16 * sizeof(int));
+  L.G2 = pl.take(k * k * d);
+  L.R2 = pl.take(k * k * d);
   size_t h1 = halfstep_part_floats(m, (int)L.KP, (int)r), h2 = halfstep_part_floats(n, (int)L.KP, (int)r);
   L.hs_part = pl.take((h1 > h2 ? h1 : h2) * f);
   L.acc_w = pl.take((L.KP * r + r) * d);
@@ -105,7 +110,7 @@ Layout make_layout(const nmf_params* p) {
   L.proxy_part = pl.take(2 * 256 * d);
   L.proxy_out = pl.take(3 * d);            // proxy sums, then ||X||^2 from compression
   L.xsq_part = pl.take((size_t)gemm_f32_sq_parts(m, k, 64) * d);
-  L.Xq = L.XqT = L.Ex = L.Bt = L.Eb = 0;
+  L.Xq = L.XqT = L.Ex = L.Bt = L.Eb = L.Bt2 = L.Eb2 = 0;
   if (p->prec != NMF_FP32) {
     const size_t es = p->prec == NMF_BF16 ? 2 : 1;
     L.Xq = pl.take((size_t)m * L.ldq * es);
@@ -113,6 +118,8 @@ Layout make_layout(const nmf_params* p) {
     L.Ex = pl.take((size_t)ceil_div(m, 128) * ceil_div(n, 128) * sizeof(int));
     L.Bt = pl.take((size_t)k * (L.ldq > L.ldqt ? L.ldq : L.ldqt) * es);
     L.Eb = pl.take((size_t)ceil_div(L.ldq > L.ldqt ? L.ldq : L.ldqt, 128) * sizeof(int));
+    L.Bt2 = pl.take((size_t)k * (L.ldq > L.ldqt ? L.ldq : L.ldqt) * es);
+    L.Eb2 = pl.take((size_t)ceil_div(L.ldq > L.ldqt ? L.ldq : L.ldqt, 128) * sizeof(int));
   }
   L.total = pl.off;
   return L;
@@ -132,6 +139,8 @@ struct nmf_ctx {
   std::string err;
   hipEvent_t ev[6];
   bool have_ev = false;
+  hipStream_t st2 = nullptr;          // second stream of nmf_compress (right range finder)
+  hipEvent_t fork = nullptr, join = nullptr;
   float ms_compress = 0, ms_step = 0, ms_residual = 0;
   bool t_compress = false, t_step = false, t_residual = false;
   template <class T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
@@ -171,37 +180,61 @@ hipError_t orth(float* Y, int64_t ld, int64_t rows, int k, double* gram_part, do
   return hipSuccess;
 }
 
-hipError_t gemm(nmf_ctx* c, const float* A, int64_t lda, int at, const float* B, float* C,
+// Scratch and stream of one range-finder chain (the two chains of nmf_compress
+// run concurrently, each with its own buffers).
+struct Chain {
+  hipStream_t st;
+  float* gemm_part;
+  double *gp, *G, *R;
+  int* qs;
+  void* Bt;
+  int* Eb;
+};
+
+Chain chain(nmf_ctx* c, int which) {
+  Layout& L = c->L;
+  Chain ch;
+  ch.st = which ? c->st2 : c->st;
+  ch.gemm_part = c->at<float>(which ? L.gemm_part2 : L.gemm_part);
+  ch.gp = c->at<double>(which ? L.gram_part2 : L.gram_part);
+  ch.G = c->at<double>(which ? L.G2 : L.G);
+  ch.R = c->at<double>(which ? L.R2 : L.R);
+  ch.qs = c->at<int>(L.qr_status) + (which ? 8 : 0);
+  ch.Bt = (L.Bt == 0) ? nullptr : (void*)c->at<char>(which ? L.Bt2 : L.Bt);
+  ch.Eb = (L.Eb == 0) ? nullptr : c->at<int>(which ? L.Eb2 : L.Eb);
+  return ch;
+}
+
+hipError_t gemm(nmf_ctx* c, const Chain& ch, const float* A, int64_t lda, int at, const float* B, float* C,
                 int64_t M, int64_t K) {
   const int64_t N = c->p.k_sketch;
   const int s = gemm_f32_pick_splits(M, N, K, at);
-  return launch_gemm_f32(A, lda, at, B, c->L.KP, C, c->L.KP, M, N, K, s,
-                         c->at<float>(c->L.gemm_part), c->st);
+  return launch_gemm_f32(A, lda, at, B, c->L.KP, C, c->L.KP, M, N, K, s, ch.gemm_part, ch.st);
 }
 
 // Low-precision range-finder product: side 0 -> X B (B is n x k'), side 1 ->
 // X^T B (B is m x k'); the thin operand is rounded (and transposed) first.
-hipError_t gemm_lowp(nmf_ctx* c, int side, const float* B, float* C) {
+hipError_t gemm_lowp(nmf_ctx* c, const Chain& ch, int side, const float* B, float* C) {
   Layout& L = c->L;
   const int64_t m = c->p.m, n = c->p.n, k = c->p.k_sketch;
   const int64_t M = side ? n : m, K = side ? m : n, Kpad = side ? L.ldqt : L.ldq;
   const int s = gemm_lp_pick_splits(M, k, Kpad, 128);
-  float* part = c->at<float>(L.gemm_part);
+  float* part = ch.gemm_part;
   hipError_t e;
   if (c->p.prec == NMF_BF16) {
-    uint16_t* Bt = c->at<uint16_t>(L.Bt);
-    if ((e = launch_prep_b_bf16(B, L.KP, K, k, Bt, Kpad, c->st))) return e;
+    uint16_t* Bt = (uint16_t*)ch.Bt;
+    if ((e = launch_prep_b_bf16(B, L.KP, K, k, Bt, Kpad, ch.st))) return e;
     const uint16_t* A = side ? c->at<uint16_t>(L.XqT) : c->at<uint16_t>(L.Xq);
-    return launch_gemm_bf16_nt(A, Kpad, Bt, Kpad, C, L.KP, M, k, Kpad, s, part, c->st);
+    return launch_gemm_bf16_nt(A, Kpad, Bt, Kpad, C, L.KP, M, k, Kpad, s, part, ch.st);
   }
-  uint8_t* Bt = c->at<uint8_t>(L.Bt);
-  int* Eb = c->at<int>(L.Eb);
-  if ((e = launch_prep_b_fp8(B, L.KP, K, k, Eb, Bt, Kpad, c->st))) return e;
+  uint8_t* Bt = (uint8_t*)ch.Bt;
+  int* Eb = ch.Eb;
+  if ((e = launch_prep_b_fp8(B, L.KP, K, k, Eb, Bt, Kpad, ch.st))) return e;
   const uint8_t* A = side ? c->at<uint8_t>(L.XqT) : c->at<uint8_t>(L.Xq);
   const int64_t tn = ceil_div(n, 128);
   // X tile (a, b) exponent at Ex[a * tn + b]; A = X: (ti, tk) = (a, b); A = X^T: (ti, tk) = (b, a)
   return launch_gemm_fp8_nt(A, Kpad, c->at<int>(L.Ex), side ? 1 : tn, side ? tn : 1, Bt, Kpad, Eb, C,
-                            L.KP, M, k, Kpad, s, part, c->st);
+                            L.KP, M, k, Kpad, s, part, ch.st);
 }
 
 // W half-step: sweep W against (Xc, Hc, G_H) derived from the summed H-side
@@ -268,6 +301,13 @@ nmf_status nmf_create(const nmf_params* p, void* workspace, size_t ws_bytes, voi
   for (int i = 0; i < 6; ++i)
     if (hipEventCreate(&c->ev[i]) != hipSuccess) { delete c; return fail(nullptr, NMF_EHIP, "event create"); }
   c->have_ev = true;
+  // second stream of the range finder (default priority) and its fork/join events
+  if (hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess) {
+    nmf_destroy(c);
+    return fail(nullptr, NMF_EHIP, "stream/event create");
+  }
   *out = c;
   return NMF_OK;
 }
@@ -276,6 +316,12 @@ void nmf_destroy(nmf_ctx* c) {
   if (!c) return;
   if (c->have_ev)
     for (int i = 0; i < 6; ++i) (void)hipEventDestroy(c->ev[i]);
+  if (c->st2) {
+    (void)hipStreamSynchronize(c->st2);
+    (void)hipStreamDestroy(c->st2);
+  }
+  if (c->fork) (void)hipEventDestroy(c->fork);
+  if (c->join) (void)hipEventDestroy(c->join);
   delete c;
 }
 
@@ -305,10 +351,8 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
   float *omL = c->at<float>(L.omL), *omR = c->at<float>(L.omR);
   float *QL = c->at<float>(L.QL), *TM = c->at<float>(L.TM), *Xc = c->at<float>(L.Xc);
   float *QR = c->at<float>(L.QR), *TN = c->at<float>(L.TN), *Xh = c->at<float>(L.Xh);
-  double *gp = c->at<double>(L.gram_part), *G = c->at<double>(L.G), *R = c->at<double>(L.R);
-  int* qs = c->at<int>(L.qr_status);
   HIPCHK(c, hipEventRecord(c->ev[0], st));
-  HIPCHK(c, launch_fill_i32(qs, 8, 0, st));
+  HIPCHK(c, launch_fill_i32(c->at<int>(L.qr_status), 16, 0, st));
   // test matrices (Sec 3)
   if (omega_L) HIPCHK(c, launch_copy2d(omL, L.KP, omega_L, k, n, k, st));
   else HIPCHK(c, launch_philox_normal(omL, n, k, L.KP, 3u, c->p.seed, st));
@@ -324,52 +368,63 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
       HIPCHK(c, launch_quant_fp8(X, ldx, m, n, c->at<int>(L.Ex), c->at<uint8_t>(L.Xq), L.ldq,
                                  c->at<uint8_t>(L.XqT), L.ldqt, st));
   }
-  auto XB = [&](const float* B, float* C) -> hipError_t {            // X B  (m x k')
-    return lp ? gemm_lowp(c, 0, B, C) : gemm(c, X, ldx, 0, B, C, m, n);
+  // The left and right range finders are independent: the right one runs on
+  // a second stream forked here and joined below, so that one chain's
+  // latency-bound orthonormalisations overlap the other's products.
+  HIPCHK(c, hipEventRecord(c->fork, st));
+  HIPCHK(c, hipStreamWaitEvent(c->st2, c->fork, 0));
+  const Chain cl = chain(c, 0), cr = chain(c, 1);
+  auto XB = [&](const Chain& ch, const float* B, float* C) -> hipError_t {            // X B  (m x k')
+    return lp ? gemm_lowp(c, ch, 0, B, C) : gemm(c, ch, X, ldx, 0, B, C, m, n);
   };
-  auto XtB = [&](const float* B, float* C) -> hipError_t {           // X^T B (n x k')
-    return lp ? gemm_lowp(c, 1, B, C) : gemm(c, X, ldx, 1, B, C, n, m);
+  auto XtB = [&](const Chain& ch, const float* B, float* C) -> hipError_t {           // X^T B (n x k')
+    return lp ? gemm_lowp(c, ch, 1, B, C) : gemm(c, ch, X, ldx, 1, B, C, n, m);
   };
+  auto ORTH = [&](const Chain& ch, float* Y, int64_t rows, bool final) -> hipError_t {
+    return orth(Y, L.KP, rows, k, ch.gp, ch.G, ch.R, ch.qs, ch.st, final);
+  };
+  const bool refine = lp && c->p.refine_fp32;
   // left range finder: Q_L = orth(X Omega_L); q x { Z = orth(X^T Q_L); Q_L = orth(X Z) };
   // only the last orthonormalisation of each side is a full CholeskyQR2
-  const bool refine = lp && c->p.refine_fp32;
-  HIPCHK(c, XB(omL, QL));
-  HIPCHK(c, orth(QL, L.KP, m, k, gp, G, R, qs, st, q == 0 && !refine));
+  HIPCHK(c, XB(cl, omL, QL));
+  HIPCHK(c, ORTH(cl, QL, m, q == 0 && !refine));
   for (int it = 0; it < q; ++it) {
-    HIPCHK(c, XtB(QL, TN));
-    HIPCHK(c, orth(TN, L.KP, n, k, gp, G, R, qs, st, false));
-    HIPCHK(c, XB(TN, QL));
-    HIPCHK(c, orth(QL, L.KP, m, k, gp, G, R, qs, st, it == q - 1 && !refine));
+    HIPCHK(c, XtB(cl, QL, TN));
+    HIPCHK(c, ORTH(cl, TN, n, false));
+    HIPCHK(c, XB(cl, TN, QL));
+    HIPCHK(c, ORTH(cl, QL, m, it == q - 1 && !refine));
   }
-  // right range finder on X^T with Omega_R
-  HIPCHK(c, XtB(omR, QR));
-  HIPCHK(c, orth(QR, L.KP, n, k, gp, G, R, qs, st, q == 0 && !refine));
+  // right range finder on X^T with Omega_R (second stream)
+  HIPCHK(c, XtB(cr, omR, QR));
+  HIPCHK(c, ORTH(cr, QR, n, q == 0 && !refine));
   for (int it = 0; it < q; ++it) {
-    HIPCHK(c, XB(QR, TM));
-    HIPCHK(c, orth(TM, L.KP, m, k, gp, G, R, qs, st, false));
-    HIPCHK(c, XtB(TM, QR));
-    HIPCHK(c, orth(QR, L.KP, n, k, gp, G, R, qs, st, it == q - 1 && !refine));
+    HIPCHK(c, XB(cr, QR, TM));
+    HIPCHK(c, ORTH(cr, TM, m, false));
+    HIPCHK(c, XtB(cr, TM, QR));
+    HIPCHK(c, ORTH(cr, QR, n, it == q - 1 && !refine));
   }
   // optional FP32 refinement: one power iteration per side on the exact X
   if (refine) {
-    HIPCHK(c, gemm(c, X, ldx, 1, QL, TN, n, m));
-    HIPCHK(c, orth(TN, L.KP, n, k, gp, G, R, qs, st, false));
-    HIPCHK(c, gemm(c, X, ldx, 0, TN, QL, m, n));
-    HIPCHK(c, orth(QL, L.KP, m, k, gp, G, R, qs, st, true));
-    HIPCHK(c, gemm(c, X, ldx, 0, QR, TM, m, n));
-    HIPCHK(c, orth(TM, L.KP, m, k, gp, G, R, qs, st, false));
-    HIPCHK(c, gemm(c, X, ldx, 1, TM, QR, n, m));
-    HIPCHK(c, orth(QR, L.KP, n, k, gp, G, R, qs, st, true));
+    HIPCHK(c, gemm(c, cl, X, ldx, 1, QL, TN, n, m));
+    HIPCHK(c, ORTH(cl, TN, n, false));
+    HIPCHK(c, gemm(c, cl, X, ldx, 0, TN, QL, m, n));
+    HIPCHK(c, ORTH(cl, QL, m, true));
+    HIPCHK(c, gemm(c, cr, X, ldx, 0, QR, TM, m, n));
+    HIPCHK(c, ORTH(cr, TM, m, false));
+    HIPCHK(c, gemm(c, cr, X, ldx, 1, TM, QR, n, m));
+    HIPCHK(c, ORTH(cr, QR, n, true));
   }
   // projected data (Sec 4), always FP32 on X: Xh = X^T Q_L (X-hat^T), Xc = X Q_R (X-check)
-  HIPCHK(c, gemm(c, X, ldx, 1, QL, Xh, n, m));
+  HIPCHK(c, gemm(c, cl, X, ldx, 1, QL, Xh, n, m));
   {   // Xc = X Q_R, with ||X||^2 in FP64 from the same pass (for the proxy residual)
     const int s = gemm_f32_pick_splits(m, k, n, 0);
     double* sqp = c->at<double>(L.xsq_part);
-    HIPCHK(c, launch_gemm_f32(X, ldx, 0, QR, L.KP, Xc, L.KP, m, k, n, s, c->at<float>(L.gemm_part), st, sqp));
+    HIPCHK(c, launch_gemm_f32(X, ldx, 0, QR, L.KP, Xc, L.KP, m, k, n, s, cr.gemm_part, cr.st, sqp));
     HIPCHK(c, launch_sum_partials_f64(sqp, gemm_f32_sq_parts(m, k, s), 1, c->at<double>(L.proxy_out) + 2,
-                                      nullptr, st));
+                                      nullptr, cr.st));
   }
+  HIPCHK(c, hipEventRecord(c->join, c->st2));
+  HIPCHK(c, hipStreamWaitEvent(st, c->join, 0));
   HIPCHK(c, hipEventRecord(c->ev[1], st));
   c->t_compress = true;
   c->compressed = true;
@@ -468,12 +523,12 @@ nmf_status nmf_residual(nmf_ctx* c, const float* X, int64_t ldx, double* rel_err
                             c->at<double>(L.res_out), c->at<unsigned>(L.counters) + 4, c->st));
   HIPCHK(c, hipEventRecord(c->ev[5], c->st));
   double h[2];
-  int qs[8];
+  int qs[16];
   HIPCHK(c, hipMemcpyAsync(h, c->at<double>(L.res_out), sizeof(h), hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipMemcpyAsync(qs, c->at<int>(L.qr_status), sizeof(qs), hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
   c->t_residual = true;
-  if (qs[1]) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
+  if (qs[1] || qs[9]) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
   *rel_err = (h[1] > 0) ? std::sqrt(h[0] / h[1]) : 0.0;
   if (!std::isfinite(h[0]) || !std::isfinite(h[1])) return fail(c, NMF_ENONFINITE, "non-finite residual");
   return NMF_OK;
@@ -641,7 +696,7 @@ nmf_status nmf_set_state(nmf_ctx* c, const float* QL, const float* QR, const flo
   HIPCHK(c, launch_copy2d(c->at<float>(L.QR), L.KP, QR, k, c->p.n, k, c->st));
   HIPCHK(c, launch_copy2d(c->at<float>(L.Xh), L.KP, Xh, k, c->p.n, k, c->st));
   HIPCHK(c, launch_copy2d(c->at<float>(L.Xc), L.KP, Xc, k, c->p.m, k, c->st));
-  HIPCHK(c, launch_fill_i32(c->at<int>(L.qr_status), 8, 0, c->st));
+  HIPCHK(c, launch_fill_i32(c->at<int>(L.qr_status), 16, 0, c->st));
   c->compressed = true;
   c->stepped = false;
   c->xsq_valid = false;
@@ -651,11 +706,11 @@ nmf_status nmf_set_state(nmf_ctx* c, const float* QL, const float* QR, const flo
 
 nmf_status nmf_sync(nmf_ctx* c, int32_t* shifted) {
   if (!c) return fail(c, NMF_EINVAL, "null context");
-  int qs[8];
+  int qs[16];
   HIPCHK(c, hipMemcpyAsync(qs, c->at<int>(c->L.qr_status), sizeof(qs), hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
-  if (shifted) *shifted = qs[2];
-  if (qs[1]) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
+  if (shifted) *shifted = qs[2] + qs[10];
+  if (qs[1] || qs[9]) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
   return NMF_OK;
 }
 
