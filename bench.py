@@ -12,13 +12,16 @@ tests/golden/make_oracle_errors.py, which calls only the oracle).
 
 Variants (same X, same cold factors):
   plain      FP32 range finder, cold start (the paper's method).
-  bf16_warm  BF16 range-finder products with FP32 accumulation, then the
-             learned warm start: the network's H rows on the compressed
-             columns, each kept only if it beats the cold row on the compressed
-             residual.  The step includes the alignment products, inference and
-             selection; it excludes training.
-  others     bf16 / fp8 (+ FP32 refinement) cold starts and fp32_warm, reported
-             alongside.
+  bf16_warm  BF16 range-finder products with FP32 accumulation (FP32
+             sketches), then the learned warm start: W from the reference
+             dictionary, H rows from the network on the compressed columns,
+             each kept only if it beats the cold row on the compressed
+             residual, then column-NNLS sweeps.  The step includes the
+             alignment products, inference, selection and sweeps; it excludes
+             training.
+  others     BF16 sketches (their error floor lies above eps at c2), bf16 /
+             fp8 (+ FP32 refinement) cold starts, fp32_warm and fp8_warm,
+             reported alongside.
 The network is trained before timing on pairs from new columns of the same
 generator (same basis W0, new coefficients): a reference fit on one new draw
 gives Q_train and W_ref; every pair is (Q_train^T x, NNLS row of x against
@@ -42,6 +45,8 @@ sys.path.insert(0, ROOT)
 GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_errors.json")
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# the headline variant: BF16 range finder, FP32 sketches, learned warm start
+HEADLINE = "bf16_warm"
 
 
 def parse():
@@ -211,11 +216,11 @@ def train_warm_start(torch, nmfrp, cfg, seed, args):
 
 
 def time_variant(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, prec, refine, warm, steps, warmup,
-                 label=""):
+                 label="", lps=0):
     from paper_1712_02248_amd import warmstart
     m, n, r, kp, q = cfg["m"], cfg["n"], cfg["r"], cfg["kp"], cfg["q"]
     max_iters = args.max_iters or cfg["iters"]
-    ctx = nmfrp.NMF(m, n, r, kp, q, seed=seed, prec=prec, refine_fp32=refine)
+    ctx = nmfrp.NMF(m, n, r, kp, q, seed=seed, prec=prec, refine_fp32=refine, lowp_sketches=lps)
 
     def step():
         ctx.compress(Xd)
@@ -418,27 +423,31 @@ def main():
     warm = (net, Q_train, W_ref, args.refine_sweeps)
     warm_net_only = (net, Q_train, W_ref, 0)
 
-    variants = [("plain", nmfrp.NMF_FP32, 0, None, args.steps, args.warmup),
-                ("bf16_warm", nmfrp.NMF_BF16, 0, warm, args.steps, args.warmup)]
+    # (name, prec, FP32 refinement, warm start, low-precision sketches, steps, warmup)
+    BF, F8, F32 = nmfrp.NMF_BF16, nmfrp.NMF_FP8_E4M3, nmfrp.NMF_FP32
+    variants = [("plain", F32, 0, None, 0, args.steps, args.warmup),
+                (HEADLINE, BF, 0, warm, 0, args.steps, args.warmup)]
     if not args.headline_only:
-        variants += [("bf16", nmfrp.NMF_BF16, 0, None, 3, 1),
-                     ("bf16_refine", nmfrp.NMF_BF16, 1, None, 3, 1),
-                     ("fp8_refine", nmfrp.NMF_FP8_E4M3, 1, None, 3, 1),
-                     ("fp8_refine_warm", nmfrp.NMF_FP8_E4M3, 1, warm, 3, 1),
-                     ("fp32_warm", nmfrp.NMF_FP32, 0, warm, 3, 1),
-                     ("bf16_warm_net_only", nmfrp.NMF_BF16, 0, warm_net_only, 3, 1),
-                     ("fp8_warm", nmfrp.NMF_FP8_E4M3, 0, warm, 3, 1)]
+        variants += [("bf16_warm_lowp_sketches", BF, 0, warm, 1, 3, 1),
+                     ("bf16", BF, 0, None, 0, 3, 1),
+                     ("bf16_lowp_sketches", BF, 0, None, 1, 3, 1),
+                     ("bf16_refine", BF, 1, None, 0, 3, 1),
+                     ("fp8_refine", F8, 1, None, 0, 3, 1),
+                     ("fp8_refine_warm", F8, 1, warm, 0, 3, 1),
+                     ("fp32_warm", F32, 0, warm, 0, 3, 1),
+                     ("bf16_warm_net_only", BF, 0, warm_net_only, 0, 3, 1),
+                     ("fp8_warm", F8, 0, warm, 0, 3, 1)]
     if args.variants:
         keep = args.variants.split(",")
         variants = [v for v in variants if v[0] in keep]
     out = {}
-    for vname, prec, refine, w, steps, warmup in variants:
+    for vname, prec, refine, w, lps, steps, warmup in variants:
         v = time_variant(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, prec, refine, w, steps, warmup,
-                         label=vname)
+                         label=vname, lps=lps)
         out[vname] = v
         log(f"[bench] {vname}: median {statistics.median(v['times']) * 1e3:.2f} ms, iters {v['iters']}, "
             f"e_init {v['e_init']:.4e}, e {v['e'][-1]:.6e}, rejected {v['rejected']}")
-    head = out.get("bf16_warm") or next(iter(out.values()))
+    head = out.get(HEADLINE) or next(iter(out.values()))
     plain = out.get("plain")
     total_head = sum(head["times"])
 

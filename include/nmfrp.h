@@ -65,6 +65,10 @@ typedef struct {
                             0 none, 1 with b_j <- b_j ||a_j|| (default), 2 literal */
   float alpha, beta;     /* sparsity / smoothness on B (Sec 4.1); 0, 0 = plain rule */
   uint64_t seed;         /* Philox4x32-10 key for device-drawn Omega and factors */
+  int32_t lowp_sketches; /* 1 (prec != FP32 only): the sketches Xh, Xc are products on
+                            the low-precision copy of X as well (extension); 0: FP32
+                            products on X */
+  int32_t reserved;      /* must be 0 */
 } nmf_params;
 
 /* ---------------------------------------------------------------- context */

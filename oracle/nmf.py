@@ -132,10 +132,11 @@ def quantize_data(X, fmt):
     return quant.e4m3_block_quantise(np.asarray(X, dtype=np.float32).astype(np.float64))[0]
 
 
-def compress_lowp(X, Omega_L, Omega_R, q, fmt, refine=False, orth=householder_q):
+def compress_lowp(X, Omega_L, Omega_R, q, fmt, refine=False, orth=householder_q, lowp_sketches=False):
     """Model of the low-precision compression: every range-finder product uses
     the quantised X and a quantised thin operand; optionally one FP32-exact
-    power iteration per side; the projected data always use the exact X."""
+    power iteration per side; the projected data use the exact X, or with
+    lowp_sketches the quantised X and quantised bases like the other products."""
     X = np.asarray(X, dtype=np.float64)
     Xq = quantize_data(X, fmt)
 
@@ -153,6 +154,8 @@ def compress_lowp(X, Omega_L, Omega_R, q, fmt, refine=False, orth=householder_q)
     if refine:
         QL = orth(X @ orth(X.T @ QL))
         QR = orth(X.T @ orth(X @ QR))
+    if lowp_sketches:
+        return QL, QR, prod(Xq.T, QL), prod(Xq, QR)
     return QL, QR, X.T @ QL, X @ QR
 
 
@@ -345,13 +348,13 @@ def gini(B):
 # ----------------------------------------------------------------------------
 
 def fasthals_rp(X, Omega_L, Omega_R, q, W0, H0t, iters, normalize=1, orth=householder_q,
-                record=False, fmt=None, refine=False, alpha=0.0, beta=0.0):
+                record=False, fmt=None, refine=False, alpha=0.0, beta=0.0, lowp_sketches=False):
     """Compress (exactly, or with the low-precision model when fmt is 'bf16' or
     'fp8'), then `iters` FastHALS-RP iterations.  Returns a dict."""
     if fmt is None:
         QL, QR, Xh, Xc = compress(X, Omega_L, Omega_R, q, orth)
     else:
-        QL, QR, Xh, Xc = compress_lowp(X, Omega_L, Omega_R, q, fmt, refine, orth)
+        QL, QR, Xh, Xc = compress_lowp(X, Omega_L, Omega_R, q, fmt, refine, orth, lowp_sketches)
     W = np.array(W0, dtype=np.float64)
     Ht = np.array(H0t, dtype=np.float64)
     hist = []

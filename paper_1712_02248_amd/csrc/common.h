@@ -42,11 +42,12 @@ int gemm_f32_pick_splits(int64_t M, int64_t N, int64_t K, int a_trans);
 
 // Low-precision copies of X and of the thin operand (quant.hip).  Xq is m x ldq,
 // XqT is n x ldqt; ldq, ldqt are multiples of 128 and the padding is zero.
+int quant_sq_parts(int64_t m, int64_t n, int64_t ldq, int64_t ldqt);
 hipError_t launch_quant_bf16(const float* X, int64_t ldx, int64_t m, int64_t n, uint16_t* Xq,
-                             int64_t ldq, uint16_t* XqT, int64_t ldqt, hipStream_t st);
+                             int64_t ldq, uint16_t* XqT, int64_t ldqt, hipStream_t st, double* sq_part = nullptr, double* sq_out = nullptr);
 // E: ceil(m/128) x ceil(n/128) tile exponents (row-major).
 hipError_t launch_quant_fp8(const float* X, int64_t ldx, int64_t m, int64_t n, int* E, uint8_t* Xq,
-                            int64_t ldq, uint8_t* XqT, int64_t ldqt, hipStream_t st);
+                            int64_t ldq, uint8_t* XqT, int64_t ldqt, hipStream_t st, double* sq_part = nullptr, double* sq_out = nullptr);
 hipError_t launch_prep_b_bf16(const float* B, int64_t ldb, int64_t K, int64_t N, uint16_t* Bt,
                               int64_t ldbt, hipStream_t st);
 // Ebt: ceil(K/128) exponents, one per 128-row block of B.

@@ -51,6 +51,11 @@ bool valid_params(const nmf_params* p, std::string* why) {
   if (p->normalize < 0 || p->normalize > 2) { *why = "normalize must be 0, 1 or 2"; return false; }
   if (p->n % 4) { *why = "n must be a multiple of 4"; return false; }
   if (p->alpha < 0 || p->beta < 0) { *why = "alpha, beta must be >= 0"; return false; }
+  if (p->lowp_sketches < 0 || p->lowp_sketches > 1 || (p->lowp_sketches && p->prec == NMF_FP32)) {
+    *why = "lowp_sketches must be 0, or 1 with a low-precision prec";
+    return false;
+  }
+  if (p->reserved != 0) { *why = "reserved must be 0"; return false; }
   return true;
 }
 
@@ -109,7 +114,11 @@ Layout make_layout(const nmf_params* p) {
   L.flags = pl.take(8 * sizeof(int));
   L.proxy_part = pl.take(2 * 256 * d);
   L.proxy_out = pl.take(3 * d);            // proxy sums, then ||X||^2 from compression
-  L.xsq_part = pl.take((size_t)gemm_f32_sq_parts(m, k, 64) * d);
+  {
+    const int64_t qp = quant_sq_parts(m, n, round_up(n, 128), round_up(m, 128));
+    const int64_t gp3 = gemm_f32_sq_parts(m, k, 64);
+    L.xsq_part = pl.take((size_t)(qp > gp3 ? qp : gp3) * d);
+  }
   L.Xq = L.XqT = L.Ex = L.Bt = L.Eb = L.Bt2 = L.Eb2 = 0;
   if (p->prec != NMF_FP32) {
     const size_t es = p->prec == NMF_BF16 ? 2 : 1;
@@ -360,13 +369,16 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
   else HIPCHK(c, launch_philox_normal(omR, m, k, L.KP, 4u, c->p.seed, st));
   // range-finder products: FP32 on X, or on its low-precision copy (extension)
   const bool lp = c->p.prec != NMF_FP32;
-  if (lp) {
+  const bool lps = lp && c->p.lowp_sketches;
+  if (lp) {   // with low-precision sketches, ||X||^2 comes from this (only FP32) pass over X
+    double* sqp = lps ? c->at<double>(L.xsq_part) : nullptr;
+    double* sqo = lps ? c->at<double>(L.proxy_out) + 2 : nullptr;
     if (c->p.prec == NMF_BF16)
       HIPCHK(c, launch_quant_bf16(X, ldx, m, n, c->at<uint16_t>(L.Xq), L.ldq, c->at<uint16_t>(L.XqT),
-                                  L.ldqt, st));
+                                  L.ldqt, st, sqp, sqo));
     else
       HIPCHK(c, launch_quant_fp8(X, ldx, m, n, c->at<int>(L.Ex), c->at<uint8_t>(L.Xq), L.ldq,
-                                 c->at<uint8_t>(L.XqT), L.ldqt, st));
+                                 c->at<uint8_t>(L.XqT), L.ldqt, st, sqp, sqo));
   }
   // The left and right range finders are independent: the right one runs on
   // a second stream forked here and joined below, so that one chain's
@@ -414,7 +426,12 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
     HIPCHK(c, gemm(c, cr, X, ldx, 1, TM, QR, n, m));
     HIPCHK(c, ORTH(cr, QR, n, true));
   }
-  // projected data (Sec 4), always FP32 on X: Xh = X^T Q_L (X-hat^T), Xc = X Q_R (X-check)
+  // projected data (Sec 4): Xh = X^T Q_L (X-hat^T), Xc = X Q_R (X-check); FP32 on X,
+  // or on the low-precision copy like the range finder (lowp_sketches)
+  if (lps) {
+    HIPCHK(c, XtB(cl, QL, Xh));
+    HIPCHK(c, XB(cr, QR, Xc));
+  } else {
   HIPCHK(c, gemm(c, cl, X, ldx, 1, QL, Xh, n, m));
   {   // Xc = X Q_R, with ||X||^2 in FP64 from the same pass (for the proxy residual)
     const int s = gemm_f32_pick_splits(m, k, n, 0);
@@ -422,6 +439,7 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
     HIPCHK(c, launch_gemm_f32(X, ldx, 0, QR, L.KP, Xc, L.KP, m, k, n, s, cr.gemm_part, cr.st, sqp));
     HIPCHK(c, launch_sum_partials_f64(sqp, gemm_f32_sq_parts(m, k, s), 1, c->at<double>(L.proxy_out) + 2,
                                       nullptr, cr.st));
+  }
   }
   HIPCHK(c, hipEventRecord(c->join, c->st2));
   HIPCHK(c, hipStreamWaitEvent(st, c->join, 0));

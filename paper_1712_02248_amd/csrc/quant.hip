@@ -48,22 +48,41 @@ NMF_DEV uint8_t e4m3_rne(float y) {
   return (uint8_t)(sign | (E << 3) | mant);
 }
 
+
+// FP64 block sum of a per-thread value into sq[blockIdx.x + gridDim.x blockIdx.y]
+// (fixed order): the sum of squares of the elements of X a block reads.
+NMF_DEV void block_sq(double v, double* __restrict__ sq) {
+  __shared__ double red[256];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sq[blockIdx.x + (int64_t)gridDim.x * blockIdx.y] = red[0];
+}
+
 constexpr int QT = 64;   // transpose tile
 
 // BF16 copy and transposed copy, 64 x 64 tiles through LDS.
 __global__ void __launch_bounds__(256)
 quant_bf16_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
-                  uint16_t* __restrict__ Xq, int64_t ldq, uint16_t* __restrict__ XqT, int64_t ldqt) {
+                  uint16_t* __restrict__ Xq, int64_t ldq, uint16_t* __restrict__ XqT, int64_t ldqt,
+                  double* __restrict__ sq) {
   __shared__ uint16_t T[QT][QT + 2];
   const int64_t i0 = (int64_t)blockIdx.y * QT, j0 = (int64_t)blockIdx.x * QT;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   uint16_t v[16];
+  double ssq = 0.0;
 #pragma unroll
   for (int p = 0; p < 16; ++p) {
     const int ii = ty + 4 * p;
     const int64_t gi = i0 + ii, gj = j0 + tx;
-    v[p] = (gi < m && gj < n) ? bf16_rne(X[gi * ldx + gj]) : (uint16_t)0;
+    const float x = (gi < m && gj < n) ? X[gi * ldx + gj] : 0.f;
+    ssq = fma((double)x, (double)x, ssq);
+    v[p] = bf16_rne(x);
   }
+  if (sq) block_sq(ssq, sq);
 #pragma unroll
   for (int p = 0; p < 16; ++p) {
     const int ii = ty + 4 * p;
@@ -87,7 +106,8 @@ quant_bf16_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n
 constexpr int QV = 128;
 __global__ void __launch_bounds__(256)
 quant_bf16_v4_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
-                     uint16_t* __restrict__ Xq, int64_t ldq, uint16_t* __restrict__ XqT, int64_t ldqt) {
+                     uint16_t* __restrict__ Xq, int64_t ldq, uint16_t* __restrict__ XqT, int64_t ldqt,
+                     double* __restrict__ sq) {
   __shared__ uint32_t T[QV][QV / 2 + 1];          // T[j][i/2] = (bf16 x[i][j], bf16 x[i+1][j])
   const int64_t i0 = (int64_t)blockIdx.y * QV, j0 = (int64_t)blockIdx.x * QV;
   const int l = threadIdx.x & 31, rp = threadIdx.x >> 5;
@@ -102,6 +122,14 @@ quant_bf16_v4_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_
       f32x4 z = {0.f, 0.f, 0.f, 0.f};
       v[2 * p + h] = (colok && gi < m) ? *(const f32x4*)(X + gi * ldx + gj) : z;
     }
+  }
+  if (sq) {
+    double ssq = 0.0;
+#pragma unroll
+    for (int p = 0; p < 16; ++p)
+#pragma unroll
+      for (int d = 0; d < 4; ++d) ssq = fma((double)v[p][d], (double)v[p][d], ssq);
+    block_sq(ssq, sq);
   }
 #pragma unroll
   for (int p = 0; p < 8; ++p) {
@@ -176,19 +204,23 @@ tile_exp_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n, 
 __global__ void __launch_bounds__(256)
 quant_fp8_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
                  const int* __restrict__ E, int tiles_n, uint8_t* __restrict__ Xq, int64_t ldq,
-                 uint8_t* __restrict__ XqT, int64_t ldqt) {
+                 uint8_t* __restrict__ XqT, int64_t ldqt, double* __restrict__ sq) {
   __shared__ uint8_t T[QT][QT + 4];
   const int64_t i0 = (int64_t)blockIdx.y * QT, j0 = (int64_t)blockIdx.x * QT;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int e = E[(i0 / 128) * tiles_n + (j0 / 128)];    // 64-tiles nest inside 128-tiles
   const float s = ldexpf(1.0f, -e);
   uint8_t v[16];
+  double ssq = 0.0;
 #pragma unroll
   for (int p = 0; p < 16; ++p) {
     const int ii = ty + 4 * p;
     const int64_t gi = i0 + ii, gj = j0 + tx;
-    v[p] = (gi < m && gj < n) ? e4m3_rne(X[gi * ldx + gj] * s) : (uint8_t)0;
+    const float x = (gi < m && gj < n) ? X[gi * ldx + gj] : 0.f;
+    ssq = fma((double)x, (double)x, ssq);
+    v[p] = (gi < m && gj < n) ? e4m3_rne(x * s) : (uint8_t)0;
   }
+  if (sq) block_sq(ssq, sq);
 #pragma unroll
   for (int p = 0; p < 16; ++p) {
     const int ii = ty + 4 * p;
@@ -270,29 +302,44 @@ unsigned grid1(int64_t total) {
 
 }  // namespace
 
+int quant_sq_parts(int64_t m, int64_t n, int64_t ldq, int64_t ldqt) {
+  (void)m;
+  (void)n;
+  return (int)(ceil_div(ldq, QT) * ceil_div(ldqt, QT));   // the larger (64 x 64 tile) grid
+}
+
 hipError_t launch_quant_bf16(const float* X, int64_t ldx, int64_t m, int64_t n, uint16_t* Xq,
-                             int64_t ldq, uint16_t* XqT, int64_t ldqt, hipStream_t st) {
+                             int64_t ldq, uint16_t* XqT, int64_t ldqt, hipStream_t st, double* sq_part,
+                             double* sq_out) {
   const bool vec = n % 4 == 0 && ldx % 4 == 0 && ((uintptr_t)X & 15) == 0 && ((uintptr_t)Xq & 7) == 0 &&
                    ((uintptr_t)XqT & 7) == 0 && ldq % QV == 0 && ldqt % QV == 0;
+  dim3 grid;
+  double* sq = sq_out ? sq_part : nullptr;
   if (vec) {
-    dim3 grid((unsigned)(ldq / QV), (unsigned)(ldqt / QV));
-    hipLaunchKernelGGL(quant_bf16_v4_kernel, grid, dim3(256), 0, st, X, ldx, m, n, Xq, ldq, XqT, ldqt);
+    grid = dim3((unsigned)(ldq / QV), (unsigned)(ldqt / QV));
+    hipLaunchKernelGGL(quant_bf16_v4_kernel, grid, dim3(256), 0, st, X, ldx, m, n, Xq, ldq, XqT, ldqt, sq);
   } else {
-    dim3 grid((unsigned)ceil_div(ldq, QT), (unsigned)ceil_div(ldqt, QT));
-    hipLaunchKernelGGL(quant_bf16_kernel, grid, dim3(256), 0, st, X, ldx, m, n, Xq, ldq, XqT, ldqt);
+    grid = dim3((unsigned)ceil_div(ldq, QT), (unsigned)ceil_div(ldqt, QT));
+    hipLaunchKernelGGL(quant_bf16_kernel, grid, dim3(256), 0, st, X, ldx, m, n, Xq, ldq, XqT, ldqt, sq);
   }
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !sq_out) return e;
+  return launch_sum_partials_f64(sq_part, (int)(grid.x * grid.y), 1, sq_out, nullptr, st);
 }
 
 hipError_t launch_quant_fp8(const float* X, int64_t ldx, int64_t m, int64_t n, int* E, uint8_t* Xq,
-                            int64_t ldq, uint8_t* XqT, int64_t ldqt, hipStream_t st) {
+                            int64_t ldq, uint8_t* XqT, int64_t ldqt, hipStream_t st, double* sq_part,
+                            double* sq_out) {
   const int tn = (int)ceil_div(n, 128), tm = (int)ceil_div(m, 128);
   hipLaunchKernelGGL(tile_exp_kernel, dim3(tn, tm), dim3(256), 0, st, X, ldx, m, n, E, tn);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   dim3 grid((unsigned)ceil_div(ldq, QT), (unsigned)ceil_div(ldqt, QT));
-  hipLaunchKernelGGL(quant_fp8_kernel, grid, dim3(256), 0, st, X, ldx, m, n, E, tn, Xq, ldq, XqT, ldqt);
-  return hipGetLastError();
+  hipLaunchKernelGGL(quant_fp8_kernel, grid, dim3(256), 0, st, X, ldx, m, n, E, tn, Xq, ldq, XqT, ldqt,
+                     sq_out ? sq_part : nullptr);
+  e = hipGetLastError();
+  if (e != hipSuccess || !sq_out) return e;
+  return launch_sum_partials_f64(sq_part, (int)(grid.x * grid.y), 1, sq_out, nullptr, st);
 }
 
 hipError_t launch_prep_b_bf16(const float* B, int64_t ldb, int64_t K, int64_t N, uint16_t* Bt,

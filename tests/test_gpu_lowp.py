@@ -103,14 +103,15 @@ def test_prepared_product_matches_full_product(lib, fmt, m, n, k, side):
     assert np.array_equal(acc, full)
 
 
-@pytest.mark.parametrize("fmt,refine", [("bf16", 0), ("bf16", 1), ("fp8", 0), ("fp8", 1)])
-def test_lowp_compression_runs(lib, fmt, refine):
+@pytest.mark.parametrize("fmt,refine,lps", [("bf16", 0, 0), ("bf16", 1, 0), ("fp8", 0, 0), ("fp8", 1, 0),
+                                            ("bf16", 0, 1)])
+def test_lowp_compression_runs(lib, fmt, refine, lps):
     """Whole run with low-precision range-finder products: the error after the
     iterations is compared with the oracle's model of the same rounding (R_q)
     and with the exact FP64 run (R_true); both gaps are printed.  Compared near
     convergence (400 iterations): early iterates depend sensitively on the
     basis of the sketch, which the two sides round differently."""
-    print(f"lowp run {fmt} refine={refine}", flush=True)
+    print(f"lowp run {fmt} refine={refine} lowp_sketches={lps}", flush=True)
     m, n, r, kp, q, iters = 2000, 512, 10, 20, 2, 400
     seed = 4242
     X = datagen.planted_parts(m, n, r, seed)[0]
@@ -118,13 +119,18 @@ def test_lowp_compression_runs(lib, fmt, refine):
     OR = datagen.gaussian(m, kp, seed, datagen.S_OMEGA_R)
     W0, H0 = datagen.init_factors(X.mean(), m, n, r, seed)
     prec = lib.NMF_BF16 if fmt == "bf16" else lib.NMF_FP8_E4M3
-    ctx = lib.NMF(m, n, r, kp, q, seed=seed, prec=prec, refine_fp32=refine)
+    ctx = lib.NMF(m, n, r, kp, q, seed=seed, prec=prec, refine_fp32=refine, lowp_sketches=lps)
     Xd = torch.from_numpy(X).cuda()
     ctx.compress(Xd, torch.from_numpy(OL).cuda(), torch.from_numpy(OR).cuda())
     ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
     ctx.step(iters)
+    ep = ctx.proxy_residual()            # ||X||^2 from the quantiser when lps, else the sketch pass
     e = ctx.residual(Xd)
-    Rq = onmf.fasthals_rp(X, OL, OR, q, W0, H0, iters, fmt=fmt, refine=bool(refine))["e"]
+    ref = onmf.fasthals_rp(X, OL, OR, q, W0, H0, iters, fmt=fmt, refine=bool(refine), lowp_sketches=bool(lps))
+    Rq = ref["e"]
+    nx2 = float(np.sum(X.astype(np.float64) ** 2))
+    ep_ref = onmf.proxy_rel_error(nx2, ref["Xh"], ref["QL"].T @ ref["W"], ref["Ht"])
+    assert abs(ep - ep_ref) <= 1e-4
     Rt = onmf.fasthals_rp(X, OL, OR, q, W0, H0, iters)["e"]
     print(f"  e_gpu={e:.6e} R_q={Rq:.6e} R_true={Rt:.6e} |gpu-Rq|={abs(e - Rq):.2e} |gpu-Rtrue|={abs(e - Rt):.2e}",
           flush=True)
