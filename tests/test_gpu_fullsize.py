@@ -1,0 +1,84 @@
+"""Parity at the benchmark's full size: c2 (X 65536 x 4096, r = 32, k' = 64,
+q = 2, 500 iterations), the device-drawn test matrices and the launch
+configuration bench.py times, against the FP64 oracle's stored errors
+(tests/golden/oracle_errors.json, written by make_oracle_errors.py from the
+oracle alone) at the stored checkpoints, plus size-independent properties of
+the sketches (GPU)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import datagen
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_errors.json")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_1712_02248_amd import nmfrp
+    nmfrp.load()
+    return nmfrp
+
+
+def test_c2_full_size_errors_match_oracle(lib):
+    print("c2 full size: generating X", flush=True)
+    name = "c2"
+    c = datagen.CONFIGS[name]
+    m, n, r, kp, q, iters = c["m"], c["n"], c["r"], c["kp"], c["q"], c["iters"]
+    seed = datagen.cfg_seed(name)
+    ref = json.load(open(GOLDEN))[name]
+    X = datagen.make_x(name)
+    W0, H0 = datagen.init_factors(X.mean(), m, n, r, seed)
+    Xd = torch.from_numpy(X).cuda()
+    ctx = lib.NMF(m, n, r, kp, q, seed=seed)
+    ctx.compress(Xd)                       # Omega from the device Philox, as in the benchmark
+    ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
+    assert ctx.sync() == 0
+    QL, QR, _, _ = ctx.state()
+    for Q in (QL, QR):
+        Qd = Q.double()
+        assert (Qd.T @ Qd - torch.eye(kp, dtype=torch.float64, device=Qd.device)).abs().max().item() < 2e-6
+    done = 0
+    checked = 0
+    for it in sorted(int(k) for k in ref["curve"]):
+        if it > iters:
+            continue
+        ctx.step(it - done)
+        done = it
+        e = ctx.residual(Xd)
+        e_ref = ref["curve"][str(it)]
+        print(f"  it={it:4d} e_gpu={e:.8e} e_oracle={e_ref:.8e} diff={abs(e - e_ref):.2e}", flush=True)
+        assert abs(e - e_ref) <= 1e-4, it
+        checked += 1
+    assert checked >= 5
+    Wg, Hg = ctx.factors()
+    assert (Wg >= 0).all().item() and (Hg >= 0).all().item()
+
+
+@pytest.mark.parametrize("prec_name,refine", [("bf16", 0), ("fp8", 1)])
+def test_c2_full_size_low_precision_within_gate_of_oracle(lib, prec_name, refine):
+    """The low-precision range finders at full size end within the 1e-4 gate of
+    the exact FP64 oracle's error after the configured 500 iterations."""
+    print(f"c2 full size {prec_name} refine={refine}", flush=True)
+    name = "c2"
+    c = datagen.CONFIGS[name]
+    m, n, r, kp, q, iters = c["m"], c["n"], c["r"], c["kp"], c["q"], c["iters"]
+    seed = datagen.cfg_seed(name)
+    ref = json.load(open(GOLDEN))[name]
+    X = datagen.make_x(name)
+    W0, H0 = datagen.init_factors(X.mean(), m, n, r, seed)
+    Xd = torch.from_numpy(X).cuda()
+    prec = lib.NMF_BF16 if prec_name == "bf16" else lib.NMF_FP8_E4M3
+    ctx = lib.NMF(m, n, r, kp, q, seed=seed, prec=prec, refine_fp32=refine)
+    ctx.compress(Xd)
+    ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
+    ctx.step(iters)
+    e = ctx.residual(Xd)
+    print(f"  e_gpu={e:.8e} e_oracle(FP64, exact X)={ref['e']:.8e} diff={abs(e - ref['e']):.2e}", flush=True)
+    assert abs(e - ref["e"]) <= 1e-4
