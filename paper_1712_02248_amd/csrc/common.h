@@ -70,6 +70,10 @@ hipError_t launch_gemm_fp8_nt(const uint8_t* A, int64_t lda, const int* EA, int6
 hipError_t launch_gram_f64(const float* Y, int64_t ldy, int64_t rows, int k, double* part,
                            int splits, double* G, const int* skip_flag, hipStream_t st);
 int gram_pick_splits(int64_t rows, int k);
+// C (ka x kb, row-major FP32) = A^T B over `rows` rows, FP64 accumulation (ka, kb <= the
+// Gram's k; part: splits x ka x kb doubles; C64: ka x kb doubles).
+hipError_t launch_atb_f32out(const float* A, int64_t lda, int ka, const float* B, int64_t ldb, int kb,
+                             int64_t rows, double* part, int splits, double* C64, float* C, hipStream_t st);
 hipError_t launch_cholesky(const double* G, int k, int64_t rows, double* Rinv, int* status,
                            int attempt, hipStream_t st);
 hipError_t launch_apply_rinv(float* Y, int64_t ldy, int64_t rows, int k, const double* Rinv,

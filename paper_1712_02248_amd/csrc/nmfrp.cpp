@@ -32,6 +32,7 @@ struct Layout {
   size_t gemm_part2, gram_part2, G2, R2;             // chain 1 (right range finder); status at qr_status + 8
   size_t hs_part, acc_w, acc_h, counters, Hc, GH, Wh, GW, scale_w;
   size_t res_part, res_out, flags, proxy_part, proxy_out, xsq_part;
+  size_t alignM, whref;               // warm start: Q_train^T Q_L (k' x k'), Q_L^T W_ref (k' x r)
   int64_t ldq, ldqt;                 // low-precision copies of X: m x ldq and n x ldqt
   size_t Xq, XqT, Ex, Bt, Eb, Bt2, Eb2;
   size_t total;
@@ -112,6 +113,8 @@ Layout make_layout(const nmf_params* p) {
   L.res_part = pl.take(2 * (size_t)residual_blocks(m, n) * d);
   L.res_out = pl.take(2 * d);
   L.flags = pl.take(8 * sizeof(int));
+  L.alignM = pl.take(L.KP * L.KP * f);
+  L.whref = pl.take(L.KP * r * f);
   L.proxy_part = pl.take(2 * 256 * d);
   L.proxy_out = pl.take(3 * d);            // proxy sums, then ||X||^2 from compression
   {
@@ -469,9 +472,11 @@ nmf_status nmf_init(nmf_ctx* c, const float* W0, const float* Ht0, float init_sc
   return NMF_OK;
 }
 
-nmf_status nmf_init_learned(nmf_ctx* c, nmf_mlp* net, const float* align_M, const float* Wh_ref,
-                            const float* W0, const float* Ht_cold, float init_scale, int32_t refine_sweeps,
-                            int64_t* n_rejected) {
+namespace {
+
+nmf_status init_learned_impl(nmf_ctx* c, nmf_mlp* net, const float* align_M, const float* Wh_ref,
+                             const float* W0, int64_t ldw0, const float* Ht_cold, float init_scale,
+                             int32_t refine_sweeps, int64_t* n_rejected) {
   if (!c) return fail(c, NMF_EINVAL, "null context");
   if (!net || !Wh_ref) return fail(c, NMF_EINVAL, "null network or Wh_ref");
   if (refine_sweeps < 0) return fail(c, NMF_EINVAL, "refine_sweeps must be >= 0");
@@ -506,7 +511,12 @@ nmf_status nmf_init_learned(nmf_ctx* c, nmf_mlp* net, const float* align_M, cons
   if (refine_sweeps > 0)
     HIPCHK(c, launch_nnls_rows(c->at<float>(L.Xh), L.KP, (int)n, k, Wh_ref, r, refine_sweeps, 1, Ht, r, c->st));
   // 5. W as in nmf_init; the first update is the W half-step
-  nmf_status s = nmf_init(c, W0, Ht, init_scale);
+  const float* W0c = W0;
+  if (W0 && ldw0 != r) {   // nmf_init copies W0 with leading dimension r
+    HIPCHK(c, launch_copy2d(c->at<float>(L.W), r, W0, ldw0, c->p.m, r, c->st));
+    W0c = c->at<float>(L.W);
+  }
+  nmf_status s = nmf_init(c, W0c, Ht, init_scale);
   if (s != NMF_OK) return s;
   if (n_rejected) {
     long long h = 0;
@@ -515,6 +525,36 @@ nmf_status nmf_init_learned(nmf_ctx* c, nmf_mlp* net, const float* align_M, cons
     *n_rejected = h;
   }
   return NMF_OK;
+}
+
+}  // namespace
+
+nmf_status nmf_init_learned(nmf_ctx* c, nmf_mlp* net, const float* align_M, const float* Wh_ref,
+                            const float* W0, const float* Ht_cold, float init_scale, int32_t refine_sweeps,
+                            int64_t* n_rejected) {
+  return init_learned_impl(c, net, align_M, Wh_ref, W0, c ? c->p.r : 0, Ht_cold, init_scale, refine_sweeps,
+                           n_rejected);
+}
+
+nmf_status nmf_init_learned_ref(nmf_ctx* c, nmf_mlp* net, const float* Q_train, int64_t ldq, const float* W_ref,
+                                int64_t ldw, const float* Ht_cold, float init_scale, int32_t refine_sweeps,
+                                int64_t* n_rejected) {
+  if (!c) return fail(c, NMF_EINVAL, "null context");
+  if (!Q_train || !W_ref) return fail(c, NMF_EINVAL, "null Q_train or W_ref");
+  const int k = c->p.k_sketch, r = c->p.r;
+  if (ldq < k || ldw < r) return fail(c, NMF_EINVAL, "leading dimension too small");
+  if (!c->compressed) return fail(c, NMF_ESTATE, "init needs the sketches: call nmf_compress or nmf_set_state first");
+  Layout& L = c->L;
+  const int64_t m = c->p.m;
+  const int splits = gram_pick_splits(m, k);
+  float* M = c->at<float>(L.alignM);
+  float* Wh = c->at<float>(L.whref);
+  double* part = c->at<double>(L.gram_part);
+  double* C64 = c->at<double>(L.G);
+  // M = Q_train^T Q_L (k' x k'), Wh_ref = Q_L^T W_ref (k' x r), FP64 sums over the m rows
+  HIPCHK(c, launch_atb_f32out(Q_train, ldq, k, c->at<float>(L.QL), L.KP, k, m, part, splits, C64, M, c->st));
+  HIPCHK(c, launch_atb_f32out(c->at<float>(L.QL), L.KP, k, W_ref, ldw, r, m, part, splits, C64, Wh, c->st));
+  return init_learned_impl(c, net, M, Wh, W_ref, ldw, Ht_cold, init_scale, refine_sweeps, n_rejected);
 }
 
 nmf_status nmf_step(nmf_ctx* c, int32_t iters) {

@@ -27,13 +27,20 @@ constexpr int GPT = GROWS * GT / 256;   // staged elements per thread
 // chunk are issued before the MFMAs of the current one.
 __global__ void __launch_bounds__(256)
 gram_f64_kernel(const float* __restrict__ Y, int64_t ldy, int64_t rows, int k, int64_t rchunk,
-                double* __restrict__ part, const int* __restrict__ skip_flag) {
+                double* __restrict__ part, const int* __restrict__ skip_flag,
+                const float* __restrict__ Yb, int64_t ldb, int kb) {
+  // Yb == NULL: the Gram Y^T Y (k x k).  Otherwise the cross product Y^T Yb
+  // (k x kb) over the same rows, partials of k x kb.
   if (skip_flag && skip_flag[0] == 0) return;
   __shared__ float Yi[GROWS][GT + 1];
   __shared__ float Yj[GROWS][GT + 1];
-  const int nb = (k + GT - 1) / GT;
-  const int bi = blockIdx.x / nb, bj = blockIdx.x % nb;
-  const bool diag = (bi == bj);
+  const bool cross = Yb != nullptr;
+  const int kc = cross ? kb : k;                     // columns of the right operand
+  const int nbj = (kc + GT - 1) / GT;
+  const int bi = blockIdx.x / nbj, bj = blockIdx.x % nbj;
+  const bool diag = !cross && (bi == bj);
+  const float* B = cross ? Yb : Y;
+  const int64_t ldbb = cross ? ldb : ldy;
   const int64_t r0 = (int64_t)blockIdx.y * rchunk;
   const int64_t r1 = (r0 + rchunk < rows) ? r0 + rchunk : rows;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -49,7 +56,7 @@ gram_f64_kernel(const float* __restrict__ Y, int64_t ldy, int64_t rows, int k, i
       const int64_t gr = c0 + rr;
       const int gi = bi * GT + cc, gj = bj * GT + cc;
       vi[p] = (gr < r1 && gi < k) ? Y[gr * ldy + gi] : 0.f;
-      if (!diag) vj[p] = (gr < r1 && gj < k) ? Y[gr * ldy + gj] : 0.f;
+      if (!diag) vj[p] = (gr < r1 && gj < kc) ? B[gr * ldbb + gj] : 0.f;
     }
   };
   if (r0 < r1) load(r0);
@@ -75,14 +82,14 @@ gram_f64_kernel(const float* __restrict__ Y, int64_t ldy, int64_t rows, int k, i
     }
     __syncthreads();
   }
-  double* P = part + (int64_t)blockIdx.y * k * k;
+  double* P = part + (int64_t)blockIdx.y * k * kc;
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = bi * GT + wave * 16 + 4 * q + (lane >> 4);
       const int j = bj * GT + t * 16 + (lane & 15);
-      if (i < k && j < k) P[(int64_t)i * k + j] = acc[t][q];
+      if (i < k && j < kc) P[(int64_t)i * kc + j] = acc[t][q];
     }
 }
 
@@ -327,10 +334,32 @@ hipError_t launch_gram_f64(const float* Y, int64_t ldy, int64_t rows, int k, dou
   const int nb = (k + GT - 1) / GT;
   const int64_t rchunk = round_up(ceil_div(rows, splits), GROWS);
   hipLaunchKernelGGL(gram_f64_kernel, dim3(nb * nb, splits), dim3(256), 0, st, Y, ldy, rows, k,
-                     rchunk, part, skip_flag);
+                     rchunk, part, skip_flag, nullptr, 0, 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_sum_partials_f64(part, splits, (int64_t)k * k, G, skip_flag, st);
+}
+
+namespace {
+__global__ void __launch_bounds__(256)
+f64_to_f32_kernel(const double* __restrict__ a, float* __restrict__ b, int64_t count) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256)
+    b[e] = (float)a[e];
+}
+}  // namespace
+
+hipError_t launch_atb_f32out(const float* A, int64_t lda, int ka, const float* B, int64_t ldb, int kb,
+                             int64_t rows, double* part, int splits, double* C64, float* C, hipStream_t st) {
+  const int nbi = (ka + GT - 1) / GT, nbj = (kb + GT - 1) / GT;
+  const int64_t rchunk = round_up(ceil_div(rows, splits), GROWS);
+  hipLaunchKernelGGL(gram_f64_kernel, dim3(nbi * nbj, splits), dim3(256), 0, st, A, lda, rows, ka, rchunk, part,
+                     nullptr, B, ldb, kb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = launch_sum_partials_f64(part, splits, (int64_t)ka * kb, C64, nullptr, st))) return e;
+  const int64_t cnt = (int64_t)ka * kb;
+  hipLaunchKernelGGL(f64_to_f32_kernel, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st, C64, C, cnt);
+  return hipGetLastError();
 }
 
 hipError_t launch_cholesky(const double* G, int k, int64_t rows, double* Rinv, int* status,

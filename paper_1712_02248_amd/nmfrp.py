@@ -77,6 +77,8 @@ _SIGS = {
     "nmf_nnls_rows": (c_i32, [c_vp, c_i64, c_i64, c_i32, c_vp, c_i32, c_i32, c_i32, c_vp, c_i64, c_vp]),
     "nmf_init_learned": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_float, c_i32,
                                  ctypes.POINTER(c_i64)]),
+    "nmf_init_learned_ref": (c_i32, [c_vp, c_vp, c_vp, c_i64, c_vp, c_i64, c_vp, ctypes.c_float, c_i32,
+                                     ctypes.POINTER(c_i64)]),
 }
 
 _lib = None
@@ -247,6 +249,20 @@ class NMF:
         self._c(load().nmf_init_learned(self.h, net.h, _ptr(align_M), _ptr(Wh_ref), _ptr(W0), _ptr(Ht_cold),
                                         float(init_scale), int(refine_sweeps),
                                         ctypes.byref(nrej) if count else None))
+        return nrej.value if count else None
+
+    def init_learned_ref(self, net, Q_train, W_ref, Ht_cold=None, init_scale=1.0, refine_sweeps=0, count=True):
+        """Warm start from the reference fit (Q_train m x k', W_ref m x r): the
+        library forms Q_train^T Q_L and Q_L^T W_ref itself; W = W_ref."""
+        if Q_train.dtype != torch.float32 or Q_train.shape != (self.m, self.kp) or Q_train.stride(1) != 1:
+            raise ValueError("Q_train: float32 m x k' with unit column stride")
+        if W_ref.dtype != torch.float32 or W_ref.shape != (self.m, self.r) or W_ref.stride(1) != 1:
+            raise ValueError("W_ref: float32 m x r with unit column stride")
+        _f32(Ht_cold, (self.n, self.r), "Ht_cold")
+        nrej = ctypes.c_int64(-1)
+        self._c(load().nmf_init_learned_ref(self.h, net.h, _ptr(Q_train), Q_train.stride(0), _ptr(W_ref),
+                                            W_ref.stride(0), _ptr(Ht_cold), float(init_scale), int(refine_sweeps),
+                                            ctypes.byref(nrej) if count else None))
         return nrej.value if count else None
 
     def sync(self):

@@ -46,6 +46,9 @@ def warm_init(ctx, net, Q_train, W_ref, Ht_cold=None, W0=None, init_scale=1.0, r
     (default: the dictionary W_ref), H from the net with per-row rejection to
     Ht_cold, then refine_sweeps column-NNLS sweeps against Q_L^T W_ref.
     Returns the number of cold rows kept (None unless count)."""
+    if W0 is None:   # the alignment products are formed inside the library
+        return ctx.init_learned_ref(net, Q_train, W_ref, Ht_cold=Ht_cold, init_scale=init_scale,
+                                    refine_sweeps=refine_sweeps, count=count)
     QL = ctx.left_basis()
     M = nmfrp.gemm(Q_train, QL, a_trans=True)           # Q_train^T Q_L, k' x k'
     Wh_ref = compressed_factor(QL, W_ref)                # Q_L^T W_ref, k' x r

@@ -218,6 +218,19 @@ def test_init_learned_selection_matches_oracle(lib):
     assert np.max((np.abs(Hr - Href) / (np.abs(Href).max(axis=1, keepdims=True) + 1e-30))[clear]) <= 1e-4
     rho_r = np.sum((Xh - Hr @ Wh.T) ** 2, 1)
     assert np.all(rho_r <= np.minimum(rho_n, rho_c) * (1 + 1e-4))    # never worse than cold
+    # the same from the reference fit itself (alignment products formed inside the library)
+    ctx.compress(dev(X), dev(OL), dev(OR))
+    nrej2 = ctx.init_learned_ref(net, dev(G), dev(Wref), Ht_cold=dev(Hcold))
+    Wg2, Hg2 = (t.cpu().numpy().astype(np.float64) for t in ctx.factors())
+    assert np.array_equal(Wg2, Wref.astype(np.float32).astype(np.float64))
+    assert np.array_equal(np.all(Hg2 == Hcold, axis=1)[clear], rej[clear])
+    assert abs(nrej2 - rej.sum()) <= np.sum(~clear)
+    assert np.max((np.abs(Hg2 - Hsel) / scale)[clear]) <= 1e-4
+    with pytest.raises(ValueError):
+        ctx.init_learned_ref(net, dev(G)[:, :kp - 1].contiguous(), dev(Wref))   # wrong shape (binding)
+    fresh = lib.NMF(m, n, r, kp, q, seed=7)
+    with pytest.raises(lib.NmfError):
+        fresh.init_learned_ref(net, dev(G), dev(Wref))                         # not compressed (library)
 
 
 def test_init_learned_rejects_bad_arguments(lib):
