@@ -6,7 +6,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
+#include <vector>
 
 #include "../../include/nmfrp.h"
 #include "common.h"
@@ -383,11 +385,6 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
       HIPCHK(c, launch_quant_fp8(X, ldx, m, n, c->at<int>(L.Ex), c->at<uint8_t>(L.Xq), L.ldq,
                                  c->at<uint8_t>(L.XqT), L.ldqt, st, sqp, sqo));
   }
-  // The left and right range finders are independent: the right one runs on
-  // a second stream forked here and joined below, so that one chain's
-  // latency-bound orthonormalisations overlap the other's products.
-  HIPCHK(c, hipEventRecord(c->fork, st));
-  HIPCHK(c, hipStreamWaitEvent(c->st2, c->fork, 0));
   const Chain cl = chain(c, 0), cr = chain(c, 1);
   auto XB = [&](const Chain& ch, const float* B, float* C) -> hipError_t {            // X B  (m x k')
     return lp ? gemm_lowp(c, ch, 0, B, C) : gemm(c, ch, X, ldx, 0, B, C, m, n);
@@ -399,50 +396,55 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
     return orth(Y, L.KP, rows, k, ch.gp, ch.G, ch.R, ch.qs, ch.st, final);
   };
   const bool refine = lp && c->p.refine_fp32;
-  // left range finder: Q_L = orth(X Omega_L); q x { Z = orth(X^T Q_L); Q_L = orth(X Z) };
-  // only the last orthonormalisation of each side is a full CholeskyQR2
-  HIPCHK(c, XB(cl, omL, QL));
-  HIPCHK(c, ORTH(cl, QL, m, q == 0 && !refine));
+  // Each range finder is a list of stages (a product, then the orthonormalisation
+  // of its result); only the last orthonormalisation of each side is a full
+  // CholeskyQR2.  Left: Q_L = orth(X Omega_L); q x { Z = orth(X^T Q_L); Q_L = orth(X Z) }.
+  // Right: the same on X^T with Omega_R.
+  using Stage = std::function<hipError_t()>;
+  std::vector<Stage> left, right;
+  const bool last0 = q == 0 && !refine;
+  // (the left chain's first stage is enqueued by hand below, around the fork)
+  right.push_back([&, last0] { hipError_t e = XtB(cr, omR, QR); return e ? e : ORTH(cr, QR, n, last0); });
   for (int it = 0; it < q; ++it) {
-    HIPCHK(c, XtB(cl, QL, TN));
-    HIPCHK(c, ORTH(cl, TN, n, false));
-    HIPCHK(c, XB(cl, TN, QL));
-    HIPCHK(c, ORTH(cl, QL, m, it == q - 1 && !refine));
+    const bool last = it == q - 1 && !refine;
+    left.push_back([&] { hipError_t e = XtB(cl, QL, TN); return e ? e : ORTH(cl, TN, n, false); });
+    left.push_back([&, last] { hipError_t e = XB(cl, TN, QL); return e ? e : ORTH(cl, QL, m, last); });
+    right.push_back([&] { hipError_t e = XB(cr, QR, TM); return e ? e : ORTH(cr, TM, m, false); });
+    right.push_back([&, last] { hipError_t e = XtB(cr, TM, QR); return e ? e : ORTH(cr, QR, n, last); });
   }
-  // right range finder on X^T with Omega_R (second stream)
-  HIPCHK(c, XtB(cr, omR, QR));
-  HIPCHK(c, ORTH(cr, QR, n, q == 0 && !refine));
-  for (int it = 0; it < q; ++it) {
-    HIPCHK(c, XB(cr, QR, TM));
-    HIPCHK(c, ORTH(cr, TM, m, false));
-    HIPCHK(c, XtB(cr, TM, QR));
-    HIPCHK(c, ORTH(cr, QR, n, it == q - 1 && !refine));
-  }
-  // optional FP32 refinement: one power iteration per side on the exact X
-  if (refine) {
-    HIPCHK(c, gemm(c, cl, X, ldx, 1, QL, TN, n, m));
-    HIPCHK(c, ORTH(cl, TN, n, false));
-    HIPCHK(c, gemm(c, cl, X, ldx, 0, TN, QL, m, n));
-    HIPCHK(c, ORTH(cl, QL, m, true));
-    HIPCHK(c, gemm(c, cr, X, ldx, 0, QR, TM, m, n));
-    HIPCHK(c, ORTH(cr, TM, m, false));
-    HIPCHK(c, gemm(c, cr, X, ldx, 1, TM, QR, n, m));
-    HIPCHK(c, ORTH(cr, QR, n, true));
+  if (refine) {   // optional FP32 refinement: one power iteration per side on the exact X
+    left.push_back([&] { hipError_t e = gemm(c, cl, X, ldx, 1, QL, TN, n, m); return e ? e : ORTH(cl, TN, n, false); });
+    left.push_back([&] { hipError_t e = gemm(c, cl, X, ldx, 0, TN, QL, m, n); return e ? e : ORTH(cl, QL, m, true); });
+    right.push_back([&] { hipError_t e = gemm(c, cr, X, ldx, 0, QR, TM, m, n); return e ? e : ORTH(cr, TM, m, false); });
+    right.push_back([&] { hipError_t e = gemm(c, cr, X, ldx, 1, TM, QR, n, m); return e ? e : ORTH(cr, QR, n, true); });
   }
   // projected data (Sec 4): Xh = X^T Q_L (X-hat^T), Xc = X Q_R (X-check); FP32 on X,
   // or on the low-precision copy like the range finder (lowp_sketches)
   if (lps) {
-    HIPCHK(c, XtB(cl, QL, Xh));
-    HIPCHK(c, XB(cr, QR, Xc));
+    left.push_back([&] { return XtB(cl, QL, Xh); });
+    right.push_back([&] { return XB(cr, QR, Xc); });
   } else {
-  HIPCHK(c, gemm(c, cl, X, ldx, 1, QL, Xh, n, m));
-  {   // Xc = X Q_R, with ||X||^2 in FP64 from the same pass (for the proxy residual)
-    const int s = gemm_f32_pick_splits(m, k, n, 0);
-    double* sqp = c->at<double>(L.xsq_part);
-    HIPCHK(c, launch_gemm_f32(X, ldx, 0, QR, L.KP, Xc, L.KP, m, k, n, s, cr.gemm_part, cr.st, sqp));
-    HIPCHK(c, launch_sum_partials_f64(sqp, gemm_f32_sq_parts(m, k, s), 1, c->at<double>(L.proxy_out) + 2,
-                                      nullptr, cr.st));
+    left.push_back([&] { return gemm(c, cl, X, ldx, 1, QL, Xh, n, m); });
+    right.push_back([&] {   // Xc = X Q_R, with ||X||^2 in FP64 from the same pass (for the proxy residual)
+      const int s = gemm_f32_pick_splits(m, k, n, 0);
+      double* sqp = c->at<double>(L.xsq_part);
+      hipError_t e = launch_gemm_f32(X, ldx, 0, QR, L.KP, Xc, L.KP, m, k, n, s, cr.gemm_part, cr.st, sqp);
+      return e ? e : launch_sum_partials_f64(sqp, gemm_f32_sq_parts(m, k, s), 1, c->at<double>(L.proxy_out) + 2,
+                                            nullptr, cr.st);
+    });
   }
+  // The two range finders are independent: the right one runs on a second
+  // stream forked after the left one's first product and joined below, so that
+  // each chain's latency-bound orthonormalisations run under the other's
+  // products.  The host enqueues the stages alternately so that neither stream
+  // waits for the host to finish the other's list.
+  HIPCHK(c, XB(cl, omL, QL));
+  HIPCHK(c, hipEventRecord(c->fork, st));
+  HIPCHK(c, hipStreamWaitEvent(c->st2, c->fork, 0));
+  HIPCHK(c, ORTH(cl, QL, m, last0));
+  for (size_t i = 0; i < right.size(); ++i) {
+    HIPCHK(c, right[i]());
+    if (i < left.size()) HIPCHK(c, left[i]());
   }
   HIPCHK(c, hipEventRecord(c->join, c->st2));
   HIPCHK(c, hipStreamWaitEvent(st, c->join, 0));

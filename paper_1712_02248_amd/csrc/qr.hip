@@ -13,6 +13,8 @@
 // status[1]: 1 if a pass failed even with the shift (sticky);
 // status[2]: number of shifted factorisations (sticky);
 // status[3]: 1 if the second pass was skipped (the first was orthonormal).
+#include <algorithm>
+
 #include "common.h"
 
 namespace {
@@ -299,6 +301,7 @@ apply_rinv_kernel(float* __restrict__ Y, int64_t ldy, int64_t rows, int k,
     const double a = (double)Ys[ar][kr];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
+      if (s >= 4 * (t + 1)) continue;   // R^{-1} is upper triangular: rows >= 16 (t + 1) of block t are 0
       const int j = t * 16 + (lane & 15);
       double b;
       if (RS) b = Rs[kr][j];
@@ -320,8 +323,10 @@ apply_rinv_kernel(float* __restrict__ Y, int64_t ldy, int64_t rows, int k,
 }  // namespace
 
 int gram_pick_splits(int64_t rows, int k) {
-  // 256 rows per split, partials capped at 32 MB
+  // 256 rows per split, or down to 64 rows per split so that short bases still
+  // spread over 256 workgroups; partials capped at 32 MB
   int64_t s = ceil_div(rows, 256);
+  if (s < 256) s = std::min<int64_t>(256, ceil_div(rows, 64));
   const int64_t cap = (32ll << 20) / ((int64_t)k * k * 8);
   if (s > cap) s = cap;
   if (s > 1024) s = 1024;
