@@ -2,7 +2,9 @@
 // with both operands K-contiguous ("NT"), FP32 accumulation, FP32 output.
 // A is the low-precision copy of X (for X B) or of X^T (for X^T B); Bt is the
 // transposed low-precision copy of the thin operand (Omega or Q).  K is padded
-// to the tile depth with zeros in both operands.
+// to the tile depth with zeros in both operands.  A is streamed once per
+// product, so its loads are nontemporal (they do not displace the thin
+// operand, which every workgroup re-reads, from L2).
 //
 // BF16: v_mfma_f32_32x32x16_bf16, lane l holds A[l % 32][16s + 8(l / 32) .. +7];
 //       D[i][j] in lane j + 32 ((i / 4) % 2), register (i / 8) 4 + i % 4.
@@ -47,7 +49,7 @@ gemm_bf16_nt_kernel(const uint16_t* __restrict__ A, int64_t lda, const uint16_t*
     for (int p = 0; p < AV; ++p) {
       const int f = tid + 256 * p, row = f / (BK / 8), c8 = f % (BK / 8);
       const int64_t gi = i0 + row;
-      ra[p] = gi < M ? *(const i32x4*)(A + gi * lda + k0 + 8 * c8) : z4;
+      ra[p] = gi < M ? __builtin_nontemporal_load((const i32x4*)(A + gi * lda + k0 + 8 * c8)) : z4;
     }
 #pragma unroll
     for (int p = 0; p < BV; ++p) {
@@ -174,7 +176,7 @@ gemm_fp8_nt_kernel(const uint8_t* __restrict__ A, int64_t lda, const int* __rest
     for (int p = 0; p < AV; ++p) {
       const int f = tid + 256 * p, row = f / (BK / 16), c16 = f % (BK / 16);
       const int64_t gi = i0 + row;
-      ra[p] = gi < M ? *(const i32x4*)(A + gi * lda + k0 + 16 * c16) : z4;
+      ra[p] = gi < M ? __builtin_nontemporal_load((const i32x4*)(A + gi * lda + k0 + 16 * c16)) : z4;
     }
 #pragma unroll
     for (int p = 0; p < BV; ++p) {
@@ -290,7 +292,9 @@ hipError_t finish(float* part, int splits, float* C, int64_t ldc, int64_t M, int
 int gemm_lp_pick_splits(int64_t M, int64_t N, int64_t Kpad, int bm) {
   const int64_t tiles = ceil_div(M, bm) * ceil_div(N, bn_lp(N));
   if (tiles <= 0) return 1;
-  int64_t s = ceil_div(1024, tiles);
+  // about 512 workgroups: two per CU in a single dispatch wave (measured best
+  // for both product shapes of the range finder)
+  int64_t s = ceil_div(512, tiles);
   const int64_t kmax = Kpad / 512;  // at least 512 deep per split
   if (s > kmax) s = kmax;
   if (s > 64) s = 64;
