@@ -132,11 +132,33 @@ def quantize_data(X, fmt):
     return quant.e4m3_block_quantise(np.asarray(X, dtype=np.float32).astype(np.float64))[0]
 
 
+def split_bf16(A):
+    """Two-term BF16 representation of FP32 values (extension): hi = bf16(a),
+    lo = bf16(a - hi), both round to nearest even; a - hi is exact in FP32.
+    |a - hi - lo| <= 2^-16 |a| for normal values.  Returns (hi, lo) as FP64."""
+    from . import quant
+    A32 = np.asarray(A, dtype=np.float32)
+    hi = quant.bf16_round(A32)
+    r = A32.astype(np.float64) - hi            # exact, and representable in FP32
+    lo = quant.bf16_round(r.astype(np.float32))
+    return hi, lo
+
+
+def split_product(A, B):
+    """Product on split-BF16 operands with the lo*lo term dropped:
+    Ah Bh + Ah Bl + Al Bh, summed here in FP64 (the GPU accumulates in FP32).
+    Differs from A B by at most about 3 * 2^-16 (|A| |B|) elementwise."""
+    Ah, Al = split_bf16(A)
+    Bh, Bl = split_bf16(B)
+    return Ah @ Bh + Ah @ Bl + Al @ Bh
+
+
 def compress_lowp(X, Omega_L, Omega_R, q, fmt, refine=False, orth=householder_q, lowp_sketches=False):
     """Model of the low-precision compression: every range-finder product uses
     the quantised X and a quantised thin operand; optionally one FP32-exact
-    power iteration per side; the projected data use the exact X, or with
-    lowp_sketches the quantised X and quantised bases like the other products."""
+    power iteration per side; the projected data use the exact X (lowp_sketches
+    0), the quantised X and quantised bases like the other products (1), or
+    split-BF16 products on X (2)."""
     X = np.asarray(X, dtype=np.float64)
     Xq = quantize_data(X, fmt)
 
@@ -154,6 +176,8 @@ def compress_lowp(X, Omega_L, Omega_R, q, fmt, refine=False, orth=householder_q,
     if refine:
         QL = orth(X @ orth(X.T @ QL))
         QR = orth(X.T @ orth(X @ QR))
+    if lowp_sketches == 2:
+        return QL, QR, split_product(X.T, QL), split_product(X, QR)
     if lowp_sketches:
         return QL, QR, prod(Xq.T, QL), prod(Xq, QR)
     return QL, QR, X.T @ QL, X @ QR

@@ -473,3 +473,41 @@ def test_column_nnls_matches_active_set_nnls():
         ref, _ = nnls(Wh, Xr[j])
         assert np.allclose(Ht[j], ref, atol=1e-9)
     assert np.all(Ht >= 0)
+
+
+def test_split_bf16_representation():
+    """Two-term BF16 split: hi and lo agree with torch's round-to-nearest-even
+    BF16 cast, |a - hi - lo| <= 2^-16 |a|, and values with at most 16
+    significant bits are represented exactly."""
+    g = np.random.default_rng(17)
+    a = (g.standard_normal(20000) * 10.0 ** g.integers(-20, 20, 20000)).astype(np.float32)
+    hi, lo = nmf.split_bf16(a)
+    t_hi = torch.from_numpy(a).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(hi, t_hi)
+    r32 = (a.astype(np.float64) - hi).astype(np.float32)
+    assert np.array_equal(r32.astype(np.float64), a.astype(np.float64) - hi)      # a - hi is exact in FP32
+    assert np.array_equal(lo, torch.from_numpy(r32).to(torch.bfloat16).to(torch.float64).numpy())
+    assert np.all(np.abs(a.astype(np.float64) - hi - lo) <= 2.0 ** -16 * np.abs(a.astype(np.float64)))
+    # 16 significant bits: integers below 2^16, scaled by powers of two
+    b = (g.integers(1, 2 ** 16, 5000) * 2.0 ** g.integers(-30, 30, 5000)).astype(np.float32)
+    bh, bl = nmf.split_bf16(b)
+    assert np.array_equal(bh + bl, b.astype(np.float64))
+
+
+def test_split_product_bound_and_exact_case():
+    """Split-BF16 product (lo*lo dropped) within 3.1 * 2^-16 (|A| |B|) of the
+    exact product, and exact when both operands are BF16 values."""
+    g = np.random.default_rng(23)
+    A = g.random((300, 500)).astype(np.float32)
+    B = g.standard_normal((500, 40)).astype(np.float32)
+    P = nmf.split_product(A, B)
+    exact = A.astype(np.float64) @ B.astype(np.float64)
+    bound = 3.1 * 2.0 ** -16 * (np.abs(A.astype(np.float64)) @ np.abs(B.astype(np.float64)))
+    assert np.all(np.abs(P - exact) <= bound)
+    # a dropped cross term would be visible: the bound is far below |Ah Bl|
+    Ah, Al = nmf.split_bf16(A)
+    Bh, Bl = nmf.split_bf16(B)
+    assert np.max(np.abs(Ah @ Bl) - bound) > 0
+    Ab = torch.from_numpy(A).to(torch.bfloat16).to(torch.float32).numpy()
+    Bb = torch.from_numpy(B).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(nmf.split_product(Ab, Bb), Ab.astype(np.float64) @ Bb.astype(np.float64))
