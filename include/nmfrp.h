@@ -58,16 +58,19 @@ typedef struct {
   int32_t k_sketch;      /* k' = r + r_ov (Sec 3); r < k' <= min(m, n) (Sec 3.1) */
   int32_t q;             /* power iterations (the paper's w, eq 3.5) */
   int32_t prec;          /* nmf_prec of the range-finder products (extension); the
-                            final sketches Xh, Xc are always FP32 products on X */
+                            projected data Xh, Xc follow lowp_sketches */
   int32_t refine_fp32;   /* 1: one FP32 power iteration per side after the
                             low-precision range finder */
   int32_t normalize;     /* a_j <- a_j/||a_j|| after the A sweep (end of Sec 4):
                             0 none, 1 with b_j <- b_j ||a_j|| (default), 2 literal */
   float alpha, beta;     /* sparsity / smoothness on B (Sec 4.1); 0, 0 = plain rule */
   uint64_t seed;         /* Philox4x32-10 key for device-drawn Omega and factors */
-  int32_t lowp_sketches; /* 1 (prec != FP32 only): the sketches Xh, Xc are products on
-                            the low-precision copy of X as well (extension); 0: FP32
-                            products on X */
+  int32_t lowp_sketches; /* the projected data Xh, Xc (extension): 0 FP32 products on
+                            X; 1 (prec != FP32 only) products on the low-precision
+                            copy of X like the range finder; 2 split-BF16 products on
+                            X (see nmf_gemm_split), about 16 significant bits per
+                            term.  ||X||^2 for nmf_proxy_residual comes from the
+                            X Q_R pass (0, 2) or the quantiser (1). */
   int32_t reserved;      /* must be 0 */
 } nmf_params;
 
@@ -222,6 +225,20 @@ int32_t nmf_gemm_lowp_splits(int64_t M, int64_t N, int64_t Kpad);
 nmf_status nmf_gemm_lowp_prepared(int32_t prec, const void* A, int64_t lda, const int32_t* EA, int64_t ea_i,
                                   int64_t ea_k, const void* Bt, const int32_t* EB, int64_t N, float* C,
                                   int64_t ldc, int64_t M, int64_t Kpad, int32_t splits, void* hip_stream);
+
+/* Split-BF16 product on FP32 X (extension; the projected data X^T Q_L and
+ * X Q_R of Sec 4 when lowp_sketches = 2): C (M x N, ldc) = op(X) B with
+ * at = 0: X is M x K, at = 1: X is K x M (ldx >= columns, ldx % 4 == 0, X
+ * 16-byte aligned); B is K x N FP32 (ldb), N <= 256.  Every value v of X and B
+ * is used as hi + lo, hi = bf16(v), lo = bf16(v - hi) (nearest even); a product
+ * term is hi hi + hi lo + lo hi with FP32 accumulation, within about
+ * 3 * 2^-16 |x| |b| of the exact term.  workspace: nmf_gemm_split_workspace_bytes()
+ * bytes, 256-byte aligned (the split thin operand and split-K partials).
+ * Asynchronous on hip_stream. */
+size_t nmf_gemm_split_workspace_bytes(int64_t M, int64_t N, int64_t K);
+nmf_status nmf_gemm_split(const float* X, int64_t ldx, int32_t at, const float* B, int64_t ldb, int64_t K,
+                          int64_t N, float* C, int64_t ldc, int64_t M, void* workspace, size_t ws_bytes,
+                          void* hip_stream);
 
 /* In-place orthonormalisation of Y (rows x k, ldy % 4 == 0) by FP64
  * CholeskyQR2 (shifted CholeskyQR3 on breakdown), k <= 128.  Synchronising;

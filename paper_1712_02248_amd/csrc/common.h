@@ -56,6 +56,27 @@ hipError_t launch_prep_b_fp8(const float* B, int64_t ldb, int64_t K, int64_t N, 
 
 // Low-precision NT products (gemm_lp.hip): C[M x N] = A[M x Kpad] Bt[N x Kpad]^T.
 int gemm_lp_pick_splits(int64_t M, int64_t N, int64_t Kpad, int bm);
+// 1: rotate the K order per XCD (thin operand too large to stay in L2), 0: per workgroup
+int rot_per_xcd(int64_t N, int64_t kchunk, int splits, int elem_bytes);
+// C[i][j] = sum over z ascending of part[z][i][j] (splits x M x N FP32 partials)
+hipError_t launch_splitk_reduce_lp(const float* part, int splits, float* C, int64_t ldc, int64_t M, int64_t N,
+                                   hipStream_t st);
+
+// Split-BF16 products on FP32 X (gemm_split.hip), for the projected data.
+// Thin operand B (K x N FP32, ldb) -> BtH (and BtL if not NULL: split lo part),
+// N x ldbt BF16, zero for k >= K; ldbt % 64 == 0.  Also the BF16 copy of the
+// range-finder products (BtL NULL).
+hipError_t launch_prep_bt(const float* B, int64_t ldb, int64_t K, int64_t N, uint16_t* BtH, uint16_t* BtL,
+                          int64_t ldbt, hipStream_t st);
+// C[M x N] = op(X) B: at = 0, X is M x K (ldx); at = 1, X is K x M.  ldx % 4 == 0,
+// 16-byte aligned X; ldbt >= round_up(K, 64).  splits > 1: partials in part
+// (splits x M x N), summed in fixed order.  sq (at = 0): FP64 sum of squares of X
+// per workgroup, gemm_split_sq_parts() values.
+int gemm_split_pick_splits(int64_t M, int64_t N, int64_t K);
+int gemm_split_sq_parts(int64_t M, int splits);
+hipError_t launch_gemm_split(const float* X, int64_t ldx, int at, const uint16_t* BtH, const uint16_t* BtL,
+                             int64_t ldbt, float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, int splits,
+                             float* part, hipStream_t st, double* sq = nullptr);
 hipError_t launch_gemm_bf16_nt(const uint16_t* A, int64_t lda, const uint16_t* Bt, int64_t ldbt,
                                float* C, int64_t ldc, int64_t M, int64_t N, int64_t Kpad, int splits,
                                float* part, hipStream_t st, bool reduce = true);

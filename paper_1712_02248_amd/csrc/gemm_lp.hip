@@ -272,22 +272,28 @@ splitk_reduce_lp(const float* __restrict__ part, int splits, float* __restrict__
 
 int bn_lp(int64_t N) { return N <= 32 ? 32 : N <= 64 ? 64 : N <= 128 ? 128 : 256; }
 
+hipError_t finish(float* part, int splits, float* C, int64_t ldc, int64_t M, int64_t N, hipStream_t st) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || splits == 1) return e;
+  return launch_splitk_reduce_lp(part, splits, C, ldc, M, N, st);
+}
+
+}  // namespace
+
 // Per-XCD rotation when the thin-operand slices the grid streams (splits
 // slices of N x kchunk elements) exceed a quarter of one XCD's 4 MiB L2.
 int rot_per_xcd(int64_t N, int64_t kchunk, int splits, int elem_bytes) {
   return (double)N * kchunk * elem_bytes * splits > 1024.0 * 1024.0 ? 1 : 0;
 }
 
-hipError_t finish(float* part, int splits, float* C, int64_t ldc, int64_t M, int64_t N, hipStream_t st) {
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || splits == 1) return e;
+hipError_t launch_splitk_reduce_lp(const float* part, int splits, float* C, int64_t ldc, int64_t M, int64_t N,
+                                   hipStream_t st) {
   int64_t g = ceil_div(M * N, 256);
   if (g > 4096) g = 4096;
+  if (g == 0) return hipSuccess;
   hipLaunchKernelGGL(splitk_reduce_lp, dim3((unsigned)g), dim3(256), 0, st, part, splits, C, ldc, M, N);
   return hipGetLastError();
 }
-
-}  // namespace
 
 int gemm_lp_pick_splits(int64_t M, int64_t N, int64_t Kpad, int bm) {
   const int64_t tiles = ceil_div(M, bm) * ceil_div(N, bn_lp(N));

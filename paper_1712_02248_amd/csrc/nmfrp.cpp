@@ -3,6 +3,7 @@
 // workspace.  All kernels run on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -37,6 +38,7 @@ struct Layout {
   size_t alignM, whref;               // warm start: Q_train^T Q_L (k' x k'), Q_L^T W_ref (k' x r)
   int64_t ldq, ldqt;                 // low-precision copies of X: m x ldq and n x ldqt
   size_t Xq, XqT, Ex, Bt, Eb, Bt2, Eb2;
+  size_t St, St2;                     // split-BF16 thin operands (hi, then lo) of the sketch products
   size_t total;
   size_t gemm_part_bytes, gram_splits_max;
 };
@@ -54,8 +56,8 @@ bool valid_params(const nmf_params* p, std::string* why) {
   if (p->normalize < 0 || p->normalize > 2) { *why = "normalize must be 0, 1 or 2"; return false; }
   if (p->n % 4) { *why = "n must be a multiple of 4"; return false; }
   if (p->alpha < 0 || p->beta < 0) { *why = "alpha, beta must be >= 0"; return false; }
-  if (p->lowp_sketches < 0 || p->lowp_sketches > 1 || (p->lowp_sketches && p->prec == NMF_FP32)) {
-    *why = "lowp_sketches must be 0, or 1 with a low-precision prec";
+  if (p->lowp_sketches < 0 || p->lowp_sketches > 2 || (p->lowp_sketches == 1 && p->prec == NMF_FP32)) {
+    *why = "lowp_sketches must be 0, 1 (with a low-precision prec) or 2";
     return false;
   }
   if (p->reserved != 0) { *why = "reserved must be 0"; return false; }
@@ -86,6 +88,12 @@ Layout make_layout(const nmf_params* p) {
   if (p->prec != NMF_FP32) {
     const int bm = 128;
     const int l1 = gemm_lp_pick_splits(m, k, L.ldq, bm), l2 = gemm_lp_pick_splits(n, k, L.ldqt, bm);
+    const size_t q1 = l1 > 1 ? (size_t)l1 * m * k : 0, q2 = l2 > 1 ? (size_t)l2 * n * k : 0;
+    if (q1 > gp) gp = q1;
+    if (q2 > gp2) gp2 = q2;
+  }
+  if (p->lowp_sketches == 2) {
+    const int l1 = gemm_split_pick_splits(m, k, n), l2 = gemm_split_pick_splits(n, k, m);
     const size_t q1 = l1 > 1 ? (size_t)l1 * m * k : 0, q2 = l2 > 1 ? (size_t)l2 * n * k : 0;
     if (q1 > gp) gp = q1;
     if (q2 > gp2) gp2 = q2;
@@ -122,7 +130,8 @@ Layout make_layout(const nmf_params* p) {
   {
     const int64_t qp = quant_sq_parts(m, n, round_up(n, 128), round_up(m, 128));
     const int64_t gp3 = gemm_f32_sq_parts(m, k, 64);
-    L.xsq_part = pl.take((size_t)(qp > gp3 ? qp : gp3) * d);
+    const int64_t gp4 = gemm_split_sq_parts(m, gemm_split_pick_splits(m, k, n));
+    L.xsq_part = pl.take((size_t)std::max(qp, std::max(gp3, gp4)) * d);
   }
   L.Xq = L.XqT = L.Ex = L.Bt = L.Eb = L.Bt2 = L.Eb2 = 0;
   if (p->prec != NMF_FP32) {
@@ -134,6 +143,11 @@ Layout make_layout(const nmf_params* p) {
     L.Eb = pl.take((size_t)ceil_div(L.ldq > L.ldqt ? L.ldq : L.ldqt, 128) * sizeof(int));
     L.Bt2 = pl.take((size_t)k * (L.ldq > L.ldqt ? L.ldq : L.ldqt) * es);
     L.Eb2 = pl.take((size_t)ceil_div(L.ldq > L.ldqt ? L.ldq : L.ldqt, 128) * sizeof(int));
+  }
+  L.St = L.St2 = 0;
+  if (p->lowp_sketches == 2) {   // hi and lo halves, k x max(ldq, ldqt) BF16 each, per chain
+    L.St = pl.take((size_t)2 * k * std::max(L.ldq, L.ldqt) * 2);
+    L.St2 = pl.take((size_t)2 * k * std::max(L.ldq, L.ldqt) * 2);
   }
   L.total = pl.off;
   return L;
@@ -374,10 +388,14 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
   else HIPCHK(c, launch_philox_normal(omR, m, k, L.KP, 4u, c->p.seed, st));
   // range-finder products: FP32 on X, or on its low-precision copy (extension)
   const bool lp = c->p.prec != NMF_FP32;
-  const bool lps = lp && c->p.lowp_sketches;
-  if (lp) {   // with low-precision sketches, ||X||^2 comes from this (only FP32) pass over X
-    double* sqp = lps ? c->at<double>(L.xsq_part) : nullptr;
-    double* sqo = lps ? c->at<double>(L.proxy_out) + 2 : nullptr;
+  const bool lps = lp && c->p.lowp_sketches == 1;
+  const bool split = c->p.lowp_sketches == 2;
+  // ||X||^2 in FP64 from the quantiser's pass over X when there is one and the
+  // sketch products are low precision or split; else from the X Q_R pass
+  const bool xsq_quant = lp && (lps || split);
+  if (lp) {
+    double* sqp = xsq_quant ? c->at<double>(L.xsq_part) : nullptr;
+    double* sqo = xsq_quant ? c->at<double>(L.proxy_out) + 2 : nullptr;
     if (c->p.prec == NMF_BF16)
       HIPCHK(c, launch_quant_bf16(X, ldx, m, n, c->at<uint16_t>(L.Xq), L.ldq, c->at<uint16_t>(L.XqT),
                                   L.ldqt, st, sqp, sqo));
@@ -423,6 +441,25 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
   if (lps) {
     left.push_back([&] { return XtB(cl, QL, Xh); });
     right.push_back([&] { return XB(cr, QR, Xc); });
+  } else if (split) {   // split-BF16 products on X
+    left.push_back([&] {
+      uint16_t* H = c->at<uint16_t>(L.St);
+      uint16_t* Lo = H + (size_t)k * L.ldqt;
+      hipError_t e = launch_prep_bt(QL, L.KP, m, k, H, Lo, L.ldqt, cl.st);
+      return e ? e : launch_gemm_split(X, ldx, 1, H, Lo, L.ldqt, Xh, L.KP, n, k, m,
+                                       gemm_split_pick_splits(n, k, m), cl.gemm_part, cl.st);
+    });
+    right.push_back([&] {
+      uint16_t* H = c->at<uint16_t>(L.St2);
+      uint16_t* Lo = H + (size_t)k * L.ldq;
+      const int s = gemm_split_pick_splits(m, k, n);
+      double* sqp = xsq_quant ? nullptr : c->at<double>(L.xsq_part);
+      hipError_t e = launch_prep_bt(QR, L.KP, n, k, H, Lo, L.ldq, cr.st);
+      if (!e) e = launch_gemm_split(X, ldx, 0, H, Lo, L.ldq, Xc, L.KP, m, k, n, s, cr.gemm_part, cr.st, sqp);
+      if (e || xsq_quant) return e;
+      return launch_sum_partials_f64(sqp, gemm_split_sq_parts(m, s), 1, c->at<double>(L.proxy_out) + 2, nullptr,
+                                     cr.st);
+    });
   } else {
     left.push_back([&] { return gemm(c, cl, X, ldx, 1, QL, Xh, n, m); });
     right.push_back([&] {   // Xc = X Q_R, with ||X||^2 in FP64 from the same pass (for the proxy residual)
@@ -867,6 +904,32 @@ nmf_status nmf_gemm_lowp(int32_t prec, const void* A, int64_t lda, const int32_t
   } else {
     return fail(nullptr, NMF_EINVAL, "prec must be BF16 or FP8_E4M3");
   }
+  return e ? fail(nullptr, NMF_EHIP, hipGetErrorString(e)) : NMF_OK;
+}
+
+size_t nmf_gemm_split_workspace_bytes(int64_t M, int64_t N, int64_t K) {
+  if (M < 0 || N <= 0 || K <= 0) return 0;
+  const int64_t Kpad = round_up(K, 64);
+  const int s = gemm_split_pick_splits(M, N, K);
+  return (size_t)round_up(2 * N * Kpad * 2, 256) + (s > 1 ? (size_t)s * M * N * 4 : 0) + 1024;
+}
+
+nmf_status nmf_gemm_split(const float* X, int64_t ldx, int32_t at, const float* B, int64_t ldb, int64_t K,
+                          int64_t N, float* C, int64_t ldc, int64_t M, void* ws, size_t ws_bytes, void* hs) {
+  if (M < 0 || N <= 0 || N > 256 || K <= 0 || (at != 0 && at != 1) || ldb < N || ldc < N ||
+      ldx < (at ? M : K) || ldx % 4)
+    return fail(nullptr, NMF_EINVAL, "bad arguments");
+  if (M == 0) return NMF_OK;
+  if (!X || !B || !C || !ws || ((uintptr_t)X & 15) || ((uintptr_t)ws & 255) ||
+      ws_bytes < nmf_gemm_split_workspace_bytes(M, N, K))
+    return fail(nullptr, NMF_EINVAL, "null pointer, X not 16-byte aligned, or workspace too small / misaligned");
+  hipStream_t st = (hipStream_t)hs;
+  const int64_t Kpad = round_up(K, 64);
+  uint16_t* H = (uint16_t*)ws;
+  uint16_t* Lo = H + N * Kpad;
+  float* part = (float*)((char*)ws + round_up(2 * N * Kpad * 2, 256));
+  hipError_t e = launch_prep_bt(B, ldb, K, N, H, Lo, Kpad, st);
+  if (!e) e = launch_gemm_split(X, ldx, at, H, Lo, Kpad, C, ldc, M, N, K, gemm_split_pick_splits(M, N, K), part, st);
   return e ? fail(nullptr, NMF_EHIP, hipGetErrorString(e)) : NMF_OK;
 }
 

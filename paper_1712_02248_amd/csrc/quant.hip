@@ -237,17 +237,6 @@ quant_fp8_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
   }
 }
 
-// B (K x N FP32, ldb) -> Bt (N x ldbt BF16), transposed and rounded; zero padding.
-__global__ void __launch_bounds__(256)
-prep_b_bf16_kernel(const float* __restrict__ B, int64_t ldb, int64_t K, int64_t N,
-                   uint16_t* __restrict__ Bt, int64_t ldbt) {
-  const int64_t total = N * ldbt;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t j = e / ldbt, k = e - j * ldbt;
-    Bt[e] = (k < K) ? bf16_rne(B[k * ldb + j]) : (uint16_t)0;
-  }
-}
 
 // B -> Bt in e4m3 with one power-of-two scale per 128-row block of B (shared by
 // all columns): Ebt[kb] = smallest e with amax(B[128 kb .. 128 kb + 127, :]) <= 448 2^e.
@@ -344,8 +333,7 @@ hipError_t launch_quant_fp8(const float* X, int64_t ldx, int64_t m, int64_t n, i
 
 hipError_t launch_prep_b_bf16(const float* B, int64_t ldb, int64_t K, int64_t N, uint16_t* Bt,
                               int64_t ldbt, hipStream_t st) {
-  hipLaunchKernelGGL(prep_b_bf16_kernel, dim3(grid1(N * ldbt)), dim3(256), 0, st, B, ldb, K, N, Bt, ldbt);
-  return hipGetLastError();
+  return launch_prep_bt(B, ldb, K, N, Bt, nullptr, ldbt, st);   // tiled transpose (gemm_split.hip)
 }
 
 hipError_t launch_prep_b_fp8(const float* B, int64_t ldb, int64_t K, int64_t N, int* Ebt, uint8_t* Bt,

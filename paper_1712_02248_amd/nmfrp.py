@@ -61,6 +61,8 @@ _SIGS = {
     "nmf_gemm_lowp_splits": (c_i32, [c_i64, c_i64, c_i64]),
     "nmf_gemm_lowp_prepared": (c_i32, [c_i32, c_vp, c_i64, c_vp, c_i64, c_i64, c_vp, c_vp, c_i64, c_vp, c_i64,
                                        c_i64, c_i64, c_i32, c_vp]),
+    "nmf_gemm_split_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64]),
+    "nmf_gemm_split": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_i64, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp, c_sz, c_vp]),
     "nmf_orth_workspace_bytes": (c_sz, [c_i64, c_i32]),
     "nmf_orth": (c_i32, [c_vp, c_i64, c_i64, c_i32, c_vp, c_sz, c_vp, c_i32_p]),
     "nmf_mlp_n_params": (c_i64, [c_i32, c_i32, c_i32]),
@@ -305,6 +307,26 @@ def gemm(A, B, a_trans=False, out=None, stream=None):
     _check(lib.nmf_gemm(_ptr(A), A.stride(0), int(a_trans), _ptr(B), B.stride(0), _ptr(out), out.stride(0),
                         M, N, K, _ptr(ws), ws.numel(), _stream(stream)))
     return out
+
+
+def gemm_split(X, at, B, stream=None):
+    """op(X) B on split-BF16 operands (X FP32 contiguous rows, at = 1 for X^T B);
+    returns C as a new FP32 device tensor."""
+    lib = load()
+    if X.dtype != torch.float32 or B.dtype != torch.float32 or X.stride(1) != 1 or B.stride(1) != 1:
+        raise ValueError("X and B must be FP32 with unit column stride")
+    rows, cols = X.shape
+    M, K = (cols, rows) if at else (rows, cols)
+    if B.shape[0] != K:
+        raise ValueError("B must have op(X)'s inner dimension rows")
+    N = B.shape[1]
+    C = torch.empty((M, N), dtype=torch.float32, device=X.device)
+    nb = lib.nmf_gemm_split_workspace_bytes(M, N, K)
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device=X.device)
+    base = (ws.data_ptr() + 255) // 256 * 256
+    _check(lib.nmf_gemm_split(_ptr(X), X.stride(0), int(at), _ptr(B), B.stride(0), K, N, _ptr(C), C.stride(0), M,
+                              base, nb, _stream(stream)))
+    return C
 
 
 def orth(Y, stream=None):

@@ -103,8 +103,63 @@ def test_prepared_product_matches_full_product(lib, fmt, m, n, k, side):
     assert np.array_equal(acc, full)
 
 
+@pytest.mark.parametrize("rows,cols,k", [(300, 200, 64), (1000, 36, 20), (77, 130, 5), (2, 4, 1), (4096, 256, 64)])
+def test_prepared_thin_operand_bit_exact(lib, rows, cols, k):
+    """The transposed BF16 copy of a thin operand (K x k) is torch's
+    round-to-nearest-even cast, zero in the padding columns."""
+    print(f"prep thin bf16 K={rows} k={k}", flush=True)
+    g = np.random.default_rng(rows + k)
+    B = (g.standard_normal((rows, k)) * 10.0 ** g.integers(-4, 4, (rows, k))).astype(np.float32)
+    X = _x(cols, rows, 3)
+    Xq, XqT, E = lib.quantize_x(torch.from_numpy(X).cuda(), lib.NMF_BF16)
+    pp = lib.LowpProduct(lib.NMF_BF16, Xq, rows, torch.from_numpy(B).cuda())
+    Bt = pp.Bt.cpu()
+    want = torch.from_numpy(B).to(torch.bfloat16).view(torch.int16).T.contiguous()
+    assert torch.equal(Bt[:, :rows], want)
+    assert int(Bt[:, rows:].abs().sum()) == 0
+
+
+def _padded(X):
+    """Copy of X (FP32) in a buffer whose row stride is a multiple of 4."""
+    rows, cols = X.shape
+    buf = torch.zeros((rows, -(-cols // 4) * 4), dtype=torch.float32)
+    buf[:, :cols] = torch.from_numpy(X)
+    return buf.cuda()[:, :cols]
+
+
+@pytest.mark.parametrize("m,n,k,at", [(1000, 300, 20, 0), (1000, 300, 64, 1), (4096, 2048, 64, 1),
+                                      (4096, 2048, 64, 0), (513, 701, 37, 0), (513, 701, 37, 1),
+                                      (130, 8, 5, 1), (2, 4, 3, 0), (300, 5000, 128, 0), (20000, 64, 64, 1)])
+def test_split_products(lib, m, n, k, at):
+    """Split-BF16 product against the oracle's model of the same arithmetic
+    (FP64 sums of the three BF16 products), within the FP32 accumulation bound,
+    and against the exact product within the split bound."""
+    print(f"split gemm {m}x{n} k={k} at={at}", flush=True)
+    g = np.random.default_rng(m + 7 * n + k + at)
+    X = (g.random((m, n)) * 10.0 ** g.integers(-2, 2, (m, n))).astype(np.float32)
+    X[: m // 5, : n // 3] = 0.0
+    K = m if at else n
+    B = g.standard_normal((K, k)).astype(np.float32)
+    C = lib.gemm_split(_padded(X), at, torch.from_numpy(B).cuda()).cpu().numpy().astype(np.float64)
+    A = X.T if at else X
+    model = onmf.split_product(A, B)
+    absprod = np.abs(A.astype(np.float64)) @ np.abs(B.astype(np.float64))
+    assert np.all(np.abs(C - model) <= 3.0 * K * 2.0 ** -24 * absprod + 1e-30)
+    exact = A.astype(np.float64) @ B.astype(np.float64)
+    assert np.all(np.abs(C - exact) <= (3.1 * 2.0 ** -16 + 3.0 * K * 2.0 ** -24) * absprod + 1e-30)
+
+
+def test_split_product_bad_arguments(lib):
+    X = torch.zeros((64, 30), dtype=torch.float32, device="cuda")      # row stride 30: not a multiple of 4
+    B = torch.zeros((30, 8), dtype=torch.float32, device="cuda")
+    with pytest.raises(lib.NmfError):
+        lib.gemm_split(X, 0, B)
+    with pytest.raises(ValueError):
+        lib.gemm_split(_padded(np.zeros((64, 32), np.float32)), 0, torch.zeros((31, 8), device="cuda"))
+
+
 @pytest.mark.parametrize("fmt,refine,lps", [("bf16", 0, 0), ("bf16", 1, 0), ("fp8", 0, 0), ("fp8", 1, 0),
-                                            ("bf16", 0, 1)])
+                                            ("bf16", 0, 1), ("bf16", 0, 2), ("fp8", 0, 2)])
 def test_lowp_compression_runs(lib, fmt, refine, lps):
     """Whole run with low-precision range-finder products: the error after the
     iterations is compared with the oracle's model of the same rounding (R_q)
@@ -124,9 +179,9 @@ def test_lowp_compression_runs(lib, fmt, refine, lps):
     ctx.compress(Xd, torch.from_numpy(OL).cuda(), torch.from_numpy(OR).cuda())
     ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
     ctx.step(iters)
-    ep = ctx.proxy_residual()            # ||X||^2 from the quantiser when lps, else the sketch pass
+    ep = ctx.proxy_residual()            # ||X||^2 from the quantiser when lps == 1, else the X Q_R pass
     e = ctx.residual(Xd)
-    ref = onmf.fasthals_rp(X, OL, OR, q, W0, H0, iters, fmt=fmt, refine=bool(refine), lowp_sketches=bool(lps))
+    ref = onmf.fasthals_rp(X, OL, OR, q, W0, H0, iters, fmt=fmt, refine=bool(refine), lowp_sketches=lps)
     Rq = ref["e"]
     nx2 = float(np.sum(X.astype(np.float64) ** 2))
     ep_ref = onmf.proxy_rel_error(nx2, ref["Xh"], ref["QL"].T @ ref["W"], ref["Ht"])
