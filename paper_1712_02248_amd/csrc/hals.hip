@@ -363,18 +363,23 @@ sum_partials_kernel(const T* __restrict__ part, int nparts, int64_t ne, double* 
   __shared__ double red[16][17];
   const int el = threadIdx.x & 15, g = threadIdx.x >> 4;
   const int64_t e = (int64_t)blockIdx.x * 16 + el;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  // partials g, g + 16, g + 32, ... in eight fixed accumulators; the eight
+  // loads of a round are issued together (latency-bound for few elements)
+  double s[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) s[u] = 0.0;
   if (e < ne) {
     int b = g;
-    for (; b + 48 < nparts; b += 64) {
-      s0 += (double)part[(int64_t)b * ne + e];
-      s1 += (double)part[(int64_t)(b + 16) * ne + e];
-      s2 += (double)part[(int64_t)(b + 32) * ne + e];
-      s3 += (double)part[(int64_t)(b + 48) * ne + e];
+    for (; b + 112 < nparts; b += 128) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + 16 * u) * ne + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s[u] += (double)v[u];
     }
-    for (; b < nparts; b += 16) s0 += (double)part[(int64_t)b * ne + e];
+    for (; b < nparts; b += 16) s[0] += (double)part[(int64_t)b * ne + e];
   }
-  red[g][el] = (s0 + s1) + (s2 + s3);
+  red[g][el] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
   __syncthreads();
   if (g == 0 && e < ne) {
     double t = 0.0;

@@ -2,48 +2,58 @@
 // evaluated directly (never through the Gram expansion, which cancels
 // catastrophically at small e) with FP64 products and FP64 accumulation.
 //
-// A workgroup owns 64 rows of X and walks all 64-column tiles, starting at
-// tile (workgroup index mod tile count).  Each wave
-// computes a 16 x 64 block of W diag(sw) Ht^T on v_mfma_f64_16x16x4_f64
-// (D[i][j] in lane j + 16 (i % 4), register i / 4), subtracts X, and
-// accumulates squares.  Workgroup partials are summed in fixed order by the
-// last workgroup to finish (completion counter, reset afterwards).
+// A workgroup owns 4 RPW rows of X (RPW per wave) and walks all 64-column tiles,
+// starting at tile (workgroup index mod tile count).  Per 16-column block the
+// wave forms E = Htb (W diag(sw))^T on v_mfma_f64_16x16x4_f64 (A = Ht rows from
+// LDS, already FP64; B = the wave's W rows, kept in registers), with the
+// block's Ht rows taken in the order c(j) = 4 (j % 4) + j / 4: E[j][i] lands in
+// lane i + 16 (j % 4), register j / 4, so lane l holds row l % 16 and the four
+// adjacent columns 4 (l / 16) .. +3 of the block, one float4 of X.  It
+// subtracts X and accumulates squares.  Workgroup partials are summed in fixed
+// order by the last workgroup to finish (completion counter, reset afterwards).
 #include "common.h"
 
 namespace {
 
-constexpr int RB = 64;       // rows per workgroup (the workgroup sweeps all columns)
+constexpr int RBMIN = 64;    // fewest rows per workgroup of any instantiation
 constexpr int CT = 64;       // columns per tile
 
-template <int RMAX>
+template <int RMAX, int RPW>
 __global__ void __launch_bounds__(256)
 residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
                 const float* __restrict__ W, const float* __restrict__ sw,
                 const float* __restrict__ Ht, int r, double* __restrict__ part,
                 double* __restrict__ out, unsigned* __restrict__ counter) {
+  constexpr int RB = 4 * RPW, NB = RPW / 16;  // rows per workgroup, 16-row blocks per wave
   constexpr int KS = RMAX / 4;                // MFMA k-steps
   constexpr int HPT = CT * RMAX / 256;        // Ht tile elements per thread
-  __shared__ float Hs[CT][RMAX + 1];
+  __shared__ double Hs[CT][RMAX + 1];
   __shared__ double red[2][256];
   __shared__ int last;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = (int64_t)blockIdx.x * RB;
   const int64_t ntile = ceil_div(n, CT);
+  const bool vec = (ldx % 4 == 0) && (((uintptr_t)X & 15) == 0);   // float4 loads of X
 
-  // A fragments (rows of W diag(sw) owned by this wave), FP64, kept for all tiles.
-  double afr[KS];
-  {
-    const int64_t gi = row0 + wave * 16 + (lane & 15);
+  // B fragments (rows of W diag(sw) owned by this wave), FP64, kept for all tiles
+  double wfr[NB][KS];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int64_t gi = row0 + wave * RPW + nb * 16 + (lane & 15);
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       const int k = 4 * s + (lane >> 4);
-      afr[s] = (gi < m && k < r) ? (double)W[gi * r + k] * (double)(sw ? sw[k] : 1.f) : 0.0;
+      wfr[nb][s] = (gi < m && k < r) ? (double)W[gi * r + k] * (double)(sw ? sw[k] : 1.f) : 0.0;
     }
   }
+  const int hrow = 4 * (lane & 3) + ((lane & 15) >> 2);   // c(lane % 16)
   // Software pipeline over the 64-column tiles of this row strip: the loads of
   // tile t+1 are issued (Ht first, then X) before the MFMAs of tile t, so each
-  // wait only covers loads issued one tile earlier.
-  float hv[HPT], xv[4][4];
+  // wait only covers loads issued one tile earlier.  n % 4 == 0, so a group of
+  // four columns is either inside or outside.
+  float hv[HPT];
+  f32x4 xv[NB][4];
+  const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
   auto load_h = [&](int64_t c0) {
 #pragma unroll
     for (int p = 0; p < HPT; ++p) {
@@ -53,12 +63,18 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
   };
   auto load_x = [&](int64_t c0) {
 #pragma unroll
-    for (int sub = 0; sub < 4; ++sub)
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t gi = row0 + wave * 16 + 4 * q + (lane >> 4);
-        const int64_t gj = c0 + sub * 16 + (lane & 15);
-        xv[sub][q] = (gi < m && gj < n) ? X[gi * ldx + gj] : 0.f;
+      for (int sub = 0; sub < 4; ++sub) {
+        const int64_t gi = row0 + wave * RPW + nb * 16 + (lane & 15);
+        const int64_t gj = c0 + sub * 16 + 4 * (lane >> 4);
+        f32x4 v = z4;
+        if (gi < m && gj < n) {
+          const float* src = X + gi * ldx + gj;
+          if (vec) v = *(const f32x4*)src;
+          else v = (f32x4){src[0], src[1], src[2], src[3]};
+        }
+        xv[nb][sub] = v;
       }
   };
   // workgroups start at different column tiles (rotated order) so that
@@ -73,40 +89,47 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
 #pragma unroll
     for (int p = 0; p < HPT; ++p) {
       const int e = tid + 256 * p;
-      Hs[e / RMAX][e % RMAX] = hv[p];
+      Hs[e / RMAX][e % RMAX] = (double)hv[p];
     }
     __syncthreads();
-    float xc[4][4];
+    f32x4 xc[NB][4];
 #pragma unroll
-    for (int sub = 0; sub < 4; ++sub)
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) xc[sub][q] = xv[sub][q];
+      for (int sub = 0; sub < 4; ++sub) xc[nb][sub] = xv[nb][sub];
     if (t + 1 < ntile) {
       load_h(col0(t + 1));
       load_x(col0(t + 1));
     }
-    f64x4 d[4];
+    f64x4 d[NB][4];
 #pragma unroll
-    for (int sub = 0; sub < 4; ++sub) d[sub] = (f64x4){0, 0, 0, 0};
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int sub = 0; sub < 4; ++sub) d[nb][sub] = (f64x4){0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       const int k = 4 * s + (lane >> 4);
 #pragma unroll
       for (int sub = 0; sub < 4; ++sub) {
-        const double b = (double)Hs[sub * 16 + (lane & 15)][k];
-        d[sub] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[s], b, d[sub], 0, 0, 0);
+        const double h = Hs[sub * 16 + hrow][k];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          d[nb][sub] = __builtin_amdgcn_mfma_f64_16x16x4f64(h, wfr[nb][s], d[nb][sub], 0, 0, 0);
       }
     }
-    // D[i][j] in lane j + 16 (i % 4), register i / 4; out-of-range entries are 0 - 0
+    // lane: row i = lane % 16 of block nb, tile columns 16 sub + 4 (lane / 16) + q in
+    // register q; out-of-range entries are 0 - 0
 #pragma unroll
-    for (int sub = 0; sub < 4; ++sub)
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double x = (double)xc[sub][q];
-        const double df = x - d[sub][q];
-        res = fma(df, df, res);
-        xx = fma(x, x, xx);
-      }
+      for (int sub = 0; sub < 4; ++sub)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double x = (double)xc[nb][sub][q];
+          const double df = x - d[nb][sub][q];
+          res = fma(df, df, res);
+          xx = fma(x, x, xx);
+        }
   }
   red[0][tid] = res;
   red[1][tid] = xx;
@@ -195,27 +218,29 @@ proxy_kernel(const float* __restrict__ Xh, int64_t ldx, const float* __restrict_
 
 }  // namespace
 
-int residual_blocks(int64_t m, int64_t n) {
+int residual_blocks(int64_t m, int64_t n) {   // upper bound over the instantiations
   (void)n;
-  return (int)ceil_div(m, RB);
+  return (int)ceil_div(m, RBMIN);
 }
 
 hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t n, const float* W,
                            const float* sw, const float* Ht, int r, double* part, double* out,
                            unsigned* counter, hipStream_t st) {
-  dim3 grid((unsigned)ceil_div(m, RB));
+  if (n % 4) return hipErrorInvalidValue;
+  // 32 rows per wave (each Ht fragment feeds two MFMA row blocks) while the W
+  // fragments fit; 16 for larger r
   if (r <= 16)
-    hipLaunchKernelGGL(residual_kernel<16>, grid, dim3(256), 0, st, X, ldx, m, n, W, sw, Ht, r, part,
-                       out, counter);
+    hipLaunchKernelGGL((residual_kernel<16, 32>), dim3((unsigned)ceil_div(m, 128)), dim3(256), 0, st, X, ldx, m,
+                       n, W, sw, Ht, r, part, out, counter);
   else if (r <= 32)
-    hipLaunchKernelGGL(residual_kernel<32>, grid, dim3(256), 0, st, X, ldx, m, n, W, sw, Ht, r, part,
-                       out, counter);
+    hipLaunchKernelGGL((residual_kernel<32, 32>), dim3((unsigned)ceil_div(m, 128)), dim3(256), 0, st, X, ldx, m,
+                       n, W, sw, Ht, r, part, out, counter);
   else if (r <= 64)
-    hipLaunchKernelGGL(residual_kernel<64>, grid, dim3(256), 0, st, X, ldx, m, n, W, sw, Ht, r, part,
-                       out, counter);
+    hipLaunchKernelGGL((residual_kernel<64, 16>), dim3((unsigned)ceil_div(m, 64)), dim3(256), 0, st, X, ldx, m,
+                       n, W, sw, Ht, r, part, out, counter);
   else if (r <= 128)
-    hipLaunchKernelGGL(residual_kernel<128>, grid, dim3(256), 0, st, X, ldx, m, n, W, sw, Ht, r, part,
-                       out, counter);
+    hipLaunchKernelGGL((residual_kernel<128, 16>), dim3((unsigned)ceil_div(m, 64)), dim3(256), 0, st, X, ldx, m,
+                       n, W, sw, Ht, r, part, out, counter);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
