@@ -4,7 +4,7 @@ BF16 compression with a learned warm start of H, against plain FP32.
 
 One step = the whole hot path on the workload's X, which is resident in HBM
 when the clock starts: compress (device-drawn Gaussian test matrices, range
-finder with power iterations and FP64 CholeskyQR2, FP32 sketches), set the
+finder with power iterations and FP64 CholeskyQR2, sketch products), set the
 initial factors, then FastHALS-RP iterations with an exact FP64 residual check
 schedule until e <= eps.  eps = (1 + 1e-3) * e_oracle, where e_oracle is the FP64
 oracle's error after the workload's iteration count (stored by
@@ -12,16 +12,18 @@ tests/golden/make_oracle_errors.py, which calls only the oracle).
 
 Variants (same X, same cold factors):
   plain      FP32 range finder, cold start (the paper's method).
-  bf16_warm  BF16 range-finder products with FP32 accumulation (FP32
-             sketches), then the learned warm start: W from the reference
+  bf16_warm  BF16 range-finder products with FP32 accumulation, split-BF16
+             sketch products on X (three BF16 products per term, about 16
+             significant bits), then the learned warm start: W from the reference
              dictionary, H rows from the network on the compressed columns,
              each kept only if it beats the cold row on the compressed
              residual, then column-NNLS sweeps.  The step includes the
              alignment products, inference, selection and sweeps; it excludes
              training.
-  others     BF16 sketches (their error floor lies above eps at c2), bf16 /
-             fp8 (+ FP32 refinement) cold starts, fp32_warm and fp8_warm,
-             reported alongside.
+  others     FP32 sketch products (bf16_warm_fp32_sketches), BF16 sketches
+             (their error floor lies above eps at c2), bf16 / fp8 (+ FP32
+             refinement) cold starts, fp32_warm and fp8_warm, reported
+             alongside.
 The network is trained before timing on pairs from new columns of the same
 generator (same basis W0, new coefficients): a reference fit on one new draw
 gives Q_train and W_ref; every pair is (Q_train^T x, NNLS row of x against
@@ -45,7 +47,7 @@ sys.path.insert(0, ROOT)
 GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_errors.json")
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
-# the headline variant: BF16 range finder, FP32 sketches, learned warm start
+# the headline variant: BF16 range finder, split-BF16 sketches, learned warm start
 HEADLINE = "bf16_warm"
 
 
@@ -423,12 +425,14 @@ def main():
     warm = (net, Q_train, W_ref, args.refine_sweeps)
     warm_net_only = (net, Q_train, W_ref, 0)
 
-    # (name, prec, FP32 refinement, warm start, low-precision sketches, steps, warmup)
+    # (name, prec, FP32 refinement, warm start, sketch products (0 FP32, 1 low precision,
+    #  2 split BF16), steps, warmup)
     BF, F8, F32 = nmfrp.NMF_BF16, nmfrp.NMF_FP8_E4M3, nmfrp.NMF_FP32
     variants = [("plain", F32, 0, None, 0, args.steps, args.warmup),
-                (HEADLINE, BF, 0, warm, 0, args.steps, args.warmup)]
+                (HEADLINE, BF, 0, warm, 2, args.steps, args.warmup)]
     if not args.headline_only:
-        variants += [("bf16_warm_lowp_sketches", BF, 0, warm, 1, 3, 1),
+        variants += [("bf16_warm_fp32_sketches", BF, 0, warm, 0, 3, 1),
+                     ("bf16_warm_lowp_sketches", BF, 0, warm, 1, 3, 1),
                      ("bf16", BF, 0, None, 0, 3, 1),
                      ("bf16_lowp_sketches", BF, 0, None, 1, 3, 1),
                      ("bf16_refine", BF, 1, None, 0, 3, 1),
@@ -436,7 +440,7 @@ def main():
                      ("fp8_refine_warm", F8, 1, warm, 0, 3, 1),
                      ("fp32_warm", F32, 0, warm, 0, 3, 1),
                      ("bf16_warm_net_only", BF, 0, warm_net_only, 0, 3, 1),
-                     ("fp8_warm", F8, 0, warm, 0, 3, 1)]
+                     ("fp8_warm", F8, 0, warm, 2, 3, 1)]
     if args.variants:
         keep = args.variants.split(",")
         variants = [v for v in variants if v[0] in keep]
@@ -480,7 +484,8 @@ def main():
         scaling="weak", vs_baseline=None, dtype="bf16", data="synthetic",
         config=dict(workload=f"{name}: X {m}x{n} FP32 synthetic ({cfg['family']} family, r_true="
                     f"{cfg['r_true']}), r={r}, k'={kp}, q={q}, eps=(1+1e-3) e_oracle({iters_cfg} it); "
-                    f"BF16 range finder + MLP warm start of H ({args.refine_sweeps} NNLS sweeps) vs plain FP32",
+                    f"BF16 range finder, split-BF16 sketches, MLP warm start of H ({args.refine_sweeps} NNLS "
+                    f"sweeps) vs plain FP32",
                     m=m, n=n, r=r, k_sketch=kp, q=q, iters_cfg=iters_cfg, check_every=args.check_every,
                     refine_sweeps=args.refine_sweeps),
         eps=eps, eps_source=eps_src, e_oracle=e_oracle,
