@@ -282,6 +282,131 @@ prep_b_fp8_kernel(const float* __restrict__ B, int64_t ldb, int64_t K, int64_t N
   }
 }
 
+// smallest integer e with a <= 448 2^e (0 for a == 0); exact comparisons with
+// power-of-two factors
+NMF_DEV int e4m3_scale_exp(float a) {
+  int e = 0;
+  if (a > 0.f) {
+    int fe;
+    frexpf(a / 448.0f, &fe);
+    e = fe - 1;
+    while (a > ldexpf(448.0f, e)) ++e;
+    while (a <= ldexpf(448.0f, e - 1)) --e;
+  }
+  return e;
+}
+
+// One pass over X for the FP8 copies: per 128 x 128 tile the exponent, the
+// codes of X (Xq) and of X^T (XqT, through LDS), and optionally the FP64 sum
+// of squares.  Grid (ldq / 128, ldqt / 128) also covers the zero padding.
+// Thread t holds columns 4 (t % 32) .. +3 of tile rows 16 (t / 32) .. +15 in
+// registers.  LDS word T[32 (c % 4) + c / 4][w] packs the codes of tile column c,
+// rows 4 w .. 4 w + 3 (row stride 33 words: the 32 lanes of a half-wave write
+// distinct banks).
+__global__ void __launch_bounds__(256)
+quant_fp8_fused_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n, int* __restrict__ E,
+                       int tiles_n, int tiles_m, uint8_t* __restrict__ Xq, int64_t ldq, uint8_t* __restrict__ XqT,
+                       int64_t ldqt, double* __restrict__ sq) {
+  __shared__ uint32_t T[128][33];
+  __shared__ float wmax[4];
+  __shared__ int sexp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c4 = tid & 31, g = tid >> 5;
+  const int64_t i0 = (int64_t)blockIdx.y * 128, j0 = (int64_t)blockIdx.x * 128;
+  const int64_t gj = j0 + 4 * c4;
+  f32x4 v[16];
+  float amax = 0.f;
+  double ssq = 0.0;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t gi = i0 + 16 * g + r;
+    f32x4 x = {0.f, 0.f, 0.f, 0.f};
+    if (gi < m && gj < n) x = __builtin_nontemporal_load((const f32x4*)(X + gi * ldx + gj));   // n % 4 == 0
+    v[r] = x;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      amax = fmaxf(amax, fabsf(x[d]));
+      ssq = fma((double)x[d], (double)x[d], ssq);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+  if (lane == 0) wmax[wave] = amax;
+  __syncthreads();
+  if (tid == 0) {
+    const int e = e4m3_scale_exp(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3])));
+    sexp = e;
+    if ((int)blockIdx.y < tiles_m && (int)blockIdx.x < tiles_n) E[blockIdx.y * tiles_n + blockIdx.x] = e;
+  }
+  if (sq) block_sq(ssq, sq);
+  __syncthreads();
+  const float s = ldexpf(1.0f, -sexp);
+  uint32_t code[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t gi = i0 + 16 * g + r;
+    uint32_t w = 0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) w |= (uint32_t)e4m3_rne(v[r][d] * s) << (8 * d);   // padding: code of 0 is 0
+    code[r] = w;
+    if (gi < m) *(uint32_t*)(Xq + gi * ldq + gj) = w;
+  }
+#pragma unroll
+  for (int d = 0; d < 4; ++d)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      uint32_t w = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) w |= ((code[4 * b + k] >> (8 * d)) & 0xFFu) << (8 * k);
+      T[32 * d + c4][4 * g + b] = w;
+    }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int jr = (tid >> 3) + 32 * q, w4 = 4 * (tid & 7);
+    const int tr = 32 * (jr & 3) + (jr >> 2);
+    if (j0 + jr < n) {
+      const i32x4 o = {(int)T[tr][w4], (int)T[tr][w4 + 1], (int)T[tr][w4 + 2], (int)T[tr][w4 + 3]};
+      *(i32x4*)(XqT + (j0 + jr) * ldqt + i0 + 4 * w4) = o;
+    }
+  }
+}
+
+// B -> Bt in e4m3 for N <= 128 in one pass: one workgroup per 128-row block of B
+// (its exponent Ebt[block] as above, then the transposed codes through LDS).
+__global__ void __launch_bounds__(256)
+prep_bt_fp8_kernel(const float* __restrict__ B, int64_t ldb, int64_t K, int64_t N, int* __restrict__ Ebt,
+                   uint8_t* __restrict__ Bt, int64_t ldbt) {
+  __shared__ float T[128][129];          // T[j][k]
+  __shared__ float wmax[4];
+  __shared__ int sexp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t k0 = (int64_t)blockIdx.x * 128;
+  float amax = 0.f;
+  for (int e = tid; e < 128 * N; e += 256) {
+    const int k = e / (int)N, j = e % (int)N;
+    const float x = (k0 + k < K) ? B[(k0 + k) * ldb + j] : 0.f;
+    T[j][k] = x;
+    amax = fmaxf(amax, fabsf(x));
+  }
+  for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
+  if (lane == 0) wmax[wave] = amax;
+  __syncthreads();
+  if (tid == 0) {
+    const int e = e4m3_scale_exp(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3])));
+    sexp = e;
+    Ebt[blockIdx.x] = e;
+  }
+  __syncthreads();
+  const float s = ldexpf(1.0f, -sexp);
+  for (int e = tid; e < 32 * N; e += 256) {
+    const int j = e >> 5, w = e & 31;
+    uint32_t o = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o |= (uint32_t)e4m3_rne(T[j][4 * w + k] * s) << (8 * k);
+    *(uint32_t*)(Bt + j * ldbt + k0 + 4 * w) = o;
+  }
+}
+
 unsigned grid1(int64_t total) {
   int64_t g = ceil_div(total, 256);
   if (g < 1) g = 1;
@@ -320,13 +445,21 @@ hipError_t launch_quant_fp8(const float* X, int64_t ldx, int64_t m, int64_t n, i
                             int64_t ldq, uint8_t* XqT, int64_t ldqt, hipStream_t st, double* sq_part,
                             double* sq_out) {
   const int tn = (int)ceil_div(n, 128), tm = (int)ceil_div(m, 128);
-  hipLaunchKernelGGL(tile_exp_kernel, dim3(tn, tm), dim3(256), 0, st, X, ldx, m, n, E, tn);
+  const bool fused = ldq % 128 == 0 && ldqt % 128 == 0 && n % 4 == 0 && ldx % 4 == 0 && ((uintptr_t)X & 15) == 0;
+  dim3 grid;
+  if (fused) {   // one pass over X
+    grid = dim3((unsigned)(ldq / 128), (unsigned)(ldqt / 128));
+    hipLaunchKernelGGL(quant_fp8_fused_kernel, grid, dim3(256), 0, st, X, ldx, m, n, E, tn, tm, Xq, ldq, XqT,
+                       ldqt, sq_out ? sq_part : nullptr);
+  } else {       // tile exponents first, then the codes
+    hipLaunchKernelGGL(tile_exp_kernel, dim3(tn, tm), dim3(256), 0, st, X, ldx, m, n, E, tn);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    grid = dim3((unsigned)ceil_div(ldq, QT), (unsigned)ceil_div(ldqt, QT));
+    hipLaunchKernelGGL(quant_fp8_kernel, grid, dim3(256), 0, st, X, ldx, m, n, E, tn, Xq, ldq, XqT, ldqt,
+                       sq_out ? sq_part : nullptr);
+  }
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  dim3 grid((unsigned)ceil_div(ldq, QT), (unsigned)ceil_div(ldqt, QT));
-  hipLaunchKernelGGL(quant_fp8_kernel, grid, dim3(256), 0, st, X, ldx, m, n, E, tn, Xq, ldq, XqT, ldqt,
-                     sq_out ? sq_part : nullptr);
-  e = hipGetLastError();
   if (e != hipSuccess || !sq_out) return e;
   return launch_sum_partials_f64(sq_part, (int)(grid.x * grid.y), 1, sq_out, nullptr, st);
 }
@@ -338,6 +471,11 @@ hipError_t launch_prep_b_bf16(const float* B, int64_t ldb, int64_t K, int64_t N,
 
 hipError_t launch_prep_b_fp8(const float* B, int64_t ldb, int64_t K, int64_t N, int* Ebt, uint8_t* Bt,
                              int64_t ldbt, hipStream_t st) {
+  if (N <= 128 && ldbt % 128 == 0) {   // one pass; also sets the exponents of the zero padding blocks (0)
+    hipLaunchKernelGGL(prep_bt_fp8_kernel, dim3((unsigned)(ldbt / 128)), dim3(256), 0, st, B, ldb, K, N, Ebt, Bt,
+                       ldbt);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(prep_b_fp8_exp_kernel, dim3((unsigned)ceil_div(K, 128)), dim3(256), 0, st, B, ldb, K,
                      N, Ebt);
   hipError_t e = hipGetLastError();
