@@ -122,7 +122,8 @@ nmf_status nmf_residual(nmf_ctx* ctx, const float* X, int64_t ldx, double* rel_e
  *   e_p^2 = (||X||^2 - ||Xh||^2 + sum_j ||xh_j - Wh h_j||^2) / ||X||^2,
  * with Wh = Q_L^T W of the last H sweep; equal to e when the columns of W lie
  * in range(Q_L), otherwise an approximation (no pass over X).  ||X||^2 is
- * accumulated in FP64 by nmf_compress (during the X Q_R product).  Needs at
+ * accumulated in FP64 by nmf_compress (in the quantiser's pass over X in
+ * low-precision runs with lowp_sketches 1 or 2, else in the X Q_R product).  Needs at
  * least one nmf_step since the last init and a compression by nmf_compress
  * (not nmf_set_state); NMF_ESTATE otherwise.  Synchronising. */
 nmf_status nmf_proxy_residual(nmf_ctx* ctx, double* rel_err);
@@ -133,8 +134,10 @@ nmf_status nmf_proxy_residual(nmf_ctx* ctx, double* rel_err);
  * nmf_compress: until the first exact residual, chunks (5 first, then 1.2
  * times the straight-line extrapolation of the last two proxy values, 5..50)
  * are followed by the sketch-only proxy (nmf_proxy_residual, no pass over X);
- * the first exact residual runs once the proxy is within 1 % of eps, after 100
- * iterations, or at max_iters.  From then on every chunk ends with an exact
+ * the first exact residual runs once the proxy is within 1 % of eps, once
+ * the proxy stalls (not decreasing, or its extrapolation needs more than 50
+ * further iterations: an offset from W's part outside range(Q_L) keeps it
+ * above eps), after 100 iterations, or at max_iters.  From then on every chunk ends with an exact
  * residual and is 1.5 times the iterations a straight-line extrapolation of
  * the last two exact values needs to reach eps (5..50; by the gap to eps:
  * 50, 20, 10, 5 for more than 10 %, 1 %, 0.3 % or less when there is no

@@ -666,11 +666,14 @@ nmf_status fit_proxy_schedule(nmf_ctx* c, const float* X, int64_t ldx, int32_t m
   int t_prev = -1;        // last evaluation (proxy in phase 1, exact in phase 2)
   double v_prev = 0.0;
   bool exact_seen = false;
+  bool far = false;       // the last extrapolation needed more than the largest chunk
   auto extrapolate = [&](double v, int t, double lo, double hi, double fac) {
     const double slope = t_prev >= 0 && t > t_prev ? (v_prev - v) / (t - t_prev) : 0.0;
     int ch;
+    far = t_prev >= 0;
     if (slope > 0) {
       const double need = std::ceil(fac * (v - eps) / slope);
+      far = far && need > hi;
       ch = need < lo ? (int)lo : need > hi ? (int)hi : (int)need;
     } else {
       const double gap = (v - eps) / (eps > 0 ? eps : 1.0);
@@ -689,7 +692,10 @@ nmf_status fit_proxy_schedule(nmf_ctx* c, const float* X, int64_t ldx, int32_t m
       if ((s = nmf_proxy_residual(c, &p)) != NMF_OK) return s;
       if (p > eps * 1.01 && done < 100 && done < max_iters) {
         chunk = extrapolate(p, done, 5, 50, 1.2);
-        continue;
+        // A proxy that would need more than the largest chunk at its current
+        // rate is taken as stalled above eps: its offset from the exact error
+        // (W's part outside range(Q_L)) does not shrink with the iterations.
+        if (!far) continue;
       }
       exact_seen = true;
       t_prev = -1;        // phase 2 extrapolates exact values only
