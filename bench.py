@@ -326,9 +326,10 @@ def kernel_timing(torch, nmfrp, Xd, m, n, kp, reps):
         res[label] = dict(ms=round(ms, 5), tflops=round(flops / (ms * 1e-3) / 1e12, 2),
                           frac_fp32_mfma=round(flops / (ms * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4),
                           x_gbs=round(4.0 * m * n / (ms * 1e-3) / 1e9, 1))
-    Xq, XqT, _ = nmfrp.quantize_x(Xd, nmfrp.NMF_BF16)
+    Xq, _, _ = nmfrp.quantize_x(Xd, nmfrp.NMF_BF16)
     P1 = nmfrp.LowpProduct(nmfrp.NMF_BF16, Xq, n, B_n)
-    P2 = nmfrp.LowpProduct(nmfrp.NMF_BF16, XqT, m, B_m)
+    # X^T B reads the same row-major copy, its tiles transposed in LDS (as in the range finder)
+    P2 = nmfrp.LowpProduct(nmfrp.NMF_BF16, Xq, m, B_m, at=True, Kpad=-(-m // 128) * 128, M=n)
     alg = 2.0 * m * n                     # bytes of X per launch (BF16)
     for label, fn, cnt in (("bf16 X*B (kernel)", P1.run, 1), ("bf16 X^T*B (kernel)", P2.run, 1),
                            ("bf16 both (kernel)", lambda: (P1.run(), P2.run()), 2)):
@@ -340,8 +341,8 @@ def kernel_timing(torch, nmfrp, Xd, m, n, kp, reps):
     achieved = alg / (dom["ms"] * 1e-3) / 1e9
     traffic = measured_traffic()
     res["roofline"] = dict(
-        bound="hbm", kernel="gemm_bf16_nt_kernel<128,64,2,2> (BF16 range-finder product; X B and X^T B "
-                            "alternating, split-K partials)",
+        bound="hbm", kernel="gemm_bf16_nt_kernel<128,64,2,2,*> (BF16 range-finder product; X B and X^T B "
+                            "alternating on the one row-major BF16 copy, split-K partials)",
         achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s", frac=round(achieved / PEAK_HBM_GBS, 4),
         traffic=traffic, algorithmic_bytes_per_launch=alg, units_per_launch=f"{m}x{n} X elements, 2 B each",
         launch_us=round(dom["ms"] * 1e3, 2), splits=[P1.splits, P2.splits],
@@ -358,9 +359,9 @@ def probe_kernels(torch, nmfrp, Xd, m, n, kp, reps):
     dst.copy_(src)
     B_n = torch.randn(n, kp, device=Xd.device)
     B_m = torch.randn(m, kp, device=Xd.device)
-    Xq, XqT, _ = nmfrp.quantize_x(Xd, nmfrp.NMF_BF16)
+    Xq, _, _ = nmfrp.quantize_x(Xd, nmfrp.NMF_BF16)
     P1 = nmfrp.LowpProduct(nmfrp.NMF_BF16, Xq, n, B_n)
-    P2 = nmfrp.LowpProduct(nmfrp.NMF_BF16, XqT, m, B_m)
+    P2 = nmfrp.LowpProduct(nmfrp.NMF_BF16, Xq, m, B_m, at=True, Kpad=-(-m // 128) * 128, M=n)
     for _ in range(reps):
         P1.run()
         P2.run()

@@ -229,6 +229,18 @@ nmf_status nmf_gemm_lowp_prepared(int32_t prec, const void* A, int64_t lda, cons
                                   int64_t ea_k, const void* Bt, const int32_t* EB, int64_t N, float* C,
                                   int64_t ldc, int64_t M, int64_t Kpad, int32_t splits, void* hip_stream);
 
+/* The X^T B product of the BF16 range finder on the row-major BF16 copy itself
+ * (extension): C = A^T Bt^T with A the K x M BF16 matrix (row-major, lda >= M,
+ * lda % 8 == 0, 16-byte aligned; it is read in chunks of 8 columns up to lda,
+ * rows K..Kpad-1 count as zero) and Bt prepared by nmf_lowp_prepare_thin (N x
+ * Kpad, Kpad % 128 == 0, N <= 128).  Tiles of A are transposed while staged
+ * into LDS; the result is bit-identical to nmf_gemm_lowp_prepared on A's
+ * transpose (same tiles, same K order).  splits as for nmf_gemm_lowp_prepared
+ * (nmf_gemm_lowp_splits(M, N, Kpad)): with splits > 1 partial z goes to
+ * C + z M N.  Asynchronous. */
+nmf_status nmf_gemm_bf16_at_prepared(const void* A, int64_t lda, int64_t K, const void* Bt, int64_t N, float* C,
+                                     int64_t ldc, int64_t M, int64_t Kpad, int32_t splits, void* hip_stream);
+
 /* Split-BF16 product on FP32 X (extension; the projected data X^T Q_L and
  * X Q_R of Sec 4 when lowp_sketches = 2): C (M x N, ldc) = op(X) B with
  * at = 0: X is M x K, at = 1: X is K x M (ldx >= columns, ldx % 4 == 0, X

@@ -45,6 +45,9 @@ int gemm_f32_pick_splits(int64_t M, int64_t N, int64_t K, int a_trans);
 int quant_sq_parts(int64_t m, int64_t n, int64_t ldq, int64_t ldqt);
 hipError_t launch_quant_bf16(const float* X, int64_t ldx, int64_t m, int64_t n, uint16_t* Xq,
                              int64_t ldq, uint16_t* XqT, int64_t ldqt, hipStream_t st, double* sq_part = nullptr, double* sq_out = nullptr);
+// Xq only (row-major), for the transposing X^T product: n % 4 == 0, aligned X and Xq.
+hipError_t launch_quant_bf16_rows(const float* X, int64_t ldx, int64_t m, int64_t n, uint16_t* Xq, int64_t ldq,
+                                  hipStream_t st, double* sq_part = nullptr, double* sq_out = nullptr);
 // E: ceil(m/128) x ceil(n/128) tile exponents (row-major).
 hipError_t launch_quant_fp8(const float* X, int64_t ldx, int64_t m, int64_t n, int* E, uint8_t* Xq,
                             int64_t ldq, uint8_t* XqT, int64_t ldqt, hipStream_t st, double* sq_part = nullptr, double* sq_out = nullptr);
@@ -77,9 +80,12 @@ int gemm_split_sq_parts(int64_t M, int splits);
 hipError_t launch_gemm_split(const float* X, int64_t ldx, int at, const uint16_t* BtH, const uint16_t* BtL,
                              int64_t ldbt, float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, int splits,
                              float* part, hipStream_t st, double* sq = nullptr);
+// a_trans = 1 (N <= 128): A is the K x lda copy of X itself (C = A^T Bt^T, M
+// columns of A, rows at or past K read as zero), not a K-contiguous copy.
 hipError_t launch_gemm_bf16_nt(const uint16_t* A, int64_t lda, const uint16_t* Bt, int64_t ldbt,
                                float* C, int64_t ldc, int64_t M, int64_t N, int64_t Kpad, int splits,
-                               float* part, hipStream_t st, bool reduce = true);
+                               float* part, hipStream_t st, bool reduce = true, int a_trans = 0,
+                               int64_t K = 0);
 // EA: exponent of A's 128 x 128 tile (ti, tk) at EA[ti * ea_i + tk * ea_k]; EB per 128-row block.
 hipError_t launch_gemm_fp8_nt(const uint8_t* A, int64_t lda, const int* EA, int64_t ea_i, int64_t ea_k,
                               const uint8_t* Bt, int64_t ldbt, const int* EB, float* C, int64_t ldc,

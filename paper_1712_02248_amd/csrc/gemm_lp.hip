@@ -18,11 +18,18 @@
 namespace {
 
 // ------------------------------------------------------------------------- BF16
-template <int BM, int BN, int WM, int WN>
+// AT = false: A is M x Kpad (K-contiguous).  AT = true: A is K x lda (the copy
+// of X itself, for X^T B): a thread loads rows 4 (t / 16) .. +3, columns
+// 8 (t % 16) .. +7 of the 64 x 128 tile and writes their transpose, eight 4-value
+// runs, into LDS; row i of the LDS tile keeps its 16-byte k chunks XOR-swizzled
+// by (i / 8) % 8, which spreads those 8-byte stores over the banks while the
+// MFMA fragment reads stay 16-byte aligned.  Rows at or past K and column
+// chunks past lda read as zero.
+template <int BM, int BN, int WM, int WN, bool AT>
 __global__ void __launch_bounds__(256)
 gemm_bf16_nt_kernel(const uint16_t* __restrict__ A, int64_t lda, const uint16_t* __restrict__ Bt,
                     int64_t ldbt, float* __restrict__ C, int64_t ldc, int64_t M, int64_t N,
-                    int64_t Kpad, int64_t kchunk, int rot_xcd) {
+                    int64_t Kpad, int64_t kchunk, int rot_xcd, int64_t K) {
   constexpr int BK = 64, ROW = BK + 8;                    // u16 per LDS row
   constexpr int TM = BM / WM / 32, TN = BN / WN / 32;
   constexpr int AV = BM * BK / 8 / 256, BV = BN * BK / 8 / 256;   // 16-byte loads per thread
@@ -44,12 +51,18 @@ gemm_bf16_nt_kernel(const uint16_t* __restrict__ A, int64_t lda, const uint16_t*
   // two K steps in flight in registers (R0, R1) while the LDS tile is consumed
   i32x4 ra0[AV], rb0[BV], ra1[AV], rb1[BV];
   const i32x4 z4 = {0, 0, 0, 0};
+  static_assert(!AT || (BM == 128 && AV == 4), "transposed A: 128-wide tiles, four rows per thread");
   auto load = [&](i32x4* ra, i32x4* rb, int64_t k0) {
 #pragma unroll
     for (int p = 0; p < AV; ++p) {
-      const int f = tid + 256 * p, row = f / (BK / 8), c8 = f % (BK / 8);
-      const int64_t gi = i0 + row;
-      ra[p] = gi < M ? __builtin_nontemporal_load((const i32x4*)(A + gi * lda + k0 + 8 * c8)) : z4;
+      if (!AT) {
+        const int f = tid + 256 * p, row = f / (BK / 8), c8 = f % (BK / 8);
+        const int64_t gi = i0 + row;
+        ra[p] = gi < M ? __builtin_nontemporal_load((const i32x4*)(A + gi * lda + k0 + 8 * c8)) : z4;
+      } else {
+        const int64_t gk = k0 + 4 * (tid >> 4) + p, gi = i0 + 8 * (tid & 15);
+        ra[p] = (gk < K && gi + 8 <= lda) ? __builtin_nontemporal_load((const i32x4*)(A + gk * lda + gi)) : z4;
+      }
     }
 #pragma unroll
     for (int p = 0; p < BV; ++p) {
@@ -59,10 +72,24 @@ gemm_bf16_nt_kernel(const uint16_t* __restrict__ A, int64_t lda, const uint16_t*
     }
   };
   auto store = [&](const i32x4* ra, const i32x4* rb) {
+    if (!AT) {
 #pragma unroll
-    for (int p = 0; p < AV; ++p) {
-      const int f = tid + 256 * p, row = f / (BK / 8), c8 = f % (BK / 8);
-      *(i32x4*)(As + row * ROW + 8 * c8) = ra[p];
+      for (int p = 0; p < AV; ++p) {
+        const int f = tid + 256 * p, row = f / (BK / 8), c8 = f % (BK / 8);
+        *(i32x4*)(As + row * ROW + 8 * c8) = ra[p];
+      }
+    } else {
+      // column c of the thread's chunk: tile row i = 8 (t % 16) + c gets k = 4 g .. 4 g + 3
+      const int cl = tid & 15, g = tid >> 4;
+      const int koff = 8 * ((g >> 1) ^ (cl & 7)) + 4 * (g & 1);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int sh = 16 * (c & 1);
+        uint32_t v[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) v[p] = ((uint32_t)ra[p][c >> 1] >> sh) & 0xFFFFu;
+        *(uint2*)(As + (8 * cl + c) * ROW + koff) = make_uint2(v[0] | (v[1] << 16), v[2] | (v[3] << 16));
+      }
     }
 #pragma unroll
     for (int p = 0; p < BV; ++p) {
@@ -78,7 +105,8 @@ gemm_bf16_nt_kernel(const uint16_t* __restrict__ A, int64_t lda, const uint16_t*
 #pragma unroll
       for (int a = 0; a < TM; ++a) {
         const int il = wm * (BM / WM) + a * 32 + l32;
-        af[a] = *(const bf16x8*)(As + il * ROW + ks * 16 + 8 * half);
+        const int kc = AT ? ((2 * ks + half) ^ ((il >> 3) & 7)) : (2 * ks + half);
+        af[a] = *(const bf16x8*)(As + il * ROW + 8 * kc);
       }
 #pragma unroll
       for (int b = 0; b < TN; ++b) {
@@ -310,9 +338,10 @@ int gemm_lp_pick_splits(int64_t M, int64_t N, int64_t Kpad, int bm) {
 
 hipError_t launch_gemm_bf16_nt(const uint16_t* A, int64_t lda, const uint16_t* Bt, int64_t ldbt,
                                float* C, int64_t ldc, int64_t M, int64_t N, int64_t Kpad, int splits,
-                               float* part, hipStream_t st, bool reduce) {
+                               float* part, hipStream_t st, bool reduce, int a_trans, int64_t K) {
   if (M == 0 || N == 0) return hipSuccess;
   if (N > 256 || Kpad % 64 || lda % 8 || ldbt % 8) return hipErrorInvalidValue;
+  if (a_trans && (N > 128 || K < 0 || K > Kpad)) return hipErrorInvalidValue;
   float* out = splits > 1 ? part : C;
   const int64_t ldo = splits > 1 ? N : ldc;
   const int64_t kchunk = round_up(ceil_div(Kpad, splits), 64);
@@ -320,12 +349,25 @@ hipError_t launch_gemm_bf16_nt(const uint16_t* A, int64_t lda, const uint16_t* B
   const int bm = bn <= 128 ? 128 : 64;
   dim3 grid((unsigned)ceil_div(M, bm), (unsigned)ceil_div(N, bn), (unsigned)splits);
   const int rx = rot_per_xcd(N, kchunk, splits, 2);
-  switch (bn) {
-    case 32: hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 32, 4, 1>), grid, dim3(256), 0, st, A, lda, Bt, ldbt, out, ldo, M, N, Kpad, kchunk, rx); break;
-    case 64: hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 64, 2, 2>), grid, dim3(256), 0, st, A, lda, Bt, ldbt, out, ldo, M, N, Kpad, kchunk, rx); break;
-    case 128: hipLaunchKernelGGL((gemm_bf16_nt_kernel<128, 128, 2, 2>), grid, dim3(256), 0, st, A, lda, Bt, ldbt, out, ldo, M, N, Kpad, kchunk, rx); break;
-    default: hipLaunchKernelGGL((gemm_bf16_nt_kernel<64, 256, 1, 4>), grid, dim3(256), 0, st, A, lda, Bt, ldbt, out, ldo, M, N, Kpad, kchunk, rx); break;
+  const int64_t kk = a_trans ? K : Kpad;
+#define NMF_BF16_LAUNCH(BM_, BN_, WM_, WN_, AT_)                                                              \
+  hipLaunchKernelGGL((gemm_bf16_nt_kernel<BM_, BN_, WM_, WN_, AT_>), grid, dim3(256), 0, st, A, lda, Bt, ldbt, \
+                     out, ldo, M, N, Kpad, kchunk, rx, kk)
+  if (a_trans) {
+    switch (bn) {
+      case 32: NMF_BF16_LAUNCH(128, 32, 4, 1, true); break;
+      case 64: NMF_BF16_LAUNCH(128, 64, 2, 2, true); break;
+      default: NMF_BF16_LAUNCH(128, 128, 2, 2, true); break;
+    }
+  } else {
+    switch (bn) {
+      case 32: NMF_BF16_LAUNCH(128, 32, 4, 1, false); break;
+      case 64: NMF_BF16_LAUNCH(128, 64, 2, 2, false); break;
+      case 128: NMF_BF16_LAUNCH(128, 128, 2, 2, false); break;
+      default: NMF_BF16_LAUNCH(64, 256, 1, 4, false); break;
+    }
   }
+#undef NMF_BF16_LAUNCH
   if (!reduce) return hipGetLastError();
   return finish(part, splits, C, ldc, M, N, st);
 }

@@ -137,7 +137,8 @@ Layout make_layout(const nmf_params* p) {
   if (p->prec != NMF_FP32) {
     const size_t es = p->prec == NMF_BF16 ? 2 : 1;
     L.Xq = pl.take((size_t)m * L.ldq * es);
-    L.XqT = pl.take((size_t)n * L.ldqt * es);
+    // BF16: X^T products read Xq through the transposing kernel; FP8 keeps X^T too
+    L.XqT = p->prec == NMF_BF16 ? 0 : pl.take((size_t)n * L.ldqt * es);
     L.Ex = pl.take((size_t)ceil_div(m, 128) * ceil_div(n, 128) * sizeof(int));
     L.Bt = pl.take((size_t)k * (L.ldq > L.ldqt ? L.ldq : L.ldqt) * es);
     L.Eb = pl.take((size_t)ceil_div(L.ldq > L.ldqt ? L.ldq : L.ldqt, 128) * sizeof(int));
@@ -252,8 +253,9 @@ hipError_t gemm_lowp(nmf_ctx* c, const Chain& ch, int side, const float* B, floa
   if (c->p.prec == NMF_BF16) {
     uint16_t* Bt = (uint16_t*)ch.Bt;
     if ((e = launch_prep_b_bf16(B, L.KP, K, k, Bt, Kpad, ch.st))) return e;
-    const uint16_t* A = side ? c->at<uint16_t>(L.XqT) : c->at<uint16_t>(L.Xq);
-    return launch_gemm_bf16_nt(A, Kpad, Bt, Kpad, C, L.KP, M, k, Kpad, s, part, ch.st);
+    // X B: Xq rows are K-contiguous; X^T B: the same Xq, transposed while staged
+    return launch_gemm_bf16_nt(c->at<uint16_t>(L.Xq), L.ldq, Bt, Kpad, C, L.KP, M, k, Kpad, s, part, ch.st, true,
+                               side, K);
   }
   uint8_t* Bt = (uint8_t*)ch.Bt;
   int* Eb = ch.Eb;
@@ -397,8 +399,7 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
     double* sqp = xsq_quant ? c->at<double>(L.xsq_part) : nullptr;
     double* sqo = xsq_quant ? c->at<double>(L.proxy_out) + 2 : nullptr;
     if (c->p.prec == NMF_BF16)
-      HIPCHK(c, launch_quant_bf16(X, ldx, m, n, c->at<uint16_t>(L.Xq), L.ldq, c->at<uint16_t>(L.XqT),
-                                  L.ldqt, st, sqp, sqo));
+      HIPCHK(c, launch_quant_bf16_rows(X, ldx, m, n, c->at<uint16_t>(L.Xq), L.ldq, st, sqp, sqo));
     else
       HIPCHK(c, launch_quant_fp8(X, ldx, m, n, c->at<int>(L.Ex), c->at<uint8_t>(L.Xq), L.ldq,
                                  c->at<uint8_t>(L.XqT), L.ldqt, st, sqp, sqo));
@@ -953,6 +954,18 @@ nmf_status nmf_lowp_prepare_thin(int32_t prec, const float* B, int64_t ldb, int6
 int32_t nmf_gemm_lowp_splits(int64_t M, int64_t N, int64_t Kpad) {
   if (M <= 0 || N <= 0 || Kpad <= 0) return 1;
   return gemm_lp_pick_splits(M, N, Kpad, 128);
+}
+
+nmf_status nmf_gemm_bf16_at_prepared(const void* A, int64_t lda, int64_t K, const void* Bt, int64_t N, float* C,
+                                     int64_t ldc, int64_t M, int64_t Kpad, int32_t splits, void* hs) {
+  if (M < 0 || N <= 0 || N > 128 || K < 0 || Kpad < K || Kpad % 128 || lda < M || lda % 8 || splits < 1 ||
+      splits > 64 || (splits == 1 && ldc < N))
+    return fail(nullptr, NMF_EINVAL, "bad arguments");
+  if (M == 0) return NMF_OK;
+  if (!A || !Bt || !C || ((uintptr_t)A & 15)) return fail(nullptr, NMF_EINVAL, "null pointer or A not 16-byte aligned");
+  const hipError_t e = launch_gemm_bf16_nt((const uint16_t*)A, lda, (const uint16_t*)Bt, Kpad, C, ldc, M, N, Kpad,
+                                           splits, C, (hipStream_t)hs, false, 1, K);
+  return e ? fail(nullptr, NMF_EHIP, hipGetErrorString(e)) : NMF_OK;
 }
 
 nmf_status nmf_gemm_lowp_prepared(int32_t prec, const void* A, int64_t lda, const int32_t* EA, int64_t ea_i,

@@ -61,6 +61,7 @@ _SIGS = {
     "nmf_gemm_lowp_splits": (c_i32, [c_i64, c_i64, c_i64]),
     "nmf_gemm_lowp_prepared": (c_i32, [c_i32, c_vp, c_i64, c_vp, c_i64, c_i64, c_vp, c_vp, c_i64, c_vp, c_i64,
                                        c_i64, c_i64, c_i32, c_vp]),
+    "nmf_gemm_bf16_at_prepared": (c_i32, [c_vp, c_i64, c_i64, c_vp, c_i64, c_vp, c_i64, c_i64, c_i64, c_i32, c_vp]),
     "nmf_gemm_split_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64]),
     "nmf_gemm_split": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_i64, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp, c_sz, c_vp]),
     "nmf_orth_workspace_bytes": (c_sz, [c_i64, c_i32]),
@@ -477,10 +478,17 @@ class LowpProduct:
     low-precision copy from quantize_x.  run() launches only the product kernel
     (split-K partials, if any, land in self.part and are summed by result())."""
 
-    def __init__(self, prec, A, K, B, E=None, ea=(0, 0), stream=None):
+    def __init__(self, prec, A, K, B, E=None, ea=(0, 0), stream=None, at=False, Kpad=None, M=None):
+        """at=True (BF16): A is the row-major copy itself, C = A[:K, :M]^T B (M
+        defaults to A's width), its tiles transposed by the product kernel; Kpad
+        is then the thin operand's padded length (a multiple of 128, >= K)."""
         lib = load()
-        self.prec, self.A, self.E, self.ea, self.stream = prec, A, E, ea, stream
-        self.M, self.Kpad = A.shape
+        self.prec, self.A, self.E, self.ea, self.stream, self.at, self.K = prec, A, E, ea, stream, at, K
+        if at:
+            self.M = A.shape[1] if M is None else M
+            self.Kpad = Kpad if Kpad is not None else -(-K // 128) * 128
+        else:
+            self.M, self.Kpad = A.shape
         self.N = B.shape[1]
         dt = torch.int16 if prec == NMF_BF16 else torch.uint8
         self.Bt = torch.zeros(self.N, self.Kpad, dtype=dt, device=A.device)
@@ -491,6 +499,11 @@ class LowpProduct:
         self.part = torch.empty(self.splits, self.M, self.N, dtype=torch.float32, device=A.device)
 
     def run(self):
+        if self.at:
+            _check(load().nmf_gemm_bf16_at_prepared(_ptr(self.A), self.A.stride(0), self.K, _ptr(self.Bt), self.N,
+                                                    _ptr(self.part), self.N, self.M, self.Kpad, self.splits,
+                                                    _stream(self.stream)))
+            return
         _check(load().nmf_gemm_lowp_prepared(self.prec, _ptr(self.A), self.A.stride(0), _ptr(self.E), self.ea[0],
                                              self.ea[1], _ptr(self.Bt), _ptr(self.EB), self.N, _ptr(self.part),
                                              self.N, self.M, self.Kpad, self.splits, _stream(self.stream)))

@@ -103,6 +103,26 @@ def test_prepared_product_matches_full_product(lib, fmt, m, n, k, side):
     assert np.array_equal(acc, full)
 
 
+@pytest.mark.parametrize("m,n,k", [(1000, 300, 64), (4096, 512, 32), (300, 200, 20), (513, 700, 128),
+                                   (130, 8, 5), (65, 1028, 64)])
+def test_transposed_product_matches_transposed_copy(lib, m, n, k):
+    """X^T B on the row-major BF16 copy (tiles transposed in LDS) is bit-identical
+    to the product on the transposed copy XqT: same tiles, same K order, rows past
+    m read as zero either way."""
+    print(f"bf16 X^T B transposed-in-LDS {m}x{n} k={k}", flush=True)
+    X = _x(m, n, 5 * m + n, spread=False)
+    Xq, XqT, _ = lib.quantize_x(torch.from_numpy(X).cuda(), lib.NMF_BF16)
+    B = torch.from_numpy(np.random.default_rng(m + k).standard_normal((m, k)).astype(np.float32)).cuda()
+    ref = lib.LowpProduct(lib.NMF_BF16, XqT, m, B)
+    at = lib.LowpProduct(lib.NMF_BF16, Xq, m, B, at=True, Kpad=XqT.shape[1], M=n)
+    assert at.splits == ref.splits and at.M == ref.M
+    assert torch.equal(at.Bt, ref.Bt)
+    ref.run()
+    at.run()
+    torch.cuda.synchronize()
+    assert torch.equal(at.part, ref.part)
+
+
 @pytest.mark.parametrize("rows,cols,k", [(300, 200, 64), (1000, 36, 20), (77, 130, 5), (2, 4, 1), (4096, 256, 64)])
 def test_prepared_thin_operand_bit_exact(lib, rows, cols, k):
     """The transposed BF16 copy of a thin operand (K x k) is torch's
