@@ -103,8 +103,11 @@ hipError_t launch_atb_f32out(const float* A, int64_t lda, int ka, const float* B
                              int64_t rows, double* part, int splits, double* C64, float* C, hipStream_t st);
 hipError_t launch_cholesky(const double* G, int k, int64_t rows, double* Rinv, int* status,
                            int attempt, hipStream_t st);
+// Bt != NULL (k <= 64): write the transposed BF16 copy of the result (k x ldbt,
+// ldbt % 64 == 0, zero past rows) instead of Y, for the next BF16 product.
 hipError_t launch_apply_rinv(float* Y, int64_t ldy, int64_t rows, int k, const double* Rinv,
-                             const int* status, int attempt, hipStream_t st);
+                             const int* status, int attempt, hipStream_t st, uint16_t* Bt = nullptr,
+                             int64_t ldbt = 0);
 
 // Fused HALS half-step (hals.hip).  The kernel derives its compressed factor C
 // and Gram G from the other side's summed partials (acc_in), sweeps the rows of

@@ -195,8 +195,12 @@ nmf_status fail(nmf_ctx* c, nmf_status s, const std::string& msg) {
 // final (an intermediate basis of the subspace iteration, which only has to
 // span the same space and be well conditioned): one CholeskyQR pass, shifted
 // on breakdown; its orthogonality error is about kappa(Y)^2 u_fp64.
+//
+// bt (intermediate bases only): the basis is written only as the transposed
+// BF16 operand of the next product (k x ldbt), not back into Y.
 hipError_t orth(float* Y, int64_t ld, int64_t rows, int k, double* gram_part, double* G,
-                double* R, int* status, hipStream_t st, bool final = true) {
+                double* R, int* status, hipStream_t st, bool final = true, uint16_t* bt = nullptr,
+                int64_t ldbt = 0) {
   hipError_t e;
   const int splits = gram_pick_splits(rows, k);
   const int passes = final ? 3 : 1;       // the first pass resets the shift flags
@@ -204,7 +208,7 @@ hipError_t orth(float* Y, int64_t ld, int64_t rows, int k, double* gram_part, do
     if ((e = launch_gram_f64(Y, ld, rows, k, gram_part, splits, G, attempt == 2 ? status : nullptr, st)))
       return e;
     if ((e = launch_cholesky(G, k, rows, R, status, attempt, st))) return e;
-    if ((e = launch_apply_rinv(Y, ld, rows, k, R, status, attempt, st))) return e;
+    if ((e = launch_apply_rinv(Y, ld, rows, k, R, status, attempt, st, final ? nullptr : bt, ldbt))) return e;
   }
   return hipSuccess;
 }
@@ -243,7 +247,7 @@ hipError_t gemm(nmf_ctx* c, const Chain& ch, const float* A, int64_t lda, int at
 
 // Low-precision range-finder product: side 0 -> X B (B is n x k'), side 1 ->
 // X^T B (B is m x k'); the thin operand is rounded (and transposed) first.
-hipError_t gemm_lowp(nmf_ctx* c, const Chain& ch, int side, const float* B, float* C) {
+hipError_t gemm_lowp(nmf_ctx* c, const Chain& ch, int side, const float* B, float* C, bool prepared = false) {
   Layout& L = c->L;
   const int64_t m = c->p.m, n = c->p.n, k = c->p.k_sketch;
   const int64_t M = side ? n : m, K = side ? m : n, Kpad = side ? L.ldqt : L.ldq;
@@ -252,7 +256,8 @@ hipError_t gemm_lowp(nmf_ctx* c, const Chain& ch, int side, const float* B, floa
   hipError_t e;
   if (c->p.prec == NMF_BF16) {
     uint16_t* Bt = (uint16_t*)ch.Bt;
-    if ((e = launch_prep_b_bf16(B, L.KP, K, k, Bt, Kpad, ch.st))) return e;
+    // prepared: the orthonormalisation that produced B already wrote its BF16 copy
+    if (!prepared && (e = launch_prep_b_bf16(B, L.KP, K, k, Bt, Kpad, ch.st))) return e;
     // X B: Xq rows are K-contiguous; X^T B: the same Xq, transposed while staged
     return launch_gemm_bf16_nt(c->at<uint16_t>(L.Xq), L.ldq, Bt, Kpad, C, L.KP, M, k, Kpad, s, part, ch.st, true,
                                side, K);
@@ -405,13 +410,20 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
                                  c->at<uint8_t>(L.XqT), L.ldqt, st, sqp, sqo));
   }
   const Chain cl = chain(c, 0), cr = chain(c, 1);
-  auto XB = [&](const Chain& ch, const float* B, float* C) -> hipError_t {            // X B  (m x k')
-    return lp ? gemm_lowp(c, ch, 0, B, C) : gemm(c, ch, X, ldx, 0, B, C, m, n);
+  // BF16 range finder: an intermediate basis whose next consumer is a BF16
+  // product is written only as that product's transposed BF16 operand
+  const bool fuse = c->p.prec == NMF_BF16 && k <= 64;
+  auto XB = [&](const Chain& ch, const float* B, float* C, bool prep) -> hipError_t {   // X B  (m x k')
+    return lp ? gemm_lowp(c, ch, 0, B, C, prep) : gemm(c, ch, X, ldx, 0, B, C, m, n);
   };
-  auto XtB = [&](const Chain& ch, const float* B, float* C) -> hipError_t {           // X^T B (n x k')
-    return lp ? gemm_lowp(c, ch, 1, B, C) : gemm(c, ch, X, ldx, 1, B, C, n, m);
+  auto XtB = [&](const Chain& ch, const float* B, float* C, bool prep) -> hipError_t {  // X^T B (n x k')
+    return lp ? gemm_lowp(c, ch, 1, B, C, prep) : gemm(c, ch, X, ldx, 1, B, C, n, m);
   };
-  auto ORTH = [&](const Chain& ch, float* Y, int64_t rows, bool final) -> hipError_t {
+  // next_lp: the basis feeds a low-precision product next
+  auto ORTH = [&](const Chain& ch, float* Y, int64_t rows, bool final, bool next_lp) -> hipError_t {
+    if (!final && fuse && next_lp)
+      return orth(Y, L.KP, rows, k, ch.gp, ch.G, ch.R, ch.qs, ch.st, false, (uint16_t*)ch.Bt,
+                  rows == m ? L.ldqt : L.ldq);
     return orth(Y, L.KP, rows, k, ch.gp, ch.G, ch.R, ch.qs, ch.st, final);
   };
   const bool refine = lp && c->p.refine_fp32;
@@ -423,25 +435,37 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
   std::vector<Stage> left, right;
   const bool last0 = q == 0 && !refine;
   // (the left chain's first stage is enqueued by hand below, around the fork)
-  right.push_back([&, last0] { hipError_t e = XtB(cr, omR, QR); return e ? e : ORTH(cr, QR, n, last0); });
+  const bool q0 = q > 0;      // the first basis feeds the power iterations
+  const bool pf = fuse;       // products after a fused orthonormalisation find B prepared
+  right.push_back([&, last0, q0] {
+    hipError_t e = XtB(cr, omR, QR, false);
+    return e ? e : ORTH(cr, QR, n, last0, q0);
+  });
   for (int it = 0; it < q; ++it) {
     const bool last = it == q - 1 && !refine;
-    left.push_back([&] { hipError_t e = XtB(cl, QL, TN); return e ? e : ORTH(cl, TN, n, false); });
-    left.push_back([&, last] { hipError_t e = XB(cl, TN, QL); return e ? e : ORTH(cl, QL, m, last); });
-    right.push_back([&] { hipError_t e = XB(cr, QR, TM); return e ? e : ORTH(cr, TM, m, false); });
-    right.push_back([&, last] { hipError_t e = XtB(cr, TM, QR); return e ? e : ORTH(cr, QR, n, last); });
+    const bool more = it < q - 1;   // another power iteration follows
+    left.push_back([&, pf] { hipError_t e = XtB(cl, QL, TN, pf); return e ? e : ORTH(cl, TN, n, false, true); });
+    left.push_back([&, last, more, pf] {
+      hipError_t e = XB(cl, TN, QL, pf);
+      return e ? e : ORTH(cl, QL, m, last, more);
+    });
+    right.push_back([&, pf] { hipError_t e = XB(cr, QR, TM, pf); return e ? e : ORTH(cr, TM, m, false, true); });
+    right.push_back([&, last, more, pf] {
+      hipError_t e = XtB(cr, TM, QR, pf);
+      return e ? e : ORTH(cr, QR, n, last, more);
+    });
   }
   if (refine) {   // optional FP32 refinement: one power iteration per side on the exact X
-    left.push_back([&] { hipError_t e = gemm(c, cl, X, ldx, 1, QL, TN, n, m); return e ? e : ORTH(cl, TN, n, false); });
-    left.push_back([&] { hipError_t e = gemm(c, cl, X, ldx, 0, TN, QL, m, n); return e ? e : ORTH(cl, QL, m, true); });
-    right.push_back([&] { hipError_t e = gemm(c, cr, X, ldx, 0, QR, TM, m, n); return e ? e : ORTH(cr, TM, m, false); });
-    right.push_back([&] { hipError_t e = gemm(c, cr, X, ldx, 1, TM, QR, n, m); return e ? e : ORTH(cr, QR, n, true); });
+    left.push_back([&] { hipError_t e = gemm(c, cl, X, ldx, 1, QL, TN, n, m); return e ? e : ORTH(cl, TN, n, false, false); });
+    left.push_back([&] { hipError_t e = gemm(c, cl, X, ldx, 0, TN, QL, m, n); return e ? e : ORTH(cl, QL, m, true, false); });
+    right.push_back([&] { hipError_t e = gemm(c, cr, X, ldx, 0, QR, TM, m, n); return e ? e : ORTH(cr, TM, m, false, false); });
+    right.push_back([&] { hipError_t e = gemm(c, cr, X, ldx, 1, TM, QR, n, m); return e ? e : ORTH(cr, QR, n, true, false); });
   }
   // projected data (Sec 4): Xh = X^T Q_L (X-hat^T), Xc = X Q_R (X-check); FP32 on X,
   // or on the low-precision copy like the range finder (lowp_sketches)
   if (lps) {
-    left.push_back([&] { return XtB(cl, QL, Xh); });
-    right.push_back([&] { return XB(cr, QR, Xc); });
+    left.push_back([&] { return XtB(cl, QL, Xh, false); });
+    right.push_back([&] { return XB(cr, QR, Xc, false); });
   } else if (split) {   // split-BF16 products on X
     left.push_back([&] {
       uint16_t* H = c->at<uint16_t>(L.St);
@@ -476,10 +500,10 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
   // each chain's latency-bound orthonormalisations run under the other's
   // products.  The host enqueues the stages alternately so that neither stream
   // waits for the host to finish the other's list.
-  HIPCHK(c, XB(cl, omL, QL));
+  HIPCHK(c, XB(cl, omL, QL, false));
   HIPCHK(c, hipEventRecord(c->fork, st));
   HIPCHK(c, hipStreamWaitEvent(c->st2, c->fork, 0));
-  HIPCHK(c, ORTH(cl, QL, m, last0));
+  HIPCHK(c, ORTH(cl, QL, m, last0, q0));
   for (size_t i = 0; i < right.size(); ++i) {
     HIPCHK(c, right[i]());
     if (i < left.size()) HIPCHK(c, left[i]());

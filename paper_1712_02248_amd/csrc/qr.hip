@@ -254,10 +254,15 @@ cholesky_kernel(const double* __restrict__ G, int k, int64_t rows, double* __res
 // write, so rows of other workgroups are never touched.  The tile is staged with
 // batched float4 loads (ldy % 4 == 0); for k <= 64 R^{-1} is staged in LDS too
 // (row stride KMAX + 2 doubles), larger k reads it from L2.
-template <int KMAX>
+// BT = true: instead of Y, write the transposed BF16 copy Bt (k x ldbt, nearest
+// even; the operand of the next low-precision product): the tile of Q goes
+// through LDS (row stride KMAX + 2 halves) and out as 16-byte chunks of Bt's
+// rows.  The grid then covers all ldbt columns, rows past `rows` giving zeros.
+template <int KMAX, bool BT>
 __global__ void __launch_bounds__(256)
 apply_rinv_kernel(float* __restrict__ Y, int64_t ldy, int64_t rows, int k,
-                  const double* __restrict__ Rinv, const int* __restrict__ status, int attempt) {
+                  const double* __restrict__ Rinv, const int* __restrict__ status, int attempt,
+                  uint16_t* __restrict__ Bt, int64_t ldbt) {
   if (status[1] != 0) return;
   if (attempt == 1 && status[3] != 0) return;   // second pass not needed
   if (attempt == 2 && status[0] == 0) return;
@@ -310,14 +315,40 @@ apply_rinv_kernel(float* __restrict__ Y, int64_t ldy, int64_t rows, int k,
     }
   }
   // D[i][j] in lane j + 16 (i % 4), register i / 4
+  if (!BT) {
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
+    for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t gi = row0 + wave * 16 + 4 * q + (lane >> 4);
-      const int j = t * 16 + (lane & 15);
-      if (gi < rows && j < k) Y[gi * ldy + j] = (float)acc[t][q];
+      for (int q = 0; q < 4; ++q) {
+        const int64_t gi = row0 + wave * 16 + 4 * q + (lane >> 4);
+        const int j = t * 16 + (lane & 15);
+        if (gi < rows && j < k) Y[gi * ldy + j] = (float)acc[t][q];
+      }
+  } else {
+    // Tb[j][i] = bf16(Q[row0 + i][j]) in the (now free) Ys tile; row stride 66 halves
+    constexpr int TS = 66;
+    static_assert(KMAX * TS * 2 <= 64 * (KMAX + 4) * 4, "Tb must fit in Ys");
+    uint16_t* Tb = reinterpret_cast<uint16_t*>(&Ys[0][0]);
+    __syncthreads();   // every wave is done reading Ys
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = wave * 16 + 4 * q + (lane >> 4), j = t * 16 + (lane & 15);
+        float v = (row0 + i < rows) ? (float)acc[t][q] : 0.f;
+        // round to FP32 first, then to BF16, as the unfused path (FP32 basis, then
+        // its BF16 copy) does; without the barrier the two roundings merge into one
+        asm volatile("" : "+v"(v));
+        Tb[j * TS + i] = __builtin_bit_cast(uint16_t, (__bf16)v);
+      }
+    __syncthreads();
+    for (int e = tid; e < k * 8; e += 256) {       // row j of Bt: 64 halves = 8 chunks of 16 bytes
+      const int j = e >> 3, c = e & 7;
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(Tb + j * TS + 8 * c);
+      const i32x4 o = {(int)src[0], (int)src[1], (int)src[2], (int)src[3]};
+      *(i32x4*)(Bt + j * ldbt + row0 + 8 * c) = o;
     }
+  }
 }
 
 }  // namespace
@@ -384,18 +415,30 @@ hipError_t launch_cholesky(const double* G, int k, int64_t rows, double* Rinv, i
 }
 
 hipError_t launch_apply_rinv(float* Y, int64_t ldy, int64_t rows, int k, const double* Rinv,
-                             const int* status, int attempt, hipStream_t st) {
+                             const int* status, int attempt, hipStream_t st, uint16_t* Bt, int64_t ldbt) {
+  if (Bt) {   // transposed BF16 operand instead of Y: the grid covers ldbt columns (ldbt % 64 == 0)
+    if (k > 64 || ldbt % 64 || ldbt < rows || ((uintptr_t)Bt & 15)) return hipErrorInvalidValue;
+    const unsigned g = (unsigned)(ldbt / 64);
+    if (g == 0) return hipSuccess;
+    if (k <= 32)
+      hipLaunchKernelGGL((apply_rinv_kernel<32, true>), dim3(g), dim3(256), 0, st, Y, ldy, rows, k, Rinv, status,
+                         attempt, Bt, ldbt);
+    else
+      hipLaunchKernelGGL((apply_rinv_kernel<64, true>), dim3(g), dim3(256), 0, st, Y, ldy, rows, k, Rinv, status,
+                         attempt, Bt, ldbt);
+    return hipGetLastError();
+  }
   const unsigned g = (unsigned)ceil_div(rows, 64);
   if (g == 0) return hipSuccess;
   if (k <= 32)
-    hipLaunchKernelGGL(apply_rinv_kernel<32>, dim3(g), dim3(256), 0, st, Y, ldy, rows, k, Rinv, status,
-                       attempt);
+    hipLaunchKernelGGL((apply_rinv_kernel<32, false>), dim3(g), dim3(256), 0, st, Y, ldy, rows, k, Rinv, status,
+                       attempt, nullptr, 0);
   else if (k <= 64)
-    hipLaunchKernelGGL(apply_rinv_kernel<64>, dim3(g), dim3(256), 0, st, Y, ldy, rows, k, Rinv, status,
-                       attempt);
+    hipLaunchKernelGGL((apply_rinv_kernel<64, false>), dim3(g), dim3(256), 0, st, Y, ldy, rows, k, Rinv, status,
+                       attempt, nullptr, 0);
   else if (k <= 128)
-    hipLaunchKernelGGL(apply_rinv_kernel<128>, dim3(g), dim3(256), 0, st, Y, ldy, rows, k, Rinv, status,
-                       attempt);
+    hipLaunchKernelGGL((apply_rinv_kernel<128, false>), dim3(g), dim3(256), 0, st, Y, ldy, rows, k, Rinv, status,
+                       attempt, nullptr, 0);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -283,33 +283,30 @@ prep_b_fp8_kernel(const float* __restrict__ B, int64_t ldb, int64_t K, int64_t N
 }
 
 // Row-major BF16 copy of X only (Xq, m x ldq, zero padding columns), for runs
-// whose X^T products read Xq through the transposing product kernel.  A
-// workgroup converts 32 rows, eight values per thread and step (two float4
-// loads, one 16-byte store); n % 4 == 0, X 16-byte aligned, ldq % 8 == 0.
+// whose X^T products read Xq through the transposing product kernel.  One
+// workgroup per 128 x 128 tile: thread t converts columns 4 (t % 32) .. +3 of
+// tile rows 16 (t / 32) .. +15, all sixteen float4 loads in flight at once;
+// n % 4 == 0, X 16-byte aligned, ldq % 128 == 0.
 __global__ void __launch_bounds__(256)
 quant_bf16_rows_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n, uint16_t* __restrict__ Xq,
                        int64_t ldq, double* __restrict__ sq) {
-  const int64_t r0 = (int64_t)blockIdx.x * 32;
-  const int64_t chunks = ldq / 8;
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.y * 128 + 16 * (tid >> 5), gj = (int64_t)blockIdx.x * 128 + 4 * (tid & 31);
+  f32x4 v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    v[r] = (i0 + r < m && gj < n) ? __builtin_nontemporal_load((const f32x4*)(X + (i0 + r) * ldx + gj)) : z;
+  }
   double ssq = 0.0;
-  for (int rr = 0; rr < 32; ++rr) {
-    const int64_t gi = r0 + rr;
-    if (gi >= m) break;
-    for (int64_t c = threadIdx.x; c < chunks; c += 256) {
-      const int64_t gj = 8 * c;
-      f32x4 a = {0.f, 0.f, 0.f, 0.f}, b = {0.f, 0.f, 0.f, 0.f};
-      if (gj < n) a = __builtin_nontemporal_load((const f32x4*)(X + gi * ldx + gj));
-      if (gj + 4 < n) b = __builtin_nontemporal_load((const f32x4*)(X + gi * ldx + gj + 4));
-      uint32_t w[4];
 #pragma unroll
-      for (int d = 0; d < 2; ++d) {
-        w[d] = (uint32_t)bf16_rne(a[2 * d]) | ((uint32_t)bf16_rne(a[2 * d + 1]) << 16);
-        w[2 + d] = (uint32_t)bf16_rne(b[2 * d]) | ((uint32_t)bf16_rne(b[2 * d + 1]) << 16);
-      }
+  for (int r = 0; r < 16; ++r) {
 #pragma unroll
-      for (int d = 0; d < 4; ++d) ssq = fma((double)a[d], (double)a[d], fma((double)b[d], (double)b[d], ssq));
-      *(i32x4*)(Xq + gi * ldq + gj) = (i32x4){(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
-    }
+    for (int d = 0; d < 4; ++d) ssq = fma((double)v[r][d], (double)v[r][d], ssq);
+    if (i0 + r < m)
+      *(uint2*)(Xq + (i0 + r) * ldq + gj) =
+          make_uint2((uint32_t)bf16_rne(v[r][0]) | ((uint32_t)bf16_rne(v[r][1]) << 16),
+                     (uint32_t)bf16_rne(v[r][2]) | ((uint32_t)bf16_rne(v[r][3]) << 16));
   }
   if (sq) block_sq(ssq, sq);
 }
@@ -450,22 +447,21 @@ unsigned grid1(int64_t total) {
 
 int quant_sq_parts(int64_t m, int64_t n, int64_t ldq, int64_t ldqt) {
   (void)n;
-  // the largest grid: 64 x 64 tiles, or 32-row strips (row-major copy only)
-  const int64_t a = ceil_div(ldq, QT) * ceil_div(ldqt, QT), b = ceil_div(m, 32);
-  return (int)(a > b ? a : b);
+  (void)m;
+  return (int)(ceil_div(ldq, QT) * ceil_div(ldqt, QT));   // the largest grid (64 x 64 tiles)
 }
 
 hipError_t launch_quant_bf16_rows(const float* X, int64_t ldx, int64_t m, int64_t n, uint16_t* Xq, int64_t ldq,
                                   hipStream_t st, double* sq_part, double* sq_out) {
   if (m == 0) return hipSuccess;
-  if (n % 4 || ldx % 4 || ((uintptr_t)X & 15) || ((uintptr_t)Xq & 15) || ldq % 8 || ldq < n)
+  if (n % 4 || ldx % 4 || ((uintptr_t)X & 15) || ((uintptr_t)Xq & 15) || ldq % 128 || ldq < n)
     return hipErrorInvalidValue;
-  const unsigned g = (unsigned)ceil_div(m, 32);
-  hipLaunchKernelGGL(quant_bf16_rows_kernel, dim3(g), dim3(256), 0, st, X, ldx, m, n, Xq, ldq,
+  const dim3 grid((unsigned)(ldq / 128), (unsigned)ceil_div(m, 128));
+  hipLaunchKernelGGL(quant_bf16_rows_kernel, grid, dim3(256), 0, st, X, ldx, m, n, Xq, ldq,
                      sq_out ? sq_part : nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !sq_out) return e;
-  return launch_sum_partials_f64(sq_part, (int)g, 1, sq_out, nullptr, st);
+  return launch_sum_partials_f64(sq_part, (int)(grid.x * grid.y), 1, sq_out, nullptr, st);
 }
 
 hipError_t launch_quant_bf16(const float* X, int64_t ldx, int64_t m, int64_t n, uint16_t* Xq,
