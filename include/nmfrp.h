@@ -137,7 +137,10 @@ nmf_status nmf_proxy_residual(nmf_ctx* ctx, double* rel_err);
  * the first exact residual runs once the proxy is within 1 % of eps, once
  * the proxy stalls (not decreasing, or its extrapolation needs more than 50
  * further iterations: an offset from W's part outside range(Q_L) keeps it
- * above eps), after 100 iterations, or at max_iters.  From then on every chunk ends with an exact
+ * above eps), after 100 iterations, or at max_iters (a proxy reading and an
+ * exact residual it lets through share one synchronisation: the residual
+ * kernel reads the proxy sums on the device and exits at once otherwise).
+ * From then on every chunk ends with an exact
  * residual and is 1.5 times the iterations a straight-line extrapolation of
  * the last two exact values needs to reach eps (5..50; by the gap to eps:
  * 50, 20, 10, 5 for more than 10 %, 1 %, 0.3 % or less when there is no

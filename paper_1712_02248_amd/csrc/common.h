@@ -148,7 +148,8 @@ hipError_t launch_proxy(const float* Xh, int64_t ldx, const float* Ht, int r, co
                         double* part, hipStream_t st);
 hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t n, const float* W,
                            const float* sw, const float* Ht, int r, double* part, double* out,
-                           unsigned* counter, hipStream_t st);
+                           unsigned* counter, hipStream_t st, const double* gate = nullptr,
+                           double gate_thr2 = 0.0);
 
 // Small utilities (util.hip).
 hipError_t launch_fill_f32(float* p, int64_t count, float v, hipStream_t st);

@@ -677,6 +677,44 @@ nmf_status nmf_proxy_residual(nmf_ctx* c, double* rel_err) {
 
 namespace {
 
+// One synchronisation for a proxy reading and, when the proxy is already within
+// thr of eps, the exact residual too: the residual kernel reads the proxy sums
+// on the device and exits at once otherwise (its output keeps a negative
+// sentinel).  *ran tells whether e was computed.
+nmf_status proxy_then_exact(nmf_ctx* c, const float* X, int64_t ldx, double thr, double* p, bool* ran, double* e) {
+  Layout& L = c->L;
+  const int nb = proxy_blocks(c->p.n);
+  double* po = c->at<double>(L.proxy_out);
+  double* ro = c->at<double>(L.res_out);
+  HIPCHK(c, launch_proxy(c->at<float>(L.Xh), L.KP, c->at<float>(L.Ht), c->p.r, c->at<float>(L.Wh), c->p.k_sketch,
+                         c->p.n, c->at<double>(L.proxy_part), c->st));
+  HIPCHK(c, launch_sum_partials_f64(c->at<double>(L.proxy_part), nb, 2, po, nullptr, c->st));
+  HIPCHK(c, launch_fill_f32(reinterpret_cast<float*>(ro), 4, -1.0f, c->st));   // two negative doubles
+  HIPCHK(c, hipEventRecord(c->ev[4], c->st));
+  HIPCHK(c, launch_residual(X, ldx, c->p.m, c->p.n, c->at<float>(L.W), c->at<float>(L.scale_w),
+                            c->at<float>(L.Ht), c->p.r, c->at<double>(L.res_part), ro,
+                            c->at<unsigned>(L.counters) + 4, c->st, po, thr * thr));
+  HIPCHK(c, hipEventRecord(c->ev[5], c->st));
+  double h[5];
+  int qs[16];
+  HIPCHK(c, hipMemcpyAsync(h, po, 3 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(h + 3, ro, 2 * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(qs, c->at<int>(L.qr_status), sizeof(qs), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (!(h[2] > 0)) return fail(c, NMF_ENONFINITE, "||X||^2 is zero or not finite");
+  const double e2 = (h[2] - h[1] + h[0]) / h[2];
+  if (!std::isfinite(e2)) return fail(c, NMF_ENONFINITE, "non-finite proxy");
+  *p = std::sqrt(e2 > 0 ? e2 : 0.0);
+  *ran = h[4] >= 0.0;
+  if (*ran) {
+    c->t_residual = true;
+    if (qs[1] || qs[9]) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
+    *e = (h[4] > 0) ? std::sqrt(h[3] / h[4]) : 0.0;
+    if (!std::isfinite(h[3]) || !std::isfinite(h[4])) return fail(c, NMF_ENONFINITE, "non-finite residual");
+  }
+  return NMF_OK;
+}
+
 // Adaptive schedule.  Phase 1 (no exact value yet): chunks of 5 or more with
 // the sketch-only proxy after each (no pass over X); the first exact FP64
 // residual runs once the proxy is within 1 % of eps, or after 100 iterations.
@@ -714,8 +752,10 @@ nmf_status fit_proxy_schedule(nmf_ctx* c, const float* X, int64_t ldx, int32_t m
     done += chunk;
     if (!exact_seen) {
       double p;
-      if ((s = nmf_proxy_residual(c, &p)) != NMF_OK) return s;
-      if (p > eps * 1.01 && done < 100 && done < max_iters) {
+      bool ran = false;
+      // the exact residual runs in the same synchronisation when the proxy is within 1 % of eps
+      if ((s = proxy_then_exact(c, X, ldx, eps * 1.01, &p, &ran, &e)) != NMF_OK) return s;
+      if (!ran && done < 100 && done < max_iters) {
         chunk = extrapolate(p, done, 5, 50, 1.2);
         // A proxy that would need more than the largest chunk at its current
         // rate is taken as stalled above eps: its offset from the exact error
@@ -724,6 +764,11 @@ nmf_status fit_proxy_schedule(nmf_ctx* c, const float* X, int64_t ldx, int32_t m
       }
       exact_seen = true;
       t_prev = -1;        // phase 2 extrapolates exact values only
+      if (ran) {
+        if (e <= eps) break;
+        chunk = extrapolate(e, done, 5, 50, 1.5);
+        continue;
+      }
     }
     if ((s = nmf_residual(c, X, ldx, &e)) != NMF_OK) return s;
     if (e <= eps) break;

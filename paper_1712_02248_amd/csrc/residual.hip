@@ -23,7 +23,14 @@ __global__ void __launch_bounds__(256)
 residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
                 const float* __restrict__ W, const float* __restrict__ sw,
                 const float* __restrict__ Ht, int r, double* __restrict__ part,
-                double* __restrict__ out, unsigned* __restrict__ counter) {
+                double* __restrict__ out, unsigned* __restrict__ counter, const double* __restrict__ gate,
+                double gate_thr2) {
+  // gate (optional): the proxy sums (sd, sx, ||X||^2); every workgroup returns at
+  // once unless (||X||^2 - sx + sd) / ||X||^2 <= gate_thr2 (out is left untouched)
+  if (gate) {
+    const double e2 = (gate[2] - gate[1] + gate[0]) / gate[2];
+    if (!(e2 <= gate_thr2)) return;
+  }
   constexpr int RB = 4 * RPW, NB = RPW / 16;  // rows per workgroup, 16-row blocks per wave
   constexpr int KS = RMAX / 4;                // MFMA k-steps
   constexpr int HPT = CT * RMAX / 256;        // Ht tile elements per thread
@@ -225,24 +232,19 @@ int residual_blocks(int64_t m, int64_t n) {   // upper bound over the instantiat
 
 hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t n, const float* W,
                            const float* sw, const float* Ht, int r, double* part, double* out,
-                           unsigned* counter, hipStream_t st) {
+                           unsigned* counter, hipStream_t st, const double* gate, double gate_thr2) {
   if (n % 4) return hipErrorInvalidValue;
   // 32 rows per wave (each Ht fragment feeds two MFMA row blocks) while the W
   // fragments fit; 16 for larger r
-  if (r <= 16)
-    hipLaunchKernelGGL((residual_kernel<16, 32>), dim3((unsigned)ceil_div(m, 128)), dim3(256), 0, st, X, ldx, m,
-                       n, W, sw, Ht, r, part, out, counter);
-  else if (r <= 32)
-    hipLaunchKernelGGL((residual_kernel<32, 32>), dim3((unsigned)ceil_div(m, 128)), dim3(256), 0, st, X, ldx, m,
-                       n, W, sw, Ht, r, part, out, counter);
-  else if (r <= 64)
-    hipLaunchKernelGGL((residual_kernel<64, 16>), dim3((unsigned)ceil_div(m, 64)), dim3(256), 0, st, X, ldx, m,
-                       n, W, sw, Ht, r, part, out, counter);
-  else if (r <= 128)
-    hipLaunchKernelGGL((residual_kernel<128, 16>), dim3((unsigned)ceil_div(m, 64)), dim3(256), 0, st, X, ldx, m,
-                       n, W, sw, Ht, r, part, out, counter);
-  else
-    return hipErrorInvalidValue;
+#define NMF_RES_LAUNCH(RM_, RPW_)                                                                              \
+  hipLaunchKernelGGL((residual_kernel<RM_, RPW_>), dim3((unsigned)ceil_div(m, 4 * RPW_)), dim3(256), 0, st, X, ldx, \
+                     m, n, W, sw, Ht, r, part, out, counter, gate, gate_thr2)
+  if (r <= 16) NMF_RES_LAUNCH(16, 32);
+  else if (r <= 32) NMF_RES_LAUNCH(32, 32);
+  else if (r <= 64) NMF_RES_LAUNCH(64, 16);
+  else if (r <= 128) NMF_RES_LAUNCH(128, 16);
+  else return hipErrorInvalidValue;
+#undef NMF_RES_LAUNCH
   return hipGetLastError();
 }
 
