@@ -354,7 +354,8 @@ nmf_status nmf_init_learned(nmf_ctx* ctx, nmf_mlp* net, const float* align_M, co
 
 /* nmf_init_learned with the alignment and the reference factor formed inside
  * the library from the reference fit itself: align_M = Q_train^T Q_L and
- * Wh_ref = Q_L^T W_ref (FP64 sums over the m rows, rounded to FP32), W = W_ref.
+ * Wh_ref = Q_L^T W_ref (FP64 sums over the m rows, rounded to FP32; the two
+ * products run concurrently on the context's two streams), W = W_ref.
  * Q_train: m x k' (ldq >= k'), W_ref: m x r (ldw >= r), device, read only.
  * The other arguments are those of nmf_init_learned. */
 nmf_status nmf_init_learned_ref(nmf_ctx* ctx, nmf_mlp* net, const float* Q_train, int64_t ldq,

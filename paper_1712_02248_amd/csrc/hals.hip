@@ -399,6 +399,37 @@ hipError_t run(const HalfStepArgs& a, int do_sweep, hipStream_t st) {
                                  st);
 }
 
+// Few elements, many partials (sums of squares, proxy sums): one workgroup per
+// element, thread t sums partials t, t + 256, ... (eight loads per round), then
+// a fixed-order tree over the 256 threads.
+template <typename T>
+__global__ void __launch_bounds__(256)
+sum_partials_few_kernel(const T* __restrict__ part, int nparts, int64_t ne, double* __restrict__ out,
+                        const int* __restrict__ skip) {
+  if (skip && skip[0] == 0) return;
+  __shared__ double red[256];
+  const int64_t e = blockIdx.x;
+  double s[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) s[u] = 0.0;
+  int b = threadIdx.x;
+  for (; b + 7 * 256 < nparts; b += 8 * 256) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(b + 256 * u) * ne + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += (double)v[u];
+  }
+  for (; b < nparts; b += 256) s[0] += (double)part[(int64_t)b * ne + e];
+  red[threadIdx.x] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[e] = red[0];
+}
+
 }  // namespace
 
 int halfstep_blocks(int64_t N) {
@@ -428,6 +459,11 @@ hipError_t launch_halfstep(const HalfStepArgs& a, int do_sweep, hipStream_t st) 
 
 hipError_t launch_sum_partials_f32(const float* part, int nparts, int64_t ne, double* out,
                                    hipStream_t st) {
+  if (ne <= 8 && nparts > 64) {
+    hipLaunchKernelGGL(sum_partials_few_kernel<float>, dim3((unsigned)ne), dim3(256), 0, st, part, nparts, ne, out,
+                       nullptr);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(sum_partials_kernel<float>, dim3((unsigned)ceil_div(ne, 16)), dim3(256), 0, st,
                      part, nparts, ne, out, nullptr);
   return hipGetLastError();
@@ -435,6 +471,11 @@ hipError_t launch_sum_partials_f32(const float* part, int nparts, int64_t ne, do
 
 hipError_t launch_sum_partials_f64(const double* part, int nparts, int64_t ne, double* out,
                                    const int* skip, hipStream_t st) {
+  if (ne <= 8 && nparts > 64) {
+    hipLaunchKernelGGL(sum_partials_few_kernel<double>, dim3((unsigned)ne), dim3(256), 0, st, part, nparts, ne, out,
+                       skip);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(sum_partials_kernel<double>, dim3((unsigned)ceil_div(ne, 16)), dim3(256), 0, st,
                      part, nparts, ne, out, skip);
   return hipGetLastError();

@@ -17,7 +17,12 @@ __global__ void __launch_bounds__(256)
 mlp_gemm_kernel(const float* __restrict__ A, int lda, const float* __restrict__ B, int ldb,
                 float* __restrict__ C, int ldc, int M, int N, int K, const float* __restrict__ bias,
                 const float* __restrict__ aux, int ldaux) {
-  constexpr int BM = 64, BN = 64, BK = 32;
+  // BK = 64: eight K steps for the 512-deep layers, so fewer global-load
+  // latencies are exposed between the (short) MFMA phases
+  constexpr int BM = 64, BN = 64, BK = 64;
+  constexpr int NV = BM * BK / 4 / 256;   // float4 per thread per operand (4)
+  constexpr int NS = BM * BK / 256;       // scalars per thread per operand (16)
+  static_assert(BM == BN, "square tiles");
   __shared__ float As[BK][BM + 4];
   __shared__ float Bs[BK][BN + 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -26,10 +31,47 @@ mlp_gemm_kernel(const float* __restrict__ A, int lda, const float* __restrict__ 
   f32x16 acc;
 #pragma unroll
   for (int x = 0; x < 16; ++x) acc[x] = 0.f;
-  float va[8], vb[8];
+  // Operand tiles: A is BM x BK, B is BK x BN.  With vec (leading dimensions
+  // multiples of 4, 16-byte aligned bases, K % 4 == 0) each thread loads two
+  // float4 of each along the contiguous dimension; otherwise eight scalars.
+  const bool vec = ((lda | ldb) & 3) == 0 && (K & 3) == 0 && (((uintptr_t)A | (uintptr_t)B) & 15) == 0;
+  float va[NS], vb[NS];
   auto load = [&](int k0) {
+    if (vec) {
 #pragma unroll
-    for (int p = 0; p < 8; ++p) {
+      for (int p = 0; p < NV; ++p) {
+        const int e = tid + 256 * p;
+        int i, k;                 // A: float4 along k (!AT) or along i (AT)
+        if (!AT) { i = e / (BK / 4); k = 4 * (e % (BK / 4)); } else { k = e / (BM / 4); i = 4 * (e % (BM / 4)); }
+        const int gi = i0 + i, gk = k0 + k;
+        f32x4 a = {0.f, 0.f, 0.f, 0.f};
+        if (!AT) {
+          if (gi < M && gk < K) a = *(const f32x4*)(A + (int64_t)gi * lda + gk);
+        } else if (gk < K) {
+          if (gi + 3 < M) a = *(const f32x4*)(A + (int64_t)gk * lda + gi);
+          else
+            for (int d = 0; d < 4; ++d) a[d] = gi + d < M ? A[(int64_t)gk * lda + gi + d] : 0.f;
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) va[4 * p + d] = a[d];
+        int j, kb;                // B: float4 along k (BT) or along j (!BT)
+        if (BT) { j = e / (BK / 4); kb = 4 * (e % (BK / 4)); } else { kb = e / (BN / 4); j = 4 * (e % (BN / 4)); }
+        const int gj = j0 + j, gkb = k0 + kb;
+        f32x4 b = {0.f, 0.f, 0.f, 0.f};
+        if (BT) {
+          if (gj < N && gkb < K) b = *(const f32x4*)(B + (int64_t)gj * ldb + gkb);
+        } else if (gkb < K) {
+          if (gj + 3 < N) b = *(const f32x4*)(B + (int64_t)gkb * ldb + gj);
+          else
+            for (int d = 0; d < 4; ++d) b[d] = gj + d < N ? B[(int64_t)gkb * ldb + gj + d] : 0.f;
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) vb[4 * p + d] = b[d];
+      }
+      return;
+    }
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
       const int e = tid + 256 * p;
       int i, k;
       if (!AT) { i = e / BK; k = e % BK; } else { k = e / BM; i = e % BM; }
@@ -42,8 +84,22 @@ mlp_gemm_kernel(const float* __restrict__ A, int lda, const float* __restrict__ 
     }
   };
   auto store = [&]() {
+    if (vec) {
 #pragma unroll
-    for (int p = 0; p < 8; ++p) {
+      for (int p = 0; p < NV; ++p) {
+        const int e = tid + 256 * p;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          if (!AT) As[4 * (e % (BK / 4)) + d][e / (BK / 4)] = va[4 * p + d];
+          else As[e / (BM / 4)][4 * (e % (BM / 4)) + d] = va[4 * p + d];
+          if (BT) Bs[4 * (e % (BK / 4)) + d][e / (BK / 4)] = vb[4 * p + d];
+          else Bs[e / (BN / 4)][4 * (e % (BN / 4)) + d] = vb[4 * p + d];
+        }
+      }
+      return;
+    }
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
       const int e = tid + 256 * p;
       int i, k;
       if (!AT) { i = e / BK; k = e % BK; } else { k = e / BM; i = e % BM; }
@@ -60,7 +116,7 @@ mlp_gemm_kernel(const float* __restrict__ A, int lda, const float* __restrict__ 
     store();
     __syncthreads();
     if (k0 + BK < K) load(k0 + BK);
-#pragma unroll
+#pragma unroll 8
     for (int kk = 0; kk < BK; kk += 2) {
       const float a = As[kk + half][wm * 32 + l32];
       const float b = Bs[kk + half][wn * 32 + l32];

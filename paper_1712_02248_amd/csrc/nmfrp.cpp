@@ -615,9 +615,15 @@ nmf_status nmf_init_learned_ref(nmf_ctx* c, nmf_mlp* net, const float* Q_train, 
   float* Wh = c->at<float>(L.whref);
   double* part = c->at<double>(L.gram_part);
   double* C64 = c->at<double>(L.G);
-  // M = Q_train^T Q_L (k' x k'), Wh_ref = Q_L^T W_ref (k' x r), FP64 sums over the m rows
+  // M = Q_train^T Q_L (k' x k'), Wh_ref = Q_L^T W_ref (k' x r), FP64 sums over the m rows;
+  // the two products are independent: the second runs on the context's second stream
+  HIPCHK(c, hipEventRecord(c->fork, c->st));
+  HIPCHK(c, hipStreamWaitEvent(c->st2, c->fork, 0));
   HIPCHK(c, launch_atb_f32out(Q_train, ldq, k, c->at<float>(L.QL), L.KP, k, m, part, splits, C64, M, c->st));
-  HIPCHK(c, launch_atb_f32out(c->at<float>(L.QL), L.KP, k, W_ref, ldw, r, m, part, splits, C64, Wh, c->st));
+  HIPCHK(c, launch_atb_f32out(c->at<float>(L.QL), L.KP, k, W_ref, ldw, r, m, c->at<double>(L.gram_part2), splits,
+                              c->at<double>(L.G2), Wh, c->st2));
+  HIPCHK(c, hipEventRecord(c->join, c->st2));
+  HIPCHK(c, hipStreamWaitEvent(c->st, c->join, 0));
   return init_learned_impl(c, net, M, Wh, W_ref, ldw, Ht_cold, init_scale, refine_sweeps, n_rejected);
 }
 
