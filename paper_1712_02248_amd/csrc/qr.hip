@@ -249,6 +249,352 @@ cholesky_kernel(const double* __restrict__ G, int k, int64_t rows, double* __res
     }
 }
 
+// 64-bit value of lane `src` (uniform result).
+__device__ __forceinline__ double readlane_f64(double v, int src) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// A_ij -= L_ip L_jp^T for 16 x 16 blocks of the LDS matrix (row stride LD):
+// one wave, four v_mfma_f64_16x16x4_f64 steps over the 16 columns of panel p.
+// A operand: lane (r, g) = (lane % 16, lane / 16) holds L[16i + r][16p + 4s + g];
+// B operand: L[16j + r][16p + 4s + g]; D[row][col] in lane col + 16 (row % 4),
+// register row / 4.
+template <int LD>
+__device__ __forceinline__ void chol_block_update(double* As, int i, int j, int p, int r, int g) {
+  f64x4 acc;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = As[(16 * i + 4 * q + g) * LD + 16 * j + r];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const double a = -As[(16 * i + r) * LD + 16 * p + 4 * s + g];
+    const double b = As[(16 * j + r) * LD + 16 * p + 4 * s + g];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) As[(16 * i + 4 * q + g) * LD + 16 * j + r] = acc[q];
+}
+
+// The value of lane (lane % 16) + 16 GO in every lane: rows of 16 lanes are
+// exchanged by v_permlane16_swap (rows 0 1 2 3 of x become 0 0 2 2 and 1 1 3 3)
+// and v_permlane32_swap (0 1 0 1 and 2 3 2 3), no LDS round trip.
+template <int GO>
+__device__ __forceinline__ double lane_group_bcast(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  uint32_t h[2] = {(uint32_t)u, (uint32_t)(u >> 32)};
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const auto a = __builtin_amdgcn_permlane16_swap(h[i], h[i], false, false);
+    const uint32_t y = (GO & 1) ? a[1] : a[0];
+    const auto b = __builtin_amdgcn_permlane32_swap(y, y, false, false);
+    h[i] = (GO & 2) ? b[1] : b[0];
+  }
+  return __builtin_bit_cast(double, ((uint64_t)h[1] << 32) | h[0]);
+}
+
+// D = L_bb^{-1} for one 16 x 16 diagonal block (dense, zeros above the
+// diagonal), by forward substitution for column c = lane % 16.  The four lane
+// groups g = lane / 16 share the column: lane (c, g) holds rows 4 q + g (the
+// MFMA output layout, q = 0..3).  Step t: the group holding row t finalises
+// x_t (the division is the product with 1 / L[t][t]), passes it to the other
+// groups (lane_group_bcast), and every row r > t takes x_r -= L[r][t] x_t.
+// The entries of L are read from LDS one step ahead; an opaque zero added to
+// their indices keeps the reads of a step from being hoisted above the step
+// before it, so only a few are live at a time.
+template <int DL>
+__device__ __forceinline__ void chol_diag_inverse(const double* Ld, const double* inv_diag, double* D, int c,
+                                                  int g) {
+  double x[4], ln[4], dn;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    x[q] = (4 * q + g == c) ? 1.0 : 0.0;
+    ln[q] = Ld[(4 * q + g) * 16];
+  }
+  dn = inv_diag[0];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    double lc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) lc[q] = ln[q];
+    const double dc = dn;
+    if (t < 15) {
+      int z = 0;
+      asm volatile("" : "+s"(z));
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ln[q] = (4 * q + 3 > t + 1) ? Ld[(4 * q + g) * 16 + t + 1 + z] : 0.0;
+      dn = inv_diag[t + 1 + z];
+    }
+    const int qt = t >> 2;
+    x[qt] = (g == (t & 3)) ? x[qt] * dc : x[qt];
+    double v;
+    switch (t & 3) {
+      case 0: v = lane_group_bcast<0>(x[qt]); break;
+      case 1: v = lane_group_bcast<1>(x[qt]); break;
+      case 2: v = lane_group_bcast<2>(x[qt]); break;
+      default: v = lane_group_bcast<3>(x[qt]); break;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (4 * q + 3 <= t) continue;   // every row of this register is <= t
+      const double nx = fma(-lc[q], v, x[q]);
+      x[q] = (4 * q + g > t) ? nx : x[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) D[(4 * q + g) * DL + c] = x[q];
+}
+
+// Blocked form of the same factorisation for k <= 64 (four waves).  G is staged
+// in LDS, padded to Kp = 16 ceil(k / 16) with the identity (the padding factors
+// to itself and leaves the leading k x k block unchanged).  Right-looking over
+// 16-column panels:
+//  - wave 0 factors panel b over its whole height, one row per lane, with no
+//    barrier or LDS round trip inside the panel.  Column t: with p its pivot and
+//    v the column, the later columns u of the panel take a[u] -= (v / p) v[u],
+//    where v[u] (the entry in the row of column u) is read from its lane before
+//    the pivot is known; the column itself becomes v / sqrt(p).  The next pivot
+//    is formed from the same uniform values (the operation its lane performs),
+//    so the serial chain per column is 1/sqrt(p) (hardware estimate and one
+//    Newton step, as above), 1/p and one FMA;
+//  - the trailing update runs on FP64 MFMA with one step of lookahead: right
+//    after panel b only column block b + 1 is updated; the other trailing blocks
+//    take panel b's update while wave 0 factors panel b + 1.  The idle waves also
+//    invert the diagonal block of the previous panel then.
+// L^{-1} = X is formed blockwise: wave w builds column block w,
+// X_ww = L_ww^{-1} = D_w, X_iw = -D_i (sum_{w <= c < i} L_ic X_cw); the last row
+// block waits only for the last diagonal inverse, which another wave forms
+// meanwhile.  Attempts, shift and status flags as in cholesky_kernel.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+cholesky_blocked_kernel(const double* __restrict__ G, int k, int64_t rows, double* __restrict__ Rinv,
+                        int* __restrict__ status, int attempt) {
+  if (attempt == 2 && status[0] == 0) return;
+  constexpr int LD = 65, DL = 17;
+  __shared__ double As[64 * LD];
+  __shared__ __align__(16) double Ldg[4 * 256];   // diagonal blocks L_bb, dense, zeros above
+  __shared__ double Ds[64 * DL];                  // D_b in rows 16 b .. 16 b + 15
+  __shared__ double idv[64];                      // 1 / L[j][j]
+  __shared__ __align__(16) double colb[128];      // the current panel column, two buffers
+  __shared__ double wred[4];
+  __shared__ int fail;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int nb = (k + 15) >> 4, Kp = 16 * nb;
+
+  if (attempt == 1) {
+    double dev = 0.0;
+    // unconditional loads from clamped (in-bounds) indices, all in flight together
+    double gv[16];
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+      const int e = tid + 256 * p, i = e >> 6, l = e & 63;
+      gv[p] = G[min(i, k - 1) * k + min(l, k - 1)];
+    }
+#pragma unroll
+    for (int p = 0; p < 16; ++p) asm volatile("" : "+v"(gv[p]));
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+      const int e = tid + 256 * p, i = e >> 6, l = e & 63;
+      if (i < k && l < k) dev = fmax(dev, fabs(gv[p] - (i == l ? 1.0 : 0.0)));
+    }
+    for (int off = 32; off > 0; off >>= 1) dev = fmax(dev, __shfl_xor(dev, off));
+    if (lane == 0) wred[wave] = dev;
+    __syncthreads();
+    const double mx = fmax(fmax(wred[0], wred[1]), fmax(wred[2], wred[3]));
+    if (mx <= 1e-6) {                     // uniform
+      if (tid == 0) status[3] = 1;
+      return;
+    }
+  }
+  if (attempt == 0 && tid == 0) {
+    status[0] = 0;
+    status[3] = 0;
+  }
+
+  for (int tryi = 0; tryi < 2; ++tryi) {
+    double shift = 0.0;
+    if (tryi == 1) {
+      double trace = 0.0;
+      for (int i = 0; i < k; ++i) trace += G[i * k + i];
+      const double u = 1.1102230246251565e-16;
+      shift = 11.0 * ((double)rows * k + (double)k * (k + 1)) * u * trace;
+    }
+    // the whole 64 x 64 tile from clamped (in-bounds) indices; the empty asm
+    // consumes every loaded value, so the loads are not sunk into the selects
+    // and all sixteen are in flight together.  Opaque copies of the base and
+    // of the thread index keep the address arithmetic inside this loop (hoisted
+    // out of it, it would stay live through the factorisation).
+    {
+      const double* Gp = G;
+      int te = tid;
+      asm volatile("" : "+s"(Gp), "+v"(te));
+      double gv[16];
+#pragma unroll
+      for (int p = 0; p < 16; ++p) {
+        const int e = te + 256 * p, i = e >> 6, l = e & 63;
+        gv[p] = Gp[min(i, k - 1) * k + min(l, k - 1)];
+      }
+#pragma unroll
+      for (int p = 0; p < 16; ++p) asm volatile("" : "+v"(gv[p]));
+#pragma unroll
+      for (int p = 0; p < 16; ++p) {
+        const int e = te + 256 * p, i = e >> 6, l = e & 63;
+        As[i * LD + l] = (i < k && l < k) ? gv[p] + (i == l ? shift : 0.0) : (i == l ? 1.0 : 0.0);
+      }
+    }
+    if (tid == 0) fail = 0;
+    __syncthreads();
+    for (int b = 0; b < nb; ++b) {
+      if (wave == 0) {
+        const int c0 = 16 * b;
+        double a[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) a[t] = (lane < Kp && lane >= c0 + t) ? As[lane * LD + c0 + t] : 0.0;
+        // lanes above the diagonal only change entries above it, which are never read
+        // Software-pipelined: the estimate for the next pivot is issued before
+        // this column's updates, whose issue hides its latency.  The two values
+        // the next pivot needs are read from their lanes (readlane); the rest of
+        // the column goes through LDS (one store, uniform-address loads).
+        // Scheduling fences keep that order.
+        double idl = 0.0;
+        bool bad = false;
+        double p = readlane_f64(a[0], c0);
+        double r0 = __builtin_amdgcn_rsq(p);
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          double* cb = colb + 64 * (t & 1);
+          cb[lane] = a[t];
+          double w[16];
+          if (t < 15) w[t + 1] = readlane_f64(a[t], c0 + t + 1);
+#pragma unroll
+          for (int u = t + 2; u < 16; ++u) w[u] = cb[c0 + u];
+          const double xn = readlane_f64(a[t < 15 ? t + 1 : 15], c0 + (t < 15 ? t + 1 : 15));
+          __builtin_amdgcn_sched_barrier(0);
+          bad = bad | !(p > 0.0) | !isfinite(p);
+          const double id = r0 * fma(-0.5 * p * r0, r0, 1.5);
+          const double rp = id * id;
+          if (t < 15) {
+            p = fma(-(w[t + 1] * rp), w[t + 1], xn);
+            r0 = __builtin_amdgcn_rsq(p);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+          const double m = a[t] * rp;
+          a[t] *= id;
+          idl = (lane == c0 + t) ? id : idl;
+#pragma unroll
+          for (int u = t + 1; u < 16; ++u) a[u] = fma(-m, w[u], a[u]);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if (bad) {
+          if (lane == 0) fail = 1;
+        } else {
+#pragma unroll
+          for (int t = 0; t < 16; ++t)
+            if (lane < Kp && lane >= c0 + t) As[lane * LD + c0 + t] = a[t];
+          if (lane >= c0 && lane < c0 + 16) {
+            const int r = lane - c0;
+            idv[lane] = idl;
+#pragma unroll
+            for (int t = 0; t < 16; ++t) Ldg[256 * b + 16 * r + t] = (t <= r) ? a[t] : 0.0;
+          }
+        }
+      } else if (b >= 1) {
+        // the rest of panel b - 1's trailing update: blocks (i, j), b < j <= i
+        int q = 0;
+        for (int j = b + 1; j < nb; ++j)
+          for (int i = j; i < nb; ++i, ++q)
+            if (q % 3 == wave - 1) chol_block_update<LD>(As, i, j, b - 1, lr, lg);
+        if (wave == 1 + (b - 1) % 3)
+          chol_diag_inverse<DL>(Ldg + 256 * (b - 1), idv + 16 * (b - 1), Ds + 16 * (b - 1) * DL, lr, lg);
+      }
+      __syncthreads();
+      if (fail) break;
+      // column block b + 1 takes panel b's update
+      if (wave < nb - b - 1) chol_block_update<LD>(As, b + 1 + wave, b + 1, b, lr, lg);
+      __syncthreads();
+    }
+    if (!fail) break;
+    if (tryi == 0 && tid == 0 && attempt < 2) {
+      status[0] = 1;               // enables the third pass (shifted CholeskyQR3)
+      atomicAdd(status + 2, 1);    // shifted orthonormalisations since compress
+    }
+    __syncthreads();
+  }
+  if (fail) {
+    if (tid == 0) status[1] = 1;
+    return;
+  }
+
+  // column blocks w < nb - 1 up to the last row block, whose D wave 3 forms meanwhile
+  const int last = nb - 1;
+  f64x4 Xr[4], T = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) Xr[i] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  if (wave == 3) chol_diag_inverse<DL>(Ldg + 256 * last, idv + 16 * last, Ds + 16 * last * DL, lr, lg);
+  if (wave < last) {
+    const int w = wave;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (i == w)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Xr[i][q] = Ds[(16 * w + 4 * q + lg) * DL + lr];
+#pragma unroll
+    for (int i = 1; i < 4; ++i) {
+      if (i <= w || i >= last) continue;   // uniform
+      f64x4 U = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int c = 0; c < i; ++c) {
+        if (c < w) continue;
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          U = __builtin_amdgcn_mfma_f64_16x16x4f64(As[(16 * i + lr) * LD + 16 * c + 4 * s + lg], Xr[c][s], U,
+                                                   0, 0, 0);
+      }
+      f64x4 Y = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        Y = __builtin_amdgcn_mfma_f64_16x16x4f64(-Ds[(16 * i + lr) * DL + 4 * s + lg], U[s], Y, 0, 0, 0);
+      Xr[i] = Y;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (c < w || c >= last) continue;
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        T = __builtin_amdgcn_mfma_f64_16x16x4f64(As[(16 * last + lr) * LD + 16 * c + 4 * s + lg], Xr[c][s], T,
+                                                 0, 0, 0);
+    }
+  }
+  __syncthreads();
+  if (wave < nb) {
+    const int w = wave;
+    f64x4 Y = {0.0, 0.0, 0.0, 0.0};
+    if (w == last) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Y[q] = Ds[(16 * w + 4 * q + lg) * DL + lr];
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        Y = __builtin_amdgcn_mfma_f64_16x16x4f64(-Ds[(16 * last + lr) * DL + 4 * s + lg], T[s], Y, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (i == last) Xr[i] = Y;
+    // R^{-1}[c][i] = X[i][c] for c <= i, 0 below the diagonal
+    const int cg = 16 * w + lr;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (i >= nb) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ig = 16 * i + 4 * q + lg;
+        if (ig < k && cg < k) Rinv[cg * k + ig] = (cg <= ig) ? Xr[i][q] : 0.0;
+      }
+    }
+  }
+}
+
 // Q = Y R^{-1} in place on FP64 MFMA (v_mfma_f64_16x16x4_f64): a workgroup owns
 // 64 rows (16 per wave) and all k columns; the tile is read into LDS before any
 // write, so rows of other workgroups are never touched.  The tile is staged with
@@ -400,11 +746,8 @@ hipError_t launch_atb_f32out(const float* A, int64_t lda, int ka, const float* B
 
 hipError_t launch_cholesky(const double* G, int k, int64_t rows, double* Rinv, int* status,
                            int attempt, hipStream_t st) {
-  if (k <= 32)
-    hipLaunchKernelGGL((cholesky_kernel<32, 8>), dim3(1), dim3(64), 0, st, G, k, rows, Rinv, status,
-                       attempt);
-  else if (k <= 64)
-    hipLaunchKernelGGL((cholesky_kernel<64, 16>), dim3(1), dim3(256), 0, st, G, k, rows, Rinv, status,
+  if (k <= 64)
+    hipLaunchKernelGGL(cholesky_blocked_kernel, dim3(1), dim3(256), 0, st, G, k, rows, Rinv, status,
                        attempt);
   else if (k <= 128)
     hipLaunchKernelGGL((cholesky_kernel<128, 32>), dim3(1), dim3(1024), 0, st, G, k, rows, Rinv,

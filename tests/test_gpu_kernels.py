@@ -58,14 +58,21 @@ def test_gemm_f32(lib, M, N, K, at):
     assert np.all(np.abs(C - ref) <= bound)
 
 
-@pytest.mark.parametrize("rows,k,cond", [(5000, 64, 1e3), (3001, 20, 1e2), (20000, 128, 1e4), (64, 64, 10.0)])
+# k = 1, 16, 17, 48, 63, 64: the 16-column panels of the blocked factorisation
+# (one panel, a full panel plus one column, ragged last panels)
+@pytest.mark.parametrize("rows,k,cond", [(5000, 64, 1e3), (3001, 20, 1e2), (20000, 128, 1e4), (64, 64, 10.0),
+                                         (2000, 1, 1.0), (2000, 16, 1e3), (2000, 17, 1e3), (4000, 48, 1e4),
+                                         (4000, 63, 1e4)])
 def test_orth_cholesky_qr2(lib, rows, k, cond):
     print(f"orth rows={rows} k={k}", flush=True)
     g = np.random.default_rng(rows + k)
     U, _ = np.linalg.qr(g.standard_normal((rows, k)))
     V, _ = np.linalg.qr(g.standard_normal((k, k)))
     Y = (U @ np.diag(np.logspace(0, -np.log10(cond), k)) @ V.T).astype(np.float32)
-    Yd = torch.from_numpy(Y).cuda()
+    ld = (k + 3) // 4 * 4                      # rows of a multiple of 4 floats
+    full = np.zeros((rows, ld), dtype=np.float32)
+    full[:, :k] = Y
+    Yd = torch.from_numpy(full).cuda()[:, :k]
     shifted = lib.orth(Yd)
     Q = Yd.cpu().numpy().astype(np.float64)
     assert shifted == 0
@@ -74,10 +81,11 @@ def test_orth_cholesky_qr2(lib, rows, k, cond):
     assert np.abs(Q @ Q.T - Qr @ Qr.T).max() < 2e-6
 
 
-def test_orth_shifted_fallback(lib):
-    print("orth shifted", flush=True)
+@pytest.mark.parametrize("k", [32, 64])
+def test_orth_shifted_fallback(lib, k):
+    print(f"orth shifted k={k}", flush=True)
     g = np.random.default_rng(3)
-    rows, k = 4000, 32
+    rows = 4000
     U, _ = np.linalg.qr(g.standard_normal((rows, k)))
     V, _ = np.linalg.qr(g.standard_normal((k, k)))
     Y = (U @ np.diag(np.logspace(0, -12, k)) @ V.T).astype(np.float32)
