@@ -154,6 +154,7 @@ hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t n, co
 // Small utilities (util.hip).
 hipError_t launch_fill_f32(float* p, int64_t count, float v, hipStream_t st);
 hipError_t launch_fill_i32(int* p, int64_t count, int v, hipStream_t st);
+hipError_t launch_gather_host(const double* po, const double* ro, const int* qs, double* out, hipStream_t st);
 hipError_t launch_copy2d(float* dst, int64_t ldd, const float* src, int64_t lds, int64_t rows,
                          int64_t cols, hipStream_t st);
 hipError_t launch_scale_cols(float* dst, int64_t ldd, const float* src, int64_t lds, int64_t rows,

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -172,8 +173,41 @@ struct nmf_ctx {
   hipEvent_t fork = nullptr, join = nullptr;
   float ms_compress = 0, ms_step = 0, ms_residual = 0;
   bool t_compress = false, t_step = false, t_residual = false;
+  double* hout = nullptr;             // pinned host results (gather_host), device view hout_dev
+  double* hout_dev = nullptr;
   template <class T> T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
 };
+
+namespace {
+
+// Pinned, device-mapped, coherent host buffers for the results the host reads
+// after a synchronisation (a kernel writes them there, so no copy command runs).
+// They are taken from a process-wide pool and returned to it, never freed: a
+// context's buffer is reused by the next context.
+constexpr size_t HOUT_DOUBLES = 16;
+std::mutex g_hout_mu;
+std::vector<double*> g_hout_free;
+
+double* take_host_out() {
+  std::lock_guard<std::mutex> lk(g_hout_mu);
+  if (!g_hout_free.empty()) {
+    double* p = g_hout_free.back();
+    g_hout_free.pop_back();
+    return p;
+  }
+  void* p = nullptr;
+  if (hipHostMalloc(&p, HOUT_DOUBLES * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+    return nullptr;
+  return (double*)p;
+}
+
+void give_host_out(double* p) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_hout_mu);
+  g_hout_free.push_back(p);
+}
+
+}  // namespace
 
 namespace {
 
@@ -343,12 +377,21 @@ nmf_status nmf_create(const nmf_params* p, void* workspace, size_t ws_bytes, voi
     nmf_destroy(c);
     return fail(nullptr, NMF_EHIP, "stream/event create");
   }
+  c->hout = take_host_out();
+  if (!c->hout || hipHostGetDevicePointer((void**)&c->hout_dev, c->hout, 0) != hipSuccess) {
+    nmf_destroy(c);
+    return fail(nullptr, NMF_EHIP, "pinned host buffer");
+  }
   *out = c;
   return NMF_OK;
 }
 
 void nmf_destroy(nmf_ctx* c) {
   if (!c) return;
+  if (c->hout) {   // no gather into the buffer may still be in flight when it is reused
+    (void)hipStreamSynchronize(c->st);
+    give_host_out(c->hout);
+  }
   if (c->have_ev)
     for (int i = 0; i < 6; ++i) (void)hipEventDestroy(c->ev[i]);
   if (c->st2) {
@@ -650,13 +693,12 @@ nmf_status nmf_residual(nmf_ctx* c, const float* X, int64_t ldx, double* rel_err
                             c->at<float>(L.Ht), c->p.r, c->at<double>(L.res_part),
                             c->at<double>(L.res_out), c->at<unsigned>(L.counters) + 4, c->st));
   HIPCHK(c, hipEventRecord(c->ev[5], c->st));
-  double h[2];
-  int qs[16];
-  HIPCHK(c, hipMemcpyAsync(h, c->at<double>(L.res_out), sizeof(h), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(c, hipMemcpyAsync(qs, c->at<int>(L.qr_status), sizeof(qs), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, launch_gather_host(nullptr, c->at<double>(L.res_out), c->at<int>(L.qr_status), c->hout_dev, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
+  const double* hr = c->hout;
+  const double h[2] = {hr[3], hr[4]};
   c->t_residual = true;
-  if (qs[1] || qs[9]) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
+  if (hr[5] != 0.0 || hr[6] != 0.0) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
   *rel_err = (h[1] > 0) ? std::sqrt(h[0] / h[1]) : 0.0;
   if (!std::isfinite(h[0]) || !std::isfinite(h[1])) return fail(c, NMF_ENONFINITE, "non-finite residual");
   return NMF_OK;
@@ -671,9 +713,9 @@ nmf_status nmf_proxy_residual(nmf_ctx* c, double* rel_err) {
   HIPCHK(c, launch_proxy(c->at<float>(L.Xh), L.KP, c->at<float>(L.Ht), c->p.r, c->at<float>(L.Wh), c->p.k_sketch,
                          c->p.n, c->at<double>(L.proxy_part), c->st));
   HIPCHK(c, launch_sum_partials_f64(c->at<double>(L.proxy_part), nb, 2, c->at<double>(L.proxy_out), nullptr, c->st));
-  double h[3];
-  HIPCHK(c, hipMemcpyAsync(h, c->at<double>(L.proxy_out), sizeof(h), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, launch_gather_host(c->at<double>(L.proxy_out), nullptr, nullptr, c->hout_dev, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
+  const double h[3] = {c->hout[0], c->hout[1], c->hout[2]};
   if (!(h[2] > 0)) return fail(c, NMF_ENONFINITE, "||X||^2 is zero or not finite");
   const double e2 = (h[2] - h[1] + h[0]) / h[2];
   if (!std::isfinite(e2)) return fail(c, NMF_ENONFINITE, "non-finite proxy");
@@ -701,12 +743,10 @@ nmf_status proxy_then_exact(nmf_ctx* c, const float* X, int64_t ldx, double thr,
                             c->at<float>(L.Ht), c->p.r, c->at<double>(L.res_part), ro,
                             c->at<unsigned>(L.counters) + 4, c->st, po, thr * thr));
   HIPCHK(c, hipEventRecord(c->ev[5], c->st));
-  double h[5];
-  int qs[16];
-  HIPCHK(c, hipMemcpyAsync(h, po, 3 * sizeof(double), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(c, hipMemcpyAsync(h + 3, ro, 2 * sizeof(double), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(c, hipMemcpyAsync(qs, c->at<int>(L.qr_status), sizeof(qs), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, launch_gather_host(po, ro, c->at<int>(L.qr_status), c->hout_dev, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
+  double h[5];
+  for (int i = 0; i < 5; ++i) h[i] = c->hout[i];
   if (!(h[2] > 0)) return fail(c, NMF_ENONFINITE, "||X||^2 is zero or not finite");
   const double e2 = (h[2] - h[1] + h[0]) / h[2];
   if (!std::isfinite(e2)) return fail(c, NMF_ENONFINITE, "non-finite proxy");
@@ -714,7 +754,7 @@ nmf_status proxy_then_exact(nmf_ctx* c, const float* X, int64_t ldx, double thr,
   *ran = h[4] >= 0.0;
   if (*ran) {
     c->t_residual = true;
-    if (qs[1] || qs[9]) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
+    if (c->hout[5] != 0.0 || c->hout[6] != 0.0) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
     *e = (h[4] > 0) ? std::sqrt(h[3] / h[4]) : 0.0;
     if (!std::isfinite(h[3]) || !std::isfinite(h[4])) return fail(c, NMF_ENONFINITE, "non-finite residual");
   }

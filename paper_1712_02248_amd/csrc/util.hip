@@ -53,6 +53,28 @@ __global__ void check_nonneg_kernel(const float* X, int64_t ldx, int64_t m, int6
   if (bad) atomicOr(flags + 1, 1);
 }
 
+// One thread copies what the host reads after a synchronisation into pinned,
+// device-mapped host memory: out[0..2] = proxy sums (po), out[3..4] = residual
+// sums (ro), out[5], out[6] = breakdown flags of the two range finders (status
+// words 1 and 9 of qs).  Null sources leave their slots untouched.
+__global__ void gather_host_kernel(const double* po, const double* ro, const int* qs, double* out) {
+  if (threadIdx.x != 0) return;
+  if (po) {
+    out[0] = po[0];
+    out[1] = po[1];
+    out[2] = po[2];
+  }
+  if (ro) {
+    out[3] = ro[0];
+    out[4] = ro[1];
+  }
+  if (qs) {
+    out[5] = (double)qs[1];
+    out[6] = (double)qs[9];
+  }
+  __threadfence_system();
+}
+
 unsigned grid_for(int64_t count) {
   int64_t g = ceil_div(count, 256);
   if (g < 1) g = 1;
@@ -65,6 +87,11 @@ unsigned grid_for(int64_t count) {
 hipError_t launch_fill_f32(float* p, int64_t count, float v, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_f32_kernel, dim3(grid_for(count)), dim3(256), 0, st, p, count, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_host(const double* po, const double* ro, const int* qs, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(gather_host_kernel, dim3(1), dim3(64), 0, st, po, ro, qs, out);
   return hipGetLastError();
 }
 
