@@ -171,6 +171,12 @@ struct nmf_ctx {
   bool have_ev = false;
   hipStream_t st2 = nullptr;          // second stream of nmf_compress (right range finder)
   hipEvent_t fork = nullptr, join = nullptr;
+  // third stream: the warm start's alignment products, which need only Q_L, run
+  // on it from ql_ready (recorded by nmf_compress once Q_L is final) under the
+  // sketch products; aligned marks their end
+  hipStream_t st3 = nullptr;
+  hipEvent_t ql_ready = nullptr, aligned = nullptr;
+  bool ql_event = false;              // ql_ready belongs to the current Q_L
   float ms_compress = 0, ms_step = 0, ms_residual = 0;
   bool t_compress = false, t_step = false, t_residual = false;
   double* hout = nullptr;             // pinned host results (gather_host), device view hout_dev
@@ -372,8 +378,11 @@ nmf_status nmf_create(const nmf_params* p, void* workspace, size_t ws_bytes, voi
   c->have_ev = true;
   // second stream of the range finder (default priority) and its fork/join events
   if (hipStreamCreateWithFlags(&c->st2, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->st3, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ql_ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->aligned, hipEventDisableTiming) != hipSuccess) {
     nmf_destroy(c);
     return fail(nullptr, NMF_EHIP, "stream/event create");
   }
@@ -398,8 +407,14 @@ void nmf_destroy(nmf_ctx* c) {
     (void)hipStreamSynchronize(c->st2);
     (void)hipStreamDestroy(c->st2);
   }
+  if (c->st3) {
+    (void)hipStreamSynchronize(c->st3);
+    (void)hipStreamDestroy(c->st3);
+  }
   if (c->fork) (void)hipEventDestroy(c->fork);
   if (c->join) (void)hipEventDestroy(c->join);
+  if (c->ql_ready) (void)hipEventDestroy(c->ql_ready);
+  if (c->aligned) (void)hipEventDestroy(c->aligned);
   delete c;
 }
 
@@ -505,15 +520,23 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
     right.push_back([&] { hipError_t e = gemm(c, cr, X, ldx, 1, TM, QR, n, m); return e ? e : ORTH(cr, QR, n, true, false); });
   }
   // projected data (Sec 4): Xh = X^T Q_L (X-hat^T), Xc = X Q_R (X-check); FP32 on X,
-  // or on the low-precision copy like the range finder (lowp_sketches)
+  // or on the low-precision copy like the range finder (lowp_sketches).  Q_L is
+  // final when the left projection starts: ql_ready marks that point.
+  c->ql_event = false;
+  auto mark_ql = [&]() -> hipError_t {
+    const hipError_t e = hipEventRecord(c->ql_ready, cl.st);
+    if (!e) c->ql_event = true;
+    return e;
+  };
   if (lps) {
-    left.push_back([&] { return XtB(cl, QL, Xh, false); });
+    left.push_back([&] { hipError_t e = mark_ql(); return e ? e : XtB(cl, QL, Xh, false); });
     right.push_back([&] { return XB(cr, QR, Xc, false); });
   } else if (split) {   // split-BF16 products on X
     left.push_back([&] {
       uint16_t* H = c->at<uint16_t>(L.St);
       uint16_t* Lo = H + (size_t)k * L.ldqt;
-      hipError_t e = launch_prep_bt(QL, L.KP, m, k, H, Lo, L.ldqt, cl.st);
+      hipError_t e = mark_ql();
+      if (!e) e = launch_prep_bt(QL, L.KP, m, k, H, Lo, L.ldqt, cl.st);
       return e ? e : launch_gemm_split(X, ldx, 1, H, Lo, L.ldqt, Xh, L.KP, n, k, m,
                                        gemm_split_pick_splits(n, k, m), cl.gemm_part, cl.st);
     });
@@ -529,7 +552,7 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
                                      cr.st);
     });
   } else {
-    left.push_back([&] { return gemm(c, cl, X, ldx, 1, QL, Xh, n, m); });
+    left.push_back([&] { hipError_t e = mark_ql(); return e ? e : gemm(c, cl, X, ldx, 1, QL, Xh, n, m); });
     right.push_back([&] {   // Xc = X Q_R, with ||X||^2 in FP64 from the same pass (for the proxy residual)
       const int s = gemm_f32_pick_splits(m, k, n, 0);
       double* sqp = c->at<double>(L.xsq_part);
@@ -658,15 +681,20 @@ nmf_status nmf_init_learned_ref(nmf_ctx* c, nmf_mlp* net, const float* Q_train, 
   float* Wh = c->at<float>(L.whref);
   double* part = c->at<double>(L.gram_part);
   double* C64 = c->at<double>(L.G);
-  // M = Q_train^T Q_L (k' x k'), Wh_ref = Q_L^T W_ref (k' x r), FP64 sums over the m rows;
-  // the two products are independent: the second runs on the context's second stream
-  HIPCHK(c, hipEventRecord(c->fork, c->st));
-  HIPCHK(c, hipStreamWaitEvent(c->st2, c->fork, 0));
-  HIPCHK(c, launch_atb_f32out(Q_train, ldq, k, c->at<float>(L.QL), L.KP, k, m, part, splits, C64, M, c->st));
-  HIPCHK(c, launch_atb_f32out(c->at<float>(L.QL), L.KP, k, W_ref, ldw, r, m, c->at<double>(L.gram_part2), splits,
-                              c->at<double>(L.G2), Wh, c->st2));
-  HIPCHK(c, hipEventRecord(c->join, c->st2));
-  HIPCHK(c, hipStreamWaitEvent(c->st, c->join, 0));
+  // M = Q_train^T Q_L (k' x k'), Wh_ref = Q_L^T W_ref (k' x r), FP64 sums over the m rows.
+  // They need only Q_L: on the third stream from the point nmf_compress marked
+  // (Q_L final), so that they run under the sketch products, one after the other
+  // in the left range finder's Gram scratch (its last use precedes that point;
+  // the right range finder's may still be running).  Only the first warm start
+  // after a compression starts there; after nmf_set_state or a previous warm start
+  // (whose network may still read M), from the present point of the context's stream.
+  if (!c->ql_event) HIPCHK(c, hipEventRecord(c->ql_ready, c->st));
+  c->ql_event = false;
+  HIPCHK(c, hipStreamWaitEvent(c->st3, c->ql_ready, 0));
+  HIPCHK(c, launch_atb_f32out(Q_train, ldq, k, c->at<float>(L.QL), L.KP, k, m, part, splits, C64, M, c->st3));
+  HIPCHK(c, launch_atb_f32out(c->at<float>(L.QL), L.KP, k, W_ref, ldw, r, m, part, splits, C64, Wh, c->st3));
+  HIPCHK(c, hipEventRecord(c->aligned, c->st3));
+  HIPCHK(c, hipStreamWaitEvent(c->st, c->aligned, 0));
   return init_learned_impl(c, net, M, Wh, W_ref, ldw, Ht_cold, init_scale, refine_sweeps, n_rejected);
 }
 
@@ -916,6 +944,7 @@ nmf_status nmf_set_state(nmf_ctx* c, const float* QL, const float* QR, const flo
   HIPCHK(c, launch_copy2d(c->at<float>(L.Xh), L.KP, Xh, k, c->p.n, k, c->st));
   HIPCHK(c, launch_copy2d(c->at<float>(L.Xc), L.KP, Xc, k, c->p.m, k, c->st));
   HIPCHK(c, launch_fill_i32(c->at<int>(L.qr_status), 16, 0, c->st));
+  c->ql_event = false;
   c->compressed = true;
   c->stepped = false;
   c->xsq_valid = false;

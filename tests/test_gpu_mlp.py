@@ -226,6 +226,16 @@ def test_init_learned_selection_matches_oracle(lib):
     assert np.array_equal(np.all(Hg2 == Hcold, axis=1)[clear], rej[clear])
     assert abs(nrej2 - rej.sum()) <= np.sum(~clear)
     assert np.max((np.abs(Hg2 - Hsel) / scale)[clear]) <= 1e-4
+    # a second warm start on the same compression, and one after set_state (the
+    # alignment products then start from the context's stream): the same rows
+    ctx.init_learned_ref(net, dev(G), dev(Wref), Ht_cold=dev(Hcold))
+    Hg3 = ctx.factors()[1].cpu().numpy().astype(np.float64)
+    assert np.array_equal(Hg3, Hg2)
+    other = lib.NMF(m, n, r, kp, q, seed=7)
+    other.set_state(*ctx.state())
+    other.init_learned_ref(net, dev(G), dev(Wref), Ht_cold=dev(Hcold))
+    Hg4 = other.factors()[1].cpu().numpy().astype(np.float64)
+    assert np.array_equal(Hg4, Hg2)
     with pytest.raises(ValueError):
         ctx.init_learned_ref(net, dev(G)[:, :kp - 1].contiguous(), dev(Wref))   # wrong shape (binding)
     fresh = lib.NMF(m, n, r, kp, q, seed=7)
