@@ -118,6 +118,18 @@ nmf_status nmf_step(nmf_ctx* ctx, int32_t iters);
 /* Exact e = ||X - W Ht^T||_F / ||X||_F in FP64 (eq 2.2).  Synchronising. */
 nmf_status nmf_residual(nmf_ctx* ctx, const float* X, int64_t ldx, double* rel_err);
 
+/* e of eq 2.2 for a stopping test against eps: from FP32 products of W diag(sw)
+ * and Ht (twice the MFMA rate of the FP64 ones, FP64 sums of squares), with
+ * the bound |e32 - e| <= beta, beta = (g (1 + e32) + u' e32) / (1 - g) + r 2^-126
+ * sqrt(m n) / ||X|| + 1e-12 e32, u = 2^-23, u' = u / (1 - u), g = (r + 1) u /
+ * (1 - (r + 1) u), which holds for W, Ht >= 0 (the factors after any step).
+ * When |e32 - eps| <= beta the side of eps is open and the exact FP64 residual
+ * (nmf_residual) runs instead: *exact = 1, *bound = 0, *rel_err exact.
+ * Otherwise *exact = 0, *bound = beta, *rel_err = e32, and e32 <= eps exactly
+ * when e <= eps.  bound and exact may be NULL.  Synchronising. */
+nmf_status nmf_residual_check(nmf_ctx* ctx, const float* X, int64_t ldx, double eps, double* rel_err,
+                              double* bound, int32_t* exact);
+
 /* Sketch-only estimate of e from the left sketch (Sec 3: X ~ Q_L Q_L^T X):
  *   e_p^2 = (||X||^2 - ||Xh||^2 + sum_j ||xh_j - Wh h_j||^2) / ||X||^2,
  * with Wh = Q_L^T W of the last H sweep; equal to e when the columns of W lie
@@ -128,7 +140,7 @@ nmf_status nmf_residual(nmf_ctx* ctx, const float* X, int64_t ldx, double* rel_e
  * (not nmf_set_state); NMF_ESTATE otherwise.  Synchronising. */
 nmf_status nmf_proxy_residual(nmf_ctx* ctx, double* rel_err);
 
-/* Runs steps in chunks, evaluating the exact residual after each chunk, until
+/* Runs steps in chunks, evaluating the residual after each chunk, until
  * e <= eps or max_iters iterations (the paper leaves the stopping rule open:
  * Alg 1-4).  check_every > 0: fixed chunk.  check_every == 0 after
  * nmf_compress: until the first exact residual, chunks (5 first, then 1.2
@@ -140,14 +152,19 @@ nmf_status nmf_proxy_residual(nmf_ctx* ctx, double* rel_err);
  * above eps), after 100 iterations, or at max_iters (a proxy reading and an
  * exact residual it lets through share one synchronisation: the residual
  * kernel reads the proxy sums on the device and exits at once otherwise).
- * From then on every chunk ends with an exact
- * residual and is 1.5 times the iterations a straight-line extrapolation of
- * the last two exact values needs to reach eps (5..50; by the gap to eps:
+ * From then on every chunk ends with a residual check
+ * and is 1.5 times the iterations a straight-line extrapolation of
+ * the last two values needs to reach eps (5..50; by the gap to eps:
  * 50, 20, 10, 5 for more than 10 %, 1 %, 0.3 % or less when there is no
- * slope).  check_every == 0 after nmf_set_state (no ||X||^2): the same exact
- * schedule, starting with e at the current factors.  Only an exact e <= eps
- * stops.  max_iters == 0 only evaluates e.  Synchronising.  *iters_done and
- * *rel_err report the iterations run and the last exact e. */
+ * slope).  In this schedule a check that follows a value more than 1 % above
+ * eps is nmf_residual_check's (FP32 products, and the exact FP64 residual
+ * whenever the FP32 value lies within its bound of eps); the others are exact.
+ * Each stop decision is that of the exact e.  Otherwise (fixed
+ * chunks, or check_every == 0 after nmf_set_state, which has no ||X||^2: the
+ * exact schedule above starting with e at the current factors) every check is
+ * the exact residual.  max_iters == 0 only evaluates e (exactly).
+ * Synchronising.  *iters_done and *rel_err report the iterations run and the
+ * last e (exact, or within nmf_residual_check's bound of it). */
 nmf_status nmf_fit(nmf_ctx* ctx, const float* X, int64_t ldx, int32_t max_iters, double eps,
                    int32_t check_every, int32_t* iters_done, double* rel_err);
 

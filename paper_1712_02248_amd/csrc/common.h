@@ -149,7 +149,7 @@ hipError_t launch_proxy(const float* Xh, int64_t ldx, const float* Ht, int r, co
 hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t n, const float* W,
                            const float* sw, const float* Ht, int r, double* part, double* out,
                            unsigned* counter, hipStream_t st, const double* gate = nullptr,
-                           double gate_thr2 = 0.0);
+                           double gate_thr2 = 0.0, bool fp32 = false);
 
 // Small utilities (util.hip).
 hipError_t launch_fill_f32(float* p, int64_t count, float v, hipStream_t st);

@@ -732,6 +732,55 @@ nmf_status nmf_residual(nmf_ctx* c, const float* X, int64_t ldx, double* rel_err
   return NMF_OK;
 }
 
+namespace {
+
+// Bound on |e32 - e| for the residual from FP32 products (W, Ht >= 0), e32 its
+// value and xsq = ||X||^2.  With u = 2^-23 and g = (r + 1) u / (1 - (r + 1) u):
+// each P_ij is a sum of r nonnegative products of FP32 values (one of them scaled
+// by sw), so |P32_ij - P_ij| <= g P_ij; the subtraction adds u' |E32_ij|,
+// u' = u / (1 - u); ||P|| <= ||X|| (1 + e).  Hence
+// |e32 - e| <= (g (1 + e32) + u' e32) / (1 - g), plus r 2^-126 sqrt(m n) / ||X||
+// for products flushed to zero below the FP32 normal range, and 1e-12 e32 for
+// the FP64 sums.
+double fp32_residual_bound(int r, int64_t m, int64_t n, double e32, double xsq) {
+  const double u = std::ldexp(1.0, -23), up = u / (1.0 - u);
+  const double g = (r + 1) * u / (1.0 - (r + 1) * u);
+  double b = (g * (1.0 + e32) + up * e32) / (1.0 - g) + 1e-12 * e32;
+  if (xsq > 0) b += r * std::ldexp(1.0, -126) * std::sqrt((double)m * (double)n) / std::sqrt(xsq);
+  return b;
+}
+
+}  // namespace
+
+nmf_status nmf_residual_check(nmf_ctx* c, const float* X, int64_t ldx, double eps, double* rel_err, double* bound,
+                              int32_t* exact) {
+  if (!c || !X || !rel_err || ldx < c->p.n) return fail(c, NMF_EINVAL, "bad arguments");
+  if (!c->initialized) return fail(c, NMF_ESTATE, "residual needs factors (nmf_init)");
+  Layout& L = c->L;
+  HIPCHK(c, hipEventRecord(c->ev[4], c->st));
+  HIPCHK(c, launch_residual(X, ldx, c->p.m, c->p.n, c->at<float>(L.W), c->at<float>(L.scale_w),
+                            c->at<float>(L.Ht), c->p.r, c->at<double>(L.res_part),
+                            c->at<double>(L.res_out), c->at<unsigned>(L.counters) + 4, c->st, nullptr, 0.0, true));
+  HIPCHK(c, hipEventRecord(c->ev[5], c->st));
+  HIPCHK(c, launch_gather_host(nullptr, c->at<double>(L.res_out), c->at<int>(L.qr_status), c->hout_dev, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  const double* hr = c->hout;
+  c->t_residual = true;
+  if (hr[5] != 0.0 || hr[6] != 0.0) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
+  if (!std::isfinite(hr[3]) || !std::isfinite(hr[4])) return fail(c, NMF_ENONFINITE, "non-finite residual");
+  const double e32 = (hr[4] > 0) ? std::sqrt(hr[3] / hr[4]) : 0.0;
+  const double b = fp32_residual_bound(c->p.r, c->p.m, c->p.n, e32, hr[4]);
+  if (std::fabs(e32 - eps) <= b) {   // either side of eps within the bound: the exact value decides
+    if (exact) *exact = 1;
+    if (bound) *bound = 0.0;
+    return nmf_residual(c, X, ldx, rel_err);
+  }
+  if (exact) *exact = 0;
+  if (bound) *bound = b;
+  *rel_err = e32;
+  return NMF_OK;
+}
+
 nmf_status nmf_proxy_residual(nmf_ctx* c, double* rel_err) {
   if (!c || !rel_err) return fail(c, NMF_EINVAL, "bad arguments");
   if (!c->stepped) return fail(c, NMF_ESTATE, "the proxy needs at least one nmf_step after init");
@@ -783,8 +832,8 @@ nmf_status proxy_then_exact(nmf_ctx* c, const float* X, int64_t ldx, double thr,
   if (*ran) {
     c->t_residual = true;
     if (c->hout[5] != 0.0 || c->hout[6] != 0.0) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
-    *e = (h[4] > 0) ? std::sqrt(h[3] / h[4]) : 0.0;
     if (!std::isfinite(h[3]) || !std::isfinite(h[4])) return fail(c, NMF_ENONFINITE, "non-finite residual");
+    *e = (h[4] > 0) ? std::sqrt(h[3] / h[4]) : 0.0;
   }
   return NMF_OK;
 }
@@ -844,7 +893,13 @@ nmf_status fit_proxy_schedule(nmf_ctx* c, const float* X, int64_t ldx, int32_t m
         continue;
       }
     }
-    if ((s = nmf_residual(c, X, ldx, &e)) != NMF_OK) return s;
+    // While the last value was more than 1 % above eps, the check is the FP32-product
+    // one (it falls back to the exact residual near eps); the checks that can stop
+    // near eps are exact from the start, so they take one pass over X.
+    const bool far_above = e > 1.01 * eps;
+    if ((s = far_above ? nmf_residual_check(c, X, ldx, eps, &e, nullptr, nullptr) : nmf_residual(c, X, ldx, &e)) !=
+        NMF_OK)
+      return s;
     if (e <= eps) break;
     chunk = extrapolate(e, done, 5, 50, 1.5);
   }

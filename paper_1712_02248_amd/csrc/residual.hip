@@ -2,6 +2,14 @@
 // evaluated directly (never through the Gram expansion, which cancels
 // catastrophically at small e) with FP64 products and FP64 accumulation.
 //
+// F32 = true: the same with FP32 products (v_mfma_f32_16x16x4f32, Ht rows in
+// natural order: its output D[j][i] sits in lane i + 16 (j / 4), register j % 4,
+// so lane l again holds X row l % 16 and columns 4 (l / 16) .. +3) and E = X - P
+// in FP32; squares are still summed in FP64.  For W, Ht >= 0 the computed e
+// stays within gamma (1 + e) of the exact one, gamma = (r + 2) u / (1 - (r + 2) u)
+// with u = 2^-23 (r products and the scaling by sw per element of P, one
+// subtraction; u covers truncating as well as nearest rounding).
+//
 // A workgroup owns 4 RPW rows of X (RPW per wave) and walks all 64-column tiles,
 // starting at tile (workgroup index mod tile count).  Per 16-column block the
 // wave forms E = Htb (W diag(sw))^T on v_mfma_f64_16x16x4_f64 (A = Ht rows from
@@ -11,6 +19,8 @@
 // adjacent columns 4 (l / 16) .. +3 of the block, one float4 of X.  It
 // subtracts X and accumulates squares.  Workgroup partials are summed in fixed
 // order by the last workgroup to finish (completion counter, reset afterwards).
+#include <type_traits>
+
 #include "common.h"
 
 namespace {
@@ -18,7 +28,7 @@ namespace {
 constexpr int RBMIN = 64;    // fewest rows per workgroup of any instantiation
 constexpr int CT = 64;       // columns per tile
 
-template <int RMAX, int RPW>
+template <int RMAX, int RPW, bool F32>
 __global__ void __launch_bounds__(256)
 residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
                 const float* __restrict__ W, const float* __restrict__ sw,
@@ -34,7 +44,9 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
   constexpr int RB = 4 * RPW, NB = RPW / 16;  // rows per workgroup, 16-row blocks per wave
   constexpr int KS = RMAX / 4;                // MFMA k-steps
   constexpr int HPT = CT * RMAX / 256;        // Ht tile elements per thread
-  __shared__ double Hs[CT][RMAX + 1];
+  typedef typename std::conditional<F32, float, double>::type T;
+  typedef typename std::conditional<F32, f32x4, f64x4>::type TV;
+  __shared__ T Hs[CT][RMAX + 1];
   __shared__ double red[2][256];
   __shared__ int last;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -42,18 +54,19 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
   const int64_t ntile = ceil_div(n, CT);
   const bool vec = (ldx % 4 == 0) && (((uintptr_t)X & 15) == 0);   // float4 loads of X
 
-  // B fragments (rows of W diag(sw) owned by this wave), FP64, kept for all tiles
-  double wfr[NB][KS];
+  // B fragments (rows of W diag(sw) owned by this wave), kept for all tiles
+  T wfr[NB][KS];
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb) {
     const int64_t gi = row0 + wave * RPW + nb * 16 + (lane & 15);
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       const int k = 4 * s + (lane >> 4);
-      wfr[nb][s] = (gi < m && k < r) ? (double)W[gi * r + k] * (double)(sw ? sw[k] : 1.f) : 0.0;
+      wfr[nb][s] = (gi < m && k < r) ? (T)W[gi * r + k] * (T)(sw ? sw[k] : 1.f) : (T)0;
     }
   }
-  const int hrow = 4 * (lane & 3) + ((lane & 15) >> 2);   // c(lane % 16)
+  // FP64: Ht rows in the order c(j) = 4 (j % 4) + j / 4; FP32: natural order
+  const int hrow = F32 ? (lane & 15) : 4 * (lane & 3) + ((lane & 15) >> 2);
   // Software pipeline over the 64-column tiles of this row strip: the loads of
   // tile t+1 are issued (Ht first, then X) before the MFMAs of tile t, so each
   // wait only covers loads issued one tile earlier.  n % 4 == 0, so a group of
@@ -96,7 +109,7 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
 #pragma unroll
     for (int p = 0; p < HPT; ++p) {
       const int e = tid + 256 * p;
-      Hs[e / RMAX][e % RMAX] = (double)hv[p];
+      Hs[e / RMAX][e % RMAX] = (T)hv[p];
     }
     __syncthreads();
     f32x4 xc[NB][4];
@@ -108,20 +121,24 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
       load_h(col0(t + 1));
       load_x(col0(t + 1));
     }
-    f64x4 d[NB][4];
+    TV d[NB][4];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int sub = 0; sub < 4; ++sub) d[nb][sub] = (f64x4){0, 0, 0, 0};
+      for (int sub = 0; sub < 4; ++sub) d[nb][sub] = (TV){0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       const int k = 4 * s + (lane >> 4);
 #pragma unroll
       for (int sub = 0; sub < 4; ++sub) {
-        const double h = Hs[sub * 16 + hrow][k];
+        const T h = Hs[sub * 16 + hrow][k];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          d[nb][sub] = __builtin_amdgcn_mfma_f64_16x16x4f64(h, wfr[nb][s], d[nb][sub], 0, 0, 0);
+        for (int nb = 0; nb < NB; ++nb) {
+          if constexpr (F32)
+            d[nb][sub] = __builtin_amdgcn_mfma_f32_16x16x4f32(h, wfr[nb][s], d[nb][sub], 0, 0, 0);
+          else
+            d[nb][sub] = __builtin_amdgcn_mfma_f64_16x16x4f64(h, wfr[nb][s], d[nb][sub], 0, 0, 0);
+        }
       }
     }
     // lane: row i = lane % 16 of block nb, tile columns 16 sub + 4 (lane / 16) + q in
@@ -133,7 +150,7 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const double x = (double)xc[nb][sub][q];
-          const double df = x - d[nb][sub][q];
+          const double df = F32 ? (double)(xc[nb][sub][q] - (float)d[nb][sub][q]) : x - (double)d[nb][sub][q];
           res = fma(df, df, res);
           xx = fma(x, x, xx);
         }
@@ -232,13 +249,19 @@ int residual_blocks(int64_t m, int64_t n) {   // upper bound over the instantiat
 
 hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t n, const float* W,
                            const float* sw, const float* Ht, int r, double* part, double* out,
-                           unsigned* counter, hipStream_t st, const double* gate, double gate_thr2) {
+                           unsigned* counter, hipStream_t st, const double* gate, double gate_thr2, bool fp32) {
   if (n % 4) return hipErrorInvalidValue;
   // 32 rows per wave (each Ht fragment feeds two MFMA row blocks) while the W
   // fragments fit; 16 for larger r
 #define NMF_RES_LAUNCH(RM_, RPW_)                                                                              \
-  hipLaunchKernelGGL((residual_kernel<RM_, RPW_>), dim3((unsigned)ceil_div(m, 4 * RPW_)), dim3(256), 0, st, X, ldx, \
-                     m, n, W, sw, Ht, r, part, out, counter, gate, gate_thr2)
+  do {                                                                                                         \
+    if (fp32)                                                                                                  \
+      hipLaunchKernelGGL((residual_kernel<RM_, RPW_, true>), dim3((unsigned)ceil_div(m, 4 * RPW_)), dim3(256), 0, \
+                         st, X, ldx, m, n, W, sw, Ht, r, part, out, counter, gate, gate_thr2);                  \
+    else                                                                                                       \
+      hipLaunchKernelGGL((residual_kernel<RM_, RPW_, false>), dim3((unsigned)ceil_div(m, 4 * RPW_)), dim3(256), 0, \
+                         st, X, ldx, m, n, W, sw, Ht, r, part, out, counter, gate, gate_thr2);                  \
+  } while (0)
   if (r <= 16) NMF_RES_LAUNCH(16, 32);
   else if (r <= 32) NMF_RES_LAUNCH(32, 32);
   else if (r <= 64) NMF_RES_LAUNCH(64, 16);

@@ -41,6 +41,7 @@ _SIGS = {
     "nmf_init": (c_i32, [c_vp, c_vp, c_vp, ctypes.c_float]),
     "nmf_step": (c_i32, [c_vp, c_i32]),
     "nmf_residual": (c_i32, [c_vp, c_vp, c_i64, c_dbl_p]),
+    "nmf_residual_check": (c_i32, [c_vp, c_vp, c_i64, ctypes.c_double, c_dbl_p, c_dbl_p, c_i32_p]),
     "nmf_proxy_residual": (c_i32, [c_vp, c_dbl_p]),
     "nmf_fit": (c_i32, [c_vp, c_vp, c_i64, c_i32, ctypes.c_double, c_i32, c_i32_p, c_dbl_p]),
     "nmf_get_factors": (c_i32, [c_vp, c_vp, c_vp]),
@@ -195,6 +196,15 @@ class NMF:
         e = ctypes.c_double()
         self._c(load().nmf_residual(self.h, _ptr(X), X.stride(0), ctypes.byref(e)))
         return e.value
+
+    def residual_check(self, X, eps):
+        """(e, bound, exact): e from FP32 products within `bound` of the exact
+        value, or the exact value (exact = True, bound 0) when the FP32 one lies
+        within its bound of eps."""
+        e, b, x = ctypes.c_double(), ctypes.c_double(), c_i32()
+        self._c(load().nmf_residual_check(self.h, _ptr(X), X.stride(0), float(eps), ctypes.byref(e),
+                                          ctypes.byref(b), ctypes.byref(x)))
+        return e.value, b.value, bool(x.value)
 
     def proxy_residual(self):
         """Sketch-only estimate of the relative error (see nmf_proxy_residual)."""

@@ -82,6 +82,33 @@ def test_residual_matches_oracle(lib):
     assert abs(e - onmf.rel_error(X, W, Ht)) <= 1e-12 * onmf.rel_error(X, W, Ht)
 
 
+@pytest.mark.parametrize("noise", [1.0, 1e-3])
+def test_residual_check_bound_and_exact_fallback(lib, noise):
+    """FP32-product residual of the stopping test: within its stated bound of the
+    exact FP64 value for W, Ht >= 0; an eps inside the bound gets the exact
+    value itself; just outside it, the FP32 value.  noise = 1: e ~ 0.5; 1e-3: a
+    near fit, e ~ 1e-3."""
+    print(f"residual check noise={noise}", flush=True)
+    m, n, r, kp = 700, 300, 7, 12
+    g = np.random.default_rng(11)
+    W = g.random((m, r)).astype(np.float32)
+    Ht = g.random((n, r)).astype(np.float32)
+    X = (W.astype(np.float64) @ Ht.T.astype(np.float64) * (1 + noise * g.random((m, n)))).astype(np.float32)
+    ctx = lib.NMF(m, n, r, kp, 1, seed=3)
+    Xd = torch.from_numpy(X).cuda()
+    ctx.compress(Xd)
+    ctx.init(torch.from_numpy(W).cuda(), torch.from_numpy(Ht).cuda())
+    e = ctx.residual(Xd)
+    assert abs(e - onmf.rel_error(X, W, Ht)) <= 1e-12 * e
+    e32, b, exact = ctx.residual_check(Xd, 10.0)
+    print(f"  e={e:.12e} e32={e32:.12e} bound={b:.3e}", flush=True)
+    assert not exact and abs(e32 - e) <= b and 0 < b <= 1e-5        # about (r + 1) 2^-23 (1 + e)
+    ex, b0, exact = ctx.residual_check(Xd, e)              # eps inside the bound
+    assert exact and b0 == 0.0 and ex == e
+    eo, b1, exact = ctx.residual_check(Xd, e32 + 2 * b)     # just outside it
+    assert not exact and eo == e32 and b1 == b
+
+
 @pytest.mark.parametrize("normalize", [1, 0, 2])
 def test_c1_first_iterations_elementwise(lib, normalize):
     print(f"c1 iterations normalize={normalize}", flush=True)
@@ -196,7 +223,10 @@ def test_fit_and_errors(lib):
     ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
     it4, e4 = ctx.fit(Xd, max_iters=200, eps=1.05 * ref["e"], check_every=0)
     assert 0 < it4 < 200 and e4 <= 1.05 * ref["e"]
-    assert abs(ctx.residual(Xd) - e4) <= 1e-12 * e4          # the reported e is exact
+    # the reported e is the stopping test's: exact, or the FP32-product value within its bound
+    e_exact = ctx.residual(Xd)
+    _, b4, _ = ctx.residual_check(Xd, 10.0)
+    assert abs(e_exact - e4) <= b4 and e_exact <= 1.05 * ref["e"]
     # without ||X||^2 (sketches imported): e at the current factors comes first
     imp = lib.NMF(m, n, r, kp, q, seed=5)
     imp.set_state(*ctx.state())
