@@ -489,35 +489,31 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
   // of its result); only the last orthonormalisation of each side is a full
   // CholeskyQR2.  Left: Q_L = orth(X Omega_L); q x { Z = orth(X^T Q_L); Q_L = orth(X Z) }.
   // Right: the same on X^T with Omega_R.
-  using Stage = std::function<hipError_t()>;
+  // A stage is a product and (except for the projections) the orthonormalisation
+  // of its result, enqueued separately (see below).
+  using Fn = std::function<hipError_t()>;
+  struct Stage {
+    Fn prod, orth;
+  };
   std::vector<Stage> left, right;
   const bool last0 = q == 0 && !refine;
   // (the left chain's first stage is enqueued by hand below, around the fork)
   const bool q0 = q > 0;      // the first basis feeds the power iterations
   const bool pf = fuse;       // products after a fused orthonormalisation find B prepared
-  right.push_back([&, last0, q0] {
-    hipError_t e = XtB(cr, omR, QR, false);
-    return e ? e : ORTH(cr, QR, n, last0, q0);
-  });
+  right.push_back({[&] { return XtB(cr, omR, QR, false); }, [&, last0, q0] { return ORTH(cr, QR, n, last0, q0); }});
   for (int it = 0; it < q; ++it) {
     const bool last = it == q - 1 && !refine;
     const bool more = it < q - 1;   // another power iteration follows
-    left.push_back([&, pf] { hipError_t e = XtB(cl, QL, TN, pf); return e ? e : ORTH(cl, TN, n, false, true); });
-    left.push_back([&, last, more, pf] {
-      hipError_t e = XB(cl, TN, QL, pf);
-      return e ? e : ORTH(cl, QL, m, last, more);
-    });
-    right.push_back([&, pf] { hipError_t e = XB(cr, QR, TM, pf); return e ? e : ORTH(cr, TM, m, false, true); });
-    right.push_back([&, last, more, pf] {
-      hipError_t e = XtB(cr, TM, QR, pf);
-      return e ? e : ORTH(cr, QR, n, last, more);
-    });
+    left.push_back({[&, pf] { return XtB(cl, QL, TN, pf); }, [&] { return ORTH(cl, TN, n, false, true); }});
+    left.push_back({[&, pf] { return XB(cl, TN, QL, pf); }, [&, last, more] { return ORTH(cl, QL, m, last, more); }});
+    right.push_back({[&, pf] { return XB(cr, QR, TM, pf); }, [&] { return ORTH(cr, TM, m, false, true); }});
+    right.push_back({[&, pf] { return XtB(cr, TM, QR, pf); }, [&, last, more] { return ORTH(cr, QR, n, last, more); }});
   }
   if (refine) {   // optional FP32 refinement: one power iteration per side on the exact X
-    left.push_back([&] { hipError_t e = gemm(c, cl, X, ldx, 1, QL, TN, n, m); return e ? e : ORTH(cl, TN, n, false, false); });
-    left.push_back([&] { hipError_t e = gemm(c, cl, X, ldx, 0, TN, QL, m, n); return e ? e : ORTH(cl, QL, m, true, false); });
-    right.push_back([&] { hipError_t e = gemm(c, cr, X, ldx, 0, QR, TM, m, n); return e ? e : ORTH(cr, TM, m, false, false); });
-    right.push_back([&] { hipError_t e = gemm(c, cr, X, ldx, 1, TM, QR, n, m); return e ? e : ORTH(cr, QR, n, true, false); });
+    left.push_back({[&] { return gemm(c, cl, X, ldx, 1, QL, TN, n, m); }, [&] { return ORTH(cl, TN, n, false, false); }});
+    left.push_back({[&] { return gemm(c, cl, X, ldx, 0, TN, QL, m, n); }, [&] { return ORTH(cl, QL, m, true, false); }});
+    right.push_back({[&] { return gemm(c, cr, X, ldx, 0, QR, TM, m, n); }, [&] { return ORTH(cr, TM, m, false, false); }});
+    right.push_back({[&] { return gemm(c, cr, X, ldx, 1, TM, QR, n, m); }, [&] { return ORTH(cr, QR, n, true, false); }});
   }
   // projected data (Sec 4): Xh = X^T Q_L (X-hat^T), Xc = X Q_R (X-check); FP32 on X,
   // or on the low-precision copy like the range finder (lowp_sketches).  Q_L is
@@ -529,18 +525,18 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
     return e;
   };
   if (lps) {
-    left.push_back([&] { hipError_t e = mark_ql(); return e ? e : XtB(cl, QL, Xh, false); });
-    right.push_back([&] { return XB(cr, QR, Xc, false); });
+    left.push_back({[&] { hipError_t e = mark_ql(); return e ? e : XtB(cl, QL, Xh, false); }, nullptr});
+    right.push_back({[&] { return XB(cr, QR, Xc, false); }, nullptr});
   } else if (split) {   // split-BF16 products on X
-    left.push_back([&] {
+    left.push_back({[&] {
       uint16_t* H = c->at<uint16_t>(L.St);
       uint16_t* Lo = H + (size_t)k * L.ldqt;
       hipError_t e = mark_ql();
       if (!e) e = launch_prep_bt(QL, L.KP, m, k, H, Lo, L.ldqt, cl.st);
       return e ? e : launch_gemm_split(X, ldx, 1, H, Lo, L.ldqt, Xh, L.KP, n, k, m,
                                        gemm_split_pick_splits(n, k, m), cl.gemm_part, cl.st);
-    });
-    right.push_back([&] {
+    }, nullptr});
+    right.push_back({[&] {
       uint16_t* H = c->at<uint16_t>(L.St2);
       uint16_t* Lo = H + (size_t)k * L.ldq;
       const int s = gemm_split_pick_splits(m, k, n);
@@ -550,16 +546,16 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
       if (e || xsq_quant) return e;
       return launch_sum_partials_f64(sqp, gemm_split_sq_parts(m, s), 1, c->at<double>(L.proxy_out) + 2, nullptr,
                                      cr.st);
-    });
+    }, nullptr});
   } else {
-    left.push_back([&] { hipError_t e = mark_ql(); return e ? e : gemm(c, cl, X, ldx, 1, QL, Xh, n, m); });
-    right.push_back([&] {   // Xc = X Q_R, with ||X||^2 in FP64 from the same pass (for the proxy residual)
+    left.push_back({[&] { hipError_t e = mark_ql(); return e ? e : gemm(c, cl, X, ldx, 1, QL, Xh, n, m); }, nullptr});
+    right.push_back({[&] {   // Xc = X Q_R, with ||X||^2 in FP64 from the same pass (for the proxy residual)
       const int s = gemm_f32_pick_splits(m, k, n, 0);
       double* sqp = c->at<double>(L.xsq_part);
       hipError_t e = launch_gemm_f32(X, ldx, 0, QR, L.KP, Xc, L.KP, m, k, n, s, cr.gemm_part, cr.st, sqp);
       return e ? e : launch_sum_partials_f64(sqp, gemm_f32_sq_parts(m, k, s), 1, c->at<double>(L.proxy_out) + 2,
                                             nullptr, cr.st);
-    });
+    }, nullptr});
   }
   // The two range finders are independent: the right one runs on a second
   // stream forked after the left one's first product and joined below, so that
@@ -570,9 +566,16 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
   HIPCHK(c, hipEventRecord(c->fork, st));
   HIPCHK(c, hipStreamWaitEvent(c->st2, c->fork, 0));
   HIPCHK(c, ORTH(cl, QL, m, last0, q0));
+  // The host enqueues both chains' products of a stage before their
+  // orthonormalisations: an orthonormalisation is up to twelve short launches,
+  // and the other stream must not wait for the host to get through them before
+  // its next (long) product is enqueued.
   for (size_t i = 0; i < right.size(); ++i) {
-    HIPCHK(c, right[i]());
-    if (i < left.size()) HIPCHK(c, left[i]());
+    const bool l = i < left.size();
+    HIPCHK(c, right[i].prod());
+    if (l) HIPCHK(c, left[i].prod());
+    if (right[i].orth) HIPCHK(c, right[i].orth());
+    if (l && left[i].orth) HIPCHK(c, left[i].orth());
   }
   HIPCHK(c, hipEventRecord(c->join, c->st2));
   HIPCHK(c, hipStreamWaitEvent(st, c->join, 0));
