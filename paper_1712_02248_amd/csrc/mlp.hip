@@ -186,11 +186,15 @@ NMF_DEV float quad_bcast_f(float v, int src) {
 // from the rows already in H when warm):
 //   h_j <- [h_j + (p_j - (G h)_j) / G_jj]_+ ,  p = Wh^T x,  G = Wh^T Wh,
 // j ascending (Gauss-Seidel); components with G_jj = 0 stay unchanged.
-// A quad of lanes per row; lane q owns components q RQ .. q RQ + RQ - 1 of h
-// and p.  (G h)_j is evaluated afresh for every j: each lane sums its own
-// components, and the four partial sums are added in the same order in every
-// lane.  Wh, G and 1/G_jj are staged in LDS, zero padded to RMAX columns.
-// 64 rows per 256-thread block.
+// A quad of lanes per row; lane q owns components q RQ .. q RQ + RQ - 1 of h,
+// p and the gradient g = p - G h.  g is formed afresh at the start of every
+// sweep (each lane sums over all components, taking the others' h from their
+// lanes); within the sweep, component j's change d = h_j' - h_j is passed from
+// its lane to the quad and every lane takes g -= G[:, j] d for its components.
+// The serial chain per component is then the update, one lane move and one
+// FMA (the same arithmetic as the direct form up to rounding).  Wh, G and
+// 1/G_jj are staged in LDS, zero padded to RMAX columns.  64 rows per
+// 256-thread block.
 template <int RMAX>
 __global__ void __launch_bounds__(256)
 nnls_rows_kernel(const float* __restrict__ Xr, int64_t ldx, int n, int k, const float* __restrict__ Wh, int r,
@@ -235,23 +239,40 @@ nnls_rows_kernel(const float* __restrict__ Xr, int64_t ldx, int n, int k, const 
     }
   }
   for (int it = 0; it < sweeps; ++it) {
+    // g = p - G h, with h of every component taken from its lane
+    float g[RQ];
+#pragma unroll
+    for (int t = 0; t < RQ; ++t) g[t] = p[t];
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+      for (int u = 0; u < RQ; ++u) {
+        const float hv = quad_bcast_f(f[u], qq);          // h of component qq RQ + u
+        const int col = qq * RQ + u;
+#pragma unroll
+        for (int t = 0; t < RQ; t += 4) {
+          const f32x4 gv = *(const f32x4*)(gs + col * RMAX + c0 + t);   // G symmetric: G[c0 + t][col]
+          g[t] = fmaf(-gv[0], hv, g[t]);
+          g[t + 1] = fmaf(-gv[1], hv, g[t + 1]);
+          g[t + 2] = fmaf(-gv[2], hv, g[t + 2]);
+          g[t + 3] = fmaf(-gv[3], hv, g[t + 3]);
+        }
+      }
 #pragma unroll
     for (int j = 0; j < RMAX; ++j) {
       const float rdj = rd[j];
       if (rdj > 0.f) {                  // uniform over the block
-        float s = 0.f;
+        const int t = j % RQ;
+        const float fn = fmaxf(fmaf(g[t], rdj, f[t]), 0.f);
+        const float d = quad_bcast_f(fn - f[t], j / RQ);  // the owner's change
+        if (q == j / RQ) f[t] = fn;
 #pragma unroll
-        for (int t = 0; t < RQ; t += 4) {
-          const f32x4 gv = *(const f32x4*)(gs + j * RMAX + c0 + t);
-          s = fmaf(gv[0], f[t], s);
-          s = fmaf(gv[1], f[t + 1], s);
-          s = fmaf(gv[2], f[t + 2], s);
-          s = fmaf(gv[3], f[t + 3], s);
-        }
-        const float gh = (quad_bcast_f(s, 0) + quad_bcast_f(s, 1)) + (quad_bcast_f(s, 2) + quad_bcast_f(s, 3));
-        if (q == j / RQ) {
-          const int t = j % RQ;
-          f[t] = fmaxf(fmaf(p[t] - gh, rdj, f[t]), 0.f);
+        for (int u = 0; u < RQ; u += 4) {
+          const f32x4 gv = *(const f32x4*)(gs + j * RMAX + c0 + u);
+          g[u] = fmaf(-gv[0], d, g[u]);
+          g[u + 1] = fmaf(-gv[1], d, g[u + 1]);
+          g[u + 2] = fmaf(-gv[2], d, g[u + 2]);
+          g[u + 3] = fmaf(-gv[3], d, g[u + 3]);
         }
       }
     }
