@@ -12,6 +12,16 @@
 
 namespace {
 
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// (a, b) -> packed BF16 pair (a in the low half) by the hardware conversion,
+// round to nearest even
+NMF_DEV uint32_t bf16_pk_rne(float a, float b) {
+  const f32x2_t v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+}
+
 NMF_DEV uint16_t bf16_rne(float x) {
   uint32_t u = __builtin_bit_cast(uint32_t, x);
   if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40);  // quiet NaN
@@ -292,21 +302,32 @@ quant_bf16_rows_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int6
                        int64_t ldq, double* __restrict__ sq) {
   const int tid = threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.y * 128 + 16 * (tid >> 5), gj = (int64_t)blockIdx.x * 128 + 4 * (tid & 31);
+  const bool rows_in = i0 + 16 <= m;   // all sixteen rows of this thread exist
   f32x4 v[16];
+  const float* src = X + i0 * ldx + gj;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const f32x4 z = {0.f, 0.f, 0.f, 0.f};
-    v[r] = (i0 + r < m && gj < n) ? __builtin_nontemporal_load((const f32x4*)(X + (i0 + r) * ldx + gj)) : z;
+    v[r] = ((rows_in || i0 + r < m) && gj < n) ? __builtin_nontemporal_load((const f32x4*)(src + r * ldx)) : z;
   }
+  // all sixteen packed rows first (distinct registers), then the stores: a store
+  // right after the conversion that reuses its registers waits for the one before
+  uint2 o[16];
   double ssq = 0.0;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
 #pragma unroll
     for (int d = 0; d < 4; ++d) ssq = fma((double)v[r][d], (double)v[r][d], ssq);
-    if (i0 + r < m)
-      *(uint2*)(Xq + (i0 + r) * ldq + gj) =
-          make_uint2((uint32_t)bf16_rne(v[r][0]) | ((uint32_t)bf16_rne(v[r][1]) << 16),
-                     (uint32_t)bf16_rne(v[r][2]) | ((uint32_t)bf16_rne(v[r][3]) << 16));
+    o[r] = make_uint2(bf16_pk_rne(v[r][0], v[r][1]), bf16_pk_rne(v[r][2], v[r][3]));
+  }
+  uint16_t* dst = Xq + i0 * ldq + gj;
+  if (rows_in) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) *(uint2*)(dst + r * ldq) = o[r];
+  } else {
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      if (i0 + r < m) *(uint2*)(dst + r * ldq) = o[r];
   }
   if (sq) block_sq(ssq, sq);
 }
