@@ -268,6 +268,59 @@ def time_variant(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, prec, refine,
                 ctx=ctx)
 
 
+def time_uncompressed(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, steps, warmup):
+    """Textbook FastHALS (Sec 2.2) on X itself to eps, from the same cold factors:
+    the paper's no-RP reference for the compressed update.  Chunks between exact
+    residual checks follow the fit's rule (by the gap to eps, then 1.5x the
+    straight-line extrapolation of the last two values, 5..50)."""
+    m, n, r, kp, q = cfg["m"], cfg["n"], cfg["r"], cfg["kp"], cfg["q"]
+    max_iters = args.max_iters or cfg["iters"]
+    ctx = nmfrp.NMF(m, n, r, kp, q, seed=seed)
+
+    def step():
+        ctx.init(W0d, H0d)
+        done, e, prev = 0, None, None
+        chunk = 50
+        while done < max_iters:
+            chunk = min(chunk, max_iters - done)
+            ctx.fasthals_step(Xd, chunk)
+            done += chunk
+            e = ctx.residual(Xd)
+            if e <= eps:
+                break
+            if prev is not None and prev[1] > e:
+                slope = (prev[1] - e) / (done - prev[0])
+                chunk = int(min(50, max(5, -(-1.5 * (e - eps) // slope))))
+            else:
+                gap = (e - eps) / eps
+                chunk = 50 if gap > 0.1 else 20 if gap > 0.01 else 10 if gap > 0.003 else 5
+            prev = (done, e)
+        return done, e
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    times, its, es = [], [], []
+    marker_push(torch, "fasthals_uncompressed: timed steps")
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        it, e = step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        its.append(it)
+        es.append(e)
+    marker_pop(torch)
+    # per-iteration time from a run of 20 iterations between HIP events
+    ctx.init(W0d, H0d)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ctx.fasthals_step(Xd, 20)
+    e1.record()
+    torch.cuda.synchronize()
+    return dict(median_s=round(statistics.median(times), 6), times_s=[round(t, 6) for t in times],
+                iters_to_eps=its, e_at_stop=es, per_iteration_ms=round(e0.elapsed_time(e1) / 20, 4))
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_bf16_c2_traffic.md")
 DOMINANT_SRC = os.path.join(ROOT, "paper_1712_02248_amd", "csrc", "gemm_lp.hip")
 
@@ -452,6 +505,11 @@ def main():
         out[vname] = v
         log(f"[bench] {vname}: median {statistics.median(v['times']) * 1e3:.2f} ms, iters {v['iters']}, "
             f"e_init {v['e_init']:.4e}, e {v['e'][-1]:.6e}, rejected {v['rejected']}")
+    unc = None
+    if not args.headline_only and (not args.variants or "fasthals_uncompressed" in args.variants.split(",")):
+        unc = time_uncompressed(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, 3, 1)
+        log(f"[bench] fasthals_uncompressed: median {unc['median_s'] * 1e3:.2f} ms, iters {unc['iters_to_eps']}, "
+            f"{unc['per_iteration_ms']:.3f} ms per iteration")
     head = out.get(HEADLINE) or next(iter(out.values()))
     plain = out.get("plain")
     total_head = sum(head["times"])
@@ -493,6 +551,9 @@ def main():
         plain_fp32=dict(value=round(pmed, 6), **summary(plain)) if plain else None,
         speedup_vs_plain=round(pmed / vmed, 3) if plain else None,
         variants={k: summary(v) for k, v in out.items()},
+        # the paper's RP vs no-RP comparison (Sec 2.2 vs eq fastHALS_a), both FP32 and cold
+        fasthals_uncompressed=(dict(unc, speedup_of_rp_plain=round(unc["median_s"] / pmed, 3) if plain else None)
+                               if unc else None),
         warm_start=warm_info,
         gemm=kt,
         update_loop=dict(algorithmic_bytes_per_iteration=upd_bytes, per_iteration_ms=round(per_iter_ms, 4),

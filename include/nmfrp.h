@@ -107,13 +107,26 @@ nmf_status nmf_compress(nmf_ctx* ctx, const float* X, int64_t ldx, const float* 
                         const float* omega_R);
 
 /* Sets the initial factors (copied): W0 m x r, Ht0 n x r, device.  NULL draws
- * U[0,1) * init_scale from Philox (streams 5 and 6). */
+ * U[0,1) * init_scale from Philox (streams 5 and 6).  Needs no sketches (the
+ * uncompressed nmf_fasthals_step runs on the factors alone); when the context
+ * is or later gets compressed, Q_R^T Ht for nmf_step follows. */
 nmf_status nmf_init(nmf_ctx* ctx, const float* W0, const float* Ht0, float init_scale);
 
 /* `iters` FastHALS-RP iterations (eq fastHALS_a): the whole W sweep against
  * (Xc, Hc = Q_R^T Ht), column normalisation, then the whole H sweep against
- * (Xh, Wh = Q_L^T W).  Asynchronous. */
+ * (Xh, Wh = Q_L^T W).  Needs the sketches (nmf_compress or nmf_set_state) and
+ * the factors (nmf_init), in either order.  Asynchronous. */
 nmf_status nmf_step(nmf_ctx* ctx, int32_t iters);
+
+/* `iters` iterations of uncompressed FastHALS (Sec 2.2) on X itself (m x n,
+ * ldx >= n, ldx % 4 == 0, 16-byte aligned): the W sweep against X Ht and
+ * Ht^T Ht, the column normalisation of nmf_params.normalize, then the H sweep
+ * against X^T W and W^T W (FP32 MFMA products over X, FP64 Grams, FP32 sweeps).
+ * The reference against which the compressed update (nmf_step) is compared.
+ * Starts from the context's factors (nmf_init; a pending normalisation of the
+ * compressed steps is applied first) and leaves them in place; the compressed
+ * state (Q_R^T Ht) is refreshed when the context is compressed.  Asynchronous. */
+nmf_status nmf_fasthals_step(nmf_ctx* ctx, const float* X, int64_t ldx, int32_t iters);
 
 /* Exact e = ||X - W Ht^T||_F / ||X||_F in FP64 (eq 2.2).  Synchronising. */
 nmf_status nmf_residual(nmf_ctx* ctx, const float* X, int64_t ldx, double* rel_err);

@@ -135,6 +135,15 @@ struct HalfStepArgs {
 int halfstep_blocks(int64_t N);
 size_t halfstep_part_floats(int64_t N, int kp, int r);
 hipError_t launch_halfstep(const HalfStepArgs& a, int do_sweep, hipStream_t st);
+// Uncompressed FastHALS (Sec 2.2): one sweep over the rows of F against P and G
+// (FP64, r x r); sq (optional) gets hals_rows_blocks(N) x r column sums of F^2.
+int hals_rows_blocks(int64_t N);
+hipError_t launch_hals_rows(const float* P, int64_t ldp, const double* G, int64_t N, int r, float* F, int64_t ldf,
+                            float* sq, hipStream_t st);
+// a_j /= sqrt(sumsq[j]) in W (M x r, ld); mode 1 also b_j *= sqrt(sumsq[j]) in Ht (N x r, ld);
+// mode 0: nothing.
+hipError_t launch_col_normalise(float* W, int64_t M, float* Ht, int64_t N, int r, int64_t ld, const double* sumsq,
+                                int mode, hipStream_t st);
 // out[e] = sum_s part[s * ne + e] in FP64, fixed order (skip: NULL or flag; skipped when *skip == 0).
 hipError_t launch_sum_partials_f32(const float* part, int nparts, int64_t ne, double* out,
                                    hipStream_t st);

@@ -430,6 +430,102 @@ sum_partials_few_kernel(const T* __restrict__ part, int nparts, int64_t ne, doub
   if (threadIdx.x == 0) out[e] = red[0];
 }
 
+
+// ------------------------------------------------- uncompressed FastHALS (Sec 2.2)
+// One sweep of the textbook rule over the rows of F (N x r, ld ldf) against the
+// full-data targets: F = W with P = X Ht and G = Ht^T Ht, or F = Ht with P = X^T W
+// and G = W^T W:  f_j <- [f_j + (p_j - (f G)_j) / G_jj]_+ , j ascending (G_jj <= 0:
+// f_j unchanged).  A quad of lanes per row, lane q owning components
+// q RMAX/4 .. +RMAX/4 - 1; gradient form as in the column NNLS (g = p - G f once,
+// then g -= G[:, j] d after component j changes by d).  G (FP64) is staged in
+// LDS as FP32.  sq (optional): per-workgroup column sums of F^2 after the sweep
+// (nblk x r), for the normalisation a_j / ||a_j|| (end of Sec 4).
+template <int RMAX>
+__global__ void __launch_bounds__(256)
+hals_rows_kernel(const float* __restrict__ P, int64_t ldp, const double* __restrict__ G, int64_t N, int r,
+                 float* __restrict__ F, int64_t ldf, float* __restrict__ sq) {
+  constexpr int RQ = RMAX / 4;
+  __shared__ __attribute__((aligned(16))) float gs[RMAX * RMAX];
+  __shared__ float rd[RMAX];
+  __shared__ float csum[4][RMAX];
+  for (int e = threadIdx.x; e < RMAX * RMAX; e += 256) {
+    const int a = e / RMAX, b = e % RMAX;
+    const double v = (a < r && b < r) ? G[a * r + b] : 0.0;
+    gs[e] = (float)v;
+    if (a == b) rd[a] = v > 0.0 ? (float)(1.0 / v) : 0.f;
+  }
+  __syncthreads();
+  const int q = threadIdx.x & 3, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t row = (int64_t)blockIdx.x * 64 + (threadIdx.x >> 2);
+  const bool valid = row < N;
+  const int c0 = q * RQ;
+  float f[RQ], g[RQ];
+#pragma unroll
+  for (int t = 0; t < RQ; ++t) {
+    const bool in = valid && c0 + t < r;
+    f[t] = in ? F[row * ldf + c0 + t] : 0.f;
+    g[t] = in ? P[row * ldp + c0 + t] : 0.f;
+  }
+  // g = p - G f, with f of every component taken from its lane
+#pragma unroll
+  for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+    for (int u = 0; u < RQ; ++u) {
+      const float hv = quad_bcast(f[u], qq);
+      const int col = qq * RQ + u;
+#pragma unroll
+      for (int t = 0; t < RQ; ++t) g[t] = fmaf(-gs[col * RMAX + c0 + t], hv, g[t]);
+    }
+#pragma unroll
+  for (int j = 0; j < RMAX; ++j) {
+    const float rdj = rd[j];
+    if (rdj > 0.f) {                      // uniform over the block
+      const int t = j % RQ;
+      const float fn = fmaxf(fmaf(g[t], rdj, f[t]), 0.f);
+      const float d = quad_bcast(fn - f[t], j / RQ);
+      if (q == j / RQ) f[t] = fn;
+#pragma unroll
+      for (int u = 0; u < RQ; ++u) g[u] = fmaf(-gs[j * RMAX + c0 + u], d, g[u]);
+    }
+  }
+  if (valid) {
+#pragma unroll
+    for (int t = 0; t < RQ; ++t)
+      if (c0 + t < r) F[row * ldf + c0 + t] = f[t];
+  }
+  if (!sq) return;                        // uniform
+  // column sums of f^2 over the block's 64 rows: the 16 rows of a wave by lane
+  // moves (xor over the row bits of the lane index), then the four waves in LDS
+#pragma unroll
+  for (int t = 0; t < RQ; ++t) {
+    float v = f[t] * f[t];
+#pragma unroll
+    for (int off = 4; off < 64; off <<= 1) v += __shfl_xor(v, off);
+    if (lane < 4 && c0 + t < RMAX) csum[wave][c0 + t] = v;   // lanes 0..3 are quads' lane q
+  }
+  __syncthreads();
+  if (threadIdx.x < r)
+    sq[(int64_t)blockIdx.x * r + threadIdx.x] =
+        (csum[0][threadIdx.x] + csum[1][threadIdx.x]) + (csum[2][threadIdx.x] + csum[3][threadIdx.x]);
+}
+
+// a_j <- a_j / ||a_j|| for the columns of W (M x r, ld ld) with ||a_j||^2 = sumsq[j]
+// (FP64); mode 1 (compensated) also b_j <- b_j ||a_j|| in Ht (N x r, ld ld); zero
+// columns stay.
+__global__ void __launch_bounds__(256)
+col_normalise_kernel(float* __restrict__ W, int64_t M, float* __restrict__ Ht, int64_t N, int r, int64_t ld,
+                     const double* __restrict__ sumsq, int mode) {
+  const int64_t tw = M * r, total = tw + (mode == 1 ? N * r : 0);
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t f = e < tw ? e : e - tw;
+    const int64_t i = f / r;
+    const int j = (int)(f - i * r);
+    const double s = sqrt(sumsq[j]);
+    if (!(s > 0.0)) continue;
+    if (e < tw) W[i * ld + j] = (float)((double)W[i * ld + j] / s);
+    else Ht[i * ld + j] = (float)((double)Ht[i * ld + j] * s);
+  }
+}
 }  // namespace
 
 int halfstep_blocks(int64_t N) {
@@ -478,5 +574,31 @@ hipError_t launch_sum_partials_f64(const double* part, int nparts, int64_t ne, d
   }
   hipLaunchKernelGGL(sum_partials_kernel<double>, dim3((unsigned)ceil_div(ne, 16)), dim3(256), 0, st,
                      part, nparts, ne, out, skip);
+  return hipGetLastError();
+}
+
+int hals_rows_blocks(int64_t N) { return (int)ceil_div(N, 64); }
+
+hipError_t launch_hals_rows(const float* P, int64_t ldp, const double* G, int64_t N, int r, float* F, int64_t ldf,
+                            float* sq, hipStream_t st) {
+  if (N == 0) return hipSuccess;
+  const dim3 grid((unsigned)hals_rows_blocks(N));
+  if (r <= 16)
+    hipLaunchKernelGGL(hals_rows_kernel<16>, grid, dim3(256), 0, st, P, ldp, G, N, r, F, ldf, sq);
+  else if (r <= 32)
+    hipLaunchKernelGGL(hals_rows_kernel<32>, grid, dim3(256), 0, st, P, ldp, G, N, r, F, ldf, sq);
+  else if (r <= 64)
+    hipLaunchKernelGGL(hals_rows_kernel<64>, grid, dim3(256), 0, st, P, ldp, G, N, r, F, ldf, sq);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_col_normalise(float* W, int64_t M, float* Ht, int64_t N, int r, int64_t ld, const double* sumsq,
+                                int mode, hipStream_t st) {
+  if (mode == 0) return hipSuccess;
+  int64_t g = ceil_div((M + N) * r, 256);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(col_normalise_kernel, dim3((unsigned)g), dim3(256), 0, st, W, M, Ht, N, r, ld, sumsq, mode);
   return hipGetLastError();
 }

@@ -582,6 +582,8 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
   HIPCHK(c, hipEventRecord(c->ev[1], st));
   c->t_compress = true;
   c->compressed = true;
+  // factors set before this compression: their Q_R^T Ht follows the new basis
+  if (c->initialized) HIPCHK(c, halfstep_h(c, 0));
   c->stepped = false;
   c->xsq_valid = true;
   return NMF_OK;
@@ -589,7 +591,6 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
 
 nmf_status nmf_init(nmf_ctx* c, const float* W0, const float* Ht0, float init_scale) {
   if (!c) return fail(c, NMF_EINVAL, "null context");
-  if (!c->compressed) return fail(c, NMF_ESTATE, "init needs the sketches: call nmf_compress or nmf_set_state first");
   Layout& L = c->L;
   const int64_t m = c->p.m, n = c->p.n;
   const int r = c->p.r;
@@ -599,7 +600,9 @@ nmf_status nmf_init(nmf_ctx* c, const float* W0, const float* Ht0, float init_sc
   if (Ht0 && Ht0 != Ht) HIPCHK(c, launch_copy2d(Ht, r, Ht0, r, n, r, c->st));
   else if (!Ht0) HIPCHK(c, launch_philox_uniform(Ht, n, r, r, 6u, c->p.seed, init_scale, c->st));
   HIPCHK(c, launch_fill_f32(c->at<float>(L.scale_w), r, 1.f, c->st));
-  HIPCHK(c, halfstep_h(c, 0));   // acc_h = Q_R^T Ht (Hc for the first W half-step)
+  // acc_h = Q_R^T Ht (Hc for the first W half-step); formed by nmf_compress when
+  // the factors come first
+  if (c->compressed) HIPCHK(c, halfstep_h(c, 0));
   c->initialized = true;
   c->stepped = false;
   return NMF_OK;
@@ -704,6 +707,7 @@ nmf_status nmf_init_learned_ref(nmf_ctx* c, nmf_mlp* net, const float* Q_train, 
 nmf_status nmf_step(nmf_ctx* c, int32_t iters) {
   if (!c || iters < 0) return fail(c, NMF_EINVAL, "bad arguments");
   if (!c->initialized) return fail(c, NMF_ESTATE, "step needs nmf_init");
+  if (!c->compressed) return fail(c, NMF_ESTATE, "step needs the sketches: call nmf_compress or nmf_set_state first");
   HIPCHK(c, hipEventRecord(c->ev[2], c->st));
   for (int t = 0; t < iters; ++t) {
     HIPCHK(c, halfstep_w(c));
@@ -712,6 +716,63 @@ nmf_status nmf_step(nmf_ctx* c, int32_t iters) {
   HIPCHK(c, hipEventRecord(c->ev[3], c->st));
   c->t_step = true;
   if (iters > 0) c->stepped = true;
+  return NMF_OK;
+}
+
+nmf_status nmf_fasthals_step(nmf_ctx* c, const float* X, int64_t ldx, int32_t iters) {
+  if (!c || !X || iters < 0) return fail(c, NMF_EINVAL, "bad arguments");
+  if (ldx < c->p.n || ldx % 4 || !aligned16(X)) return fail(c, NMF_EINVAL, "X needs ldx >= n, ldx % 4 == 0, 16-byte alignment");
+  if (!c->initialized) return fail(c, NMF_ESTATE, "fasthals step needs factors (nmf_init)");
+  if (iters == 0) return NMF_OK;
+  Layout& L = c->L;
+  const int64_t m = c->p.m, n = c->p.n;
+  const int r = c->p.r;
+  const int64_t rp = round_up(r, 4);   // rows of the working copies: 16-byte aligned operands
+  hipStream_t st = c->st;
+  float *W = c->at<float>(L.W), *Ht = c->at<float>(L.Ht), *sw = c->at<float>(L.scale_w);
+  // working copies in the test-matrix buffers (free after compression; k' > r, so
+  // K = k' rounded up to 4 >= rp), products in the temporaries
+  float *Wp = c->at<float>(L.omR), *Hp = c->at<float>(L.omL);
+  float *PW = c->at<float>(L.TM), *PH = c->at<float>(L.TN);   // X Ht (m x r), X^T W (n x r)
+  double* G = c->at<double>(L.G);                             // r x r Gram (r < k')
+  double* cs = c->at<double>(L.acc_w);                        // r column sums of W^2
+  float* sqp = c->at<float>(L.hs_part);
+  float* gp = c->at<float>(L.gemm_part);
+  const size_t hs_floats = std::max(halfstep_part_floats(m, (int)L.KP, r), halfstep_part_floats(n, (int)L.KP, r));
+  if ((size_t)hals_rows_blocks(m) * r > hs_floats) return fail(c, NMF_ENOMEM, "column-sum partials exceed the scratch");
+  // W with the compressed steps' pending column normalisation applied
+  HIPCHK(c, launch_fill_f32(Wp, m * rp, 0.f, st));
+  HIPCHK(c, launch_fill_f32(Hp, n * rp, 0.f, st));
+  HIPCHK(c, launch_scale_cols(Wp, rp, W, r, m, r, sw, st));
+  HIPCHK(c, launch_copy2d(Hp, rp, Ht, r, n, r, st));
+  // split-K partials within the context's product scratch
+  auto splits_for = [&](int64_t M, int64_t K, int at) {
+    int s = gemm_f32_pick_splits(M, r, K, at);
+    while (s > 1 && gemm_f32_part_floats(M, r, s) * sizeof(float) > L.gemm_part_bytes) s /= 2;
+    return s;
+  };
+  const int s_w = splits_for(m, n, 0), s_h = splits_for(n, m, 1);
+  const bool nrm = c->p.normalize != 0;
+  for (int it = 0; it < iters; ++it) {
+    // W sweep against X Ht and Ht^T Ht, then a_j / ||a_j||
+    HIPCHK(c, launch_gemm_f32(X, ldx, 0, Hp, rp, PW, rp, m, r, n, s_w, gp, st));
+    HIPCHK(c, launch_gram_f64(Hp, rp, n, r, c->at<double>(L.gram_part), gram_pick_splits(n, r), G, nullptr, st));
+    HIPCHK(c, launch_hals_rows(PW, rp, G, m, r, Wp, rp, nrm ? sqp : nullptr, st));
+    if (nrm) {
+      HIPCHK(c, launch_sum_partials_f32(sqp, hals_rows_blocks(m), r, cs, st));
+      HIPCHK(c, launch_col_normalise(Wp, m, Hp, n, r, rp, cs, c->p.normalize, st));
+    }
+    // H sweep against X^T W and W^T W
+    HIPCHK(c, launch_gemm_f32(X, ldx, 1, Wp, rp, PH, rp, n, r, m, s_h, gp, st));
+    HIPCHK(c, launch_gram_f64(Wp, rp, m, r, c->at<double>(L.gram_part), gram_pick_splits(m, r), G, nullptr, st));
+    HIPCHK(c, launch_hals_rows(PH, rp, G, n, r, Hp, rp, nullptr, st));
+  }
+  HIPCHK(c, launch_copy2d(W, r, Wp, rp, m, r, st));
+  HIPCHK(c, launch_copy2d(Ht, r, Hp, rp, n, r, st));
+  HIPCHK(c, launch_fill_f32(sw, r, 1.f, st));
+  // the compressed update's state (Q_R^T Ht) follows the new factors
+  if (c->compressed) HIPCHK(c, halfstep_h(c, 0));
+  c->stepped = false;
   return NMF_OK;
 }
 

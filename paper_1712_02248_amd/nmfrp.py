@@ -40,6 +40,7 @@ _SIGS = {
     "nmf_compress": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp]),
     "nmf_init": (c_i32, [c_vp, c_vp, c_vp, ctypes.c_float]),
     "nmf_step": (c_i32, [c_vp, c_i32]),
+    "nmf_fasthals_step": (c_i32, [c_vp, c_vp, c_i64, c_i32]),
     "nmf_residual": (c_i32, [c_vp, c_vp, c_i64, c_dbl_p]),
     "nmf_residual_check": (c_i32, [c_vp, c_vp, c_i64, ctypes.c_double, c_dbl_p, c_dbl_p, c_i32_p]),
     "nmf_proxy_residual": (c_i32, [c_vp, c_dbl_p]),
@@ -191,6 +192,12 @@ class NMF:
 
     def step(self, iters=1):
         self._c(load().nmf_step(self.h, int(iters)))
+
+    def fasthals_step(self, X, iters=1):
+        """Uncompressed FastHALS iterations (Sec 2.2) on X from the current factors."""
+        if X.dtype != torch.float32 or X.stride(1) != 1:
+            raise ValueError("X: float32, unit column stride")
+        self._c(load().nmf_fasthals_step(self.h, _ptr(X), X.stride(0), int(iters)))
 
     def residual(self, X):
         e = ctypes.c_double()

@@ -128,6 +128,58 @@ def test_c1_first_iterations_elementwise(lib, normalize):
         assert (Wg >= 0).all() and (Hg >= 0).all()
 
 
+@pytest.mark.parametrize("normalize", [1, 0, 2])
+def test_uncompressed_fasthals_matches_oracle(lib, normalize):
+    """nmf_fasthals_step (Sec 2.2, on X itself) against the oracle's textbook
+    FastHALS: factors after 1, 2 and 5 iterations, elementwise (the tolerance of
+    the compressed iterations), and the compressed update continuing from them."""
+    print(f"uncompressed fasthals normalize={normalize}", flush=True)
+    m, n, r, kp, q = 512, 256, 10, 20, 2
+    X, OL, OR, W0, H0 = small_case(m, n, r, kp, datagen.cfg_seed("c1"))
+    for iters in (1, 2, 5):
+        ctx, Xd = gpu_run(lib, X, OL, OR, W0, H0, r, kp, q, 0, normalize)
+        ctx.fasthals_step(Xd, iters)
+        Wg, Hg = (t.cpu().numpy().astype(np.float64) for t in ctx.factors())
+        W, Ht = onmf.fasthals(X, W0, H0, iters, normalize)
+        tol = 2e-3 * iters
+        assert np.abs(Wg - W).max() <= tol * np.abs(W).max(), iters
+        assert np.abs(Hg - Ht).max() <= tol * np.abs(Ht).max(), iters
+        assert (Wg >= 0).all() and (Hg >= 0).all()
+        assert abs(ctx.residual(Xd) - onmf.rel_error(X, W, Ht)) <= 1e-4
+    # the compressed update picks up from the uncompressed factors (Q_R^T Ht refreshed)
+    rQL, rQR, rXh, rXc = onmf.compress(X, OL, OR, q)
+    ctx.step(1)
+    W1, H1 = onmf.fasthals_rp_iteration(W, Ht, rXh, rXc, rQL, rQR, normalize)
+    Wg1, Hg1 = (t.cpu().numpy().astype(np.float64) for t in ctx.factors())
+    assert np.abs(Wg1 - W1).max() <= 2e-2 * np.abs(W1).max()
+    assert np.abs(Hg1 - H1).max() <= 2e-2 * np.abs(H1).max()
+
+
+def test_init_before_compress_and_uncompressed_without_sketches(lib):
+    """Factors set before the compression give the same compressed iterations
+    as the usual order (Q_R^T Ht formed by the compression); the uncompressed
+    iterations need no sketches; the compressed ones refuse to run without."""
+    print("init order", flush=True)
+    m, n, r, kp, q = 512, 256, 10, 20, 2
+    X, OL, OR, W0, H0 = small_case(m, n, r, kp, datagen.cfg_seed("c1"))
+    ref, Xd = gpu_run(lib, X, OL, OR, W0, H0, r, kp, q, 3)
+    Wr, Hr = (t.cpu().numpy() for t in ref.factors())
+    ctx = lib.NMF(m, n, r, kp, q, seed=7)
+    ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
+    with pytest.raises(lib.NmfError):
+        ctx.step(1)                                        # no sketches yet
+    ctx.compress(Xd, torch.from_numpy(OL).cuda(), torch.from_numpy(OR).cuda())
+    ctx.step(3)
+    Wg, Hg = (t.cpu().numpy() for t in ctx.factors())
+    assert np.array_equal(Wg, Wr) and np.array_equal(Hg, Hr)
+    plain = lib.NMF(m, n, r, kp, q, seed=7)
+    plain.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
+    plain.fasthals_step(Xd, 2)
+    W, Ht = onmf.fasthals(X, W0, H0, 2)
+    Wp, Hp = (t.cpu().numpy().astype(np.float64) for t in plain.factors())
+    assert np.abs(Wp - W).max() <= 4e-3 * np.abs(W).max() and np.abs(Hp - Ht).max() <= 4e-3 * np.abs(Ht).max()
+
+
 def test_c1_full_parity_200_iterations(lib):
     print("c1 200 iterations", flush=True)
     c = datagen.CONFIGS["c1"]
