@@ -71,6 +71,9 @@ def parse():
                     help="column-NNLS sweeps on the warm rows against the reference dictionary")
     ap.add_argument("--headline-only", action="store_true", help="time only plain and bf16_warm")
     ap.add_argument("--variants", default="", help="comma list of variants to time (default: all)")
+    ap.add_argument("--sweep", default="", help="parameter study instead of the bench: P1, P2 or c2 "
+                    "(components r x power iterations q, FastHALS-RP against FastHALS, sketch spectrum)")
+    ap.add_argument("--sweep-seeds", type=int, default=3, help="test-matrix seeds per sweep point (median)")
     ap.add_argument("--probe-kernels", action="store_true",
                     help="only a copy of known size and the dominant kernel (for counter runs)")
     return ap.parse_args()
@@ -424,6 +427,88 @@ def probe_kernels(torch, nmfrp, Xd, m, n, kp, reps):
                           source_sha256_16=source_digest(DOMINANT_SRC))), flush=True)
 
 
+# Parameter study grids (Sec 5.2): components r, oversampling r_ov (k' = r + r_ov),
+# power iterations q.  P1 and P2 stand in for the two data sets of that section
+# (their grids; r above 64 exceeds this build's kernels), c2 is the bench workload.
+SWEEPS = {
+    "P1": dict(rs=[10, 20, 30, 40, 50], r_ov=5, qs=[1, 2, 3, 4, 5]),
+    "P2": dict(rs=[50, 60, 70, 80, 90], r_ov=12, qs=[1, 3, 5, 7, 9, 11]),
+    "c2": dict(rs=[16, 32, 48, 64], r_ov=32, qs=[0, 1, 2, 3, 4]),
+}
+
+
+def run_sweep(torch, nmfrp, datagen, name, args):
+    """FastHALS-RP (median over test-matrix seeds) and FastHALS after the workload's
+    iteration count, for every (r, q) of the grid, with the compressed data's
+    singular values and their decay fits (both readings of the decay law)."""
+    cfg = dict(datagen.CONFIGS[name])
+    grid = SWEEPS[name]
+    m, n, iters = cfg["m"], cfg["n"], cfg["iters"]
+    seed = datagen.cfg_seed(name)
+    log(f"[sweep] generating {name} X {m}x{n}")
+    X = datagen.make_x(name)
+    Xd = torch.from_numpy(X).cuda()
+    points, unc, skipped = [], {}, []
+    spec = None
+    for r in grid["rs"]:
+        kp = r + grid["r_ov"]
+        if r > 64 or kp > 128 or kp > min(m, n):
+            skipped.append(dict(r=r, kp=kp, why="r > 64 or k' > 128 exceeds this build's kernels"))
+            continue
+        W0, H0 = datagen.init_factors(X.mean(), m, n, r, seed)
+        W0d, H0d = torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda()
+        ctx = nmfrp.NMF(m, n, r, kp, 0, seed=seed)
+        ctx.init(W0d, H0d)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.fasthals_step(Xd, iters)
+        torch.cuda.synchronize()
+        unc[r] = dict(r=r, e=ctx.residual(Xd), iters_ms=round((time.perf_counter() - t0) * 1e3, 3))
+        del ctx
+        for q in grid["qs"]:
+            es, tc, ti = [], [], []
+            for s_ in range(args.sweep_seeds):
+                ctx = nmfrp.NMF(m, n, r, kp, q, seed=seed + 1000 * s_)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                ctx.compress(Xd)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                ctx.init(W0d, H0d)
+                ctx.step(iters)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                es.append(ctx.residual(Xd))
+                tc.append(t1 - t0)
+                ti.append(t2 - t1)
+                if s_ == 0:
+                    sig = ctx.sketch_spectrum().numpy()
+                del ctx
+            pt = dict(r=r, kp=kp, q=q, e_median=statistics.median(es), e=es,
+                      compress_ms=round(statistics.median(tc) * 1e3, 3), iters_ms=round(statistics.median(ti) * 1e3, 3),
+                      e_fasthals=unc[r]["e"])
+            points.append(pt)
+            log(f"[sweep] r={r} k'={kp} q={q}: e_rp {pt['e_median']:.6e} (FastHALS {unc[r]['e']:.6e}), "
+                f"compress {pt['compress_ms']} ms, {iters} iterations {pt['iters_ms']} ms")
+            spec = (r, kp, q, sig)
+    best = {}
+    for pt in points:
+        b = best.get(pt["r"])
+        if b is None or pt["e_median"] < b["e_median"]:
+            best[pt["r"]] = pt
+    out = dict(study="parameter sweep (Sec 5.2)", workload=name, m=m, n=n, iters=iters, r_ov=grid["r_ov"],
+               seeds=args.sweep_seeds, data="synthetic", points=points, fasthals=list(unc.values()),
+               best_q={r: b["q"] for r, b in best.items()}, skipped=skipped)
+    if spec is not None:
+        r, kp, q, sig = spec
+        j = np.arange(1, kp + 1, dtype=np.float64)
+        ls = np.log(np.maximum(sig, 1e-300))
+        out["spectrum"] = dict(r=r, kp=kp, q=q, sigma=[float(v) for v in sig],
+                               decay_power=float(-np.polyfit(np.log(j), ls, 1)[0]),
+                               decay_exp=float(-np.polyfit(j, ls, 1)[0]))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -437,6 +522,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     nmfrp.load()
+    if args.sweep:
+        run_sweep(torch, nmfrp, datagen, args.sweep, args)
+        return
     name = args.workload
     cfg = dict(datagen.CONFIGS[name])
     cfg["name"] = name

@@ -153,6 +153,19 @@ nmf_status nmf_residual_check(nmf_ctx* ctx, const float* X, int64_t ldx, double 
  * (not nmf_set_state); NMF_ESTATE otherwise.  Synchronising. */
 nmf_status nmf_proxy_residual(nmf_ctx* ctx, double* rel_err);
 
+/* Singular values of the compressed data X-hat = Q_L^T X (Sec 4; k' x n),
+ * sigma_1 >= ... >= sigma_k', written to sigma (host memory, k' doubles).  For
+ * every j they are at most sigma_j(X), and the leading ones approach sigma_j(X)
+ * as the basis captures the dominant subspace (Sec 3.1; the power iterations of
+ * eq 3.5 sharpen it).  Their decay is what the paper's parameter study relates
+ * the best power-iteration count to (Sec 5.2).  Computed as the square roots of
+ * the eigenvalues of X-hat X-hat^T (FP64 Gram of the stored X-hat, FP64 Jacobi;
+ * see nmf_sym_eigvals).  Needs a compression (nmf_compress or nmf_set_state),
+ * NMF_ESTATE otherwise; NMF_ENONFINITE for non-finite compressed data.
+ * Synchronising; uses the range finder's scratch, so it must not overlap an
+ * nmf_compress on the same context. */
+nmf_status nmf_sketch_spectrum(nmf_ctx* ctx, double* sigma);
+
 /* Runs steps in chunks, evaluating the residual after each chunk, until
  * e <= eps or max_iters iterations (the paper leaves the stopping rule open:
  * Alg 1-4).  check_every > 0: fixed chunk.  check_every == 0 after
@@ -294,6 +307,17 @@ nmf_status nmf_gemm_split(const float* X, int64_t ldx, int32_t at, const float* 
 size_t nmf_orth_workspace_bytes(int64_t rows, int32_t k);
 nmf_status nmf_orth(float* Y, int64_t ldy, int64_t rows, int32_t k, void* workspace,
                     size_t ws_bytes, void* hip_stream, int32_t* shifted);
+
+/* Eigenvalues of a symmetric k x k FP64 matrix (device, row-major, lda >= k;
+ * only the lower triangle, column <= row, is read), 1 <= k <= 128, written to w
+ * (device, k doubles) in descending order.  Cyclic Jacobi in parallel
+ * (round-robin) order in one workgroup (Golub and Van Loan, Sec 8.5), until the
+ * off-diagonal Frobenius norm is below 1e-13 of the matrix's (at most 40
+ * sweeps), so each eigenvalue is within that bound.  The building block of
+ * nmf_sketch_spectrum.  Synchronising; *sweeps (may be NULL) = sweeps used.
+ * NMF_ENONFINITE (w not written) if an entry read is not finite. */
+nmf_status nmf_sym_eigvals(const double* A, int64_t lda, int32_t k, double* w, void* hip_stream,
+                           int32_t* sweeps);
 
 
 /* --------------------------------------------------- learned warm start of H

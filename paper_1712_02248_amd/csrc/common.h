@@ -97,6 +97,10 @@ hipError_t launch_gemm_fp8_nt(const uint8_t* A, int64_t lda, const int* EA, int6
 hipError_t launch_gram_f64(const float* Y, int64_t ldy, int64_t rows, int k, double* part,
                            int splits, double* G, const int* skip_flag, hipStream_t st);
 int gram_pick_splits(int64_t rows, int k);
+// Eigenvalues of a symmetric k x k FP64 matrix (k <= 128; lower triangle read) by
+// parallel cyclic Jacobi in one workgroup (eig.hip): w descending, or their clamped
+// square roots with sqrt_out; info[0] = sweeps, info[1] = 1 for a non-finite entry.
+hipError_t launch_sym_eig(const double* A, int64_t lda, int k, int sqrt_out, double* w, int* info, hipStream_t st);
 // C (ka x kb, row-major FP32) = A^T B over `rows` rows, FP64 accumulation (ka, kb <= the
 // Gram's k; part: splits x ka x kb doubles; C64: ka x kb doubles).
 hipError_t launch_atb_f32out(const float* A, int64_t lda, int ka, const float* B, int64_t ldb, int kb,

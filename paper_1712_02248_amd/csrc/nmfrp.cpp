@@ -864,6 +864,26 @@ nmf_status nmf_proxy_residual(nmf_ctx* c, double* rel_err) {
   return NMF_OK;
 }
 
+nmf_status nmf_sketch_spectrum(nmf_ctx* c, double* sigma) {
+  if (!c || !sigma) return fail(c, NMF_EINVAL, "bad arguments");
+  if (!c->compressed) return fail(c, NMF_ESTATE, "the spectrum needs the compressed data (nmf_compress or nmf_set_state)");
+  Layout& L = c->L;
+  const int k = c->p.k_sketch;
+  const int64_t n = c->p.n;
+  // X-hat X-hat^T = Xh^T Xh (k' x k', FP64) in the second chain's scratch, then its eigenvalues
+  double* G = c->at<double>(L.G2);
+  double* w = c->at<double>(L.R2);
+  int* info = (int*)(c->hout_dev + 8);
+  HIPCHK(c, launch_gram_f64(c->at<float>(L.Xh), L.KP, n, k, c->at<double>(L.gram_part2), gram_pick_splits(n, k), G,
+                            nullptr, c->st));
+  HIPCHK(c, launch_sym_eig(G, k, k, 1, w, info, c->st));
+  HIPCHK(c, hipMemcpyAsync(sigma, w, (size_t)k * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  const int* hi = (const int*)(c->hout + 8);
+  if (hi[1]) return fail(c, NMF_ENONFINITE, "non-finite compressed data");
+  return NMF_OK;
+}
+
 namespace {
 
 // One synchronisation for a proxy reading and, when the proxy is already within
@@ -1280,6 +1300,25 @@ nmf_status nmf_orth(float* Y, int64_t ldy, int64_t rows, int32_t k, void* ws, si
   if (e) return fail(nullptr, NMF_EHIP, hipGetErrorString(e));
   if (shifted) *shifted = h[0];
   if (h[1]) return fail(nullptr, NMF_EBREAKDOWN, "Cholesky breakdown even with the shift");
+  return NMF_OK;
+}
+
+nmf_status nmf_sym_eigvals(const double* A, int64_t lda, int32_t k, double* w, void* hs, int32_t* sweeps) {
+  if (!A || !w || k <= 0 || k > 128 || lda < k) return fail(nullptr, NMF_EINVAL, "bad arguments");
+  double* ho = take_host_out();
+  double* hd = nullptr;
+  if (!ho || hipHostGetDevicePointer((void**)&hd, ho, 0) != hipSuccess) {
+    give_host_out(ho);
+    return fail(nullptr, NMF_ENOMEM, "no pinned result buffer");
+  }
+  hipStream_t st = (hipStream_t)hs;
+  hipError_t e = launch_sym_eig(A, lda, k, 0, w, (int*)hd, st);
+  if (!e) e = hipStreamSynchronize(st);
+  const int h[2] = {((const int*)ho)[0], ((const int*)ho)[1]};
+  give_host_out(ho);
+  if (e) return fail(nullptr, NMF_EHIP, hipGetErrorString(e));
+  if (sweeps) *sweeps = h[0];
+  if (h[1]) return fail(nullptr, NMF_ENONFINITE, "non-finite matrix entry");
   return NMF_OK;
 }
 

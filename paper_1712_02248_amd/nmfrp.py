@@ -44,6 +44,7 @@ _SIGS = {
     "nmf_residual": (c_i32, [c_vp, c_vp, c_i64, c_dbl_p]),
     "nmf_residual_check": (c_i32, [c_vp, c_vp, c_i64, ctypes.c_double, c_dbl_p, c_dbl_p, c_i32_p]),
     "nmf_proxy_residual": (c_i32, [c_vp, c_dbl_p]),
+    "nmf_sketch_spectrum": (c_i32, [c_vp, c_dbl_p]),
     "nmf_fit": (c_i32, [c_vp, c_vp, c_i64, c_i32, ctypes.c_double, c_i32, c_i32_p, c_dbl_p]),
     "nmf_get_factors": (c_i32, [c_vp, c_vp, c_vp]),
     "nmf_get_state": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
@@ -68,6 +69,7 @@ _SIGS = {
     "nmf_gemm_split": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_i64, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp, c_sz, c_vp]),
     "nmf_orth_workspace_bytes": (c_sz, [c_i64, c_i32]),
     "nmf_orth": (c_i32, [c_vp, c_i64, c_i64, c_i32, c_vp, c_sz, c_vp, c_i32_p]),
+    "nmf_sym_eigvals": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_vp, c_i32_p]),
     "nmf_mlp_n_params": (c_i64, [c_i32, c_i32, c_i32]),
     "nmf_mlp_workspace_bytes": (c_sz, [c_i32, c_i32, c_i32, c_i32]),
     "nmf_mlp_create": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_vp, c_vp, c_sz, c_vp, ctypes.POINTER(c_vp)]),
@@ -219,6 +221,12 @@ class NMF:
         self._c(load().nmf_proxy_residual(self.h, ctypes.byref(e)))
         return e.value
 
+    def sketch_spectrum(self):
+        """Singular values of X-hat = Q_L^T X, descending (see nmf_sketch_spectrum)."""
+        sig = (ctypes.c_double * self.kp)()
+        self._c(load().nmf_sketch_spectrum(self.h, sig))
+        return torch.tensor(sig[:], dtype=torch.float64)
+
     def fit(self, X, max_iters, eps=0.0, check_every=10):
         it = c_i32()
         e = ctypes.c_double()
@@ -357,6 +365,19 @@ def orth(Y, stream=None):
     sh = c_i32()
     _check(lib.nmf_orth(_ptr(Y), Y.stride(0), rows, k, base, nb, _stream(stream), ctypes.byref(sh)))
     return sh.value
+
+
+def sym_eigvals(A, stream=None):
+    """Eigenvalues (descending) of the symmetric FP64 device matrix A (k x k, lower
+    triangle read); returns (device tensor of k values, Jacobi sweeps)."""
+    lib = load()
+    k = A.shape[0]
+    if A.dtype != torch.float64 or A.dim() != 2 or A.shape[1] != k or A.stride(1) != 1:
+        raise ValueError("A must be a row-major square float64 tensor")
+    w = torch.empty(k, dtype=torch.float64, device=A.device)
+    sw = c_i32()
+    _check(lib.nmf_sym_eigvals(_ptr(A), A.stride(0), k, _ptr(w), _stream(stream), ctypes.byref(sw)))
+    return w, sw.value
 
 
 def quantize_x(X, prec, stream=None):
