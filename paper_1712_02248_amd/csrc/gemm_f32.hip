@@ -228,7 +228,10 @@ hipError_t run(const float* A, int64_t lda, int a_trans, const float* B, int64_t
 }
 
 int bn_for(int64_t N) { return N <= 32 ? 32 : N <= 64 ? 64 : N <= 128 ? 128 : 256; }
-int bm_for(int bn) { return bn <= 128 ? 128 : 64; }
+// N <= 32 (the update's r-wide products): 256-row tiles, two 32x32 blocks per
+// wave, so each thin-operand fragment read from LDS feeds two MFMAs; measured
+// 10-20 % faster than 128-row tiles at 65536 x 4096 x 32
+int bm_for(int bn) { return bn <= 32 ? 256 : bn <= 128 ? 128 : 64; }
 
 }  // namespace
 
@@ -240,7 +243,8 @@ int gemm_f32_pick_splits(int64_t M, int64_t N, int64_t K, int a_trans) {
   const int bn = bn_for(N), bm = bm_for(bn);
   const int64_t tiles = ceil_div(M, bm) * ceil_div(N, bn);
   if (tiles <= 0) return 1;
-  int64_t s = ceil_div(1024, tiles);
+  // about 1024 workgroups, 512 for the 256-row tiles (measured best for each)
+  int64_t s = ceil_div(bm >= 256 ? 512 : 1024, tiles);
   const int64_t kmax = K / 256;  // keep at least 8 BK steps per split
   if (s > kmax) s = kmax;
   if (s < 1) s = 1;
@@ -264,7 +268,7 @@ hipError_t launch_gemm_f32(const float* A, int64_t lda, int a_trans, const float
   const int64_t ldo = splits > 1 ? N : ldc;
   hipError_t e;
   switch (bn_for(N)) {
-    case 32: e = run<128, 32, 4, 1>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;
+    case 32: e = run<256, 32, 4, 1>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;
     case 64: e = run<128, 64, 2, 2>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;
     case 128: e = run<128, 128, 2, 2>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;
     default: e = run<64, 256, 1, 4>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;

@@ -41,6 +41,8 @@ GEMM_CASES = [
     (1000, 20, 1004, False), (1000, 20, 1004, True), (4096, 64, 4096, False), (4096, 64, 8192, True),
     (300, 128, 512, False), (512, 256, 1000, True), (130, 100, 36, False), (64, 32, 65536, True),
     (257, 256, 260, False), (4, 4, 4, True), (0, 8, 16, False),
+    # N <= 32 on 256-row tiles: several tiles with a ragged tail, split-K
+    (1300, 32, 5000, False), (780, 20, 70000, True), (4100, 28, 4096, True),
 ]
 
 
