@@ -51,14 +51,16 @@ __global__ __launch_bounds__(256) void sym_eig_jacobi_kernel(const double* __res
   __shared__ double red[4];
   const int t = threadIdx.x;
   const int ld = k + 1;
+  // whole-matrix passes: eight rows at a time, 32 columns per row (no division)
+  const int ri = t >> 5, cj = t & 31;
   double fro = 0.0, off = 0.0;
-  for (int e = t; e < k * k; e += 256) {
-    const int i = e / k, j = e % k;
-    const double v = i >= j ? A[(int64_t)i * lda + j] : A[(int64_t)j * lda + i];
-    S[i * ld + j] = v;
-    fro += v * v;
-    if (i != j) off += v * v;
-  }
+  for (int i = ri; i < k; i += 8)
+    for (int j = cj; j < k; j += 32) {
+      const double v = i >= j ? A[(int64_t)i * lda + j] : A[(int64_t)j * lda + i];
+      S[i * ld + j] = v;
+      fro += v * v;
+      if (i != j) off += v * v;
+    }
   fro = block_sum_d(fro, red);
   off = block_sum_d(off, red);
   if (!isfinite(fro)) {
@@ -101,35 +103,32 @@ __global__ __launch_bounds__(256) void sym_eig_jacobi_kernel(const double* __res
         sn[t] = s;
       }
       __syncthreads();
+      // four threads per pair (t / 4), each taking every fourth row or column
+      const int i = t >> 2, j0 = t & 3;
+      const int p = i < P ? pp[i] : -1, q = i < P ? qq[i] : -1;
+      const double c = i < P ? cs[i] : 1.0, s = i < P ? sn[i] : 0.0;
       // rows p, q of J^T A
-      for (int e = t; e < P * k; e += 256) {
-        const int i = e / k, j = e % k;
-        const int p = pp[i], q = qq[i];
-        if (p < 0) continue;
-        const double c = cs[i], s = sn[i];
-        const double a = S[p * ld + j], b = S[q * ld + j];
-        S[p * ld + j] = c * a - s * b;
-        S[q * ld + j] = s * a + c * b;
-      }
+      if (p >= 0)
+        for (int j = j0; j < k; j += 4) {
+          const double a = S[p * ld + j], b = S[q * ld + j];
+          S[p * ld + j] = c * a - s * b;
+          S[q * ld + j] = s * a + c * b;
+        }
       __syncthreads();
       // columns p, q of (J^T A) J
-      for (int e = t; e < P * k; e += 256) {
-        const int i = e / k, j = e % k;
-        const int p = pp[i], q = qq[i];
-        if (p < 0) continue;
-        const double c = cs[i], s = sn[i];
-        const double a = S[j * ld + p], b = S[j * ld + q];
-        S[j * ld + p] = c * a - s * b;
-        S[j * ld + q] = s * a + c * b;
-      }
+      if (p >= 0)
+        for (int j = j0; j < k; j += 4) {
+          const double a = S[j * ld + p], b = S[j * ld + q];
+          S[j * ld + p] = c * a - s * b;
+          S[j * ld + q] = s * a + c * b;
+        }
       __syncthreads();
     }
     ++sweeps;
     double o = 0.0;
-    for (int e = t; e < k * k; e += 256) {
-      const int i = e / k, j = e % k;
-      if (i != j) o += S[i * ld + j] * S[i * ld + j];
-    }
+    for (int i = ri; i < k; i += 8)
+      for (int j = cj; j < k; j += 32)
+        if (i != j) o += S[i * ld + j] * S[i * ld + j];
     off = block_sum_d(o, red);
   }
   // descending order by rank (equal values keep index order)
