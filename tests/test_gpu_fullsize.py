@@ -85,3 +85,31 @@ def test_c2_full_size_low_precision_within_gate_of_oracle(lib, prec_name, refine
     e = ctx.residual(Xd)
     print(f"  e_gpu={e:.8e} e_oracle(FP64, exact X)={ref['e']:.8e} diff={abs(e - ref['e']):.2e}", flush=True)
     assert abs(e - ref["e"]) <= 1e-4
+
+
+def test_c2_full_size_uncompressed_fasthals_matches_oracle(lib):
+    """Textbook FastHALS on X itself (Sec 2.2) at full size, in the launch
+    configuration the benchmark times: factors after 1 and 2 iterations from the
+    cold start against the oracle's, elementwise (the tolerance of the small
+    cases), and the exact residual within the 1e-4 gate."""
+    from oracle import nmf as onmf
+    print("c2 full size uncompressed: generating X", flush=True)
+    name = "c2"
+    c = datagen.CONFIGS[name]
+    m, n, r, kp, q = c["m"], c["n"], c["r"], c["kp"], c["q"]
+    seed = datagen.cfg_seed(name)
+    X = datagen.make_x(name)
+    W0, H0 = datagen.init_factors(X.mean(), m, n, r, seed)
+    Xd = torch.from_numpy(X).cuda()
+    ctx = lib.NMF(m, n, r, kp, q, seed=seed)
+    ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
+    W, Ht = W0.astype(np.float64), H0.astype(np.float64)
+    for it in (1, 2):
+        ctx.fasthals_step(Xd, 1)
+        W, Ht = onmf.fasthals_iteration(X, W, Ht)
+        Wg, Hg = (t.cpu().numpy().astype(np.float64) for t in ctx.factors())
+        tol = 2e-3 * it
+        print(f"  it={it} max|dW|={np.abs(Wg - W).max():.2e} max|dH|={np.abs(Hg - Ht).max():.2e}", flush=True)
+        assert np.abs(Wg - W).max() <= tol * np.abs(W).max(), it
+        assert np.abs(Hg - Ht).max() <= tol * np.abs(Ht).max(), it
+        assert abs(ctx.residual(Xd) - onmf.rel_error(X, W, Ht)) <= 1e-4, it
