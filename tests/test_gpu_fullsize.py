@@ -113,3 +113,31 @@ def test_c2_full_size_uncompressed_fasthals_matches_oracle(lib):
         assert np.abs(Wg - W).max() <= tol * np.abs(W).max(), it
         assert np.abs(Hg - Ht).max() <= tol * np.abs(Ht).max(), it
         assert abs(ctx.residual(Xd) - onmf.rel_error(X, W, Ht)) <= 1e-4, it
+
+
+def test_c2_full_size_sketch_spectrum_matches_oracle(lib):
+    """Singular values of X-hat = Q_L^T X at full size from the device-drawn
+    test matrices, against the oracle's compression with the same Philox draws:
+    within 1e-5 of sigma_1, descending, and the squares summing to at most
+    ||X||_F^2 (X-hat is a projection of X)."""
+    from oracle import nmf as onmf
+    from oracle import philox as ophilox
+    from oracle import spectrum as ospec
+    print("c2 full size spectrum: generating X", flush=True)
+    name = "c2"
+    c = datagen.CONFIGS[name]
+    m, n, r, kp, q = c["m"], c["n"], c["r"], c["kp"], c["q"]
+    seed = datagen.cfg_seed(name)
+    X = datagen.make_x(name)
+    Xd = torch.from_numpy(X).cuda()
+    ctx = lib.NMF(m, n, r, kp, q, seed=seed)
+    ctx.compress(Xd)
+    sig = ctx.sketch_spectrum().numpy()
+    OL = ophilox.normal(n, kp, 3, seed).astype(np.float32)
+    OR = ophilox.normal(m, kp, 4, seed).astype(np.float32)
+    QL = onmf.compress(X, OL, OR, q)[0]
+    ref = ospec.sketch_singular_values(X, QL)
+    print(f"  sigma_1 {sig[0]:.6e} (oracle {ref[0]:.6e}), max diff {np.abs(sig - ref).max():.2e}", flush=True)
+    assert np.abs(sig - ref).max() <= 1e-5 * ref[0]
+    assert np.all(np.diff(sig) <= 0)
+    assert (sig ** 2).sum() <= (X.astype(np.float64) ** 2).sum() * (1 + 1e-6)
