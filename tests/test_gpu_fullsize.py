@@ -141,3 +141,37 @@ def test_c2_full_size_sketch_spectrum_matches_oracle(lib):
     assert np.abs(sig - ref).max() <= 1e-5 * ref[0]
     assert np.all(np.diff(sig) <= 0)
     assert (sig ** 2).sum() <= (X.astype(np.float64) ** 2).sum() * (1 + 1e-6)
+
+
+def test_c3_full_size_bf16_within_gate_of_oracle(lib):
+    """Document-count data at full size (100000 x 20000 Poisson counts from 64
+    planted topics, k' = 128, q = 2): BF16 range-finder products with FP32
+    accumulation, FP64 CholeskyQR2, FP32 sketches, the device-drawn test
+    matrices; the relative error at the oracle's stored checkpoints up to the
+    configured 150 iterations within the 1e-4 gate of the FP64 oracle's."""
+    name = "c3"
+    ref = json.load(open(GOLDEN))[name]
+    c = datagen.CONFIGS[name]
+    m, n, r, kp, q, iters = c["m"], c["n"], c["r"], c["kp"], c["q"], c["iters"]
+    seed = datagen.cfg_seed(name)
+    print("c3 full size: generating X (about a minute on the host)", flush=True)
+    X = datagen.make_x(name)
+    W0, H0 = datagen.init_factors(X.mean(), m, n, r, seed)
+    Xd = torch.from_numpy(X).cuda()
+    del X
+    ctx = lib.NMF(m, n, r, kp, q, seed=seed, prec=lib.NMF_BF16)
+    ctx.compress(Xd)
+    ctx.init(torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda())
+    assert ctx.sync() == 0
+    done = checked = 0
+    for it in sorted(int(k) for k in ref["curve"]):
+        if it > iters:
+            continue
+        ctx.step(it - done)
+        done = it
+        e = ctx.residual(Xd)
+        e_ref = ref["curve"][str(it)]
+        print(f"  it={it:4d} e_gpu={e:.8e} e_oracle={e_ref:.8e} diff={abs(e - e_ref):.2e}", flush=True)
+        assert abs(e - e_ref) <= 1e-4, it
+        checked += 1
+    assert checked >= 5

@@ -38,7 +38,8 @@ def rel_norm(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-@pytest.mark.parametrize("k,hdim,r,B", [(20, 96, 10, 300), (64, 512, 32, 1024), (5, 7, 3, 1)])
+# (128, 512, 64): the network of the document-count workload (k' = 128, r = 64)
+@pytest.mark.parametrize("k,hdim,r,B", [(20, 96, 10, 300), (64, 512, 32, 1024), (128, 512, 64, 1024), (5, 7, 3, 1)])
 def test_loss_and_gradients_match_oracle(lib, k, hdim, r, B):
     print(f"mlp loss/grad k={k} h={hdim} r={r} B={B}", flush=True)
     p0 = datagen.mlp_he_init(k, hdim, r, seed=11)
@@ -141,7 +142,8 @@ def test_training_natural_order_and_convergence(lib):
     assert hist[-1] < 0.02 * hist[0]
 
 
-@pytest.mark.parametrize("k,r,rows,sweeps", [(20, 10, 1000, 50), (64, 32, 3000, 200), (7, 1, 5, 3)])
+@pytest.mark.parametrize("k,r,rows,sweeps", [(20, 10, 1000, 50), (64, 32, 3000, 200), (128, 64, 2000, 50),
+                                             (7, 1, 5, 3)])
 def test_nnls_rows_match_oracle(lib, k, r, rows, sweeps):
     print(f"nnls rows k={k} r={r} rows={rows}", flush=True)
     g = np.random.default_rng(41)
