@@ -134,3 +134,25 @@ def test_sweep_points_match_oracle(lib, r, q):
         ctx.fasthals_step(Xd, 50)
         Wu, Hu = onmf.fasthals(X, W0, H0, 50)
         assert abs(ctx.residual(Xd) - onmf.rel_error(X, Wu, Hu)) <= 1e-4
+
+
+def test_sym_eigvals_degenerate_inputs(lib):
+    """A zero matrix (no sweep), and off-diagonal entries so small that the
+    rotation's tau overflows the plain formula (its guarded branch)."""
+    print("sym_eigvals degenerate", flush=True)
+    w, sweeps = lib.sym_eigvals(torch.zeros(5, 5, dtype=torch.float64, device="cuda"))
+    assert sweeps == 0 and np.array_equal(w.cpu().numpy(), np.zeros(5))
+    # the (1, 3) entry keeps the sweeps running; the (0, 2) pair then has
+    # tau ~ 5e159, where t = 1 / (2 tau) replaces the formula that would overflow
+    A = np.diag([3.0, 1.0, 2.0, -1.0])
+    A[2, 0] = A[0, 2] = 1e-160
+    A[3, 1] = A[1, 3] = 0.5
+    w, sweeps = lib.sym_eigvals(torch.from_numpy(A).cuda())
+    got = w.cpu().numpy()
+    assert sweeps >= 1 and np.all(np.isfinite(got))
+    assert np.abs(got - ospec.sym_eigvals(A)).max() <= 1e-12 * np.linalg.norm(A)
+    # only a pair of tiny entries: below the stopping bound from the start
+    B = np.diag([3.0, 1.0, 2.0, -1.0])
+    B[3, 1] = B[1, 3] = 1e-300
+    w, sweeps = lib.sym_eigvals(torch.from_numpy(B).cuda())
+    assert sweeps == 0 and np.array_equal(w.cpu().numpy(), np.array([3.0, 2.0, 1.0, -1.0]))
