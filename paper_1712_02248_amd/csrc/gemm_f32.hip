@@ -228,10 +228,11 @@ hipError_t run(const float* A, int64_t lda, int a_trans, const float* B, int64_t
 }
 
 int bn_for(int64_t N) { return N <= 32 ? 32 : N <= 64 ? 64 : N <= 128 ? 128 : 256; }
-// N <= 32 (the update's r-wide products): 256-row tiles, two 32x32 blocks per
-// wave, so each thin-operand fragment read from LDS feeds two MFMAs; measured
-// 10-20 % faster than 128-row tiles at 65536 x 4096 x 32
-int bm_for(int bn) { return bn <= 32 ? 256 : bn <= 128 ? 128 : 64; }
+// N <= 64: 256-row tiles, every wave owning 64 rows (two 32-row blocks), so each
+// thin-operand fragment read from LDS feeds two MFMAs per column block.  Measured
+// against 128-row tiles at 65536 x 4096: 10-20 % faster at N = 32 (the update's
+// r-wide products) and 12-19 % at N = 64 (the compression products).
+int bm_for(int bn) { return bn <= 64 ? 256 : bn <= 128 ? 128 : 64; }
 
 }  // namespace
 
@@ -269,7 +270,7 @@ hipError_t launch_gemm_f32(const float* A, int64_t lda, int a_trans, const float
   hipError_t e;
   switch (bn_for(N)) {
     case 32: e = run<256, 32, 4, 1>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;
-    case 64: e = run<128, 64, 2, 2>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;
+    case 64: e = run<256, 64, 4, 1>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;
     case 128: e = run<128, 128, 2, 2>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;
     default: e = run<64, 256, 1, 4>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;
   }
