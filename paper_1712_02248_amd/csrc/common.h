@@ -34,7 +34,7 @@ hipError_t launch_philox_uniform(float* out, int64_t rows, int64_t cols, int64_t
 //   floats) and are summed in fixed order by a second kernel.
 size_t gemm_f32_part_floats(int64_t M, int64_t N, int splits);
 // sq (optional, A not transposed): FP64 sum of squares of A per workgroup, gemm_f32_sq_parts() values
-int gemm_f32_sq_parts(int64_t M, int64_t N, int splits);
+int gemm_f32_sq_parts(int64_t M, int64_t N, int64_t K, int splits);
 hipError_t launch_gemm_f32(const float* A, int64_t lda, int a_trans, const float* B, int64_t ldb,
                            float* C, int64_t ldc, int64_t M, int64_t N, int64_t K,
                            int splits, float* part, hipStream_t st, double* sq = nullptr);

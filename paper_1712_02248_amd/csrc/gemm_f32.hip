@@ -228,20 +228,31 @@ hipError_t run(const float* A, int64_t lda, int a_trans, const float* B, int64_t
 }
 
 int bn_for(int64_t N) { return N <= 32 ? 32 : N <= 64 ? 64 : N <= 128 ? 128 : 256; }
-// N <= 64: 256-row tiles, every wave owning 64 rows (two 32-row blocks), so each
-// thin-operand fragment read from LDS feeds two MFMAs per column block.  Measured
-// against 128-row tiles at 65536 x 4096: 10-20 % faster at N = 32 (the update's
-// r-wide products) and 12-19 % at N = 64 (the compression products).
-int bm_for(int bn) { return bn <= 64 ? 256 : bn <= 128 ? 128 : 64; }
+// N <= 64 on large products: 256-row tiles, every wave owning 64 rows (two 32-row
+// blocks), so each thin-operand fragment read from LDS feeds two MFMAs per column
+// block.  Measured against 128-row tiles at 65536 x 4096: 10-20 % faster at N = 32
+// (the update's r-wide products) and 12-19 % at N = 64 (the compression products).
+// When they would leave fewer than 256 workgroups even with the deepest split-K
+// (400 x 4096: 16), 128-row tiles are kept; there they were 35-40 % faster.
+int bm_pick(int64_t M, int64_t N, int64_t K) {
+  const int bn = bn_for(N);
+  if (bn > 64) return bn <= 128 ? 128 : 64;
+  int64_t kmax = K / 256;
+  if (kmax > 64) kmax = 64;
+  if (kmax < 1) kmax = 1;
+  return ceil_div(M, 256) * kmax >= 256 ? 256 : 128;
+}
 
 }  // namespace
 
 // Number of sum-of-squares partials launch_gemm_f32 writes for these sizes.
-int gemm_f32_sq_parts(int64_t M, int64_t N, int splits) { return (int)(ceil_div(M, bm_for(bn_for(N))) * splits); }
+int gemm_f32_sq_parts(int64_t M, int64_t N, int64_t K, int splits) {
+  return (int)(ceil_div(M, bm_pick(M, N, K)) * splits);
+}
 
 int gemm_f32_pick_splits(int64_t M, int64_t N, int64_t K, int a_trans) {
   (void)a_trans;
-  const int bn = bn_for(N), bm = bm_for(bn);
+  const int bn = bn_for(N), bm = bm_pick(M, N, K);
   const int64_t tiles = ceil_div(M, bm) * ceil_div(N, bn);
   if (tiles <= 0) return 1;
   // about 1024 workgroups, 512 for the 256-row tiles (measured best for each)
@@ -268,9 +279,16 @@ hipError_t launch_gemm_f32(const float* A, int64_t lda, int a_trans, const float
   float* out = splits > 1 ? part : C;
   const int64_t ldo = splits > 1 ? N : ldc;
   hipError_t e;
+  const bool tall = bm_pick(M, N, K) == 256;
   switch (bn_for(N)) {
-    case 32: e = run<256, 32, 4, 1>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;
-    case 64: e = run<256, 64, 4, 1>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;
+    case 32:
+      e = tall ? run<256, 32, 4, 1>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st)
+               : run<128, 32, 4, 1>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st);
+      break;
+    case 64:
+      e = tall ? run<256, 64, 4, 1>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st)
+               : run<128, 64, 2, 2>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st);
+      break;
     case 128: e = run<128, 128, 2, 2>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;
     default: e = run<64, 256, 1, 4>(A, lda, a_trans, B, ldb, out, ldo, M, N, K, splits, sq, st); break;
   }

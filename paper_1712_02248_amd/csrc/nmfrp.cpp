@@ -130,7 +130,7 @@ Layout make_layout(const nmf_params* p) {
   L.proxy_out = pl.take(3 * d);            // proxy sums, then ||X||^2 from compression
   {
     const int64_t qp = quant_sq_parts(m, n, round_up(n, 128), round_up(m, 128));
-    const int64_t gp3 = gemm_f32_sq_parts(m, k, 64);
+    const int64_t gp3 = gemm_f32_sq_parts(m, k, n, 64);
     const int64_t gp4 = gemm_split_sq_parts(m, gemm_split_pick_splits(m, k, n));
     L.xsq_part = pl.take((size_t)std::max(qp, std::max(gp3, gp4)) * d);
   }
@@ -553,7 +553,7 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
       const int s = gemm_f32_pick_splits(m, k, n, 0);
       double* sqp = c->at<double>(L.xsq_part);
       hipError_t e = launch_gemm_f32(X, ldx, 0, QR, L.KP, Xc, L.KP, m, k, n, s, cr.gemm_part, cr.st, sqp);
-      return e ? e : launch_sum_partials_f64(sqp, gemm_f32_sq_parts(m, k, s), 1, c->at<double>(L.proxy_out) + 2,
+      return e ? e : launch_sum_partials_f64(sqp, gemm_f32_sq_parts(m, k, n, s), 1, c->at<double>(L.proxy_out) + 2,
                                             nullptr, cr.st);
     }, nullptr});
   }

@@ -43,8 +43,10 @@ GEMM_CASES = [
     (257, 256, 260, False), (4, 4, 4, True), (0, 8, 16, False),
     # N <= 32 on 256-row tiles: several tiles with a ragged tail, split-K
     (1300, 32, 5000, False), (780, 20, 70000, True), (4100, 28, 4096, True),
-    # 33 <= N <= 64 on 256-row tiles: ragged tails, split-K
+    # 33 <= N <= 64: ragged tails and split-K on 128-row tiles (too few workgroups
+    # for 256-row ones) and on 256-row tiles (the last two)
     (3000, 64, 2000, False), (1000, 60, 4100, True), (300, 36, 70000, True),
+    (4200, 48, 16384, False), (2100, 64, 20000, True),
 ]
 
 
