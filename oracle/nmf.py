@@ -340,16 +340,6 @@ def objective(X, W, Ht):
     return 0.5 * frob_sq_diff(X, W, Ht)[0]
 
 
-def compressed_objectives(W, Ht, Xh, Xc, QL, QR):
-    """J_R = 1/2||X-check - A B-check^T||^2 and J_L = 1/2||X-hat - A-hat B^T||^2
-    (the two objectives of Alg 3 / Alg 4)."""
-    Hc = QR.T @ Ht
-    Wh = QL.T @ W
-    JR = 0.5 * np.sum((Xc - W @ Hc.T) ** 2)
-    JL = 0.5 * np.sum((Xh.T - Wh @ Ht.T) ** 2)
-    return JR, JL
-
-
 def proxy_rel_error(normX2, Xh, Wh, Ht):
     """Sketch-only estimate of e: ||X||^2 - ||X-hat||^2 + ||X-hat - A-hat B^T||^2,
     exact when the columns of W lie in range(Q_L)."""
