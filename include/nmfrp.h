@@ -237,6 +237,21 @@ nmf_status nmf_gemm(const float* A, int64_t lda, int32_t a_trans, const float* B
                     float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, void* workspace,
                     size_t ws_bytes, void* hip_stream);
 
+/* nmf_gemm for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product, kernels and split-K choice, with the split-K partials in a static
+ * per-GPU device array of NMF_NOALLOC_SCRATCH_BYTES instead of a workspace.  The
+ * call allocates nothing (no hipMalloc, hipFree or allocating library routine);
+ * the caller passes A, B and C as for nmf_gemm.  Products whose partials need
+ * more than the array (splits x M x N floats, see nmf_gemm_workspace_bytes)
+ * return NMF_EINVAL without launching.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams or threads) race.  The
+ * array is looked up on the first call on each device and held until the
+ * process ends.  Asynchronous on hip_stream. */
+#define NMF_NOALLOC_SCRATCH_BYTES (64u << 20)
+nmf_status nmf_gemm_noalloc(const float* A, int64_t lda, int32_t a_trans, const float* B, int64_t ldb,
+                            float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, void* hip_stream);
+
 /* Low-precision copies of X for the range-finder products (extension): writes
  * Xq (m x ldq) and its transpose XqT (n x ldqt), zero padded; ldq >= n and
  * ldqt >= m, both multiples of 128.  prec = NMF_BF16: uint16 BF16 bit patterns,

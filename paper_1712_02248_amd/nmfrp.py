@@ -56,6 +56,7 @@ _SIGS = {
     "nmf_gemm_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64, c_i32]),
     "nmf_gemm": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_i64, c_vp, c_i64, c_i64, c_i64, c_i64, c_vp,
                          c_sz, c_vp]),
+    "nmf_gemm_noalloc": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_i64, c_vp, c_i64, c_i64, c_i64, c_i64, c_vp]),
     "nmf_quantize_x": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_i32, c_vp, c_i64, c_vp, c_i64, c_vp, c_vp]),
     "nmf_gemm_lowp_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64]),
     "nmf_gemm_lowp": (c_i32, [c_i32, c_vp, c_i64, c_vp, c_i64, c_i64, c_vp, c_i64, c_i64, c_i64, c_vp, c_i64,
@@ -332,6 +333,24 @@ def gemm(A, B, a_trans=False, out=None, stream=None):
     ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=A.device)
     _check(lib.nmf_gemm(_ptr(A), A.stride(0), int(a_trans), _ptr(B), B.stride(0), _ptr(out), out.stride(0),
                         M, N, K, _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def gemm_noalloc(A, B, a_trans=False, out=None, stream=None):
+    """gemm() through the allocation-free entry point (split-K partials in the
+    library's static per-GPU scratch; no workspace)."""
+    lib = load()
+    if a_trans:
+        K, M = A.shape
+    else:
+        M, K = A.shape
+    K2, N = B.shape
+    if K2 != K:
+        raise ValueError("shape mismatch")
+    if out is None:
+        out = torch.empty(M, N, dtype=torch.float32, device=A.device)
+    _check(lib.nmf_gemm_noalloc(_ptr(A), A.stride(0), int(a_trans), _ptr(B), B.stride(0), _ptr(out), out.stride(0),
+                                M, N, K, _stream(stream)))
     return out
 
 
