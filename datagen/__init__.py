@@ -10,7 +10,15 @@ Workloads (X is m x n, rows are datapoints):
                        (rank 32); X = max(0, W0 H0 + 0.01 N(0,1)).
   c3   100000 x 20000: topic-model counts, theta_i ~ Dir(0.1), Zipf(1.1) word
                        distributions per topic, X_iw ~ Poisson(200 (theta_i Phi)_w).
-  c5   262144 x 16384: the c2 family with rank 128.
+  c5   262144 x 16384: the c2 family with rank 128, its factors rounded to
+                       multiples of 2^-8 (W0 = Bernoulli(0.2) floor(256 U) / 256,
+                       H0 = floor(256 U) / 256), so that W0 H0 is exact in FP32
+                       in any summation order; the noise is N(0,1) from
+                       Philox4x32-10 (stream 2, key = the workload seed, element
+                       (i, j) at flat index i n + j), and
+                       X = max(0, fl32(W0 H0 + fl32(0.01 z))) in FP32.  Either
+                       side forms X from these numbers (the device in HBM, the
+                       oracle in host row panels).
   P1   400 x 4096:     stand-in for the paper's dense image data: the c2 family
                        with 40 parts, rescaled to [0, 1] and quantised to 256 levels.
   P2   5000 x 1000:    stand-in for the paper's sparse word counts: the c3 family
@@ -26,7 +34,8 @@ CONFIGS = {
     "c1": dict(idx=0, m=512, n=256, r=10, kp=20, q=2, iters=200, family="c1", r_true=10, prec="fp32"),
     "c2": dict(idx=1, m=65536, n=4096, r=32, kp=64, q=2, iters=500, family="parts", r_true=32, prec="fp32"),
     "c3": dict(idx=2, m=100000, n=20000, r=64, kp=128, q=2, iters=150, family="lda", r_true=64, prec="bf16"),
-    "c5": dict(idx=4, m=262144, n=16384, r=128, kp=256, q=1, iters=300, family="parts", r_true=128, prec="fp8"),
+    "c5": dict(idx=4, m=262144, n=16384, r=128, kp=256, q=1, iters=300, family="dyadic_parts", r_true=128,
+               prec="fp8"),
     "P1": dict(idx=10, m=400, n=4096, r=20, kp=25, q=4, iters=500, family="parts_q256", r_true=40, prec="fp32"),
     "P2": dict(idx=11, m=5000, n=1000, r=60, kp=72, q=9, iters=150, family="lda", r_true=20, prec="fp32"),
 }
@@ -69,6 +78,21 @@ def planted_parts(m, n, r, seed, noise=0.01, density=0.2, block=8192):
     return X, W0, H0
 
 
+def dyadic_parts_factors(m, n, r, seed, density=0.2):
+    """Factors of the dyadic parts family (c5): W0 = Bernoulli(density) U8 and
+    H0 = U8, U8 = floor(256 U[0,1)) / 256, as FP32 (exact).  Every product of
+    two entries is a multiple of 2^-16 below 1, so the r-term sums of W0 H0 are
+    exact in FP32 (24-bit significand) for r <= 128, in any order."""
+    g = rng(seed, S_W0)
+    W0 = (g.random((m, r)) < density) * np.floor(256.0 * g.random((m, r))) / 256.0
+    H0 = np.floor(256.0 * rng(seed, S_H0).random((r, n))) / 256.0
+    return W0.astype(np.float32), H0.astype(np.float32)
+
+
+DYADIC_NOISE = np.float32(0.01)   # noise scale of the dyadic parts family
+DYADIC_NOISE_STREAM = S_NOISE     # Philox stream of its noise
+
+
 def planted_parts_q256(m, n, r, seed):
     X, W0, H0 = planted_parts(m, n, r, seed)
     X = np.round(255.0 * X / X.max()) / 255.0
@@ -105,6 +129,9 @@ def make_x(name, m=None, n=None, r_true=None, seed=None):
         return planted_c1(m, n, r_true, seed)[0]
     if fam == "parts":
         return planted_parts(m, n, r_true, seed)[0]
+    if fam == "dyadic_parts":
+        raise ValueError("the dyadic parts family (c5) is formed in row panels by its consumer, "
+                         "from dyadic_parts_factors and Philox noise")
     if fam == "parts_q256":
         return planted_parts_q256(m, n, r_true, seed)[0]
     if fam == "lda":

@@ -76,25 +76,60 @@ def cholesky_qr2(Y, force_shift=False):
         return Q3, True
 
 
+class RowPanels:
+    """An FP32 data matrix too large to hold in FP64, used through its products:
+    X B is formed panel by panel as float64(X_p) B, and X^T B as the sum over
+    the panels, in ascending order, of float64(X_p)^T B_p.  The values are those
+    of the whole FP64 products up to the order of the FP64 sums."""
+
+    def __init__(self, X, panel=8192):
+        self.data = X
+        self.shape = X.shape
+        self.panel = panel
+
+    def matmul(self, B):
+        B = np.asarray(B, dtype=np.float64)
+        out = np.empty((self.shape[0], B.shape[1]))
+        for i in range(0, self.shape[0], self.panel):
+            out[i:i + self.panel] = np.asarray(self.data[i:i + self.panel], dtype=np.float64) @ B
+        return out
+
+    def tmatmul(self, B):
+        B = np.asarray(B, dtype=np.float64)
+        out = np.zeros((self.shape[1], B.shape[1]))
+        for i in range(0, self.shape[0], self.panel):
+            out += np.asarray(self.data[i:i + self.panel], dtype=np.float64).T @ B[i:i + self.panel]
+        return out
+
+
+def _subspace_iteration(fwd, adj, Omega, q, orth):
+    """Q = orth(fwd(Omega)), then q times Z = orth(adj(Q)), Q = orth(fwd(Z))."""
+    Q = orth(fwd(np.asarray(Omega, dtype=np.float64)))
+    for _ in range(q):
+        Z = orth(adj(Q))
+        Q = orth(fwd(Z))
+    return Q
+
+
 def range_finder(X, Omega, q, orth=householder_q):
     """Basis Q of P(X) = (X X^T)^q X Omega (eq 3.5), as subspace iteration.
 
     X: a x b, Omega: b x k'.  Returns a x k' with orthonormal columns.
     """
     X = np.asarray(X, dtype=np.float64)
-    Q = orth(X @ np.asarray(Omega, dtype=np.float64))
-    for _ in range(q):
-        Z = orth(X.T @ Q)
-        Q = orth(X @ Z)
-    return Q
+    return _subspace_iteration(lambda B: X @ B, lambda B: X.T @ B, Omega, q, orth)
 
 
 def compress(X, Omega_L, Omega_R, q, orth=householder_q):
     """Two-sided compression of Sec 3.1 and the projected data of Sec 4.
 
     Q_L from P(X) with Omega_L (n x k'), Q_R from P(X^T) with Omega_R (m x k');
-    Xh = X^T Q_L (n x k'), Xc = X Q_R (m x k').
+    Xh = X^T Q_L (n x k'), Xc = X Q_R (m x k').  X may be a RowPanels.
     """
+    if isinstance(X, RowPanels):
+        QL = _subspace_iteration(X.matmul, X.tmatmul, Omega_L, q, orth)
+        QR = _subspace_iteration(X.tmatmul, X.matmul, Omega_R, q, orth)
+        return QL, QR, X.tmatmul(QL), X.matmul(QR)
     X = np.asarray(X, dtype=np.float64)
     QL = range_finder(X, Omega_L, q, orth)
     QR = range_finder(X.T, Omega_R, q, orth)
@@ -316,7 +351,7 @@ def column_nnls(Xh_rows, Wh, sweeps, Ht0=None):
 
 def frob_sq_diff(X, W, Ht, block=4096):
     """sum (X - W Ht^T)^2 and sum X^2, directly, in FP64, row blocks."""
-    X = np.asarray(X)
+    X = X.data if isinstance(X, RowPanels) else np.asarray(X)
     W = np.asarray(W, dtype=np.float64)
     Ht = np.asarray(Ht, dtype=np.float64)
     res = 0.0

@@ -48,10 +48,12 @@ def philox4x32_10(c0, c1, c2, c3, k0, k1):
     return c0, c1, c2, c3
 
 
-def _blocks(count, stream, seed):
-    """Raw Philox words for the first ``count`` flat elements, shape (nblocks, 4)."""
+def _blocks(count, stream, seed, start=0):
+    """Raw Philox words for the ``count`` flat elements from index ``start``
+    (a multiple of 4), shape (nblocks, 4)."""
+    assert start % 4 == 0
     nblk = (count + 3) // 4
-    blk = np.arange(nblk, dtype=np.uint64)
+    blk = np.arange(start // 4, start // 4 + nblk, dtype=np.uint64)
     c0 = (blk & MASK32).astype(np.uint32)
     c1 = (blk >> np.uint64(32)).astype(np.uint32)
     c2 = np.full(nblk, stream & 0xFFFFFFFF, dtype=np.uint32)
@@ -66,10 +68,12 @@ def raw_words(count, stream, seed):
     return _blocks(count, stream, seed).reshape(-1)[:count]
 
 
-def normal(rows, cols, stream, seed):
-    """N(0,1) matrix (rows x cols) in FP64 by Box-Muller on Philox words."""
+def normal(rows, cols, stream, seed, row0=0):
+    """N(0,1) matrix (rows x cols) in FP64 by Box-Muller on Philox words; with
+    row0, rows row0 .. row0 + rows - 1 of a matrix of `cols` columns (flat
+    indices from row0 * cols, which must be a multiple of 4)."""
     count = rows * cols
-    w = _blocks(count, stream, seed).astype(np.float64)
+    w = _blocks(count, stream, seed, row0 * cols).astype(np.float64)
     u = (w + 0.5) * 2.0 ** -32
     out = np.empty_like(u)
     for a, b in ((0, 1), (2, 3)):

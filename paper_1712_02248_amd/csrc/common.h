@@ -135,10 +135,17 @@ struct HalfStepArgs {
   float* part;          // nblk x (kp*r + r) workgroup partials
   double* acc_out;      // kp*r + r summed partials of this half-step
   float alpha, beta;    // sparsity / smoothness (0, 0 = plain rule)
+  float* gbuf;          // N x r scratch (wide-factor path, with a sweep)
+  float* aux;           // halfstep_big_aux_floats() scratch (wide-factor path)
 };
 int halfstep_blocks(int64_t N);
 size_t halfstep_part_floats(int64_t N, int kp, int r);
 hipError_t launch_halfstep(const HalfStepArgs& a, int do_sweep, hipStream_t st);
+// Wide factors (r <= 128, k' <= 256, beyond the fused kernel's r <= 64, k' <= 128):
+// prep, gradient product, row sweep and partial products as separate launches.
+bool halfstep_big(int kp, int r);
+size_t halfstep_big_aux_floats();
+hipError_t launch_halfstep_big(const HalfStepArgs& a, int do_sweep, hipStream_t st);
 // Uncompressed FastHALS (Sec 2.2): one sweep over the rows of F against P and G
 // (FP64, r x r); sq (optional) gets hals_rows_blocks(N) x r column sums of F^2.
 int hals_rows_blocks(int64_t N);

@@ -78,9 +78,11 @@ prep_bt_kernel(const float* __restrict__ B, int64_t ldb, int64_t K, int64_t N, u
   }
 }
 
-constexpr int SBM = 128, SBN = 64, SBK = 64, SROW = SBK + 8;   // u16 per LDS row
+constexpr int SBM = 128, SBK = 64, SROW = SBK + 8;   // u16 per LDS row
 
-template <bool AT>
+// SBN = 64 (N <= 64), 128 or 256 for wider thin operands (k' up to 256: one
+// pass over X per product instead of one per 64 columns).
+template <bool AT, int SBN>
 __global__ void __launch_bounds__(256)
 gemm_split_kernel(const float* __restrict__ X, int64_t ldx, const uint16_t* __restrict__ BtH,
                   const uint16_t* __restrict__ BtL, int64_t ldbt, float* __restrict__ C, int64_t ldc,
@@ -315,20 +317,37 @@ hipError_t launch_gemm_split(const float* X, int64_t ldx, int at, const uint16_t
                              float* part, hipStream_t st, double* sq) {
   if (M == 0 || N == 0) return hipSuccess;
   if (ldx % 4 || ldbt % 64 || ldbt < round_up(K, 64) || splits < 1) return hipErrorInvalidValue;
+  const int sbn = N <= 64 ? 64 : N <= 128 ? 128 : 256;
   // 32-bit in-tile offsets: SBM rows of X (at = 0) or SBK rows (at = 1), and SBN rows of Bt
-  if ((int64_t)SBM * ldx >= (1ll << 30) || (int64_t)SBN * ldbt >= (1ll << 30)) return hipErrorInvalidValue;
+  if ((int64_t)SBM * ldx >= (1ll << 30) || (int64_t)sbn * ldbt >= (1ll << 30)) return hipErrorInvalidValue;
   float* out = splits > 1 ? part : C;
   const int64_t ldo = splits > 1 ? N : ldc;
   const int64_t kchunk = round_up(ceil_div(K, splits), 64);
-  dim3 grid((unsigned)ceil_div(M, 128), (unsigned)ceil_div(N, 64), (unsigned)splits);
+  dim3 grid((unsigned)ceil_div(M, 128), (unsigned)ceil_div(N, sbn), (unsigned)splits);
   // thin operand per split: N x kchunk values of hi and lo (4 bytes per value)
   const int rx = rot_per_xcd(N, kchunk, splits, 4);
-  if (at)
-    hipLaunchKernelGGL(gemm_split_kernel<true>, grid, dim3(256), 0, st, X, ldx, BtH, BtL, ldbt, out, ldo, M, N,
-                       K, kchunk, rx, nullptr);
-  else
-    hipLaunchKernelGGL(gemm_split_kernel<false>, grid, dim3(256), 0, st, X, ldx, BtH, BtL, ldbt, out, ldo, M, N,
-                       K, kchunk, rx, sq);
+  if (sbn == 64) {
+    if (at)
+      hipLaunchKernelGGL((gemm_split_kernel<true, 64>), grid, dim3(256), 0, st, X, ldx, BtH, BtL, ldbt, out, ldo,
+                         M, N, K, kchunk, rx, nullptr);
+    else
+      hipLaunchKernelGGL((gemm_split_kernel<false, 64>), grid, dim3(256), 0, st, X, ldx, BtH, BtL, ldbt, out, ldo,
+                         M, N, K, kchunk, rx, sq);
+  } else if (sbn == 128) {
+    if (at)
+      hipLaunchKernelGGL((gemm_split_kernel<true, 128>), grid, dim3(256), 0, st, X, ldx, BtH, BtL, ldbt, out,
+                         ldo, M, N, K, kchunk, rx, nullptr);
+    else
+      hipLaunchKernelGGL((gemm_split_kernel<false, 128>), grid, dim3(256), 0, st, X, ldx, BtH, BtL, ldbt, out,
+                         ldo, M, N, K, kchunk, rx, sq);
+  } else {
+    if (at)
+      hipLaunchKernelGGL((gemm_split_kernel<true, 256>), grid, dim3(256), 0, st, X, ldx, BtH, BtL, ldbt, out,
+                         ldo, M, N, K, kchunk, rx, nullptr);
+    else
+      hipLaunchKernelGGL((gemm_split_kernel<false, 256>), grid, dim3(256), 0, st, X, ldx, BtH, BtL, ldbt, out,
+                         ldo, M, N, K, kchunk, rx, sq);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || splits == 1) return e;
   return launch_splitk_reduce_lp(part, splits, C, ldc, M, N, st);

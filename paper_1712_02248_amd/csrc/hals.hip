@@ -541,6 +541,7 @@ size_t halfstep_part_floats(int64_t N, int kp, int r) {
 hipError_t launch_halfstep(const HalfStepArgs& a, int do_sweep, hipStream_t st) {
   if (a.N == 0) return hipSuccess;
   if (a.kp % 4 || a.lds % 4 || a.ldq % 4) return hipErrorInvalidValue;
+  if (halfstep_big(a.kp, a.r)) return launch_halfstep_big(a, do_sweep, st);
   if (a.kp <= 32) {
     if (a.r <= 16) return run<16, 32>(a, do_sweep, st);
     if (a.r <= 32) return run<32, 32>(a, do_sweep, st);
@@ -589,6 +590,8 @@ hipError_t launch_hals_rows(const float* P, int64_t ldp, const double* G, int64_
     hipLaunchKernelGGL(hals_rows_kernel<32>, grid, dim3(256), 0, st, P, ldp, G, N, r, F, ldf, sq);
   else if (r <= 64)
     hipLaunchKernelGGL(hals_rows_kernel<64>, grid, dim3(256), 0, st, P, ldp, G, N, r, F, ldf, sq);
+  else if (r <= 128)
+    hipLaunchKernelGGL(hals_rows_kernel<128>, grid, dim3(256), 0, st, P, ldp, G, N, r, F, ldf, sq);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

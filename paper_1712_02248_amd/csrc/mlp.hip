@@ -284,6 +284,125 @@ nnls_rows_kernel(const float* __restrict__ Xr, int64_t ldx, int n, int k, const 
   }
 }
 
+// The same column NNLS for wide factors (64 < r <= 128, k <= 256), where Wh and
+// G no longer fit in LDS together.  G = Wh^T Wh is formed by each workgroup on
+// FP64 MFMA from Wh in global memory (upper 16 x 16 blocks, mirrored) and staged
+// permuted; p = Wh^T x goes through LDS in 64-row chunks of Wh.  Components are
+// interleaved over the quad (lane q owns components 4 u + q), and the gradient
+// g = p - G h is formed once from the starting rows, then kept exact by
+// g -= G[:, j] d after every change d of component j, over all sweeps.
+__global__ void __launch_bounds__(256)
+nnls_rows_wide_kernel(const float* __restrict__ Xr, int64_t ldx, int n, int k, const float* __restrict__ Wh, int r,
+                      int sweeps, int warm, float* __restrict__ H, int64_t ldh) {
+  constexpr int RM = 128, RQ = RM / 4, CH = 64;
+  __shared__ __attribute__((aligned(16))) float Gq[RM * RM];    // Gq[c][q][u] = G[c][4 u + q]
+  __shared__ __attribute__((aligned(16))) float Wq[CH * RM];    // Wq[c][q][u] = Wh[c0 + c][4 u + q]
+  __shared__ float rd[RM];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, g4 = lane >> 4;
+  // G on FP64 MFMA: blocks (ti, tj), ti <= tj, dealt over the four waves
+  for (int t = wave; t < 36; t += 4) {
+    int ti = 0, rem = t;
+    while (rem >= 8 - ti) { rem -= 8 - ti; ++ti; }
+    const int tj = ti + rem;
+    f64x4 d = {0.0, 0.0, 0.0, 0.0};
+    for (int c0 = 0; c0 < k; c0 += 4) {
+      const int c = c0 + g4;
+      const int ja = 16 * ti + l16, jb = 16 * tj + l16;
+      const double a = (c < k && ja < r) ? (double)Wh[(int64_t)c * r + ja] : 0.0;
+      const double b = (c < k && jb < r) ? (double)Wh[(int64_t)c * r + jb] : 0.0;
+      d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {   // D[i][j] in lane j + 16 (i % 4), register i / 4
+      const int i = 16 * ti + 4 * x + g4, j = 16 * tj + l16;
+      const float v = (float)d[x];
+      Gq[i * RM + (j & 3) * RQ + (j >> 2)] = v;
+      Gq[j * RM + (i & 3) * RQ + (i >> 2)] = v;
+      if (i == j) rd[i] = (i < r && d[x] > 0.0) ? (float)(1.0 / d[x]) : 0.f;
+    }
+  }
+  const int q = tid & 3;
+  const int row = blockIdx.x * 64 + (tid >> 2);
+  const bool valid = row < n;
+  float f[RQ], g[RQ];
+#pragma unroll
+  for (int u = 0; u < RQ; ++u) {
+    const int c = 4 * u + q;
+    f[u] = (warm && valid && c < r) ? H[(int64_t)row * ldh + c] : 0.f;
+    g[u] = 0.f;
+  }
+  // p = Wh^T x (into g)
+  for (int c0 = 0; c0 < k; c0 += CH) {
+    __syncthreads();
+    for (int e = tid; e < CH * RM; e += 256) {
+      const int c = e / RM, j = e % RM;
+      Wq[c * RM + (j & 3) * RQ + (j >> 2)] = (c0 + c < k && j < r) ? Wh[(int64_t)(c0 + c) * r + j] : 0.f;
+    }
+    __syncthreads();
+    const int cn = k - c0 < CH ? k - c0 : CH;
+    for (int c = 0; c < cn; ++c) {
+      const float x = valid ? Xr[(int64_t)row * ldx + c0 + c] : 0.f;
+      const float* w = Wq + c * RM + q * RQ;
+#pragma unroll
+      for (int u = 0; u < RQ; u += 4) {
+        const f32x4 wv = *(const f32x4*)(w + u);
+        g[u] = fmaf(x, wv[0], g[u]);
+        g[u + 1] = fmaf(x, wv[1], g[u + 1]);
+        g[u + 2] = fmaf(x, wv[2], g[u + 2]);
+        g[u + 3] = fmaf(x, wv[3], g[u + 3]);
+      }
+    }
+  }
+  __syncthreads();
+  // g = p - G h with h of every component from its lane (G symmetric: G[4u+q][col] = Gq[col][q][u])
+  if (warm) {
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+      for (int v = 0; v < RQ; ++v) {
+        const float hv = quad_bcast_f(f[v], qq);
+        const float* gr = Gq + (4 * v + qq) * RM + q * RQ;
+#pragma unroll
+        for (int u = 0; u < RQ; u += 4) {
+          const f32x4 gv = *(const f32x4*)(gr + u);
+          g[u] = fmaf(-gv[0], hv, g[u]);
+          g[u + 1] = fmaf(-gv[1], hv, g[u + 1]);
+          g[u + 2] = fmaf(-gv[2], hv, g[u + 2]);
+          g[u + 3] = fmaf(-gv[3], hv, g[u + 3]);
+        }
+      }
+  }
+  for (int it = 0; it < sweeps; ++it) {
+#pragma unroll
+    for (int j = 0; j < RM; ++j) {
+      const float rdj = rd[j];
+      if (rdj > 0.f) {                  // uniform over the block
+        const int t = j >> 2;
+        const float fn = fmaxf(fmaf(g[t], rdj, f[t]), 0.f);
+        const float d = quad_bcast_f(fn - f[t], j & 3);   // the owner's change
+        if (q == (j & 3)) f[t] = fn;
+        const float* gr = Gq + j * RM + q * RQ;
+#pragma unroll
+        for (int u = 0; u < RQ; u += 4) {
+          const f32x4 gv = *(const f32x4*)(gr + u);
+          g[u] = fmaf(-gv[0], d, g[u]);
+          g[u + 1] = fmaf(-gv[1], d, g[u + 1]);
+          g[u + 2] = fmaf(-gv[2], d, g[u + 2]);
+          g[u + 3] = fmaf(-gv[3], d, g[u + 3]);
+        }
+      }
+    }
+  }
+  if (valid) {
+#pragma unroll
+    for (int u = 0; u < RQ; ++u) {
+      const int c = 4 * u + q;
+      if (c < r) H[(int64_t)row * ldh + c] = f[u];
+    }
+  }
+}
+
 NMF_DEV float softplusf(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
 NMF_DEV float sigmoidf(float z) {
   if (z >= 0.f) return 1.f / (1.f + expf(-z));
@@ -446,6 +565,7 @@ hipError_t launch_scale_rows(const float* X, int64_t ldx, const int* idx, int64_
 }
 
 size_t nnls_rows_lds_bytes(int k, int r) {
+  if (r > 64) return 0;   // the wide-factor kernel has static LDS only
   const int rmax = r <= 16 ? 16 : r <= 32 ? 32 : 64;
   return (size_t)(k * rmax + rmax * rmax + rmax) * sizeof(float);
 }
@@ -461,6 +581,8 @@ hipError_t launch_nnls_rows(const float* Xr, int64_t ldx, int n, int k, const fl
     hipLaunchKernelGGL(nnls_rows_kernel<32>, grid, dim3(256), lds, st, Xr, ldx, n, k, Wh, r, sweeps, warm, H, ldh);
   else if (r <= 64)
     hipLaunchKernelGGL(nnls_rows_kernel<64>, grid, dim3(256), lds, st, Xr, ldx, n, k, Wh, r, sweeps, warm, H, ldh);
+  else if (r <= 128 && k <= 256)
+    hipLaunchKernelGGL(nnls_rows_wide_kernel, grid, dim3(256), 0, st, Xr, ldx, n, k, Wh, r, sweeps, warm, H, ldh);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

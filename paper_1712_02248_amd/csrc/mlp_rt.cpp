@@ -292,7 +292,8 @@ nmf_status nmf_nnls_rows(const float* Xr, int64_t ldx, int64_t rows, int32_t k, 
                          int32_t sweeps, int32_t warm_start, float* Ht, int64_t ldh, void* hip_stream) {
   if (rows < 0 || k < 1 || r < 1 || sweeps < 0) return mfail(nullptr, NMF_EINVAL, "bad sizes");
   if (warm_start != 0 && warm_start != 1) return mfail(nullptr, NMF_EINVAL, "warm_start must be 0 or 1");
-  if (r > 64) return mfail(nullptr, NMF_EINVAL, "r > 64 is not supported by this build");
+  if (r > 128) return mfail(nullptr, NMF_EINVAL, "r > 128 is not supported by this build");
+  if (r > 64 && k > 256) return mfail(nullptr, NMF_EINVAL, "k > 256 is not supported with r > 64");
   if (k > 1024 || nnls_rows_lds_bytes(k, r) > 64 * 1024) return mfail(nullptr, NMF_EINVAL, "k too large for r");
   if (rows > INT32_MAX) return mfail(nullptr, NMF_EINVAL, "too many rows");
   if (rows == 0) return NMF_OK;

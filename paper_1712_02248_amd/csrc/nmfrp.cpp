@@ -35,6 +35,7 @@ struct Layout {
   size_t gemm_part, gram_part, G, R, qr_status;     // chain 0 (left range finder)
   size_t gemm_part2, gram_part2, G2, R2;             // chain 1 (right range finder); status at qr_status + 8
   size_t hs_part, acc_w, acc_h, counters, Hc, GH, Wh, GW, scale_w;
+  size_t hs_aux;                      // wide-factor half-steps: C, G, 1/G_jj, scales
   size_t res_part, res_out, flags, proxy_part, proxy_out, xsq_part;
   size_t alignM, whref;               // warm start: Q_train^T Q_L (k' x k'), Q_L^T W_ref (k' x r)
   int64_t ldq, ldqt;                 // low-precision copies of X: m x ldq and n x ldqt
@@ -49,8 +50,8 @@ bool valid_params(const nmf_params* p, std::string* why) {
   if (p->m <= 0 || p->n <= 0 || p->r <= 0) { *why = "m, n, r must be positive"; return false; }
   if (!(p->r < p->k_sketch)) { *why = "need r < k' (Sec 3.1)"; return false; }
   if (p->k_sketch > p->m || p->k_sketch > p->n) { *why = "need k' <= min(m, n)"; return false; }
-  if (p->k_sketch > 128) { *why = "k' > 128 is not supported by this build"; return false; }
-  if (p->r > 64) { *why = "r > 64 is not supported by this build"; return false; }
+  if (p->k_sketch > 256) { *why = "k' > 256 is not supported by this build"; return false; }
+  if (p->r > 128) { *why = "r > 128 is not supported by this build"; return false; }
   if (p->q < 0) { *why = "q must be >= 0"; return false; }
   if (p->prec < NMF_FP32 || p->prec > NMF_FP8_E4M3) { *why = "prec must be FP32, BF16 or FP8_E4M3"; return false; }
   if (p->refine_fp32 < 0 || p->refine_fp32 > 1) { *why = "refine_fp32 must be 0 or 1"; return false; }
@@ -121,6 +122,7 @@ Layout make_layout(const nmf_params* p) {
   L.Wh = pl.take(L.KP * r * f);
   L.GW = pl.take(r * r * f);
   L.scale_w = pl.take(r * f);
+  L.hs_aux = pl.take(halfstep_big_aux_floats() * f);
   L.res_part = pl.take(2 * (size_t)residual_blocks(m, n) * d);
   L.res_out = pl.take(2 * d);
   L.flags = pl.take(8 * sizeof(int));
@@ -138,8 +140,9 @@ Layout make_layout(const nmf_params* p) {
   if (p->prec != NMF_FP32) {
     const size_t es = p->prec == NMF_BF16 ? 2 : 1;
     L.Xq = pl.take((size_t)m * L.ldq * es);
-    // BF16: X^T products read Xq through the transposing kernel; FP8 keeps X^T too
-    L.XqT = p->prec == NMF_BF16 ? 0 : pl.take((size_t)n * L.ldqt * es);
+    // BF16: X^T products read Xq through the transposing kernel (k' <= 128); FP8,
+    // and BF16 with wider sketches, keep a copy of X^T too
+    L.XqT = (p->prec == NMF_BF16 && k <= 128) ? 0 : pl.take((size_t)n * L.ldqt * es);
     L.Ex = pl.take((size_t)ceil_div(m, 128) * ceil_div(n, 128) * sizeof(int));
     L.Bt = pl.take((size_t)k * (L.ldq > L.ldqt ? L.ldq : L.ldqt) * es);
     L.Eb = pl.take((size_t)ceil_div(L.ldq > L.ldqt ? L.ldq : L.ldqt, 128) * sizeof(int));
@@ -298,7 +301,10 @@ hipError_t gemm_lowp(nmf_ctx* c, const Chain& ch, int side, const float* B, floa
     uint16_t* Bt = (uint16_t*)ch.Bt;
     // prepared: the orthonormalisation that produced B already wrote its BF16 copy
     if (!prepared && (e = launch_prep_b_bf16(B, L.KP, K, k, Bt, Kpad, ch.st))) return e;
-    // X B: Xq rows are K-contiguous; X^T B: the same Xq, transposed while staged
+    // X B: Xq rows are K-contiguous; X^T B: the same Xq, transposed while staged,
+    // or (k' > 128) the copy of X^T
+    if (side && L.XqT)
+      return launch_gemm_bf16_nt(c->at<uint16_t>(L.XqT), L.ldqt, Bt, Kpad, C, L.KP, M, k, Kpad, s, part, ch.st);
     return launch_gemm_bf16_nt(c->at<uint16_t>(L.Xq), L.ldq, Bt, Kpad, C, L.KP, M, k, Kpad, s, part, ch.st, true,
                                side, K);
   }
@@ -325,6 +331,7 @@ hipError_t halfstep_w(nmf_ctx* c) {
   a.N = c->p.m; a.kp = (int)L.KP; a.r = c->p.r;
   a.part = c->at<float>(L.hs_part); a.acc_out = c->at<double>(L.acc_w);
   a.alpha = 0.f; a.beta = 0.f;
+  a.gbuf = c->at<float>(L.TM); a.aux = c->at<float>(L.hs_aux);   // the m-side temporary is free while stepping
   return launch_halfstep(a, 1, c->st);
 }
 
@@ -342,6 +349,7 @@ hipError_t halfstep_h(nmf_ctx* c, int do_sweep) {
   a.N = c->p.n; a.kp = (int)L.KP; a.r = c->p.r;
   a.part = c->at<float>(L.hs_part); a.acc_out = c->at<double>(L.acc_h);
   a.alpha = c->p.alpha; a.beta = c->p.beta;
+  a.gbuf = c->at<float>(L.TN); a.aux = c->at<float>(L.hs_aux);   // the n-side temporary is free while stepping
   return launch_halfstep(a, do_sweep, c->st);
 }
 
@@ -461,7 +469,10 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
   if (lp) {
     double* sqp = xsq_quant ? c->at<double>(L.xsq_part) : nullptr;
     double* sqo = xsq_quant ? c->at<double>(L.proxy_out) + 2 : nullptr;
-    if (c->p.prec == NMF_BF16)
+    if (c->p.prec == NMF_BF16 && L.XqT)
+      HIPCHK(c, launch_quant_bf16(X, ldx, m, n, c->at<uint16_t>(L.Xq), L.ldq, c->at<uint16_t>(L.XqT), L.ldqt, st,
+                                  sqp, sqo));
+    else if (c->p.prec == NMF_BF16)
       HIPCHK(c, launch_quant_bf16_rows(X, ldx, m, n, c->at<uint16_t>(L.Xq), L.ldq, st, sqp, sqo));
     else
       HIPCHK(c, launch_quant_fp8(X, ldx, m, n, c->at<int>(L.Ex), c->at<uint8_t>(L.Xq), L.ldq,
@@ -1280,7 +1291,7 @@ size_t nmf_orth_workspace_bytes(int64_t rows, int32_t k) {
 
 nmf_status nmf_orth(float* Y, int64_t ldy, int64_t rows, int32_t k, void* ws, size_t ws_bytes,
                     void* hs, int32_t* shifted) {
-  if (!Y || rows < k || k <= 0 || k > 128 || ldy < k || ldy % 4) return fail(nullptr, NMF_EINVAL, "bad arguments");
+  if (!Y || rows < k || k <= 0 || k > 256 || ldy < k || ldy % 4) return fail(nullptr, NMF_EINVAL, "bad arguments");
   if (!ws || ws_bytes < nmf_orth_workspace_bytes(rows, k) || ((uintptr_t)ws & 255)) return fail(nullptr, NMF_ENOMEM, "workspace too small or misaligned");
   const int s = gram_pick_splits(rows, k);
   char* p = (char*)ws;

@@ -107,44 +107,150 @@ gram_f64_kernel(const float* __restrict__ Y, int64_t ldy, int64_t rows, int k, i
 // attempt 1: second pass; if G is already within 1e-6 of I (the first pass was
 //            orthonormal to working precision) it only sets status[3] (skip).
 // attempt 2: third pass, only after a shifted factorisation (status[0]).
+// Factorisation of the k x k lower triangle of G (ld ldg) plus shift I, k <= KMAX,
+// and R^{-1} written to Rinv (ld ldr; upper triangle, zeros below), visible to
+// the whole workgroup on return.  Returns false (uniformly, nothing written) on
+// a non-positive or non-finite pivot.  Called by every thread of a TD x TD
+// workgroup.
+template <int KMAX, int TD>
+__device__ bool chol_factor_inverse(const double* __restrict__ G, int ldg, int k, double shift,
+                                    double* __restrict__ Rinv, int ldr, double (*colj)[KMAX],
+                                    double (*rowj)[KMAX], int* fail) {
+  constexpr int PB = KMAX / TD;
+  const int tid = threadIdx.x, tx = tid % TD, ty = tid / TD;
+  double M[PB][PB], X[PB][PB];
+#pragma unroll
+  for (int a = 0; a < PB; ++a)
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+      const int i = ty + TD * a, l = tx + TD * b;
+      M[a][b] = (i < k && l <= i) ? G[i * ldg + l] + (i == l ? shift : 0.0) : 0.0;
+      X[a][b] = (i < k && i == l) ? 1.0 : 0.0;
+    }
+  if (tid == 0) *fail = 0;
+  __syncthreads();
+  bool stop = false;
+#pragma unroll
+  for (int b0 = 0; b0 < PB; ++b0) {
+    for (int jj = 0; jj < TD; ++jj) {
+      const int j = b0 * TD + jj;
+      if (j >= k || stop) break;
+      // publish column j of A and row j of X (both unscaled) into buffer j % 2;
+      // a thread writes buffer j % 2 again only after the barrier of step
+      // j + 1, which every reader of step j has passed
+      const int bf = j & 1;
+      if (tx == jj) {
+#pragma unroll
+        for (int a = 0; a < PB; ++a) colj[bf][ty + TD * a] = M[a][b0];
+      }
+      if (ty == jj) {
+#pragma unroll
+        for (int b = 0; b < PB; ++b) rowj[bf][tx + TD * b] = X[b0][b];
+      }
+      __syncthreads();
+      const double p = colj[bf][j];
+      if (!(p > 0.0) || !isfinite(p)) {   // uniform: every thread reads the same p
+        stop = true;
+        if (tid == 0) *fail = 1;
+        break;
+      }
+      // 1/sqrt(p): hardware estimate and one Newton step; d = p / sqrt(p)
+      double id = __builtin_amdgcn_rsq(p);
+      id = id * fma(-0.5 * p * id, id, 1.5);
+      const double d = p * id;
+      double lc[PB], lr[PB], xj[PB];
+#pragma unroll
+      for (int a = 0; a < PB; ++a) lc[a] = colj[bf][ty + TD * a] * id;     // L[i][j]
+#pragma unroll
+      for (int b = 0; b < PB; ++b) {
+        lr[b] = colj[bf][tx + TD * b] * id;                                // L[l][j]
+        xj[b] = rowj[bf][tx + TD * b] * id;                                // X[j][c] / L[j][j]
+      }
+#pragma unroll
+      for (int a = 0; a < PB; ++a) {
+        const int i = ty + TD * a;
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+          const int l = tx + TD * b;
+          if (j < l && l <= i) M[a][b] -= lc[a] * lr[b];
+          if (l <= j && j < i) X[a][b] -= lc[a] * xj[b];
+        }
+      }
+      if (tx == jj) {
+#pragma unroll
+        for (int a = 0; a < PB; ++a) {
+          const int i = ty + TD * a;
+          if (i > j) M[a][b0] = lc[a];
+          else if (i == j) M[a][b0] = d;
+        }
+      }
+      if (ty == jj) {
+#pragma unroll
+        for (int b = 0; b < PB; ++b)
+          if (tx + TD * b <= j) X[b0][b] = xj[b];
+      }
+    }
+  }
+  __syncthreads();
+  if (*fail) return false;
+  // R^{-1}[c][i] = X[i][c] for c <= i, 0 below the diagonal
+#pragma unroll
+  for (int a = 0; a < PB; ++a)
+#pragma unroll
+    for (int b = 0; b < PB; ++b) {
+      const int i = ty + TD * a, c = tx + TD * b;
+      if (i < k && c < k) Rinv[c * ldr + i] = (c <= i) ? X[a][b] : 0.0;
+    }
+  __syncthreads();   // R^{-1} is read by other threads of the workgroup next
+  return true;
+}
+
+// Largest |G_il - delta_il| over the k x k matrix, reduced over the workgroup
+// (wred: one slot per wave).
+__device__ double gram_identity_dev(const double* __restrict__ G, int k, double* wred) {
+  double dev = 0.0;
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    const int i = e / k, l = e % k;
+    dev = fmax(dev, fabs(G[e] - (i == l ? 1.0 : 0.0)));
+  }
+  for (int off = 32; off > 0; off >>= 1) dev = fmax(dev, __shfl_xor(dev, off));
+  if ((threadIdx.x & 63) == 0) wred[threadIdx.x >> 6] = dev;
+  __syncthreads();
+  double mx = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mx = fmax(mx, wred[w]);
+  return mx;
+}
+
+// One workgroup factorises G = L L^T and inverts L, then writes
+// R^{-1} = L^{-T} (upper, k x k).  TD x TD threads hold both matrices in
+// registers, block-cyclically: thread (tx, ty) owns rows i = ty + TD a and
+// columns l = tx + TD b (a, b < PB).  Column j (right-looking, pivot
+// p = A[j][j], L[i][j] = A[i][j] / sqrt(p), A[i][l] -= L[i][j] L[l][j] for
+// j < l <= i) is published through LDS together with row j of X, where X = L^{-1}
+// is built by forward elimination on the identity in the same loop
+// (X[j][:] /= L[j][j], then X[i][:] -= L[i][j] X[j][:] for i > j).
+// attempt 0: first pass, resets the per-orthonormalisation flags.
+// attempt 1: second pass; if G is already within 1e-6 of I (the first pass was
+//            orthonormal to working precision) it only sets status[3] (skip).
+// attempt 2: third pass, only after a shifted factorisation (status[0]).
 template <int KMAX, int TD>
 __global__ void __launch_bounds__(TD * TD)
 cholesky_kernel(const double* __restrict__ G, int k, int64_t rows, double* __restrict__ Rinv,
                 int* __restrict__ status, int attempt) {
-  constexpr int PB = KMAX / TD;
   constexpr int NW = TD * TD / 64;
   if (attempt == 2 && status[0] == 0) return;
   __shared__ double colj[2][KMAX], rowj[2][KMAX];   // double-buffered: one barrier per column
   __shared__ double wred[NW];
   __shared__ int fail;
-  const int tid = threadIdx.x, tx = tid % TD, ty = tid / TD;
-
-  if (attempt == 1) {
-    double dev = 0.0;
-#pragma unroll
-    for (int a = 0; a < PB; ++a)
-#pragma unroll
-      for (int b = 0; b < PB; ++b) {
-        const int i = ty + TD * a, l = tx + TD * b;
-        if (i < k && l < k) dev = fmax(dev, fabs(G[i * k + l] - (i == l ? 1.0 : 0.0)));
-      }
-    for (int off = 32; off > 0; off >>= 1) dev = fmax(dev, __shfl_xor(dev, off));
-    if ((tid & 63) == 0) wred[tid >> 6] = dev;
-    __syncthreads();
-    double mx = 0.0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) mx = fmax(mx, wred[w]);
-    if (mx <= 1e-6) {                     // uniform
-      if (tid == 0) status[3] = 1;
-      return;
-    }
+  const int tid = threadIdx.x;
+  if (attempt == 1 && gram_identity_dev(G, k, wred) <= 1e-6) {   // uniform
+    if (tid == 0) status[3] = 1;
+    return;
   }
   if (attempt == 0 && tid == 0) {
     status[0] = 0;
     status[3] = 0;
   }
-
-  double M[PB][PB], X[PB][PB];
   for (int tryi = 0; tryi < 2; ++tryi) {
     double shift = 0.0;
     if (tryi == 1) {
@@ -153,100 +259,143 @@ cholesky_kernel(const double* __restrict__ G, int k, int64_t rows, double* __res
       const double u = 1.1102230246251565e-16;
       shift = 11.0 * ((double)rows * k + (double)k * (k + 1)) * u * trace;
     }
-#pragma unroll
-    for (int a = 0; a < PB; ++a)
-#pragma unroll
-      for (int b = 0; b < PB; ++b) {
-        const int i = ty + TD * a, l = tx + TD * b;
-        M[a][b] = (i < k && l <= i) ? G[i * k + l] + (i == l ? shift : 0.0) : 0.0;
-        X[a][b] = (i < k && i == l) ? 1.0 : 0.0;
-      }
-    if (tid == 0) fail = 0;
-    __syncthreads();
-    bool stop = false;
-#pragma unroll
-    for (int b0 = 0; b0 < PB; ++b0) {
-      for (int jj = 0; jj < TD; ++jj) {
-        const int j = b0 * TD + jj;
-        if (j >= k || stop) break;
-        // publish column j of A and row j of X (both unscaled) into buffer j % 2;
-        // a thread writes buffer j % 2 again only after the barrier of step
-        // j + 1, which every reader of step j has passed
-        const int bf = j & 1;
-        if (tx == jj) {
-#pragma unroll
-          for (int a = 0; a < PB; ++a) colj[bf][ty + TD * a] = M[a][b0];
-        }
-        if (ty == jj) {
-#pragma unroll
-          for (int b = 0; b < PB; ++b) rowj[bf][tx + TD * b] = X[b0][b];
-        }
-        __syncthreads();
-        const double p = colj[bf][j];
-        if (!(p > 0.0) || !isfinite(p)) {   // uniform: every thread reads the same p
-          stop = true;
-          if (tid == 0) fail = 1;
-          break;
-        }
-        // 1/sqrt(p): hardware estimate and one Newton step; d = p / sqrt(p)
-        double id = __builtin_amdgcn_rsq(p);
-        id = id * fma(-0.5 * p * id, id, 1.5);
-        const double d = p * id;
-        double lc[PB], lr[PB], xj[PB];
-#pragma unroll
-        for (int a = 0; a < PB; ++a) lc[a] = colj[bf][ty + TD * a] * id;     // L[i][j]
-#pragma unroll
-        for (int b = 0; b < PB; ++b) {
-          lr[b] = colj[bf][tx + TD * b] * id;                                // L[l][j]
-          xj[b] = rowj[bf][tx + TD * b] * id;                                // X[j][c] / L[j][j]
-        }
-#pragma unroll
-        for (int a = 0; a < PB; ++a) {
-          const int i = ty + TD * a;
-#pragma unroll
-          for (int b = 0; b < PB; ++b) {
-            const int l = tx + TD * b;
-            if (j < l && l <= i) M[a][b] -= lc[a] * lr[b];
-            if (l <= j && j < i) X[a][b] -= lc[a] * xj[b];
-          }
-        }
-        if (tx == jj) {
-#pragma unroll
-          for (int a = 0; a < PB; ++a) {
-            const int i = ty + TD * a;
-            if (i > j) M[a][b0] = lc[a];
-            else if (i == j) M[a][b0] = d;
-          }
-        }
-        if (ty == jj) {
-#pragma unroll
-          for (int b = 0; b < PB; ++b)
-            if (tx + TD * b <= j) X[b0][b] = xj[b];
-        }
-      }
-    }
-    __syncthreads();
-    if (!fail) break;
+    if (chol_factor_inverse<KMAX, TD>(G, k, k, shift, Rinv, k, colj, rowj, &fail)) return;
     if (tryi == 0 && tid == 0 && attempt < 2) {
       status[0] = 1;               // enables the third pass (shifted CholeskyQR3)
       atomicAdd(status + 2, 1);    // shifted orthonormalisations since compress
     }
     __syncthreads();
   }
-  if (fail) {
-    if (tid == 0) status[1] = 1;
+  if (tid == 0) status[1] = 1;
+}
+
+// 16 x 16 tile (i0, j0) of op(A) op(B) over K on v_mfma_f64_16x16x4_f64, with
+// element (i, c) of A at A[i ai + c ac] and (c, j) of B at B[c bc + j bj]
+// (entries outside the ranges given as 0).  D[i][j] in lane j + 16 (i % 4),
+// register i / 4.  One wave.
+__device__ f64x4 mm16_f64(const double* A, int ai, int ac, int na, const double* B, int bc, int bj, int nb, int K,
+                          int i0, int j0) {
+  const int lane = threadIdx.x & 63, l = lane & 15, g = lane >> 4;
+  f64x4 d = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int c = k0 + g;
+    const double a = (i0 + l < na && c < K) ? A[(i0 + l) * ai + c * ac] : 0.0;
+    const double b = (j0 + l < nb && c < K) ? B[c * bc + (j0 + l) * bj] : 0.0;
+    d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
+  }
+  return d;
+}
+
+// 128 < k <= 256: the same factorisation by 2 x 2 blocks of 128 (one workgroup
+// of 32 x 32 threads).  With G = [G11 G12; G21 G22] and L = [L11 0; L21 L22]:
+// L11 from G11 (R11^{-1} = L11^{-T}), L21 = G21 R11^{-1}, L22 from the Schur
+// complement S = G22 - L21 L21^T, and
+//   R^{-1} = [R11^{-1}, -R11^{-1} L21^T R22^{-1}; 0, R22^{-1}].
+// Rinv (k x k) doubles as the scratch: L21 in its lower-left block, S in its
+// upper-right block until it is factored; the lower-left block is zeroed last.
+// The shift of a failed first try applies to the whole diagonal.
+__global__ void __launch_bounds__(1024)
+cholesky256_kernel(const double* __restrict__ G, int k, int64_t rows, double* __restrict__ Rinv,
+                   int* __restrict__ status, int attempt) {
+  constexpr int KB = 128, NWV = 16;
+  if (attempt == 2 && status[0] == 0) return;
+  __shared__ double colj[2][KB], rowj[2][KB];
+  __shared__ double wred[NWV];
+  __shared__ int fail;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int l16 = lane & 15, g4 = lane >> 4;
+  const int k2 = k - KB, nb2 = (k2 + 15) / 16;
+  if (attempt == 1 && gram_identity_dev(G, k, wred) <= 1e-6) {   // uniform
+    if (tid == 0) status[3] = 1;
     return;
   }
-  // R^{-1}[c][i] = X[i][c] for c <= i, 0 below the diagonal
-#pragma unroll
-  for (int a = 0; a < PB; ++a)
-#pragma unroll
-    for (int b = 0; b < PB; ++b) {
-      const int i = ty + TD * a, c = tx + TD * b;
-      if (i < k && c < k) {
-        Rinv[c * k + i] = (c <= i) ? X[a][b] : 0.0;
-      }
+  if (attempt == 0 && tid == 0) {
+    status[0] = 0;
+    status[3] = 0;
+  }
+  double* R11 = Rinv;                    // k x k, ld k
+  double* R12 = Rinv + KB;               // KB x k2
+  double* R21 = Rinv + (int64_t)KB * k;  // k2 x KB (scratch: L21, then T^T)
+  double* R22 = R21 + KB;                // k2 x k2
+  for (int tryi = 0; tryi < 2; ++tryi) {
+    double shift = 0.0;
+    if (tryi == 1) {
+      double trace = 0.0;
+      for (int i = 0; i < k; ++i) trace += G[i * k + i];
+      const double u = 1.1102230246251565e-16;
+      shift = 11.0 * ((double)rows * k + (double)k * (k + 1)) * u * trace;
     }
+    bool ok = chol_factor_inverse<KB, 32>(G, k, KB, shift, R11, k, colj, rowj, &fail);
+    if (ok) {
+      // L21 = G21 R11^{-1} (k2 x KB) -> lower-left block
+      for (int t = wave; t < nb2 * (KB / 16); t += NWV) {
+        const int ti = t / (KB / 16), tj = t % (KB / 16);
+        const f64x4 d = mm16_f64(G + (int64_t)KB * k, k, 1, k2, R11, k, 1, KB, KB, 16 * ti, 16 * tj);
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          const int i = 16 * ti + 4 * x + g4, j = 16 * tj + l16;
+          if (i < k2) R21[i * k + j] = d[x];
+        }
+      }
+      __syncthreads();
+      // S = G22 + shift I - L21 L21^T (k2 x k2) -> upper-right block
+      for (int t = wave; t < nb2 * nb2; t += NWV) {
+        const int ti = t / nb2, tj = t % nb2;
+        const f64x4 d = mm16_f64(R21, k, 1, k2, R21, 1, k, k2, KB, 16 * ti, 16 * tj);
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          const int i = 16 * ti + 4 * x + g4, j = 16 * tj + l16;
+          if (i < k2 && j < k2)
+            R12[i * k + j] = G[(int64_t)(KB + i) * k + KB + j] + (i == j ? shift : 0.0) - d[x];
+        }
+      }
+      __syncthreads();
+      ok = chol_factor_inverse<KB, 32>(R12, k, k2, 0.0, R22, k, colj, rowj, &fail);
+    }
+    if (ok) {
+      // T = L21^T R22^{-1} (KB x k2), held in registers across the barrier,
+      // then stored transposed over L21 (lower-left block)
+      f64x4 T[4];
+      const int nt = (KB / 16) * nb2;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int t = wave + NWV * s;
+        if (t < nt) T[s] = mm16_f64(R21, 1, k, KB, R22, k, 1, k2, k2, 16 * (t / nb2), 16 * (t % nb2));
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int t = wave + NWV * s;
+        if (t < nt) {
+#pragma unroll
+          for (int x = 0; x < 4; ++x) {
+            const int i = 16 * (t / nb2) + 4 * x + g4, j = 16 * (t % nb2) + l16;   // T[i][j], i < KB
+            if (j < k2) R21[j * k + i] = T[s][x];
+          }
+        }
+      }
+      __syncthreads();
+      // R12 = -R11^{-1} T (KB x k2), T[c][j] read at R21[j k + c]
+      for (int t = wave; t < (KB / 16) * nb2; t += NWV) {
+        const int ti = t / nb2, tj = t % nb2;
+        const f64x4 d = mm16_f64(R11, k, 1, KB, R21, 1, k, k2, KB, 16 * ti, 16 * tj);
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          const int i = 16 * ti + 4 * x + g4, j = 16 * tj + l16;
+          if (j < k2) R12[i * k + j] = -d[x];
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < k2 * KB; e += 1024) R21[(e / KB) * k + e % KB] = 0.0;
+      return;
+    }
+    if (tryi == 0 && tid == 0 && attempt < 2) {
+      status[0] = 1;               // enables the third pass (shifted CholeskyQR3)
+      atomicAdd(status + 2, 1);    // shifted orthonormalisations since compress
+    }
+    __syncthreads();
+  }
+  if (tid == 0) status[1] = 1;
 }
 
 // 64-bit value of lane `src` (uniform result).
@@ -752,6 +901,8 @@ hipError_t launch_cholesky(const double* G, int k, int64_t rows, double* Rinv, i
   else if (k <= 128)
     hipLaunchKernelGGL((cholesky_kernel<128, 32>), dim3(1), dim3(1024), 0, st, G, k, rows, Rinv,
                        status, attempt);
+  else if (k <= 256)
+    hipLaunchKernelGGL(cholesky256_kernel, dim3(1), dim3(1024), 0, st, G, k, rows, Rinv, status, attempt);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -781,6 +932,9 @@ hipError_t launch_apply_rinv(float* Y, int64_t ldy, int64_t rows, int k, const d
                        attempt, nullptr, 0);
   else if (k <= 128)
     hipLaunchKernelGGL((apply_rinv_kernel<128, false>), dim3(g), dim3(256), 0, st, Y, ldy, rows, k, Rinv, status,
+                       attempt, nullptr, 0);
+  else if (k <= 256)
+    hipLaunchKernelGGL((apply_rinv_kernel<256, false>), dim3(g), dim3(256), 0, st, Y, ldy, rows, k, Rinv, status,
                        attempt, nullptr, 0);
   else
     return hipErrorInvalidValue;

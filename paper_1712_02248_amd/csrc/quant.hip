@@ -421,22 +421,22 @@ quant_fp8_fused_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int6
   }
 }
 
-// B -> Bt in e4m3 for N <= 128 in one pass: one workgroup per 128-row block of B
-// (its exponent Ebt[block] as above, then the transposed codes through LDS).
+// B -> Bt in e4m3 for N <= 256 in one launch: one workgroup per 128-row block of
+// B (its exponent Ebt[block] as above from all N columns, then the transposed
+// codes of each 128-column half through LDS).
 __global__ void __launch_bounds__(256)
 prep_bt_fp8_kernel(const float* __restrict__ B, int64_t ldb, int64_t K, int64_t N, int* __restrict__ Ebt,
                    uint8_t* __restrict__ Bt, int64_t ldbt) {
-  __shared__ float T[128][129];          // T[j][k]
+  __shared__ float T[128][129];          // T[j][k] of the current column half
   __shared__ float wmax[4];
   __shared__ int sexp;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t k0 = (int64_t)blockIdx.x * 128;
+  const int nn = (int)N;
   float amax = 0.f;
-  for (int e = tid; e < 128 * N; e += 256) {
-    const int k = e / (int)N, j = e % (int)N;
-    const float x = (k0 + k < K) ? B[(k0 + k) * ldb + j] : 0.f;
-    T[j][k] = x;
-    amax = fmaxf(amax, fabsf(x));
+  for (int e = tid; e < 128 * nn; e += 256) {
+    const int k = e / nn, j = e % nn;
+    if (k0 + k < K) amax = fmaxf(amax, fabsf(B[(k0 + k) * ldb + j]));
   }
   for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
   if (lane == 0) wmax[wave] = amax;
@@ -448,12 +448,21 @@ prep_bt_fp8_kernel(const float* __restrict__ B, int64_t ldb, int64_t K, int64_t 
   }
   __syncthreads();
   const float s = ldexpf(1.0f, -sexp);
-  for (int e = tid; e < 32 * N; e += 256) {
-    const int j = e >> 5, w = e & 31;
-    uint32_t o = 0;
+  for (int j0 = 0; j0 < nn; j0 += 128) {
+    const int nh = nn - j0 < 128 ? nn - j0 : 128;
+    for (int e = tid; e < 128 * nh; e += 256) {
+      const int k = e / nh, j = e % nh;
+      T[j][k] = (k0 + k < K) ? B[(k0 + k) * ldb + j0 + j] : 0.f;
+    }
+    __syncthreads();
+    for (int e = tid; e < 32 * nh; e += 256) {
+      const int j = e >> 5, w = e & 31;
+      uint32_t o = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) o |= (uint32_t)e4m3_rne(T[j][4 * w + k] * s) << (8 * k);
-    *(uint32_t*)(Bt + j * ldbt + k0 + 4 * w) = o;
+      for (int k = 0; k < 4; ++k) o |= (uint32_t)e4m3_rne(T[j][4 * w + k] * s) << (8 * k);
+      *(uint32_t*)(Bt + (int64_t)(j0 + j) * ldbt + k0 + 4 * w) = o;
+    }
+    __syncthreads();
   }
 }
 
@@ -534,7 +543,7 @@ hipError_t launch_prep_b_bf16(const float* B, int64_t ldb, int64_t K, int64_t N,
 
 hipError_t launch_prep_b_fp8(const float* B, int64_t ldb, int64_t K, int64_t N, int* Ebt, uint8_t* Bt,
                              int64_t ldbt, hipStream_t st) {
-  if (N <= 128 && ldbt % 128 == 0) {   // one pass; also sets the exponents of the zero padding blocks (0)
+  if (N <= 256 && ldbt % 128 == 0) {   // one launch; also sets the exponents of the zero padding blocks (0)
     hipLaunchKernelGGL(prep_bt_fp8_kernel, dim3((unsigned)(ldbt / 128)), dim3(256), 0, st, B, ldb, K, N, Ebt, Bt,
                        ldbt);
     return hipGetLastError();
