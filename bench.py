@@ -1,6 +1,6 @@
 #!/usr/bin/env python3
 """Time-to-relative-error for compressed NMF (FastHALS-RP) on one MI355X:
-BF16 compression with a learned warm start of H, against plain FP32.
+low-precision compression with a learned warm start of H, against plain FP32.
 
 One step = the whole hot path on the workload's X, which is resident in HBM
 when the clock starts: compress (device-drawn Gaussian test matrices, range
@@ -10,20 +10,21 @@ schedule until e <= eps.  eps = (1 + 1e-3) * e_oracle, where e_oracle is the FP6
 oracle's error after the workload's iteration count (stored by
 tests/golden/make_oracle_errors.py, which calls only the oracle).
 
-Variants (same X, same cold factors):
-  plain      FP32 range finder, cold start (the paper's method).
-  bf16_warm  BF16 range-finder products with FP32 accumulation, split-BF16
-             sketch products on X (three BF16 products per term, about 16
-             significant bits), then the learned warm start: W from the reference
-             dictionary, H rows from the network on the compressed columns,
-             each kept only if it beats the cold row on the compressed
-             residual, then column-NNLS sweeps.  The step includes the
-             alignment products, inference, selection and sweeps; it excludes
-             training.
-  others     FP32 sketch products (bf16_warm_fp32_sketches), BF16 sketches
-             (their error floor lies above eps at c2), bf16 / fp8 (+ FP32
-             refinement) cold starts, fp32_warm and fp8_warm, reported
-             alongside.
+Workloads (default c5):
+  c5  X 262144 x 16384 (16 GiB, dyadic parts family formed on the device),
+      r = 128, k' = 256, q = 1, 300 iterations.  Headline `fp8_warm`: e4m3
+      range-finder products with 128 x 128 block scales, one refinement power
+      iteration per side on X (split-BF16 products), split-BF16 sketch products,
+      then the learned warm start: W from the reference dictionary, H rows from
+      the network on the compressed columns, each kept only if it beats the cold
+      row on the compressed residual, then column-NNLS sweeps.
+  c2  X 65536 x 4096 (parts family), r = 32, k' = 64, q = 2, 500 iterations.
+      Headline `bf16_warm`: BF16 range finder, split-BF16 sketches, warm start.
+Every workload also times plain FP32 FastHALS-RP from the cold factors (the
+paper's method) and variants that separate what each part contributes: the
+network replaced by the cold rows with the same dictionary and sweeps
+(`*_ctrl_no_net`), the network with a cold W (`*_net_cold_w`), no sweeps
+(`*_net_no_sweeps`), cold starts of each precision.
 The network is trained before timing on pairs from new columns of the same
 generator (same basis W0, new coefficients): a reference fit on one new draw
 gives Q_train and W_ref; every pair is (Q_train^T x, NNLS row of x against
@@ -46,9 +47,12 @@ sys.path.insert(0, ROOT)
 
 GOLDEN = os.path.join(ROOT, "tests", "golden", "oracle_errors.json")
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP8_TFLOPS = 5000.0
 PEAK_HBM_GBS = 8000.0
-# the headline variant: BF16 range finder, split-BF16 sketches, learned warm start
-HEADLINE = "bf16_warm"
+# the headline variant per workload: low-precision range finder, split-BF16
+# sketches (and refinement), learned warm start
+HEADLINE = {"c2": "bf16_warm", "c5": "fp8_warm"}
 
 
 def parse():
@@ -56,20 +60,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c5")
     ap.add_argument("--check-every", type=int, default=0, help="0: adaptive residual checks")
     ap.add_argument("--max-iters", type=int, default=0, help="0: the workload's iteration count")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=65536, help="rows of X in the oracle sample")
-    ap.add_argument("--cpu-iters", type=int, default=300, help="oracle iterations timed in the sample")
+    ap.add_argument("--cpu-rows", type=int, default=0, help="rows of X in the oracle sample (0: per workload)")
+    ap.add_argument("--cpu-iters", type=int, default=0, help="oracle iterations timed in the sample (0: per workload)")
     ap.add_argument("--pairs", type=int, default=200000, help="training pairs (rounded up to 4096)")
     ap.add_argument("--epochs", type=int, default=50, help="most training passes")
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--nnls-sweeps", type=int, default=100)
     ap.add_argument("--refine-sweeps", type=int, default=20,
                     help="column-NNLS sweeps on the warm rows against the reference dictionary")
-    ap.add_argument("--headline-only", action="store_true", help="time only plain and bf16_warm")
+    ap.add_argument("--headline-only", action="store_true", help="time only plain and the headline variant")
     ap.add_argument("--variants", default="", help="comma list of variants to time (default: all)")
     ap.add_argument("--sweep", default="", help="parameter study instead of the bench: P1, P2 or c2 "
                     "(components r x power iterations q, FastHALS-RP against FastHALS, sketch spectrum)")
@@ -95,13 +99,15 @@ def blas_threads():
 
 
 def cpu_baseline(cfg, X, W0, H0, iters_needed, rows, iters_sample):
-    """The FP64 oracle on a row sample of X, scaled linearly to the full workload."""
+    """The FP64 oracle on a row sample of X, scaled linearly to the full workload.
+    X None: the rows are formed by the oracle's own generator (the dyadic parts
+    family lives on the device only); that generation is not timed."""
     import datagen
-    from oracle import nmf, philox
+    from oracle import inputs, nmf, philox
     m, n, r, kp, q = cfg["m"], cfg["n"], cfg["r"], cfg["kp"], cfg["q"]
     ms = min(rows, m)
     seed = datagen.cfg_seed(cfg["name"])
-    Xs = X[:ms]
+    Xs = X[:ms] if X is not None else inputs.dyadic_parts_rows(cfg["name"], 0, ms)
     OL = philox.normal(n, kp, 3, seed).astype(np.float32)
     OR = philox.normal(ms, kp, 4, seed).astype(np.float32)
     t0 = time.perf_counter()
@@ -139,34 +145,26 @@ def marker_pop(torch):
         pass
 
 
-def gpu_fresh_columns(torch, nmfrp, W0d, ncols, seed, chunk, noise=0.01):
-    """New columns of the parts family drawn on the device (input synthesis,
-    untimed): max(0, W0 h + noise N(0,1)) with h from the chunk's own stream."""
-    import datagen
-    H = torch.from_numpy(datagen.fresh_h(W0d.shape[1], ncols, seed, chunk).astype(np.float32)).cuda()
-    N = nmfrp.gaussian(W0d.shape[0], ncols, 1000 + chunk, seed)
-    return torch.clamp_min(W0d @ H + noise * N, 0.0)
-
-
-def train_warm_start(torch, nmfrp, cfg, seed, args):
-    """Reference fit, pair generation and Adam training (all untimed)."""
+def train_warm_start(torch, nmfrp, cfg, seed, args, fresh):
+    """Reference fit, pair generation and Adam training (all untimed).
+    fresh(ncols, chunk): new columns of the workload's generator (device)."""
     import datagen
     from paper_1712_02248_amd import warmstart
     m, n, r, kp, q = cfg["m"], cfg["n"], cfg["r"], cfg["kp"], cfg["q"]
     info = {}
-    W0gen = torch.from_numpy(datagen.parts_w0(m, cfg["r_true"], seed).astype(np.float32)).cuda()
     t0 = time.perf_counter()
-    # reference fit on one new draw of the generator
-    Xt = gpu_fresh_columns(torch, nmfrp, W0gen, n, seed, 0)
+    # reference fit on one new draw of the generator (FP32 compression)
+    Xt = fresh(n, 0)
+    mean_t = float(Xt.sum(dtype=torch.float64)) / (m * n)
     ctx = nmfrp.NMF(m, n, r, kp, q, seed=seed + 1)
-    Wi, Hi = datagen.init_factors(float(Xt.mean()), m, n, r, seed + 1)
+    Wi, Hi = datagen.init_factors(mean_t, m, n, r, seed + 1)
     ctx.compress(Xt)
     ctx.init(torch.from_numpy(Wi).cuda(), torch.from_numpy(Hi).cuda())
     _, e_ref = ctx.fit(Xt, cfg["iters"], 0.0, cfg["iters"])
     Q_train = ctx.left_basis()
     W_ref, _ = ctx.factors()
     Wh_star = warmstart.compressed_factor(Q_train, W_ref)
-    del Xt
+    del Xt, ctx
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     # pairs from new columns
@@ -176,13 +174,14 @@ def train_warm_start(torch, nmfrp, cfg, seed, args):
     Xin = torch.empty(npairs, kp, device="cuda")
     T = torch.empty(npairs, r, device="cuda")
     for c in range(nchunks):
-        Xf = gpu_fresh_columns(torch, nmfrp, W0gen, chunk, seed, 1 + c)
+        Xf = fresh(chunk, 1 + c)
         a, b = warmstart.make_pairs(Q_train, Wh_star, Xf, sweeps=args.nnls_sweeps)
         Xin[c * chunk:(c + 1) * chunk] = a
         T[c * chunk:(c + 1) * chunk] = b
-    Xv = gpu_fresh_columns(torch, nmfrp, W0gen, chunk, seed, 1 + nchunks)
+        del Xf
+    Xv = fresh(chunk, 1 + nchunks)
     Xin_v, T_v = warmstart.make_pairs(Q_train, Wh_star, Xv, sweeps=args.nnls_sweeps)
-    del Xf, Xv
+    del Xv
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     # Adam training in rounds of 5 passes; the learning rate drops 3x when the
@@ -220,20 +219,37 @@ def train_warm_start(torch, nmfrp, cfg, seed, args):
     return net, Q_train, W_ref, info
 
 
+def warm_start(ctx, warm, W0d, H0d, count=False):
+    """The initialisation of a warm variant.  warm = (net, Q_train, W_ref, sweeps,
+    mode): mode "ref" sets W = W_ref and H from the network with rejection, then
+    the sweeps; "no_net" the same without the network (cold rows, then the
+    sweeps); "cold_w" H from the network with rejection and the sweeps, W from the
+    cold draw."""
+    from paper_1712_02248_amd import warmstart
+    net, Q_train, W_ref, sweeps, mode = warm
+    if mode == "no_net":
+        return ctx.init_learned_ref(None, Q_train, W_ref, Ht_cold=H0d, refine_sweeps=sweeps, count=count)
+    if mode == "cold_w":
+        return warmstart.warm_init(ctx, net, Q_train, W_ref, Ht_cold=H0d, W0=W0d, refine_sweeps=sweeps,
+                                   count=count)
+    return warmstart.warm_init(ctx, net, Q_train, W_ref, Ht_cold=H0d, refine_sweeps=sweeps, count=count)
+
+
 def time_variant(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, prec, refine, warm, steps, warmup,
                  label="", lps=0):
-    from paper_1712_02248_amd import warmstart
     m, n, r, kp, q = cfg["m"], cfg["n"], cfg["r"], cfg["kp"], cfg["q"]
     max_iters = args.max_iters or cfg["iters"]
     ctx = nmfrp.NMF(m, n, r, kp, q, seed=seed, prec=prec, refine_fp32=refine, lowp_sketches=lps)
 
-    def step():
+    def start(count=False):
         ctx.compress(Xd)
         if warm is None:
             ctx.init(W0d, H0d)
-        else:
-            net, Q_train, W_ref, sweeps = warm
-            warmstart.warm_init(ctx, net, Q_train, W_ref, Ht_cold=H0d, refine_sweeps=sweeps)
+            return None
+        return warm_start(ctx, warm, W0d, H0d, count=count)
+
+    def step():
+        start()
         return ctx.fit(Xd, max_iters, eps, args.check_every)
 
     for _ in range(warmup):
@@ -251,15 +267,7 @@ def time_variant(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, prec, refine,
     marker_pop(torch)
     # error right after the initialisation and after 20 iterations, then the
     # stage split (library events) of a repeat of the last step's work
-    def start():
-        ctx.compress(Xd)
-        if warm is None:
-            ctx.init(W0d, H0d)
-            return None
-        net, Q_train, W_ref, sweeps = warm
-        return warmstart.warm_init(ctx, net, Q_train, W_ref, Ht_cold=H0d, refine_sweeps=sweeps, count=True)
-
-    nrej = start()
+    nrej = start(count=True)
     e0 = ctx.residual(Xd)
     ctx.step(20)
     e20 = ctx.residual(Xd)
@@ -267,8 +275,8 @@ def time_variant(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, prec, refine,
     ctx.step(its[-1])
     e_fixed = ctx.residual(Xd)
     st = ctx.stage_times()
-    return dict(times=times, iters=its, e=es, e_init=e0, e_20=e20, e_fixed=e_fixed, stages=st, rejected=nrej,
-                ctx=ctx)
+    ctx.close()
+    return dict(times=times, iters=its, e=es, e_init=e0, e_20=e20, e_fixed=e_fixed, stages=st, rejected=nrej)
 
 
 def time_uncompressed(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, steps, warmup):
@@ -324,8 +332,9 @@ def time_uncompressed(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, steps, w
                 iters_to_eps=its, e_at_stop=es, per_iteration_ms=round(e0.elapsed_time(e1) / 20, 4))
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_bf16_c2_traffic.md")
-DOMINANT_SRC = os.path.join(ROOT, "paper_1712_02248_amd", "csrc", "gemm_lp.hip")
+# committed HBM-counter summary of the dominant kernel per workload, and the
+# source file it was taken on
+TRAFFIC = {"c2": ("gemm_bf16_c2_traffic.md", "gemm_lp.hip"), "c5": ("gemm_fp8_c5_traffic.md", "gemm_lp.hip")}
 
 
 def source_digest(path):
@@ -333,17 +342,21 @@ def source_digest(path):
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(name):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, or None when it is missing or was taken on a different source."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if name not in TRAFFIC:
+        return None
+    path = os.path.join(ROOT, "profiles", TRAFFIC[name][0])
+    src = os.path.join(ROOT, "paper_1712_02248_amd", "csrc", TRAFFIC[name][1])
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if line.startswith("- ") and ":" in line:
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
-    if vals.get("source sha256/16") != source_digest(DOMINANT_SRC):
+    if vals.get("source sha256/16") != source_digest(src):
         return None
     try:
         return float(vals["HBM bytes per launch"])
@@ -351,12 +364,31 @@ def measured_traffic():
         return None
 
 
-def kernel_timing(torch, nmfrp, Xd, m, n, kp, reps):
+def lowp_products(torch, nmfrp, Xd, m, n, kp, prec):
+    """The range-finder products of the workload's precision at its shapes, on
+    prepared thin operands (X B and X^T B as the range finder issues them): BF16
+    reads the one row-major copy (X^T B transposed in LDS), FP8 its two copies."""
+    dev = Xd.device
+    B_n = torch.randn(n, kp, device=dev)
+    B_m = torch.randn(m, kp, device=dev)
+    Xq, XqT, E = nmfrp.quantize_x(Xd, prec)
+    if prec == nmfrp.NMF_BF16 and kp <= 128:
+        P1 = nmfrp.LowpProduct(prec, Xq, n, B_n)
+        P2 = nmfrp.LowpProduct(prec, Xq, m, B_m, at=True, Kpad=-(-m // 128) * 128, M=n)
+        del XqT
+    else:
+        tn = E.shape[1] if E is not None else 0
+        P1 = nmfrp.LowpProduct(prec, Xq, n, B_n, E, (tn, 1))
+        P2 = nmfrp.LowpProduct(prec, XqT, m, B_m, E, (1, tn))
+    return P1, P2
+
+
+def kernel_timing(torch, nmfrp, Xd, m, n, kp, reps, prec, name):
     """Per-launch times of the compression products at the workload's shapes.
-    The dominant kernel of the BF16 path, the BF16 product, is timed alone on
-    prepared operands (X B and X^T B alternating, as the range finder issues
-    them); the FP32 products are timed per library call (product plus split-K
-    sum)."""
+    The dominant kernel of the headline path, the low-precision range-finder
+    product, is timed alone on prepared operands (X B and X^T B alternating, as
+    the range finder issues them); the FP32 products are timed per library call
+    (product plus split-K sum); the split-BF16 sketch product per call."""
     dev = Xd.device
     B_n = torch.randn(n, kp, device=dev)
     B_m = torch.randn(m, kp, device=dev)
@@ -377,59 +409,66 @@ def kernel_timing(torch, nmfrp, Xd, m, n, kp, reps):
     flops = 2.0 * m * n * kp
     res = {}
     for label, fn in (("fp32 X*B (call)", lambda: nmfrp.gemm(Xd, B_n, False, Y_m)),
-                      ("fp32 X^T*B (call)", lambda: nmfrp.gemm(Xd, B_m, True, Y_n))):
+                      ("fp32 X^T*B (call)", lambda: nmfrp.gemm(Xd, B_m, True, Y_n)),
+                      ("split-bf16 X*B (call)", lambda: nmfrp.gemm_split(Xd, 0, B_n)),
+                      ("split-bf16 X^T*B (call)", lambda: nmfrp.gemm_split(Xd, 1, B_m))):
         ms = timed(fn, 1)
         res[label] = dict(ms=round(ms, 5), tflops=round(flops / (ms * 1e-3) / 1e12, 2),
                           frac_fp32_mfma=round(flops / (ms * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4),
                           x_gbs=round(4.0 * m * n / (ms * 1e-3) / 1e9, 1))
-    Xq, _, _ = nmfrp.quantize_x(Xd, nmfrp.NMF_BF16)
-    P1 = nmfrp.LowpProduct(nmfrp.NMF_BF16, Xq, n, B_n)
-    # X^T B reads the same row-major copy, its tiles transposed in LDS (as in the range finder)
-    P2 = nmfrp.LowpProduct(nmfrp.NMF_BF16, Xq, m, B_m, at=True, Kpad=-(-m // 128) * 128, M=n)
-    alg = 2.0 * m * n                     # bytes of X per launch (BF16)
-    for label, fn, cnt in (("bf16 X*B (kernel)", P1.run, 1), ("bf16 X^T*B (kernel)", P2.run, 1),
-                           ("bf16 both (kernel)", lambda: (P1.run(), P2.run()), 2)):
+        log(f"[bench] {label}: {ms:.4f} ms  {res[label]['tflops']:.1f} TFLOP/s  X at {res[label]['x_gbs']} GB/s")
+    del Y_m, Y_n
+    P1, P2 = lowp_products(torch, nmfrp, Xd, m, n, kp, prec)
+    es = 2 if prec == nmfrp.NMF_BF16 else 1
+    fmt = "bf16" if prec == nmfrp.NMF_BF16 else "fp8"
+    alg = float(es) * m * n                     # bytes of X per launch
+    for label, fn, cnt in ((f"{fmt} X*B (kernel)", P1.run, 1), (f"{fmt} X^T*B (kernel)", P2.run, 1),
+                           (f"{fmt} both (kernel)", lambda: (P1.run(), P2.run()), 2)):
         ms = timed(fn, cnt)
         res[label] = dict(ms=round(ms, 5), tflops=round(flops / (ms * 1e-3) / 1e12, 2),
                           x_gbs=round(alg / (ms * 1e-3) / 1e9, 1))
         log(f"[bench] {label}: {ms:.4f} ms  {res[label]['tflops']:.1f} TFLOP/s  X at {res[label]['x_gbs']} GB/s")
-    dom = res["bf16 both (kernel)"]
+    dom = res[f"{fmt} both (kernel)"]
     achieved = alg / (dom["ms"] * 1e-3) / 1e9
-    traffic = measured_traffic()
+    peak_mfma = PEAK_BF16_TFLOPS if fmt == "bf16" else PEAK_FP8_TFLOPS
+    kname = ("gemm_bf16_nt_kernel (BF16 range-finder product; X B and X^T B alternating on the one row-major BF16 "
+             "copy, split-K partials)" if fmt == "bf16" and kp <= 128 else
+             f"gemm_{fmt}_nt_kernel ({fmt.upper()} range-finder product; X B on the copy of X and X^T B on the copy "
+             "of X^T, alternating, split-K partials)")
     res["roofline"] = dict(
-        bound="hbm", kernel="gemm_bf16_nt_kernel<128,64,2,2,*> (BF16 range-finder product; X B and X^T B "
-                            "alternating on the one row-major BF16 copy, split-K partials)",
+        bound="hbm", kernel=kname,
         achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s", frac=round(achieved / PEAK_HBM_GBS, 4),
-        traffic=traffic, algorithmic_bytes_per_launch=alg, units_per_launch=f"{m}x{n} X elements, 2 B each",
+        traffic=measured_traffic(name), algorithmic_bytes_per_launch=alg,
+        units_per_launch=f"{m}x{n} X elements, {es} B each",
         launch_us=round(dom["ms"] * 1e3, 2), splits=[P1.splits, P2.splits],
-        mfma_tflops=dom["tflops"], mfma_frac_bf16=round(dom["tflops"] / 2500.0, 4))
+        mfma_tflops=dom["tflops"], mfma_peak_tflops=peak_mfma,
+        mfma_frac=round(dom["tflops"] / peak_mfma, 4))
     return res
 
 
-def probe_kernels(torch, nmfrp, Xd, m, n, kp, reps):
+def probe_kernels(torch, nmfrp, Xd, m, n, kp, reps, prec):
     """For hardware-counter runs: a plain copy of known size, then the dominant
     kernel at the workload's shapes (reps launches of each shape)."""
     src = torch.empty(m * n, dtype=torch.float32, device=Xd.device).fill_(1.0)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     dst.copy_(src)
-    B_n = torch.randn(n, kp, device=Xd.device)
-    B_m = torch.randn(m, kp, device=Xd.device)
-    Xq, _, _ = nmfrp.quantize_x(Xd, nmfrp.NMF_BF16)
-    P1 = nmfrp.LowpProduct(nmfrp.NMF_BF16, Xq, n, B_n)
-    P2 = nmfrp.LowpProduct(nmfrp.NMF_BF16, Xq, m, B_m, at=True, Kpad=-(-m // 128) * 128, M=n)
+    del src, dst
+    P1, P2 = lowp_products(torch, nmfrp, Xd, m, n, kp, prec)
     for _ in range(reps):
         P1.run()
         P2.run()
     torch.cuda.synchronize()
-    print(json.dumps(dict(probe="kernels", copy_bytes=4 * m * n, bf16_x_bytes=2 * m * n,
+    es = 2 if prec == nmfrp.NMF_BF16 else 1
+    print(json.dumps(dict(probe="kernels", copy_bytes=4 * m * n, x_bytes=es * m * n,
                           splits=[P1.splits, P2.splits], M=[m, n], N=kp, reps=reps,
-                          source_sha256_16=source_digest(DOMINANT_SRC))), flush=True)
+                          source_sha256_16=source_digest(os.path.join(ROOT, "paper_1712_02248_amd", "csrc",
+                                                                      "gemm_lp.hip")))), flush=True)
 
 
 # Parameter study grids (Sec 5.2): components r, oversampling r_ov (k' = r + r_ov),
 # power iterations q.  P1 and P2 stand in for the two data sets of that section
-# (their grids; r above 64 exceeds this build's kernels), c2 is the bench workload.
+# (their grids), c2 is the workload of the same name.
 SWEEPS = {
     "P1": dict(rs=[10, 20, 30, 40, 50], r_ov=5, qs=[1, 2, 3, 4, 5]),
     "P2": dict(rs=[50, 60, 70, 80, 90], r_ov=12, qs=[1, 3, 5, 7, 9, 11]),
@@ -452,8 +491,8 @@ def run_sweep(torch, nmfrp, datagen, name, args):
     spec = None
     for r in grid["rs"]:
         kp = r + grid["r_ov"]
-        if r > 64 or kp > 128 or kp > min(m, n):
-            skipped.append(dict(r=r, kp=kp, why="r > 64 or k' > 128 exceeds this build's kernels"))
+        if r > 128 or kp > 128 or kp > min(m, n):
+            skipped.append(dict(r=r, kp=kp, why="r > 128 or k' > 128 (the sketch spectrum's limit) or k' > min(m, n)"))
             continue
         W0, H0 = datagen.init_factors(X.mean(), m, n, r, seed)
         W0d, H0d = torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda()
@@ -528,25 +567,39 @@ def main():
     name = args.workload
     cfg = dict(datagen.CONFIGS[name])
     cfg["name"] = name
-    if cfg["family"] != "parts":
-        sys.exit("bench.py: the warm-start protocol draws new columns of the parts family (c2, c5)")
+    if cfg["family"] not in ("parts", "dyadic_parts"):
+        sys.exit("bench.py: the warm-start protocol draws new columns of the parts families (c2, c5)")
     m, n, r, kp, q = cfg["m"], cfg["n"], cfg["r"], cfg["kp"], cfg["q"]
     iters_cfg = cfg["iters"]
     seed = datagen.cfg_seed(name)
+    head_name = HEADLINE[name]
+    BF, F8, F32 = nmfrp.NMF_BF16, nmfrp.NMF_FP8_E4M3, nmfrp.NMF_FP32
+    lp_prec = F8 if name == "c5" else BF
 
     golden = json.load(open(GOLDEN)).get(name) if os.path.exists(GOLDEN) else None
     if args.probe_kernels:   # counters do not depend on the values of X
         g = torch.Generator(device="cuda:0")
         g.manual_seed(seed)
-        probe_kernels(torch, nmfrp, torch.rand(m, n, device="cuda:0", generator=g), m, n, kp, 5)
+        probe_kernels(torch, nmfrp, torch.rand(m, n, device="cuda:0", generator=g), m, n, kp, 5, lp_prec)
         return
-    log(f"[bench] generating {name} X {m}x{n} on the host")
-    X = datagen.make_x(name)
-    W0, H0 = datagen.init_factors(X.mean(), m, n, r, seed)
+    from datagen import device as ddev
     dev = torch.device("cuda:0")
-    Xd = torch.from_numpy(X).to(dev)
+    if cfg["family"] == "dyadic_parts":
+        log(f"[bench] forming {name} X {m}x{n} on the device")
+        Xd, W0gen, mean = ddev.dyadic_parts_x(torch, nmfrp.gaussian, name)
+        X = None
+        fresh = lambda ncols, chunk: ddev.dyadic_fresh_columns(torch, nmfrp.gaussian, W0gen, ncols, seed, chunk)
+    else:
+        log(f"[bench] generating {name} X {m}x{n} on the host")
+        X = datagen.make_x(name)
+        mean = X.mean()
+        Xd = torch.from_numpy(X).to(dev)
+        W0gen = torch.from_numpy(datagen.parts_w0(m, cfg["r_true"], seed).astype(np.float32)).to(dev)
+        fresh = lambda ncols, chunk: ddev.parts_fresh_columns(torch, nmfrp.gaussian, W0gen, ncols, seed, chunk)
+    W0, H0 = datagen.init_factors(mean, m, n, r, seed)
     W0d = torch.from_numpy(W0).to(dev)
     H0d = torch.from_numpy(H0).to(dev)
+    torch.cuda.synchronize()
 
     if golden is not None:
         e_oracle = golden["e"]
@@ -560,29 +613,47 @@ def main():
         e_oracle = None
         eps = (1.0 + 1e-3) * e_ref
         eps_src = "gpu-fp32-reference"
+        del c0
     log(f"[bench] eps = {eps:.6e} ({eps_src})")
 
     log("[bench] training the warm-start network (untimed)")
-    net, Q_train, W_ref, warm_info = train_warm_start(torch, nmfrp, cfg, seed, args)
-    warm = (net, Q_train, W_ref, args.refine_sweeps)
-    warm_net_only = (net, Q_train, W_ref, 0)
+    net, Q_train, W_ref, warm_info = train_warm_start(torch, nmfrp, cfg, seed, args, fresh)
+    sw = args.refine_sweeps
 
-    # (name, prec, FP32 refinement, warm start, sketch products (0 FP32, 1 low precision,
-    #  2 split BF16), steps, warmup)
-    BF, F8, F32 = nmfrp.NMF_BF16, nmfrp.NMF_FP8_E4M3, nmfrp.NMF_FP32
-    variants = [("plain", F32, 0, None, 0, args.steps, args.warmup),
-                (HEADLINE, BF, 0, warm, 2, args.steps, args.warmup)]
+    def warm(mode="ref", sweeps=sw):
+        return (net, Q_train, W_ref, sweeps, mode)
+
+    # (name, prec, refinement (0 none, 1 FP32, 2 split-BF16), warm start, sketch
+    #  products (0 FP32, 1 low precision, 2 split BF16), steps, warmup)
+    S, W_ = args.steps, args.warmup
+    if name == "c5":
+        variants = [("plain", F32, 0, None, 0, S, W_),
+                    (head_name, F8, 2, warm(), 2, S, W_)]
+        extra = [("fp8_warm_fp32_refine", F8, 1, warm(), 2, 2, 1),
+                 ("fp8_ctrl_no_net", F8, 2, warm("no_net"), 2, 3, 1),
+                 ("fp8_net_cold_w", F8, 2, warm("cold_w"), 2, 2, 1),
+                 ("fp8_net_no_sweeps", F8, 2, warm(sweeps=0), 2, 3, 1),
+                 ("fp8_refine", F8, 2, None, 2, 2, 1),
+                 ("bf16_warm", BF, 0, warm(), 2, 3, 1),
+                 ("bf16", BF, 0, None, 2, 2, 1),
+                 ("fp32_warm", F32, 0, warm(), 2, 3, 1)]
+    else:
+        variants = [("plain", F32, 0, None, 0, S, W_),
+                    (head_name, BF, 0, warm(), 2, S, W_)]
+        extra = [("bf16_warm_fp32_sketches", BF, 0, warm(), 0, 3, 1),
+                 ("bf16_warm_lowp_sketches", BF, 0, warm(), 1, 3, 1),
+                 ("bf16_ctrl_no_net", BF, 0, warm("no_net"), 2, 3, 1),
+                 ("bf16_net_cold_w", BF, 0, warm("cold_w"), 2, 3, 1),
+                 ("bf16_net_no_sweeps", BF, 0, warm(sweeps=0), 2, 3, 1),
+                 ("bf16", BF, 0, None, 0, 3, 1),
+                 ("bf16_lowp_sketches", BF, 0, None, 1, 3, 1),
+                 ("bf16_refine", BF, 1, None, 0, 3, 1),
+                 ("fp8_refine", F8, 1, None, 0, 3, 1),
+                 ("fp8_refine_warm", F8, 1, warm(), 0, 3, 1),
+                 ("fp32_warm", F32, 0, warm(), 0, 3, 1),
+                 ("fp8_warm", F8, 0, warm(), 2, 3, 1)]
     if not args.headline_only:
-        variants += [("bf16_warm_fp32_sketches", BF, 0, warm, 0, 3, 1),
-                     ("bf16_warm_lowp_sketches", BF, 0, warm, 1, 3, 1),
-                     ("bf16", BF, 0, None, 0, 3, 1),
-                     ("bf16_lowp_sketches", BF, 0, None, 1, 3, 1),
-                     ("bf16_refine", BF, 1, None, 0, 3, 1),
-                     ("fp8_refine", F8, 1, None, 0, 3, 1),
-                     ("fp8_refine_warm", F8, 1, warm, 0, 3, 1),
-                     ("fp32_warm", F32, 0, warm, 0, 3, 1),
-                     ("bf16_warm_net_only", BF, 0, warm_net_only, 0, 3, 1),
-                     ("fp8_warm", F8, 0, warm, 2, 3, 1)]
+        variants += extra
     if args.variants:
         keep = args.variants.split(",")
         variants = [v for v in variants if v[0] in keep]
@@ -595,16 +666,16 @@ def main():
             f"e_init {v['e_init']:.4e}, e {v['e'][-1]:.6e}, rejected {v['rejected']}")
     unc = None
     if not args.headline_only and (not args.variants or "fasthals_uncompressed" in args.variants.split(",")):
-        unc = time_uncompressed(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, 3, 1)
+        unc = time_uncompressed(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, 2 if name == "c5" else 3, 1)
         log(f"[bench] fasthals_uncompressed: median {unc['median_s'] * 1e3:.2f} ms, iters {unc['iters_to_eps']}, "
             f"{unc['per_iteration_ms']:.3f} ms per iteration")
-    head = out.get(HEADLINE) or next(iter(out.values()))
+    head = out.get(head_name) or next(iter(out.values()))
     plain = out.get("plain")
     total_head = sum(head["times"])
 
     # ---- kernel timing at the exact shapes of the compression, HIP events on the
     # stream the kernels are launched on (the current torch stream).
-    kt = kernel_timing(torch, nmfrp, Xd, m, n, kp, args.kernel_reps)
+    kt = kernel_timing(torch, nmfrp, Xd, m, n, kp, args.kernel_reps, lp_prec, name)
     roofline = kt.pop("roofline")
 
     def summary(v):
@@ -622,19 +693,22 @@ def main():
     ref_v = plain or head
     per_iter_ms = ref_v["stages"]["step_ms"] / max(ref_v["iters"][-1], 1)
     upd_bytes = 8.0 * (m + n) * (kp + r)
+    upd_flops = 2.0 * r * (m + n) * (2 * kp + r)
     vmed = statistics.median(head["times"])
     pmed = statistics.median(plain["times"]) if plain else None
+    hdesc = ("FP8 e4m3 range finder (128 x 128 block scales) with one split-BF16 refinement power iteration per "
+             "side, split-BF16 sketches" if name == "c5" else "BF16 range finder, split-BF16 sketches")
     line = dict(
-        metric="time-to-rel-error eps (s), BF16 compression + learned warm start (plain FP32 alongside)",
+        metric=f"time-to-rel-error eps (s), {'FP8' if name == 'c5' else 'BF16'} compression + learned warm start "
+               "(plain FP32 alongside)",
         value=round(vmed, 6), unit="s", n_gpus=1, steps=args.steps,
         warmup=args.warmup, ms_per_step=round(total_head / args.steps * 1e3, 3), higher_is_better=False,
-        scaling="weak", vs_baseline=None, dtype="bf16", data="synthetic",
+        scaling="weak", vs_baseline=None, dtype="fp8" if name == "c5" else "bf16", data="synthetic",
         config=dict(workload=f"{name}: X {m}x{n} FP32 synthetic ({cfg['family']} family, r_true="
                     f"{cfg['r_true']}), r={r}, k'={kp}, q={q}, eps=(1+1e-3) e_oracle({iters_cfg} it); "
-                    f"BF16 range finder, split-BF16 sketches, MLP warm start of H ({args.refine_sweeps} NNLS "
-                    f"sweeps) vs plain FP32",
+                    f"{hdesc}, MLP warm start of H ({sw} NNLS sweeps) vs plain FP32",
                     m=m, n=n, r=r, k_sketch=kp, q=q, iters_cfg=iters_cfg, check_every=args.check_every,
-                    refine_sweeps=args.refine_sweeps),
+                    refine_sweeps=sw),
         eps=eps, eps_source=eps_src, e_oracle=e_oracle,
         plain_fp32=dict(value=round(pmed, 6), **summary(plain)) if plain else None,
         speedup_vs_plain=round(pmed / vmed, 3) if plain else None,
@@ -644,13 +718,18 @@ def main():
                                if unc else None),
         warm_start=warm_info,
         gemm=kt,
-        update_loop=dict(algorithmic_bytes_per_iteration=upd_bytes, per_iteration_ms=round(per_iter_ms, 4),
-                         gbs=round(upd_bytes / (per_iter_ms * 1e-3) / 1e9, 1)),
+        update_loop=dict(algorithmic_bytes_per_iteration=upd_bytes, algorithmic_flops_per_iteration=upd_flops,
+                         per_iteration_ms=round(per_iter_ms, 4),
+                         gbs=round(upd_bytes / (per_iter_ms * 1e-3) / 1e9, 1),
+                         tflops=round(upd_flops / (per_iter_ms * 1e-3) / 1e12, 2),
+                         frac_fp32_mfma=round(upd_flops / (per_iter_ms * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4)),
         roofline=roofline,
     )
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a row sample (cpu_baseline)")
-        line["cpu_baseline"] = cpu_baseline(cfg, X, W0, H0, ref_v["iters"][-1], args.cpu_rows, args.cpu_iters)
+        rows = args.cpu_rows or (8192 if name == "c5" else 65536)
+        its = args.cpu_iters or (10 if name == "c5" else 300)
+        line["cpu_baseline"] = cpu_baseline(cfg, X, W0, H0, ref_v["iters"][-1], rows, its)
     print(json.dumps(line), flush=True)
 
 

@@ -59,8 +59,10 @@ typedef struct {
   int32_t q;             /* power iterations (the paper's w, eq 3.5) */
   int32_t prec;          /* nmf_prec of the range-finder products (extension); the
                             projected data Xh, Xc follow lowp_sketches */
-  int32_t refine_fp32;   /* 1: one FP32 power iteration per side after the
-                            low-precision range finder */
+  int32_t refine_fp32;   /* with a low-precision prec: one power iteration per
+                            side on X itself after the low-precision range finder,
+                            its products in FP32 (1) or split-BF16 (2, as
+                            nmf_gemm_split: about 16 significant bits per term) */
   int32_t normalize;     /* a_j <- a_j/||a_j|| after the A sweep (end of Sec 4):
                             0 none, 1 with b_j <- b_j ||a_j|| (default), 2 literal */
   float alpha, beta;     /* sparsity / smoothness on B (Sec 4.1); 0, 0 = plain rule */
@@ -414,9 +416,11 @@ nmf_status nmf_nnls_rows(const float* Xr, int64_t ldx, int64_t rows, int32_t k, 
  * can only lower a row's rho, so no row ends worse than its cold row.  W is
  * set as by nmf_init (W0, typically the reference dictionary, or Philox stream
  * 5), so the first nmf_step update is the W half-step.  The net must have
- * k_in = k' and r_out = r; it runs on the context's stream.  *n_rejected (host,
- * may be NULL; then the call is asynchronous) receives the number of cold rows
- * kept. */
+ * k_in = k' and r_out = r; it runs on the context's stream.  net = NULL is the
+ * same initialisation without a network (the control that measures what the
+ * network adds): every row starts from its cold row, then the refine_sweeps.
+ * *n_rejected (host, may be NULL; then the call is asynchronous) receives the
+ * number of cold rows kept (n without a network). */
 nmf_status nmf_init_learned(nmf_ctx* ctx, nmf_mlp* net, const float* align_M, const float* Wh_ref,
                             const float* W0, const float* Ht_cold, float init_scale,
                             int32_t refine_sweeps, int64_t* n_rejected);

@@ -101,6 +101,46 @@ class RowPanels:
             out += np.asarray(self.data[i:i + self.panel], dtype=np.float64).T @ B[i:i + self.panel]
         return out
 
+    def _split(self, i):
+        """hi, lo of the split-BF16 representation of panel i (FP64 values)."""
+        from . import quant
+        P = np.asarray(self.data[i:i + self.panel], dtype=np.float32)
+        hi = quant.bf16_round_bits(P)
+        lo = quant.bf16_round_bits(P - hi)      # P - hi is exact in FP32
+        return hi.astype(np.float64), lo.astype(np.float64)
+
+    def split_matmul(self, B):
+        """split_product(X, B) panel by panel."""
+        Bh, Bl = split_bf16(B)
+        out = np.empty((self.shape[0], B.shape[1]))
+        for i in range(0, self.shape[0], self.panel):
+            hi, lo = self._split(i)
+            out[i:i + self.panel] = hi @ Bh + hi @ Bl + lo @ Bh
+        return out
+
+    def split_tmatmul(self, B):
+        """split_product(X^T, B), the panels' contributions added in ascending order."""
+        out = np.zeros((self.shape[1], B.shape[1]))
+        for i in range(0, self.shape[0], self.panel):
+            hi, lo = self._split(i)
+            Bh, Bl = split_bf16(B[i:i + self.panel])
+            out += hi.T @ Bh + hi.T @ Bl + lo.T @ Bh
+        return out
+
+    def quantised(self, fmt):
+        """The data as stored for the low-precision products (quantize_data per
+        panel; the panels are whole 128-row tile rows), held as FP32 (exact)."""
+        import concurrent.futures
+        assert self.panel % 128 == 0
+        Q = np.empty(self.shape, dtype=np.float32)
+
+        def one(i):
+            Q[i:i + self.panel] = quantize_data(np.asarray(self.data[i:i + self.panel]), fmt)
+
+        with concurrent.futures.ThreadPoolExecutor(8) as ex:   # panels are independent
+            list(ex.map(one, range(0, self.shape[0], self.panel)))
+        return RowPanels(Q, self.panel)
+
 
 def _subspace_iteration(fwd, adj, Omega, q, orth):
     """Q = orth(fwd(Omega)), then q times Z = orth(adj(Q)), Q = orth(fwd(Z))."""
@@ -190,32 +230,45 @@ def split_product(A, B):
 
 def compress_lowp(X, Omega_L, Omega_R, q, fmt, refine=False, orth=householder_q, lowp_sketches=False):
     """Model of the low-precision compression: every range-finder product uses
-    the quantised X and a quantised thin operand; optionally one FP32-exact
-    power iteration per side; the projected data use the exact X (lowp_sketches
+    the quantised X and a quantised thin operand; optionally one power iteration
+    per side on X itself, its products exact (refine True or 1, the FP32 pass)
+    or split-BF16 (refine 2); the projected data use the exact X (lowp_sketches
     0), the quantised X and quantised bases like the other products (1), or
     split-BF16 products on X (2)."""
-    X = np.asarray(X, dtype=np.float64)
-    Xq = quantize_data(X, fmt)
+    if isinstance(X, RowPanels):   # the same steps with the products over row panels
+        Xqp = X.quantised(fmt)
+        xq, xqt = (lambda B: Xqp.matmul(B)), (lambda B: Xqp.tmatmul(B))
+        x, xt = X.matmul, X.tmatmul
+        sx, sxt = X.split_matmul, X.split_tmatmul
+    else:
+        X = np.asarray(X, dtype=np.float64)
+        Xq = quantize_data(X, fmt)
+        xq, xqt = (lambda B: Xq @ B), (lambda B: Xq.T @ B)
+        x, xt = (lambda B: X @ B), (lambda B: X.T @ B)
+        sx, sxt = (lambda B: split_product(X, B)), (lambda B: split_product(X.T, B))
 
-    def prod(A, B):
-        return A @ quantize_thin(B, fmt)
+    def prod(side, B):   # side 0: Xq B, side 1: Xq^T B, on the rounded thin operand
+        return (xqt if side else xq)(quantize_thin(B, fmt))
 
-    QL = orth(prod(Xq, Omega_L))
+    QL = orth(prod(0, Omega_L))
     for _ in range(q):
-        Z = orth(prod(Xq.T, QL))
-        QL = orth(prod(Xq, Z))
-    QR = orth(prod(Xq.T, Omega_R))
+        Z = orth(prod(1, QL))
+        QL = orth(prod(0, Z))
+    QR = orth(prod(1, Omega_R))
     for _ in range(q):
-        Z = orth(prod(Xq, QR))
-        QR = orth(prod(Xq.T, Z))
-    if refine:
-        QL = orth(X @ orth(X.T @ QL))
-        QR = orth(X.T @ orth(X @ QR))
+        Z = orth(prod(0, QR))
+        QR = orth(prod(1, Z))
+    if refine == 2:
+        QL = orth(sx(orth(sxt(QL))))
+        QR = orth(sxt(orth(sx(QR))))
+    elif refine:
+        QL = orth(x(orth(xt(QL))))
+        QR = orth(xt(orth(x(QR))))
     if lowp_sketches == 2:
-        return QL, QR, split_product(X.T, QL), split_product(X, QR)
+        return QL, QR, sxt(QL), sx(QR)
     if lowp_sketches:
-        return QL, QR, prod(Xq.T, QL), prod(Xq, QR)
-    return QL, QR, X.T @ QL, X @ QR
+        return QL, QR, prod(1, QL), prod(0, QR)
+    return QL, QR, xt(QL), x(QR)
 
 
 # ----------------------------------------------------------------------------

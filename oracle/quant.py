@@ -48,6 +48,14 @@ def bf16_round(x32):
     return _round_to_grid(x, 7, -126, inf_at=2.0 ** 128)
 
 
+def bf16_round_bits(x32):
+    """The same rounding as bf16_round on the FP32 bit patterns (finite values):
+    add 0x7FFF plus the lowest kept bit, clear the low 16 bits.  For large arrays."""
+    u = np.ascontiguousarray(x32, dtype=np.float32).view(np.uint32)
+    r = (u + np.uint32(0x7FFF) + ((u >> np.uint32(16)) & np.uint32(1))) & np.uint32(0xFFFF0000)
+    return r.view(np.float32)
+
+
 def e4m3_round(x):
     """Real -> e4m3 (FN) round-to-nearest-even with saturation to +-448."""
     return _round_to_grid(x, 3, -6, maxval=448.0)

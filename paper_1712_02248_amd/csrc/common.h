@@ -197,6 +197,8 @@ hipError_t launch_adam(float* p, const float* g, float* m1, float* m2, int64_t n
                        hipStream_t st);
 hipError_t launch_infer_out(const float* Z3, const float* nrm, int Bn, int r, float* out, int64_t ldo,
                             hipStream_t st);
+// count[0] = number of nonzero flags (n flags)
+hipError_t launch_count(const int* flags, int n, long long* count, hipStream_t st);
 hipError_t launch_select(const float* Xh, int64_t ldx, int n, int k, const float* Wh, int r, const float* Hn,
                          const float* Hc, float* Hout, int* rejected, long long* count, hipStream_t st);
 

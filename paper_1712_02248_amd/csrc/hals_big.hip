@@ -25,50 +25,81 @@ constexpr int BR = 128;              // factor width of this path (columns padde
 constexpr int BNB = BR / 16;         // 16-column blocks of G
 
 // ------------------------------------------------------------------- prep
-// Block (bi, bj) of G = C^T C on v_mfma_f64_16x16x4_f64 (one wave): A[i][k] =
-// C[k][16 bi + i], B[k][j] = C[k][16 bj + j]; D[i][j] in lane j + 16 (i % 4),
-// register i / 4.  Blocks with bj == 0 also write their 16 columns of C and of
-// the scales; diagonal blocks write 1/(G_jj + beta).
-__global__ void __launch_bounds__(64)
+// Block (bi, bj) of G = C^T C on v_mfma_f64_16x16x4_f64: the two 16-column
+// slices of C are staged in LDS with all loads in flight, the four waves take
+// a quarter of k' each (A[i][k] = C[k][16 bi + i], B[k][j] = C[k][16 bj + j];
+// D[i][j] in lane j + 16 (i % 4), register i / 4), and the four partial blocks
+// are added in wave order.  Blocks with bj == 0 also write their 16 columns of
+// C and of the scales; diagonal blocks write 1/(G_jj + beta).
+constexpr int PKMAX = 256;
+__global__ void __launch_bounds__(256)
 hs_prep_kernel(HalfStepArgs a, float* __restrict__ Cp, float* __restrict__ Gp, float* __restrict__ rdiag,
                float* __restrict__ scl) {
-  const int bi = blockIdx.x, bj = blockIdx.y, lane = threadIdx.x;
+  __shared__ double Ci[PKMAX][17], Cj[PKMAX][17];
+  __shared__ double sf[2][16];
+  __shared__ f64x4 part[4][64];
+  const int bi = blockIdx.x, bj = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l = lane & 15, g = lane >> 4;
   const int kp = a.kp, r = a.r;
-  auto sfac = [&](int j) -> double {
-    if (a.norm_in && a.normalize && j < r) {
-      const double nrm = sqrt(a.acc_in[(int64_t)kp * r + j]);
-      return nrm > 0.0 ? nrm : 1.0;
+  if (tid < 32) {   // the column normalisation of C when the sum comes from the W side (end of Sec 4)
+    const int jj = 16 * (tid < 16 ? bi : bj) + (tid & 15);
+    double sj = 1.0;
+    if (a.norm_in && a.normalize && jj < r) {
+      const double nrm = sqrt(a.acc_in[(int64_t)kp * r + jj]);
+      sj = nrm > 0.0 ? nrm : 1.0;
     }
-    return 1.0;
-  };
-  const int ji = 16 * bi + l, jj = 16 * bj + l;
-  const double si = sfac(ji), sj = sfac(jj);
-  f64x4 d = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < kp; k0 += 4) {
-    const int kk = k0 + g;
-    const double av = (kk < kp && ji < r) ? a.acc_in[(int64_t)kk * r + ji] / si : 0.0;
-    const double bv = (kk < kp && jj < r) ? a.acc_in[(int64_t)kk * r + jj] / sj : 0.0;
-    d = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, d, 0, 0, 0);
+    sf[tid >> 4][tid & 15] = sj;
   }
+  // raw slices: thread t loads columns (t % 16) of rows t / 16, t / 16 + 16, ...
+  constexpr int PR = PKMAX / 16;
+  double vi[PR], vj[PR];
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    const int i = 16 * bi + 4 * x + g, j = 16 * bj + l;
-    const float gv = (float)d[x];
-    Gp[i * BR + j] = gv;
-    if (a.G_pub && i < r && j < r) a.G_pub[i * r + j] = gv;
-    if (bi == bj && i == j) {
-      const float den = (j < r) ? gv + a.beta : 0.f;
-      rdiag[j] = den > 0.f ? 1.f / den : 0.f;
+  for (int p = 0; p < PR; ++p) {
+    const int c = tid / 16 + 16 * p, jl = tid % 16;
+    const int ji = 16 * bi + jl, jjj = 16 * bj + jl;
+    vi[p] = (c < kp && ji < r) ? a.acc_in[(int64_t)c * r + ji] : 0.0;
+    vj[p] = (c < kp && jjj < r) ? a.acc_in[(int64_t)c * r + jjj] : 0.0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < PR; ++p) {
+    const int c = tid / 16 + 16 * p, jl = tid % 16;
+    Ci[c][jl] = vi[p] / sf[0][jl];
+    Cj[c][jl] = vj[p] / sf[1][jl];
+  }
+  __syncthreads();
+  f64x4 d = {0.0, 0.0, 0.0, 0.0};
+  const int kq = (kp + 15) / 16 * 4;            // k range per wave, a multiple of 4
+  for (int k0 = wave * kq; k0 < (wave + 1) * kq && k0 < kp; k0 += 4) {
+    const int kk = k0 + g;
+    d = __builtin_amdgcn_mfma_f64_16x16x4f64(Ci[kk][l], Cj[kk][l], d, 0, 0, 0);   // rows >= kp are zero
+  }
+  part[wave][lane] = d;
+  __syncthreads();
+  if (wave == 0) {
+    const f64x4 t = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int i = 16 * bi + 4 * x + g, j = 16 * bj + l;
+      const float gv = (float)t[x];
+      Gp[i * BR + j] = gv;
+      if (a.G_pub && i < r && j < r) a.G_pub[i * r + j] = gv;
+      if (bi == bj && i == j) {
+        const float den = (j < r) ? gv + a.beta : 0.f;
+        rdiag[j] = den > 0.f ? 1.f / den : 0.f;
+      }
     }
   }
   if (bj == 0) {
-    for (int c = g; c < kp; c += 4) {
-      const float cv = ji < r ? (float)(a.acc_in[(int64_t)c * r + ji] / si) : 0.f;
+    for (int e = tid; e < kp * 16; e += 256) {
+      const int c = e / 16, jl = e % 16, ji = 16 * bi + jl;
+      const float cv = (float)Ci[c][jl];
       Cp[c * BR + ji] = cv;
       if (a.C_pub && ji < r) a.C_pub[c * r + ji] = cv;
     }
-    if (g == 0) {
+    if (tid < 16) {
+      const int ji = 16 * bi + tid;
+      const double si = sf[0][tid];
       float sc = 1.f;
       if (a.norm_in) sc = (a.normalize == 1) ? (float)si : 1.f;   // compensation b_j *= ||a_j||
       else if (a.scale) sc = (ji < r) ? a.scale[ji] : 1.f;
@@ -223,7 +254,10 @@ __device__ __forceinline__ float quad_bcast_b(float v, int src) {
 // (j % 4) forms the new f_j and the change d goes to the quad; every lane then
 // takes g -= d G[j][.] for its slots u >= 4 floor(j / 16) (the slots below hold
 // components <= j, whose gradients are never read again).  G is staged in LDS
-// permuted, Gq[j][q][u] = G[j][4 u + q], so those reads are 16-byte loads.
+// permuted, Gq[j][q][u] = G[j][4 u + q], so those reads are 16-byte loads.  A
+// workgroup sweeps the 64-row tiles blockIdx.x, blockIdx.x + gridDim.x, ...;
+// the rows of its next tile are loaded while the current one is swept.
+template <bool PLAIN>   // alpha = beta = 0: the plain rule
 __global__ void __launch_bounds__(256)
 hs_sweep_kernel(const float* __restrict__ gin, const float* __restrict__ Gp, const float* __restrict__ rdiag,
                 const float* __restrict__ scl, float* __restrict__ F, int64_t N, int r, float alpha, float beta) {
@@ -240,40 +274,60 @@ hs_sweep_kernel(const float* __restrict__ gin, const float* __restrict__ Gp, con
     sc[threadIdx.x] = scl[threadIdx.x];
   }
   __syncthreads();
-  const bool plain = alpha == 0.f && beta == 0.f;
-  const int q = threadIdx.x & 3;
-  for (int64_t row = (int64_t)blockIdx.x * 64 + (threadIdx.x >> 2); row - (threadIdx.x >> 2) < N;
-       row += (int64_t)gridDim.x * 64) {
-    const bool valid = row < N;
-    float f[RQ], g[RQ];
+  const int q = threadIdx.x & 3, rl = threadIdx.x >> 2;
+  const int64_t ntiles = ceil_div(N, 64);
+  float f[RQ], g[RQ], fx[RQ], gx[RQ];
+  auto load = [&](int64_t tile, float* fo, float* go) {
+    const int64_t row = tile * 64 + rl;
 #pragma unroll
     for (int u = 0; u < RQ; ++u) {
-      const int c = 4 * u + q;
-      const bool in = valid && c < r;
-      f[u] = in ? F[row * r + c] * sc[c] : 0.f;
-      g[u] = in ? gin[row * r + c] : 0.f;
+      fo[u] = 0.f;
+      go[u] = 0.f;
     }
+    if (tile < ntiles && row < N) {
+      const float* fr = F + row * r;
+      const float* gr = gin + row * r;
 #pragma unroll
-    for (int j = 0; j < BR; ++j) {
-      const float rdj = rd[j];
-      if (rdj > 0.f) {                          // uniform over the block
-        const int t = j >> 2;
-        const float v = plain ? f[t] + g[t] * rdj : (f[t] * gjj[j] + g[t] - alpha) * rdj;
-        const float fn = v > 0.f ? v : 0.f;
-        const float d = quad_bcast_b(fn - f[t], j & 3);
-        if (q == (j & 3)) f[t] = fn;
-        const float* gr = Gq + j * BR + q * RQ;
-#pragma unroll
-        for (int u = 4 * (j >> 4); u < RQ; u += 4) {
-          const f32x4 gv = *(const f32x4*)(gr + u);
-          g[u] -= d * gv[0];
-          g[u + 1] -= d * gv[1];
-          g[u + 2] -= d * gv[2];
-          g[u + 3] -= d * gv[3];
+      for (int u = 0; u < RQ; ++u) {
+        const int c = 4 * u + q;
+        if (c < r) {
+          fo[u] = fr[c];
+          go[u] = gr[c];
         }
       }
     }
-    if (valid) {
+  };
+  load(blockIdx.x, fx, gx);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t row = tile * 64 + rl;
+#pragma unroll
+    for (int u = 0; u < RQ; ++u) {
+      f[u] = fx[u] * sc[4 * u + q];
+      g[u] = gx[u];
+    }
+    load(tile + gridDim.x, fx, gx);            // in flight during the sweep
+    // fully unrolled: every register index below is a compile-time constant
+#pragma clang loop unroll(full)
+    for (int j = 0; j < BR; ++j) {
+      // no branch: a component with 1/(G_jj + beta) = 0 keeps f_j, so its d is 0
+      const float rdj = rd[j];
+      const int t = j >> 2;
+      const float v = PLAIN ? f[t] + g[t] * rdj : (f[t] * gjj[j] + g[t] - alpha) * rdj;
+      const float fn = rdj > 0.f ? (v > 0.f ? v : 0.f) : f[t];
+      const float d = quad_bcast_b(fn - f[t], j & 3);
+      if (q == (j & 3)) f[t] = fn;
+      const float* gr = Gq + j * BR + q * RQ;
+#pragma unroll
+      for (int u = 4 * (j >> 4); u < RQ; u += 4) {
+        const f32x4 gv = *(const f32x4*)(gr + u);
+        g[u] -= d * gv[0];
+        g[u + 1] -= d * gv[1];
+        g[u + 2] -= d * gv[2];
+        g[u + 3] -= d * gv[3];
+      }
+      __builtin_amdgcn_sched_barrier(0);   // keep each step's loads with it (register pressure)
+    }
+    if (row < N) {
 #pragma unroll
       for (int u = 0; u < RQ; ++u) {
         const int c = 4 * u + q;
@@ -314,30 +368,45 @@ hs_qtf_kernel(const float* __restrict__ Qb, int64_t ldq, const float* __restrict
   const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
   const int64_t ntiles = ceil_div(N, TRW);
   const int half = lane >> 5, l32 = lane & 31;
-  __syncthreads();
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  // the next tile is loaded into registers while the current one is used
+  f32x4 qv[QV];
+  float fv[FE];
+  auto load = [&](int64_t tile) {
     const int64_t row0 = tile * TRW;
 #pragma unroll
     for (int p = 0; p < QV; ++p) {
       const int e = tid + 256 * p, i = e / (KPMAX / 4), c4 = e % (KPMAX / 4);
-      f32x4 v = z4;
-      if (row0 + i < N && 4 * c4 < kp) v = *(const f32x4*)(Qb + (row0 + i) * ldq + 4 * c4);   // padding is zero
-      *(f32x4*)(Qs + i * QROW + 4 * c4) = v;
+      qv[p] = (tile < ntiles && row0 + i < N && 4 * c4 < kp) ? *(const f32x4*)(Qb + (row0 + i) * ldq + 4 * c4) : z4;
     }
 #pragma unroll
     for (int p = 0; p < FE; ++p) {
       const int e = tid + 256 * p, i = e / BR, j = e % BR;
-      Fs[i * FROW + j] = (row0 + i < N && j < r) ? F[(row0 + i) * r + j] * sc[j] : 0.f;
+      fv[p] = (tile < ntiles && row0 + i < N && j < r) ? F[(row0 + i) * r + j] : 0.f;   // padding is zero
+    }
+  };
+  __syncthreads();
+  load(blockIdx.x);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+#pragma unroll
+    for (int p = 0; p < QV; ++p) {
+      const int e = tid + 256 * p, i = e / (KPMAX / 4), c4 = e % (KPMAX / 4);
+      *(f32x4*)(Qs + i * QROW + 4 * c4) = qv[p];
+    }
+#pragma unroll
+    for (int p = 0; p < FE; ++p) {
+      const int e = tid + 256 * p, i = e / BR, j = e % BR;
+      Fs[i * FROW + j] = fv[p] * sc[j];
     }
     __syncthreads();
+    load(tile + gridDim.x);
     {   // column sums of squares: two threads per column, fixed order
       const int j = tid % BR, pr = tid / BR;
-      float s = 0.f;
+      float sq = 0.f;
       for (int i = pr; i < TRW; i += 2) {
         const float v = Fs[i * FROW + j];
-        s += v * v;
+        sq += v * v;
       }
-      colsq += s;
+      colsq += sq;
     }
 #pragma unroll 2
     for (int k = 0; k < TRW; k += 2) {
@@ -387,7 +456,8 @@ hipError_t launch_halfstep_big(const HalfStepArgs& a, int do_sweep, hipStream_t 
   float* scl = rdiag + BR;
   const int nblk = halfstep_blocks(a.N);
   if (do_sweep) {
-    hipLaunchKernelGGL(hs_prep_kernel, dim3(BNB, BNB), dim3(64), 0, st, a, Cp, Gp, rdiag, scl);
+    if (a.kp > PKMAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(hs_prep_kernel, dim3(BNB, BNB), dim3(256), 0, st, a, Cp, Gp, rdiag, scl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (a.N >= 128 * 512)
@@ -397,8 +467,12 @@ hipError_t launch_halfstep_big(const HalfStepArgs& a, int do_sweep, hipStream_t 
       hipLaunchKernelGGL(hs_grad_kernel<64>, dim3((unsigned)ceil_div(a.N, 64)), dim3(256), 0, st, a.S, a.lds, a.F,
                          scl, Cp, Gp, a.gbuf, a.N, a.kp, a.r);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(hs_sweep_kernel, dim3((unsigned)nblk), dim3(256), 0, st, a.gbuf, Gp, rdiag, scl, a.F, a.N, a.r,
-                       a.alpha, a.beta);
+    if (a.alpha == 0.f && a.beta == 0.f)
+      hipLaunchKernelGGL(hs_sweep_kernel<true>, dim3((unsigned)nblk), dim3(256), 0, st, a.gbuf, Gp, rdiag, scl, a.F,
+                         a.N, a.r, a.alpha, a.beta);
+    else
+      hipLaunchKernelGGL(hs_sweep_kernel<false>, dim3((unsigned)nblk), dim3(256), 0, st, a.gbuf, Gp, rdiag, scl,
+                         a.F, a.N, a.r, a.alpha, a.beta);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   // after a sweep F is final; without one its pending column scales apply on load

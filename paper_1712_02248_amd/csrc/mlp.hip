@@ -374,24 +374,25 @@ nnls_rows_wide_kernel(const float* __restrict__ Xr, int64_t ldx, int n, int k, c
       }
   }
   for (int it = 0; it < sweeps; ++it) {
-#pragma unroll
+    // fully unrolled (compile-time register indices), no branch: a component with
+    // G_jj = 0 (1/G_jj stored as 0) keeps its value, so its d is 0
+#pragma clang loop unroll(full)
     for (int j = 0; j < RM; ++j) {
       const float rdj = rd[j];
-      if (rdj > 0.f) {                  // uniform over the block
-        const int t = j >> 2;
-        const float fn = fmaxf(fmaf(g[t], rdj, f[t]), 0.f);
-        const float d = quad_bcast_f(fn - f[t], j & 3);   // the owner's change
-        if (q == (j & 3)) f[t] = fn;
-        const float* gr = Gq + j * RM + q * RQ;
+      const int t = j >> 2;
+      const float fn = rdj > 0.f ? fmaxf(fmaf(g[t], rdj, f[t]), 0.f) : f[t];
+      const float d = quad_bcast_f(fn - f[t], j & 3);   // the owner's change
+      if (q == (j & 3)) f[t] = fn;
+      const float* gr = Gq + j * RM + q * RQ;
 #pragma unroll
-        for (int u = 0; u < RQ; u += 4) {
-          const f32x4 gv = *(const f32x4*)(gr + u);
-          g[u] = fmaf(-gv[0], d, g[u]);
-          g[u + 1] = fmaf(-gv[1], d, g[u + 1]);
-          g[u + 2] = fmaf(-gv[2], d, g[u + 2]);
-          g[u + 3] = fmaf(-gv[3], d, g[u + 3]);
-        }
+      for (int u = 0; u < RQ; u += 4) {
+        const f32x4 gv = *(const f32x4*)(gr + u);
+        g[u] = fmaf(-gv[0], d, g[u]);
+        g[u + 1] = fmaf(-gv[1], d, g[u + 1]);
+        g[u + 2] = fmaf(-gv[2], d, g[u + 2]);
+        g[u + 3] = fmaf(-gv[3], d, g[u + 3]);
       }
+      __builtin_amdgcn_sched_barrier(0);   // keep each step's loads with it (register pressure)
     }
   }
   if (valid) {
@@ -616,6 +617,11 @@ hipError_t launch_adam(float* p, const float* g, float* m1, float* m2, int64_t n
 hipError_t launch_infer_out(const float* Z3, const float* nrm, int Bn, int r, float* out, int64_t ldo,
                             hipStream_t st) {
   hipLaunchKernelGGL(infer_out_kernel, dim3(g1((int64_t)Bn * r)), dim3(256), 0, st, Z3, nrm, Bn, r, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_count(const int* flags, int n, long long* count, hipStream_t st) {
+  hipLaunchKernelGGL(count_kernel, dim3(1), dim3(256), 0, st, flags, n, count);
   return hipGetLastError();
 }
 

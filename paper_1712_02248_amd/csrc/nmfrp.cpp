@@ -54,7 +54,7 @@ bool valid_params(const nmf_params* p, std::string* why) {
   if (p->r > 128) { *why = "r > 128 is not supported by this build"; return false; }
   if (p->q < 0) { *why = "q must be >= 0"; return false; }
   if (p->prec < NMF_FP32 || p->prec > NMF_FP8_E4M3) { *why = "prec must be FP32, BF16 or FP8_E4M3"; return false; }
-  if (p->refine_fp32 < 0 || p->refine_fp32 > 1) { *why = "refine_fp32 must be 0 or 1"; return false; }
+  if (p->refine_fp32 < 0 || p->refine_fp32 > 2) { *why = "refine_fp32 must be 0, 1 or 2"; return false; }
   if (p->normalize < 0 || p->normalize > 2) { *why = "normalize must be 0, 1 or 2"; return false; }
   if (p->n % 4) { *why = "n must be a multiple of 4"; return false; }
   if (p->alpha < 0 || p->beta < 0) { *why = "alpha, beta must be >= 0"; return false; }
@@ -94,7 +94,8 @@ Layout make_layout(const nmf_params* p) {
     if (q1 > gp) gp = q1;
     if (q2 > gp2) gp2 = q2;
   }
-  if (p->lowp_sketches == 2) {
+  const bool split_any = p->lowp_sketches == 2 || (p->prec != NMF_FP32 && p->refine_fp32 == 2);
+  if (split_any) {
     const int l1 = gemm_split_pick_splits(m, k, n), l2 = gemm_split_pick_splits(n, k, m);
     const size_t q1 = l1 > 1 ? (size_t)l1 * m * k : 0, q2 = l2 > 1 ? (size_t)l2 * n * k : 0;
     if (q1 > gp) gp = q1;
@@ -150,7 +151,7 @@ Layout make_layout(const nmf_params* p) {
     L.Eb2 = pl.take((size_t)ceil_div(L.ldq > L.ldqt ? L.ldq : L.ldqt, 128) * sizeof(int));
   }
   L.St = L.St2 = 0;
-  if (p->lowp_sketches == 2) {   // hi and lo halves, k x max(ldq, ldqt) BF16 each, per chain
+  if (split_any) {   // hi and lo halves, k x max(ldq, ldqt) BF16 each, per chain
     L.St = pl.take((size_t)2 * k * std::max(L.ldq, L.ldqt) * 2);
     L.St2 = pl.take((size_t)2 * k * std::max(L.ldq, L.ldqt) * 2);
   }
@@ -520,7 +521,23 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
     right.push_back({[&, pf] { return XB(cr, QR, TM, pf); }, [&] { return ORTH(cr, TM, m, false, true); }});
     right.push_back({[&, pf] { return XtB(cr, TM, QR, pf); }, [&, last, more] { return ORTH(cr, QR, n, last, more); }});
   }
-  if (refine) {   // optional FP32 refinement: one power iteration per side on the exact X
+  // split-BF16 product op(X) B on X itself (refine_fp32 = 2, lowp_sketches = 2),
+  // the thin operand split into the chain's hi / lo buffers first
+  auto SPLIT = [&](const Chain& ch, int which, int at, const float* B, float* C, int64_t M, int64_t K,
+                   double* sq) -> hipError_t {
+    const int64_t ldbt = at ? L.ldqt : L.ldq;
+    uint16_t* H = c->at<uint16_t>(which ? L.St2 : L.St);
+    uint16_t* Lo = H + (size_t)k * ldbt;
+    hipError_t e = launch_prep_bt(B, L.KP, K, k, H, Lo, ldbt, ch.st);
+    return e ? e : launch_gemm_split(X, ldx, at, H, Lo, ldbt, C, L.KP, M, k, K, gemm_split_pick_splits(M, k, K),
+                                     ch.gemm_part, ch.st, sq);
+  };
+  if (refine && c->p.refine_fp32 == 2) {   // the refinement on split-BF16 products (about 16 significant bits)
+    left.push_back({[&] { return SPLIT(cl, 0, 1, QL, TN, n, m, nullptr); }, [&] { return ORTH(cl, TN, n, false, false); }});
+    left.push_back({[&] { return SPLIT(cl, 0, 0, TN, QL, m, n, nullptr); }, [&] { return ORTH(cl, QL, m, true, false); }});
+    right.push_back({[&] { return SPLIT(cr, 1, 0, QR, TM, m, n, nullptr); }, [&] { return ORTH(cr, TM, m, false, false); }});
+    right.push_back({[&] { return SPLIT(cr, 1, 1, TM, QR, n, m, nullptr); }, [&] { return ORTH(cr, QR, n, true, false); }});
+  } else if (refine) {   // optional FP32 refinement: one power iteration per side on the exact X
     left.push_back({[&] { return gemm(c, cl, X, ldx, 1, QL, TN, n, m); }, [&] { return ORTH(cl, TN, n, false, false); }});
     left.push_back({[&] { return gemm(c, cl, X, ldx, 0, TN, QL, m, n); }, [&] { return ORTH(cl, QL, m, true, false); }});
     right.push_back({[&] { return gemm(c, cr, X, ldx, 0, QR, TM, m, n); }, [&] { return ORTH(cr, TM, m, false, false); }});
@@ -625,34 +642,45 @@ nmf_status init_learned_impl(nmf_ctx* c, nmf_mlp* net, const float* align_M, con
                              const float* W0, int64_t ldw0, const float* Ht_cold, float init_scale,
                              int32_t refine_sweeps, int64_t* n_rejected) {
   if (!c) return fail(c, NMF_EINVAL, "null context");
-  if (!net || !Wh_ref) return fail(c, NMF_EINVAL, "null network or Wh_ref");
+  if (!Wh_ref) return fail(c, NMF_EINVAL, "null Wh_ref");
   if (refine_sweeps < 0) return fail(c, NMF_EINVAL, "refine_sweeps must be >= 0");
   if (!c->compressed) return fail(c, NMF_ESTATE, "init needs the sketches: call nmf_compress or nmf_set_state first");
-  int nk, nh, nr;
-  mlp_dims(net, &nk, &nh, &nr);
   const int k = c->p.k_sketch, r = c->p.r;
-  if (nk != k || nr != r) return fail(c, NMF_EINVAL, "network must map k' inputs to r outputs");
+  if (net) {
+    int nk, nh, nr;
+    mlp_dims(net, &nk, &nh, &nr);
+    if (nk != k || nr != r) return fail(c, NMF_EINVAL, "network must map k' inputs to r outputs");
+  }
   Layout& L = c->L;
   const int64_t n = c->p.n;
+  long long* cnt = reinterpret_cast<long long*>(c->at<double>(L.res_out));
+  float* Ht = c->at<float>(L.Ht);
+  if (!net) {   // the control without a network: the cold rows go to the sweeps as they are
+    if (Ht_cold) HIPCHK(c, launch_copy2d(Ht, r, Ht_cold, r, n, r, c->st));
+    else HIPCHK(c, launch_philox_uniform(Ht, n, r, r, 6u, c->p.seed, init_scale, c->st));
+    int* ones = reinterpret_cast<int*>(c->at<float>(L.TN));
+    HIPCHK(c, launch_fill_i32(ones, n, 1, c->st));
+    HIPCHK(c, launch_count(ones, (int)n, cnt, c->st));
+  }
   // 1. network input: x-tilde = M x-hat (rows: Xh M^T), else x-hat itself
   const float* in = c->at<float>(L.Xh);
   int64_t ld_in = L.KP;
-  if (align_M) {
+  if (net && align_M) {
     float* Xa = c->at<float>(L.omL);  // n x k' (the test matrix is not needed after compression)
     HIPCHK(c, launch_mlp_gemm(0, 1, 0, in, (int)L.KP, align_M, k, Xa, k, (int)n, k, k, nullptr, nullptr, 0, c->st));
     in = Xa;
     ld_in = k;
   }
-  // 2. the network's rows and the cold rows
-  float* Hn = c->at<float>(L.TN);
-  HIPCHK(c, mlp_infer_rows(net, in, ld_in, n, Hn, r, c->st));
-  float* Ht = c->at<float>(L.Ht);
-  if (Ht_cold) HIPCHK(c, launch_copy2d(Ht, r, Ht_cold, r, n, r, c->st));
-  else HIPCHK(c, launch_philox_uniform(Ht, n, r, r, 6u, c->p.seed, init_scale, c->st));
-  // 3. per-row choice by the compressed residual against Wh_ref, in place into Ht
-  int* rej = reinterpret_cast<int*>(Hn + n * r);   // TN is n x KP floats, r < KP
-  long long* cnt = reinterpret_cast<long long*>(c->at<double>(L.res_out));
-  HIPCHK(c, launch_select(c->at<float>(L.Xh), L.KP, (int)n, k, Wh_ref, r, Hn, Ht, Ht, rej, cnt, c->st));
+  if (net) {
+    // 2. the network's rows and the cold rows
+    float* Hn = c->at<float>(L.TN);
+    HIPCHK(c, mlp_infer_rows(net, in, ld_in, n, Hn, r, c->st));
+    if (Ht_cold) HIPCHK(c, launch_copy2d(Ht, r, Ht_cold, r, n, r, c->st));
+    else HIPCHK(c, launch_philox_uniform(Ht, n, r, r, 6u, c->p.seed, init_scale, c->st));
+    // 3. per-row choice by the compressed residual against Wh_ref, in place into Ht
+    int* rej = reinterpret_cast<int*>(Hn + n * r);   // TN is n x KP floats, r < KP
+    HIPCHK(c, launch_select(c->at<float>(L.Xh), L.KP, (int)n, k, Wh_ref, r, Hn, Ht, Ht, rej, cnt, c->st));
+  }
   // 4. optional column-NNLS sweeps against Wh_ref from the selected rows (each
   //    sweep lowers every row's compressed residual)
   if (refine_sweeps > 0)

@@ -95,6 +95,83 @@ gram_f64_kernel(const float* __restrict__ Y, int64_t ldy, int64_t rows, int k, i
     }
 }
 
+// G = Y^T Y for 128 < k <= 256 by 128 x 128 blocks: the three blocks (0, 0),
+// (0, 1), (1, 1) of the symmetric result, the off-diagonal one written to both
+// triangles of the split's partial (k x k).  Per 64-row chunk the two 128-column
+// slices are staged in LDS (FP32, converted to FP64 as they enter the MFMA), the
+// next chunk loaded into registers meanwhile.  Wave w owns row blocks 2 w, 2 w + 1
+// and all eight column blocks of 16 (v_mfma_f64_16x16x4_f64; A[i][kk] =
+// Y[kk][i], B[kk][j] = Y[kk][j]; D[i][j] in lane j + 16 (i % 4), register i / 4).
+__global__ void __launch_bounds__(256)
+gram_wide_kernel(const float* __restrict__ Y, int64_t ldy, int64_t rows, int k, int64_t rchunk,
+                 double* __restrict__ part, const int* __restrict__ skip_flag) {
+  if (skip_flag && skip_flag[0] == 0) return;
+  constexpr int WB = 128, CR = 64, SROW = WB + 4, PE = CR * WB / 256;
+  __shared__ float Yi[CR * SROW], Yj[CR * SROW];
+  const int blk = blockIdx.x;                       // 0: (0, 0), 1: (0, 1), 2: (1, 1)
+  const int bi = blk == 2 ? 1 : 0, bj = blk == 0 ? 0 : 1;
+  const bool diag = bi == bj;
+  const int64_t r0 = (int64_t)blockIdx.y * rchunk;
+  const int64_t r1 = (r0 + rchunk < rows) ? r0 + rchunk : rows;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, g4 = lane >> 4;
+  f64x4 acc[2][8];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  float vi[PE], vj[PE];
+  auto load = [&](int64_t c0) {
+#pragma unroll
+    for (int p = 0; p < PE; ++p) {
+      const int e = tid + 256 * p, rr = e / WB, cc = e % WB;
+      const int64_t gr = c0 + rr;
+      const int gi = WB * bi + cc, gj = WB * bj + cc;
+      vi[p] = (gr < r1 && gi < k) ? Y[gr * ldy + gi] : 0.f;
+      if (!diag) vj[p] = (gr < r1 && gj < k) ? Y[gr * ldy + gj] : 0.f;
+    }
+  };
+  if (r0 < r1) load(r0);
+  for (int64_t c0 = r0; c0 < r1; c0 += CR) {
+#pragma unroll
+    for (int p = 0; p < PE; ++p) {
+      const int e = tid + 256 * p, rr = e / WB, cc = e % WB;
+      Yi[rr * SROW + cc] = vi[p];
+      if (!diag) Yj[rr * SROW + cc] = vj[p];
+    }
+    __syncthreads();
+    if (c0 + CR < r1) load(c0 + CR);
+    const float* B = diag ? Yi : Yj;
+#pragma unroll 2
+    for (int kk = 0; kk < CR; kk += 4) {
+      const int rr = kk + g4;
+      double av[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = (double)Yi[rr * SROW + 32 * wave + 16 * a + l16];
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const double bv = (double)B[rr * SROW + 16 * b + l16];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv, acc[a][b], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  double* P = part + (int64_t)blockIdx.y * k * k;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int i = WB * bi + 32 * wave + 16 * a + 4 * x + g4, j = WB * bj + 16 * b + l16;
+        if (i < k && j < k) {
+          P[(int64_t)i * k + j] = acc[a][b][x];
+          if (!diag) P[(int64_t)j * k + i] = acc[a][b][x];
+        }
+      }
+}
+
 // One workgroup factorises G = L L^T and inverts L, then writes
 // R^{-1} = L^{-T} (upper, k x k).  TD x TD threads hold both matrices in
 // registers, block-cyclically: thread (tx, ty) owns rows i = ty + TD a and
@@ -291,8 +368,9 @@ __device__ f64x4 mm16_f64(const double* A, int ai, int ac, int na, const double*
 // L11 from G11 (R11^{-1} = L11^{-T}), L21 = G21 R11^{-1}, L22 from the Schur
 // complement S = G22 - L21 L21^T, and
 //   R^{-1} = [R11^{-1}, -R11^{-1} L21^T R22^{-1}; 0, R22^{-1}].
-// Rinv (k x k) doubles as the scratch: L21 in its lower-left block, S in its
-// upper-right block until it is factored; the lower-left block is zeroed last.
+// Rinv (k x k) doubles as the scratch: L21 in its lower-left block, S and then
+// R11^{-1} L21^T in its upper-right block, the transpose of R12 in the lower-left
+// block before it is copied up; the lower-left block is zeroed last.
 // The shift of a failed first try applies to the whole diagonal.
 __global__ void __launch_bounds__(1024)
 cholesky256_kernel(const double* __restrict__ G, int k, int64_t rows, double* __restrict__ Rinv,
@@ -353,37 +431,31 @@ cholesky256_kernel(const double* __restrict__ G, int k, int64_t rows, double* __
       ok = chol_factor_inverse<KB, 32>(R12, k, k2, 0.0, R22, k, colj, rowj, &fail);
     }
     if (ok) {
-      // T = L21^T R22^{-1} (KB x k2), held in registers across the barrier,
-      // then stored transposed over L21 (lower-left block)
-      f64x4 T[4];
-      const int nt = (KB / 16) * nb2;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int t = wave + NWV * s;
-        if (t < nt) T[s] = mm16_f64(R21, 1, k, KB, R22, k, 1, k2, k2, 16 * (t / nb2), 16 * (t % nb2));
-      }
-      __syncthreads();
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int t = wave + NWV * s;
-        if (t < nt) {
-#pragma unroll
-          for (int x = 0; x < 4; ++x) {
-            const int i = 16 * (t / nb2) + 4 * x + g4, j = 16 * (t % nb2) + l16;   // T[i][j], i < KB
-            if (j < k2) R21[j * k + i] = T[s][x];
-          }
-        }
-      }
-      __syncthreads();
-      // R12 = -R11^{-1} T (KB x k2), T[c][j] read at R21[j k + c]
+      // U = R11^{-1} L21^T (KB x k2) -> upper-right block (S is consumed)
       for (int t = wave; t < (KB / 16) * nb2; t += NWV) {
         const int ti = t / nb2, tj = t % nb2;
         const f64x4 d = mm16_f64(R11, k, 1, KB, R21, 1, k, k2, KB, 16 * ti, 16 * tj);
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
           const int i = 16 * ti + 4 * x + g4, j = 16 * tj + l16;
-          if (j < k2) R12[i * k + j] = -d[x];
+          if (j < k2) R12[i * k + j] = d[x];
         }
+      }
+      __syncthreads();
+      // R12 = -U R22^{-1}, stored transposed over L21 (lower-left block, dead now)
+      for (int t = wave; t < (KB / 16) * nb2; t += NWV) {
+        const int ti = t / nb2, tj = t % nb2;
+        const f64x4 d = mm16_f64(R12, k, 1, KB, R22, k, 1, k2, k2, 16 * ti, 16 * tj);
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          const int i = 16 * ti + 4 * x + g4, j = 16 * tj + l16;
+          if (j < k2) R21[j * k + i] = -d[x];
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < k2 * KB; e += 1024) {   // back into the upper-right block, then zeros below
+        const int j = e / KB, i = e % KB;
+        R12[i * k + j] = R21[j * k + i];
       }
       __syncthreads();
       for (int e = tid; e < k2 * KB; e += 1024) R21[(e / KB) * k + e % KB] = 0.0;
@@ -747,8 +819,8 @@ cholesky_blocked_kernel(const double* __restrict__ G, int k, int64_t rows, doubl
 // Q = Y R^{-1} in place on FP64 MFMA (v_mfma_f64_16x16x4_f64): a workgroup owns
 // 64 rows (16 per wave) and all k columns; the tile is read into LDS before any
 // write, so rows of other workgroups are never touched.  The tile is staged with
-// batched float4 loads (ldy % 4 == 0); for k <= 64 R^{-1} is staged in LDS too
-// (row stride KMAX + 2 doubles), larger k reads it from L2.
+// batched float4 loads (ldy % 4 == 0); R^{-1} is staged in LDS too (row stride
+// KMAX + 2 doubles).  (Wider bases: apply_rinv_wide_kernel.)
 // BT = true: instead of Y, write the transposed BF16 copy Bt (k x ldbt, nearest
 // even; the operand of the next low-precision product): the tile of Q goes
 // through LDS (row stride KMAX + 2 halves) and out as 16-byte chunks of Bt's
@@ -846,14 +918,102 @@ apply_rinv_kernel(float* __restrict__ Y, int64_t ldy, int64_t rows, int k,
   }
 }
 
+// Q = Y R^{-1} in place for wide bases (64 < k <= KMAX): a workgroup owns 64
+// rows and all k columns (the tile is read into LDS before any write); R^{-1}
+// goes through LDS in chunks of 32 rows (FP64), the next chunk loaded into
+// registers while the current one is used.  Wave w owns output columns
+// w KMAX/4 .. +KMAX/4 - 1 and all 64 rows: 4 x (KMAX/64) blocks of 16 x 16 on
+// v_mfma_f64_16x16x4_f64 (A[i][kk] = Y[i][kk], B[kk][j] = R^{-1}[kk][j]; D[i][j]
+// in lane j + 16 (i % 4), register i / 4).  R^{-1} is upper triangular, so a
+// chunk that starts at row c0 skips the blocks of columns below c0.
+template <int KMAX>
+__global__ void __launch_bounds__(256)
+apply_rinv_wide_kernel(float* __restrict__ Y, int64_t ldy, int64_t rows, int k, const double* __restrict__ Rinv,
+                       const int* __restrict__ status, int attempt) {
+  if (status[1] != 0) return;
+  if (attempt == 1 && status[3] != 0) return;   // second pass not needed
+  if (attempt == 2 && status[0] == 0) return;
+  constexpr int CK = 32, YROW = KMAX + 4, RROW = KMAX + 2;
+  constexpr int CT = KMAX / 64;                  // 16-column blocks per wave
+  constexpr int V4 = 64 * KMAX / 4 / 256;        // float4 of the Y tile per thread
+  constexpr int RE = CK * KMAX / 256;            // R^{-1} chunk elements per thread
+  __shared__ __attribute__((aligned(16))) float Ys[64 * YROW];
+  __shared__ double Rs[CK * RROW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, g4 = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * 64;
+#pragma unroll
+  for (int p = 0; p < V4; ++p) {
+    const int e = tid + 256 * p, i = e / (KMAX / 4), c = 4 * (e % (KMAX / 4));
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+    if (row0 + i < rows && c < k) {
+      v = *(const f32x4*)(Y + (row0 + i) * ldy + c);
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        if (c + d >= k) v[d] = 0.f;              // a partial last group (k % 4 != 0)
+    }
+    *(f32x4*)(Ys + i * YROW + c) = v;
+  }
+  double rv[RE];
+  auto load_chunk = [&](int c0) {
+#pragma unroll
+    for (int p = 0; p < RE; ++p) {
+      const int e = tid + 256 * p, kk = e / KMAX, j = e % KMAX;
+      rv[p] = (c0 + kk < k && j < k) ? Rinv[(int64_t)(c0 + kk) * k + j] : 0.0;
+    }
+  };
+  f64x4 acc[4][CT];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  const int jb0 = wave * (KMAX / 4);             // first output column of this wave
+  load_chunk(0);
+  for (int c0 = 0; c0 < k; c0 += CK) {
+    __syncthreads();                             // the previous chunk is consumed (and the Y tile stored)
+#pragma unroll
+    for (int p = 0; p < RE; ++p) {
+      const int e = tid + 256 * p, kk = e / KMAX, j = e % KMAX;
+      Rs[kk * RROW + j] = rv[p];
+    }
+    __syncthreads();
+    if (c0 + CK < k) load_chunk(c0 + CK);
+#pragma unroll
+    for (int s = 0; s < CK / 4; ++s) {
+      const int kk = 4 * s + g4;
+      double av[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = (double)Ys[(16 * a + l16) * YROW + c0 + kk];
+#pragma unroll
+      for (int b = 0; b < CT; ++b) {
+        if (jb0 + 16 * b + 15 < c0) continue;    // R^{-1} rows >= c0 are zero in these columns (uniform)
+        const double bv = Rs[kk * RROW + jb0 + 16 * b + l16];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv, acc[a][b], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int64_t gi = row0 + 16 * a + 4 * x + g4;
+        const int j = jb0 + 16 * b + l16;
+        if (gi < rows && j < k) Y[gi * ldy + j] = (float)acc[a][b][x];
+      }
+}
+
 }  // namespace
 
 int gram_pick_splits(int64_t rows, int k) {
   // 256 rows per split, or down to 64 rows per split so that short bases still
-  // spread over 256 workgroups; partials capped at 32 MB
+  // spread over 256 workgroups; partials capped at 32 MB (64 MB for k > 128,
+  // whose three-block grid needs more splits to fill the chip)
   int64_t s = ceil_div(rows, 256);
   if (s < 256) s = std::min<int64_t>(256, ceil_div(rows, 64));
-  const int64_t cap = (32ll << 20) / ((int64_t)k * k * 8);
+  const int64_t cap = ((k > 128 ? 64ll : 32ll) << 20) / ((int64_t)k * k * 8);
   if (s > cap) s = cap;
   if (s > 1024) s = 1024;
   if (s < 1) s = 1;
@@ -864,8 +1024,12 @@ hipError_t launch_gram_f64(const float* Y, int64_t ldy, int64_t rows, int k, dou
                            int splits, double* G, const int* skip_flag, hipStream_t st) {
   const int nb = (k + GT - 1) / GT;
   const int64_t rchunk = round_up(ceil_div(rows, splits), GROWS);
-  hipLaunchKernelGGL(gram_f64_kernel, dim3(nb * nb, splits), dim3(256), 0, st, Y, ldy, rows, k,
-                     rchunk, part, skip_flag, nullptr, 0, 0);
+  if (k > 128 && k <= 256)
+    hipLaunchKernelGGL(gram_wide_kernel, dim3(3, splits), dim3(256), 0, st, Y, ldy, rows, k, rchunk, part,
+                       skip_flag);
+  else
+    hipLaunchKernelGGL(gram_f64_kernel, dim3(nb * nb, splits), dim3(256), 0, st, Y, ldy, rows, k,
+                       rchunk, part, skip_flag, nullptr, 0, 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_sum_partials_f64(part, splits, (int64_t)k * k, G, skip_flag, st);
@@ -931,11 +1095,11 @@ hipError_t launch_apply_rinv(float* Y, int64_t ldy, int64_t rows, int k, const d
     hipLaunchKernelGGL((apply_rinv_kernel<64, false>), dim3(g), dim3(256), 0, st, Y, ldy, rows, k, Rinv, status,
                        attempt, nullptr, 0);
   else if (k <= 128)
-    hipLaunchKernelGGL((apply_rinv_kernel<128, false>), dim3(g), dim3(256), 0, st, Y, ldy, rows, k, Rinv, status,
-                       attempt, nullptr, 0);
+    hipLaunchKernelGGL(apply_rinv_wide_kernel<128>, dim3(g), dim3(256), 0, st, Y, ldy, rows, k, Rinv, status,
+                       attempt);
   else if (k <= 256)
-    hipLaunchKernelGGL((apply_rinv_kernel<256, false>), dim3(g), dim3(256), 0, st, Y, ldy, rows, k, Rinv, status,
-                       attempt, nullptr, 0);
+    hipLaunchKernelGGL(apply_rinv_wide_kernel<256>, dim3(g), dim3(256), 0, st, Y, ldy, rows, k, Rinv, status,
+                       attempt);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -269,13 +269,15 @@ class NMF:
                      count=True):
         """Warm start of H from `net` (an Mlp) with per-row rejection against
         Wh_ref (k' x r); returns the number of cold rows kept (None if count
-        is False, in which case the call does not synchronise)."""
+        is False, in which case the call does not synchronise).  net=None: the
+        same initialisation without a network (cold rows, then the sweeps)."""
         _f32(Wh_ref, (self.kp, self.r), "Wh_ref")
         _f32(align_M, (self.kp, self.kp), "align_M")
         _f32(W0, (self.m, self.r), "W0")
         _f32(Ht_cold, (self.n, self.r), "Ht_cold")
         nrej = ctypes.c_int64(-1)
-        self._c(load().nmf_init_learned(self.h, net.h, _ptr(align_M), _ptr(Wh_ref), _ptr(W0), _ptr(Ht_cold),
+        self._c(load().nmf_init_learned(self.h, net.h if net is not None else None, _ptr(align_M), _ptr(Wh_ref),
+                                        _ptr(W0), _ptr(Ht_cold),
                                         float(init_scale), int(refine_sweeps),
                                         ctypes.byref(nrej) if count else None))
         return nrej.value if count else None
@@ -289,7 +291,8 @@ class NMF:
             raise ValueError("W_ref: float32 m x r with unit column stride")
         _f32(Ht_cold, (self.n, self.r), "Ht_cold")
         nrej = ctypes.c_int64(-1)
-        self._c(load().nmf_init_learned_ref(self.h, net.h, _ptr(Q_train), Q_train.stride(0), _ptr(W_ref),
+        self._c(load().nmf_init_learned_ref(self.h, net.h if net is not None else None, _ptr(Q_train),
+                                            Q_train.stride(0), _ptr(W_ref),
                                             W_ref.stride(0), _ptr(Ht_cold), float(init_scale), int(refine_sweeps),
                                             ctypes.byref(nrej) if count else None))
         return nrej.value if count else None

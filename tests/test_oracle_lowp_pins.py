@@ -142,6 +142,12 @@ def test_refinement_pass_captures_exact_range():
         QL, QR, _, _ = nmf.compress_lowp(X, OL, OR, 1, fmt, refine=True)
         assert np.linalg.norm(Xd - QL @ (QL.T @ Xd)) / nx < 1e-12
         assert np.linalg.norm(Xd - (Xd @ QR) @ QR.T) / nx < 1e-12
+        # the refinement on split-BF16 products: the products carry about 16
+        # significant bits, so the captured range is good to about 2^-16 relative
+        # (a pass on the rounded copy of X would stay at the chain's level above)
+        QL, QR, _, _ = nmf.compress_lowp(X, OL, OR, 1, fmt, refine=2)
+        for res in (np.linalg.norm(Xd - QL @ (QL.T @ Xd)) / nx, np.linalg.norm(Xd - (Xd @ QR) @ QR.T) / nx):
+            assert 1e-12 < res < 2.0 ** -16
 
 
 def test_split_sketches_within_bound_of_exact_products():
