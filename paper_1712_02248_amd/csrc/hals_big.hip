@@ -6,17 +6,20 @@
 //   prep   C = (the other side's Qb'^T F') / its column norms when they come
 //          from the W side (the normalisation at the end of Sec 4), G = C^T C
 //          on FP64 MFMA, 1/(G_jj + beta), the column scales of F;
-//   grad   g = S C - (F diag(scl)) G for every row (the row of X-check B-check
-//          or X-hat^T A-hat minus f G), one FP32 MFMA product with the two
-//          operand pairs concatenated along K;
-//   sweep  the Gauss-Seidel sweep j = 1..r of each row in gradient form:
-//          f_j <- [f_j + g_j / G_jj]_+ (Sec 4.1: [(f_j G_jj + g_j - alpha) /
-//          (G_jj + beta)]_+), then g_l -= d G_jl with d the change of f_j;
+//   grad   a = S C - (F diag(scl)) U for every row, U the strictly lower
+//          triangle of G (a_l = the row of X-check B-check or X-hat^T A-hat at
+//          l minus the terms of the components after l), one FP32 MFMA product
+//          with the two operand pairs concatenated along K;
+//   sweep  the Gauss-Seidel sweep j = 1..r of each row (the rule
+//          f_j <- [f_j + g_j / G_jj]_+, Sec 4.1: [(f_j G_jj + g_j - alpha) /
+//          (G_jj + beta)]_+) as a forward substitution over a;
 //   qtf    this side's partials Qb^T F (the other side's compressed factor)
 //          and the column sums of F^2, per workgroup, on FP32 MFMA.
 //
 // Semantics (scales, published C / G / 1/||a_j||, alpha, beta, normalisation
 // modes) are those of the fused kernel for narrower factors.
+#include <algorithm>
+
 #include "common.h"
 
 namespace {
@@ -110,32 +113,45 @@ hs_prep_kernel(HalfStepArgs a, float* __restrict__ Cp, float* __restrict__ Gp, f
 }
 
 // ------------------------------------------------------------------- grad
-// g (N x r, ld r) = [S | F diag(scl)] [C ; -G]: K runs over the kp columns of S
-// (padded to a multiple of 32 with zeros), then over the BR columns of F.
+// a (N x r, ld r) = [S | F diag(scl)] [C ; -U]: K runs over the kp columns of S
+// (padded to a multiple of 32 with zeros), then over the BR columns of F, with
+// U[i][l] = G_il for i > l, else 0, and alpha subtracted.  A component that
+// keeps its value (1/(G_ll + beta) = 0: a zero column of C, or padding) gets
+// a_l = f_l scl_l instead (column l of C zeroed, column l of -U the unit vector,
+// no alpha), and its row of G stays whole in the product (the sweep never
+// corrects for it).
 // 256 threads, 2 x 2 waves over a BM x 128 tile; v_mfma_f32_32x32x2_f32 with
-// the k order permuted within groups of 8 so that a lane reads its four A values
-// of a group as one 16-byte LDS load (lanes 0-31 take k = 8 g + s, lanes 32-63
-// k = 8 g + 4 + s in step s).  The next K step is loaded into registers while
+// the k order permuted within groups of 8 so that a lane reads its four A and
+// its four B values of a group as one 16-byte LDS load each (lanes 0-31 take
+// k = 8 g + s, lanes 32-63 k = 8 g + 4 + s in step s): A is staged row-major
+// and B transposed (each thread loads a 4 x 4 block of B and transposes it in
+// registers), both with row stride 36 floats, which keeps 16-byte accesses
+// free of bank conflicts.  The fragments of group g + 1 are read from LDS while
+// the MFMAs of group g run, and the next K step is loaded into registers while
 // the LDS tile is consumed.
-template <int BM>
+template <int BM, bool FVEC>   // FVEC: rows of F are 16-byte aligned (r % 4 == 0)
 __global__ void __launch_bounds__(256)
 hs_grad_kernel(const float* __restrict__ S, int64_t lds, const float* __restrict__ F, const float* __restrict__ scl,
-               const float* __restrict__ Cp, const float* __restrict__ Gp, float* __restrict__ gout, int64_t N,
-               int kp, int r) {
+               const float* __restrict__ Cp, const float* __restrict__ Gp, const float* __restrict__ rdiag,
+               float alpha, float* __restrict__ gout, int64_t N, int kp, int r) {
   constexpr int BK = 32, BN = BR, WM = 2, WN = 2;
   constexpr int TM = BM / WM / 32, TN = BN / WN / 32;
-  constexpr int AROW = BK + 4, BROW = BN + 4;
-  constexpr int AE = BM * BK / 256;        // A elements per thread
-  constexpr int BV = BK * BN / 4 / 256;    // B float4 per thread
+  constexpr int AROW = BK + 4, BROW = BK + 4;
+  constexpr int AP = BM * BK / 4 / 256;    // A float4 per thread
+  static_assert(BK * BN / 16 == 256, "one 4 x 4 block of B per thread");
   __shared__ __attribute__((aligned(16))) float As[BM * AROW];
-  __shared__ __attribute__((aligned(16))) float Bs[BK * BROW];
-  __shared__ float sc[BR];
+  __shared__ __attribute__((aligned(16))) float Bt[BN * BROW];   // Bt[j][k] = B[k][j]
+  __shared__ float sc[BR], rdl[BR];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
   const int64_t i0 = (int64_t)blockIdx.x * BM;
-  if (tid < BR) sc[tid] = scl[tid];
-  const int ks = (kp + BK - 1) / BK;       // K steps over S
-  const int T = ks + BR / BK;              // then over F
+  if (tid < BR) {
+    sc[tid] = scl[tid];
+    rdl[tid] = rdiag[tid];
+  }
+  // any component below r that keeps its value (rare): the general operand masks
+  const bool anykept = __syncthreads_or(tid < r && rdiag[tid] == 0.f);
+  const int ks = (kp + BK - 1) / BK;       // K steps over S, then BR / BK over F
   f32x16 acc[TM][TN];
 #pragma unroll
   for (int x = 0; x < TM; ++x)
@@ -143,72 +159,97 @@ hs_grad_kernel(const float* __restrict__ S, int64_t lds, const float* __restrict
     for (int y = 0; y < TN; ++y)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[x][y][e] = 0.f;
-  float ra[AE];
-  f32x4 rb[BV];
+  f32x4 ra[AP];                            // A: row (t / 8) + 32 p, columns 4 (t % 8) .. +3 of the step
+  f32x4 rb[4];                             // B: rows 4 kq .. +3, columns 4 c4 .. +3 of the step
+  const int kq = tid >> 5, c4 = tid & 31, ca = 4 * (tid & 7);
   const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
-  __syncthreads();
-  // A: thread t loads row (t / 8) + 32 p, columns 4 (t % 8) .. +3 of the 32-wide step
-  auto load = [&](int t) {
-    const bool fs = t >= ks;                // F part
-    const int k0 = fs ? (t - ks) * BK : t * BK;
+  auto kept = [&](int l) { return l < r && rdl[l] == 0.f; };
+  // Loads are unconditional, from clamped addresses, and out-of-range elements
+  // are zeroed when the tile is stored: guarded loads become exec-masked blocks
+  // whose waits serialise them.  Rows of C up to 255 and of G up to 127 lie
+  // inside their buffers.
+  auto loadS = [&](int k0) {
 #pragma unroll
-    for (int p = 0; p < AE / 4; ++p) {
-      const int row = (tid >> 3) + 32 * p, c = 4 * (tid & 7);
-      const int64_t gi = i0 + row;
-      if (!fs) {
-        f32x4 v = z4;
-        if (gi < N && k0 + c < kp) v = *(const f32x4*)(S + gi * lds + k0 + c);   // padding columns are zero
-        ra[4 * p] = v[0]; ra[4 * p + 1] = v[1]; ra[4 * p + 2] = v[2]; ra[4 * p + 3] = v[3];
+    for (int p = 0; p < AP; ++p) {
+      const int64_t gi = i0 + (tid >> 3) + 32 * p;
+      const bool ok = gi < N && k0 + ca < kp;
+      ra[p] = *(const f32x4*)(S + (ok ? gi * lds + k0 + ca : 0));
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rb[e] = *(const f32x4*)(Cp + (int64_t)(k0 + 4 * kq + e) * BR + 4 * c4);
+  };
+  auto loadF = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < AP; ++p) {
+      const int64_t gi = i0 + (tid >> 3) + 32 * p;
+      if (FVEC) {
+        const bool ok = gi < N && k0 + ca < r;
+        ra[p] = *(const f32x4*)(F + (ok ? gi * r + k0 + ca : 0));
       } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int l = k0 + c + e;
-          ra[4 * p + e] = (gi < N && l < r) ? F[gi * r + l] * sc[l] : 0.f;
-        }
+        for (int e = 0; e < 4; ++e) ra[p][e] = F[(gi < N && k0 + ca + e < r) ? gi * r + k0 + ca + e : 0];
       }
     }
 #pragma unroll
-    for (int p = 0; p < BV; ++p) {
-      const int f = tid + 256 * p, kk = f / (BN / 4), c4 = f % (BN / 4);
-      f32x4 v = z4;
-      if (!fs) {
-        if (k0 + kk < kp) v = *(const f32x4*)(Cp + (int64_t)(k0 + kk) * BR + 4 * c4);
-      } else {
-        v = *(const f32x4*)(Gp + (int64_t)(k0 + kk) * BR + 4 * c4);
-        v = -v;
+    for (int e = 0; e < 4; ++e) rb[e] = *(const f32x4*)(Gp + (int64_t)(k0 + 4 * kq + e) * BR + 4 * c4);
+  };
+  auto storeA = [&](int k0, int lim, bool fs) {
+#pragma unroll
+    for (int p = 0; p < AP; ++p) {
+      const int row = (tid >> 3) + 32 * p;
+      const bool rok = i0 + row < N;
+      f32x4 v;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float x = fs ? ra[p][e] * sc[k0 + ca + e] : ra[p][e];   // the pending column scales of F
+        v[e] = (rok && k0 + ca + e < lim) ? x : 0.f;
       }
-      rb[p] = v;
+      *(f32x4*)(As + row * AROW + ca) = v;
     }
   };
-  auto store = [&]() {
+  // column 4 c4 + d of the rows 4 kq .. 4 kq + 3 goes to Bt[4 c4 + d][4 kq ..]
+  auto storeS = [&](int k0) {
+    storeA(k0, kp, false);
 #pragma unroll
-    for (int p = 0; p < AE / 4; ++p) {
-      const int row = (tid >> 3) + 32 * p, c = 4 * (tid & 7);
-      *(f32x4*)(As + row * AROW + c) = (f32x4){ra[4 * p], ra[4 * p + 1], ra[4 * p + 2], ra[4 * p + 3]};
+    for (int d = 0; d < 4; ++d) {
+      const int l = 4 * c4 + d;
+      f32x4 v;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = k0 + 4 * kq + e < kp ? rb[e][d] : 0.f;   // rows of C past kp are stale
+      if (anykept && kept(l)) v = z4;
+      *(f32x4*)(Bt + l * BROW + 4 * kq) = v;
     }
+  };
+  auto storeF = [&](int k0) {
+    storeA(k0, r, true);
 #pragma unroll
-    for (int p = 0; p < BV; ++p) {
-      const int f = tid + 256 * p, kk = f / (BN / 4), c4 = f % (BN / 4);
-      *(f32x4*)(Bs + kk * BROW + 4 * c4) = rb[p];
+    for (int d = 0; d < 4; ++d) {
+      const int l = 4 * c4 + d;
+      f32x4 v;
+      if (!anykept) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = k0 + 4 * kq + e > l ? -rb[e][d] : 0.f;
+      } else {
+        const bool kl = kept(l);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = k0 + 4 * kq + e;
+          v[e] = kl ? (i == l ? 1.f : 0.f) : ((kept(i) || i > l) ? -rb[e][d] : 0.f);
+        }
+      }
+      *(f32x4*)(Bt + l * BROW + 4 * kq) = v;
     }
   };
   const int half = lane >> 5, l32 = lane & 31;
-  load(0);
-  for (int t = 0; t < T; ++t) {
-    store();
-    __syncthreads();
-    if (t + 1 < T) load(t + 1);
+  auto mma = [&]() {
 #pragma unroll
     for (int gq = 0; gq < BK / 8; ++gq) {
       const int kb = 8 * gq + 4 * half;
-      f32x4 af[TM];
-      float bf[TN][4];
+      f32x4 af[TM], bf[TN];
 #pragma unroll
       for (int x = 0; x < TM; ++x) af[x] = *(const f32x4*)(As + (wm * (BM / WM) + 32 * x + l32) * AROW + kb);
 #pragma unroll
-      for (int y = 0; y < TN; ++y)
-#pragma unroll
-        for (int s = 0; s < 4; ++s) bf[y][s] = Bs[(kb + s) * BROW + wn * (BN / WN) + 32 * y + l32];
+      for (int y = 0; y < TN; ++y) bf[y] = *(const f32x4*)(Bt + (wn * (BN / WN) + 32 * y + l32) * BROW + kb);
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -217,6 +258,26 @@ hs_grad_kernel(const float* __restrict__ S, int64_t lds, const float* __restrict
           for (int y = 0; y < TN; ++y)
             acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[x][s], bf[y][s], acc[x][y], 0, 0, 0);
     }
+  };
+  // the next step's loads are issued before this step's MFMAs (the scheduler
+  // would otherwise sink them behind the MFMAs and expose their latency)
+  __syncthreads();
+  loadS(0);
+  for (int t = 0; t < ks; ++t) {
+    storeS(t * BK);
+    __syncthreads();
+    if (t + 1 < ks) loadS((t + 1) * BK);
+    else loadF(0);
+    __builtin_amdgcn_sched_barrier(0);
+    mma();
+    __syncthreads();
+  }
+  for (int t = 0; t < BR / BK; ++t) {
+    storeF(t * BK);
+    __syncthreads();
+    if (t + 1 < BR / BK) loadF((t + 1) * BK);
+    __builtin_amdgcn_sched_barrier(0);
+    mma();
     __syncthreads();
   }
   // D[i][j] of a 32 x 32 tile: lane j + 32 ((i / 4) % 2), register (i / 8) 4 + i % 4
@@ -225,11 +286,12 @@ hs_grad_kernel(const float* __restrict__ S, int64_t lds, const float* __restrict
 #pragma unroll
     for (int y = 0; y < TN; ++y) {
       const int j = wn * (BN / WN) + 32 * y + l32;
+      const float aj = kept(j) ? 0.f : alpha;
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int il = (e >> 2) * 8 + half * 4 + (e & 3);
         const int64_t gi = i0 + wm * (BM / WM) + 32 * x + il;
-        if (gi < N && j < r) gout[gi * r + j] = acc[x][y][e];
+        if (gi < N && j < r) gout[gi * r + j] = acc[x][y][e] - aj;
       }
     }
 }
@@ -248,90 +310,142 @@ __device__ __forceinline__ float quad_bcast_b(float v, int src) {
 }
 
 // ------------------------------------------------------------------- sweep
-// One quad of lanes per row, components interleaved over the quad: lane q owns
-// components 4 u + q (u = 0..31), so that after component j the components
-// still to come (> j) are spread over all four lanes.  At step j the owner lane
-// (j % 4) forms the new f_j and the change d goes to the quad; every lane then
-// takes g -= d G[j][.] for its slots u >= 4 floor(j / 16) (the slots below hold
-// components <= j, whose gradients are never read again).  G is staged in LDS
-// permuted, Gq[j][q][u] = G[j][4 u + q], so those reads are 16-byte loads.  A
-// workgroup sweeps the 64-row tiles blockIdx.x, blockIdx.x + gridDim.x, ...;
-// the rows of its next tile are loaded while the current one is swept.
-template <bool PLAIN>   // alpha = beta = 0: the plain rule
+// The sweep j = 1..r of one row as a forward substitution with a ReLU: with the
+// gradient kernel's a_l = (S C)_l - sum_{i > l} f_i G_il - alpha, the rule
+// f_l <- [(f_l G_ll + g_l - alpha) / (G_ll + beta)]_+ (Sec 4.1; the plain rule
+// at alpha = beta = 0) reads n_l = [(a_l - sum_{i < l} n_i G_il) rho_l]_+ with
+// rho_l = 1 / (G_ll + beta), over the new values n_i of the components before l,
+// so the old f never enters the sweep and each component needs one register.
+// The LDS copy of G holds only its strictly lower triangle (Gs[j][c] = G_cj for
+// c > j, else 0), so from step j on the register of component j keeps its
+// final a_j (every later update subtracts an exact zero) and n_j = [a_j rho_j]_+
+// is formed again when the row is stored.  A component that keeps its value
+// arrives as a_l = f_l scl_l and passes with rho = 1; its row and column of Gs
+// are zero.
+//
+// One quad of lanes per row: lane q owns components 16 u + 4 q + c (u = 0..7,
+// c = 0..3), so a row is read and written as 16-byte pieces, a lane's slice of a
+// row of Gs is one 16-byte LDS load per 16 components, and after component j
+// the components still to come are spread evenly over the quad (all four lanes
+// skip the blocks u < floor(j / 16)).  At step j the owner lane ((j / 4) % 4)
+// forms n_j and the quad receives it by DPP.  A quad sweeps R rows at once
+// (rows t, t + 64, ... of a 64 R-row tile): they share every read of Gs, and
+// the reads of step j + 1 are in flight during step j.  A workgroup sweeps the
+// tiles blockIdx.x, blockIdx.x + gridDim.x, ...
+template <int R>
 __global__ void __launch_bounds__(256)
-hs_sweep_kernel(const float* __restrict__ gin, const float* __restrict__ Gp, const float* __restrict__ rdiag,
-                const float* __restrict__ scl, float* __restrict__ F, int64_t N, int r, float alpha, float beta) {
-  constexpr int RQ = BR / 4;
-  __shared__ __attribute__((aligned(16))) float Gq[BR * BR];
-  __shared__ float rd[BR], gjj[BR], sc[BR];
-  for (int e = threadIdx.x; e < BR * BR; e += 256) {
-    const int j = e / BR, c = e % BR;          // c = 4 u + q  ->  Gq[j][q][u]
-    Gq[j * BR + (c & 3) * RQ + (c >> 2)] = Gp[e];
-  }
+hs_sweep_kernel(const float* __restrict__ ain, const float* __restrict__ Gp, const float* __restrict__ rdiag,
+                float* __restrict__ F, int64_t N, int r) {
+  constexpr int RQ = BR / 4;   // slots per lane
+  // rho first: its reads then take immediate LDS offsets
+  __shared__ __attribute__((aligned(16))) float sm[BR + BR * BR];
+  float* rho = sm;
+  float* Gs = sm + BR;
   if (threadIdx.x < BR) {
-    rd[threadIdx.x] = rdiag[threadIdx.x];
-    gjj[threadIdx.x] = Gp[threadIdx.x * BR + threadIdx.x];
-    sc[threadIdx.x] = scl[threadIdx.x];
+    const float d = rdiag[threadIdx.x];
+    rho[threadIdx.x] = d == 0.f ? 1.f : d;
+  }
+  for (int e = threadIdx.x; e < BR * BR; e += 256) {
+    const int j = e / BR, c = e % BR;
+    Gs[e] = (c > j && rdiag[j] != 0.f && rdiag[c] != 0.f) ? Gp[e] : 0.f;   // G is symmetric
   }
   __syncthreads();
-  const int q = threadIdx.x & 3, rl = threadIdx.x >> 2;
-  const int64_t ntiles = ceil_div(N, 64);
-  float f[RQ], g[RQ], fx[RQ], gx[RQ];
-  auto load = [&](int64_t tile, float* fo, float* go) {
-    const int64_t row = tile * 64 + rl;
+  const int q = threadIdx.x & 3, ql = threadIdx.x >> 2;
+  const bool vec = (r & 3) == 0;
+  const int64_t ntiles = ceil_div(N, 64 * R);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // slot 4 u + c of a row holds component 16 u + 4 q + c
+    float a[R][RQ];
+    // unconditional loads (guarded ones would serialise on their waits): a row
+    // past N reads row N - 1 and is never stored (rows are independent); a
+    // component past r reads as zero
+    if (vec) {
 #pragma unroll
-    for (int u = 0; u < RQ; ++u) {
-      fo[u] = 0.f;
-      go[u] = 0.f;
-    }
-    if (tile < ntiles && row < N) {
-      const float* fr = F + row * r;
-      const float* gr = gin + row * r;
+      for (int p = 0; p < R; ++p) {
+        const int64_t row = std::min<int64_t>(tile * 64 * R + 64 * p + ql, N - 1);
 #pragma unroll
-      for (int u = 0; u < RQ; ++u) {
-        const int c = 4 * u + q;
-        if (c < r) {
-          fo[u] = fr[c];
-          go[u] = gr[c];
+        for (int u = 0; u < RQ / 4; ++u) {
+          const int c0 = 16 * u + 4 * q;
+          const bool ok = c0 < r;
+          const f32x4 v = *(const f32x4*)(ain + row * r + (ok ? c0 : 0));
+#pragma unroll
+          for (int c = 0; c < 4; ++c) a[p][4 * u + c] = ok ? v[c] : 0.f;
         }
       }
-    }
-  };
-  load(blockIdx.x, fx, gx);
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int64_t row = tile * 64 + rl;
+    } else {
 #pragma unroll
-    for (int u = 0; u < RQ; ++u) {
-      f[u] = fx[u] * sc[4 * u + q];
-      g[u] = gx[u];
+      for (int p = 0; p < R; ++p) {
+        const int64_t row = std::min<int64_t>(tile * 64 * R + 64 * p + ql, N - 1);
+#pragma unroll
+        for (int u = 0; u < RQ / 4; ++u)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int cc = 16 * u + 4 * q + c;
+            const bool ok = cc < r;
+            const float v = ain[row * r + (ok ? cc : 0)];
+            a[p][4 * u + c] = ok ? v : 0.f;
+          }
+      }
     }
-    load(tile + gridDim.x, fx, gx);            // in flight during the sweep
+    f32x4 gb[2][RQ / 4];
+    float rb[2];
+    auto gload = [&](int j, int b) {
+      rb[b] = rho[j];
+#pragma unroll
+      for (int u = j >> 4; u < RQ / 4; ++u) gb[b][u] = *(const f32x4*)(Gs + j * BR + 16 * u + 4 * q);
+    };
+    gload(0, 0);
     // fully unrolled: every register index below is a compile-time constant
 #pragma clang loop unroll(full)
     for (int j = 0; j < BR; ++j) {
-      // no branch: a component with 1/(G_jj + beta) = 0 keeps f_j, so its d is 0
-      const float rdj = rd[j];
-      const int t = j >> 2;
-      const float v = PLAIN ? f[t] + g[t] * rdj : (f[t] * gjj[j] + g[t] - alpha) * rdj;
-      const float fn = rdj > 0.f ? (v > 0.f ? v : 0.f) : f[t];
-      const float d = quad_bcast_b(fn - f[t], j & 3);
-      if (q == (j & 3)) f[t] = fn;
-      const float* gr = Gq + j * BR + q * RQ;
+      const int b = j & 1, qj = (j >> 2) & 3, sj = 4 * (j >> 4) + (j & 3);
+      if (j + 1 < BR) gload(j + 1, b ^ 1);
+      float nb[R];
 #pragma unroll
-      for (int u = 4 * (j >> 4); u < RQ; u += 4) {
-        const f32x4 gv = *(const f32x4*)(gr + u);
-        g[u] -= d * gv[0];
-        g[u + 1] -= d * gv[1];
-        g[u + 2] -= d * gv[2];
-        g[u + 3] -= d * gv[3];
+      for (int p = 0; p < R; ++p) {
+        const float v = a[p][sj] * rb[b];
+        nb[p] = quad_bcast_b(v > 0.f ? v : 0.f, qj);
       }
-      __builtin_amdgcn_sched_barrier(0);   // keep each step's loads with it (register pressure)
-    }
-    if (row < N) {
 #pragma unroll
-      for (int u = 0; u < RQ; ++u) {
-        const int c = 4 * u + q;
-        if (c < r) F[row * r + c] = f[u];
+      for (int u = j >> 4; u < RQ / 4; ++u)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int p = 0; p < R; ++p) a[p][4 * u + c] -= nb[p] * gb[b][u][c];
+      if ((j & 15) == 15) {   // block j / 16 is final: pin it here rather than let its last updates sink to the store
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+          for (int p = 0; p < R; ++p) asm volatile("" : "+v"(a[p][4 * (j >> 4) + c]));
+      }
+      __builtin_amdgcn_sched_barrier(0);   // keep each step's work together (register pressure)
+    }
+#pragma unroll
+    for (int u = 0; u < RQ / 4; ++u) {
+      const f32x4 rv = *(const f32x4*)(rho + 16 * u + 4 * q);
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int p = 0; p < R; ++p) {
+          const float v = a[p][4 * u + c] * rv[c];
+          a[p][4 * u + c] = v > 0.f ? v : 0.f;
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < R; ++p) {
+      const int64_t row = tile * 64 * R + 64 * p + ql;
+      if (row >= N) continue;
+      float* fr = F + row * r;
+#pragma unroll
+      for (int u = 0; u < RQ / 4; ++u) {
+        const int c0 = 16 * u + 4 * q;
+        if (vec) {
+          if (c0 < r) *(f32x4*)(fr + c0) = (f32x4){a[p][4 * u], a[p][4 * u + 1], a[p][4 * u + 2], a[p][4 * u + 3]};
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            if (c0 + c < r) fr[c0 + c] = a[p][4 * u + c];
+        }
       }
     }
   }
@@ -339,21 +453,21 @@ hs_sweep_kernel(const float* __restrict__ gin, const float* __restrict__ Gp, con
 
 // ------------------------------------------------------------------- qtf
 // Workgroup partial Qb^T (F diag(sc)) (kp x r) and column sums of its squares,
-// over the 64-row tiles blockIdx.x, blockIdx.x + gridDim.x, ...  The tiles of
+// over the TRW-row tiles blockIdx.x, blockIdx.x + gridDim.x, ...  The tiles of
 // Qb and F are staged in LDS; v_mfma_f32_32x32x2_f32 with A[c][i] = Qb[i][c] and
 // B[i][j] = F[i][j], contraction over the tile's rows.  Wave w owns the 32-row
 // blocks c of its quarter and all four 32-column blocks j.
-template <int KPMAX>
+template <int KPMAX, int TRW, bool FVEC>   // FVEC: rows of F are 16-byte aligned (r % 4 == 0)
 __global__ void __launch_bounds__(256)
 hs_qtf_kernel(const float* __restrict__ Qb, int64_t ldq, const float* __restrict__ F, const float* __restrict__ scale,
               int64_t N, int kp, int r, float* __restrict__ part) {
-  constexpr int TRW = 64, QROW = KPMAX + 4, FROW = BR + 4;
+  constexpr int QROW = KPMAX + 4, FROW = BR + 4;
   constexpr int NTM = KPMAX / 32 / 4;       // 32-row blocks of the output per wave
   constexpr int QV = TRW * KPMAX / 4 / 256; // float4 of Qb per thread
-  constexpr int FE = TRW * BR / 256;        // F elements per thread
+  constexpr int FV = TRW * BR / 4 / 256;    // float4 of F per thread
   __shared__ __attribute__((aligned(16))) float Qs[TRW * QROW];
   __shared__ __attribute__((aligned(16))) float Fs[TRW * FROW];
-  __shared__ float sc[BR];
+  __shared__ __attribute__((aligned(16))) float sc[BR];
   __shared__ float csum[2][BR];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (tid < BR) sc[tid] = (scale && tid < r) ? scale[tid] : 1.f;
@@ -370,32 +484,50 @@ hs_qtf_kernel(const float* __restrict__ Qb, int64_t ldq, const float* __restrict
   const int half = lane >> 5, l32 = lane & 31;
   // the next tile is loaded into registers while the current one is used
   f32x4 qv[QV];
-  float fv[FE];
+  f32x4 fv[FV];
   auto load = [&](int64_t tile) {
     const int64_t row0 = tile * TRW;
+    if (tile >= ntiles) return;
+    // unconditional loads from clamped addresses (guarded loads would serialise
+    // on their waits); the tile is masked when it is stored
 #pragma unroll
     for (int p = 0; p < QV; ++p) {
       const int e = tid + 256 * p, i = e / (KPMAX / 4), c4 = e % (KPMAX / 4);
-      qv[p] = (tile < ntiles && row0 + i < N && 4 * c4 < kp) ? *(const f32x4*)(Qb + (row0 + i) * ldq + 4 * c4) : z4;
+      const bool ok = row0 + i < N && 4 * c4 < kp;
+      qv[p] = *(const f32x4*)(Qb + (ok ? (row0 + i) * ldq + 4 * c4 : 0));
     }
 #pragma unroll
-    for (int p = 0; p < FE; ++p) {
-      const int e = tid + 256 * p, i = e / BR, j = e % BR;
-      fv[p] = (tile < ntiles && row0 + i < N && j < r) ? F[(row0 + i) * r + j] : 0.f;   // padding is zero
+    for (int p = 0; p < FV; ++p) {
+      const int e = tid + 256 * p, i = e / (BR / 4), j = 4 * (e % (BR / 4));
+      const bool ok = row0 + i < N;
+      if (FVEC) {
+        fv[p] = *(const f32x4*)(F + ((ok && j < r) ? (row0 + i) * r + j : 0));
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) fv[p][c] = F[(ok && j + c < r) ? (row0 + i) * r + j + c : 0];
+      }
     }
   };
   __syncthreads();
   load(blockIdx.x);
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t row0 = tile * TRW;
 #pragma unroll
     for (int p = 0; p < QV; ++p) {
       const int e = tid + 256 * p, i = e / (KPMAX / 4), c4 = e % (KPMAX / 4);
-      *(f32x4*)(Qs + i * QROW + 4 * c4) = qv[p];
+      *(f32x4*)(Qs + i * QROW + 4 * c4) = (row0 + i < N && 4 * c4 < kp) ? qv[p] : z4;
     }
 #pragma unroll
-    for (int p = 0; p < FE; ++p) {
-      const int e = tid + 256 * p, i = e / BR, j = e % BR;
-      Fs[i * FROW + j] = fv[p] * sc[j];
+    for (int p = 0; p < FV; ++p) {   // padding is zero
+      const int e = tid + 256 * p, i = e / (BR / 4), j = 4 * (e % (BR / 4));
+      const f32x4 sv = *(const f32x4*)(sc + j);
+      f32x4 v;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const float x = fv[p][c] * sv[c];
+        v[c] = (row0 + i < N && j + c < r) ? x : 0.f;
+      }
+      *(f32x4*)(Fs + i * FROW + j) = v;
     }
     __syncthreads();
     load(tile + gridDim.x);
@@ -408,18 +540,25 @@ hs_qtf_kernel(const float* __restrict__ Qb, int64_t ldq, const float* __restrict
       }
       colsq += sq;
     }
-#pragma unroll 2
-    for (int k = 0; k < TRW; k += 2) {
+    // the operands of step k + 2 are read from LDS while the MFMAs of step k run
+    float av[2][NTM], bv[2][4];
+    auto frag = [&](int k, int b) {
       const int i = k + half;
-      float av[NTM], bv[4];
 #pragma unroll
-      for (int x = 0; x < NTM; ++x) av[x] = Qs[i * QROW + 32 * (wave * NTM + x) + l32];
+      for (int x = 0; x < NTM; ++x) av[b][x] = Qs[i * QROW + 32 * (wave * NTM + x) + l32];
 #pragma unroll
-      for (int y = 0; y < 4; ++y) bv[y] = Fs[i * FROW + 32 * y + l32];
+      for (int y = 0; y < 4; ++y) bv[b][y] = Fs[i * FROW + 32 * y + l32];
+    };
+    frag(0, 0);
+#pragma clang loop unroll(full)
+    for (int k = 0; k < TRW; k += 2) {
+      const int b = (k >> 1) & 1;
+      if (k + 2 < TRW) frag(k + 2, b ^ 1);
 #pragma unroll
       for (int x = 0; x < NTM; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[x], bv[y], acc[x][y], 0, 0, 0);
+        for (int y = 0; y < 4; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[b][x], bv[b][y], acc[x][y], 0, 0, 0);
     }
     __syncthreads();
   }
@@ -460,29 +599,56 @@ hipError_t launch_halfstep_big(const HalfStepArgs& a, int do_sweep, hipStream_t 
     hipLaunchKernelGGL(hs_prep_kernel, dim3(BNB, BNB), dim3(256), 0, st, a, Cp, Gp, rdiag, scl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (a.N >= 128 * 512)
-      hipLaunchKernelGGL(hs_grad_kernel<128>, dim3((unsigned)ceil_div(a.N, 128)), dim3(256), 0, st, a.S, a.lds, a.F,
-                         scl, Cp, Gp, a.gbuf, a.N, a.kp, a.r);
-    else
-      hipLaunchKernelGGL(hs_grad_kernel<64>, dim3((unsigned)ceil_div(a.N, 64)), dim3(256), 0, st, a.S, a.lds, a.F,
-                         scl, Cp, Gp, a.gbuf, a.N, a.kp, a.r);
+    const bool fv = (a.r & 3) == 0;
+    const dim3 g128((unsigned)ceil_div(a.N, 128)), g64((unsigned)ceil_div(a.N, 64));
+    if (a.N >= 128 * 512) {
+      if (fv)
+        hipLaunchKernelGGL((hs_grad_kernel<128, true>), g128, dim3(256), 0, st, a.S, a.lds, a.F, scl, Cp, Gp, rdiag,
+                           a.alpha, a.gbuf, a.N, a.kp, a.r);
+      else
+        hipLaunchKernelGGL((hs_grad_kernel<128, false>), g128, dim3(256), 0, st, a.S, a.lds, a.F, scl, Cp, Gp, rdiag,
+                           a.alpha, a.gbuf, a.N, a.kp, a.r);
+    } else {
+      if (fv)
+        hipLaunchKernelGGL((hs_grad_kernel<64, true>), g64, dim3(256), 0, st, a.S, a.lds, a.F, scl, Cp, Gp, rdiag,
+                           a.alpha, a.gbuf, a.N, a.kp, a.r);
+      else
+        hipLaunchKernelGGL((hs_grad_kernel<64, false>), g64, dim3(256), 0, st, a.S, a.lds, a.F, scl, Cp, Gp, rdiag,
+                           a.alpha, a.gbuf, a.N, a.kp, a.r);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (a.alpha == 0.f && a.beta == 0.f)
-      hipLaunchKernelGGL(hs_sweep_kernel<true>, dim3((unsigned)nblk), dim3(256), 0, st, a.gbuf, Gp, rdiag, scl, a.F,
-                         a.N, a.r, a.alpha, a.beta);
+    // 64 R-row tiles; at most two workgroups per CU are resident (LDS), so at
+    // most 512 loop over the tiles.  R = 4 rows per quad for tall sides, fewer
+    // where that would leave CUs idle.
+    const int R = a.N >= 131072 ? 4 : (a.N >= 32768 ? 2 : 1);
+    const unsigned sblk = (unsigned)std::min<int64_t>(ceil_div(a.N, 64 * R), 512);
+    if (R == 4)
+      hipLaunchKernelGGL(hs_sweep_kernel<4>, dim3(sblk), dim3(256), 0, st, a.gbuf, Gp, rdiag, a.F, a.N, a.r);
+    else if (R == 2)
+      hipLaunchKernelGGL(hs_sweep_kernel<2>, dim3(sblk), dim3(256), 0, st, a.gbuf, Gp, rdiag, a.F, a.N, a.r);
     else
-      hipLaunchKernelGGL(hs_sweep_kernel<false>, dim3((unsigned)nblk), dim3(256), 0, st, a.gbuf, Gp, rdiag, scl,
-                         a.F, a.N, a.r, a.alpha, a.beta);
+      hipLaunchKernelGGL(hs_sweep_kernel<1>, dim3(sblk), dim3(256), 0, st, a.gbuf, Gp, rdiag, a.F, a.N, a.r);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   // after a sweep F is final; without one its pending column scales apply on load
   const float* qscale = do_sweep ? nullptr : a.scale;
-  if (a.kp <= 128)
-    hipLaunchKernelGGL(hs_qtf_kernel<128>, dim3((unsigned)nblk), dim3(256), 0, st, a.Qb, a.ldq, a.F, qscale, a.N,
-                       a.kp, a.r, a.part);
-  else
-    hipLaunchKernelGGL(hs_qtf_kernel<256>, dim3((unsigned)nblk), dim3(256), 0, st, a.Qb, a.ldq, a.F, qscale, a.N,
-                       a.kp, a.r, a.part);
+  const bool fv = (a.r & 3) == 0;
+  const dim3 qg((unsigned)nblk);
+  if (a.kp <= 128) {
+    if (fv)
+      hipLaunchKernelGGL((hs_qtf_kernel<128, 64, true>), qg, dim3(256), 0, st, a.Qb, a.ldq, a.F, qscale, a.N, a.kp,
+                         a.r, a.part);
+    else
+      hipLaunchKernelGGL((hs_qtf_kernel<128, 64, false>), qg, dim3(256), 0, st, a.Qb, a.ldq, a.F, qscale, a.N, a.kp,
+                         a.r, a.part);
+  } else {
+    if (fv)
+      hipLaunchKernelGGL((hs_qtf_kernel<256, 32, true>), qg, dim3(256), 0, st, a.Qb, a.ldq, a.F, qscale, a.N, a.kp,
+                         a.r, a.part);
+    else
+      hipLaunchKernelGGL((hs_qtf_kernel<256, 32, false>), qg, dim3(256), 0, st, a.Qb, a.ldq, a.F, qscale, a.N, a.kp,
+                         a.r, a.part);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_sum_partials_f32(a.part, nblk, (int64_t)a.kp * a.r + a.r, a.acc_out, st);
