@@ -82,23 +82,30 @@ class RowPanels:
     the panels, in ascending order, of float64(X_p)^T B_p.  The values are those
     of the whole FP64 products up to the order of the FP64 sums."""
 
-    def __init__(self, X, panel=8192):
+    def __init__(self, X, panel=8192, transform=None):
         self.data = X
         self.shape = X.shape
         self.panel = panel
+        self.transform = transform   # applied to each FP32 panel before its product
+
+    def _panel(self, i):
+        P = np.asarray(self.data[i:i + self.panel])
+        if self.transform is not None:
+            P = self.transform(P)
+        return np.asarray(P, dtype=np.float64)
 
     def matmul(self, B):
         B = np.asarray(B, dtype=np.float64)
         out = np.empty((self.shape[0], B.shape[1]))
         for i in range(0, self.shape[0], self.panel):
-            out[i:i + self.panel] = np.asarray(self.data[i:i + self.panel], dtype=np.float64) @ B
+            out[i:i + self.panel] = self._panel(i) @ B
         return out
 
     def tmatmul(self, B):
         B = np.asarray(B, dtype=np.float64)
         out = np.zeros((self.shape[1], B.shape[1]))
         for i in range(0, self.shape[0], self.panel):
-            out += np.asarray(self.data[i:i + self.panel], dtype=np.float64).T @ B[i:i + self.panel]
+            out += self._panel(i).T @ B[i:i + self.panel]
         return out
 
     def _split(self, i):
@@ -128,18 +135,12 @@ class RowPanels:
         return out
 
     def quantised(self, fmt):
-        """The data as stored for the low-precision products (quantize_data per
-        panel; the panels are whole 128-row tile rows), held as FP32 (exact)."""
-        import concurrent.futures
+        """The data as stored for the low-precision products: quantize_data of
+        each panel (the panels are whole 128-row tile rows, so the values are
+        those of the whole matrix), formed inside each product rather than held."""
         assert self.panel % 128 == 0
-        Q = np.empty(self.shape, dtype=np.float32)
-
-        def one(i):
-            Q[i:i + self.panel] = quantize_data(np.asarray(self.data[i:i + self.panel]), fmt)
-
-        with concurrent.futures.ThreadPoolExecutor(8) as ex:   # panels are independent
-            list(ex.map(one, range(0, self.shape[0], self.panel)))
-        return RowPanels(Q, self.panel)
+        assert self.transform is None
+        return RowPanels(self.data, self.panel, transform=lambda P: quantize_data(P, fmt))
 
 
 def _subspace_iteration(fwd, adj, Omega, q, orth):

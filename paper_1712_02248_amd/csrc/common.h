@@ -76,7 +76,7 @@ hipError_t launch_prep_bt(const float* B, int64_t ldb, int64_t K, int64_t N, uin
 // (splits x M x N), summed in fixed order.  sq (at = 0): FP64 sum of squares of X
 // per workgroup, gemm_split_sq_parts() values.
 int gemm_split_pick_splits(int64_t M, int64_t N, int64_t K);
-int gemm_split_sq_parts(int64_t M, int splits);
+int gemm_split_sq_parts(int64_t M, int64_t N, int splits);
 hipError_t launch_gemm_split(const float* X, int64_t ldx, int at, const uint16_t* BtH, const uint16_t* BtL,
                              int64_t ldbt, float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, int splits,
                              float* part, hipStream_t st, double* sq = nullptr);

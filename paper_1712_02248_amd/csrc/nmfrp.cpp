@@ -134,7 +134,7 @@ Layout make_layout(const nmf_params* p) {
   {
     const int64_t qp = quant_sq_parts(m, n, round_up(n, 128), round_up(m, 128));
     const int64_t gp3 = gemm_f32_sq_parts(m, k, n, 64);
-    const int64_t gp4 = gemm_split_sq_parts(m, gemm_split_pick_splits(m, k, n));
+    const int64_t gp4 = gemm_split_sq_parts(m, k, gemm_split_pick_splits(m, k, n));
     L.xsq_part = pl.take((size_t)std::max(qp, std::max(gp3, gp4)) * d);
   }
   L.Xq = L.XqT = L.Ex = L.Bt = L.Eb = L.Bt2 = L.Eb2 = 0;
@@ -572,7 +572,7 @@ nmf_status nmf_compress(nmf_ctx* c, const float* X, int64_t ldx, const float* om
       hipError_t e = launch_prep_bt(QR, L.KP, n, k, H, Lo, L.ldq, cr.st);
       if (!e) e = launch_gemm_split(X, ldx, 0, H, Lo, L.ldq, Xc, L.KP, m, k, n, s, cr.gemm_part, cr.st, sqp);
       if (e || xsq_quant) return e;
-      return launch_sum_partials_f64(sqp, gemm_split_sq_parts(m, s), 1, c->at<double>(L.proxy_out) + 2, nullptr,
+      return launch_sum_partials_f64(sqp, gemm_split_sq_parts(m, k, s), 1, c->at<double>(L.proxy_out) + 2, nullptr,
                                      cr.st);
     }, nullptr});
   } else {

@@ -919,88 +919,113 @@ apply_rinv_kernel(float* __restrict__ Y, int64_t ldy, int64_t rows, int k,
 }
 
 // Q = Y R^{-1} in place for wide bases (64 < k <= KMAX): a workgroup owns 64
-// rows and all k columns (the tile is read into LDS before any write); R^{-1}
-// goes through LDS in chunks of 32 rows (FP64), the next chunk loaded into
-// registers while the current one is used.  Wave w owns output columns
-// w KMAX/4 .. +KMAX/4 - 1 and all 64 rows: 4 x (KMAX/64) blocks of 16 x 16 on
-// v_mfma_f64_16x16x4_f64 (A[i][kk] = Y[i][kk], B[kk][j] = R^{-1}[kk][j]; D[i][j]
-// in lane j + 16 (i % 4), register i / 4).  R^{-1} is upper triangular, so a
-// chunk that starts at row c0 skips the blocks of columns below c0.
+// rows and all k columns (the tile is read into LDS before any write, 66 KB:
+// two workgroups per CU).  Each wave owns four (KMAX 256) or two (KMAX 128)
+// 16-column blocks of the output, {w, 7 - w, 8 + w, 15 - w}, which balances
+// the work of the upper-triangular R^{-1} over the waves, and all 64 rows:
+// v_mfma_f64_16x16x4_f64 with A[i][kk] = Y[i][kk] from LDS and B[kk][j] =
+// R^{-1}[kk][j] read by the wave straight from global memory (no other wave
+// uses its columns; R^{-1} stays in L2), two k-steps ahead in registers.
+// D[i][j] lies in lane j + 16 (i % 4), register i / 4.  A block b only takes
+// the k-steps 4 s <= 16 b + 15 (R^{-1} is zero below its diagonal).  Loads are
+// unconditional from clamped addresses, values outside k x k zeroed after.
 template <int KMAX>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))   // two workgroups per CU
 apply_rinv_wide_kernel(float* __restrict__ Y, int64_t ldy, int64_t rows, int k, const double* __restrict__ Rinv,
                        const int* __restrict__ status, int attempt) {
   if (status[1] != 0) return;
   if (attempt == 1 && status[3] != 0) return;   // second pass not needed
   if (attempt == 2 && status[0] == 0) return;
-  constexpr int CK = 32, YROW = KMAX + 4, RROW = KMAX + 2;
-  constexpr int CT = KMAX / 64;                  // 16-column blocks per wave
+  constexpr int YROW = KMAX + 4;
+  constexpr int NBW = KMAX / 64;                 // 16-column blocks per wave
   constexpr int V4 = 64 * KMAX / 4 / 256;        // float4 of the Y tile per thread
-  constexpr int RE = CK * KMAX / 256;            // R^{-1} chunk elements per thread
+  constexpr int SC = 2;                          // k-steps per chunk (8 rows of R^{-1})
   __shared__ __attribute__((aligned(16))) float Ys[64 * YROW];
-  __shared__ double Rs[CK * RROW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, g4 = lane >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * 64;
+  {
+    f32x4 yv[V4];
 #pragma unroll
-  for (int p = 0; p < V4; ++p) {
-    const int e = tid + 256 * p, i = e / (KMAX / 4), c = 4 * (e % (KMAX / 4));
-    f32x4 v = {0.f, 0.f, 0.f, 0.f};
-    if (row0 + i < rows && c < k) {
-      v = *(const f32x4*)(Y + (row0 + i) * ldy + c);
-#pragma unroll
-      for (int d = 0; d < 4; ++d)
-        if (c + d >= k) v[d] = 0.f;              // a partial last group (k % 4 != 0)
+    for (int p = 0; p < V4; ++p) {
+      const int e = tid + 256 * p, i = e / (KMAX / 4), c = 4 * (e % (KMAX / 4));
+      yv[p] = *(const f32x4*)(Y + ((row0 + i < rows && c < k) ? (row0 + i) * ldy + c : 0));
     }
-    *(f32x4*)(Ys + i * YROW + c) = v;
+#pragma unroll
+    for (int p = 0; p < V4; ++p) {
+      const int e = tid + 256 * p, i = e / (KMAX / 4), c = 4 * (e % (KMAX / 4));
+      f32x4 v;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) v[d] = (row0 + i < rows && c + d < k) ? yv[p][d] : 0.f;   // k % 4 != 0
+      *(f32x4*)(Ys + i * YROW + c) = v;
+    }
   }
-  double rv[RE];
-  auto load_chunk = [&](int c0) {
-#pragma unroll
-    for (int p = 0; p < RE; ++p) {
-      const int e = tid + 256 * p, kk = e / KMAX, j = e % KMAX;
-      rv[p] = (c0 + kk < k && j < k) ? Rinv[(int64_t)(c0 + kk) * k + j] : 0.0;
-    }
-  };
-  f64x4 acc[4][CT];
+  // this wave's blocks: b = w, 7 - w (and 8 + w, 15 - w)
+  int blk[NBW];
+  blk[0] = wave;
+  blk[1] = 7 - wave;
+  if (NBW == 4) {
+    blk[NBW > 2 ? 2 : 0] = 8 + wave;
+    blk[NBW > 3 ? 3 : 0] = 15 - wave;
+  }
+  f64x4 acc[4][NBW];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < CT; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  const int jb0 = wave * (KMAX / 4);             // first output column of this wave
-  load_chunk(0);
-  for (int c0 = 0; c0 < k; c0 += CK) {
-    __syncthreads();                             // the previous chunk is consumed (and the Y tile stored)
+    for (int b = 0; b < NBW; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  // B fragments of k-steps s0, s0 + 1: lane holds R^{-1}[4 s + g4][16 blk + l16]
+  double bq0[SC][NBW], bq1[SC][NBW];
+  auto loadb = [&](double (*bq)[NBW], int s0) {
 #pragma unroll
-    for (int p = 0; p < RE; ++p) {
-      const int e = tid + 256 * p, kk = e / KMAX, j = e % KMAX;
-      Rs[kk * RROW + j] = rv[p];
-    }
-    __syncthreads();
-    if (c0 + CK < k) load_chunk(c0 + CK);
+    for (int u = 0; u < SC; ++u)
 #pragma unroll
-    for (int s = 0; s < CK / 4; ++s) {
-      const int kk = 4 * s + g4;
+      for (int b = 0; b < NBW; ++b) {
+        const int kr = 4 * (s0 + u) + g4, j = 16 * blk[b] + l16;
+        bq[u][b] = Rinv[(kr < k && j < k) ? (int64_t)kr * k + j : 0];
+      }
+  };
+  auto chunk = [&](double (*bq)[NBW], int s0) {
+#pragma unroll
+    for (int u = 0; u < SC; ++u) {
+      const int s = s0 + u;
       double av[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = (double)Ys[(16 * a + l16) * YROW + c0 + kk];
+      for (int a = 0; a < 4; ++a) av[a] = (double)Ys[(16 * a + l16) * YROW + 4 * s + g4];
 #pragma unroll
-      for (int b = 0; b < CT; ++b) {
-        if (jb0 + 16 * b + 15 < c0) continue;    // R^{-1} rows >= c0 are zero in these columns (uniform)
-        const double bv = Rs[kk * RROW + jb0 + 16 * b + l16];
+      for (int b = 0; b < NBW; ++b) {
+        if (s > 4 * blk[b] + 3) continue;        // rows below block b's diagonal (uniform)
+        const int kr = 4 * s + g4, j = 16 * blk[b] + l16;
+        const double bv = (kr < k && j < k) ? bq[u][b] : 0.0;
 #pragma unroll
         for (int a = 0; a < 4; ++a) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv, acc[a][b], 0, 0, 0);
       }
     }
+  };
+  // the last k-step any block of this wave needs
+  int smax = 0;
+#pragma unroll
+  for (int b = 0; b < NBW; ++b) smax = max(smax, 4 * blk[b] + 4);
+  loadb(bq0, 0);
+  __syncthreads();                               // the Y tile is in LDS
+  for (int s0 = 0; s0 < smax; s0 += 2 * SC) {
+    if (s0 + SC < smax) loadb(bq1, s0 + SC);
+    __builtin_amdgcn_sched_barrier(0);           // the next chunk's loads stay ahead of the MFMAs
+    chunk(bq0, s0);
+    if (s0 + SC < smax) {
+      if (s0 + 2 * SC < smax) loadb(bq0, s0 + 2 * SC);
+      __builtin_amdgcn_sched_barrier(0);
+      chunk(bq1, s0 + SC);
+    }
   }
+  __syncthreads();                               // every wave has read the whole tile
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < CT; ++b)
+    for (int b = 0; b < NBW; ++b)
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
         const int64_t gi = row0 + 16 * a + 4 * x + g4;
-        const int j = jb0 + 16 * b + l16;
+        const int j = 16 * blk[b] + l16;
         if (gi < rows && j < k) Y[gi * ldy + j] = (float)acc[a][b][x];
       }
 }

@@ -55,14 +55,31 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
   const bool vec = (ldx % 4 == 0) && (((uintptr_t)X & 15) == 0);   // float4 loads of X
 
   // B fragments (rows of W diag(sw) owned by this wave), kept for all tiles
+  // (all loads issued first, unconditionally from clamped addresses, and
+  // converted after: guarded loads serialise on their waits)
   T wfr[NB][KS];
+  {
+    float wv[NB][KS], sv[KS];
+    const float* swp = sw ? sw : W;   // a valid address either way
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    const int64_t gi = row0 + wave * RPW + nb * 16 + (lane & 15);
+    for (int s = 0; s < KS; ++s) sv[s] = swp[4 * s + (lane >> 4) < r ? 4 * s + (lane >> 4) : 0];
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int k = 4 * s + (lane >> 4);
-      wfr[nb][s] = (gi < m && k < r) ? (T)W[gi * r + k] * (T)(sw ? sw[k] : 1.f) : (T)0;
+    for (int nb = 0; nb < NB; ++nb) {
+      const int64_t gi = row0 + wave * RPW + nb * 16 + (lane & 15);
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int k = 4 * s + (lane >> 4);
+        wv[nb][s] = W[(gi < m && k < r) ? gi * r + k : 0];
+      }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int64_t gi = row0 + wave * RPW + nb * 16 + (lane & 15);
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int k = 4 * s + (lane >> 4);
+        wfr[nb][s] = (gi < m && k < r) ? (T)wv[nb][s] * (T)(sw ? sv[s] : 1.f) : (T)0;
+      }
     }
   }
   // FP64: Ht rows in the order c(j) = 4 (j % 4) + j / 4; FP32: natural order
@@ -70,7 +87,9 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
   // Software pipeline over the 64-column tiles of this row strip: the loads of
   // tile t+1 are issued (Ht first, then X) before the MFMAs of tile t, so each
   // wait only covers loads issued one tile earlier.  n % 4 == 0, so a group of
-  // four columns is either inside or outside.
+  // four columns is either inside or outside.  Loads are unconditional from
+  // clamped addresses and out-of-range values are zeroed when the tile is used
+  // (guarded loads become exec-masked blocks whose waits serialise them).
   float hv[HPT];
   f32x4 xv[NB][4];
   const f32x4 z4 = {0.f, 0.f, 0.f, 0.f};
@@ -78,7 +97,7 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
 #pragma unroll
     for (int p = 0; p < HPT; ++p) {
       const int e = tid + 256 * p, jj = e / RMAX, k = e % RMAX;
-      hv[p] = (c0 + jj < n && k < r) ? Ht[(c0 + jj) * r + k] : 0.f;
+      hv[p] = Ht[(c0 + jj < n && k < r) ? (c0 + jj) * r + k : 0];
     }
   };
   auto load_x = [&](int64_t c0) {
@@ -88,13 +107,9 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
       for (int sub = 0; sub < 4; ++sub) {
         const int64_t gi = row0 + wave * RPW + nb * 16 + (lane & 15);
         const int64_t gj = c0 + sub * 16 + 4 * (lane >> 4);
-        f32x4 v = z4;
-        if (gi < m && gj < n) {
-          const float* src = X + gi * ldx + gj;
-          if (vec) v = *(const f32x4*)src;
-          else v = (f32x4){src[0], src[1], src[2], src[3]};
-        }
-        xv[nb][sub] = v;
+        const float* src = X + ((gi < m && gj < n) ? gi * ldx + gj : 0);
+        if (vec) xv[nb][sub] = *(const f32x4*)src;
+        else xv[nb][sub] = (f32x4){src[0], src[1], src[2], src[3]};
       }
   };
   // workgroups start at different column tiles (rotated order) so that
@@ -106,17 +121,22 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
   load_x(col0(0));
   for (int64_t t = 0; t < ntile; ++t) {
     __syncthreads();   // readers of the previous Hs are done
+    const int64_t c0 = col0(t);
 #pragma unroll
     for (int p = 0; p < HPT; ++p) {
-      const int e = tid + 256 * p;
-      Hs[e / RMAX][e % RMAX] = (T)hv[p];
+      const int e = tid + 256 * p, jj = e / RMAX, k = e % RMAX;
+      Hs[jj][k] = (c0 + jj < n && k < r) ? (T)hv[p] : (T)0;
     }
     __syncthreads();
     f32x4 xc[NB][4];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int sub = 0; sub < 4; ++sub) xc[nb][sub] = xv[nb][sub];
+      for (int sub = 0; sub < 4; ++sub) {
+        const int64_t gi = row0 + wave * RPW + nb * 16 + (lane & 15);
+        const int64_t gj = c0 + sub * 16 + 4 * (lane >> 4);
+        xc[nb][sub] = (gi < m && gj < n) ? xv[nb][sub] : z4;
+      }
     if (t + 1 < ntile) {
       load_h(col0(t + 1));
       load_x(col0(t + 1));

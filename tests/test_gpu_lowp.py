@@ -149,7 +149,9 @@ def _padded(X):
 
 @pytest.mark.parametrize("m,n,k,at", [(1000, 300, 20, 0), (1000, 300, 64, 1), (4096, 2048, 64, 1),
                                       (4096, 2048, 64, 0), (513, 701, 37, 0), (513, 701, 37, 1),
-                                      (130, 8, 5, 1), (2, 4, 3, 0), (300, 5000, 128, 0), (20000, 64, 64, 1)])
+                                      (130, 8, 5, 1), (2, 4, 3, 0), (300, 5000, 128, 0), (20000, 64, 64, 1),
+                                      (1000, 300, 200, 0), (700, 513, 256, 1), (3001, 515, 140, 0),
+                                      (515, 3001, 250, 1), (600, 2000, 129, 1), (9000, 77, 256, 0)])
 def test_split_products(lib, m, n, k, at):
     """Split-BF16 product against the oracle's model of the same arithmetic
     (FP64 sums of the three BF16 products), within the FP32 accumulation bound,
