@@ -266,15 +266,17 @@ def time_variant(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, prec, refine,
         es.append(e)
     marker_pop(torch)
     # error right after the initialisation and after 20 iterations, then the
-    # stage split (library events) of a repeat of the last step's work
+    # stage split (library events) of a repeat of the last step's work, ending
+    # with the stopping test the fit runs (split-BF16 residual, exact near eps)
     nrej = start(count=True)
     e0 = ctx.residual(Xd)
     ctx.step(20)
     e20 = ctx.residual(Xd)
     start()
     ctx.step(its[-1])
-    e_fixed = ctx.residual(Xd)
+    ctx.residual_check(Xd, eps)
     st = ctx.stage_times()
+    e_fixed = ctx.residual(Xd)
     ctx.close()
     return dict(times=times, iters=its, e=es, e_init=e0, e_20=e20, e_fixed=e_fixed, stages=st, rejected=nrej)
 

@@ -133,14 +133,17 @@ nmf_status nmf_fasthals_step(nmf_ctx* ctx, const float* X, int64_t ldx, int32_t 
 /* Exact e = ||X - W Ht^T||_F / ||X||_F in FP64 (eq 2.2).  Synchronising. */
 nmf_status nmf_residual(nmf_ctx* ctx, const float* X, int64_t ldx, double* rel_err);
 
-/* e of eq 2.2 for a stopping test against eps: from FP32 products of W diag(sw)
- * and Ht (twice the MFMA rate of the FP64 ones, FP64 sums of squares), with
- * the bound |e32 - e| <= beta, beta = (g (1 + e32) + u' e32) / (1 - g) + r 2^-126
- * sqrt(m n) / ||X|| + 1e-12 e32, u = 2^-23, u' = u / (1 - u), g = (r + 1) u /
- * (1 - (r + 1) u), which holds for W, Ht >= 0 (the factors after any step).
- * When |e32 - eps| <= beta the side of eps is open and the exact FP64 residual
+/* e of eq 2.2 for a stopping test against eps: from split-BF16 products of
+ * W diag(sw) and Ht (v = hi + lo with hi = bf16(v), lo = bf16(v - hi); the
+ * terms hi hi + hi lo + lo hi on BF16 MFMA with FP32 accumulation, one pass over
+ * X, FP64 sums of squares), with the bound |e_s - e| <= beta,
+ * beta = (g (1 + e_s) + u' e_s) / (1 - g) + 3 KR 2^-126 sqrt(m n) / ||X|| + 1e-12 e_s,
+ * u = 2^-23, u' = u / (1 - u), g = g0 / (1 - g0),
+ * g0 = 2^-24 + 3.03 2^-16 + 1.02 (3 KR) u, KR = 64 for r <= 64 and 128 for
+ * r <= 128, which holds for W, Ht >= 0 (the factors after any step).
+ * When |e_s - eps| <= beta the side of eps is open and the exact FP64 residual
  * (nmf_residual) runs instead: *exact = 1, *bound = 0, *rel_err exact.
- * Otherwise *exact = 0, *bound = beta, *rel_err = e32, and e32 <= eps exactly
+ * Otherwise *exact = 0, *bound = beta, *rel_err = e_s, and e_s <= eps exactly
  * when e <= eps.  bound and exact may be NULL.  Synchronising. */
 nmf_status nmf_residual_check(nmf_ctx* ctx, const float* X, int64_t ldx, double eps, double* rel_err,
                               double* bound, int32_t* exact);
@@ -171,23 +174,22 @@ nmf_status nmf_sketch_spectrum(nmf_ctx* ctx, double* sigma);
 /* Runs steps in chunks, evaluating the residual after each chunk, until
  * e <= eps or max_iters iterations (the paper leaves the stopping rule open:
  * Alg 1-4).  check_every > 0: fixed chunk.  check_every == 0 after
- * nmf_compress: until the first exact residual, chunks (5 first, then 1.2
+ * nmf_compress: until the first residual, chunks (5 first, then 1.2
  * times the straight-line extrapolation of the last two proxy values, 5..50)
  * are followed by the sketch-only proxy (nmf_proxy_residual, no pass over X);
- * the first exact residual runs once the proxy is within 1 % of eps, once
+ * the first residual runs once the proxy is within 1 % of eps, once
  * the proxy stalls (not decreasing, or its extrapolation needs more than 50
  * further iterations: an offset from W's part outside range(Q_L) keeps it
- * above eps), after 100 iterations, or at max_iters (a proxy reading and an
- * exact residual it lets through share one synchronisation: the residual
- * kernel reads the proxy sums on the device and exits at once otherwise).
+ * above eps), after 100 iterations, or at max_iters (a proxy reading and a
+ * residual it lets through share one synchronisation: the residual kernel
+ * reads the proxy sums on the device and exits at once otherwise).
  * From then on every chunk ends with a residual check
  * and is 1.5 times the iterations a straight-line extrapolation of
  * the last two values needs to reach eps (5..50; by the gap to eps:
  * 50, 20, 10, 5 for more than 10 %, 1 %, 0.3 % or less when there is no
- * slope).  In this schedule a check that follows a value more than 1 % above
- * eps is nmf_residual_check's (FP32 products, and the exact FP64 residual
- * whenever the FP32 value lies within its bound of eps); the others are exact.
- * Each stop decision is that of the exact e.  Otherwise (fixed
+ * slope).  In this schedule every residual is nmf_residual_check's (split-BF16
+ * products, and the exact FP64 residual whenever that value lies within its
+ * bound of eps).  Each stop decision is that of the exact e.  Otherwise (fixed
  * chunks, or check_every == 0 after nmf_set_state, which has no ||X||^2: the
  * exact schedule above starting with e at the current factors) every check is
  * the exact residual.  max_iters == 0 only evaluates e (exactly).

@@ -169,7 +169,15 @@ hipError_t launch_proxy(const float* Xh, int64_t ldx, const float* Ht, int r, co
 hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t n, const float* W,
                            const float* sw, const float* Ht, int r, double* part, double* out,
                            unsigned* counter, hipStream_t st, const double* gate = nullptr,
-                           double gate_thr2 = 0.0, bool fp32 = false);
+                           double gate_thr2 = 0.0);
+// The same sums from split-BF16 products (stopping tests): KR = r padded (64 or
+// 128, 0 when r > 128); ws holds residual_split_halves() BF16 values (the splits
+// of W diag(sw) and Ht); fewer partials than residual_blocks().
+int residual_split_kr(int r);
+size_t residual_split_halves(int64_t m, int64_t n, int r);
+hipError_t launch_residual_split(const float* X, int64_t ldx, int64_t m, int64_t n, const float* W, const float* sw,
+                                 const float* Ht, int r, uint16_t* ws, double* part, double* out, unsigned* counter,
+                                 hipStream_t st, const double* gate = nullptr, double gate_thr2 = 0.0);
 
 // Small utilities (util.hip).
 hipError_t launch_fill_f32(float* p, int64_t count, float v, hipStream_t st);

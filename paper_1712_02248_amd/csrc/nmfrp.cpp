@@ -37,6 +37,7 @@ struct Layout {
   size_t hs_part, acc_w, acc_h, counters, Hc, GH, Wh, GW, scale_w;
   size_t hs_aux;                      // wide-factor half-steps: C, G, 1/G_jj, scales
   size_t res_part, res_out, flags, proxy_part, proxy_out, xsq_part;
+  size_t rsplit;                      // split-BF16 residual: BF16 splits of W diag(sw) and Ht
   size_t alignM, whref;               // warm start: Q_train^T Q_L (k' x k'), Q_L^T W_ref (k' x r)
   int64_t ldq, ldqt;                 // low-precision copies of X: m x ldq and n x ldqt
   size_t Xq, XqT, Ex, Bt, Eb, Bt2, Eb2;
@@ -126,6 +127,7 @@ Layout make_layout(const nmf_params* p) {
   L.hs_aux = pl.take(halfstep_big_aux_floats() * f);
   L.res_part = pl.take(2 * (size_t)residual_blocks(m, n) * d);
   L.res_out = pl.take(2 * d);
+  L.rsplit = pl.take(residual_split_halves(m, n, r) * sizeof(uint16_t));
   L.flags = pl.take(8 * sizeof(int));
   L.alignM = pl.take(L.KP * L.KP * f);
   L.whref = pl.take(L.KP * r * f);
@@ -845,11 +847,19 @@ namespace {
 // |e32 - e| <= (g (1 + e32) + u' e32) / (1 - g), plus r 2^-126 sqrt(m n) / ||X||
 // for products flushed to zero below the FP32 normal range, and 1e-12 e32 for
 // the FP64 sums.
-double fp32_residual_bound(int r, int64_t m, int64_t n, double e32, double xsq) {
+// |e_s - e| for the split-BF16 residual, W, Ht >= 0: per product the FP32
+// scaling of W (2^-24) and the split representation (v = hi + lo + d with
+// |d| <= 2^-16 |v|: the three kept terms miss at most 3.03 2^-16 |v_a v_b|), per
+// element 3 KR FP32 additions over terms whose magnitudes sum to at most
+// 1.02 sum |w h| (u = 2^-23 covers truncation as well as nearest rounding); the
+// elementwise bound g sum_k |w_ik h_jk| has norm g ||W Ht^T|| <= g (1 + e) ||X||,
+// and the subtraction X - P adds u' e.
+double split_residual_bound(int KR, int64_t m, int64_t n, double es, double xsq) {
   const double u = std::ldexp(1.0, -23), up = u / (1.0 - u);
-  const double g = (r + 1) * u / (1.0 - (r + 1) * u);
-  double b = (g * (1.0 + e32) + up * e32) / (1.0 - g) + 1e-12 * e32;
-  if (xsq > 0) b += r * std::ldexp(1.0, -126) * std::sqrt((double)m * (double)n) / std::sqrt(xsq);
+  const double g0 = std::ldexp(1.0, -24) + 3.03 * std::ldexp(1.0, -16) + 1.02 * 3 * KR * u;
+  const double g = g0 / (1.0 - g0);
+  double b = (g * (1.0 + es) + up * es) / (1.0 - g) + 1e-12 * es;
+  if (xsq > 0) b += 3 * KR * std::ldexp(1.0, -126) * std::sqrt((double)m * (double)n) / std::sqrt(xsq);
   return b;
 }
 
@@ -861,9 +871,9 @@ nmf_status nmf_residual_check(nmf_ctx* c, const float* X, int64_t ldx, double ep
   if (!c->initialized) return fail(c, NMF_ESTATE, "residual needs factors (nmf_init)");
   Layout& L = c->L;
   HIPCHK(c, hipEventRecord(c->ev[4], c->st));
-  HIPCHK(c, launch_residual(X, ldx, c->p.m, c->p.n, c->at<float>(L.W), c->at<float>(L.scale_w),
-                            c->at<float>(L.Ht), c->p.r, c->at<double>(L.res_part),
-                            c->at<double>(L.res_out), c->at<unsigned>(L.counters) + 4, c->st, nullptr, 0.0, true));
+  HIPCHK(c, launch_residual_split(X, ldx, c->p.m, c->p.n, c->at<float>(L.W), c->at<float>(L.scale_w),
+                                  c->at<float>(L.Ht), c->p.r, c->at<uint16_t>(L.rsplit), c->at<double>(L.res_part),
+                                  c->at<double>(L.res_out), c->at<unsigned>(L.counters) + 4, c->st));
   HIPCHK(c, hipEventRecord(c->ev[5], c->st));
   HIPCHK(c, launch_gather_host(nullptr, c->at<double>(L.res_out), c->at<int>(L.qr_status), c->hout_dev, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
@@ -872,7 +882,7 @@ nmf_status nmf_residual_check(nmf_ctx* c, const float* X, int64_t ldx, double ep
   if (hr[5] != 0.0 || hr[6] != 0.0) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
   if (!std::isfinite(hr[3]) || !std::isfinite(hr[4])) return fail(c, NMF_ENONFINITE, "non-finite residual");
   const double e32 = (hr[4] > 0) ? std::sqrt(hr[3] / hr[4]) : 0.0;
-  const double b = fp32_residual_bound(c->p.r, c->p.m, c->p.n, e32, hr[4]);
+  const double b = split_residual_bound(residual_split_kr(c->p.r), c->p.m, c->p.n, e32, hr[4]);
   if (std::fabs(e32 - eps) <= b) {   // either side of eps within the bound: the exact value decides
     if (exact) *exact = 1;
     if (bound) *bound = 0.0;
@@ -926,10 +936,12 @@ nmf_status nmf_sketch_spectrum(nmf_ctx* c, double* sigma) {
 namespace {
 
 // One synchronisation for a proxy reading and, when the proxy is already within
-// thr of eps, the exact residual too: the residual kernel reads the proxy sums
-// on the device and exits at once otherwise (its output keeps a negative
-// sentinel).  *ran tells whether e was computed.
-nmf_status proxy_then_exact(nmf_ctx* c, const float* X, int64_t ldx, double thr, double* p, bool* ran, double* e) {
+// thr of eps, the split-BF16 residual too: its kernel reads the proxy sums on
+// the device and exits at once otherwise (its output keeps a negative
+// sentinel).  *ran tells whether e was evaluated; when the split value lies
+// within its bound of eps, the exact FP64 residual decides (*e exact).
+nmf_status proxy_then_check(nmf_ctx* c, const float* X, int64_t ldx, double eps, double thr, double* p, bool* ran,
+                            double* e) {
   Layout& L = c->L;
   const int nb = proxy_blocks(c->p.n);
   double* po = c->at<double>(L.proxy_out);
@@ -939,9 +951,9 @@ nmf_status proxy_then_exact(nmf_ctx* c, const float* X, int64_t ldx, double thr,
   HIPCHK(c, launch_sum_partials_f64(c->at<double>(L.proxy_part), nb, 2, po, nullptr, c->st));
   HIPCHK(c, launch_fill_f32(reinterpret_cast<float*>(ro), 4, -1.0f, c->st));   // two negative doubles
   HIPCHK(c, hipEventRecord(c->ev[4], c->st));
-  HIPCHK(c, launch_residual(X, ldx, c->p.m, c->p.n, c->at<float>(L.W), c->at<float>(L.scale_w),
-                            c->at<float>(L.Ht), c->p.r, c->at<double>(L.res_part), ro,
-                            c->at<unsigned>(L.counters) + 4, c->st, po, thr * thr));
+  HIPCHK(c, launch_residual_split(X, ldx, c->p.m, c->p.n, c->at<float>(L.W), c->at<float>(L.scale_w),
+                                  c->at<float>(L.Ht), c->p.r, c->at<uint16_t>(L.rsplit), c->at<double>(L.res_part),
+                                  ro, c->at<unsigned>(L.counters) + 4, c->st, po, thr * thr));
   HIPCHK(c, hipEventRecord(c->ev[5], c->st));
   HIPCHK(c, launch_gather_host(po, ro, c->at<int>(L.qr_status), c->hout_dev, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
@@ -956,17 +968,21 @@ nmf_status proxy_then_exact(nmf_ctx* c, const float* X, int64_t ldx, double thr,
     c->t_residual = true;
     if (c->hout[5] != 0.0 || c->hout[6] != 0.0) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
     if (!std::isfinite(h[3]) || !std::isfinite(h[4])) return fail(c, NMF_ENONFINITE, "non-finite residual");
-    *e = (h[4] > 0) ? std::sqrt(h[3] / h[4]) : 0.0;
+    const double es = (h[4] > 0) ? std::sqrt(h[3] / h[4]) : 0.0;
+    if (std::fabs(es - eps) <= split_residual_bound(residual_split_kr(c->p.r), c->p.m, c->p.n, es, h[4]))
+      return nmf_residual(c, X, ldx, e);   // the side of eps is open: the exact value decides
+    *e = es;
   }
   return NMF_OK;
 }
 
-// Adaptive schedule.  Phase 1 (no exact value yet): chunks of 5 or more with
-// the sketch-only proxy after each (no pass over X); the first exact FP64
-// residual runs once the proxy is within 1 % of eps, or after 100 iterations.
-// Phase 2: the next chunk is 1.5x the iterations a straight-line extrapolation
-// of the last two exact values needs to reach eps (5..50).  Only an exact
-// e <= eps stops the fit.
+// Adaptive schedule.  Phase 1 (no residual yet): chunks of 5 or more with the
+// sketch-only proxy after each (no pass over X); the first residual runs once
+// the proxy is within 1 % of eps, or after 100 iterations.  Phase 2: the next
+// chunk is 1.5x the iterations a straight-line extrapolation of the last two
+// residuals needs to reach eps (5..50).  Every residual is the stopping test's
+// (split-BF16 products, the exact FP64 value when eps lies within their
+// bound), so each stop decision is that of the exact e.
 nmf_status fit_proxy_schedule(nmf_ctx* c, const float* X, int64_t ldx, int32_t max_iters, double eps,
                               int* iters_done, double* rel_err) {
   nmf_status s;
@@ -974,7 +990,7 @@ nmf_status fit_proxy_schedule(nmf_ctx* c, const float* X, int64_t ldx, int32_t m
   double e = NAN;
   int t_prev = -1;        // last evaluation (proxy in phase 1, exact in phase 2)
   double v_prev = 0.0;
-  bool exact_seen = false;
+  bool res_seen = false;
   bool far = false;       // the last extrapolation needed more than the largest chunk
   auto extrapolate = [&](double v, int t, double lo, double hi, double fac) {
     const double slope = t_prev >= 0 && t > t_prev ? (v_prev - v) / (t - t_prev) : 0.0;
@@ -996,11 +1012,11 @@ nmf_status fit_proxy_schedule(nmf_ctx* c, const float* X, int64_t ldx, int32_t m
     if (chunk > max_iters - done) chunk = max_iters - done;
     if ((s = nmf_step(c, chunk)) != NMF_OK) return s;
     done += chunk;
-    if (!exact_seen) {
+    if (!res_seen) {
       double p;
       bool ran = false;
-      // the exact residual runs in the same synchronisation when the proxy is within 1 % of eps
-      if ((s = proxy_then_exact(c, X, ldx, eps * 1.01, &p, &ran, &e)) != NMF_OK) return s;
+      // the residual runs in the same synchronisation when the proxy is within 1 % of eps
+      if ((s = proxy_then_check(c, X, ldx, eps, eps * 1.01, &p, &ran, &e)) != NMF_OK) return s;
       if (!ran && done < 100 && done < max_iters) {
         chunk = extrapolate(p, done, 5, 50, 1.2);
         // A proxy that would need more than the largest chunk at its current
@@ -1008,21 +1024,15 @@ nmf_status fit_proxy_schedule(nmf_ctx* c, const float* X, int64_t ldx, int32_t m
         // (W's part outside range(Q_L)) does not shrink with the iterations.
         if (!far) continue;
       }
-      exact_seen = true;
-      t_prev = -1;        // phase 2 extrapolates exact values only
+      res_seen = true;
+      t_prev = -1;        // phase 2 extrapolates residuals only
       if (ran) {
         if (e <= eps) break;
         chunk = extrapolate(e, done, 5, 50, 1.5);
         continue;
       }
     }
-    // While the last value was more than 1 % above eps, the check is the FP32-product
-    // one (it falls back to the exact residual near eps); the checks that can stop
-    // near eps are exact from the start, so they take one pass over X.
-    const bool far_above = e > 1.01 * eps;
-    if ((s = far_above ? nmf_residual_check(c, X, ldx, eps, &e, nullptr, nullptr) : nmf_residual(c, X, ldx, &e)) !=
-        NMF_OK)
-      return s;
+    if ((s = nmf_residual_check(c, X, ldx, eps, &e, nullptr, nullptr)) != NMF_OK) return s;
     if (e <= eps) break;
     chunk = extrapolate(e, done, 5, 50, 1.5);
   }

@@ -1,14 +1,7 @@
 // Exact relative error e = ||X - W Ht^T||_F / ||X||_F (the objective of eq 2.2),
 // evaluated directly (never through the Gram expansion, which cancels
-// catastrophically at small e) with FP64 products and FP64 accumulation.
-//
-// F32 = true: the same with FP32 products (v_mfma_f32_16x16x4f32, Ht rows in
-// natural order: its output D[j][i] sits in lane i + 16 (j / 4), register j % 4,
-// so lane l again holds X row l % 16 and columns 4 (l / 16) .. +3) and E = X - P
-// in FP32; squares are still summed in FP64.  For W, Ht >= 0 the computed e
-// stays within gamma (1 + e) of the exact one, gamma = (r + 2) u / (1 - (r + 2) u)
-// with u = 2^-23 (r products and the scaling by sw per element of P, one
-// subtraction; u covers truncating as well as nearest rounding).
+// catastrophically at small e) with FP64 products and FP64 accumulation; and a
+// faster value for stopping tests from split-BF16 products (residual_split_kernel).
 //
 // A workgroup owns 4 RPW rows of X (RPW per wave) and walks all 64-column tiles,
 // starting at tile (workgroup index mod tile count).  Per 16-column block the
@@ -19,16 +12,18 @@
 // adjacent columns 4 (l / 16) .. +3 of the block, one float4 of X.  It
 // subtracts X and accumulates squares.  Workgroup partials are summed in fixed
 // order by the last workgroup to finish (completion counter, reset afterwards).
-#include <type_traits>
+#include <algorithm>
 
 #include "common.h"
 
 namespace {
 
 constexpr int RBMIN = 64;    // fewest rows per workgroup of any instantiation
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 constexpr int CT = 64;       // columns per tile
 
-template <int RMAX, int RPW, bool F32>
+template <int RMAX, int RPW>
 __global__ void __launch_bounds__(256)
 residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
                 const float* __restrict__ W, const float* __restrict__ sw,
@@ -44,8 +39,8 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
   constexpr int RB = 4 * RPW, NB = RPW / 16;  // rows per workgroup, 16-row blocks per wave
   constexpr int KS = RMAX / 4;                // MFMA k-steps
   constexpr int HPT = CT * RMAX / 256;        // Ht tile elements per thread
-  typedef typename std::conditional<F32, float, double>::type T;
-  typedef typename std::conditional<F32, f32x4, f64x4>::type TV;
+  typedef double T;
+  typedef f64x4 TV;
   __shared__ T Hs[CT][RMAX + 1];
   __shared__ double red[2][256];
   __shared__ int last;
@@ -82,8 +77,8 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
       }
     }
   }
-  // FP64: Ht rows in the order c(j) = 4 (j % 4) + j / 4; FP32: natural order
-  const int hrow = F32 ? (lane & 15) : 4 * (lane & 3) + ((lane & 15) >> 2);
+  // Ht rows in the order c(j) = 4 (j % 4) + j / 4
+  const int hrow = 4 * (lane & 3) + ((lane & 15) >> 2);
   // Software pipeline over the 64-column tiles of this row strip: the loads of
   // tile t+1 are issued (Ht first, then X) before the MFMAs of tile t, so each
   // wait only covers loads issued one tile earlier.  n % 4 == 0, so a group of
@@ -153,12 +148,8 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
       for (int sub = 0; sub < 4; ++sub) {
         const T h = Hs[sub * 16 + hrow][k];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          if constexpr (F32)
-            d[nb][sub] = __builtin_amdgcn_mfma_f32_16x16x4f32(h, wfr[nb][s], d[nb][sub], 0, 0, 0);
-          else
-            d[nb][sub] = __builtin_amdgcn_mfma_f64_16x16x4f64(h, wfr[nb][s], d[nb][sub], 0, 0, 0);
-        }
+        for (int nb = 0; nb < NB; ++nb)
+          d[nb][sub] = __builtin_amdgcn_mfma_f64_16x16x4f64(h, wfr[nb][s], d[nb][sub], 0, 0, 0);
       }
     }
     // lane: row i = lane % 16 of block nb, tile columns 16 sub + 4 (lane / 16) + q in
@@ -170,7 +161,7 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const double x = (double)xc[nb][sub][q];
-          const double df = F32 ? (double)(xc[nb][sub][q] - (float)d[nb][sub][q]) : x - (double)d[nb][sub][q];
+          const double df = x - d[nb][sub][q];
           res = fma(df, df, res);
           xx = fma(x, x, xx);
         }
@@ -260,6 +251,214 @@ proxy_kernel(const float* __restrict__ Xh, int64_t ldx, const float* __restrict_
   }
 }
 
+// ------------------------------------------------------------------- split
+// Residual for a stopping test on split-BF16 products: P = (W diag(sw)) Ht^T
+// from hi hi + hi lo + lo hi of the BF16 splits (v = hi + lo, hi = bf16(v),
+// lo = bf16(v - hi)), FP32 accumulation on v_mfma_f32_32x32x16_bf16, E = X - P
+// in FP32, squares summed in FP64.  For W, Ht >= 0 the result lies within
+// g (1 + e) + u' e of the exact e (g from the representation, 3.03 2^-16 per
+// product, the scaling of W, and 3 KR FP32 additions per element; the host
+// states the bound).  The splits are formed once per call (split_rows_kernel).
+//
+// A workgroup of 512 threads owns 256 rows of X (32 per wave) and walks all
+// 64-column tiles from a rotated start; each wave keeps the A fragments of its
+// rows (W splits, all KR columns) in registers.  The hi and lo splits of the
+// tile's 64 rows of Ht go through LDS (two stages, rows padded by 8 halves: the
+// 16-byte fragment reads are free of bank conflicts), the next tile's splits
+// and X values are loaded while the current tile is consumed, one barrier per
+// tile.  Loads are unconditional from clamped addresses, values outside the
+// matrices zeroed after.
+
+// hi and lo BF16 splits of A diag(scale) (rows x r, lda), zero from column r
+// to KR (ld KR).
+__global__ void __launch_bounds__(256)
+split_rows_kernel(const float* __restrict__ A, int64_t lda, const float* __restrict__ scale, int64_t rows, int r,
+                  int KR, uint16_t* __restrict__ hi, uint16_t* __restrict__ lo) {
+  const int64_t total = rows * (KR / 2);
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / (KR / 2);
+    const int k = 2 * (int)(e % (KR / 2));
+    float v[2];
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const bool ok = k + d < r;
+      const float a = A[ok ? i * lda + k + d : 0];
+      const float sc = scale ? scale[ok ? k + d : 0] : 1.f;
+      v[d] = ok ? a * sc : 0.f;
+    }
+    const f32x2 pv = {v[0], v[1]};
+    const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector(pv, bf16x2));
+    const f32x2 rv = {v[0] - __builtin_bit_cast(float, h << 16), v[1] - __builtin_bit_cast(float, h & 0xFFFF0000u)};
+    const uint32_t l = __builtin_bit_cast(uint32_t, __builtin_convertvector(rv, bf16x2));
+    *(uint32_t*)(hi + i * KR + k) = h;
+    *(uint32_t*)(lo + i * KR + k) = l;
+  }
+}
+
+template <int KR>
+__global__ void __launch_bounds__(512)
+residual_split_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
+                      const uint16_t* __restrict__ Wh, const uint16_t* __restrict__ Wl,
+                      const uint16_t* __restrict__ Hh, const uint16_t* __restrict__ Hl, double* __restrict__ part,
+                      double* __restrict__ out, unsigned* __restrict__ counter, const double* __restrict__ gate,
+                      double gate_thr2) {
+  if (gate) {   // as in residual_kernel: every workgroup returns unless the proxy is within the gate
+    const double e2 = (gate[2] - gate[1] + gate[0]) / gate[2];
+    if (!(e2 <= gate_thr2)) return;
+  }
+  constexpr int CT = 64, HROW = KR + 8, KS = KR / 16;
+  constexpr int HV = CT * KR / 8 / 512;          // 16-byte loads of each split per thread
+  static_assert(HV >= 1, "KR >= 64");
+  __shared__ __attribute__((aligned(16))) uint16_t Hs[2][2][CT * HROW];
+  __shared__ double red[2][512];
+  __shared__ int last;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l32 = lane & 31, half = lane >> 5;
+  const int64_t row0 = (int64_t)blockIdx.x * 256 + 32 * wave;   // this wave's 32 rows
+  const int64_t ntile = ceil_div(n, CT);
+  // A fragments: lane holds W[row0 + l32][16 ks + 8 half .. +7] (hi, lo)
+  bf16x8 ah[KS], al[KS];
+  {
+    const int64_t wr = row0 + l32 < m ? row0 + l32 : 0;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      ah[ks] = *(const bf16x8*)(Wh + wr * KR + 16 * ks + 8 * half);
+      al[ks] = *(const bf16x8*)(Wl + wr * KR + 16 * ks + 8 * half);
+    }
+    if (row0 + l32 >= m) {
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) ah[ks] = al[ks] = (bf16x8){};
+    }
+  }
+  // Ht splits of a tile: thread loads 16 bytes at row (tid + 512 p) / (KR / 8),
+  // chunk (tid + 512 p) % (KR / 8) of each split (rows past n read row 0)
+  i32x4 hh[HV], hl[HV];
+  auto loadH = [&](int64_t c0) {
+#pragma unroll
+    for (int p = 0; p < HV; ++p) {
+      const int f = tid + 512 * p, jr = f / (KR / 8), ch = f % (KR / 8);
+      const int64_t j = c0 + jr < n ? c0 + jr : 0;
+      hh[p] = *(const i32x4*)(Hh + j * KR + 8 * ch);
+      hl[p] = *(const i32x4*)(Hl + j * KR + 8 * ch);
+    }
+  };
+  auto storeH = [&](int64_t c0, int b) {
+    const i32x4 zi = {0, 0, 0, 0};
+#pragma unroll
+    for (int p = 0; p < HV; ++p) {
+      const int f = tid + 512 * p, jr = f / (KR / 8), ch = f % (KR / 8);
+      const bool ok = c0 + jr < n;
+      *(i32x4*)(&Hs[b][0][jr * HROW + 8 * ch]) = ok ? hh[p] : zi;
+      *(i32x4*)(&Hs[b][1][jr * HROW + 8 * ch]) = ok ? hl[p] : zi;
+    }
+  };
+  // X in the output layout of a 32 x 32 block: register x holds row
+  // 8 (x / 4) + 4 half + x % 4, column l32 (two column blocks per tile)
+  float xv[2][16];
+  auto xrow = [&](int x) { return row0 + 8 * (x >> 2) + 4 * half + (x & 3); };
+  auto loadX = [&](int64_t c0) {
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int x = 0; x < 16; ++x) {
+        const int64_t i = xrow(x), j = c0 + 32 * cb + l32;
+        xv[cb][x] = X[(i < m && j < n) ? i * ldx + j : 0];
+      }
+  };
+  const int64_t rot = (int64_t)blockIdx.x % ntile;
+  auto col0 = [&](int64_t t) { return ((t + rot) % ntile) * CT; };
+  double res = 0.0, xx = 0.0;
+  loadH(col0(0));
+  loadX(col0(0));
+  storeH(col0(0), 0);
+  __syncthreads();
+  for (int64_t t = 0; t < ntile; ++t) {
+    const int64_t c0 = col0(t);
+    float xc[2][16];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int x = 0; x < 16; ++x) {
+        const int64_t i = xrow(x), j = c0 + 32 * cb + l32;
+        xc[cb][x] = (i < m && j < n) ? xv[cb][x] : 0.f;
+      }
+    if (t + 1 < ntile) {
+      loadH(col0(t + 1));
+      loadX(col0(t + 1));
+    }
+    __builtin_amdgcn_sched_barrier(0);   // the next tile's loads stay ahead of the MFMAs
+    const int b = (int)(t & 1);
+    f32x16 d[2];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) d[cb][e] = 0.f;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        const int jl = 32 * cb + l32;
+        const bf16x8 bh = *(const bf16x8*)(&Hs[b][0][jl * HROW + 16 * ks + 8 * half]);
+        const bf16x8 bl = *(const bf16x8*)(&Hs[b][1][jl * HROW + 16 * ks + 8 * half]);
+        d[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[ks], bh, d[cb], 0, 0, 0);   // small terms first
+        d[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ks], bl, d[cb], 0, 0, 0);
+        d[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[ks], bh, d[cb], 0, 0, 0);
+      }
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int x = 0; x < 16; ++x) {   // out-of-range entries are 0 - 0
+        const double df = (double)(xc[cb][x] - d[cb][x]);
+        res = fma(df, df, res);
+        xx = fma((double)xc[cb][x], (double)xc[cb][x], xx);
+      }
+    if (t + 1 < ntile) storeH(col0(t + 1), b ^ 1);   // that stage was last read before the previous barrier
+    __syncthreads();
+  }
+  red[0][tid] = res;
+  red[1][tid] = xx;
+  __syncthreads();
+  for (int w = 256; w > 0; w >>= 1) {
+    if (tid < w) {
+      red[0][tid] += red[0][tid + w];
+      red[1][tid] += red[1][tid + w];
+    }
+    __syncthreads();
+  }
+  const int nblk = gridDim.x;
+  const int bid = blockIdx.x;
+  if (tid == 0) {
+    part[2 * bid] = red[0][0];
+    part[2 * bid + 1] = red[1][0];
+    __threadfence();
+    last = (atomicAdd(counter, 1u) == (unsigned)nblk - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const volatile double* vp = part;
+  double a0 = 0.0, a1 = 0.0;
+  for (int q = tid; q < nblk; q += 512) {
+    a0 += vp[2 * q];
+    a1 += vp[2 * q + 1];
+  }
+  red[0][tid] = a0;
+  red[1][tid] = a1;
+  __syncthreads();
+  for (int w = 256; w > 0; w >>= 1) {
+    if (tid < w) {
+      red[0][tid] += red[0][tid + w];
+      red[1][tid] += red[1][tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[0] = red[0][0];
+    out[1] = red[1][0];
+    *counter = 0u;
+  }
+}
+
 }  // namespace
 
 int residual_blocks(int64_t m, int64_t n) {   // upper bound over the instantiations
@@ -269,19 +468,13 @@ int residual_blocks(int64_t m, int64_t n) {   // upper bound over the instantiat
 
 hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t n, const float* W,
                            const float* sw, const float* Ht, int r, double* part, double* out,
-                           unsigned* counter, hipStream_t st, const double* gate, double gate_thr2, bool fp32) {
+                           unsigned* counter, hipStream_t st, const double* gate, double gate_thr2) {
   if (n % 4) return hipErrorInvalidValue;
   // 32 rows per wave (each Ht fragment feeds two MFMA row blocks) while the W
   // fragments fit; 16 for larger r
 #define NMF_RES_LAUNCH(RM_, RPW_)                                                                              \
-  do {                                                                                                         \
-    if (fp32)                                                                                                  \
-      hipLaunchKernelGGL((residual_kernel<RM_, RPW_, true>), dim3((unsigned)ceil_div(m, 4 * RPW_)), dim3(256), 0, \
-                         st, X, ldx, m, n, W, sw, Ht, r, part, out, counter, gate, gate_thr2);                  \
-    else                                                                                                       \
-      hipLaunchKernelGGL((residual_kernel<RM_, RPW_, false>), dim3((unsigned)ceil_div(m, 4 * RPW_)), dim3(256), 0, \
-                         st, X, ldx, m, n, W, sw, Ht, r, part, out, counter, gate, gate_thr2);                  \
-  } while (0)
+  hipLaunchKernelGGL((residual_kernel<RM_, RPW_>), dim3((unsigned)ceil_div(m, 4 * RPW_)), dim3(256), 0, st, X, ldx, \
+                     m, n, W, sw, Ht, r, part, out, counter, gate, gate_thr2)
   if (r <= 16) NMF_RES_LAUNCH(16, 32);
   else if (r <= 32) NMF_RES_LAUNCH(32, 32);
   else if (r <= 64) NMF_RES_LAUNCH(64, 16);
@@ -302,3 +495,33 @@ hipError_t launch_proxy(const float* Xh, int64_t ldx, const float* Ht, int r, co
   hipLaunchKernelGGL(proxy_kernel, dim3(proxy_blocks(n)), dim3(256), lds, st, Xh, ldx, Ht, r, Wh, kp, n, part);
   return hipGetLastError();
 }
+
+int residual_split_kr(int r) { return r <= 64 ? 64 : r <= 128 ? 128 : 0; }
+
+size_t residual_split_halves(int64_t m, int64_t n, int r) {
+  const int KR = residual_split_kr(r);
+  return KR ? (size_t)2 * (m + n) * KR : 0;
+}
+
+hipError_t launch_residual_split(const float* X, int64_t ldx, int64_t m, int64_t n, const float* W, const float* sw,
+                                 const float* Ht, int r, uint16_t* ws, double* part, double* out, unsigned* counter,
+                                 hipStream_t st, const double* gate, double gate_thr2) {
+  const int KR = residual_split_kr(r);
+  if (!KR || m == 0 || n == 0) return hipErrorInvalidValue;
+  uint16_t* Wh = ws;
+  uint16_t* Wl = Wh + m * KR;
+  uint16_t* Hh = Wl + m * KR;
+  uint16_t* Hl = Hh + n * KR;
+  auto grid = [&](int64_t rows) { return dim3((unsigned)std::min<int64_t>(ceil_div(rows * (KR / 2), 256), 8192)); };
+  hipLaunchKernelGGL(split_rows_kernel, grid(m), dim3(256), 0, st, W, (int64_t)r, sw, m, r, KR, Wh, Wl);
+  hipLaunchKernelGGL(split_rows_kernel, grid(n), dim3(256), 0, st, Ht, (int64_t)r, nullptr, n, r, KR, Hh, Hl);
+  const dim3 g((unsigned)ceil_div(m, 256));
+  if (KR == 64)
+    hipLaunchKernelGGL(residual_split_kernel<64>, g, dim3(512), 0, st, X, ldx, m, n, Wh, Wl, Hh, Hl, part, out,
+                       counter, gate, gate_thr2);
+  else
+    hipLaunchKernelGGL(residual_split_kernel<128>, g, dim3(512), 0, st, X, ldx, m, n, Wh, Wl, Hh, Hl, part, out,
+                       counter, gate, gate_thr2);
+  return hipGetLastError();
+}
+

@@ -71,6 +71,9 @@ def _run_to_checkpoints(lib, ctx, Xd, ref, iters, gate, tag):
         worst = max(worst, abs(e - e_ref))
         print(f"  {tag} it={it:4d} e_gpu={e:.8e} e_oracle={e_ref:.8e} diff={abs(e - e_ref):.2e}", flush=True)
         assert abs(e - e_ref) <= gate, it
+        # the split-BF16 residual of the stopping test: within its bound of the exact one
+        es, bound, exact = ctx.residual_check(Xd, 10.0)
+        assert not exact and abs(es - e) <= bound <= 1.2e-4, it
         checked += 1
     assert checked >= 8
     return worst
