@@ -336,7 +336,7 @@ def time_uncompressed(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, steps, w
 
 # committed HBM-counter summary of the dominant kernel per workload, and the
 # source file it was taken on
-TRAFFIC = {"c2": ("gemm_bf16_c2_traffic.md", "gemm_lp.hip"), "c5": ("gemm_fp8_c5_traffic.md", "gemm_lp.hip")}
+TRAFFIC = {"c2": ("gemm_bf16_c2_traffic.md", "gemm_lp.hip"), "c5": ("gemm_split_c5_traffic.md", "gemm_split.hip")}
 
 
 def source_digest(path):
@@ -387,10 +387,13 @@ def lowp_products(torch, nmfrp, Xd, m, n, kp, prec):
 
 def kernel_timing(torch, nmfrp, Xd, m, n, kp, reps, prec, name):
     """Per-launch times of the compression products at the workload's shapes.
-    The dominant kernel of the headline path, the low-precision range-finder
-    product, is timed alone on prepared operands (X B and X^T B alternating, as
-    the range finder issues them); the FP32 products are timed per library call
-    (product plus split-K sum); the split-BF16 sketch product per call."""
+    The low-precision range-finder products and (c5) the split-BF16 products are
+    timed alone on prepared operands (X B and X^T B alternating, as the range
+    finder issues them); the FP32 products and the split-BF16 products are also
+    timed per library call (product plus split-K sum).  The dominant kernel of
+    the headline path, which the roofline object describes, is the BF16
+    range-finder product at c2 and the split-BF16 product at c5 (its refinement
+    power iteration and projected data)."""
     dev = Xd.device
     B_n = torch.randn(n, kp, device=dev)
     B_m = torch.randn(m, kp, device=dev)
@@ -430,6 +433,31 @@ def kernel_timing(torch, nmfrp, Xd, m, n, kp, reps, prec, name):
         res[label] = dict(ms=round(ms, 5), tflops=round(flops / (ms * 1e-3) / 1e12, 2),
                           x_gbs=round(alg / (ms * 1e-3) / 1e9, 1))
         log(f"[bench] {label}: {ms:.4f} ms  {res[label]['tflops']:.1f} TFLOP/s  X at {res[label]['x_gbs']} GB/s")
+    if name == "c5":
+        S1, S2 = nmfrp.SplitProduct(Xd, 0, B_n), nmfrp.SplitProduct(Xd, 1, B_m)
+        for label, fn, cnt in (("split-bf16 X*B (kernel)", S1.run, 1), ("split-bf16 X^T*B (kernel)", S2.run, 1),
+                               ("split-bf16 both (kernel)", lambda: (S1.run(), S2.run()), 2)):
+            ms = timed(fn, cnt)
+            res[label] = dict(ms=round(ms, 5), tflops=round(flops / (ms * 1e-3) / 1e12, 2),
+                              x_gbs=round(4.0 * m * n / (ms * 1e-3) / 1e9, 1))
+            log(f"[bench] {label}: {ms:.4f} ms  {res[label]['tflops']:.1f} TFLOP/s  "
+                f"X at {res[label]['x_gbs']} GB/s")
+        dom = res["split-bf16 both (kernel)"]
+        # three BF16 MFMA products per product term: the split arithmetic's peak is a third of BF16's
+        peak = PEAK_BF16_TFLOPS / 3.0
+        achieved = flops / (dom["ms"] * 1e-3) / 1e12
+        res["roofline"] = dict(
+            bound="mfma",
+            kernel="gemm_split_wide_kernel (split-BF16 product on FP32 X: the refinement power iteration and the "
+                   "projected data; X B and X^T B alternating, split-K partials)",
+            achieved=round(achieved, 2), peak=round(peak, 2), unit="TFLOP/s", frac=round(achieved / peak, 4),
+            traffic=measured_traffic(name), algorithmic_flops_per_launch=flops,
+            units_per_launch=f"{m}x{n} X elements x {kp} thin columns, 2 flops each",
+            launch_us=round(dom["ms"] * 1e3, 2), splits=[S1.splits, S2.splits],
+            peak_note="BF16 dense 2500 TFLOP/s / 3 (hi hi + hi lo + lo hi per term)",
+            x_gbs=dom["x_gbs"], x_hbm_frac=round(dom["x_gbs"] / PEAK_HBM_GBS, 4))
+        del S1, S2
+        return res
     dom = res[f"{fmt} both (kernel)"]
     achieved = alg / (dom["ms"] * 1e-3) / 1e9
     peak_mfma = PEAK_BF16_TFLOPS if fmt == "bf16" else PEAK_FP8_TFLOPS
@@ -448,7 +476,7 @@ def kernel_timing(torch, nmfrp, Xd, m, n, kp, reps, prec, name):
     return res
 
 
-def probe_kernels(torch, nmfrp, Xd, m, n, kp, reps, prec):
+def probe_kernels(torch, nmfrp, Xd, m, n, kp, reps, prec, name):
     """For hardware-counter runs: a plain copy of known size, then the dominant
     kernel at the workload's shapes (reps launches of each shape)."""
     src = torch.empty(m * n, dtype=torch.float32, device=Xd.device).fill_(1.0)
@@ -456,6 +484,18 @@ def probe_kernels(torch, nmfrp, Xd, m, n, kp, reps, prec):
     torch.cuda.synchronize()
     dst.copy_(src)
     del src, dst
+    if name == "c5":   # the split-BF16 product on FP32 X
+        S1 = nmfrp.SplitProduct(Xd, 0, torch.randn(n, kp, device=Xd.device))
+        S2 = nmfrp.SplitProduct(Xd, 1, torch.randn(m, kp, device=Xd.device))
+        for _ in range(reps):
+            S1.run()
+            S2.run()
+        torch.cuda.synchronize()
+        print(json.dumps(dict(probe="kernels", copy_bytes=4 * m * n, x_bytes=4 * m * n, splits=[S1.splits, S2.splits],
+                              M=[m, n], N=kp, reps=reps,
+                              source_sha256_16=source_digest(os.path.join(ROOT, "paper_1712_02248_amd", "csrc",
+                                                                          "gemm_split.hip")))), flush=True)
+        return
     P1, P2 = lowp_products(torch, nmfrp, Xd, m, n, kp, prec)
     for _ in range(reps):
         P1.run()
@@ -582,7 +622,7 @@ def main():
     if args.probe_kernels:   # counters do not depend on the values of X
         g = torch.Generator(device="cuda:0")
         g.manual_seed(seed)
-        probe_kernels(torch, nmfrp, torch.rand(m, n, device="cuda:0", generator=g), m, n, kp, 5, lp_prec)
+        probe_kernels(torch, nmfrp, torch.rand(m, n, device="cuda:0", generator=g), m, n, kp, 5, lp_prec, name)
         return
     from datagen import device as ddev
     dev = torch.device("cuda:0")

@@ -320,6 +320,22 @@ nmf_status nmf_gemm_split(const float* X, int64_t ldx, int32_t at, const float* 
                           int64_t N, float* C, int64_t ldc, int64_t M, void* workspace, size_t ws_bytes,
                           void* hip_stream);
 
+/* The split-BF16 product in parts (callers that keep the thin operand
+ * prepared; timing the product kernel alone).  nmf_split_prepare_thin writes
+ * the hi and lo BF16 parts of B (K x N FP32, ldb, N <= 256) transposed into BtH
+ * and BtL (N x ldbt each, ldbt % 64 == 0, ldbt >= K rounded up to 64, zero
+ * padded).  nmf_gemm_split_splits gives the split-K count nmf_gemm_split uses.
+ * nmf_gemm_split_prepared launches only the product kernel of nmf_gemm_split:
+ * with splits == 1 it writes C (M x N, ldc); with splits > 1 it writes partial
+ * z (M x N, leading dimension N) at C + z M N, which the caller sums.
+ * Asynchronous on hip_stream. */
+nmf_status nmf_split_prepare_thin(const float* B, int64_t ldb, int64_t K, int64_t N, uint16_t* BtH, uint16_t* BtL,
+                                  int64_t ldbt, void* hip_stream);
+int32_t nmf_gemm_split_splits(int64_t M, int64_t N, int64_t K);
+nmf_status nmf_gemm_split_prepared(const float* X, int64_t ldx, int32_t at, const uint16_t* BtH, const uint16_t* BtL,
+                                   int64_t ldbt, int64_t K, int64_t N, float* C, int64_t ldc, int64_t M,
+                                   int32_t splits, void* hip_stream);
+
 /* In-place orthonormalisation of Y (rows x k, ldy % 4 == 0) by FP64
  * CholeskyQR2 (shifted CholeskyQR3 on breakdown), k <= 128.  Synchronising;
  * *shifted (may be NULL) = 1 if the shifted fallback ran. */

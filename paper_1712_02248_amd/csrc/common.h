@@ -80,6 +80,10 @@ int gemm_split_sq_parts(int64_t M, int64_t N, int splits);
 hipError_t launch_gemm_split(const float* X, int64_t ldx, int at, const uint16_t* BtH, const uint16_t* BtL,
                              int64_t ldbt, float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, int splits,
                              float* part, hipStream_t st, double* sq = nullptr);
+// the product kernel alone (splits > 1: partials z at part + z M N, not summed)
+hipError_t launch_gemm_split_kernel(const float* X, int64_t ldx, int at, const uint16_t* BtH, const uint16_t* BtL,
+                             int64_t ldbt, float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, int splits,
+                             float* part, hipStream_t st, double* sq = nullptr);
 // a_trans = 1 (N <= 128): A is the K x lda copy of X itself (C = A^T Bt^T, M
 // columns of A, rows at or past K read as zero), not a K-contiguous copy.
 hipError_t launch_gemm_bf16_nt(const uint16_t* A, int64_t lda, const uint16_t* Bt, int64_t ldbt,

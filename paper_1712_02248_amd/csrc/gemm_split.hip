@@ -531,6 +531,14 @@ int gemm_split_sq_parts(int64_t M, int64_t N, int splits) {
 hipError_t launch_gemm_split(const float* X, int64_t ldx, int at, const uint16_t* BtH, const uint16_t* BtL,
                              int64_t ldbt, float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, int splits,
                              float* part, hipStream_t st, double* sq) {
+  hipError_t e = launch_gemm_split_kernel(X, ldx, at, BtH, BtL, ldbt, C, ldc, M, N, K, splits, part, st, sq);
+  if (e != hipSuccess || splits == 1 || M == 0 || N == 0) return e;
+  return launch_splitk_reduce_lp(part, splits, C, ldc, M, N, st);
+}
+
+hipError_t launch_gemm_split_kernel(const float* X, int64_t ldx, int at, const uint16_t* BtH, const uint16_t* BtL,
+                                    int64_t ldbt, float* C, int64_t ldc, int64_t M, int64_t N, int64_t K,
+                                    int splits, float* part, hipStream_t st, double* sq) {
   if (M == 0 || N == 0) return hipSuccess;
   if (ldx % 4 || ldbt % 64 || ldbt < round_up(K, 64) || splits < 1) return hipErrorInvalidValue;
   const int sbn = N <= 64 ? 64 : N <= 128 ? 128 : 256;
@@ -565,7 +573,5 @@ hipError_t launch_gemm_split(const float* X, int64_t ldx, int at, const uint16_t
       hipLaunchKernelGGL((gemm_split_wide_kernel<false>), wgrid, dim3(WNT), 0, st, X, ldx, BtH, BtL, ldbt, out, ldo,
                          M, N, K, kchunk, rx, sq);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || splits == 1) return e;
-  return launch_splitk_reduce_lp(part, splits, C, ldc, M, N, st);
+  return hipGetLastError();
 }

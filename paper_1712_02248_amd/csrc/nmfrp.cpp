@@ -1272,6 +1272,31 @@ nmf_status nmf_gemm_split(const float* X, int64_t ldx, int32_t at, const float* 
   return e ? fail(nullptr, NMF_EHIP, hipGetErrorString(e)) : NMF_OK;
 }
 
+nmf_status nmf_split_prepare_thin(const float* B, int64_t ldb, int64_t K, int64_t N, uint16_t* BtH, uint16_t* BtL,
+                                  int64_t ldbt, void* hs) {
+  if (K <= 0 || N <= 0 || N > 256 || ldb < N || ldbt % 64 || ldbt < round_up(K, 64) || !B || !BtH || !BtL)
+    return fail(nullptr, NMF_EINVAL, "bad arguments");
+  const hipError_t e = launch_prep_bt(B, ldb, K, N, BtH, BtL, ldbt, (hipStream_t)hs);
+  return e ? fail(nullptr, NMF_EHIP, hipGetErrorString(e)) : NMF_OK;
+}
+
+int32_t nmf_gemm_split_splits(int64_t M, int64_t N, int64_t K) {
+  if (M <= 0 || N <= 0 || K <= 0) return 0;
+  return gemm_split_pick_splits(M, N, K);
+}
+
+nmf_status nmf_gemm_split_prepared(const float* X, int64_t ldx, int32_t at, const uint16_t* BtH, const uint16_t* BtL,
+                                   int64_t ldbt, int64_t K, int64_t N, float* C, int64_t ldc, int64_t M,
+                                   int32_t splits, void* hs) {
+  if (M < 0 || N <= 0 || N > 256 || K <= 0 || (at != 0 && at != 1) || ldc < N || ldx < (at ? M : K) || ldx % 4 ||
+      ldbt % 64 || ldbt < round_up(K, 64) || splits < 1 || splits > 64)
+    return fail(nullptr, NMF_EINVAL, "bad arguments");
+  if (M == 0) return NMF_OK;
+  if (!X || !BtH || !BtL || !C || ((uintptr_t)X & 15)) return fail(nullptr, NMF_EINVAL, "null pointer or X not 16-byte aligned");
+  const hipError_t e = launch_gemm_split_kernel(X, ldx, at, BtH, BtL, ldbt, C, ldc, M, N, K, splits, C, (hipStream_t)hs);
+  return e ? fail(nullptr, NMF_EHIP, hipGetErrorString(e)) : NMF_OK;
+}
+
 nmf_status nmf_lowp_prepare_thin(int32_t prec, const float* B, int64_t ldb, int64_t K, int64_t N, void* Bt,
                                  int64_t Kpad, int32_t* EB, void* hs) {
   if (N <= 0 || N > 256 || K <= 0 || Kpad < K || Kpad % 128 || ldb < N) return fail(nullptr, NMF_EINVAL, "bad arguments");

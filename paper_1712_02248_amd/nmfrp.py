@@ -68,6 +68,10 @@ _SIGS = {
     "nmf_gemm_bf16_at_prepared": (c_i32, [c_vp, c_i64, c_i64, c_vp, c_i64, c_vp, c_i64, c_i64, c_i64, c_i32, c_vp]),
     "nmf_gemm_split_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64]),
     "nmf_gemm_split": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_i64, c_i64, c_i64, c_vp, c_i64, c_i64, c_vp, c_sz, c_vp]),
+    "nmf_split_prepare_thin": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_vp, c_vp, c_i64, c_vp]),
+    "nmf_gemm_split_splits": (c_i32, [c_i64, c_i64, c_i64]),
+    "nmf_gemm_split_prepared": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_vp, c_i64, c_i64, c_i64, c_vp, c_i64, c_i64,
+                                        c_i32, c_vp]),
     "nmf_orth_workspace_bytes": (c_sz, [c_i64, c_i32]),
     "nmf_orth": (c_i32, [c_vp, c_i64, c_i64, c_i32, c_vp, c_sz, c_vp, c_i32_p]),
     "nmf_sym_eigvals": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_vp, c_i32_p]),
@@ -375,6 +379,40 @@ def gemm_split(X, at, B, stream=None):
     _check(lib.nmf_gemm_split(_ptr(X), X.stride(0), int(at), _ptr(B), B.stride(0), K, N, _ptr(C), C.stride(0), M,
                               base, nb, _stream(stream)))
     return C
+
+
+class SplitProduct:
+    """op(X) B on split-BF16 operands with the thin operand B (K x N) split once;
+    run() launches only the product kernel (split-K partials, if any, land in
+    self.part and are summed by result(), in ascending order)."""
+
+    def __init__(self, X, at, B, stream=None):
+        lib = load()
+        if X.dtype != torch.float32 or B.dtype != torch.float32 or X.stride(1) != 1 or B.stride(1) != 1:
+            raise ValueError("X and B must be FP32 with unit column stride")
+        rows, cols = X.shape
+        self.M, self.K = (cols, rows) if at else (rows, cols)
+        if B.shape[0] != self.K:
+            raise ValueError("B must have op(X)'s inner dimension rows")
+        self.X, self.at, self.stream, self.N = X, int(at), stream, B.shape[1]
+        self.ldbt = -(-self.K // 64) * 64
+        self.Bh = torch.zeros(self.N, self.ldbt, dtype=torch.int16, device=X.device)
+        self.Bl = torch.zeros(self.N, self.ldbt, dtype=torch.int16, device=X.device)
+        _check(lib.nmf_split_prepare_thin(_ptr(B), B.stride(0), self.K, self.N, _ptr(self.Bh), _ptr(self.Bl),
+                                          self.ldbt, _stream(stream)))
+        self.splits = int(lib.nmf_gemm_split_splits(self.M, self.N, self.K))
+        self.part = torch.empty(self.splits, self.M, self.N, dtype=torch.float32, device=X.device)
+
+    def run(self):
+        _check(load().nmf_gemm_split_prepared(_ptr(self.X), self.X.stride(0), self.at, _ptr(self.Bh), _ptr(self.Bl),
+                                              self.ldbt, self.K, self.N, _ptr(self.part), self.N, self.M,
+                                              self.splits, _stream(self.stream)))
+
+    def result(self):
+        out = self.part[0].clone()
+        for z in range(1, self.splits):
+            out += self.part[z]
+        return out
 
 
 def orth(Y, stream=None):

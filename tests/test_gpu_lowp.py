@@ -171,6 +171,24 @@ def test_split_products(lib, m, n, k, at):
     assert np.all(np.abs(C - exact) <= (3.1 * 2.0 ** -16 + 3.0 * K * 2.0 ** -24) * absprod + 1e-30)
 
 
+@pytest.mark.parametrize("m,n,k,at", [(3001, 515, 140, 0), (515, 30001, 200, 1), (4096, 2048, 64, 1),
+                                      (70000, 300, 256, 0)])
+def test_split_product_prepared_equals_call(lib, m, n, k, at):
+    """The prepared split product (thin operand split once, product kernel alone,
+    partials summed in ascending order) gives nmf_gemm_split's result bit for bit."""
+    print(f"split prepared {m}x{n} k={k} at={at}", flush=True)
+    g = np.random.default_rng(m + n + k)
+    X = _padded(g.random((m, n)).astype(np.float32))
+    K = m if at else n
+    B = torch.from_numpy(g.standard_normal((K, k)).astype(np.float32)).cuda()
+    ref = lib.gemm_split(X, at, B)
+    P = lib.SplitProduct(X, at, B)
+    P.run()
+    got = P.result()
+    print(f"  splits {P.splits}", flush=True)
+    assert torch.equal(got, ref)
+
+
 def test_split_product_bad_arguments(lib):
     X = torch.zeros((64, 30), dtype=torch.float32, device="cuda")      # row stride 30: not a multiple of 4
     B = torch.zeros((30, 8), dtype=torch.float32, device="cuda")
