@@ -354,6 +354,23 @@ nmf_status nmf_orth(float* Y, int64_t ldy, int64_t rows, int32_t k, void* worksp
 nmf_status nmf_sym_eigvals(const double* A, int64_t lda, int32_t k, double* w, void* hip_stream,
                            int32_t* sweeps);
 
+/* Gini coefficient of a rows x cols FP32 matrix (device, row-major, ldb >= cols),
+ * the sparsity measure of Sec 5.1 for B:
+ *   G = sum_i (2 i - N - 1) b_(i) / (N sum_i b_i),  i = 1..N = rows cols,
+ * over the entries sorted ascending (b_(1) <= ... <= b_(N)).  G is 0 for a
+ * constant matrix and approaches 1 when one entry carries all of the sum.  The
+ * entries are sorted on the device (radix sort of order-preserving 32-bit keys)
+ * and both sums are formed in FP64 over the sorted order; equal values give the
+ * same sums in any order, so the result does not depend on how ties are broken.
+ * workspace: device, 256-byte aligned, nmf_gini_workspace_bytes(rows, cols)
+ * bytes, caller-owned.  Synchronising (the result is written to *gini on the
+ * host).  NMF_EINVAL for rows or cols < 1, N >= 2^32, ldb < cols, a null pointer
+ * or a workspace too small; NMF_ENONFINITE if an entry or the sum is not finite
+ * or the sum is 0 (G undefined). */
+size_t nmf_gini_workspace_bytes(int64_t rows, int64_t cols);
+nmf_status nmf_gini(const float* B, int64_t ldb, int64_t rows, int64_t cols, void* workspace, size_t ws_bytes,
+                    void* hip_stream, double* gini);
+
 
 /* --------------------------------------------------- learned warm start of H
  * Extension (the paper has no learned component): a multilayer perceptron maps

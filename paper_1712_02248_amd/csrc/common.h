@@ -165,6 +165,12 @@ hipError_t launch_sum_partials_f32(const float* part, int nparts, int64_t ne, do
 hipError_t launch_sum_partials_f64(const double* part, int nparts, int64_t ne, double* out,
                                    const int* skip, hipStream_t st);
 
+// Gini coefficient (gini.hip): out2[0] = sum_i (2 i - N - 1) b_(i) (sorted
+// ascending, i from 1), out2[1] = sum_i b_i, both FP64.
+size_t gini_workspace_bytes(int64_t rows, int64_t cols);
+hipError_t launch_gini(const float* B, int64_t ldb, int64_t rows, int64_t cols, void* ws, double* out2,
+                       hipStream_t st);
+
 // Residual (residual.hip): sum (X - W diag(sw) Ht^T)^2 and sum X^2 in FP64.
 int residual_blocks(int64_t m, int64_t n);
 int proxy_blocks(int64_t n);

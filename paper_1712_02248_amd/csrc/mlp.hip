@@ -487,32 +487,60 @@ infer_out_kernel(const float* __restrict__ Z3, const float* __restrict__ nrm, in
 }
 
 // Warm-start selection: rho(h) = ||x - Wh h||^2 in FP64 for the net's and the
-// cold rows; keep the net's row unless it is worse.  One wave per row.
+// cold rows; keep the net's row unless it is worse.  One wave per row; lane c
+// (and c + 64, ... up to k) forms (Wh h)_c with j ascending, the lanes' squared
+// differences are summed over c ascending and then across the wave.  Wh is
+// staged in LDS transposed (whs[j][c], row stride kpp = k rounded up to 64, zero
+// padded) so the lanes read consecutive words.
 __global__ void __launch_bounds__(256)
 select_kernel(const float* __restrict__ Xh, int64_t ldx, int n, int k, const float* __restrict__ Wh, int r,
               const float* __restrict__ Hn, const float* __restrict__ Hc, float* __restrict__ Hout,
               int* __restrict__ rejected) {
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (row >= n) return;
-  double rn = 0.0, rc = 0.0;
-  for (int c = lane; c < k; c += 64) {
-    double pn = 0.0, pc = 0.0;
-    for (int j = 0; j < r; ++j) {
-      const double w = Wh[c * r + j];
-      pn += w * Hn[(int64_t)row * r + j];
-      pc += w * Hc[(int64_t)row * r + j];
+  extern __shared__ float whs[];                 // r x kpp
+  __shared__ float hs[4][2][128];                // the wave's rows of Hn and Hc (r <= 128)
+  const int kpp = (k + 63) & ~63, nt = kpp >> 6;
+  for (int e = threadIdx.x; e < kpp * r; e += 256) {
+    const int j = e / kpp, c = e - j * kpp;
+    whs[e] = c < k ? Wh[c * r + j] : 0.f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int row = blockIdx.x * 4 + wave; row < n; row += gridDim.x * 4) {
+    double pn[4] = {0.0, 0.0, 0.0, 0.0}, pc[4] = {0.0, 0.0, 0.0, 0.0};
+    const float* hn = Hn + (int64_t)row * r;
+    const float* hc = Hc + (int64_t)row * r;
+    for (int j = lane; j < 128; j += 64) {
+      hs[wave][0][j] = j < r ? hn[j] : 0.f;
+      hs[wave][1][j] = j < r ? hc[j] : 0.f;
     }
-    const double x = Xh[(int64_t)row * ldx + c];
-    rn += (x - pn) * (x - pn);
-    rc += (x - pc) * (x - pc);
+    for (int j = 0; j < r; ++j) {
+      const double a = hs[wave][0][j], b = hs[wave][1][j];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < nt) {
+          const double w = whs[j * kpp + 64 * t + lane];
+          pn[t] += w * a;
+          pc[t] += w * b;
+        }
+    }
+    double rn = 0.0, rc = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = 64 * t + lane;
+      if (c < k) {
+        const double x = Xh[(int64_t)row * ldx + c];
+        rn += (x - pn[t]) * (x - pn[t]);
+        rc += (x - pc[t]) * (x - pc[t]);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      rn += __shfl_xor(rn, off);
+      rc += __shfl_xor(rc, off);
+    }
+    const bool rej = rn > rc;
+    for (int j = lane; j < r; j += 64) Hout[(int64_t)row * r + j] = rej ? hc[j] : hn[j];
+    if (lane == 0) rejected[row] = rej ? 1 : 0;
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    rn += __shfl_xor(rn, off);
-    rc += __shfl_xor(rc, off);
-  }
-  const bool rej = rn > rc;
-  for (int j = lane; j < r; j += 64) Hout[(int64_t)row * r + j] = rej ? Hc[(int64_t)row * r + j] : Hn[(int64_t)row * r + j];
-  if (lane == 0) rejected[row] = rej ? 1 : 0;
 }
 
 __global__ void count_kernel(const int* __restrict__ flags, int n, long long* __restrict__ out) {
@@ -628,8 +656,11 @@ hipError_t launch_count(const int* flags, int n, long long* count, hipStream_t s
 hipError_t launch_select(const float* Xh, int64_t ldx, int n, int k, const float* Wh, int r, const float* Hn,
                          const float* Hc, float* Hout, int* rejected, long long* count, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(select_kernel, dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, Xh, ldx, n, k, Wh, r,
-                     Hn, Hc, Hout, rejected);
+  if (k > 256 || r > 128) return hipErrorInvalidValue;
+  const int64_t nb = ceil_div(n, 4);
+  const size_t lds = (size_t)((k + 63) & ~63) * r * sizeof(float);
+  hipLaunchKernelGGL(select_kernel, dim3((unsigned)(nb < 256 ? nb : 256)), dim3(256), lds, st, Xh, ldx, n, k, Wh,
+                     r, Hn, Hc, Hout, rejected);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(count_kernel, dim3(1), dim3(256), 0, st, rejected, n, count);

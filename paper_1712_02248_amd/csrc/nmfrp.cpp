@@ -1396,4 +1396,32 @@ nmf_status nmf_sym_eigvals(const double* A, int64_t lda, int32_t k, double* w, v
   return NMF_OK;
 }
 
+size_t nmf_gini_workspace_bytes(int64_t rows, int64_t cols) {
+  if (rows < 1 || cols < 1 || rows * cols >= (int64_t)1 << 32) return 0;
+  return gini_workspace_bytes(rows, cols);
+}
+
+nmf_status nmf_gini(const float* B, int64_t ldb, int64_t rows, int64_t cols, void* ws, size_t ws_bytes, void* hs,
+                    double* gini) {
+  if (!B || !ws || !gini || rows < 1 || cols < 1 || ldb < cols || rows * cols >= (int64_t)1 << 32 ||
+      ((uintptr_t)ws & 255) || ws_bytes < gini_workspace_bytes(rows, cols))
+    return fail(nullptr, NMF_EINVAL, "bad arguments");
+  double* ho = take_host_out();
+  double* hd = nullptr;
+  if (!ho || hipHostGetDevicePointer((void**)&hd, ho, 0) != hipSuccess) {
+    give_host_out(ho);
+    return fail(nullptr, NMF_ENOMEM, "no pinned result buffer");
+  }
+  hipStream_t st = (hipStream_t)hs;
+  hipError_t e = launch_gini(B, ldb, rows, cols, ws, hd, st);
+  if (!e) e = hipStreamSynchronize(st);
+  const double s1 = ho[0], s2 = ho[1];
+  give_host_out(ho);
+  if (e) return fail(nullptr, NMF_EHIP, hipGetErrorString(e));
+  if (!std::isfinite(s1) || !std::isfinite(s2) || s2 == 0.0)
+    return fail(nullptr, NMF_ENONFINITE, "Gini undefined (non-finite entries or a zero sum)");
+  *gini = s1 / ((double)(rows * cols) * s2);
+  return NMF_OK;
+}
+
 }  // extern "C"

@@ -423,20 +423,37 @@ quant_fp8_fused_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int6
 
 // B -> Bt in e4m3 for N <= 256 in one launch: one workgroup per 128-row block of
 // B (its exponent Ebt[block] as above from all N columns, then the transposed
-// codes of each 128-column half through LDS).
+// codes).  Wave w loads rows 32 w .. 32 w + 31 of the block, lane l columns
+// 4 l .. 4 l + 3 (one 1 KB row segment per wave and load, all 32 loads in
+// flight); the codes of four consecutive rows of a column are packed into one
+// word of T[c][w4] (rows 4 w4 .. 4 w4 + 3; row stride 33 words), and eight
+// threads per column store its 128 codes as 16-byte chunks.
+template <bool VEC>
 __global__ void __launch_bounds__(256)
 prep_bt_fp8_kernel(const float* __restrict__ B, int64_t ldb, int64_t K, int64_t N, int* __restrict__ Ebt,
                    uint8_t* __restrict__ Bt, int64_t ldbt) {
-  __shared__ float T[128][129];          // T[j][k] of the current column half
+  __shared__ uint32_t T[256 * 33];
   __shared__ float wmax[4];
   __shared__ int sexp;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t k0 = (int64_t)blockIdx.x * 128;
-  const int nn = (int)N;
+  const int64_t k0 = (int64_t)blockIdx.x * 128 + 32 * wave;
+  const int nn = (int)N, c0 = 4 * lane;
+  f32x4 v[32];
   float amax = 0.f;
-  for (int e = tid; e < 128 * nn; e += 256) {
-    const int k = e / nn, j = e % nn;
-    if (k0 + k < K) amax = fmaxf(amax, fabsf(B[(k0 + k) * ldb + j]));
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const int64_t k = k0 + i;
+    f32x4 x = {0.f, 0.f, 0.f, 0.f};
+    if (VEC) {
+      if (k < K && c0 < nn) x = *(const f32x4*)(B + k * ldb + c0);   // N % 4 == 0
+    } else {
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        if (k < K && c0 + d < nn) x[d] = B[k * ldb + c0 + d];
+    }
+    v[i] = x;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) amax = fmaxf(amax, fabsf(x[d]));
   }
   for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off));
   if (lane == 0) wmax[wave] = amax;
@@ -448,21 +465,21 @@ prep_bt_fp8_kernel(const float* __restrict__ B, int64_t ldb, int64_t K, int64_t 
   }
   __syncthreads();
   const float s = ldexpf(1.0f, -sexp);
-  for (int j0 = 0; j0 < nn; j0 += 128) {
-    const int nh = nn - j0 < 128 ? nn - j0 : 128;
-    for (int e = tid; e < 128 * nh; e += 256) {
-      const int k = e / nh, j = e % nh;
-      T[j][k] = (k0 + k < K) ? B[(k0 + k) * ldb + j0 + j] : 0.f;
-    }
-    __syncthreads();
-    for (int e = tid; e < 32 * nh; e += 256) {
-      const int j = e >> 5, w = e & 31;
-      uint32_t o = 0;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) o |= (uint32_t)e4m3_rne(T[j][4 * w + k] * s) << (8 * k);
-      *(uint32_t*)(Bt + (int64_t)(j0 + j) * ldbt + k0 + 4 * w) = o;
+  for (int d = 0; d < 4; ++d)
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      uint32_t w = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) w |= (uint32_t)e4m3_rne(v[4 * a + b][d] * s) << (8 * b);   // padding: code 0
+      T[(c0 + d) * 33 + 8 * wave + a] = w;
     }
-    __syncthreads();
+  __syncthreads();
+  const int w4 = 4 * (tid & 7);
+  for (int j = tid >> 3; j < nn; j += 32) {
+    const uint32_t* t = T + j * 33 + w4;
+    const i32x4 o = {(int)t[0], (int)t[1], (int)t[2], (int)t[3]};
+    *(i32x4*)(Bt + (int64_t)j * ldbt + (int64_t)blockIdx.x * 128 + 4 * w4) = o;
   }
 }
 
@@ -543,9 +560,13 @@ hipError_t launch_prep_b_bf16(const float* B, int64_t ldb, int64_t K, int64_t N,
 
 hipError_t launch_prep_b_fp8(const float* B, int64_t ldb, int64_t K, int64_t N, int* Ebt, uint8_t* Bt,
                              int64_t ldbt, hipStream_t st) {
-  if (N <= 256 && ldbt % 128 == 0) {   // one launch; also sets the exponents of the zero padding blocks (0)
-    hipLaunchKernelGGL(prep_bt_fp8_kernel, dim3((unsigned)(ldbt / 128)), dim3(256), 0, st, B, ldb, K, N, Ebt, Bt,
-                       ldbt);
+  if (N <= 256 && ldbt % 128 == 0 && ((uintptr_t)Bt & 15) == 0) {
+    // one launch; also sets the exponents of the zero padding blocks (0)
+    const dim3 grid((unsigned)(ldbt / 128));
+    if (N % 4 == 0 && ldb % 4 == 0 && ((uintptr_t)B & 15) == 0)
+      hipLaunchKernelGGL(prep_bt_fp8_kernel<true>, grid, dim3(256), 0, st, B, ldb, K, N, Ebt, Bt, ldbt);
+    else
+      hipLaunchKernelGGL(prep_bt_fp8_kernel<false>, grid, dim3(256), 0, st, B, ldb, K, N, Ebt, Bt, ldbt);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(prep_b_fp8_exp_kernel, dim3((unsigned)ceil_div(K, 128)), dim3(256), 0, st, B, ldb, K,

@@ -214,25 +214,55 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
 // Sketch-only proxy of the residual (Sec 3: Q_L Q_L^T X approximates X):
 //   e_p^2 = (||X||^2 - ||Xh||^2 + sum_j ||xh_j - Wh h_j||^2) / ||X||^2,
 // exact when the columns of W lie in range(Q_L).  Per row j of Xh (n x k') and
-// Ht (n x r), one wave: lane c forms d_c = xh_jc - sum_l Wh[c][l] h_jl.
+// Ht (n x r), one wave: lane c (and c + 64, ..., up to k') forms
+// d_c = xh_jc - sum_l Wh[c][l] h_jl, l ascending, in FP64.  Wh is staged
+// transposed (whs[l][c], row stride kpp = k' rounded up to 64, zero padded) so
+// the lanes of a wave read consecutive words.
 // Block partials (two FP64 sums) go to part[2 blockIdx.x + {0, 1}].
 __global__ void __launch_bounds__(256)
 proxy_kernel(const float* __restrict__ Xh, int64_t ldx, const float* __restrict__ Ht, int r,
              const float* __restrict__ Wh, int kp, int64_t n, double* __restrict__ part) {
-  extern __shared__ float whs[];                 // kp x r
+  extern __shared__ float whs[];                 // r x kpp
   __shared__ double red[2][256];
-  for (int e = threadIdx.x; e < kp * r; e += 256) whs[e] = Wh[e];
+  __shared__ float hrow[4][128];                 // the wave's current row of Ht (r <= 128)
+  const int kpp = (kp + 63) & ~63, nt = kpp >> 6;
+  for (int e = threadIdx.x; e < kpp * r; e += 256) {
+    const int l = e / kpp, c = e - l * kpp;
+    whs[e] = c < kp ? Wh[c * r + l] : 0.f;
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double sd = 0.0, sx = 0.0;
-  for (int64_t row = (int64_t)blockIdx.x * 4 + wave; row < n; row += (int64_t)gridDim.x * 4) {
-    for (int c = lane; c < kp; c += 64) {
-      double acc = 0.0;
-      for (int l = 0; l < r; ++l) acc += (double)whs[c * r + l] * (double)Ht[row * r + l];
-      const double x = Xh[row * ldx + c];
-      const double d = x - acc;
-      sd += d * d;
-      sx += x * x;
+  const int64_t step = (int64_t)gridDim.x * 4;
+  int64_t row = (int64_t)blockIdx.x * 4 + wave;
+  float h0 = 0.f, h1 = 0.f;                      // the row's entries lane, lane + 64
+  if (row < n) {
+    h0 = lane < r ? Ht[row * r + lane] : 0.f;
+    h1 = lane + 64 < r ? Ht[row * r + lane + 64] : 0.f;
+  }
+  for (; row < n; row += step) {
+    hrow[wave][lane] = h0;
+    hrow[wave][lane + 64] = h1;
+    if (row + step < n) {                        // the next row's loads stay in flight
+      h0 = lane < r ? Ht[(row + step) * r + lane] : 0.f;
+      h1 = lane + 64 < r ? Ht[(row + step) * r + lane + 64] : 0.f;
+    }
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int l = 0; l < r; ++l) {
+      const double hl = (double)hrow[wave][l];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < nt) acc[t] += (double)whs[l * kpp + 64 * t + lane] * hl;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = 64 * t + lane;
+      if (c < kp) {
+        const double x = Xh[row * ldx + c];
+        const double d = x - acc[t];
+        sd += d * d;
+        sx += x * x;
+      }
     }
   }
   red[0][threadIdx.x] = sd;
@@ -491,7 +521,8 @@ int proxy_blocks(int64_t n) {
 
 hipError_t launch_proxy(const float* Xh, int64_t ldx, const float* Ht, int r, const float* Wh, int kp, int64_t n,
                         double* part, hipStream_t st) {
-  const size_t lds = (size_t)kp * r * sizeof(float);
+  if (kp > 256 || r > 128) return hipErrorInvalidValue;
+  const size_t lds = (size_t)((kp + 63) & ~63) * r * sizeof(float);
   hipLaunchKernelGGL(proxy_kernel, dim3(proxy_blocks(n)), dim3(256), lds, st, Xh, ldx, Ht, r, Wh, kp, n, part);
   return hipGetLastError();
 }

@@ -75,6 +75,8 @@ _SIGS = {
     "nmf_orth_workspace_bytes": (c_sz, [c_i64, c_i32]),
     "nmf_orth": (c_i32, [c_vp, c_i64, c_i64, c_i32, c_vp, c_sz, c_vp, c_i32_p]),
     "nmf_sym_eigvals": (c_i32, [c_vp, c_i64, c_i32, c_vp, c_vp, c_i32_p]),
+    "nmf_gini_workspace_bytes": (c_sz, [c_i64, c_i64]),
+    "nmf_gini": (c_i32, [c_vp, c_i64, c_i64, c_i64, c_vp, c_sz, c_vp, c_dbl_p]),
     "nmf_mlp_n_params": (c_i64, [c_i32, c_i32, c_i32]),
     "nmf_mlp_workspace_bytes": (c_sz, [c_i32, c_i32, c_i32, c_i32]),
     "nmf_mlp_create": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_vp, c_vp, c_sz, c_vp, ctypes.POINTER(c_vp)]),
@@ -438,6 +440,23 @@ def sym_eigvals(A, stream=None):
     sw = c_i32()
     _check(lib.nmf_sym_eigvals(_ptr(A), A.stride(0), k, _ptr(w), _stream(stream), ctypes.byref(sw)))
     return w, sw.value
+
+
+def gini(B, stream=None):
+    """Gini coefficient (Sec 5.1) of the float32 device matrix B (rows x cols,
+    row-major, unit column stride), sorted on the device; returns a float."""
+    lib = load()
+    if B.dtype != torch.float32 or B.dim() != 2 or not B.is_cuda or B.stride(1) != 1:
+        raise ValueError("B must be a row-major float32 device matrix")
+    rows, cols = B.shape
+    nb = lib.nmf_gini_workspace_bytes(rows, cols)
+    if nb == 0:
+        _check(-1)
+    ws = torch.empty(nb + 256, dtype=torch.uint8, device=B.device)
+    base = (ws.data_ptr() + 255) // 256 * 256
+    g = ctypes.c_double()
+    _check(lib.nmf_gini(_ptr(B), B.stride(0), rows, cols, base, nb, _stream(stream), ctypes.byref(g)))
+    return g.value
 
 
 def quantize_x(X, prec, stream=None):

@@ -108,8 +108,12 @@ def test_c2_full_size_uncompressed_fasthals_matches_oracle(lib):
         ctx.fasthals_step(Xd, 1)
         W, Ht = onmf.fasthals_iteration(X, W, Ht)
         Wg, Hg = (t.cpu().numpy().astype(np.float64) for t in ctx.factors())
-        tol = 2e-3 * it
-        print(f"  it={it} max|dW|={np.abs(Wg - W).max():.2e} max|dH|={np.abs(Hg - Ht).max():.2e}", flush=True)
+        tol = 1e-4 * it      # measured 2.0e-5 and 2.5e-5 of the largest entry
+        print(f"  it={it} max|dW|={np.abs(Wg - W).max():.2e} max|dH|={np.abs(Hg - Ht).max():.2e} "
+              f"|dW|/|W|={np.linalg.norm(Wg - W) / np.linalg.norm(W):.2e} "
+              f"|dH|/|H|={np.linalg.norm(Hg - Ht) / np.linalg.norm(Ht):.2e} "
+              f"max rel {np.abs(Wg - W).max() / np.abs(W).max():.2e} {np.abs(Hg - Ht).max() / np.abs(Ht).max():.2e}",
+              flush=True)
         assert np.abs(Wg - W).max() <= tol * np.abs(W).max(), it
         assert np.abs(Hg - Ht).max() <= tol * np.abs(Ht).max(), it
         assert abs(ctx.residual(Xd) - onmf.rel_error(X, W, Ht)) <= 1e-4, it
@@ -175,3 +179,66 @@ def test_c3_full_size_bf16_within_gate_of_oracle(lib):
         assert abs(e - e_ref) <= 1e-4, it
         checked += 1
     assert checked >= 5
+
+
+def test_c2_full_size_warm_start_matches_oracle(lib):
+    """The warm start at full size with the benchmark's network shape and sweep
+    count (nmf_init_learned_ref, 20 column-NNLS sweeps; device-drawn test
+    matrices, FP32 compression: the warm start does not depend on how the
+    sketches were formed, and the oracle's exact compression takes seconds where
+    its low-precision model takes minutes), against the oracle on sampled rows
+    of H: the network's rows on the aligned compressed columns, the per-row
+    rejection by rho(h) = ||x-hat - Q_L^T W_ref h||^2 and the sweeps.  Each side
+    forms the alignment products from its own Q_L; rows are independent, so the
+    oracle computes only the sampled ones.  The network is untrained (He init),
+    the stand-in for Q_train is a Gaussian m x k' matrix scaled by 1/sqrt(m), and
+    the cold rows alternate between zero (the network loses there) and far off
+    (it wins), so both branches run."""
+    from oracle import mlp as omlp
+    from oracle import nmf as onmf
+    from oracle import philox as ophilox
+    print("c2 full size warm start: generating X", flush=True)
+    name = "c2"
+    c = datagen.CONFIGS[name]
+    m, n, r, kp, q = c["m"], c["n"], c["r"], c["kp"], c["q"]
+    seed = datagen.cfg_seed(name)
+    X = datagen.make_x(name)
+    hdim, sweeps = 512, 20
+    p0 = datagen.mlp_he_init(kp, hdim, r, seed=77)
+    G = datagen.gaussian(m, kp, seed + 1, datagen.S_FRESH) / np.float32(np.sqrt(m))   # stands in for Q_train
+    Wref = datagen.uniform((m, r), seed + 2, datagen.S_FRESH)
+    Hcold = (1e3 * datagen.uniform((n, r), seed + 3, datagen.S_FRESH)).astype(np.float32)
+    Hcold[0::2] = 0.0
+    # ---- HIP path
+    Xd = torch.from_numpy(X).cuda()
+    ctx = lib.NMF(m, n, r, kp, q, seed=seed)
+    ctx.compress(Xd)
+    net = lib.Mlp(kp, hdim, r, torch.from_numpy(p0).cuda(), max_batch=4096)
+    nrej = ctx.init_learned_ref(net, torch.from_numpy(G).cuda(), torch.from_numpy(Wref).cuda(),
+                                Ht_cold=torch.from_numpy(Hcold).cuda(), refine_sweeps=sweeps)
+    Wg, Hg = (t.cpu().numpy().astype(np.float64) for t in ctx.factors())
+    assert np.array_equal(Wg, Wref.astype(np.float64))
+    # ---- oracle, sampled rows
+    print("  oracle compression", flush=True)
+    OL = ophilox.normal(n, kp, 3, seed).astype(np.float32)
+    OR = ophilox.normal(m, kp, 4, seed).astype(np.float32)
+    QL, _, Xh, _ = onmf.compress(X, OL, OR, q)
+    M = G.T.astype(np.float64) @ QL
+    Wh = QL.T @ Wref.astype(np.float64)
+    rows = np.unique(np.concatenate([[0, 1, 2, 3, n - 2, n - 1],
+                                     np.random.default_rng(seed).choice(n, 250, replace=False)]))
+    P = omlp.unflatten(p0.astype(np.float64), kp, hdim, r)
+    xs = Xh[rows]
+    Hn = omlp.infer(P, xs @ M.T)
+    Hsel, rej = omlp.select_warm(xs, Wh, Hn, Hcold[rows])
+    rho_n = np.sum((xs - Hn @ Wh.T) ** 2, 1)
+    rho_c = np.sum((xs - Hcold[rows].astype(np.float64) @ Wh.T) ** 2, 1)
+    clear = np.abs(rho_n - rho_c) > 1e-3 * rho_c
+    assert 0 < rej[clear].sum() < clear.sum() and clear.sum() > 0.9 * len(rows)
+    Href = onmf.column_nnls(xs, Wh, sweeps, Ht0=Hsel)
+    err = (np.abs(Hg[rows] - Href) / (np.abs(Href).max(axis=1, keepdims=True) + 1e-30))[clear]
+    print(f"  {len(rows)} rows ({clear.sum()} decided clearly, {rej[clear].sum()} rejected), "
+          f"rejected in all {nrej}, largest row-relative gap {err.max():.2e}", flush=True)
+    assert err.max() <= 1e-4
+    del Xd
+    torch.cuda.empty_cache()

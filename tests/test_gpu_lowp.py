@@ -57,7 +57,8 @@ def test_quantize_fp8_matches_block_model(lib, m, n):
 @pytest.mark.parametrize("fmt,m,n,k,side", [("bf16", 1000, 300, 20, 0), ("bf16", 1000, 300, 64, 1),
                                             ("bf16", 4096, 2048, 128, 1), ("fp8", 1000, 300, 20, 0),
                                             ("fp8", 1000, 300, 64, 1), ("fp8", 2048, 4096, 128, 0),
-                                            ("bf16", 300, 5000, 256, 0), ("fp8", 513, 700, 256, 1)])
+                                            ("bf16", 300, 5000, 256, 0), ("fp8", 513, 700, 256, 1),
+                                            ("fp8", 1000, 300, 21, 1), ("fp8", 3000, 260, 256, 1)])
 def test_lowp_products(lib, fmt, m, n, k, side):
     print(f"lowp gemm {fmt} {m}x{n} k={k} side={side}", flush=True)
     X = _x(m, n, m + 3 * n + k, spread=False)

@@ -122,16 +122,23 @@ def test_c1_first_iterations_elementwise(lib, normalize):
         W, Ht = W0.astype(np.float64), H0.astype(np.float64)
         for _ in range(iters):
             W, Ht = onmf.fasthals_rp_iteration(W, Ht, rXh, rXc, rQL, rQR, normalize)
-        tol = 2e-3 * iters
-        assert np.abs(Wg - W).max() <= tol * np.abs(W).max(), iters
-        assert np.abs(Hg - Ht).max() <= tol * np.abs(Ht).max(), iters
+        dw = np.linalg.norm(Wg - W) / np.linalg.norm(W)
+        dh = np.linalg.norm(Hg - Ht) / np.linalg.norm(Ht)
+        mw = np.abs(Wg - W).max() / np.abs(W).max()
+        mh = np.abs(Hg - Ht).max() / np.abs(Ht).max()
+        print(f"  it={iters} |dW|/|W|={dw:.2e} |dH|/|H|={dh:.2e} max {mw:.2e} {mh:.2e}", flush=True)
+        # FP32 arithmetic against FP64: measured at most 2.7e-5 of the largest
+        # entry and 1.8e-5 in relative norm over these cases (five iterations,
+        # the literal normalisation the largest); the gates sit 4-30x above
+        assert mw <= 1e-4 * iters and mh <= 1e-4 * iters, iters
+        assert dw <= 5e-5 * iters and dh <= 5e-5 * iters, iters
         assert (Wg >= 0).all() and (Hg >= 0).all()
 
 
 @pytest.mark.parametrize("normalize", [1, 0, 2])
 def test_uncompressed_fasthals_matches_oracle(lib, normalize):
     """nmf_fasthals_step (Sec 2.2, on X itself) against the oracle's textbook
-    FastHALS: factors after 1, 2 and 5 iterations, elementwise (the tolerance of
+    FastHALS: factors after 1, 2 and 5 iterations, elementwise (the tolerances of
     the compressed iterations), and the compressed update continuing from them."""
     print(f"uncompressed fasthals normalize={normalize}", flush=True)
     m, n, r, kp, q = 512, 256, 10, 20, 2
@@ -141,9 +148,16 @@ def test_uncompressed_fasthals_matches_oracle(lib, normalize):
         ctx.fasthals_step(Xd, iters)
         Wg, Hg = (t.cpu().numpy().astype(np.float64) for t in ctx.factors())
         W, Ht = onmf.fasthals(X, W0, H0, iters, normalize)
-        tol = 2e-3 * iters
-        assert np.abs(Wg - W).max() <= tol * np.abs(W).max(), iters
-        assert np.abs(Hg - Ht).max() <= tol * np.abs(Ht).max(), iters
+        dw = np.linalg.norm(Wg - W) / np.linalg.norm(W)
+        dh = np.linalg.norm(Hg - Ht) / np.linalg.norm(Ht)
+        mw = np.abs(Wg - W).max() / np.abs(W).max()
+        mh = np.abs(Hg - Ht).max() / np.abs(Ht).max()
+        print(f"  it={iters} |dW|/|W|={dw:.2e} |dH|/|H|={dh:.2e} max {mw:.2e} {mh:.2e}", flush=True)
+        # FP32 arithmetic against FP64: measured at most 2.7e-5 of the largest
+        # entry and 1.8e-5 in relative norm over these cases (five iterations,
+        # the literal normalisation the largest); the gates sit 4-30x above
+        assert mw <= 1e-4 * iters and mh <= 1e-4 * iters, iters
+        assert dw <= 5e-5 * iters and dh <= 5e-5 * iters, iters
         assert (Wg >= 0).all() and (Hg >= 0).all()
         assert abs(ctx.residual(Xd) - onmf.rel_error(X, W, Ht)) <= 1e-4
     # the compressed update picks up from the uncompressed factors (Q_R^T Ht refreshed)
@@ -316,8 +330,13 @@ def test_sparsity_smoothness_rule_matches_oracle(lib, alpha, beta):
     Wg, Hg = (t.cpu().numpy().astype(np.float64) for t in ctx.factors())
     ref = onmf.fasthals_rp(X, OL, OR, q, W0, H0, iters, normalize=0, alpha=alpha, beta=beta)
     assert abs(e - ref["e"]) <= 1e-4
-    assert np.abs(Hg - ref["Ht"]).max() <= 2e-3 * np.abs(ref["Ht"]).max()
-    assert np.abs(Wg - ref["W"]).max() <= 2e-3 * np.abs(ref["W"]).max()
+    print(f"  |dW|/|W|={np.linalg.norm(Wg - ref['W']) / np.linalg.norm(ref['W']):.2e} "
+          f"|dH|/|H|={np.linalg.norm(Hg - ref['Ht']) / np.linalg.norm(ref['Ht']):.2e} "
+          f"max {np.abs(Wg - ref['W']).max() / np.abs(ref['W']).max():.2e} "
+          f"{np.abs(Hg - ref['Ht']).max() / np.abs(ref['Ht']).max():.2e}", flush=True)
+    # measured at most 1.4e-5 of the largest entry after the 20 iterations
+    assert np.abs(Hg - ref["Ht"]).max() <= 2e-4 * np.abs(ref["Ht"]).max()
+    assert np.abs(Wg - ref["W"]).max() <= 2e-4 * np.abs(ref["W"]).max()
     # the L1 term produces exact zeros in B where the oracle has them
     zo = ref["Ht"] == 0
     if alpha > 0:
