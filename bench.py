@@ -17,7 +17,8 @@ Workloads (default c5):
       iteration per side on X (split-BF16 products), split-BF16 sketch products,
       then the learned warm start: W from the reference dictionary, H rows from
       the network on the compressed columns, each kept only if it beats the cold
-      row on the compressed residual, then column-NNLS sweeps.
+      row on the compressed residual, then column-NNLS sweeps; the iterations'
+      products on split-BF16 MFMA (`fp8_warm_fp32_updates` keeps them FP32).
   c2  X 65536 x 4096 (parts family), r = 32, k' = 64, q = 2, 500 iterations.
       Headline `bf16_warm`: BF16 range finder, split-BF16 sketches, warm start.
 Every workload also times plain FP32 FastHALS-RP from the cold factors (the
@@ -236,10 +237,10 @@ def warm_start(ctx, warm, W0d, H0d, count=False):
 
 
 def time_variant(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, prec, refine, warm, steps, warmup,
-                 label="", lps=0):
+                 label="", lps=0, up=0):
     m, n, r, kp, q = cfg["m"], cfg["n"], cfg["r"], cfg["kp"], cfg["q"]
     max_iters = args.max_iters or cfg["iters"]
-    ctx = nmfrp.NMF(m, n, r, kp, q, seed=seed, prec=prec, refine_fp32=refine, lowp_sketches=lps)
+    ctx = nmfrp.NMF(m, n, r, kp, q, seed=seed, prec=prec, refine_fp32=refine, lowp_sketches=lps, update_prec=up)
 
     def start(count=False):
         ctx.compress(Xd)
@@ -666,19 +667,21 @@ def main():
         return (net, Q_train, W_ref, sweeps, mode)
 
     # (name, prec, refinement (0 none, 1 FP32, 2 split-BF16), warm start, sketch
-    #  products (0 FP32, 1 low precision, 2 split BF16), steps, warmup)
+    #  products (0 FP32, 1 low precision, 2 split BF16), steps, warmup[, update
+    #  products (0 FP32, 1 split BF16)])
     S, W_ = args.steps, args.warmup
     if name == "c5":
         variants = [("plain", F32, 0, None, 0, S, W_),
-                    (head_name, F8, 2, warm(), 2, S, W_)]
-        extra = [("fp8_warm_fp32_refine", F8, 1, warm(), 2, 2, 1),
-                 ("fp8_ctrl_no_net", F8, 2, warm("no_net"), 2, 3, 1),
-                 ("fp8_net_cold_w", F8, 2, warm("cold_w"), 2, 2, 1),
-                 ("fp8_net_no_sweeps", F8, 2, warm(sweeps=0), 2, 3, 1),
-                 ("fp8_refine", F8, 2, None, 2, 2, 1),
-                 ("bf16_warm", BF, 0, warm(), 2, 3, 1),
-                 ("bf16", BF, 0, None, 2, 2, 1),
-                 ("fp32_warm", F32, 0, warm(), 2, 3, 1)]
+                    (head_name, F8, 2, warm(), 2, S, W_, 1)]
+        extra = [("fp8_warm_fp32_updates", F8, 2, warm(), 2, 2, 1, 0),
+                 ("fp8_warm_fp32_refine", F8, 1, warm(), 2, 2, 1, 1),
+                 ("fp8_ctrl_no_net", F8, 2, warm("no_net"), 2, 2, 1, 1),
+                 ("fp8_net_cold_w", F8, 2, warm("cold_w"), 2, 2, 1, 1),
+                 ("fp8_net_no_sweeps", F8, 2, warm(sweeps=0), 2, 2, 1, 1),
+                 ("fp8_refine", F8, 2, None, 2, 2, 1, 1),
+                 ("bf16_warm", BF, 0, warm(), 2, 3, 1, 1),
+                 ("bf16", BF, 0, None, 2, 2, 1, 1),
+                 ("fp32_warm", F32, 0, warm(), 2, 2, 1)]
     else:
         variants = [("plain", F32, 0, None, 0, S, W_),
                     (head_name, BF, 0, warm(), 2, S, W_)]
@@ -700,9 +703,9 @@ def main():
         keep = args.variants.split(",")
         variants = [v for v in variants if v[0] in keep]
     out = {}
-    for vname, prec, refine, w, lps, steps, warmup in variants:
+    for vname, prec, refine, w, lps, steps, warmup, *up in variants:
         v = time_variant(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, prec, refine, w, steps, warmup,
-                         label=vname, lps=lps)
+                         label=vname, lps=lps, up=up[0] if up else 0)
         out[vname] = v
         log(f"[bench] {vname}: median {statistics.median(v['times']) * 1e3:.2f} ms, iters {v['iters']}, "
             f"e_init {v['e_init']:.4e}, e {v['e'][-1]:.6e}, rejected {v['rejected']}")
@@ -739,7 +742,8 @@ def main():
     vmed = statistics.median(head["times"])
     pmed = statistics.median(plain["times"]) if plain else None
     hdesc = ("FP8 e4m3 range finder (128 x 128 block scales) with one split-BF16 refinement power iteration per "
-             "side, split-BF16 sketches" if name == "c5" else "BF16 range finder, split-BF16 sketches")
+             "side, split-BF16 sketches and update products" if name == "c5" else
+             "BF16 range finder, split-BF16 sketches")
     line = dict(
         metric=f"time-to-rel-error eps (s), {'FP8' if name == 'c5' else 'BF16'} compression + learned warm start "
                "(plain FP32 alongside)",

@@ -73,7 +73,13 @@ typedef struct {
                             X (see nmf_gemm_split), about 16 significant bits per
                             term.  ||X||^2 for nmf_proxy_residual comes from the
                             X Q_R pass (0, 2) or the quantiser (1). */
-  int32_t reserved;      /* must be 0 */
+  int32_t update_prec;   /* products of the update loop (extension): 0 FP32 MFMA; 1
+                            split-BF16 MFMA (v = hi + lo as in nmf_gemm_split, terms
+                            hi hi + hi lo + lo hi, FP32 accumulation: within
+                            3.03 2^-16 |a||b| per term, the order of FP32's own
+                            accumulation error over the k' + r terms).  1 needs the
+                            wide-factor half-steps (r > 64 or k' > 128), else
+                            NMF_EINVAL. */
 } nmf_params;
 
 /* ---------------------------------------------------------------- context */

@@ -141,6 +141,7 @@ struct HalfStepArgs {
   float alpha, beta;    // sparsity / smoothness (0, 0 = plain rule)
   float* gbuf;          // N x r scratch (wide-factor path, with a sweep)
   float* aux;           // halfstep_big_aux_floats() scratch (wide-factor path)
+  int split;            // wide-factor path: 1 = products on split-BF16 MFMA instead of FP32 MFMA
 };
 int halfstep_blocks(int64_t N);
 size_t halfstep_part_floats(int64_t N, int kp, int r);

@@ -296,6 +296,204 @@ hs_grad_kernel(const float* __restrict__ S, int64_t lds, const float* __restrict
     }
 }
 
+// hi and lo BF16 halves of (a, b), packed (a in the low half), nearest even:
+// v = hi + lo + d with |d| <= 2^-16 |v|, v - hi exact in FP32.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+NMF_DEV void split_pair(float a, float b, uint32_t& h, uint32_t& l) {
+  const f32x2_t v = {a, b};
+  h = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
+  const f32x2_t w = {a - __builtin_bit_cast(float, h << 16), b - __builtin_bit_cast(float, h & 0xFFFF0000u)};
+  l = __builtin_bit_cast(uint32_t, __builtin_convertvector(w, bf16x2_t));
+}
+
+// The gradient product of hs_grad_kernel on split-BF16 MFMA: every operand
+// value v is carried as hi + lo (hi = bf16(v), lo = bf16(v - hi)) and a term as
+// hi hi + hi lo + lo hi on v_mfma_f32_32x32x16_bf16 with FP32 accumulation
+// (within 3.03 2^-16 |s||c| of the exact term; FP32 accumulation over the
+// k' + r terms is of the same order).  Loads, masks, scales and the epilogue
+// are those of the FP32 kernel.  The split happens when a step is stored to LDS:
+// A rows and the transposed B rows are K-contiguous halves with row stride 40
+// (16-byte fragment reads of 16 consecutive rows fall in distinct banks); a
+// lane's fragment is the 8 values k = 8 (lane / 32) .. +7 of a 16-deep substep.
+template <int BM, bool FVEC>
+__global__ void __launch_bounds__(256)
+hs_grad_split_kernel(const float* __restrict__ S, int64_t lds, const float* __restrict__ F,
+                     const float* __restrict__ scl, const float* __restrict__ Cp, const float* __restrict__ Gp,
+                     const float* __restrict__ rdiag, float alpha, float* __restrict__ gout, int64_t N, int kp,
+                     int r) {
+  constexpr int BK = 32, BN = BR, WM = 2, WN = 2, ST = BK + 8;
+  constexpr int TM = BM / WM / 32, TN = BN / WN / 32;
+  constexpr int AP = BM * BK / 4 / 256;    // A float4 per thread
+  static_assert(BK * BN / 16 == 256, "one 4 x 4 block of B per thread");
+  __shared__ __attribute__((aligned(16))) uint16_t AsH[BM * ST], AsL[BM * ST];
+  __shared__ __attribute__((aligned(16))) uint16_t BsH[BN * ST], BsL[BN * ST];   // Bs[j][k] = B[k][j]
+  __shared__ float sc[BR], rdl[BR];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t i0 = (int64_t)blockIdx.x * BM;
+  if (tid < BR) {
+    sc[tid] = scl[tid];
+    rdl[tid] = rdiag[tid];
+  }
+  const bool anykept = __syncthreads_or(tid < r && rdiag[tid] == 0.f);
+  const int ks = (kp + BK - 1) / BK;
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int x = 0; x < TM; ++x)
+#pragma unroll
+    for (int y = 0; y < TN; ++y)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[x][y][e] = 0.f;
+  f32x4 ra[AP];
+  f32x4 rb[4];
+  const int kq = tid >> 5, c4 = tid & 31, ca = 4 * (tid & 7);
+  auto kept = [&](int l) { return l < r && rdl[l] == 0.f; };
+  auto loadS = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < AP; ++p) {
+      const int64_t gi = i0 + (tid >> 3) + 32 * p;
+      const bool ok = gi < N && k0 + ca < kp;
+      ra[p] = *(const f32x4*)(S + (ok ? gi * lds + k0 + ca : 0));
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rb[e] = *(const f32x4*)(Cp + (int64_t)(k0 + 4 * kq + e) * BR + 4 * c4);
+  };
+  auto loadF = [&](int k0) {
+#pragma unroll
+    for (int p = 0; p < AP; ++p) {
+      const int64_t gi = i0 + (tid >> 3) + 32 * p;
+      if (FVEC) {
+        const bool ok = gi < N && k0 + ca < r;
+        ra[p] = *(const f32x4*)(F + (ok ? gi * r + k0 + ca : 0));
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ra[p][e] = F[(gi < N && k0 + ca + e < r) ? gi * r + k0 + ca + e : 0];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rb[e] = *(const f32x4*)(Gp + (int64_t)(k0 + 4 * kq + e) * BR + 4 * c4);
+  };
+  auto put = [&](uint16_t* H, uint16_t* L, int off, const f32x4& v) {
+    uint32_t h0, l0, h1, l1;
+    split_pair(v[0], v[1], h0, l0);
+    split_pair(v[2], v[3], h1, l1);
+    *(uint2*)(H + off) = make_uint2(h0, h1);
+    *(uint2*)(L + off) = make_uint2(l0, l1);
+  };
+  auto storeA = [&](int k0, int lim, bool fs) {
+#pragma unroll
+    for (int p = 0; p < AP; ++p) {
+      const int row = (tid >> 3) + 32 * p;
+      const bool rok = i0 + row < N;
+      f32x4 v;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float x = fs ? ra[p][e] * sc[k0 + ca + e] : ra[p][e];
+        v[e] = (rok && k0 + ca + e < lim) ? x : 0.f;
+      }
+      put(AsH, AsL, row * ST + ca, v);
+    }
+  };
+  auto storeS = [&](int k0) {
+    storeA(k0, kp, false);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int l = 4 * c4 + d;
+      f32x4 v;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] = k0 + 4 * kq + e < kp ? rb[e][d] : 0.f;
+      if (anykept && kept(l)) v = (f32x4){0.f, 0.f, 0.f, 0.f};
+      put(BsH, BsL, l * ST + 4 * kq, v);
+    }
+  };
+  auto storeF = [&](int k0) {
+    storeA(k0, r, true);
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int l = 4 * c4 + d;
+      f32x4 v;
+      if (!anykept) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = k0 + 4 * kq + e > l ? -rb[e][d] : 0.f;
+      } else {
+        const bool kl = kept(l);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int i = k0 + 4 * kq + e;
+          v[e] = kl ? (i == l ? 1.f : 0.f) : ((kept(i) || i > l) ? -rb[e][d] : 0.f);
+        }
+      }
+      put(BsH, BsL, l * ST + 4 * kq, v);
+    }
+  };
+  const int half = lane >> 5, l32 = lane & 31;
+  auto mma = [&]() {
+#pragma unroll
+    for (int q = 0; q < BK / 16; ++q) {
+      const int kb = 16 * q + 8 * half;
+      bf16x8 ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+      for (int x = 0; x < TM; ++x) {
+        const int row = wm * (BM / WM) + 32 * x + l32;
+        ah[x] = *(const bf16x8*)(AsH + row * ST + kb);
+        al[x] = *(const bf16x8*)(AsL + row * ST + kb);
+      }
+#pragma unroll
+      for (int y = 0; y < TN; ++y) {
+        const int col = wn * (BN / WN) + 32 * y + l32;
+        bh[y] = *(const bf16x8*)(BsH + col * ST + kb);
+        bl[y] = *(const bf16x8*)(BsL + col * ST + kb);
+      }
+      // small terms first; the accumulators alternate between dependent MFMAs
+#pragma unroll
+      for (int x = 0; x < TM; ++x)
+#pragma unroll
+        for (int y = 0; y < TN; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[x], bh[y], acc[x][y], 0, 0, 0);
+#pragma unroll
+      for (int x = 0; x < TM; ++x)
+#pragma unroll
+        for (int y = 0; y < TN; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bl[y], acc[x][y], 0, 0, 0);
+#pragma unroll
+      for (int x = 0; x < TM; ++x)
+#pragma unroll
+        for (int y = 0; y < TN; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bh[y], acc[x][y], 0, 0, 0);
+    }
+  };
+  __syncthreads();
+  loadS(0);
+  for (int t = 0; t < ks; ++t) {
+    storeS(t * BK);
+    __syncthreads();
+    if (t + 1 < ks) loadS((t + 1) * BK);
+    else loadF(0);
+    __builtin_amdgcn_sched_barrier(0);
+    mma();
+    __syncthreads();
+  }
+  for (int t = 0; t < BR / BK; ++t) {
+    storeF(t * BK);
+    __syncthreads();
+    if (t + 1 < BR / BK) loadF((t + 1) * BK);
+    __builtin_amdgcn_sched_barrier(0);
+    mma();
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < TM; ++x)
+#pragma unroll
+    for (int y = 0; y < TN; ++y) {
+      const int j = wn * (BN / WN) + 32 * y + l32;
+      const float aj = kept(j) ? 0.f : alpha;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int il = (e >> 2) * 8 + half * 4 + (e & 3);
+        const int64_t gi = i0 + wm * (BM / WM) + 32 * x + il;
+        if (gi < N && j < r) gout[gi * r + j] = acc[x][y][e] - aj;
+      }
+    }
+}
+
 // Broadcast of lane src of each quad to the quad (DPP quad permute).
 __device__ __forceinline__ float quad_bcast_b(float v, int src) {
   const int x = __builtin_bit_cast(int, v);
@@ -579,6 +777,175 @@ hs_qtf_kernel(const float* __restrict__ Qb, int64_t ldq, const float* __restrict
   if (tid < r) P[kp * r + tid] = csum[0][tid] + csum[1][tid];
 }
 
+// hs_qtf_kernel on split-BF16 MFMA (hi hi + hi lo + lo hi, FP32 accumulation).
+// The contraction runs over the tile's rows, so both operands are staged
+// K-contiguous: QsT[c][i] = Qb[row0 + i][c] and FsT[j][i] = F[row0 + i][j] sc[j]
+// as hi and lo halves (row stride TRW + 8: 16-byte fragment reads of 16
+// consecutive rows fall in distinct banks).  Each thread loads 4 x 4 blocks
+// (four rows, four columns; a wave reads whole row segments) and transposes
+// them in registers when it stores the halves.  The column sums of the squares
+// of F diag(sc) are formed in FP32 from the same registers; each thread keeps
+// the sums of its four columns over its rows, added over the threads of a
+// column in a fixed order at the end.
+template <int KPMAX, int TRW, bool FVEC>
+__global__ void __launch_bounds__(256)
+hs_qtf_split_kernel(const float* __restrict__ Qb, int64_t ldq, const float* __restrict__ F,
+                    const float* __restrict__ scale, int64_t N, int kp, int r, float* __restrict__ part) {
+  constexpr int ST = TRW + 8;
+  constexpr int NTM = KPMAX / 32 / 4;       // 32-row blocks of the output per wave
+  constexpr int QCB = KPMAX / 4, FCB = BR / 4;
+  constexpr int QB = TRW / 4 * QCB / 256;   // 4 x 4 blocks of Qb per thread
+  constexpr int FB = TRW / 4 * FCB / 256;   // 4 x 4 blocks of F per thread
+  static_assert(QB >= 1 && FB >= 1, "tile shape");
+  __shared__ __attribute__((aligned(16))) uint16_t QH[KPMAX * ST], QL[KPMAX * ST];
+  __shared__ __attribute__((aligned(16))) uint16_t FH[BR * ST], FL[BR * ST];
+  __shared__ __attribute__((aligned(16))) float sc[BR];
+  __shared__ float csum[256 / FCB][BR];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid < BR) sc[tid] = (scale && tid < r) ? scale[tid] : 1.f;
+  f32x16 acc[NTM][4];
+#pragma unroll
+  for (int x = 0; x < NTM; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[x][y][e] = 0.f;
+  float colsq[FB][4];
+#pragma unroll
+  for (int p = 0; p < FB; ++p)
+#pragma unroll
+    for (int d = 0; d < 4; ++d) colsq[p][d] = 0.f;
+  const int64_t ntiles = ceil_div(N, TRW);
+  const int half = lane >> 5, l32 = lane & 31;
+  f32x4 qv[QB][4], fv[FB][4];
+  // block b = tid + 256 p: rows 4 (b / ncb) .. +3, columns 4 (b % ncb) .. +3
+  auto load = [&](int64_t tile) {
+    if (tile >= ntiles) return;
+    const int64_t row0 = tile * TRW;
+#pragma unroll
+    for (int p = 0; p < QB; ++p) {
+      const int b = tid + 256 * p, i = 4 * (b / QCB), c = 4 * (b % QCB);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const bool ok = row0 + i + e < N && c < kp;
+        qv[p][e] = *(const f32x4*)(Qb + (ok ? (row0 + i + e) * ldq + c : 0));
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < FB; ++p) {
+      const int b = tid + 256 * p, i = 4 * (b / FCB), j = 4 * (b % FCB);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const bool ok = row0 + i + e < N;
+        if (FVEC) {
+          fv[p][e] = *(const f32x4*)(F + ((ok && j < r) ? (row0 + i + e) * r + j : 0));
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) fv[p][e][c] = F[(ok && j + c < r) ? (row0 + i + e) * r + j + c : 0];
+        }
+      }
+    }
+  };
+  __syncthreads();
+  load(blockIdx.x);
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t row0 = tile * TRW;
+#pragma unroll
+    for (int p = 0; p < QB; ++p) {
+      const int b = tid + 256 * p, i = 4 * (b / QCB), c = 4 * (b % QCB);
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (row0 + i + e < N && c + d < kp) ? qv[p][e][d] : 0.f;
+        uint32_t h0, l0, h1, l1;
+        split_pair(v[0], v[1], h0, l0);
+        split_pair(v[2], v[3], h1, l1);
+        *(uint2*)(QH + (c + d) * ST + i) = make_uint2(h0, h1);
+        *(uint2*)(QL + (c + d) * ST + i) = make_uint2(l0, l1);
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < FB; ++p) {
+      const int b = tid + 256 * p, i = 4 * (b / FCB), j = 4 * (b % FCB);
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float x = fv[p][e][d] * sc[j + d];
+          v[e] = (row0 + i + e < N && j + d < r) ? x : 0.f;
+          colsq[p][d] += v[e] * v[e];
+        }
+        uint32_t h0, l0, h1, l1;
+        split_pair(v[0], v[1], h0, l0);
+        split_pair(v[2], v[3], h1, l1);
+        *(uint2*)(FH + (j + d) * ST + i) = make_uint2(h0, h1);
+        *(uint2*)(FL + (j + d) * ST + i) = make_uint2(l0, l1);
+      }
+    }
+    __syncthreads();
+    load(tile + gridDim.x);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < TRW / 16; ++q) {
+      const int kb = 16 * q + 8 * half;
+      bf16x8 ah[NTM], al[NTM], bh[4], bl[4];
+#pragma unroll
+      for (int x = 0; x < NTM; ++x) {
+        const int c = 32 * (wave * NTM + x) + l32;
+        ah[x] = *(const bf16x8*)(QH + c * ST + kb);
+        al[x] = *(const bf16x8*)(QL + c * ST + kb);
+      }
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        const int j = 32 * y + l32;
+        bh[y] = *(const bf16x8*)(FH + j * ST + kb);
+        bl[y] = *(const bf16x8*)(FL + j * ST + kb);
+      }
+#pragma unroll
+      for (int x = 0; x < NTM; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[x], bh[y], acc[x][y], 0, 0, 0);
+#pragma unroll
+      for (int x = 0; x < NTM; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bl[y], acc[x][y], 0, 0, 0);
+#pragma unroll
+      for (int x = 0; x < NTM; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bh[y], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  float* P = part + (int64_t)blockIdx.x * (kp * r + r);
+#pragma unroll
+  for (int x = 0; x < NTM; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int j = 32 * y + l32;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int c = 32 * (wave * NTM + x) + (e >> 2) * 8 + half * 4 + (e & 3);
+        if (c < kp && j < r) P[c * r + j] = acc[x][y][e];
+      }
+    }
+  // column j = 4 (tid % FCB) + d: threads tid % FCB == j / 4, rows blocks tid / FCB (+ 256 / FCB p)
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    float t = 0.f;
+#pragma unroll
+    for (int p = 0; p < FB; ++p) t += colsq[p][d];
+    csum[tid / FCB][4 * (tid % FCB) + d] = t;
+  }
+  __syncthreads();
+  if (tid < r) {
+    float t = 0.f;
+    for (int g = 0; g < 256 / FCB; ++g) t += csum[g][tid];
+    P[kp * r + tid] = t;
+  }
+}
+
 }  // namespace
 
 // Floats of the auxiliary buffer of this path: C (256 x 128), G (128 x 128),
@@ -601,21 +968,28 @@ hipError_t launch_halfstep_big(const HalfStepArgs& a, int do_sweep, hipStream_t 
     if (e != hipSuccess) return e;
     const bool fv = (a.r & 3) == 0;
     const dim3 g128((unsigned)ceil_div(a.N, 128)), g64((unsigned)ceil_div(a.N, 64));
-    if (a.N >= 128 * 512) {
-      if (fv)
-        hipLaunchKernelGGL((hs_grad_kernel<128, true>), g128, dim3(256), 0, st, a.S, a.lds, a.F, scl, Cp, Gp, rdiag,
-                           a.alpha, a.gbuf, a.N, a.kp, a.r);
-      else
-        hipLaunchKernelGGL((hs_grad_kernel<128, false>), g128, dim3(256), 0, st, a.S, a.lds, a.F, scl, Cp, Gp, rdiag,
-                           a.alpha, a.gbuf, a.N, a.kp, a.r);
+#define HS_GRAD(K, BM, FV, G)                                                                                      \
+  hipLaunchKernelGGL((K<BM, FV>), G, dim3(256), 0, st, a.S, a.lds, a.F, scl, Cp, Gp, rdiag, a.alpha, a.gbuf, a.N, \
+                     a.kp, a.r)
+    const bool tall = a.N >= 128 * 512;
+    if (a.split) {
+      if (tall) {
+        if (fv) HS_GRAD(hs_grad_split_kernel, 128, true, g128);
+        else HS_GRAD(hs_grad_split_kernel, 128, false, g128);
+      } else {
+        if (fv) HS_GRAD(hs_grad_split_kernel, 64, true, g64);
+        else HS_GRAD(hs_grad_split_kernel, 64, false, g64);
+      }
     } else {
-      if (fv)
-        hipLaunchKernelGGL((hs_grad_kernel<64, true>), g64, dim3(256), 0, st, a.S, a.lds, a.F, scl, Cp, Gp, rdiag,
-                           a.alpha, a.gbuf, a.N, a.kp, a.r);
-      else
-        hipLaunchKernelGGL((hs_grad_kernel<64, false>), g64, dim3(256), 0, st, a.S, a.lds, a.F, scl, Cp, Gp, rdiag,
-                           a.alpha, a.gbuf, a.N, a.kp, a.r);
+      if (tall) {
+        if (fv) HS_GRAD(hs_grad_kernel, 128, true, g128);
+        else HS_GRAD(hs_grad_kernel, 128, false, g128);
+      } else {
+        if (fv) HS_GRAD(hs_grad_kernel, 64, true, g64);
+        else HS_GRAD(hs_grad_kernel, 64, false, g64);
+      }
     }
+#undef HS_GRAD
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // 64 R-row tiles; at most two workgroups per CU are resident (LDS), so at
     // most 512 loop over the tiles.  R = 4 rows per quad for tall sides, fewer
@@ -634,21 +1008,26 @@ hipError_t launch_halfstep_big(const HalfStepArgs& a, int do_sweep, hipStream_t 
   const float* qscale = do_sweep ? nullptr : a.scale;
   const bool fv = (a.r & 3) == 0;
   const dim3 qg((unsigned)nblk);
-  if (a.kp <= 128) {
-    if (fv)
-      hipLaunchKernelGGL((hs_qtf_kernel<128, 64, true>), qg, dim3(256), 0, st, a.Qb, a.ldq, a.F, qscale, a.N, a.kp,
-                         a.r, a.part);
-    else
-      hipLaunchKernelGGL((hs_qtf_kernel<128, 64, false>), qg, dim3(256), 0, st, a.Qb, a.ldq, a.F, qscale, a.N, a.kp,
-                         a.r, a.part);
+#define HS_QTF(K, KP, TR, FV) \
+  hipLaunchKernelGGL((K<KP, TR, FV>), qg, dim3(256), 0, st, a.Qb, a.ldq, a.F, qscale, a.N, a.kp, a.r, a.part)
+  if (a.split) {
+    if (a.kp <= 128) {
+      if (fv) HS_QTF(hs_qtf_split_kernel, 128, 64, true);
+      else HS_QTF(hs_qtf_split_kernel, 128, 64, false);
+    } else {
+      if (fv) HS_QTF(hs_qtf_split_kernel, 256, 32, true);
+      else HS_QTF(hs_qtf_split_kernel, 256, 32, false);
+    }
   } else {
-    if (fv)
-      hipLaunchKernelGGL((hs_qtf_kernel<256, 32, true>), qg, dim3(256), 0, st, a.Qb, a.ldq, a.F, qscale, a.N, a.kp,
-                         a.r, a.part);
-    else
-      hipLaunchKernelGGL((hs_qtf_kernel<256, 32, false>), qg, dim3(256), 0, st, a.Qb, a.ldq, a.F, qscale, a.N, a.kp,
-                         a.r, a.part);
+    if (a.kp <= 128) {
+      if (fv) HS_QTF(hs_qtf_kernel, 128, 64, true);
+      else HS_QTF(hs_qtf_kernel, 128, 64, false);
+    } else {
+      if (fv) HS_QTF(hs_qtf_kernel, 256, 32, true);
+      else HS_QTF(hs_qtf_kernel, 256, 32, false);
+    }
   }
+#undef HS_QTF
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_sum_partials_f32(a.part, nblk, (int64_t)a.kp * a.r + a.r, a.acc_out, st);

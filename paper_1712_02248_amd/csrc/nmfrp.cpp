@@ -63,7 +63,11 @@ bool valid_params(const nmf_params* p, std::string* why) {
     *why = "lowp_sketches must be 0, 1 (with a low-precision prec) or 2";
     return false;
   }
-  if (p->reserved != 0) { *why = "reserved must be 0"; return false; }
+  if (p->update_prec < 0 || p->update_prec > 1) { *why = "update_prec must be 0 or 1"; return false; }
+  if (p->update_prec == 1 && !halfstep_big(p->k_sketch, p->r)) {
+    *why = "update_prec 1 (split-BF16 update products) needs the wide-factor half-steps (r > 64 or k' > 128)";
+    return false;
+  }
   return true;
 }
 
@@ -334,7 +338,7 @@ hipError_t halfstep_w(nmf_ctx* c) {
   a.N = c->p.m; a.kp = (int)L.KP; a.r = c->p.r;
   a.part = c->at<float>(L.hs_part); a.acc_out = c->at<double>(L.acc_w);
   a.alpha = 0.f; a.beta = 0.f;
-  a.gbuf = c->at<float>(L.TM); a.aux = c->at<float>(L.hs_aux);   // the m-side temporary is free while stepping
+  a.gbuf = c->at<float>(L.TM); a.aux = c->at<float>(L.hs_aux); a.split = c->p.update_prec;   // the m-side temporary is free while stepping
   return launch_halfstep(a, 1, c->st);
 }
 
@@ -352,7 +356,7 @@ hipError_t halfstep_h(nmf_ctx* c, int do_sweep) {
   a.N = c->p.n; a.kp = (int)L.KP; a.r = c->p.r;
   a.part = c->at<float>(L.hs_part); a.acc_out = c->at<double>(L.acc_h);
   a.alpha = c->p.alpha; a.beta = c->p.beta;
-  a.gbuf = c->at<float>(L.TN); a.aux = c->at<float>(L.hs_aux);   // the n-side temporary is free while stepping
+  a.gbuf = c->at<float>(L.TN); a.aux = c->at<float>(L.hs_aux); a.split = c->p.update_prec;   // the n-side temporary is free while stepping
   return launch_halfstep(a, do_sweep, c->st);
 }
 

@@ -27,7 +27,7 @@ class Params(ctypes.Structure):
     _fields_ = [("m", c_i64), ("n", c_i64), ("r", c_i32), ("k_sketch", c_i32), ("q", c_i32),
                 ("prec", c_i32), ("refine_fp32", c_i32), ("normalize", c_i32),
                 ("alpha", ctypes.c_float), ("beta", ctypes.c_float), ("seed", c_u64),
-                ("lowp_sketches", c_i32), ("reserved", c_i32)]
+                ("lowp_sketches", c_i32), ("update_prec", c_i32)]
 
 
 # name -> (restype, argtypes)
@@ -154,10 +154,10 @@ class NMF:
     """
 
     def __init__(self, m, n, r, k_sketch, q, seed=0, normalize=1, alpha=0.0, beta=0.0,
-                 prec=NMF_FP32, refine_fp32=0, lowp_sketches=0, device="cuda", stream=None):
+                 prec=NMF_FP32, refine_fp32=0, lowp_sketches=0, update_prec=0, device="cuda", stream=None):
         lib = load()
         self.p = Params(m, n, r, k_sketch, q, prec, refine_fp32, normalize, alpha, beta, seed,
-                        lowp_sketches, 0)
+                        lowp_sketches, update_prec)
         nbytes = lib.nmf_workspace_bytes(ctypes.byref(self.p))
         if nbytes == 0:
             _check(-1)

@@ -79,13 +79,16 @@ def _run_to_checkpoints(lib, ctx, Xd, ref, iters, gate, tag):
     return worst
 
 
-def test_c5_full_size_plain_fp32_matches_oracle(lib, c5):
+@pytest.mark.parametrize("up", [0, 1])
+def test_c5_full_size_plain_fp32_matches_oracle(lib, c5, up):
     """The paper's method at full size with the benchmark's launch configuration:
-    FP32 range finder and sketches, device-drawn test matrices, cold factors."""
+    FP32 range finder and sketches, device-drawn test matrices, cold factors; the
+    update products on FP32 MFMA (up 0, the plain method) or on split-BF16 MFMA
+    (up 1, as in the low-precision variants)."""
     Xd, W0d, H0d, _ = c5
     c = datagen.CONFIGS[NAME]
     ref = json.load(open(GOLDEN))[NAME]
-    ctx = lib.NMF(c["m"], c["n"], c["r"], c["kp"], c["q"], seed=datagen.cfg_seed(NAME))
+    ctx = lib.NMF(c["m"], c["n"], c["r"], c["kp"], c["q"], seed=datagen.cfg_seed(NAME), update_prec=up)
     ctx.compress(Xd)
     ctx.init(W0d, H0d)
     assert ctx.sync() == 0
@@ -93,7 +96,7 @@ def test_c5_full_size_plain_fp32_matches_oracle(lib, c5):
     for Q in (QL, QR):
         Qd = Q.double()
         assert (Qd.T @ Qd - torch.eye(c["kp"], dtype=torch.float64, device=Qd.device)).abs().max().item() < 5e-6
-    worst = _run_to_checkpoints(lib, ctx, Xd, ref, c["iters"], 1e-4, "fp32")
+    worst = _run_to_checkpoints(lib, ctx, Xd, ref, c["iters"], 1e-4, f"fp32 up={up}")
     print(f"  largest gap {worst:.2e}", flush=True)
     Wg, Hg = ctx.factors()
     assert (Wg >= 0).all().item() and (Hg >= 0).all().item()
@@ -102,7 +105,8 @@ def test_c5_full_size_plain_fp32_matches_oracle(lib, c5):
 
 def test_c5_full_size_fp8_refined_matches_the_oracle_low_precision_model(lib, c5):
     """FP8 e4m3 range finder (128 x 128 block scales), one refinement power
-    iteration per side on X itself and the sketches on split-BF16 products: the
+    iteration per side on X itself, the sketches and the update loop on
+    split-BF16 products (the benchmark's headline configuration): the
     error at every stored checkpoint within the 1e-4 gate of the oracle's model of
     the same rounding (R_q: the quantised X and thin operands, the split
     products), and the gap to the exact FP64 run (R_true) printed.  Against R_true
@@ -116,7 +120,7 @@ def test_c5_full_size_fp8_refined_matches_the_oracle_low_precision_model(lib, c5
     Xd, W0d, H0d, _ = c5
     c = datagen.CONFIGS[NAME]
     ctx = lib.NMF(c["m"], c["n"], c["r"], c["kp"], c["q"], seed=datagen.cfg_seed(NAME), prec=lib.NMF_FP8_E4M3,
-                  refine_fp32=2, lowp_sketches=2)
+                  refine_fp32=2, lowp_sketches=2, update_prec=1)
     ctx.compress(Xd)
     ctx.init(W0d, H0d)
     assert ctx.sync() == 0

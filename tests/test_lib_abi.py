@@ -53,7 +53,8 @@ def test_workspace_sizing_and_validation():
     assert ok >= 4 * 20 * (3 * 256 + 5 * 512)
     bad = [dict(r=20), dict(r=25), dict(k_sketch=300), dict(n=254), dict(q=-1), dict(normalize=3),
            dict(m=0), dict(alpha=-1.0), dict(k_sketch=257, m=1000, n=1000), dict(lowp_sketches=1),
-           dict(lowp_sketches=3, prec=1), dict(lowp_sketches=-1), dict(reserved=1)]
+           dict(lowp_sketches=3, prec=1), dict(lowp_sketches=-1), dict(update_prec=2), dict(update_prec=-1),
+           dict(update_prec=1)]   # split-BF16 update products need the wide-factor path
     assert lib.nmf_workspace_bytes(ctypes.byref(_params(lowp_sketches=1, prec=1))) > 0
     # split-BF16 sketches: any prec; the split thin operands add to the workspace
     for prec in (0, 1, 2):
