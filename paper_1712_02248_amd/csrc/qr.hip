@@ -1033,12 +1033,19 @@ apply_rinv_wide_kernel(float* __restrict__ Y, int64_t ldy, int64_t rows, int k, 
 }  // namespace
 
 int gram_pick_splits(int64_t rows, int k) {
+  if (k > 128) {
+    // three blocks per split, two workgroups resident per CU (LDS): 170 splits
+    // give 510 workgroups, two per CU in one wave of residency (with 128 splits,
+    // 384 workgroups left half the CUs with twice the rows of the others);
+    // partials 170 k^2 FP64 (89 MB at k = 256)
+    int64_t s = std::min<int64_t>(170, ceil_div(rows, 64));
+    return (int)(s < 1 ? 1 : s);
+  }
   // 256 rows per split, or down to 64 rows per split so that short bases still
-  // spread over 256 workgroups; partials capped at 32 MB (64 MB for k > 128,
-  // whose three-block grid needs more splits to fill the chip)
+  // spread over 256 workgroups; partials capped at 32 MB
   int64_t s = ceil_div(rows, 256);
   if (s < 256) s = std::min<int64_t>(256, ceil_div(rows, 64));
-  const int64_t cap = ((k > 128 ? 64ll : 32ll) << 20) / ((int64_t)k * k * 8);
+  const int64_t cap = (32ll << 20) / ((int64_t)k * k * 8);
   if (s > cap) s = cap;
   if (s > 1024) s = 1024;
   if (s < 1) s = 1;

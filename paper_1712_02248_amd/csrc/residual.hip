@@ -214,17 +214,19 @@ residual_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64_t n,
 // Sketch-only proxy of the residual (Sec 3: Q_L Q_L^T X approximates X):
 //   e_p^2 = (||X||^2 - ||Xh||^2 + sum_j ||xh_j - Wh h_j||^2) / ||X||^2,
 // exact when the columns of W lie in range(Q_L).  Per row j of Xh (n x k') and
-// Ht (n x r), one wave: lane c (and c + 64, ..., up to k') forms
+// Ht (n x r): lane c (and c + 64, ... up to k') forms
 // d_c = xh_jc - sum_l Wh[c][l] h_jl, l ascending, in FP64.  Wh is staged
 // transposed (whs[l][c], row stride kpp = k' rounded up to 64, zero padded) so
-// the lanes of a wave read consecutive words.
+// the lanes of a wave read consecutive words; a wave takes four rows at once
+// (their rows of Ht staged in LDS), so each value of Wh read serves four rows.
 // Block partials (two FP64 sums) go to part[2 blockIdx.x + {0, 1}].
 __global__ void __launch_bounds__(256)
 proxy_kernel(const float* __restrict__ Xh, int64_t ldx, const float* __restrict__ Ht, int r,
              const float* __restrict__ Wh, int kp, int64_t n, double* __restrict__ part) {
+  constexpr int RW = 4;                          // rows per wave and pass
   extern __shared__ float whs[];                 // r x kpp
   __shared__ double red[2][256];
-  __shared__ float hrow[4][128];                 // the wave's current row of Ht (r <= 128)
+  __shared__ float hrow[4][RW][128];             // the wave's rows of Ht (r <= 128)
   const int kpp = (kp + 63) & ~63, nt = kpp >> 6;
   for (int e = threadIdx.x; e < kpp * r; e += 256) {
     const int l = e / kpp, c = e - l * kpp;
@@ -233,35 +235,42 @@ proxy_kernel(const float* __restrict__ Xh, int64_t ldx, const float* __restrict_
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double sd = 0.0, sx = 0.0;
-  const int64_t step = (int64_t)gridDim.x * 4;
-  int64_t row = (int64_t)blockIdx.x * 4 + wave;
-  float h0 = 0.f, h1 = 0.f;                      // the row's entries lane, lane + 64
-  if (row < n) {
-    h0 = lane < r ? Ht[row * r + lane] : 0.f;
-    h1 = lane + 64 < r ? Ht[row * r + lane + 64] : 0.f;
-  }
-  for (; row < n; row += step) {
-    hrow[wave][lane] = h0;
-    hrow[wave][lane + 64] = h1;
-    if (row + step < n) {                        // the next row's loads stay in flight
-      h0 = lane < r ? Ht[(row + step) * r + lane] : 0.f;
-      h1 = lane + 64 < r ? Ht[(row + step) * r + lane + 64] : 0.f;
+  const int64_t step = (int64_t)gridDim.x * 4 * RW;
+  for (int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * RW; row0 < n; row0 += step) {
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+      const int64_t row = row0 + q < n ? row0 + q : n - 1;   // rows past n: a copy, not summed
+      hrow[wave][q][lane] = lane < r ? Ht[row * r + lane] : 0.f;
+      hrow[wave][q][lane + 64] = lane + 64 < r ? Ht[row * r + lane + 64] : 0.f;
     }
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double acc[RW][4];
+#pragma unroll
+    for (int q = 0; q < RW; ++q)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[q][t] = 0.0;
     for (int l = 0; l < r; ++l) {
-      const double hl = (double)hrow[wave][l];
+      double w[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (t < nt) acc[t] += (double)whs[l * kpp + 64 * t + lane] * hl;
+      for (int t = 0; t < 4; ++t) w[t] = t < nt ? (double)whs[l * kpp + 64 * t + lane] : 0.0;
+#pragma unroll
+      for (int q = 0; q < RW; ++q) {
+        const double hl = (double)hrow[wave][q][l];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[q][t] += w[t] * hl;
+      }
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int c = 64 * t + lane;
-      if (c < kp) {
-        const double x = Xh[row * ldx + c];
-        const double d = x - acc[t];
-        sd += d * d;
-        sx += x * x;
+    for (int q = 0; q < RW; ++q) {
+      if (row0 + q >= n) continue;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int c = 64 * t + lane;
+        if (c < kp) {
+          const double x = Xh[(row0 + q) * ldx + c];
+          const double d = x - acc[q][t];
+          sd += d * d;
+          sx += x * x;
+        }
       }
     }
   }
@@ -515,7 +524,7 @@ hipError_t launch_residual(const float* X, int64_t ldx, int64_t m, int64_t n, co
 }
 
 int proxy_blocks(int64_t n) {
-  int64_t b = ceil_div(n, 4);
+  int64_t b = ceil_div(n, 16);   // four waves of four rows
   return (int)(b < 256 ? (b < 1 ? 1 : b) : 256);
 }
 
