@@ -14,6 +14,10 @@
  * Conventions for every call below
  *  - Matrices are row-major.  Pointers named X, W, Ht, Q*, X*, omega_*, and the
  *    buffers of the MLP calls are DEVICE pointers; sizes are element counts.
+ *  - The second factor crosses the boundary as Ht (n x r), the transpose of an
+ *    r x n H: row j of Ht is the coefficient vector of data column j, the unit
+ *    the H sweep, the column NNLS and the warm-start network work on.  A caller
+ *    holding H (r x n, row-major) passes it as Ht by transposing.
  *  - All work is queued on the HIP stream given at creation; calls return after
  *    queueing unless documented as synchronising.  Asynchronous HIP faults and
  *    device-side flags surface at the next synchronising call.
