@@ -81,6 +81,11 @@ def parse():
     ap.add_argument("--sweep-seeds", type=int, default=3, help="test-matrix seeds per sweep point (median)")
     ap.add_argument("--probe-kernels", action="store_true",
                     help="only a copy of known size and the dominant kernel (for counter runs)")
+    ap.add_argument("--c4", action="store_true",
+                    help="the warm-start study on new columns instead of the bench: the network trained "
+                         "on the 65536 x 4096 parts workload's generator, applied to --c4-cols fresh columns, "
+                         "then 20 iterations against the cold start and the controls")
+    ap.add_argument("--c4-cols", type=int, default=50000)
     return ap.parse_args()
 
 
@@ -591,6 +596,64 @@ def run_sweep(torch, nmfrp, datagen, name, args):
     print(json.dumps(out), flush=True)
 
 
+def run_c4(torch, nmfrp, datagen, args):
+    """The warm-start experiment on new columns: a network trained on pairs from
+    the 65536 x 4096 parts workload's generator (the bench's protocol) is applied
+    to a new problem of --c4-cols columns from the same generator (same parts W0,
+    new coefficients), compressed as the c2 headline compresses (BF16 range
+    finder, split-BF16 sketches).  Reported: the error right after each
+    initialisation and after 20 FastHALS-RP iterations, for the cold factors,
+    the warm start (W_ref, network rows with rejection, 20 NNLS sweeps), the
+    control without the network, the network with a cold W, and the warm start
+    without sweeps."""
+    from datagen import device as ddev
+    cfg = dict(datagen.CONFIGS["c2"])
+    cfg["name"] = "c2"
+    m, r, kp, q = cfg["m"], cfg["r"], cfg["kp"], cfg["q"]
+    seed = datagen.cfg_seed("c2")
+    W0gen = torch.from_numpy(datagen.parts_w0(m, cfg["r_true"], seed).astype(np.float32)).cuda()
+    fresh = lambda ncols, chunk: ddev.parts_fresh_columns(torch, nmfrp.gaussian, W0gen, ncols, seed, chunk)
+    log("[c4] training the warm-start network")
+    net, Q_train, W_ref, info = train_warm_start(torch, nmfrp, cfg, seed, args, fresh)
+    n4 = args.c4_cols
+    X4 = fresh(n4, 100000)      # a chunk id the training does not use
+    mean = float(X4.sum(dtype=torch.float64)) / (m * n4)
+    W0, H0 = datagen.init_factors(mean, m, n4, r, seed + 7)
+    W0d, H0d = torch.from_numpy(W0).cuda(), torch.from_numpy(H0).cuda()
+    ctx = nmfrp.NMF(m, n4, r, kp, q, seed=seed, prec=nmfrp.NMF_BF16, lowp_sketches=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.compress(X4)
+    torch.cuda.synchronize()
+    t_comp = time.perf_counter() - t0
+    sw = args.refine_sweeps
+    rows = {}
+    for label, warm in (("cold", None), ("warm", (net, Q_train, W_ref, sw, "ref")),
+                        ("ctrl_no_net", (net, Q_train, W_ref, sw, "no_net")),
+                        ("net_cold_w", (net, Q_train, W_ref, sw, "cold_w")),
+                        ("warm_no_sweeps", (net, Q_train, W_ref, 0, "ref"))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if warm is None:
+            ctx.init(W0d, H0d)
+            nrej = None
+        else:
+            nrej = warm_start(ctx, warm, W0d, H0d, count=True)
+        torch.cuda.synchronize()
+        t_init = time.perf_counter() - t0
+        e0 = ctx.residual(X4)
+        ctx.step(20)
+        e20 = ctx.residual(X4)
+        rows[label] = dict(e_after_init=e0, e_after_20_iters=e20, init_ms=round(t_init * 1e3, 3), rejected_rows=nrej)
+        log(f"[c4] {label}: e after init {e0:.6e}, after 20 iterations {e20:.6e}, init {t_init * 1e3:.2f} ms, "
+            f"rejected {nrej}")
+    ctx.close()
+    print(json.dumps(dict(study="warm start on new columns", m=m, n=n4, r=r, k_sketch=kp, q=q, data="synthetic",
+                          generator="parts (same W0 as the 65536 x 4096 workload, new coefficients)",
+                          compress_ms=round(t_comp * 1e3, 3), refine_sweeps=sw, training=info, results=rows)),
+          flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -606,6 +669,9 @@ def main():
     nmfrp.load()
     if args.sweep:
         run_sweep(torch, nmfrp, datagen, args.sweep, args)
+        return
+    if args.c4:
+        run_c4(torch, nmfrp, datagen, args)
         return
     name = args.workload
     cfg = dict(datagen.CONFIGS[name])
