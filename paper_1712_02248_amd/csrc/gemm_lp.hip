@@ -285,6 +285,133 @@ gemm_fp8_nt_kernel(const uint8_t* __restrict__ A, int64_t lda, const int* __rest
     }
 }
 
+// Wide thin operands (128 < N <= 256): 512 threads over a 128 x 256 tile, eight
+// waves of 64 x 64 (4 x 4 blocks of 16 x 16), two LDS stages (the tile of step
+// t + 1 is stored while step t is read) with one barrier per step, and two
+// register sets carrying the next two steps' loads.  Each output element
+// accumulates the same MFMAs in the same K order as gemm_fp8_nt_kernel, so the
+// results are identical.
+__global__ void __launch_bounds__(512)
+gemm_fp8_wide_kernel(const uint8_t* __restrict__ A, int64_t lda, const int* __restrict__ EA, int64_t ea_i,
+                     int64_t ea_k, const uint8_t* __restrict__ Bt, int64_t ldbt, const int* __restrict__ EB,
+                     float* __restrict__ C, int64_t ldc, int64_t M, int64_t N, int64_t Kpad, int64_t kchunk,
+                     int rot_xcd) {
+  constexpr int BM = 128, BN = 256, BK = 128, ROW = BK + 16, NT = 512;
+  constexpr int WM = 2, WN = 4, TM = BM / WM / 16, TN = BN / WN / 16;   // 4 x 4 tiles per wave
+  constexpr int AV = BM * BK / 16 / NT, BV = BN * BK / 16 / NT;          // 2, 4
+  constexpr int STAGE = (BM + BN) * ROW;
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * STAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int64_t i0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kend = kbeg + kchunk < Kpad ? kbeg + kchunk : Kpad;
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  i32x4 ra0[AV], rb0[BV], ra1[AV], rb1[BV];
+  const i32x4 z4 = {0, 0, 0, 0};
+  auto load = [&](i32x4* ra, i32x4* rb, int64_t k0) {
+#pragma unroll
+    for (int p = 0; p < AV; ++p) {
+      const int f = tid + NT * p, row = f / (BK / 16), c16 = f % (BK / 16);
+      const int64_t gi = i0 + row;
+      ra[p] = gi < M ? __builtin_nontemporal_load((const i32x4*)(A + gi * lda + k0 + 16 * c16)) : z4;
+    }
+#pragma unroll
+    for (int p = 0; p < BV; ++p) {
+      const int f = tid + NT * p, row = f / (BK / 16), c16 = f % (BK / 16);
+      const int64_t gj = n0 + row;
+      rb[p] = gj < N ? *(const i32x4*)(Bt + gj * ldbt + k0 + 16 * c16) : z4;
+    }
+  };
+  auto store = [&](const i32x4* ra, const i32x4* rb, int stage) {
+    uint8_t* As = lds + stage * STAGE;
+    uint8_t* Bs = As + BM * ROW;
+#pragma unroll
+    for (int p = 0; p < AV; ++p) {
+      const int f = tid + NT * p, row = f / (BK / 16), c16 = f % (BK / 16);
+      *(i32x4*)(As + row * ROW + 16 * c16) = ra[p];
+    }
+#pragma unroll
+    for (int p = 0; p < BV; ++p) {
+      const int f = tid + NT * p, row = f / (BK / 16), c16 = f % (BK / 16);
+      *(i32x4*)(Bs + row * ROW + 16 * c16) = rb[p];
+    }
+  };
+  const int g4 = lane >> 4, l16 = lane & 15;
+  const int64_t ti = i0 / 128;
+  const int64_t T = kend > kbeg ? (kend - kbeg) / BK : 0;
+  const int64_t wg = blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z);
+  const int64_t rot = T == 0 ? 0 : rot_xcd ? ((wg % 8) * T) / 8 : (int64_t)blockIdx.x % T;
+  auto kstep = [&](int64_t s) { return kbeg + ((s + rot) % T) * BK; };
+  auto compute = [&](int64_t k0, int stage) {
+    const uint8_t* As = lds + stage * STAGE;
+    const uint8_t* Bs = As + BM * ROW;
+    const int64_t kb = k0 / 128;
+    const int sa = 127 + EA[ti * ea_i + kb * ea_k];
+    const int sb = 127 + EB[kb];
+    i32x8 af[TM], bf[TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      const int il = wm * (BM / WM) + a * 16 + l16;
+      const i32x4 lo = *(const i32x4*)(As + il * ROW + 32 * g4);
+      const i32x4 hi = *(const i32x4*)(As + il * ROW + 32 * g4 + 16);
+      af[a] = (i32x8){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    }
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int jl = wn * (BN / WN) + b * 16 + l16;
+      const i32x4 lo = *(const i32x4*)(Bs + jl * ROW + 32 * g4);
+      const i32x4 hi = *(const i32x4*)(Bs + jl * ROW + 32 * g4 + 16);
+      bf[b] = (i32x8){lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    }
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(af[a], bf[b], acc[a][b], 0, 0, 0,
+                                                                      sa, 0, sb);
+  };
+  // step s is staged in stage s % 2 from register set s % 2
+  if (T > 0) {
+    load(ra0, rb0, kstep(0));
+    if (T > 1) load(ra1, rb1, kstep(1));
+    store(ra0, rb0, 0);
+    if (T > 2) load(ra0, rb0, kstep(2));
+    __syncthreads();
+    for (int64_t t = 0; t < T; t += 2) {
+      // set 1: step t + 1, set 0: step t + 2
+      if (t + 1 < T) store(ra1, rb1, 1);
+      if (t + 3 < T) load(ra1, rb1, kstep(t + 3));
+      __builtin_amdgcn_sched_barrier(0);
+      compute(kstep(t), 0);
+      __syncthreads();
+      if (t + 1 < T) {
+        if (t + 2 < T) store(ra0, rb0, 0);
+        if (t + 4 < T) load(ra0, rb0, kstep(t + 4));
+        __builtin_amdgcn_sched_barrier(0);
+        compute(kstep(t + 1), 1);
+        __syncthreads();
+      }
+    }
+  }
+  float* Cz = C + (int64_t)blockIdx.z * (M * ldc);
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int64_t gj = n0 + wn * (BN / WN) + b * 16 + l16;
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int64_t gi = i0 + wm * (BM / WM) + a * 16 + 4 * g4 + x;
+        if (gi < M && gj < N) Cz[gi * ldc + gj] = acc[a][b][x];
+      }
+    }
+}
+
 __global__ void __launch_bounds__(256)
 splitk_reduce_lp(const float* __restrict__ part, int splits, float* __restrict__ C, int64_t ldc,
                  int64_t M, int64_t N) {
@@ -388,7 +515,7 @@ hipError_t launch_gemm_fp8_nt(const uint8_t* A, int64_t lda, const int* EA, int6
     case 32: hipLaunchKernelGGL((gemm_fp8_nt_kernel<32, 1>), grid, dim3(256), 0, st, A, lda, EA, ea_i, ea_k, Bt, ldbt, EB, out, ldo, M, N, Kpad, kchunk, rx); break;
     case 64: hipLaunchKernelGGL((gemm_fp8_nt_kernel<64, 2>), grid, dim3(256), 0, st, A, lda, EA, ea_i, ea_k, Bt, ldbt, EB, out, ldo, M, N, Kpad, kchunk, rx); break;
     case 128: hipLaunchKernelGGL((gemm_fp8_nt_kernel<128, 2>), grid, dim3(256), 0, st, A, lda, EA, ea_i, ea_k, Bt, ldbt, EB, out, ldo, M, N, Kpad, kchunk, rx); break;
-    default: hipLaunchKernelGGL((gemm_fp8_nt_kernel<256, 4>), grid, dim3(256), 0, st, A, lda, EA, ea_i, ea_k, Bt, ldbt, EB, out, ldo, M, N, Kpad, kchunk, rx); break;
+    default: hipLaunchKernelGGL(gemm_fp8_wide_kernel, grid, dim3(512), 0, st, A, lda, EA, ea_i, ea_k, Bt, ldbt, EB, out, ldo, M, N, Kpad, kchunk, rx); break;
   }
   if (!reduce) return hipGetLastError();
   return finish(part, splits, C, ldc, M, N, st);
