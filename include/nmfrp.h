@@ -183,26 +183,28 @@ nmf_status nmf_sketch_spectrum(nmf_ctx* ctx, double* sigma);
 
 /* Runs steps in chunks, evaluating the residual after each chunk, until
  * e <= eps or max_iters iterations (the paper leaves the stopping rule open:
- * Alg 1-4).  check_every > 0: fixed chunk.  check_every == 0 after
- * nmf_compress: until the first residual, chunks (5 first, then 1.2
- * times the straight-line extrapolation of the last two proxy values, 5..50)
- * are followed by the sketch-only proxy (nmf_proxy_residual, no pass over X);
- * the first residual runs once the proxy is within 1 % of eps, once
- * the proxy stalls (not decreasing, or its extrapolation needs more than 50
- * further iterations: an offset from W's part outside range(Q_L) keeps it
- * above eps), after 100 iterations, or at max_iters (a proxy reading and a
- * residual it lets through share one synchronisation: the residual kernel
- * reads the proxy sums on the device and exits at once otherwise).
- * From then on every chunk ends with a residual check
- * and is 1.5 times the iterations a straight-line extrapolation of
- * the last two values needs to reach eps (5..50; by the gap to eps:
- * 50, 20, 10, 5 for more than 10 %, 1 %, 0.3 % or less when there is no
- * slope).  In this schedule every residual is nmf_residual_check's (split-BF16
- * products, and the exact FP64 residual whenever that value lies within its
- * bound of eps).  Each stop decision is that of the exact e.  Otherwise (fixed
- * chunks, or check_every == 0 after nmf_set_state, which has no ||X||^2: the
- * exact schedule above starting with e at the current factors) every check is
- * the exact residual.  max_iters == 0 only evaluates e (exactly).
+ * Alg 1-4).  check_every > 0: fixed chunks, each ending with the exact
+ * residual.  check_every == 0 after nmf_compress: after every chunk (5 first,
+ * then 1.2 times the iterations a straight-line extrapolation of the last two
+ * readings needs to reach the target, 5..50; with one reading 20, 10 or 5 by
+ * its distance from it) the residual is estimated on a sample of the rows
+ * (split-BF16 products over every s-th 256-row strip, s = strips / 64, split
+ * into column parts; all strips for m <= 16384; the ratio of the sampled sums
+ * of (X - P)^2 and X^2).  The target is eps - beta, beta the bound of
+ * nmf_residual_check's split value, below which that value decides e <= eps by
+ * itself.  The split residual over all of X runs once the estimate reaches the
+ * target, once it is within 1 % of eps with the target out of reach (more than
+ * 20 further iterations at the current rate, or no progress), and after the
+ * last chunk.  A split value within its bound of eps is followed by a few more
+ * iterations and a second split residual when the target is at most 10
+ * iterations away, and otherwise (or on a second such value, or after the last
+ * chunk) by the exact FP64 residual.  Each stop decision is that of the exact
+ * e; an estimate that errs high
+ * only delays a stop by a chunk.  check_every == 0 after nmf_set_state: the
+ * exact residual after every chunk, starting with e at the current factors,
+ * each chunk 1.5 times the iterations a straight-line extrapolation of the last
+ * two values needs (5..50; 50, 20, 10 or 5 by the gap to eps when there is no
+ * slope).  max_iters == 0 only evaluates e (exactly).
  * Synchronising.  *iters_done and *rel_err report the iterations run and the
  * last e (exact, or within nmf_residual_check's bound of it). */
 nmf_status nmf_fit(nmf_ctx* ctx, const float* X, int64_t ldx, int32_t max_iters, double eps,

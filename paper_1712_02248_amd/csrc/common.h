@@ -188,7 +188,8 @@ int residual_split_kr(int r);
 size_t residual_split_halves(int64_t m, int64_t n, int r);
 hipError_t launch_residual_split(const float* X, int64_t ldx, int64_t m, int64_t n, const float* W, const float* sw,
                                  const float* Ht, int r, uint16_t* ws, double* part, double* out, unsigned* counter,
-                                 hipStream_t st, const double* gate = nullptr, double gate_thr2 = 0.0);
+                                 hipStream_t st, const double* gate = nullptr, double gate_thr2 = 0.0,
+                                 int64_t sstep = 1);   // sstep > 1: every sstep-th 256-row strip only
 
 // Small utilities (util.hip).
 hipError_t launch_fill_f32(float* p, int64_t count, float v, hipStream_t st);

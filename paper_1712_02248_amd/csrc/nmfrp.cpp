@@ -869,10 +869,10 @@ double split_residual_bound(int KR, int64_t m, int64_t n, double es, double xsq)
 
 }  // namespace
 
-nmf_status nmf_residual_check(nmf_ctx* c, const float* X, int64_t ldx, double eps, double* rel_err, double* bound,
-                              int32_t* exact) {
-  if (!c || !X || !rel_err || ldx < c->p.n) return fail(c, NMF_EINVAL, "bad arguments");
-  if (!c->initialized) return fail(c, NMF_ESTATE, "residual needs factors (nmf_init)");
+namespace {
+
+// The split-BF16 residual over all of X and its bound (split_residual_bound).
+nmf_status split_check(nmf_ctx* c, const float* X, int64_t ldx, double* es, double* beta) {
   Layout& L = c->L;
   HIPCHK(c, hipEventRecord(c->ev[4], c->st));
   HIPCHK(c, launch_residual_split(X, ldx, c->p.m, c->p.n, c->at<float>(L.W), c->at<float>(L.scale_w),
@@ -885,8 +885,20 @@ nmf_status nmf_residual_check(nmf_ctx* c, const float* X, int64_t ldx, double ep
   c->t_residual = true;
   if (hr[5] != 0.0 || hr[6] != 0.0) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
   if (!std::isfinite(hr[3]) || !std::isfinite(hr[4])) return fail(c, NMF_ENONFINITE, "non-finite residual");
-  const double e32 = (hr[4] > 0) ? std::sqrt(hr[3] / hr[4]) : 0.0;
-  const double b = split_residual_bound(residual_split_kr(c->p.r), c->p.m, c->p.n, e32, hr[4]);
+  *es = (hr[4] > 0) ? std::sqrt(hr[3] / hr[4]) : 0.0;
+  *beta = split_residual_bound(residual_split_kr(c->p.r), c->p.m, c->p.n, *es, hr[4]);
+  return NMF_OK;
+}
+
+}  // namespace
+
+nmf_status nmf_residual_check(nmf_ctx* c, const float* X, int64_t ldx, double eps, double* rel_err, double* bound,
+                              int32_t* exact) {
+  if (!c || !X || !rel_err || ldx < c->p.n) return fail(c, NMF_EINVAL, "bad arguments");
+  if (!c->initialized) return fail(c, NMF_ESTATE, "residual needs factors (nmf_init)");
+  double e32 = 0.0, b = 0.0;
+  nmf_status s;
+  if ((s = split_check(c, X, ldx, &e32, &b)) != NMF_OK) return s;
   if (std::fabs(e32 - eps) <= b) {   // either side of eps within the bound: the exact value decides
     if (exact) *exact = 1;
     if (bound) *bound = 0.0;
@@ -939,74 +951,74 @@ nmf_status nmf_sketch_spectrum(nmf_ctx* c, double* sigma) {
 
 namespace {
 
-// One synchronisation for a proxy reading and, when the proxy is already within
-// thr of eps, the split-BF16 residual too: its kernel reads the proxy sums on
-// the device and exits at once otherwise (its output keeps a negative
-// sentinel).  *ran tells whether e was evaluated; when the split value lies
-// within its bound of eps, the exact FP64 residual decides (*e exact).
-nmf_status proxy_then_check(nmf_ctx* c, const float* X, int64_t ldx, double eps, double thr, double* p, bool* ran,
-                            double* e) {
+// Residual estimated on a sample of the rows: the split-BF16 sums over every
+// s-th 256-row strip (s = strips / 64, about 64 strips; all of them for
+// m <= 16384), e_hat^2 = sum (X - P)^2 / sum X^2 over the sample.  A scheduling
+// signal only: no stop is decided on it.
+nmf_status sampled_residual(nmf_ctx* c, const float* X, int64_t ldx, double* eh) {
   Layout& L = c->L;
-  const int nb = proxy_blocks(c->p.n);
-  double* po = c->at<double>(L.proxy_out);
-  double* ro = c->at<double>(L.res_out);
-  HIPCHK(c, launch_proxy(c->at<float>(L.Xh), L.KP, c->at<float>(L.Ht), c->p.r, c->at<float>(L.Wh), c->p.k_sketch,
-                         c->p.n, c->at<double>(L.proxy_part), c->st));
-  HIPCHK(c, launch_sum_partials_f64(c->at<double>(L.proxy_part), nb, 2, po, nullptr, c->st));
-  HIPCHK(c, launch_fill_f32(reinterpret_cast<float*>(ro), 4, -1.0f, c->st));   // two negative doubles
-  HIPCHK(c, hipEventRecord(c->ev[4], c->st));
+  const int64_t strips = ceil_div(c->p.m, (int64_t)256);
+  const int64_t sstep = strips > 64 ? strips / 64 : 1;
   HIPCHK(c, launch_residual_split(X, ldx, c->p.m, c->p.n, c->at<float>(L.W), c->at<float>(L.scale_w),
                                   c->at<float>(L.Ht), c->p.r, c->at<uint16_t>(L.rsplit), c->at<double>(L.res_part),
-                                  ro, c->at<unsigned>(L.counters) + 4, c->st, po, thr * thr));
-  HIPCHK(c, hipEventRecord(c->ev[5], c->st));
-  HIPCHK(c, launch_gather_host(po, ro, c->at<int>(L.qr_status), c->hout_dev, c->st));
+                                  c->at<double>(L.res_out), c->at<unsigned>(L.counters) + 4, c->st, nullptr, 0.0,
+                                  sstep));
+  HIPCHK(c, launch_gather_host(nullptr, c->at<double>(L.res_out), c->at<int>(L.qr_status), c->hout_dev, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
-  double h[5];
-  for (int i = 0; i < 5; ++i) h[i] = c->hout[i];
-  if (!(h[2] > 0)) return fail(c, NMF_ENONFINITE, "||X||^2 is zero or not finite");
-  const double e2 = (h[2] - h[1] + h[0]) / h[2];
-  if (!std::isfinite(e2)) return fail(c, NMF_ENONFINITE, "non-finite proxy");
-  *p = std::sqrt(e2 > 0 ? e2 : 0.0);
-  *ran = h[4] >= 0.0;
-  if (*ran) {
-    c->t_residual = true;
-    if (c->hout[5] != 0.0 || c->hout[6] != 0.0) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
-    if (!std::isfinite(h[3]) || !std::isfinite(h[4])) return fail(c, NMF_ENONFINITE, "non-finite residual");
-    const double es = (h[4] > 0) ? std::sqrt(h[3] / h[4]) : 0.0;
-    if (std::fabs(es - eps) <= split_residual_bound(residual_split_kr(c->p.r), c->p.m, c->p.n, es, h[4]))
-      return nmf_residual(c, X, ldx, e);   // the side of eps is open: the exact value decides
-    *e = es;
-  }
+  const double* hr = c->hout;
+  if (hr[5] != 0.0 || hr[6] != 0.0) return fail(c, NMF_EBREAKDOWN, "Cholesky breakdown in the range finder");
+  if (!std::isfinite(hr[3]) || !std::isfinite(hr[4])) return fail(c, NMF_ENONFINITE, "non-finite residual");
+  *eh = (hr[4] > 0) ? std::sqrt(hr[3] / hr[4]) : 0.0;
   return NMF_OK;
 }
 
-// Adaptive schedule.  Phase 1 (no residual yet): chunks of 5 or more with the
-// sketch-only proxy after each (no pass over X); the first residual runs once
-// the proxy is within 1 % of eps, or after 100 iterations.  Phase 2: the next
-// chunk is 1.5x the iterations a straight-line extrapolation of the last two
-// residuals needs to reach eps (5..50).  Every residual is the stopping test's
-// (split-BF16 products, the exact FP64 value when eps lies within their
-// bound), so each stop decision is that of the exact e.
-nmf_status fit_proxy_schedule(nmf_ctx* c, const float* X, int64_t ldx, int32_t max_iters, double eps,
-                              int* iters_done, double* rel_err) {
+// Adaptive schedule.  After every chunk (5 first, then 1.2x the iterations a
+// straight-line extrapolation of the last two readings needs to reach the
+// target, 5..50; with one reading 20, 10 or 5 by its distance from it) the
+// residual is estimated on a sample of the rows (sampled_residual).  The target
+// is eps - beta, beta the bound of the split-BF16 residual (split_check) at the
+// estimate: below it the split residual decides e <= eps by itself.  The split
+// residual over all of X runs once the estimate reaches the target, once it is
+// within 1 % of eps with the target out of reach (more than 20 further
+// iterations at the current rate, or no progress), and after the last chunk.
+// A split value within its bound of eps leaves the side of eps open: if the
+// target is a few iterations away (at most 10 at the current rate) the
+// iterations continue and the split residual runs again; otherwise, and for a
+// second open value in a row or after the last chunk, the exact FP64 residual
+// settles it.  Every stop decision is therefore that of the exact e; an
+// estimate that errs high only delays a stop.
+nmf_status fit_sampled_schedule(nmf_ctx* c, const float* X, int64_t ldx, int32_t max_iters, double eps,
+                                int* iters_done, double* rel_err) {
   nmf_status s;
   int done = 0, chunk = 5;
+  bool open = false;
   double e = NAN;
-  int t_prev = -1;        // last evaluation (proxy in phase 1, exact in phase 2)
+  bool fresh = false;     // e belongs to the current factors
+  int t_prev = -1;
   double v_prev = 0.0;
-  bool res_seen = false;
-  bool far = false;       // the last extrapolation needed more than the largest chunk
-  auto extrapolate = [&](double v, int t, double lo, double hi, double fac) {
+  const double kr3 = 3.0 * residual_split_kr(c->p.r);
+  // the bound at e, with ||X|| large enough that the underflow term is negligible
+  auto beta_at = [&](double v) {
+    const double u = std::ldexp(1.0, -23), up = u / (1.0 - u);
+    const double g0 = std::ldexp(1.0, -24) + 3.03 * std::ldexp(1.0, -16) + 1.02 * kr3 * u, g = g0 / (1.0 - g0);
+    return (g * (1.0 + v) + up * v) / (1.0 - g) + 1e-12 * v;
+  };
+  // iterations to reach `target` from v at the rate of the last two readings (inf: no progress)
+  auto need_for = [&](double v, int t, double target) {
     const double slope = t_prev >= 0 && t > t_prev ? (v_prev - v) / (t - t_prev) : 0.0;
+    if (v <= target) return 0.0;
+    return slope > 0 ? (v - target) / slope : HUGE_VAL;
+  };
+  auto next_chunk = [&](double v, int t, double target, int lo) {
+    const double need = need_for(v, t, target);
     int ch;
-    far = t_prev >= 0;
-    if (slope > 0) {
-      const double need = std::ceil(fac * (v - eps) / slope);
-      far = far && need > hi;
-      ch = need < lo ? (int)lo : need > hi ? (int)hi : (int)need;
+    if (std::isfinite(need) && t_prev >= 0) {
+      const double n12 = std::ceil(1.2 * need);
+      ch = n12 < lo ? lo : n12 > 50 ? 50 : (int)n12;
     } else {
-      const double gap = (v - eps) / (eps > 0 ? eps : 1.0);
-      ch = gap > 0.1 ? 50 : gap > 0.01 ? 20 : gap > 0.003 ? 10 : 5;
+      const double gap = (v - target) / (target > 0 ? target : 1.0);
+      ch = gap > 0.1 ? 20 : gap > 0.01 ? 10 : 5;
+      if (ch < lo) ch = lo;
     }
     t_prev = t;
     v_prev = v;
@@ -1016,31 +1028,36 @@ nmf_status fit_proxy_schedule(nmf_ctx* c, const float* X, int64_t ldx, int32_t m
     if (chunk > max_iters - done) chunk = max_iters - done;
     if ((s = nmf_step(c, chunk)) != NMF_OK) return s;
     done += chunk;
-    if (!res_seen) {
-      double p;
-      bool ran = false;
-      // the residual runs in the same synchronisation when the proxy is within 1 % of eps
-      if ((s = proxy_then_check(c, X, ldx, eps, eps * 1.01, &p, &ran, &e)) != NMF_OK) return s;
-      if (!ran && done < 100 && done < max_iters) {
-        chunk = extrapolate(p, done, 5, 50, 1.2);
-        // A proxy that would need more than the largest chunk at its current
-        // rate is taken as stalled above eps: its offset from the exact error
-        // (W's part outside range(Q_L)) does not shrink with the iterations.
-        if (!far) continue;
-      }
-      res_seen = true;
-      t_prev = -1;        // phase 2 extrapolates residuals only
-      if (ran) {
+    fresh = false;
+    double v;
+    if ((s = sampled_residual(c, X, ldx, &v)) != NMF_OK) return s;
+    const bool last = done >= max_iters;
+    int lo = 5;
+    const double target = eps - beta_at(v);
+    const bool stalled = v <= eps * 1.01 && (t_prev < 0 || need_for(v, done, target) > 20.0);
+    if (v <= target || stalled || open || last) {
+      double es, b;
+      if ((s = split_check(c, X, ldx, &es, &b)) != NMF_OK) return s;
+      if (std::fabs(es - eps) > b) {           // decided by the split value
+        e = es;
+        fresh = true;
+        open = false;
         if (e <= eps) break;
-        chunk = extrapolate(e, done, 5, 50, 1.5);
-        continue;
+      } else if (open || last || need_for(es, done, eps - b) > 10.0) {   // settled by the exact residual
+        if ((s = nmf_residual(c, X, ldx, &e)) != NMF_OK) return s;
+        fresh = true;
+        open = false;
+        if (e <= eps) break;
+        es = e;
+      } else {
+        open = true;
+        lo = 2;
       }
+      v = es;
     }
-    if ((s = nmf_residual_check(c, X, ldx, eps, &e, nullptr, nullptr)) != NMF_OK) return s;
-    if (e <= eps) break;
-    chunk = extrapolate(e, done, 5, 50, 1.5);
+    chunk = next_chunk(v, done, eps - beta_at(v), lo);
   }
-  if (std::isnan(e) && (s = nmf_residual(c, X, ldx, &e)) != NMF_OK) return s;
+  if (!fresh && (s = nmf_residual(c, X, ldx, &e)) != NMF_OK) return s;
   *iters_done = done;
   *rel_err = e;
   return NMF_OK;
@@ -1054,7 +1071,7 @@ nmf_status nmf_fit(nmf_ctx* c, const float* X, int64_t ldx, int32_t max_iters, d
   if (check_every == 0 && max_iters > 0 && c->xsq_valid && c->initialized) {
     int it = 0;
     double ee = 0.0;
-    const nmf_status st = fit_proxy_schedule(c, X, ldx, max_iters, eps, &it, &ee);
+    const nmf_status st = fit_sampled_schedule(c, X, ldx, max_iters, eps, &it, &ee);
     if (iters_done) *iters_done = it;
     if (rel_err) *rel_err = ee;
     return st;

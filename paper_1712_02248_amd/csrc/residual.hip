@@ -340,7 +340,7 @@ residual_split_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64
                       const uint16_t* __restrict__ Wh, const uint16_t* __restrict__ Wl,
                       const uint16_t* __restrict__ Hh, const uint16_t* __restrict__ Hl, double* __restrict__ part,
                       double* __restrict__ out, unsigned* __restrict__ counter, const double* __restrict__ gate,
-                      double gate_thr2) {
+                      double gate_thr2, int64_t sstep) {
   if (gate) {   // as in residual_kernel: every workgroup returns unless the proxy is within the gate
     const double e2 = (gate[2] - gate[1] + gate[0]) / gate[2];
     if (!(e2 <= gate_thr2)) return;
@@ -353,7 +353,8 @@ residual_split_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64
   __shared__ int last;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l32 = lane & 31, half = lane >> 5;
-  const int64_t row0 = (int64_t)blockIdx.x * 256 + 32 * wave;   // this wave's 32 rows
+  // this wave's 32 rows of strip blockIdx.x * sstep (every sstep-th 256-row strip)
+  const int64_t row0 = (int64_t)blockIdx.x * sstep * 256 + 32 * wave;
   const int64_t ntile = ceil_div(n, CT);
   // A fragments: lane holds W[row0 + l32][16 ks + 8 half .. +7] (hi, lo)
   bf16x8 ah[KS], al[KS];
@@ -404,14 +405,19 @@ residual_split_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64
         xv[cb][x] = X[(i < m && j < n) ? i * ldx + j : 0];
       }
   };
-  const int64_t rot = (int64_t)blockIdx.x % ntile;
-  auto col0 = [&](int64_t t) { return ((t + rot) % ntile) * CT; };
+  // column part blockIdx.y of gridDim.y: tiles tbeg .. tbeg + nt - 1, from a rotated start
+  const int tbeg = (int)((int64_t)blockIdx.y * ntile / gridDim.y);
+  const int nt = (int)(((int64_t)blockIdx.y + 1) * ntile / gridDim.y) - tbeg;
+  const int rot = nt > 0 ? (int)(blockIdx.x % (unsigned)nt) : 0;
+  auto col0 = [&](int t) { return (int64_t)(tbeg + (t + rot) % nt) * CT; };
   double res = 0.0, xx = 0.0;
-  loadH(col0(0));
-  loadX(col0(0));
-  storeH(col0(0), 0);
+  if (nt > 0) {
+    loadH(col0(0));
+    loadX(col0(0));
+    storeH(col0(0), 0);
+  }
   __syncthreads();
-  for (int64_t t = 0; t < ntile; ++t) {
+  for (int t = 0; t < nt; ++t) {
     const int64_t c0 = col0(t);
     float xc[2][16];
 #pragma unroll
@@ -421,7 +427,7 @@ residual_split_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64
         const int64_t i = xrow(x), j = c0 + 32 * cb + l32;
         xc[cb][x] = (i < m && j < n) ? xv[cb][x] : 0.f;
       }
-    if (t + 1 < ntile) {
+    if (t + 1 < nt) {
       loadH(col0(t + 1));
       loadX(col0(t + 1));
     }
@@ -451,7 +457,7 @@ residual_split_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64
         res = fma(df, df, res);
         xx = fma((double)xc[cb][x], (double)xc[cb][x], xx);
       }
-    if (t + 1 < ntile) storeH(col0(t + 1), b ^ 1);   // that stage was last read before the previous barrier
+    if (t + 1 < nt) storeH(col0(t + 1), b ^ 1);   // that stage was last read before the previous barrier
     __syncthreads();
   }
   red[0][tid] = res;
@@ -464,8 +470,8 @@ residual_split_kernel(const float* __restrict__ X, int64_t ldx, int64_t m, int64
     }
     __syncthreads();
   }
-  const int nblk = gridDim.x;
-  const int bid = blockIdx.x;
+  const int nblk = gridDim.x * gridDim.y;
+  const int bid = blockIdx.x + gridDim.x * blockIdx.y;
   if (tid == 0) {
     part[2 * bid] = red[0][0];
     part[2 * bid + 1] = red[1][0];
@@ -545,8 +551,9 @@ size_t residual_split_halves(int64_t m, int64_t n, int r) {
 
 hipError_t launch_residual_split(const float* X, int64_t ldx, int64_t m, int64_t n, const float* W, const float* sw,
                                  const float* Ht, int r, uint16_t* ws, double* part, double* out, unsigned* counter,
-                                 hipStream_t st, const double* gate, double gate_thr2) {
+                                 hipStream_t st, const double* gate, double gate_thr2, int64_t sstep) {
   const int KR = residual_split_kr(r);
+  if (sstep < 1) return hipErrorInvalidValue;
   if (!KR || m == 0 || n == 0) return hipErrorInvalidValue;
   uint16_t* Wh = ws;
   uint16_t* Wl = Wh + m * KR;
@@ -555,13 +562,16 @@ hipError_t launch_residual_split(const float* X, int64_t ldx, int64_t m, int64_t
   auto grid = [&](int64_t rows) { return dim3((unsigned)std::min<int64_t>(ceil_div(rows * (KR / 2), 256), 8192)); };
   hipLaunchKernelGGL(split_rows_kernel, grid(m), dim3(256), 0, st, W, (int64_t)r, sw, m, r, KR, Wh, Wl);
   hipLaunchKernelGGL(split_rows_kernel, grid(n), dim3(256), 0, st, Ht, (int64_t)r, nullptr, n, r, KR, Hh, Hl);
-  const dim3 g((unsigned)ceil_div(m, 256));
+  // the sample: every sstep-th strip, each split into up to sstep column parts
+  // (as many workgroups as the full pass, each with a share of the columns)
+  const int64_t parts = std::min<int64_t>(sstep, std::max<int64_t>(1, ceil_div(n, 64)));
+  const dim3 g((unsigned)ceil_div(ceil_div(m, 256), sstep), (unsigned)parts);
   if (KR == 64)
     hipLaunchKernelGGL(residual_split_kernel<64>, g, dim3(512), 0, st, X, ldx, m, n, Wh, Wl, Hh, Hl, part, out,
-                       counter, gate, gate_thr2);
+                       counter, gate, gate_thr2, sstep);
   else
     hipLaunchKernelGGL(residual_split_kernel<128>, g, dim3(512), 0, st, X, ldx, m, n, Wh, Wl, Hh, Hl, part, out,
-                       counter, gate, gate_thr2);
+                       counter, gate, gate_thr2, sstep);
   return hipGetLastError();
 }
 
