@@ -793,7 +793,8 @@ def main():
         st = v["stages"]
         it = v["iters"][-1]
         return dict(median_s=round(statistics.median(v["times"]), 6), times_s=[round(t, 6) for t in v["times"]],
-                    iters_to_eps=v["iters"], e_at_stop=v["e"], e_after_init=v["e_init"],
+                    iters_to_eps=v["iters"], reached_eps=all(e <= eps for e in v["e"]), e_at_stop=v["e"],
+                    e_after_init=v["e_init"],
                     e_after_20_iters=v["e_20"],
                     e_after_same_iters=v["e_fixed"],
                     rejected_rows=v["rejected"],

@@ -265,3 +265,35 @@ def test_wide_network_gradients_and_inference(lib):
     out = net.infer(dev(Xb)).cpu().numpy().astype(np.float64)
     ref = omlp.infer(P, Xb.astype(np.float64))
     assert rel_norm(out, ref) <= 1e-5
+
+
+def test_adaptive_fit_on_a_sampled_residual(lib):
+    """nmf_fit's adaptive schedule on a tall problem, where the schedule's residual
+    estimates sample every s-th row strip in column parts: the run never stops
+    before the exact error reaches eps, stops within a few chunks after it, and
+    the reported error is the stopping test's (within its bound of the exact)."""
+    m, n, r, kp, q = TALL
+    print(f"adaptive fit m={m} n={n} r={r} k'={kp}", flush=True)
+    seed = 9000 + r + kp
+    X, OL, OR, W0, H0 = parts_case(m, n, r, r, kp, seed)
+    Xd = dev(X)
+    ref = lib.NMF(m, n, r, kp, q, seed=7)
+    ref.compress(Xd, dev(OL), dev(OR))
+    ref.init(dev(W0), dev(H0))
+    curve = [ref.residual(Xd)]
+    for _ in range(60):
+        ref.step(1)
+        curve.append(ref.residual(Xd))
+    eps = 1.0005 * curve[40]
+    first = next(i for i, e in enumerate(curve) if e <= eps)
+    ctx = lib.NMF(m, n, r, kp, q, seed=7)
+    ctx.compress(Xd, dev(OL), dev(OR))
+    ctx.init(dev(W0), dev(H0))
+    it, e = ctx.fit(Xd, 200, eps, check_every=0)
+    e_exact = ctx.residual(Xd)
+    _, b, _ = ctx.residual_check(Xd, 10.0)
+    print(f"  eps {eps:.6e}: first iteration at eps {first}, fit stopped at {it} with e {e:.6e} "
+          f"(exact {e_exact:.6e})", flush=True)
+    assert e_exact <= eps and it >= first
+    assert it <= first + 25
+    assert abs(e - e_exact) <= b
