@@ -78,12 +78,13 @@ typedef struct {
                             term.  ||X||^2 for nmf_proxy_residual comes from the
                             X Q_R pass (0, 2) or the quantiser (1). */
   int32_t update_prec;   /* products of the update loop (extension): 0 FP32 MFMA; 1
-                            split-BF16 MFMA (v = hi + lo as in nmf_gemm_split, terms
-                            hi hi + hi lo + lo hi, FP32 accumulation: within
-                            3.03 2^-16 |a||b| per term, the order of FP32's own
-                            accumulation error over the k' + r terms).  1 needs the
-                            wide-factor half-steps (r > 64 or k' > 128), else
-                            NMF_EINVAL. */
+                            BF16 MFMA on split operands with FP32 accumulation:
+                            the gradient a = S C - F U with three parts per value
+                            (v = hi + mid + lo exactly; six part products, FP32
+                            accuracy: a nearly cancels as the sweep converges),
+                            Q^T F with two (v = hi + lo, within 2^-16 |v|; terms
+                            hi hi + hi lo + lo hi).  1 needs the wide-factor
+                            half-steps (r > 64 or k' > 128), else NMF_EINVAL. */
 } nmf_params;
 
 /* ---------------------------------------------------------------- context */

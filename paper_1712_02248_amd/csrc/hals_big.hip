@@ -306,15 +306,27 @@ NMF_DEV void split_pair(float a, float b, uint32_t& h, uint32_t& l) {
   const f32x2_t w = {a - __builtin_bit_cast(float, h << 16), b - __builtin_bit_cast(float, h & 0xFFFF0000u)};
   l = __builtin_bit_cast(uint32_t, __builtin_convertvector(w, bf16x2_t));
 }
+// Three BF16 parts: v = hi + mid + lo exactly (v - hi and then v - hi - mid are
+// exact in FP32 and the last remainder has at most 8 significant bits), unless
+// the parts fall below the BF16 normal range.
+NMF_DEV void split3_pair(float a, float b, uint32_t& h, uint32_t& m, uint32_t& l) {
+  split_pair(a, b, h, m);
+  const float ra = a - __builtin_bit_cast(float, h << 16), rb = b - __builtin_bit_cast(float, h & 0xFFFF0000u);
+  const f32x2_t w = {ra - __builtin_bit_cast(float, m << 16), rb - __builtin_bit_cast(float, m & 0xFFFF0000u)};
+  l = __builtin_bit_cast(uint32_t, __builtin_convertvector(w, bf16x2_t));
+}
 
-// The gradient product of hs_grad_kernel on split-BF16 MFMA: every operand
-// value v is carried as hi + lo (hi = bf16(v), lo = bf16(v - hi)) and a term as
-// hi hi + hi lo + lo hi on v_mfma_f32_32x32x16_bf16 with FP32 accumulation
-// (within 3.03 2^-16 |s||c| of the exact term; FP32 accumulation over the
-// k' + r terms is of the same order).  Loads, masks, scales and the epilogue
-// are those of the FP32 kernel.  The split happens when a step is stored to LDS:
-// A rows and the transposed B rows are K-contiguous halves with row stride 40
-// (16-byte fragment reads of 16 consecutive rows fall in distinct banks); a
+// The gradient product of hs_grad_kernel on BF16 MFMA with three-part operands:
+// every operand value is carried as hi + mid + lo (split3_pair, exact), and a
+// term as the six products of parts whose orders sum to at most two (lo lo,
+// lo mid and mid lo, below 2^-24 |s||c|, are dropped), on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation: FP32 accuracy.  Two parts
+// do not suffice here: a = S C - F U nearly cancels as the sweep converges, and
+// 16-bit operands move the factors measurably (the Q^T F product, a sum of
+// like-signed terms, keeps two parts).  Loads, masks, scales and the epilogue
+// are those of the FP32 kernel.  The split happens when a step is stored to
+// LDS: A rows and the transposed B rows are K-contiguous halves with row stride
+// 40 (16-byte fragment reads of 16 consecutive rows fall in distinct banks); a
 // lane's fragment is the 8 values k = 8 (lane / 32) .. +7 of a 16-deep substep.
 template <int BM, bool FVEC>
 __global__ void __launch_bounds__(256)
@@ -326,8 +338,8 @@ hs_grad_split_kernel(const float* __restrict__ S, int64_t lds, const float* __re
   constexpr int TM = BM / WM / 32, TN = BN / WN / 32;
   constexpr int AP = BM * BK / 4 / 256;    // A float4 per thread
   static_assert(BK * BN / 16 == 256, "one 4 x 4 block of B per thread");
-  __shared__ __attribute__((aligned(16))) uint16_t AsH[BM * ST], AsL[BM * ST];
-  __shared__ __attribute__((aligned(16))) uint16_t BsH[BN * ST], BsL[BN * ST];   // Bs[j][k] = B[k][j]
+  __shared__ __attribute__((aligned(16))) uint16_t AsH[BM * ST], AsM[BM * ST], AsL[BM * ST];
+  __shared__ __attribute__((aligned(16))) uint16_t BsH[BN * ST], BsM[BN * ST], BsL[BN * ST];   // Bs[j][k] = B[k][j]
   __shared__ float sc[BR], rdl[BR];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WN, wn = wave % WN;
@@ -374,11 +386,12 @@ hs_grad_split_kernel(const float* __restrict__ S, int64_t lds, const float* __re
 #pragma unroll
     for (int e = 0; e < 4; ++e) rb[e] = *(const f32x4*)(Gp + (int64_t)(k0 + 4 * kq + e) * BR + 4 * c4);
   };
-  auto put = [&](uint16_t* H, uint16_t* L, int off, const f32x4& v) {
-    uint32_t h0, l0, h1, l1;
-    split_pair(v[0], v[1], h0, l0);
-    split_pair(v[2], v[3], h1, l1);
+  auto put = [&](uint16_t* H, uint16_t* Mi, uint16_t* L, int off, const f32x4& v) {
+    uint32_t h0, m0, l0, h1, m1, l1;
+    split3_pair(v[0], v[1], h0, m0, l0);
+    split3_pair(v[2], v[3], h1, m1, l1);
     *(uint2*)(H + off) = make_uint2(h0, h1);
+    *(uint2*)(Mi + off) = make_uint2(m0, m1);
     *(uint2*)(L + off) = make_uint2(l0, l1);
   };
   auto storeA = [&](int k0, int lim, bool fs) {
@@ -392,7 +405,7 @@ hs_grad_split_kernel(const float* __restrict__ S, int64_t lds, const float* __re
         const float x = fs ? ra[p][e] * sc[k0 + ca + e] : ra[p][e];
         v[e] = (rok && k0 + ca + e < lim) ? x : 0.f;
       }
-      put(AsH, AsL, row * ST + ca, v);
+      put(AsH, AsM, AsL, row * ST + ca, v);
     }
   };
   auto storeS = [&](int k0) {
@@ -404,7 +417,7 @@ hs_grad_split_kernel(const float* __restrict__ S, int64_t lds, const float* __re
 #pragma unroll
       for (int e = 0; e < 4; ++e) v[e] = k0 + 4 * kq + e < kp ? rb[e][d] : 0.f;
       if (anykept && kept(l)) v = (f32x4){0.f, 0.f, 0.f, 0.f};
-      put(BsH, BsL, l * ST + 4 * kq, v);
+      put(BsH, BsM, BsL, l * ST + 4 * kq, v);
     }
   };
   auto storeF = [&](int k0) {
@@ -424,7 +437,7 @@ hs_grad_split_kernel(const float* __restrict__ S, int64_t lds, const float* __re
           v[e] = kl ? (i == l ? 1.f : 0.f) : ((kept(i) || i > l) ? -rb[e][d] : 0.f);
         }
       }
-      put(BsH, BsL, l * ST + 4 * kq, v);
+      put(BsH, BsM, BsL, l * ST + 4 * kq, v);
     }
   };
   const int half = lane >> 5, l32 = lane & 31;
@@ -432,32 +445,32 @@ hs_grad_split_kernel(const float* __restrict__ S, int64_t lds, const float* __re
 #pragma unroll
     for (int q = 0; q < BK / 16; ++q) {
       const int kb = 16 * q + 8 * half;
-      bf16x8 ah[TM], al[TM], bh[TN], bl[TN];
+      bf16x8 ah[TM], am[TM], al[TM], bh[TN], bm[TN], bl[TN];
 #pragma unroll
       for (int x = 0; x < TM; ++x) {
         const int row = wm * (BM / WM) + 32 * x + l32;
         ah[x] = *(const bf16x8*)(AsH + row * ST + kb);
+        am[x] = *(const bf16x8*)(AsM + row * ST + kb);
         al[x] = *(const bf16x8*)(AsL + row * ST + kb);
       }
 #pragma unroll
       for (int y = 0; y < TN; ++y) {
         const int col = wn * (BN / WN) + 32 * y + l32;
         bh[y] = *(const bf16x8*)(BsH + col * ST + kb);
+        bm[y] = *(const bf16x8*)(BsM + col * ST + kb);
         bl[y] = *(const bf16x8*)(BsL + col * ST + kb);
       }
       // small terms first; the accumulators alternate between dependent MFMAs
-#pragma unroll
-      for (int x = 0; x < TM; ++x)
-#pragma unroll
-        for (int y = 0; y < TN; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[x], bh[y], acc[x][y], 0, 0, 0);
-#pragma unroll
-      for (int x = 0; x < TM; ++x)
-#pragma unroll
-        for (int y = 0; y < TN; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bl[y], acc[x][y], 0, 0, 0);
-#pragma unroll
-      for (int x = 0; x < TM; ++x)
-#pragma unroll
-        for (int y = 0; y < TN; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[x], bh[y], acc[x][y], 0, 0, 0);
+#define HS_MM(A, B)                                                                                       \
+  _Pragma("unroll") for (int x = 0; x < TM; ++x) _Pragma("unroll") for (int y = 0; y < TN; ++y) acc[x][y] = \
+      __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[x], B[y], acc[x][y], 0, 0, 0)
+      HS_MM(al, bh);
+      HS_MM(am, bm);
+      HS_MM(ah, bl);
+      HS_MM(am, bh);
+      HS_MM(ah, bm);
+      HS_MM(ah, bh);
+#undef HS_MM
     }
   };
   __syncthreads();

@@ -89,13 +89,9 @@ def test_wide_iterations_match_oracle(lib, m, n, r, kp, q, normalize, up):
         # so every later sweep starts away from the fitted scale; there the FP32
         # differences of the first iteration grow fast (measured at r = 128,
         # k' = 256: 6e-5 after one iteration, 2.7e-3 after two)
+        # the same for both product precisions (the split gradient carries three
+        # BF16 parts, FP32 accuracy): measured at most 7.7e-5 with up = 1
         tol = 1e-4 * iters if (normalize != 2 or iters == 1) else 5e-3 * iters
-        if up:
-            # split-BF16 operands carry 16 significant bits (|v - hi - lo| <=
-            # 2^-16 |v|) where FP32 carries 24, and the sweep amplifies the
-            # difference: measured 1.5e-4 to 4.8e-4 after 1-5 iterations, flat
-            # in the iteration count (8.1e-3 after five with the literal rule)
-            tol = 1e-3 if normalize != 2 else 5e-3 * iters
         assert dw <= tol and dh <= tol, iters
     e, e_ref = ctx.residual(Xd), onmf.rel_error(X, W, Ht)
     assert abs(e - e_ref) <= 1e-5
