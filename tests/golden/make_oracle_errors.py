@@ -31,8 +31,12 @@ def run_lowp(name, fmt, refine, lps):
     m, n, r, kp, q, iters = c["m"], c["n"], c["r"], c["kp"], c["q"], c["iters"]
     seed = datagen.cfg_seed(name)
     t0 = time.perf_counter()
-    X32 = inputs.dyadic_parts_rows(name)
-    mean = float(np.sum(X32, dtype=np.float64)) / (m * n)
+    if c["family"] == "dyadic_parts":
+        X32 = inputs.dyadic_parts_rows(name)
+        mean = float(np.sum(X32, dtype=np.float64)) / (m * n)
+    else:
+        X32 = datagen.make_x(name)
+        mean = X32.mean()
     X = nmf.RowPanels(X32)
     W0, H0 = datagen.init_factors(mean, m, n, r, seed)
     OL = philox.normal(n, kp, 3, seed).astype(np.float32)
