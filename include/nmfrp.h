@@ -350,7 +350,7 @@ nmf_status nmf_gemm_split_prepared(const float* X, int64_t ldx, int32_t at, cons
                                    int32_t splits, void* hip_stream);
 
 /* In-place orthonormalisation of Y (rows x k, ldy % 4 == 0) by FP64
- * CholeskyQR2 (shifted CholeskyQR3 on breakdown), k <= 128.  Synchronising;
+ * CholeskyQR2 (shifted CholeskyQR3 on breakdown), k <= 256.  Synchronising;
  * *shifted (may be NULL) = 1 if the shifted fallback ran. */
 size_t nmf_orth_workspace_bytes(int64_t rows, int32_t k);
 nmf_status nmf_orth(float* Y, int64_t ldy, int64_t rows, int32_t k, void* workspace,
