@@ -21,6 +21,11 @@ Workloads (default c5):
       products on split-BF16 MFMA (`fp8_warm_fp32_updates` keeps them FP32).
   c2  X 65536 x 4096 (parts family), r = 32, k' = 64, q = 2, 500 iterations.
       Headline `bf16_warm`: BF16 range finder, split-BF16 sketches, warm start.
+  c3  X 100000 x 20000 Poisson document counts from 64 planted topics, r = 64,
+      k' = 128, q = 2, 150 iterations: BF16 range finder (FP32 or split-BF16
+      sketches) against plain FP32, both from the cold factors (new columns of a
+      topic model are new words, which its generator does not define, so there
+      is no warm start here).  The default c5 run appends this block as "c3".
 Every workload also times plain FP32 FastHALS-RP from the cold factors (the
 paper's method) and variants that separate what each part contributes: the
 network replaced by the cold rows with the same dictionary and sweeps
@@ -80,12 +85,14 @@ def parse():
                     "(components r x power iterations q, FastHALS-RP against FastHALS, sketch spectrum)")
     ap.add_argument("--sweep-seeds", type=int, default=3, help="test-matrix seeds per sweep point (median)")
     ap.add_argument("--probe-kernels", action="store_true",
-                    help="only a copy of known size and the dominant kernel (for counter runs)")
+                    help="only a copy of known size and the dominant kernel (for counter runs); at c5 then "
+                         "the FP8 range-finder products and iterations with FP32 and split-BF16 updates")
     ap.add_argument("--c4", action="store_true",
                     help="the warm-start study on new columns instead of the bench: the network trained "
                          "on the 65536 x 4096 parts workload's generator, applied to --c4-cols fresh columns, "
                          "then 20 iterations against the cold start and the controls")
     ap.add_argument("--c4-cols", type=int, default=50000)
+    ap.add_argument("--no-c3", action="store_true", help="leave out the c3 block of the default c5 run")
     return ap.parse_args()
 
 
@@ -497,7 +504,32 @@ def probe_kernels(torch, nmfrp, Xd, m, n, kp, reps, prec, name):
             S1.run()
             S2.run()
         torch.cuda.synchronize()
-        print(json.dumps(dict(probe="kernels", copy_bytes=4 * m * n, x_bytes=4 * m * n, splits=[S1.splits, S2.splits],
+        splits = [S1.splits, S2.splits]
+        del S1, S2
+        # then the FP8 range-finder products, and reps FastHALS-RP iterations with
+        # FP32 and with split-BF16 update products (FP8 compression, cold factors)
+        P1, P2 = lowp_products(torch, nmfrp, Xd, m, n, kp, nmfrp.NMF_FP8_E4M3)
+        for _ in range(reps):
+            P1.run()
+            P2.run()
+        torch.cuda.synchronize()
+        del P1, P2
+        import datagen
+        cfg = datagen.CONFIGS[name]
+        r = cfg["r"]
+        g = torch.Generator(device=Xd.device)
+        g.manual_seed(7)
+        W0 = torch.rand(m, r, device=Xd.device, generator=g)
+        H0 = torch.rand(n, r, device=Xd.device, generator=g)
+        for up in (0, 1):
+            ctx = nmfrp.NMF(m, n, r, kp, cfg["q"], seed=1, prec=nmfrp.NMF_FP8_E4M3, refine_fp32=2, lowp_sketches=2,
+                            update_prec=up)
+            ctx.compress(Xd)
+            ctx.init(W0, H0)
+            ctx.step(reps)
+            ctx.sync()
+            ctx.close()
+        print(json.dumps(dict(probe="kernels", copy_bytes=4 * m * n, x_bytes=4 * m * n, splits=splits,
                               M=[m, n], N=kp, reps=reps,
                               source_sha256_16=source_digest(os.path.join(ROOT, "paper_1712_02248_amd", "csrc",
                                                                           "gemm_split.hip")))), flush=True)
@@ -654,6 +686,54 @@ def run_c4(torch, nmfrp, datagen, args):
           flush=True)
 
 
+def run_c3(torch, nmfrp, datagen, args, steps=3, warmup=1):
+    """c3 time to eps: the BF16 range finder (FP32 sketches, as the parity test and
+    the oracle's BF16 model have them, and split-BF16 sketches) against plain FP32,
+    from the cold factors, eps = (1 + 1e-3) e_oracle(150 it); and the BF16
+    range-finder product at c3's shapes (X B and X^T B on the one row-major BF16
+    copy).  X is drawn on the host (untimed) and resident in HBM when the clock
+    starts."""
+    name = "c3"
+    cfg = dict(datagen.CONFIGS[name])
+    cfg["name"] = name
+    m, n, r, kp, q = cfg["m"], cfg["n"], cfg["r"], cfg["kp"], cfg["q"]
+    seed = datagen.cfg_seed(name)
+    e_oracle = json.load(open(GOLDEN))[name]["e"]
+    eps = (1.0 + 1e-3) * e_oracle
+    dev = torch.device("cuda:0")
+    log(f"[bench] c3: generating X {m}x{n} on the host (untimed)")
+    X = datagen.make_x(name)
+    W0, H0 = datagen.init_factors(X.mean(), m, n, r, seed)
+    Xd = torch.from_numpy(X).to(dev)
+    del X
+    W0d, H0d = torch.from_numpy(W0).to(dev), torch.from_numpy(H0).to(dev)
+    torch.cuda.synchronize()
+    F32, BF = nmfrp.NMF_FP32, nmfrp.NMF_BF16
+    out = {}
+    for vname, prec, lps in (("plain", F32, 0), ("bf16", BF, 0), ("bf16_split_sketches", BF, 2)):
+        v = time_variant(torch, nmfrp, cfg, seed, Xd, W0d, H0d, eps, args, prec, 0, None, steps, warmup,
+                         label=f"c3 {vname}", lps=lps)
+        st, it = v["stages"], v["iters"][-1]
+        out[vname] = dict(median_s=round(statistics.median(v["times"]), 6), times_s=[round(t, 6) for t in v["times"]],
+                          iters_to_eps=v["iters"], reached_eps=all(e <= eps for e in v["e"]), e_at_stop=v["e"],
+                          stage_ms=dict(compress=round(st["compress_ms"], 3), iterations=round(st["step_ms"], 3),
+                                        per_iteration=round(st["step_ms"] / max(it, 1), 4),
+                                        residual=round(st["residual_ms"], 4)))
+        log(f"[bench] c3 {vname}: median {out[vname]['median_s'] * 1e3:.2f} ms, iters {v['iters']}, "
+            f"e {v['e'][-1]:.8e}")
+    kt = kernel_timing(torch, nmfrp, Xd, m, n, kp, args.kernel_reps, BF, name)
+    best = min(("bf16", "bf16_split_sketches"), key=lambda k: out[k]["median_s"])
+    res = dict(workload=f"c3: X {m}x{n} FP32 synthetic (Poisson counts of {cfg['r_true']} planted topics), r={r}, "
+                        f"k'={kp}, q={q}, eps=(1+1e-3) e_oracle({cfg['iters']} it); BF16 range finder vs plain FP32, "
+                        "cold factors",
+               eps=eps, e_oracle=e_oracle, variants=out, fastest_bf16=best,
+               speedup_vs_plain=round(out["plain"]["median_s"] / out[best]["median_s"], 3),
+               gemm=kt)
+    del Xd, W0d, H0d
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -674,10 +754,14 @@ def main():
         run_c4(torch, nmfrp, datagen, args)
         return
     name = args.workload
+    if name == "c3":
+        print(json.dumps(run_c3(torch, nmfrp, datagen, args, args.steps, args.warmup)), flush=True)
+        return
     cfg = dict(datagen.CONFIGS[name])
     cfg["name"] = name
     if cfg["family"] not in ("parts", "dyadic_parts"):
-        sys.exit("bench.py: the warm-start protocol draws new columns of the parts families (c2, c5)")
+        sys.exit("bench.py: the warm-start protocol draws new columns of the parts families (c2, c5); "
+                 "c3 runs with --workload c3")
     m, n, r, kp, q = cfg["m"], cfg["n"], cfg["r"], cfg["kp"], cfg["q"]
     iters_cfg = cfg["iters"]
     seed = datagen.cfg_seed(name)
@@ -838,6 +922,11 @@ def main():
                          frac_fp32_mfma=round(upd_flops / (per_iter_ms * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4)),
         roofline=roofline,
     )
+    if name == "c5" and not (args.headline_only or args.variants or args.no_c3):
+        # c3, the BF16 configuration: the c5 data leave HBM first
+        del Xd, W0d, H0d, net, Q_train, W_ref, W0gen
+        torch.cuda.empty_cache()
+        line["c3"] = run_c3(torch, nmfrp, datagen, args)
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a row sample (cpu_baseline)")
         rows = args.cpu_rows or (8192 if name == "c5" else 65536)
