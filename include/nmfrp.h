@@ -200,8 +200,8 @@ nmf_status nmf_sketch_spectrum(nmf_ctx* ctx, double* sigma);
  * iterations and a second split residual when the target is at most 10
  * iterations away, and otherwise (or on a second such value, or after the last
  * chunk) by the exact FP64 residual.  Each stop decision is that of the exact
- * e; an estimate that errs high
- * only delays a stop by a chunk.  check_every == 0 after nmf_set_state: the
+ * e; an estimate that errs high only delays a stop by a chunk.
+ * check_every == 0 after nmf_set_state: the
  * exact residual after every chunk, starting with e at the current factors,
  * each chunk 1.5 times the iterations a straight-line extrapolation of the last
  * two values needs (5..50; 50, 20, 10 or 5 by the gap to eps when there is no
