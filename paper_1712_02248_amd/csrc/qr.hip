@@ -346,21 +346,61 @@ cholesky_kernel(const double* __restrict__ G, int k, int64_t rows, double* __res
   if (tid == 0) status[1] = 1;
 }
 
-// 16 x 16 tile (i0, j0) of op(A) op(B) over K on v_mfma_f64_16x16x4_f64, with
-// element (i, c) of A at A[i ai + c ac] and (c, j) of B at B[c bc + j bj]
-// (entries outside the ranges given as 0).  D[i][j] in lane j + 16 (i % 4),
-// register i / 4.  One wave.
-__device__ f64x4 mm16_f64(const double* A, int ai, int ac, int na, const double* B, int bc, int bj, int nb, int K,
-                          int i0, int j0) {
-  const int lane = threadIdx.x & 63, l = lane & 15, g = lane >> 4;
-  f64x4 d = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    const int c = k0 + g;
-    const double a = (i0 + l < na && c < K) ? A[(i0 + l) * ai + c * ac] : 0.0;
-    const double b = (j0 + l < nb && c < K) ? B[c * bc + (j0 + l) * bj] : 0.0;
-    d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, d, 0, 0, 0);
+// C = op(A) op(B), na x nb (each <= 128) over K <= 128, by the whole 1024-thread
+// workgroup on v_mfma_f64_16x16x4_f64: element (i, c) of A is A[i ai + c ac],
+// (c, j) of B is B[c bc + j bj], zero outside the ranges.  K is staged into LDS
+// in chunks of 32 (A chunk na x 32, B chunk 32 x nb), every load of a chunk in
+// flight together and coalesced along whichever stride is 1; wave w accumulates
+// the 16 x 16 tiles t = w, w + 16, ... (row-major over the tile grid) over k in
+// ascending steps of 4 and hands each to st(ti, tj, d), with D[i][j] in lane
+// j + 16 (i % 4), register i / 4.  Called by every thread (it holds barriers).
+constexpr int MMC = 32, MAS = MMC + 1, MBS = 128 + 1;
+template <typename Store>
+__device__ __attribute__((noinline)) void mm_lds_f64(const double* A, int ai, int ac, int na, const double* B, int bc, int bj, int nb,
+                           int K, double* As, double* Bs, Store st) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, g4 = lane >> 4;
+  const int ntj = (nb + 15) / 16, nt = ((na + 15) / 16) * ntj;
+  f64x4 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < K; k0 += MMC) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int e = tid + 1024 * p;
+      const int i = ac == 1 ? e >> 5 : e & 127, c = ac == 1 ? e & 31 : e >> 7;
+      av[p] = (i < na && k0 + c < K) ? A[(int64_t)i * ai + (int64_t)(k0 + c) * ac] : 0.0;
+      const int jb = bj == 1 ? e & 127 : e >> 5, cb = bj == 1 ? e >> 7 : e & 31;
+      bv[p] = (jb < nb && k0 + cb < K) ? B[(int64_t)(k0 + cb) * bc + (int64_t)jb * bj] : 0.0;
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int e = tid + 1024 * p;
+      const int i = ac == 1 ? e >> 5 : e & 127, c = ac == 1 ? e & 31 : e >> 7;
+      As[i * MAS + c] = av[p];
+      const int jb = bj == 1 ? e & 127 : e >> 5, cb = bj == 1 ? e >> 7 : e & 31;
+      Bs[cb * MBS + jb] = bv[p];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = wave + 16 * q;
+      if (t >= nt) break;   // uniform
+      const int ti = t / ntj, tj = t % ntj;
+#pragma unroll
+      for (int s4 = 0; s4 < MMC / 4; ++s4) {
+        const double a = As[(16 * ti + l16) * MAS + 4 * s4 + g4];
+        const double b = Bs[(4 * s4 + g4) * MBS + 16 * tj + l16];
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[q], 0, 0, 0);
+      }
+    }
+    __syncthreads();
   }
-  return d;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int t = wave + 16 * q;
+    if (t < nt) st(t / ntj, t % ntj, acc[q]);
+  }
 }
 
 // 128 < k <= 256: the same factorisation by 2 x 2 blocks of 128 (one workgroup
@@ -379,10 +419,11 @@ cholesky256_kernel(const double* __restrict__ G, int k, int64_t rows, double* __
   if (attempt == 2 && status[0] == 0) return;
   __shared__ double colj[2][KB], rowj[2][KB];
   __shared__ double wred[NWV];
+  __shared__ double mmA[KB * MAS], mmB[MMC * MBS];   // staged operand chunks of the block products
   __shared__ int fail;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int l16 = lane & 15, g4 = lane >> 4;
-  const int k2 = k - KB, nb2 = (k2 + 15) / 16;
+  const int k2 = k - KB;
   if (attempt == 1 && gram_identity_dev(G, k, wred) <= 1e-6) {   // uniform
     if (tid == 0) status[3] = 1;
     return;
@@ -406,52 +447,44 @@ cholesky256_kernel(const double* __restrict__ G, int k, int64_t rows, double* __
     bool ok = chol_factor_inverse<KB, 32>(G, k, KB, shift, R11, k, colj, rowj, &fail);
     if (ok) {
       // L21 = G21 R11^{-1} (k2 x KB) -> lower-left block
-      for (int t = wave; t < nb2 * (KB / 16); t += NWV) {
-        const int ti = t / (KB / 16), tj = t % (KB / 16);
-        const f64x4 d = mm16_f64(G + (int64_t)KB * k, k, 1, k2, R11, k, 1, KB, KB, 16 * ti, 16 * tj);
+      mm_lds_f64(G + (int64_t)KB * k, k, 1, k2, R11, k, 1, KB, KB, mmA, mmB, [&](int ti, int tj, f64x4 d) {
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
           const int i = 16 * ti + 4 * x + g4, j = 16 * tj + l16;
           if (i < k2) R21[i * k + j] = d[x];
         }
-      }
+      });
       __syncthreads();
       // S = G22 + shift I - L21 L21^T (k2 x k2) -> upper-right block
-      for (int t = wave; t < nb2 * nb2; t += NWV) {
-        const int ti = t / nb2, tj = t % nb2;
-        const f64x4 d = mm16_f64(R21, k, 1, k2, R21, 1, k, k2, KB, 16 * ti, 16 * tj);
+      mm_lds_f64(R21, k, 1, k2, R21, 1, k, k2, KB, mmA, mmB, [&](int ti, int tj, f64x4 d) {
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
           const int i = 16 * ti + 4 * x + g4, j = 16 * tj + l16;
           if (i < k2 && j < k2)
             R12[i * k + j] = G[(int64_t)(KB + i) * k + KB + j] + (i == j ? shift : 0.0) - d[x];
         }
-      }
+      });
       __syncthreads();
       ok = chol_factor_inverse<KB, 32>(R12, k, k2, 0.0, R22, k, colj, rowj, &fail);
     }
     if (ok) {
       // U = R11^{-1} L21^T (KB x k2) -> upper-right block (S is consumed)
-      for (int t = wave; t < (KB / 16) * nb2; t += NWV) {
-        const int ti = t / nb2, tj = t % nb2;
-        const f64x4 d = mm16_f64(R11, k, 1, KB, R21, 1, k, k2, KB, 16 * ti, 16 * tj);
+      mm_lds_f64(R11, k, 1, KB, R21, 1, k, k2, KB, mmA, mmB, [&](int ti, int tj, f64x4 d) {
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
           const int i = 16 * ti + 4 * x + g4, j = 16 * tj + l16;
           if (j < k2) R12[i * k + j] = d[x];
         }
-      }
+      });
       __syncthreads();
       // R12 = -U R22^{-1}, stored transposed over L21 (lower-left block, dead now)
-      for (int t = wave; t < (KB / 16) * nb2; t += NWV) {
-        const int ti = t / nb2, tj = t % nb2;
-        const f64x4 d = mm16_f64(R12, k, 1, KB, R22, k, 1, k2, k2, 16 * ti, 16 * tj);
+      mm_lds_f64(R12, k, 1, KB, R22, k, 1, k2, k2, mmA, mmB, [&](int ti, int tj, f64x4 d) {
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
           const int i = 16 * ti + 4 * x + g4, j = 16 * tj + l16;
           if (j < k2) R21[j * k + i] = -d[x];
         }
-      }
+      });
       __syncthreads();
       for (int e = tid; e < k2 * KB; e += 1024) {   // back into the upper-right block, then zeros below
         const int j = e / KB, i = e % KB;
