@@ -215,14 +215,17 @@ __device__ bool chol_factor_inverse(const double* __restrict__ G, int ldg, int k
       // publish column j of A and row j of X (both unscaled) into buffer j % 2;
       // a thread writes buffer j % 2 again only after the barrier of step
       // j + 1, which every reader of step j has passed
+      // (rows of blocks a < b0 lie above row j, columns of blocks b > b0 to the
+      // right of column j: the updates below never touch or read them, which the
+      // unrolled block indices let the compiler drop)
       const int bf = j & 1;
       if (tx == jj) {
 #pragma unroll
-        for (int a = 0; a < PB; ++a) colj[bf][ty + TD * a] = M[a][b0];
+        for (int a = b0; a < PB; ++a) colj[bf][ty + TD * a] = M[a][b0];
       }
       if (ty == jj) {
 #pragma unroll
-        for (int b = 0; b < PB; ++b) rowj[bf][tx + TD * b] = X[b0][b];
+        for (int b = 0; b <= b0; ++b) rowj[bf][tx + TD * b] = X[b0][b];
       }
       __syncthreads();
       const double p = colj[bf][j];
@@ -237,25 +240,25 @@ __device__ bool chol_factor_inverse(const double* __restrict__ G, int ldg, int k
       const double d = p * id;
       double lc[PB], lr[PB], xj[PB];
 #pragma unroll
-      for (int a = 0; a < PB; ++a) lc[a] = colj[bf][ty + TD * a] * id;     // L[i][j]
+      for (int a = 0; a < PB; ++a) lc[a] = a >= b0 ? colj[bf][ty + TD * a] * id : 0.0;   // L[i][j]
 #pragma unroll
       for (int b = 0; b < PB; ++b) {
-        lr[b] = colj[bf][tx + TD * b] * id;                                // L[l][j]
-        xj[b] = rowj[bf][tx + TD * b] * id;                                // X[j][c] / L[j][j]
+        lr[b] = b >= b0 ? colj[bf][tx + TD * b] * id : 0.0;                       // L[l][j]
+        xj[b] = b <= b0 ? rowj[bf][tx + TD * b] * id : 0.0;                       // X[j][c] / L[j][j]
       }
 #pragma unroll
-      for (int a = 0; a < PB; ++a) {
+      for (int a = b0; a < PB; ++a) {
         const int i = ty + TD * a;
 #pragma unroll
         for (int b = 0; b < PB; ++b) {
           const int l = tx + TD * b;
-          if (j < l && l <= i) M[a][b] -= lc[a] * lr[b];
-          if (l <= j && j < i) X[a][b] -= lc[a] * xj[b];
+          if (b >= b0 && b <= a && j < l && l <= i) M[a][b] -= lc[a] * lr[b];
+          if (b <= b0 && l <= j && j < i) X[a][b] -= lc[a] * xj[b];
         }
       }
       if (tx == jj) {
 #pragma unroll
-        for (int a = 0; a < PB; ++a) {
+        for (int a = b0; a < PB; ++a) {
           const int i = ty + TD * a;
           if (i > j) M[a][b0] = lc[a];
           else if (i == j) M[a][b0] = d;
@@ -263,7 +266,7 @@ __device__ bool chol_factor_inverse(const double* __restrict__ G, int ldg, int k
       }
       if (ty == jj) {
 #pragma unroll
-        for (int b = 0; b < PB; ++b)
+        for (int b = 0; b <= b0; ++b)
           if (tx + TD * b <= j) X[b0][b] = xj[b];
       }
     }
